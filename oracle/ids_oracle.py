@@ -1,0 +1,353 @@
+"""Plain FP64 CPU oracle for the implicit difference scheme (IDS).
+
+TEST INFRASTRUCTURE ONLY.  Imported by ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py``; never by the product path.
+
+Paper: Gu, Huang, Ji, Carpentieri, Alikhanov, "Fast iterative method with a
+second order implicit difference scheme for time-space fractional
+convection-diffusion equations", arXiv:1603.00279.
+
+What is computed, and where it is defined:
+
+* Grunwald coefficients g_k = (-1)^k binom(beta, k)  -- Lemma 2, computed with
+  the recurrence of Lemma 3.
+* WSGD weights omega_k from lambda_1, lambda_0, lambda_-1  -- Lemma 2.
+* L2-1sigma coefficients a_l, b_l, c_m^(alpha,sigma,j)  -- Lemma 1.
+* The matrices Q and W_beta  -- (3.2);  A^(j+sigma), B^(j+sigma), eta_j  --
+  (3.1) and (3.3).
+* The history term  tau^-alpha/Gamma(2-alpha) sum_{s<j} c_{j-s}(u^{s+1}-u^s),
+  entering the right-hand side with a minus sign  -- (3.1).
+* One time level: g = B u^j - history + f^{j+sigma};  u^{j+1} = A^{-1} g by
+  dense Gaussian elimination (LAPACK dgesv)  -- Algorithm 2 with the direct
+  solver the paper uses as its baseline (Sec. 3.2).
+* The Strang circulant preconditioner P^(j+sigma) as a dense matrix, and
+  the eigenvalues of circulants  -- (3.7), Lemma 8, Sec. 3.2.
+* Row-by-row evaluation of (A u)_i and g_i by direct O(n) sums, for checks at
+  sizes where no dense matrix fits.
+
+Every function is pinned by ``tests/test_oracle_*.py`` against closed forms,
+library special cases, the numbers printed in the paper's tables, and an
+independent all-levels-at-once assembly of the scheme.
+
+Readings of the paper taken here (each is also listed in the design notes):
+
+* n = interior unknowns, h = (b-a)/(n+1) (the paper's N is n+1).
+* The history term enters (3.3) with the minus sign of (3.1).
+* gamma, d_+-, f are sampled at t_{j+sigma}.
+* Strang circulant of a Toeplitz matrix with lags t_m:  c_k = t_k for
+  0 <= k <= floor(n/2), c_k = t_{k-n} otherwise; s(W^T) is taken as s(W)^T,
+  whose eigenvalues are the conjugates of those of s(W) as Sec. 3.2 states.
+* DFT sign convention lambda_k = sum_m c_m exp(-2 pi i m k / n).
+"""
+from __future__ import annotations
+
+import math
+from typing import Iterable, Optional
+
+import numpy as np
+
+__all__ = [
+    "grunwald_weights", "wsgd_lambdas", "wsgd_weights", "l21s_a", "l21s_b", "l21s_c",
+    "l21s_kappa", "eta", "matrix_Q", "toeplitz_W", "level_scalars", "level_L", "level_A",
+    "level_B", "history_term", "rhs", "level_solve", "march", "error_norms",
+    "strang_column", "circulant", "preconditioner_matrix", "circulant_eigenvalues",
+    "embedding_column", "apply_A_rows", "rhs_rows", "caputo_l21s",
+]
+
+
+# ---------------------------------------------------------------------------
+# Space discretisation: Lemma 2 (WSGD) with the recurrence of Lemma 3.
+# ---------------------------------------------------------------------------
+
+def grunwald_weights(beta: float, K: int) -> np.ndarray:
+    """g_k^(beta) = (-1)^k binom(beta, k) for k = 0..K (Lemma 2), evaluated by
+    the recurrence g_0 = 1, g_k = (1 - (beta+1)/k) g_{k-1} of Lemma 3."""
+    factors = np.empty(K + 1, dtype=np.float64)
+    factors[0] = 1.0
+    k = np.arange(1, K + 1, dtype=np.float64)
+    factors[1:] = 1.0 - (beta + 1.0) / k
+    return np.cumprod(factors)
+
+
+def wsgd_lambdas(beta: float):
+    """lambda_1, lambda_0, lambda_-1 of Lemma 2."""
+    lam1 = (beta * beta + 3.0 * beta + 2.0) / 12.0
+    lam0 = (4.0 - beta * beta) / 6.0
+    lamm1 = (beta * beta - 3.0 * beta + 2.0) / 12.0
+    return lam1, lam0, lamm1
+
+
+def wsgd_weights(beta: float, K: int) -> np.ndarray:
+    """omega_k^(beta), k = 0..K (Lemma 2):
+    omega_0 = l1 g_0, omega_1 = l1 g_1 + l0 g_0,
+    omega_k = l1 g_k + l0 g_{k-1} + l_-1 g_{k-2} (k >= 2)."""
+    g = grunwald_weights(beta, K)
+    lam1, lam0, lamm1 = wsgd_lambdas(beta)
+    w = lam1 * g
+    if K >= 1:
+        w[1:] += lam0 * g[:-1]
+    if K >= 2:
+        w[2:] += lamm1 * g[:-2]
+    return w
+
+
+# ---------------------------------------------------------------------------
+# Time discretisation: the L2-1sigma formula of Lemma 1.
+# ---------------------------------------------------------------------------
+
+def l21s_a(alpha: float, L: int) -> np.ndarray:
+    """a_0 = sigma^(1-alpha); a_l = (l+sigma)^(1-alpha) - (l-1+sigma)^(1-alpha)
+    for l = 1..L (Lemma 1)."""
+    sigma = 1.0 - alpha / 2.0
+    a = np.empty(L + 1, dtype=np.float64)
+    a[0] = sigma ** (1.0 - alpha)
+    for l in range(1, L + 1):
+        a[l] = (l + sigma) ** (1.0 - alpha) - (l - 1 + sigma) ** (1.0 - alpha)
+    return a
+
+
+def l21s_b(alpha: float, L: int) -> np.ndarray:
+    """b_l for l = 1..L (index 0 unused, set to 0) (Lemma 1):
+    b_l = [(l+sigma)^(2-alpha) - (l-1+sigma)^(2-alpha)]/(2-alpha)
+          - [(l+sigma)^(1-alpha) + (l-1+sigma)^(1-alpha)]/2."""
+    sigma = 1.0 - alpha / 2.0
+    b = np.zeros(L + 1, dtype=np.float64)
+    for l in range(1, L + 1):
+        b[l] = (((l + sigma) ** (2.0 - alpha) - (l - 1 + sigma) ** (2.0 - alpha)) / (2.0 - alpha)
+                - 0.5 * ((l + sigma) ** (1.0 - alpha) + (l - 1 + sigma) ** (1.0 - alpha)))
+    return b
+
+
+def l21s_c(alpha: float, j: int) -> np.ndarray:
+    """c_m^(alpha,sigma,j) for m = 0..j (Lemma 1).
+
+    j = 0: c_0 = a_0.  j >= 1: c_0 = a_0 + b_1; c_m = a_m + b_{m+1} - b_m for
+    1 <= m <= j-1; c_j = a_j - b_j."""
+    a = l21s_a(alpha, j + 1)
+    b = l21s_b(alpha, j + 1)
+    c = np.empty(j + 1, dtype=np.float64)
+    if j == 0:
+        c[0] = a[0]
+        return c
+    c[0] = a[0] + b[1]
+    for m in range(1, j):
+        c[m] = a[m] + b[m + 1] - b[m]
+    c[j] = a[j] - b[j]
+    return c
+
+
+def l21s_kappa(alpha: float, tau: float) -> float:
+    """tau^-alpha / Gamma(2 - alpha), the prefactor of Lemma 1."""
+    return tau ** (-alpha) / math.gamma(2.0 - alpha)
+
+
+def caputo_l21s(alpha: float, tau: float, values: np.ndarray, j: int) -> float:
+    """Delta^alpha_{0,t_{j+sigma}} u of Lemma 1 for u sampled at t_0..t_{j+1}."""
+    c = l21s_c(alpha, j)
+    acc = 0.0
+    for s in range(j + 1):
+        acc += c[j - s] * (values[s + 1] - values[s])
+    return l21s_kappa(alpha, tau) * acc
+
+
+def eta(alpha: float, tau: float, j: int) -> float:
+    """eta_j = c_0^(alpha,sigma,j) / (tau^alpha Gamma(2-alpha))  (Sec. 3, after (3.1))."""
+    return l21s_kappa(alpha, tau) * l21s_c(alpha, j)[0]
+
+
+# ---------------------------------------------------------------------------
+# Matrix form (3.1)-(3.3).
+# ---------------------------------------------------------------------------
+
+def matrix_Q(n: int) -> np.ndarray:
+    """Q of (3.2): +1 on the superdiagonal, -1 on the subdiagonal."""
+    Q = np.zeros((n, n))
+    i = np.arange(n - 1)
+    Q[i, i + 1] = 1.0
+    Q[i + 1, i] = -1.0
+    return Q
+
+
+def toeplitz_W(beta: float, n: int) -> np.ndarray:
+    """W_beta of (3.2): W[i, k] = omega_{i-k+1} for i - k + 1 >= 0, else 0."""
+    w = wsgd_weights(beta, n)
+    lag = np.arange(n)[:, None] - np.arange(n)[None, :] + 1
+    return np.where(lag >= 0, w[np.clip(lag, 0, n)], 0.0)
+
+
+def level_scalars(prob, j: int):
+    """(eta_j, gamma^(j+sigma), D_+^(j+sigma), D_-^(j+sigma)) for level j."""
+    t = prob.t_sigma(j)
+    return eta(prob.alpha, prob.tau, j), prob.gamma(t), prob.dplus(t), prob.dminus(t)
+
+
+def level_L(prob, j: int) -> np.ndarray:
+    """gamma/(2h) Q + D_+/h^beta W + D_-/h^beta W^T at t_{j+sigma}."""
+    _, gam, dp, dm = level_scalars(prob, j)
+    n, h, beta = prob.n, prob.h, prob.beta
+    W = toeplitz_W(beta, n)
+    return gam / (2.0 * h) * matrix_Q(n) + dp / h ** beta * W + dm / h ** beta * W.T
+
+
+def level_A(prob, j: int) -> np.ndarray:
+    """A^(j+sigma) = eta_j I - sigma L  (3.3)."""
+    e = level_scalars(prob, j)[0]
+    return e * np.eye(prob.n) - prob.sigma * level_L(prob, j)
+
+
+def level_B(prob, j: int) -> np.ndarray:
+    """B^(j+sigma) = eta_j I + (1 - sigma) L  (3.3)."""
+    e = level_scalars(prob, j)[0]
+    return e * np.eye(prob.n) + (1.0 - prob.sigma) * level_L(prob, j)
+
+
+def history_term(prob, U: np.ndarray, j: int) -> np.ndarray:
+    """tau^-alpha/Gamma(2-alpha) * sum_{s=0}^{j-1} c_{j-s}^(j) (u^{s+1} - u^s),
+    the delta u^(j) of (3.3) (zero for j = 0)."""
+    n = U.shape[1]
+    acc = np.zeros(n)
+    if j == 0:
+        return acc
+    c = l21s_c(prob.alpha, j)
+    for s in range(j):
+        acc += c[j - s] * (U[s + 1] - U[s])
+    return l21s_kappa(prob.alpha, prob.tau) * acc
+
+
+def rhs(prob, U: np.ndarray, j: int, f_j: np.ndarray) -> np.ndarray:
+    """g^(j+1) = B^(j+sigma) u^j - history + f^(j+sigma)  ((3.1), Algorithm 2)."""
+    return level_B(prob, j) @ U[j] - history_term(prob, U, j) + f_j
+
+
+def level_solve(prob, U: np.ndarray, j: int, f_j: np.ndarray) -> np.ndarray:
+    """u^{j+1} = (A^(j+sigma))^{-1} g^(j+1) by Gaussian elimination."""
+    return np.linalg.solve(level_A(prob, j), rhs(prob, U, j, f_j))
+
+
+def march(prob, f_levels: Optional[Iterable[np.ndarray]] = None, levels: Optional[int] = None,
+          u0: Optional[np.ndarray] = None) -> np.ndarray:
+    """Algorithm 2 with a dense direct solve at every level.
+
+    Returns U with U[j] = u^j on the interior nodes, j = 0..levels."""
+    M = prob.M if levels is None else levels
+    U = np.zeros((M + 1, prob.n))
+    U[0] = prob.initial_vector() if u0 is None else u0
+    flist = list(f_levels) if f_levels is not None else None
+    for j in range(M):
+        f_j = flist[j] if flist is not None else prob.source_level(j)
+        U[j + 1] = level_solve(prob, U, j, f_j)
+    return U
+
+
+def error_norms(prob, U: np.ndarray):
+    """(max_j ||E^j||_0, max_{i,j} |E_i^j|) with ||v||_0 = sqrt(h sum v_i^2)
+    (Sec. 2.2 and the tables of Sec. 4)."""
+    x = prob.x_interior()
+    l2 = 0.0
+    cmax = 0.0
+    for j in range(U.shape[0]):
+        E = U[j] - prob.exact(x, j * prob.tau)
+        l2 = max(l2, math.sqrt(prob.h * float(E @ E)))
+        cmax = max(cmax, float(np.max(np.abs(E))))
+    return l2, cmax
+
+
+# ---------------------------------------------------------------------------
+# Circulant preconditioner (3.7) and circulant spectra (Sec. 3.2, Lemma 8).
+# ---------------------------------------------------------------------------
+
+def strang_column(lag_value, n: int) -> np.ndarray:
+    """First column of the Strang circulant of a Toeplitz matrix whose entry
+    at lag m = i - k is lag_value(m):  c_k = t_k (0 <= k <= floor(n/2)),
+    c_k = t_{k-n} (floor(n/2) < k < n)."""
+    c = np.zeros(n)
+    for k in range(n):
+        c[k] = lag_value(k) if k <= n // 2 else lag_value(k - n)
+    return c
+
+
+def circulant(col: np.ndarray) -> np.ndarray:
+    """Dense circulant C[i, k] = col[(i - k) mod n]."""
+    n = len(col)
+    i = np.arange(n)[:, None]
+    k = np.arange(n)[None, :]
+    return col[(i - k) % n]
+
+
+def _W_lag(beta: float, n: int):
+    w = wsgd_weights(beta, n + 1)
+
+    def lag(m):
+        return w[m + 1] if m >= -1 else 0.0
+    return lag
+
+
+def _Q_lag(m):
+    return -1.0 if m == 1 else (1.0 if m == -1 else 0.0)
+
+
+def preconditioner_matrix(prob, j: int) -> np.ndarray:
+    """P^(j+sigma) = eta_j I - sigma (gamma/(2h) s(Q) + D_+/h^beta s(W)
+    + D_-/h^beta s(W)^T)  (3.7), as a dense matrix."""
+    e, gam, dp, dm = level_scalars(prob, j)
+    n, h, beta = prob.n, prob.h, prob.beta
+    sQ = circulant(strang_column(_Q_lag, n))
+    sW = circulant(strang_column(_W_lag(beta, n), n))
+    return e * np.eye(n) - prob.sigma * (gam / (2.0 * h) * sQ + dp / h ** beta * sW
+                                         + dm / h ** beta * sW.T)
+
+
+def circulant_eigenvalues(col: np.ndarray) -> np.ndarray:
+    """lambda_k = sum_m col_m exp(-2 pi i m k / n): the eigenvalues of the
+    circulant with first column col, via the library FFT."""
+    return np.fft.fft(col)
+
+
+def embedding_column(beta: float, n: int, L: int) -> np.ndarray:
+    """First column of a length-L (L >= 2n - 1) circulant whose leading n x n
+    block is W_beta: c_m = omega_{m+1} (0 <= m < n), c_{L-1} = omega_0, else 0."""
+    if L < 2 * n - 1:
+        raise ValueError("embedding length must be at least 2n - 1")
+    w = wsgd_weights(beta, n)
+    c = np.zeros(L)
+    c[:n] = w[1:n + 1]
+    c[L - 1] += w[0]
+    return c
+
+
+# ---------------------------------------------------------------------------
+# Row-by-row evaluation for large n (no dense matrix).
+# ---------------------------------------------------------------------------
+
+def apply_A_rows(prob, j: int, u: np.ndarray, rows: np.ndarray, which: str = "A") -> np.ndarray:
+    """(A^(j+sigma) u)_i (or B) for the given 0-based rows by direct sums:
+    (Q u)_i = u_{i+1} - u_{i-1};  (W u)_i = sum_{m <= i+1} omega_{i-m+1} u_m;
+    (W^T u)_i = sum_{m >= i-1} omega_{m-i+1} u_m."""
+    e, gam, dp, dm = level_scalars(prob, j)
+    n, h, beta, sigma = prob.n, prob.h, prob.beta, prob.sigma
+    w = wsgd_weights(beta, n + 1)
+    out = np.empty(len(rows))
+    for r, i in enumerate(rows):
+        i = int(i)
+        qu = (u[i + 1] if i + 1 < n else 0.0) - (u[i - 1] if i >= 1 else 0.0)
+        hi = min(i + 1, n - 1)
+        # W row: m = 0..hi, weight omega_{i-m+1}
+        wu = float(np.dot(w[i + 1 - hi:i + 2][::-1], u[0:hi + 1]))
+        lo = max(i - 1, 0)
+        # W^T row: m = lo..n-1, weight omega_{m-i+1}
+        wtu = float(np.dot(w[lo - i + 1:n - i + 1], u[lo:n]))
+        Lu = gam / (2.0 * h) * qu + dp / h ** beta * wu + dm / h ** beta * wtu
+        out[r] = e * u[i] - sigma * Lu if which == "A" else e * u[i] + (1.0 - sigma) * Lu
+    return out
+
+
+def rhs_rows(prob, U: np.ndarray, j: int, f_j: np.ndarray, rows: np.ndarray) -> np.ndarray:
+    """g_i^(j+1) for the given rows (same definition as ``rhs``)."""
+    Bu = apply_A_rows(prob, j, U[j], rows, which="B")
+    if j == 0:
+        return Bu + f_j[rows]
+    c = l21s_c(prob.alpha, j)
+    acc = np.zeros(len(rows))
+    for s in range(j):
+        acc += c[j - s] * (U[s + 1][rows] - U[s][rows])
+    return Bu - l21s_kappa(prob.alpha, prob.tau) * acc + f_j[rows]

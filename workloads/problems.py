@@ -1,0 +1,294 @@
+"""Problem statements and manufactured solutions for the TSFCDE (1.1).
+
+Conventions (shared by the oracle and the GPU path):
+
+* ``n`` is the number of interior unknowns; the mesh is x_i = a + i*h,
+  i = 0..n+1, h = (b - a)/(n + 1).  The paper's N (number of subintervals,
+  Sec. 2.1) is therefore n + 1.
+* ``M`` is the number of time steps, tau = T/M, t_j = j*tau.
+* Coefficients gamma(t), d_+(t), d_-(t) and the source f(x, t) are plain
+  callables; the scheme samples them at t_{j+sigma} (Sec. 2.1).
+
+Manufactured solutions have the separable form u(x, t) = theta(t) * P(x),
+with theta a finite sum of powers of t and P a polynomial carrying a double
+root at both ends of [a, b].  The source f is then closed form:
+
+  Caputo derivative of t^e (e > 0):  Gamma(e+1)/Gamma(e+1-alpha) t^(e-alpha)
+  left RL derivative of (x-a)^k:      Gamma(k+1)/Gamma(k+1-beta) (x-a)^(k-beta)
+  right RL derivative of (b-x)^k:     Gamma(k+1)/Gamma(k+1-beta) (b-x)^(k-beta)
+
+(definitions (1.2)-(1.4)), and f = D_t^alpha u - gamma u_x - d_+ D_left u
+- d_- D_right u by (1.1).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, Optional, Sequence, Tuple
+
+import numpy as np
+
+SEED_BASE = 20160301
+
+
+@dataclass
+class ManufacturedSolution:
+    """u(x, t) = theta(t) * P(x).
+
+    ``theta_terms``: list of (coefficient, exponent) pairs, theta(t) = sum c t^e.
+    ``poly_s``: coefficients of P in powers of s = x - a (ascending order);
+    entries for s^0 and s^1 must vanish (double root at x = a), and the
+    polynomial must have a double root at x = b too.
+    """
+
+    theta_terms: Sequence[Tuple[float, float]]
+    poly_s: np.ndarray
+    a: float = 0.0
+    b: float = 1.0
+
+    def __post_init__(self):
+        p = np.asarray(self.poly_s, dtype=np.float64)
+        self.poly_s = p
+        # Coefficients of P in powers of r = b - x: substitute s = (b-a) - r.
+        ell = self.b - self.a
+        deg = len(p) - 1
+        q = np.zeros(deg + 1)
+        for k, pk in enumerate(p):
+            # ((b-a) - r)^k = sum_m C(k,m) (b-a)^(k-m) (-r)^m
+            for m in range(k + 1):
+                q[m] += pk * math.comb(k, m) * ell ** (k - m) * (-1.0) ** m
+        # P has a double root at x = b by construction; the r^0, r^1
+        # coefficients are zero in exact arithmetic and are set so here, so
+        # that no rounding residue multiplies the singular (b-x)^(k-beta).
+        q[:2] = 0.0
+        if abs(p[0]) > 0 or abs(p[1]) > 0:
+            raise ValueError("P must have a double root at x = a")
+        self.poly_r = q
+
+    # --- time factor -----------------------------------------------------
+    def theta(self, t):
+        return sum(c * (t ** e if e != 0 else 1.0) for c, e in self.theta_terms)
+
+    def caputo_theta(self, t, alpha):
+        out = 0.0
+        for c, e in self.theta_terms:
+            if e == 0:
+                continue
+            out += c * math.gamma(e + 1.0) / math.gamma(e + 1.0 - alpha) * t ** (e - alpha)
+        return out
+
+    # --- space factor ----------------------------------------------------
+    def P(self, x):
+        s = np.asarray(x, dtype=np.float64) - self.a
+        return np.polynomial.polynomial.polyval(s, self.poly_s)
+
+    def dP(self, x):
+        s = np.asarray(x, dtype=np.float64) - self.a
+        return np.polynomial.polynomial.polyval(s, np.polynomial.polynomial.polyder(self.poly_s))
+
+    def rl_left(self, x, beta):
+        s = np.asarray(x, dtype=np.float64) - self.a
+        out = np.zeros_like(s)
+        for k, pk in enumerate(self.poly_s):
+            if pk == 0.0:
+                continue
+            out += pk * math.gamma(k + 1.0) / math.gamma(k + 1.0 - beta) * s ** (k - beta)
+        return out
+
+    def rl_right(self, x, beta):
+        r = self.b - np.asarray(x, dtype=np.float64)
+        out = np.zeros_like(r)
+        for k, qk in enumerate(self.poly_r):
+            if qk == 0.0:
+                continue
+            out += qk * math.gamma(k + 1.0) / math.gamma(k + 1.0 - beta) * r ** (k - beta)
+        return out
+
+    def u(self, x, t):
+        return self.theta(t) * self.P(x)
+
+    def profiles(self, x, beta):
+        """The four x-profiles [P, P', D_left P, D_right P] (shape 4 x len(x))."""
+        return np.stack([self.P(x), self.dP(x), self.rl_left(x, beta), self.rl_right(x, beta)])
+
+    def profile_coeffs(self, t, alpha, gamma, dplus, dminus):
+        """Scalars c(t) with f(x, t) = sum_k c_k(t) * profiles_k(x)."""
+        th = self.theta(t)
+        return np.array([self.caputo_theta(t, alpha), -th * gamma(t), -th * dplus(t), -th * dminus(t)])
+
+
+@dataclass
+class Problem:
+    """Problem (1.1) with its discretisation sizes.
+
+    f(x, t) takes an array x and a scalar t; phi(x) an array x.
+    """
+
+    alpha: float
+    beta: float
+    n: int
+    M: int
+    gamma: Callable[[float], float]
+    dplus: Callable[[float], float]
+    dminus: Callable[[float], float]
+    a: float = 0.0
+    b: float = 1.0
+    T: float = 1.0
+    solution: Optional[ManufacturedSolution] = None
+    phi_fn: Optional[Callable] = None
+    f_fn: Optional[Callable] = None
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    # --- mesh ------------------------------------------------------------
+    @property
+    def h(self) -> float:
+        return (self.b - self.a) / (self.n + 1)
+
+    @property
+    def tau(self) -> float:
+        return self.T / self.M
+
+    @property
+    def sigma(self) -> float:
+        return 1.0 - self.alpha / 2.0
+
+    def x_interior(self) -> np.ndarray:
+        return self.a + self.h * np.arange(1, self.n + 1, dtype=np.float64)
+
+    def t_sigma(self, j: int) -> float:
+        """t_{j+sigma} = (j + sigma) * tau (Lemma 1)."""
+        return (j + self.sigma) * self.tau
+
+    # --- data ------------------------------------------------------------
+    def phi(self, x) -> np.ndarray:
+        if self.phi_fn is not None:
+            return np.asarray(self.phi_fn(x), dtype=np.float64)
+        if self.solution is not None:
+            return self.solution.u(x, 0.0)
+        return np.zeros_like(np.asarray(x, dtype=np.float64))
+
+    def f(self, x, t) -> np.ndarray:
+        if self.f_fn is not None:
+            return np.asarray(self.f_fn(x, t), dtype=np.float64)
+        if self.solution is None:
+            return np.zeros_like(np.asarray(x, dtype=np.float64))
+        sol = self.solution
+        return (sol.caputo_theta(t, self.alpha) * sol.P(x)
+                - sol.theta(t) * (self.gamma(t) * sol.dP(x)
+                                  + self.dplus(t) * sol.rl_left(x, self.beta)
+                                  + self.dminus(t) * sol.rl_right(x, self.beta)))
+
+    def exact(self, x, t) -> np.ndarray:
+        if self.solution is None:
+            raise ValueError("no closed-form solution for this problem")
+        return self.solution.u(x, t)
+
+    # --- level samples ---------------------------------------------------
+    def coefficient_samples(self):
+        """gamma, d_+, d_- at t_{j+sigma}, j = 0..M-1 (arrays of length M)."""
+        ts = [self.t_sigma(j) for j in range(self.M)]
+        return (np.array([self.gamma(t) for t in ts], dtype=np.float64),
+                np.array([self.dplus(t) for t in ts], dtype=np.float64),
+                np.array([self.dminus(t) for t in ts], dtype=np.float64))
+
+    def initial_vector(self) -> np.ndarray:
+        return self.phi(self.x_interior())
+
+    def source_level(self, j: int) -> np.ndarray:
+        """f(x_i, t_{j+sigma}) on the interior nodes."""
+        return self.f(self.x_interior(), self.t_sigma(j))
+
+    def source_profiles(self):
+        """(profiles[4, n], coeffs[M, 4]) with f_j = coeffs[j] @ profiles.
+
+        Available for manufactured problems without a custom f; it lets a
+        caller build all M source vectors as one small matrix product.
+        """
+        if self.solution is None or self.f_fn is not None:
+            raise ValueError("separable source only for manufactured problems")
+        prof = self.solution.profiles(self.x_interior(), self.beta)
+        co = np.stack([self.solution.profile_coeffs(self.t_sigma(j), self.alpha, self.gamma,
+                                                    self.dplus, self.dminus)
+                       for j in range(self.M)])
+        return prof, co
+
+
+def _x2_one_minus_x2(extra=(1.0,)):
+    """Coefficients in s = x of x^2 (1-x)^2 * (e0 + e1 x + e2 x^2 ...) on [0, 1]."""
+    base = np.array([0.0, 0.0, 1.0, -2.0, 1.0])
+    return np.polynomial.polynomial.polymul(base, np.asarray(extra, dtype=np.float64))
+
+
+def example1(alpha: float, beta: float, N: int, M: Optional[int] = None) -> Problem:
+    """Example 1 of Sec. 4: d_+ = 0.8, d_- = 0.5, gamma = -0.1 on [0,1]x[0,1],
+    u = (t^(2+alpha) + 1) x^2 (1-x)^2.  ``N`` is the paper's number of
+    subintervals (h = 1/N); ``M`` defaults to N (tau = h)."""
+    M = N if M is None else M
+    sol = ManufacturedSolution([(1.0, 2.0 + alpha), (1.0, 0.0)], _x2_one_minus_x2())
+    return Problem(alpha=alpha, beta=beta, n=N - 1, M=M,
+                   gamma=lambda t: -0.1, dplus=lambda t: 0.8, dminus=lambda t: 0.5,
+                   solution=sol, name=f"example1(alpha={alpha},beta={beta},N={N},M={M})")
+
+
+def example2(alpha: float, beta: float, N: int, M: Optional[int] = None) -> Problem:
+    """Example 2 of Sec. 4: d_+ = 9 sin t, d_- = 4 sin t, gamma = -t, same
+    solution family as Example 1 (the exact solution printed there drops the
+    '+1' that its initial condition and source require)."""
+    M = N if M is None else M
+    sol = ManufacturedSolution([(1.0, 2.0 + alpha), (1.0, 0.0)], _x2_one_minus_x2())
+    return Problem(alpha=alpha, beta=beta, n=N - 1, M=M,
+                   gamma=lambda t: -t, dplus=lambda t: 9.0 * math.sin(t),
+                   dminus=lambda t: 4.0 * math.sin(t),
+                   solution=sol, name=f"example2(alpha={alpha},beta={beta},N={N},M={M})")
+
+
+def config_small(n: int = 64, M: int = 64, alpha: float = 0.5, beta: float = 1.5) -> Problem:
+    """Small plain-method case: alpha=0.5, beta=1.5, n=64 interior points, M=64,
+    gamma = -(1+t)/2, d_+ = 1+t, d_- = 0.5(1+t), u = t^2 x^2 (1-x)^2, phi = 0."""
+    sol = ManufacturedSolution([(1.0, 2.0)], _x2_one_minus_x2())
+    return Problem(alpha=alpha, beta=beta, n=n, M=M,
+                   gamma=lambda t: -(1.0 + t) / 2.0, dplus=lambda t: 1.0 + t,
+                   dminus=lambda t: 0.5 * (1.0 + t), solution=sol,
+                   name=f"small(n={n},M={M},alpha={alpha},beta={beta})")
+
+
+def config_large(n: int = 1 << 20, M: int = 512, alpha: float = 0.7, beta: float = 1.8,
+                 seed: int = SEED_BASE + 1) -> Problem:
+    """Large single-instance case: alpha=0.7, beta=1.8, n=2^20, M=512, the
+    coefficient family of ``config_small`` and
+    u = t^2 x^2 (1-x)^2 (A0 + A1 x + A2 x^2) with A_i ~ U(0.5, 2) drawn from
+    ``numpy.random.default_rng(seed)``."""
+    rng = np.random.default_rng(seed)
+    amps = rng.uniform(0.5, 2.0, size=3)
+    sol = ManufacturedSolution([(1.0, 2.0)], _x2_one_minus_x2(amps))
+    return Problem(alpha=alpha, beta=beta, n=n, M=M,
+                   gamma=lambda t: -(1.0 + t) / 2.0, dplus=lambda t: 1.0 + t,
+                   dminus=lambda t: 0.5 * (1.0 + t), solution=sol,
+                   name=f"large(n={n},M={M},alpha={alpha},beta={beta})",
+                   meta={"amplitudes": amps.tolist(), "seed": seed})
+
+
+def batched_instances(count: int = 512, M: int = 128, nmin: int = 1 << 10, nmax: int = 1 << 16,
+                      seed: int = SEED_BASE + 3):
+    """Independent instances of uneven size: n = round(exp(U(ln nmin, ln nmax))),
+    alpha ~ U(0.1, 0.95), beta ~ U(1.1, 1.95), d_+- = c_+-(1+t) with
+    c_+- ~ U(0.2, 2), gamma = g (1+t) with g ~ U(-1, 1), and a per-instance
+    solution u = A t^2 x^2 (1-x)^2 with A ~ U(0.5, 2)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        alpha = float(rng.uniform(0.1, 0.95))
+        beta = float(rng.uniform(1.1, 1.95))
+        cp, cm = (float(v) for v in rng.uniform(0.2, 2.0, size=2))
+        g = float(rng.uniform(-1.0, 1.0))
+        A = float(rng.uniform(0.5, 2.0))
+        sol = ManufacturedSolution([(A, 2.0)], _x2_one_minus_x2())
+        out.append(Problem(alpha=alpha, beta=beta, n=n, M=M,
+                           gamma=(lambda t, g=g: g * (1.0 + t)),
+                           dplus=(lambda t, c=cp: c * (1.0 + t)),
+                           dminus=(lambda t, c=cm: c * (1.0 + t)),
+                           solution=sol, name=f"batch[{k}](n={n})",
+                           meta={"c_plus": cp, "c_minus": cm, "g": g, "A": A}))
+    return out
