@@ -1,0 +1,197 @@
+/*
+ * tsfcde.h -- C ABI of the MI355X (gfx950) time-level solver for the
+ * time-space fractional convection-diffusion equation (TSFCDE)
+ *
+ *   D_t^alpha u = gamma(t) u_x + d_+(t) aD_x^beta u + d_-(t) xD_b^beta u + f,
+ *   u(x,0) = phi(x),  u(a,t) = u(b,t) = 0,                       problem (1.1)
+ *
+ * of Gu, Huang, Ji, Carpentieri and Alikhanov, arXiv:1603.00279.
+ *
+ * Each call to tsfcde_step advances the implicit difference scheme (IDS) by
+ * one time level (Algorithm 2): it assembles the right-hand side
+ * g = B^(j+sigma) u^j - delta u^(j) + f^(j+sigma) of (3.3), including the
+ * L2-1sigma history sum over all earlier levels (Lemma 1), and solves the
+ * nonsymmetric Toeplitz system A^(j+sigma) u^(j+1) = g by CGS with the Strang
+ * circulant preconditioner (3.7) (Sec. 3.2).  Every Toeplitz product is an
+ * FFT over a circulant embedding of length 2n; every preconditioner solve is
+ * an n-point circulant FFT solve.  All of it runs in the library's own HIP
+ * kernels on the stream given to tsfcde_plan.
+ *
+ * Conventions
+ *  - n is the number of interior unknowns, h = (b-a)/(n+1); the paper's N
+ *    (number of subintervals) is n+1.  M is the number of time steps,
+ *    tau = T/M.  gamma, d_+, d_- and f are sampled at t_{j+sigma},
+ *    sigma = 1 - alpha/2 (Lemma 1, Sec. 2.1).
+ *  - All device pointers are plain HIP device addresses (e.g. the data
+ *    pointer of a torch tensor on the same device).  Vectors are contiguous
+ *    FP64 arrays of n values ordered x_1..x_n.
+ *  - Every call returns a status: TSFCDE_OK (0) or a negative TSFCDE_E*
+ *    code; tsfcde_strerror names it.  Invalid arguments are rejected on the
+ *    host before any device work.
+ *  - A plan is bound to one device and one stream and is not thread-safe.
+ *    Device work is asynchronous on that stream except where a call is
+ *    documented to synchronize (tsfcde_step/tsfcde_solve synchronize on the
+ *    convergence flag between Krylov chunks).
+ */
+#ifndef TSFCDE_H
+#define TSFCDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------- */
+#define TSFCDE_OK 0
+#define TSFCDE_EINVAL (-1)       /* argument out of range (see tsfcde_plan) */
+#define TSFCDE_ENOMEM (-2)       /* workspace too small                      */
+#define TSFCDE_EDEVICE (-3)      /* a HIP runtime call failed                */
+#define TSFCDE_ENOCONV (-4)      /* maxit reached; solution/stats still set  */
+#define TSFCDE_EBREAKDOWN (-5)   /* CGS breakdown (rho or r~'v = 0)          */
+#define TSFCDE_ENONFINITE (-6)   /* NaN/Inf met in the iteration             */
+#define TSFCDE_EDONE (-7)        /* all M levels already computed            */
+#define TSFCDE_EUNSUPPORTED (-8) /* valid problem outside this build's sizes */
+
+/* ---- options -------------------------------------------------------- */
+#define TSFCDE_FP64 0            /* every step in FP64                       */
+#define TSFCDE_WS_ZERO 0         /* Krylov initial guess 0 (as in Sec. 4)    */
+#define TSFCDE_WS_PREV 1         /* initial guess u^j (previous level)       */
+#define TSFCDE_FLAG_TRUE_RESIDUAL 1 /* also compute |g - A u|/|g| per level  */
+#define TSFCDE_FLAG_VERIFY 2     /* on recursive convergence, recompute r = g - A x
+                                    and restart CGS from x while the true residual
+                                    is above rtol |g| and still falling (at most 3
+                                    restarts); also restarts once per breakdown  */
+
+/* operators for tsfcde_apply */
+#define TSFCDE_OP_A 0            /* y = A^(j+sigma) x      (3.3)            */
+#define TSFCDE_OP_B 1            /* y = B^(j+sigma) x      (3.3)            */
+#define TSFCDE_OP_PINV 2         /* y = (P^(j+sigma))^{-1} x   (3.7)        */
+
+/* spectra for tsfcde_spectrum */
+#define TSFCDE_SPEC_EMBED 0      /* DFT of the length-2n circulant embedding of W_beta */
+#define TSFCDE_SPEC_STRANG 1     /* DFT of the n-point Strang circulant s(W_beta)      */
+
+typedef double (*tsfcde_coef_fn)(double t, void *user);
+typedef double (*tsfcde_ic_fn)(double x, void *user);
+
+/* Problem statement (1.1) plus solver options.  The caller owns it; the
+ * plan copies what it needs during tsfcde_plan. */
+typedef struct tsfcde_problem {
+    double alpha;      /* time order, 0 < alpha <= 1                        */
+    double beta;       /* space order, 1 < beta <= 2                        */
+    double a, b;       /* space interval, a < b                             */
+    double T;          /* final time, T > 0                                 */
+    int64_t n;         /* interior unknowns (this build: power of two >= 16) */
+    int64_t M;         /* time steps, M >= 1                                */
+    /* gamma(t), d_+(t), d_-(t): either callbacks (called on the host during
+     * tsfcde_plan at t_{j+sigma}, j = 0..M-1) or, when a callback is NULL,
+     * host arrays of those M samples.  d_+- must be >= 0 (problem (1.1);
+     * Theorem 3.1 needs it for the preconditioner to be invertible). */
+    tsfcde_coef_fn gamma, dplus, dminus;
+    void *coef_user;
+    const double *gamma_at, *dplus_at, *dminus_at;
+    /* phi(x): callback on the host at x_1..x_n during tsfcde_plan; NULL means
+     * u^0 = 0 unless tsfcde_set_state provides it. */
+    tsfcde_ic_fn phi;
+    void *phi_user;
+    double rtol;       /* Krylov stop: |r_k|_2 <= rtol |g|_2 (<= 0: 1e-10)   */
+    int32_t maxit;     /* CGS iterations per level (<= 0: 500)              */
+    int32_t precision; /* TSFCDE_FP64                                       */
+    int32_t warm_start;/* TSFCDE_WS_ZERO or TSFCDE_WS_PREV                  */
+    int32_t flags;     /* TSFCDE_FLAG_*                                     */
+} tsfcde_problem;
+
+typedef struct tsfcde_stats {
+    int32_t iters;        /* CGS iterations of this level                    */
+    int32_t outer_iters;  /* refinement sweeps (1 for the plain FP64 path)   */
+    int32_t restarts;     /* CGS restarts (breakdown or true-residual gap)   */
+    int32_t status;       /* TSFCDE_OK or the level's error code             */
+    double relres;        /* recursive |r_k|_2 / |g|_2 at exit               */
+    double relres_true;   /* |g - A u|_2/|g|_2 (FLAG_TRUE_RESIDUAL), else -1 */
+    double backward_err;  /* reserved (-1)                                   */
+    double seconds;       /* host wall time of the level                     */
+} tsfcde_stats;
+
+typedef struct tsfcde_plan_s *tsfcde_plan_t;
+
+/* Device workspace needed by a plan for this problem, in bytes.  Returns
+ * TSFCDE_EINVAL / TSFCDE_EUNSUPPORTED for a problem tsfcde_plan would refuse. */
+int tsfcde_workspace_bytes(const tsfcde_problem *prob, size_t *bytes);
+
+/* Validate the problem, sample the coefficients, build the L2-1sigma tables
+ * (Lemma 1), the WSGD weights (Lemma 2) and the two circulant spectra
+ * (Sec. 3.2) on the device.  d_workspace: caller-owned device memory of at
+ * least tsfcde_workspace_bytes bytes, 256-byte aligned, kept alive until
+ * tsfcde_destroy.  stream: a hipStream_t (NULL = default stream).  On success
+ * *out is a plan at level 0 with u^0 = phi(x_i). */
+int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, void *stream,
+                tsfcde_plan_t *out);
+
+/* Set the stored levels u^0..u^level from d_U ((level+1) x n, row-major,
+ * device) and make `level` the current level (checkpoint resume; test
+ * inputs).  0 <= level <= M. */
+int tsfcde_set_state(tsfcde_plan_t plan, int64_t level, const double *d_U);
+
+/* Advance one level j -> j+1 (Algorithm 2, one pass of its loop).
+ * d_f: f(x_i, t_{j+sigma}) on the device (n values), or NULL for f = 0.
+ * d_u_out: optional device copy of u^{j+1} (n values) or NULL.
+ * st: optional per-level statistics.  Returns TSFCDE_ENOCONV /
+ * TSFCDE_EBREAKDOWN / TSFCDE_ENONFINITE with u^{j+1} set to the last iterate;
+ * TSFCDE_EDONE when all M levels are done. */
+int tsfcde_step(tsfcde_plan_t plan, const double *d_f, double *d_u_out, tsfcde_stats *st);
+
+/* Run every remaining level.  d_F: device array whose row j (stride ldF
+ * doubles, ldF >= n) holds f at t_{j+sigma} for absolute level j, or NULL for
+ * f = 0.  d_U_out: optional device copy of U ((M+1) x n).  per_level:
+ * optional host array of M stats (entries of already-computed levels are
+ * left untouched).  Stops at the first level that fails and returns its code. */
+int tsfcde_solve(tsfcde_plan_t plan, const double *d_F, int64_t ldF, double *d_U_out,
+                 tsfcde_stats *per_level);
+
+/* y = op x at level j (0 <= j < M) for op in TSFCDE_OP_*; device vectors of
+ * n values; d_x and d_y must not overlap the plan's workspace. */
+int tsfcde_apply(tsfcde_plan_t plan, int32_t op, int64_t j, const double *d_x, double *d_y);
+
+/* Right-hand side g of (3.3) for level j from the stored levels u^0..u^j
+ * (requires j <= current level) and f (device, or NULL for 0). */
+int tsfcde_rhs(tsfcde_plan_t plan, int64_t j, const double *d_f, double *d_g);
+
+/* WSGD weights omega_0..omega_n (Lemma 2) into d_w (n+1 doubles, device). */
+int tsfcde_weights(tsfcde_plan_t plan, double *d_w);
+
+/* Circulant spectra in natural frequency order as interleaved complex FP64:
+ * TSFCDE_SPEC_EMBED: DFT_{2n} of the embedding column of W_beta,
+ *   k = 0..n (n+1 complex values);
+ * TSFCDE_SPEC_STRANG: DFT_n of the Strang column of W_beta, k = 0..n/2
+ *   (n/2+1 complex values).  DFT sign: lambda_k = sum_m c_m e^{-2 pi i mk/L}. */
+int tsfcde_spectrum(tsfcde_plan_t plan, int32_t which, double *d_out);
+
+/* Device pointer to the stored levels U ((M+1) x n, row j = u^j), owned by
+ * the plan; valid until tsfcde_destroy. */
+const double *tsfcde_history(tsfcde_plan_t plan);
+
+/* Current level j (u^0..u^j are stored). */
+int64_t tsfcde_level(tsfcde_plan_t plan);
+
+/* Per-kernel timing with HIP events recorded on the plan's stream.
+ * kernel_class: 0 = history sum, 1 = FFT column passes, 2 = FFT middle
+ * passes (row FFTs with the symbol multiply/divide), 3 = all kernels of a
+ * Krylov iteration chunk.  enable != 0 starts recording and clears the
+ * totals; tsfcde_profile_read synchronizes the stream and returns the number
+ * of recorded launches and their summed duration in milliseconds. */
+int tsfcde_profile(tsfcde_plan_t plan, int32_t kernel_class, int32_t enable);
+int tsfcde_profile_read(tsfcde_plan_t plan, int32_t kernel_class, int64_t *launches,
+                        double *milliseconds);
+
+/* Release the plan (host state only; the caller frees the workspace). */
+int tsfcde_destroy(tsfcde_plan_t plan);
+
+/* Static description of a status code. */
+const char *tsfcde_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSFCDE_H */

@@ -1,0 +1,14 @@
+"""MI355X (gfx950) time-level solver for the time-space fractional
+convection-diffusion equation of Gu, Huang, Ji, Carpentieri and Alikhanov
+(arXiv:1603.00279): the implicit difference scheme's per-level right-hand side
+with the L2-1sigma history sum, and the Strang-preconditioned CGS solve of the
+nonsymmetric Toeplitz system, in hand-written HIP kernels behind a C ABI
+(include/tsfcde.h).
+"""
+from ._native import (  # noqa: F401
+    TSFCDE_OK, TSFCDE_EINVAL, TSFCDE_ENOMEM, TSFCDE_EDEVICE, TSFCDE_ENOCONV, TSFCDE_EBREAKDOWN,
+    TSFCDE_ENONFINITE, TSFCDE_EDONE, TSFCDE_EUNSUPPORTED, TSFCDE_FP64, TSFCDE_WS_ZERO, TSFCDE_WS_PREV,
+    TSFCDE_FLAG_TRUE_RESIDUAL, TSFCDE_FLAG_VERIFY, TSFCDE_OP_A, TSFCDE_OP_B, TSFCDE_OP_PINV, TSFCDE_SPEC_EMBED,
+    TSFCDE_SPEC_STRANG, TsfcdeError, lib, header_symbols,
+)
+from .solver import TimeLevelSolver  # noqa: F401

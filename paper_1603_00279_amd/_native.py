@@ -1,0 +1,113 @@
+"""ctypes binding of libtsfcde.so (declarations in include/tsfcde.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  torch is imported first so that the library binds to the HIP
+runtime torch has already loaded (one runtime per process).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_void_p, c_char_p
+
+import torch  # noqa: F401  -- must precede loading the HIP library
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libtsfcde.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "tsfcde.h")
+
+COEF_FN = ctypes.CFUNCTYPE(c_double, c_double, c_void_p)
+IC_FN = ctypes.CFUNCTYPE(c_double, c_double, c_void_p)
+
+TSFCDE_OK = 0
+STATUS = {0: "TSFCDE_OK", -1: "TSFCDE_EINVAL", -2: "TSFCDE_ENOMEM", -3: "TSFCDE_EDEVICE",
+          -4: "TSFCDE_ENOCONV", -5: "TSFCDE_EBREAKDOWN", -6: "TSFCDE_ENONFINITE",
+          -7: "TSFCDE_EDONE", -8: "TSFCDE_EUNSUPPORTED"}
+TSFCDE_EINVAL, TSFCDE_ENOMEM, TSFCDE_EDEVICE = -1, -2, -3
+TSFCDE_ENOCONV, TSFCDE_EBREAKDOWN, TSFCDE_ENONFINITE = -4, -5, -6
+TSFCDE_EDONE, TSFCDE_EUNSUPPORTED = -7, -8
+TSFCDE_FP64 = 0
+TSFCDE_WS_ZERO, TSFCDE_WS_PREV = 0, 1
+TSFCDE_FLAG_TRUE_RESIDUAL = 1
+TSFCDE_FLAG_VERIFY = 2
+TSFCDE_OP_A, TSFCDE_OP_B, TSFCDE_OP_PINV = 0, 1, 2
+TSFCDE_SPEC_EMBED, TSFCDE_SPEC_STRANG = 0, 1
+
+
+class tsfcde_problem(ctypes.Structure):
+    _fields_ = [
+        ("alpha", c_double), ("beta", c_double), ("a", c_double), ("b", c_double), ("T", c_double),
+        ("n", c_int64), ("M", c_int64),
+        ("gamma", COEF_FN), ("dplus", COEF_FN), ("dminus", COEF_FN), ("coef_user", c_void_p),
+        ("gamma_at", POINTER(c_double)), ("dplus_at", POINTER(c_double)), ("dminus_at", POINTER(c_double)),
+        ("phi", IC_FN), ("phi_user", c_void_p),
+        ("rtol", c_double), ("maxit", c_int32), ("precision", c_int32), ("warm_start", c_int32),
+        ("flags", c_int32),
+    ]
+
+
+class tsfcde_stats(ctypes.Structure):
+    _fields_ = [
+        ("iters", c_int32), ("outer_iters", c_int32), ("restarts", c_int32), ("status", c_int32),
+        ("relres", c_double), ("relres_true", c_double), ("backward_err", c_double), ("seconds", c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_SIGS = {
+    "tsfcde_workspace_bytes": (c_int32, [POINTER(tsfcde_problem), POINTER(c_size_t)]),
+    "tsfcde_plan": (c_int32, [POINTER(tsfcde_problem), c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
+    "tsfcde_set_state": (c_int32, [c_void_p, c_int64, c_void_p]),
+    "tsfcde_step": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(tsfcde_stats)]),
+    "tsfcde_solve": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, POINTER(tsfcde_stats)]),
+    "tsfcde_apply": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_void_p]),
+    "tsfcde_rhs": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p]),
+    "tsfcde_weights": (c_int32, [c_void_p, c_void_p]),
+    "tsfcde_spectrum": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "tsfcde_history": (c_void_p, [c_void_p]),
+    "tsfcde_level": (c_int64, [c_void_p]),
+    "tsfcde_profile": (c_int32, [c_void_p, c_int32, c_int32]),
+    "tsfcde_profile_read": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
+    "tsfcde_destroy": (c_int32, [c_void_p]),
+    "tsfcde_strerror": (c_char_p, [c_int32]),
+}
+
+_LIB = None
+
+
+def header_symbols(path: str = HEADER):
+    """Names of the functions declared in include/tsfcde.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsfcde_[a-z_]+)\s*\(", text)) - {"tsfcde_coef_fn", "tsfcde_ic_fn"})
+
+
+def lib():
+    """Load libtsfcde.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1603_00279_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+class TsfcdeError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = lib().tsfcde_strerror(code).decode()
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({msg})")
+        self.code = code
+
+
+def check(code: int, where: str):
+    if code != TSFCDE_OK:
+        raise TsfcdeError(code, where)
+    return code

@@ -1,0 +1,176 @@
+// fft_core.hpp -- register/LDS Stockham FFT building blocks for gfx950.
+//
+// A transform of length P (power of two, 2..4096) is held by P/E lanes, each
+// lane owning E = min(P, 16) complex values.  Lane j holds the elements at
+// positions j + (P/E)*m, m = 0..E-1 ("canonical layout").  One Stockham
+// stage of radix RAD combines, for butterfly index bf, the inputs
+// bf + (P/RAD)*r; with bf = j + (P/E)*q these are exactly the lane's own
+// values v[q + (E/RAD)*r], so every stage starts from registers.  Outputs go
+// to LDS at the self-sorting position (bf/NS)*NS*RAD + bf%NS + r*NS and are
+// read back in canonical layout for the next stage; after the last stage the
+// canonical layout holds the transform in natural frequency order.
+//
+// Twiddles come from a table tw_P[m] = exp(-2 pi i m / P) (FP64, built on the
+// device at plan time); the inverse transform uses conjugates.  Butterfly
+// constants are exact algebraic values of cos/sin(2 pi k/16).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsf {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// multiply by -i (DIR < 0) or +i (DIR > 0)
+template <int DIR> __device__ __forceinline__ double2 mul_i(double2 a) {
+    return DIR < 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
+}
+
+// exp(DIR * 2 pi i * K / 16) applied to a, K compile-time in [0, 16).
+template <int K, int DIR> __device__ __forceinline__ double2 rot16(double2 a) {
+    constexpr double C1 = 0.92387953251128675613;  // cos(pi/8)
+    constexpr double S1 = 0.38268343236508977173;  // sin(pi/8)
+    constexpr double H = 0.70710678118654752440;   // sqrt(1/2)
+    constexpr int k = K & 15;
+    if constexpr (k == 0) return a;
+    else if constexpr (k == 4) return mul_i<DIR>(a);
+    else if constexpr (k == 8) return make_double2(-a.x, -a.y);
+    else if constexpr (k == 12) return mul_i<-DIR>(a);
+    else {
+        // cos/sin of 2 pi k/16 with the angle's sign fixed by DIR
+        constexpr double cs[16] = {1, C1, H, S1, 0, -S1, -H, -C1, -1, -C1, -H, -S1, 0, S1, H, C1};
+        constexpr double sn[16] = {0, S1, H, C1, 1, C1, H, S1, 0, -S1, -H, -C1, -1, -C1, -H, -S1};
+        const double c = cs[k];
+        const double s = DIR > 0 ? sn[k] : -sn[k];
+        return make_double2(fma(a.x, c, -a.y * s), fma(a.x, s, a.y * c));
+    }
+}
+
+// In-place DFT of length R (2, 4, 8, 16) on a[0..R), natural order in and out,
+// kernel exp(DIR * 2 pi i jk / R).  Radix-2 decimation in time, fully unrolled.
+template <int R, int DIR> struct Dft {
+    static __device__ __forceinline__ void run(double2 *a) {
+        if constexpr (R == 1) {
+            return;
+        } else if constexpr (R == 2) {
+            double2 t = a[1];
+            a[1] = csub(a[0], t);
+            a[0] = cadd(a[0], t);
+        } else {
+            constexpr int H = R / 2;
+            double2 e[H], o[H];
+#pragma unroll
+            for (int i = 0; i < H; ++i) { e[i] = a[2 * i]; o[i] = a[2 * i + 1]; }
+            Dft<H, DIR>::run(e);
+            Dft<H, DIR>::run(o);
+            apply<0>(a, e, o);
+        }
+    }
+    template <int K> static __device__ __forceinline__ void apply(double2 *a, const double2 *e, const double2 *o) {
+        if constexpr (K < R / 2) {
+            double2 t = rot16<K * (16 / R), DIR>(o[K]);
+            a[K] = cadd(e[K], t);
+            a[K + R / 2] = csub(e[K], t);
+            apply<K + 1>(a, e, o);
+        }
+    }
+};
+
+template <int P> struct Geo {
+    static constexpr int E = P >= 16 ? 16 : P;  // values per lane
+    static constexpr int T = P / E;             // lanes per transform
+};
+
+// LDS index padding: one spare slot every 16 elements breaks the bank
+// pattern of the power-of-two strides in the stage write-back.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lpad_size(int P) { return P + (P >> 4) + 1; }
+
+// Offset of the length-P sub-table inside the packed twiddle array
+// (tables for P = 2, 4, 8, ... are stored back to back).
+__host__ __device__ constexpr int tw_offset(int P) { return P - 2; }
+
+template <int P, int E, int RAD, int NS, int DIR>
+__device__ __forceinline__ void stage_bfly(double2 (&v)[E], int j, const double2 *__restrict__ twP) {
+    constexpr int NB = E / RAD;
+    constexpr int T = P / E;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        double2 a[RAD];
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) a[r] = v[q + NB * r];
+        if constexpr (NS > 1) {
+            const int bf = j + T * q;
+            const int k = bf & (NS - 1);
+            constexpr int STRIDE = P / (NS * RAD);
+#pragma unroll
+            for (int r = 1; r < RAD; ++r) {
+                double2 w = twP[r * k * STRIDE];
+                if (DIR > 0) w.y = -w.y;
+                a[r] = cmul(a[r], w);
+            }
+        }
+        Dft<RAD, DIR>::run(a);
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) v[q + NB * r] = a[r];
+    }
+}
+
+// Full transform of length P on the canonical register layout.  `lds` points
+// at this transform's LDS slab; element position p lives at
+// lds[lpad(p) * LS], where LS is the interleave stride (several transforms
+// may share a slab, interleaved).  All lanes of the workgroup must call this
+// (it contains barriers); lanes with active == false only take part in the
+// barriers.
+template <int P, int NS, int DIR>
+__device__ __forceinline__ void fft_stages(double2 (&v)[Geo<P>::E], int j, bool active,
+                                           const double2 *__restrict__ twP, double2 *lds, int LS) {
+    if constexpr (NS < P) {
+        constexpr int E = Geo<P>::E;
+        constexpr int T = Geo<P>::T;
+        constexpr int REM = P / NS;
+        constexpr int RAD = REM >= 16 ? 16 : REM;
+        constexpr int NB = E / RAD;
+        stage_bfly<P, E, RAD, NS, DIR>(v, j, twP);
+        if (active) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int bf = j + T * q;
+                const int base = (bf & ~(NS - 1)) * RAD + (bf & (NS - 1));
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) lds[lpad(base + r * NS) * LS] = v[q + NB * r];
+            }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = lds[lpad(j + T * m) * LS];
+        }
+        __syncthreads();
+        fft_stages<P, NS * RAD, DIR>(v, j, active, twP, lds, LS);
+    }
+}
+
+template <int P, int DIR>
+__device__ __forceinline__ void fft(double2 (&v)[Geo<P>::E], int j, bool active,
+                                    const double2 *__restrict__ tw_all, double2 *lds, int LS) {
+    fft_stages<P, 1, DIR>(v, j, active, tw_all + tw_offset(P), lds, LS);
+}
+
+// Two-level twiddle table for exp(-2 pi i m / L), m < L:
+// w(m) = hi[m >> shift] * lo[m & ((1 << shift) - 1)].
+struct Tw2 {
+    const double2 *lo;
+    const double2 *hi;
+    int shift;
+    __device__ __forceinline__ double2 operator()(int64_t m) const {
+        return cmul(hi[m >> shift], lo[m & ((int64_t(1) << shift) - 1)]);
+    }
+};
+
+}  // namespace tsf

@@ -1,0 +1,788 @@
+// kernels.hpp -- gfx950 kernels of the TSFCDE time-level solver.
+//
+// Real transforms of length L = 2N run as complex transforms of length
+// N = R x C (R rows, C columns, row-major, N complex values) in three passes:
+//   pass A (k_col, forward): length-R FFTs down the columns of the packed
+//     input z[m] = x[2m] + i x[2m+1], times the four-step twiddle
+//     W_N^(col*row); a workgroup owns B adjacent columns so every row
+//     segment it reads/writes is B*16 contiguous bytes.
+//   middle (k_mid): per pair of rows (k1, R-k1) -- the rows that hold
+//     frequencies k and N-k -- forward length-C FFTs, the real-to-complex
+//     untangle, the per-level symbol multiply (Toeplitz matvec through the
+//     circulant embedding) or divide (Strang preconditioner solve), the
+//     complex-to-real retangle, and inverse length-C FFTs.  The spectrum is
+//     never written out in natural order: position k1*C + k2 holds frequency
+//     k1 + R*k2, and the stored symbol tables use the same layout.
+//   pass C (k_col, inverse): conjugate twiddle, inverse length-R FFTs down the
+//     columns, unpack to real.
+// Vector updates of the Krylov iteration are fused into pass A (prologue) and
+// pass C (epilogue); dot products are reduced per workgroup and finished by
+// the last workgroup to arrive, in a fixed order (deterministic results).
+#pragma once
+#include "fft_core.hpp"
+
+namespace tsf {
+
+// ---------------------------------------------------------------------------
+// Device scalars of the CGS iteration (one struct per plan).
+// ---------------------------------------------------------------------------
+struct DevScalars {
+    double rho, rho_prev, alpha, beta, rtv, rnorm2, gnorm2, tol2;
+    double aux0, aux1, rtol2, pad0;
+    int iter, done, status, fresh;  // fresh: next CGS iteration starts from r (u = p = r)
+    unsigned int cnt[8];  // arrival counters of the last-workgroup reductions
+};
+
+enum : int { ST_OK = 0, ST_BREAKDOWN = 1, ST_NONFINITE = 2 };
+
+// Symbol of one level: S(k) = s0 + cre*Re(L_k) + i*(cim*Im(L_k) + cq*sin(2 pi k / L)),
+// where L_k is the stored spectrum of W_beta (embedding or Strang).  For a
+// product (MODE 0) y = S * x * scale; for a solve (MODE 1) y = x / (S * scale).
+struct SymParams {
+    double s0, cre, cim, cq, scale;
+};
+
+// ---------------------------------------------------------------------------
+// Reductions: wave64 shuffles, then LDS across waves, then the last workgroup
+// sums the per-workgroup partials in index order.
+// ---------------------------------------------------------------------------
+template <int NACC>
+__device__ __forceinline__ bool block_reduce_last(double (&acc)[NACC], double *partials, unsigned *counter,
+                                                  double (&tot)[NACC]) {
+    __shared__ double red[NACC][16];
+    __shared__ int is_last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwave = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) {
+        double v = acc[a];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[a][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) {
+            double s = 0.0;
+            for (int w = 0; w < nwave; ++w) s += red[a][w];
+            __hip_atomic_store(&partials[(size_t)blockIdx.x * NACC + a], s, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __threadfence();
+        unsigned prev = atomicAdd(counter, 1u);
+        is_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    double loc[NACC];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) loc[a] = 0.0;
+    for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a)
+            loc[a] += __hip_atomic_load(&partials[(size_t)i * NACC + a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) {
+        double v = loc[a];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[a][wave] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) {
+        double s = 0.0;
+        for (int w = 0; w < nwave; ++w) s += red[a][w];
+        tot[a] = s;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+    return true;
+}
+
+__device__ __forceinline__ bool finite(double x) { return isfinite(x); }
+
+// ---------------------------------------------------------------------------
+// Pass-A loaders (forward column pass).  load(row, col) returns packed
+// element m = row*C + col of the real input, z[m] = x[2m] + i x[2m+1].
+// ---------------------------------------------------------------------------
+struct InReal {  // plain real vector, zero beyond nr values
+    const double *x;
+    int64_t nr, C;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ double2 load(int row, int64_t col) const {
+        int64_t i = 2 * (row * C + col);
+        if (i >= nr) return make_double2(0.0, 0.0);
+        return *reinterpret_cast<const double2 *>(x + i);
+    }
+};
+
+// CGS: u = r + beta q ; p = u + beta (q + beta p) (first iteration: u = p = r);
+// writes u and p, transforms p.
+struct InCgsUP {
+    const double *r;
+    double *u, *p;
+    const double *q;
+    int64_t nr, C;
+    double beta;
+    bool first;
+    __device__ void prep(const DevScalars *sc) {
+        first = sc->fresh != 0;
+        beta = sc->beta;
+    }
+    __device__ __forceinline__ double2 load(int row, int64_t col) {
+        int64_t i = 2 * (row * C + col);
+        if (i >= nr) return make_double2(0.0, 0.0);
+        double2 rv = *reinterpret_cast<const double2 *>(r + i);
+        double2 uv, pv;
+        if (first) {
+            uv = rv;
+            pv = rv;
+        } else {
+            double2 qv = *reinterpret_cast<const double2 *>(q + i);
+            double2 po = *reinterpret_cast<const double2 *>(p + i);
+            uv = make_double2(fma(beta, qv.x, rv.x), fma(beta, qv.y, rv.y));
+            pv = make_double2(fma(beta, fma(beta, po.x, qv.x), uv.x), fma(beta, fma(beta, po.y, qv.y), uv.y));
+        }
+        *reinterpret_cast<double2 *>(u + i) = uv;
+        *reinterpret_cast<double2 *>(p + i) = pv;
+        return pv;
+    }
+};
+
+// CGS: q = u - alpha vhat (written); transforms u + q.
+struct InCgsQ {
+    const double *u, *vhat;
+    double *q;
+    int64_t nr, C;
+    double alpha;
+    __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
+    __device__ __forceinline__ double2 load(int row, int64_t col) {
+        int64_t i = 2 * (row * C + col);
+        if (i >= nr) return make_double2(0.0, 0.0);
+        double2 uv = *reinterpret_cast<const double2 *>(u + i);
+        double2 vv = *reinterpret_cast<const double2 *>(vhat + i);
+        double2 qv = make_double2(fma(-alpha, vv.x, uv.x), fma(-alpha, vv.y, uv.y));
+        *reinterpret_cast<double2 *>(q + i) = qv;
+        return make_double2(uv.x + qv.x, uv.y + qv.y);
+    }
+};
+
+// CGS: x = x + alpha uhat (written); transforms uhat.
+struct InCgsX {
+    const double *uhat;
+    double *x;
+    int64_t nr, C;
+    double alpha;
+    __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
+    __device__ __forceinline__ double2 load(int row, int64_t col) {
+        int64_t i = 2 * (row * C + col);
+        if (i >= nr) return make_double2(0.0, 0.0);
+        double2 uh = *reinterpret_cast<const double2 *>(uhat + i);
+        double2 xv = *reinterpret_cast<double2 *>(x + i);
+        *reinterpret_cast<double2 *>(x + i) = make_double2(fma(alpha, uh.x, xv.x), fma(alpha, uh.y, xv.y));
+        return uh;
+    }
+};
+
+// Pass-A store: spectrum buffer y[row*C + col] = val * W_N^(row*col).
+struct OutSpec {
+    double2 *y;
+    Tw2 tw;  // table for exp(-2 pi i m / L), L = 2N
+    int64_t C;
+    static constexpr int NACC = 0;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *) const {
+        y[row * C + col] = cmul(val, tw(2 * (int64_t)row * col));
+    }
+    __device__ void final(const double *, DevScalars *) const {}
+    double *partials;
+    unsigned *counter;
+};
+
+// ---------------------------------------------------------------------------
+// Pass-C loader and stores (inverse column pass).
+// ---------------------------------------------------------------------------
+struct InSpec {
+    const double2 *y;
+    Tw2 tw;
+    int64_t C;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ double2 load(int row, int64_t col) const {
+        return cmul(y[row * C + col], cconj(tw(2 * (int64_t)row * col)));
+    }
+};
+
+struct OutReal {  // x[2m], x[2m+1] for 2m < nr
+    double *x;
+    int64_t nr, C;
+    static constexpr int NACC = 0;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) *reinterpret_cast<double2 *>(x + i) = val;
+    }
+    __device__ void final(const double *, DevScalars *) const {}
+    double *partials;
+    unsigned *counter;
+};
+
+// vhat = A phat; accumulates rt . vhat; the last workgroup sets alpha = rho / (rt . vhat).
+struct OutCgsDot {
+    double *vhat;
+    const double *rt;
+    int64_t nr, C;
+    static constexpr int NACC = 1;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) {
+            *reinterpret_cast<double2 *>(vhat + i) = val;
+            double2 t = *reinterpret_cast<const double2 *>(rt + i);
+            acc[0] = fma(t.x, val.x, fma(t.y, val.y, acc[0]));
+        }
+    }
+    __device__ void final(const double *tot, DevScalars *sc) const {
+        sc->rtv = tot[0];
+        double a = sc->rho / tot[0];
+        if (tot[0] == 0.0) {
+            sc->status = ST_BREAKDOWN;
+            sc->done = 1;
+        } else if (!finite(a)) {
+            sc->status = ST_NONFINITE;
+            sc->done = 1;
+        }
+        sc->alpha = a;
+    }
+    double *partials;
+    unsigned *counter;
+};
+
+// r = r - alpha (A uhat); accumulates r.r and rt.r; the last workgroup advances
+// the recurrence scalars and tests |r| <= rtol |g|.
+struct OutCgsR {
+    double *r;
+    const double *rt;
+    int64_t nr, C;
+    double alpha;
+    static constexpr int NACC = 2;
+    __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) {
+            double2 rv = *reinterpret_cast<const double2 *>(r + i);
+            rv.x = fma(-alpha, val.x, rv.x);
+            rv.y = fma(-alpha, val.y, rv.y);
+            *reinterpret_cast<double2 *>(r + i) = rv;
+            double2 t = *reinterpret_cast<const double2 *>(rt + i);
+            acc[0] = fma(rv.x, rv.x, fma(rv.y, rv.y, acc[0]));
+            acc[1] = fma(t.x, rv.x, fma(t.y, rv.y, acc[1]));
+        }
+    }
+    __device__ void final(const double *tot, DevScalars *sc) const {
+        sc->rnorm2 = tot[0];
+        sc->rho_prev = sc->rho;
+        sc->rho = tot[1];
+        sc->beta = tot[1] / sc->rho_prev;
+        sc->iter += 1;
+        sc->fresh = 0;
+        if (!finite(tot[0]) || !finite(tot[1])) {
+            sc->status = ST_NONFINITE;
+            sc->done = 1;
+        } else if (tot[0] <= sc->tol2) {
+            sc->done = 1;
+        } else if (tot[1] == 0.0) {
+            sc->status = ST_BREAKDOWN;
+            sc->done = 1;
+        }
+    }
+    double *partials;
+    unsigned *counter;
+};
+
+// Right-hand side of (3.3) from y = A u^j:
+//   g = (eta/sigma) u^j - ((1-sigma)/sigma) y - H + f     (= B u^j - H + f)
+//   x0 = u^j (warm) or 0;  r = g - A x0 ;  rt = r.
+// The last workgroup initialises the CGS scalars for the level.
+struct OutRhs {
+    const double *uj, *H, *f;
+    double *g, *r, *rt, *x;
+    int64_t nr, C;
+    double c_u, c_y;  // eta/sigma, (1-sigma)/sigma
+    int warm, has_hist;
+    static constexpr int NACC = 2;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) {
+            double2 u = *reinterpret_cast<const double2 *>(uj + i);
+            double2 gv = make_double2(fma(c_u, u.x, -c_y * val.x), fma(c_u, u.y, -c_y * val.y));
+            if (has_hist) {
+                double2 hv = *reinterpret_cast<const double2 *>(H + i);
+                gv.x -= hv.x;
+                gv.y -= hv.y;
+            }
+            if (f) {
+                double2 fv = *reinterpret_cast<const double2 *>(f + i);
+                gv.x += fv.x;
+                gv.y += fv.y;
+            }
+            double2 rv = warm ? make_double2(gv.x - val.x, gv.y - val.y) : gv;
+            *reinterpret_cast<double2 *>(g + i) = gv;
+            *reinterpret_cast<double2 *>(r + i) = rv;
+            *reinterpret_cast<double2 *>(rt + i) = rv;
+            *reinterpret_cast<double2 *>(x + i) = warm ? u : make_double2(0.0, 0.0);
+            acc[0] = fma(gv.x, gv.x, fma(gv.y, gv.y, acc[0]));
+            acc[1] = fma(rv.x, rv.x, fma(rv.y, rv.y, acc[1]));
+        }
+    }
+    __device__ void final(const double *tot, DevScalars *sc) const {
+        sc->gnorm2 = tot[0];
+        sc->rnorm2 = tot[1];
+        sc->rho = tot[1];
+        sc->rho_prev = 1.0;
+        sc->beta = 0.0;
+        sc->alpha = 0.0;
+        sc->tol2 = sc->rtol2 * tot[0];
+        sc->iter = 0;
+        sc->fresh = 1;
+        sc->aux0 = tot[1];
+        sc->status = ST_OK;
+        sc->done = (tot[1] <= sc->tol2) ? 1 : 0;
+        if (!finite(tot[0]) || !finite(tot[1])) {
+            sc->status = ST_NONFINITE;
+            sc->done = 1;
+        }
+    }
+    double *partials;
+    unsigned *counter;
+};
+
+// |g - A x|^2 into aux0.
+struct OutTrueRes {
+    const double *g;
+    int64_t nr, C;
+    static constexpr int NACC = 1;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) {
+            double2 gv = *reinterpret_cast<const double2 *>(g + i);
+            double dx = gv.x - val.x, dy = gv.y - val.y;
+            acc[0] = fma(dx, dx, fma(dy, dy, acc[0]));
+        }
+    }
+    __device__ void final(const double *tot, DevScalars *sc) const { sc->aux0 = tot[0]; }
+    double *partials;
+    unsigned *counter;
+};
+
+// Restart of CGS from the current iterate x (true-residual verification and
+// breakdown recovery): y = A x, r = g - y, rt = r; the last workgroup resets
+// the recurrence and records |r|^2 in aux0.
+struct OutRestart {
+    const double *g;
+    double *r, *rt;
+    int64_t nr, C;
+    static constexpr int NACC = 1;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) {
+            double2 gv = *reinterpret_cast<const double2 *>(g + i);
+            double2 rv = make_double2(gv.x - val.x, gv.y - val.y);
+            *reinterpret_cast<double2 *>(r + i) = rv;
+            *reinterpret_cast<double2 *>(rt + i) = rv;
+            acc[0] = fma(rv.x, rv.x, fma(rv.y, rv.y, acc[0]));
+        }
+    }
+    __device__ void final(const double *tot, DevScalars *sc) const {
+        sc->aux0 = tot[0];
+        sc->rnorm2 = tot[0];
+        sc->rho = tot[0];
+        sc->rho_prev = 1.0;
+        sc->beta = 0.0;
+        sc->alpha = 0.0;
+        sc->fresh = 1;
+        sc->status = ST_OK;
+        sc->done = (tot[0] <= sc->tol2) ? 1 : 0;
+        if (!finite(tot[0])) {
+            sc->status = ST_NONFINITE;
+            sc->done = 1;
+        }
+    }
+    double *partials;
+    unsigned *counter;
+};
+
+// ---------------------------------------------------------------------------
+// Column pass: length-R FFTs down B adjacent columns per workgroup.
+// ---------------------------------------------------------------------------
+template <int R> struct ColGeo {
+    static constexpr int E = Geo<R>::E;
+    static constexpr int T = Geo<R>::T;
+    static constexpr int B = 256 / T;
+};
+
+template <int R, int DIR, class In, class Out>
+__global__ void __launch_bounds__(256) k_col(int64_t C, In in, Out out, const double2 *__restrict__ tw_all,
+                                             DevScalars *sc, int pred) {
+    if (pred && sc->done) return;
+    constexpr int E = ColGeo<R>::E, T = ColGeo<R>::T, B = ColGeo<R>::B;
+    __shared__ double2 lds[lpad_size(R) * B];
+    const int t = threadIdx.x;
+    const int b = t % B, j = t / B;
+    const int64_t c = (int64_t)blockIdx.x * B + b;
+    const bool active = c < C;
+    in.prep(sc);
+    out.prep(sc);
+    double2 v[E];
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = in.load(j + T * m, c);
+    }
+    fft<R, DIR>(v, j, active, tw_all, lds + b, B);
+    double acc[Out::NACC > 0 ? Out::NACC : 1];
+#pragma unroll
+    for (int a = 0; a < (Out::NACC > 0 ? Out::NACC : 1); ++a) acc[a] = 0.0;
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) out.store(j + T * m, c, v[m], acc);
+    }
+    if constexpr (Out::NACC > 0) {
+        double tot[Out::NACC];
+        if (block_reduce_last<Out::NACC>(acc, out.partials, out.counter, tot)) {
+            if (threadIdx.x == 0) out.final(tot, sc);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Middle pass: row pairs, untangle, symbol, retangle.
+// MODE 0: y = S x (product); MODE 1: y = x / S (solve); MODE 2: write the
+// forward spectrum X (natural-frequency values at native positions) to `spec`
+// (k = 0 and k = N packed as (X_0, X_N) at position 0) and stop.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__device__ __forceinline__ void pair_update(double2 &za, double2 &zb, double2 w, double2 La, double2 Lb,
+                                            const SymParams &sp, double2 *xa_out, double2 *xb_out) {
+    const double2 A = za, Bc = cconj(zb);
+    const double2 E2 = cadd(A, Bc);
+    const double2 O2 = mul_i<-1>(csub(A, Bc));  // (A - Bc) / i
+    const double2 wO = cmul(w, O2);
+    const double2 Xa = cadd(E2, wO);           // 2 X_k
+    const double2 Xb = cconj(csub(E2, wO));    // 2 X_{N-k}
+    if constexpr (MODE == 2) {
+        *xa_out = cscale(Xa, 0.5);
+        *xb_out = cscale(Xb, 0.5);
+        return;
+    } else {
+        const double s = -w.y;  // sin(2 pi k / L)
+        const double2 Sa = make_double2(fma(sp.cre, La.x, sp.s0), fma(sp.cim, La.y, sp.cq * s));
+        const double2 Sb = make_double2(fma(sp.cre, Lb.x, sp.s0), fma(sp.cim, Lb.y, sp.cq * s));
+        double2 Ya, Yb;
+        if constexpr (MODE == 0) {
+            Ya = cscale(cmul(Sa, Xa), sp.scale);
+            Yb = cscale(cmul(Sb, Xb), sp.scale);
+        } else {
+            const double2 Da = cscale(Sa, sp.scale), Db = cscale(Sb, sp.scale);
+            const double ia = 1.0 / fma(Da.x, Da.x, Da.y * Da.y);
+            const double ib = 1.0 / fma(Db.x, Db.x, Db.y * Db.y);
+            Ya = cscale(cmul(Xa, cconj(Da)), ia);
+            Yb = cscale(cmul(Xb, cconj(Db)), ib);
+        }
+        const double2 E2n = cadd(Ya, cconj(Yb));
+        const double2 O2n = cmul(csub(Ya, cconj(Yb)), cconj(w));
+        za = cadd(E2n, mul_i<1>(O2n));
+        zb = cadd(cconj(E2n), mul_i<1>(cconj(O2n)));
+    }
+}
+
+template <int C_> struct MidGeo {
+    static constexpr int E = Geo<C_>::E;
+    static constexpr int T = Geo<C_>::T;
+    static constexpr int NT = (2 * T + 63) / 64 * 64;  // threads per workgroup
+    static constexpr int LS = lpad_size(C_);
+};
+
+template <int C_, int MODE>
+__global__ void __launch_bounds__(MidGeo<C_>::NT) k_mid(int64_t R, double2 *Y, const double2 *spec, double2 *spec_out,
+                                                        Tw2 twL, SymParams sp, const double2 *__restrict__ tw_all,
+                                                        DevScalars *sc, int pred) {
+    if (pred && sc->done) return;
+    constexpr int E = MidGeo<C_>::E, T = MidGeo<C_>::T, LS = MidGeo<C_>::LS;
+    constexpr int64_t C = C_;
+    __shared__ double2 lds[2 * LS];
+    const int wg = blockIdx.x;
+    const int64_t ra = wg == 0 ? 0 : wg;
+    const int64_t rb = wg == 0 ? R / 2 : R - wg;
+    const int t = threadIdx.x;
+    const int sel = t / T, j = t % T;
+    const bool active = sel < 2;
+    const int64_t row = sel == 0 ? ra : rb;
+    double2 *slab = lds + (sel < 2 ? sel : 0) * LS;
+    double2 v[E];
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = Y[row * C + j + T * m];
+    }
+    fft<C_, -1>(v, j, active, tw_all, slab, 1);
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) slab[lpad(j + T * m)] = v[m];
+    }
+    __syncthreads();
+    double2 *s0 = lds, *s1 = lds + LS;
+    const int nthr = blockDim.x;
+    if (wg != 0) {
+        for (int k2 = t; k2 < C_; k2 += nthr) {
+            const int k2b = C_ - 1 - k2;
+            double2 za = s0[lpad(k2)], zb = s1[lpad(k2b)];
+            const int64_t k = ra + R * k2;
+            const int64_t pa = ra * C + k2, pb = rb * C + k2b;
+            double2 La = make_double2(0, 0), Lb = make_double2(0, 0);
+            if constexpr (MODE != 2) {
+                La = spec[pa];
+                Lb = spec[pb];
+            }
+            double2 xa, xb;
+            pair_update<MODE>(za, zb, twL(k), La, Lb, sp, &xa, &xb);
+            if constexpr (MODE == 2) {
+                spec_out[pa] = xa;
+                spec_out[pb] = xb;
+            } else {
+                s0[lpad(k2)] = za;
+                s1[lpad(k2b)] = zb;
+            }
+        }
+    } else {
+        // rows 0 and R/2 pair with themselves.
+        const int ntask = C_ + 1;
+        for (int task = t; task < ntask; task += nthr) {
+            if (task <= C_ / 2) {
+                const int k2 = task;
+                const int k2b = (C_ - k2) & (C_ - 1);
+                double2 za = s0[lpad(k2)], zb = s0[lpad(k2b)];
+                const int64_t k = R * k2;
+                double2 La = make_double2(0, 0), Lb = make_double2(0, 0);
+                if constexpr (MODE != 2) {
+                    if (k2 == 0) {
+                        const double2 L0 = spec[0];
+                        La = make_double2(L0.x, 0.0);  // lambda_0
+                        Lb = make_double2(L0.y, 0.0);  // lambda_N
+                    } else {
+                        La = spec[k2];
+                        Lb = spec[k2b];
+                    }
+                }
+                const double2 w = k2 == 0 ? make_double2(1.0, 0.0) : twL(k);
+                double2 xa, xb;
+                pair_update<MODE>(za, zb, w, La, Lb, sp, &xa, &xb);
+                if constexpr (MODE == 2) {
+                    if (k2 == 0) {
+                        spec_out[0] = make_double2(xa.x, xb.x);
+                    } else {
+                        spec_out[k2] = xa;
+                        spec_out[k2b] = xb;
+                    }
+                } else {
+                    s0[lpad(k2)] = za;
+                    if (k2 != 0 && k2b != k2) s0[lpad(k2b)] = zb;
+                }
+            } else {
+                const int k2 = task - (C_ / 2 + 1);
+                const int k2b = C_ - 1 - k2;
+                double2 za = s1[lpad(k2)], zb = s1[lpad(k2b)];
+                const int64_t k = R / 2 + R * k2;
+                const int64_t pa = (R / 2) * C + k2, pb = (R / 2) * C + k2b;
+                double2 La = make_double2(0, 0), Lb = make_double2(0, 0);
+                if constexpr (MODE != 2) {
+                    La = spec[pa];
+                    Lb = spec[pb];
+                }
+                double2 xa, xb;
+                pair_update<MODE>(za, zb, twL(k), La, Lb, sp, &xa, &xb);
+                if constexpr (MODE == 2) {
+                    spec_out[pa] = xa;
+                    spec_out[pb] = xb;
+                } else {
+                    s1[lpad(k2)] = za;
+                    s1[lpad(k2b)] = zb;
+                }
+            }
+        }
+    }
+    if constexpr (MODE == 2) return;
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = slab[lpad(j + T * m)];
+    }
+    __syncthreads();
+    fft<C_, 1>(v, j, active, tw_all, slab, 1);
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) Y[row * C + j + T * m] = v[m];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// History sum of (3.3):  H = kappa * sum_{s=0}^{j-1} c_{j-s}^(j) (u^{s+1} - u^s)
+// with c_j^(j) = clast (s = 0) and c_m^(j) = cbase[m] (1 <= m <= j-1).
+// Each lane streams two adjacent unknowns through all stored levels.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_history(const double *__restrict__ U, int64_t n, int j,
+                                                 const double *__restrict__ cbase, double clast, double kappa,
+                                                 double *__restrict__ H) {
+    const int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    double2 prev = *reinterpret_cast<const double2 *>(U + i);
+    double2 acc = make_double2(0.0, 0.0);
+    int s = 0;
+    // four levels in flight per step
+    for (; s + 4 <= j; s += 4) {
+        double2 x1 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1) * n + i);
+        double2 x2 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 2) * n + i);
+        double2 x3 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 3) * n + i);
+        double2 x4 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 4) * n + i);
+        const double c1 = s == 0 ? clast : cbase[j - s];
+        const double c2 = cbase[j - s - 1], c3 = cbase[j - s - 2], c4 = cbase[j - s - 3];
+        acc.x = fma(c1, x1.x - prev.x, acc.x);
+        acc.y = fma(c1, x1.y - prev.y, acc.y);
+        acc.x = fma(c2, x2.x - x1.x, acc.x);
+        acc.y = fma(c2, x2.y - x1.y, acc.y);
+        acc.x = fma(c3, x3.x - x2.x, acc.x);
+        acc.y = fma(c3, x3.y - x2.y, acc.y);
+        acc.x = fma(c4, x4.x - x3.x, acc.x);
+        acc.y = fma(c4, x4.y - x3.y, acc.y);
+        prev = x4;
+    }
+    for (; s < j; ++s) {
+        double2 x1 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1) * n + i);
+        const double c1 = s == 0 ? clast : cbase[j - s];
+        acc.x = fma(c1, x1.x - prev.x, acc.x);
+        acc.y = fma(c1, x1.y - prev.y, acc.y);
+        prev = x1;
+    }
+    *reinterpret_cast<double2 *>(H + i) = make_double2(kappa * acc.x, kappa * acc.y);
+}
+
+// ---------------------------------------------------------------------------
+// Plan-time kernels.
+// ---------------------------------------------------------------------------
+
+// Packed tables tw_P[m] = exp(-2 pi i m / P) for P = 2, 4, ..., PMAX.
+__global__ void k_twiddle_packed(double2 *tw, int pmax_log2) {
+    const int64_t total = (int64_t(1) << (pmax_log2 + 1)) - 2;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        // idx = (P - 2) + m with P the largest power of two such that P - 2 <= idx
+        int lg = 1;
+        while (((int64_t(1) << (lg + 1)) - 2) <= idx) ++lg;
+        const int64_t P = int64_t(1) << lg;
+        const int64_t m = idx - (P - 2);
+        double s, c;
+        sincospi(2.0 * (double)m / (double)P, &s, &c);
+        tw[idx] = make_double2(c, -s);
+    }
+}
+
+// Two-level table for exp(-2 pi i m / L): lo[e] = w(e), e < 2^shift;
+// hi[e] = w(e * 2^shift), e < nhi.
+__global__ void k_twiddle_tw2(double2 *lo, double2 *hi, int64_t L, int shift, int64_t nhi) {
+    const int64_t nlo = int64_t(1) << shift;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nlo + nhi;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = idx < nlo ? idx : (idx - nlo) << shift;
+        // reduce m/L to [0, 1) exactly (L is a power of two)
+        const double frac = (double)(m & (L - 1)) / (double)L;
+        double s, c;
+        sincospi(2.0 * frac, &s, &c);
+        if (idx < nlo) lo[idx] = make_double2(c, -s);
+        else hi[idx - nlo] = make_double2(c, -s);
+    }
+}
+
+// g_k = prod_{i=1..k} (1 - (beta+1)/i), k = 0..K (Lemma 3 recurrence), by a
+// single-workgroup chunked product scan.
+__global__ void __launch_bounds__(1024) k_grunwald(double beta, int64_t K, double *g) {
+    __shared__ double pre[1024];
+    const int t = threadIdx.x;
+    const int64_t tot = K + 1;
+    const int64_t chunk = (tot + 1023) / 1024;
+    const int64_t k0 = t * chunk, k1 = min(tot, k0 + chunk);
+    double p = 1.0;
+    for (int64_t k = k0; k < k1; ++k) p *= (k == 0) ? 1.0 : (1.0 - (beta + 1.0) / (double)k);
+    pre[t] = p;
+    __syncthreads();
+    // inclusive Hillis-Steele product scan over the 1024 chunk products
+    for (int d = 1; d < 1024; d <<= 1) {
+        double other = t >= d ? pre[t - d] : 1.0;
+        __syncthreads();
+        pre[t] *= other;
+        __syncthreads();
+    }
+    double run = t == 0 ? 1.0 : pre[t - 1];
+    for (int64_t k = k0; k < k1; ++k) {
+        run *= (k == 0) ? 1.0 : (1.0 - (beta + 1.0) / (double)k);
+        g[k] = run;
+    }
+}
+
+// omega_k = l1 g_k + l0 g_{k-1} + lm1 g_{k-2}  (Lemma 2), k = 0..K.
+__global__ void k_wsgd(const double *g, int64_t K, double l1, double l0, double lm1, double *w) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= K; k += (int64_t)gridDim.x * blockDim.x) {
+        double v = l1 * g[k];
+        if (k >= 1) v = fma(l0, g[k - 1], v);
+        if (k >= 2) v = fma(lm1, g[k - 2], v);
+        w[k] = v;
+    }
+}
+
+// First column of the length-L circulant embedding of W_beta:
+// c_m = omega_{m+1} (m < n), c_{L-1} = omega_0, else 0.
+__global__ void k_embed_column(const double *w, int64_t n, int64_t L, double *c) {
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < L; m += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (m < n) v = w[m + 1];
+        if (m == L - 1) v += w[0];
+        c[m] = v;
+    }
+}
+
+// First column of the Strang circulant s(W_beta): lag k for 0 <= k <= n/2,
+// lag k - n otherwise; W has lags -1..n-1 with entry omega_{lag+1}.
+__global__ void k_strang_column(const double *w, int64_t n, double *c) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t lag = k <= n / 2 ? k : k - n;
+        c[k] = lag >= -1 ? w[lag + 1] : 0.0;
+    }
+}
+
+// Native-order spectrum (position k1*C + k2 <-> frequency k1 + R*k2, X_0/X_N
+// packed at position 0) to natural order k = 0..N.
+__global__ void k_spec_export(const double2 *spec, int64_t R, int64_t C, double2 *out) {
+    const int64_t N = R * C;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= N; k += (int64_t)gridDim.x * blockDim.x) {
+        double2 v;
+        if (k == 0) v = make_double2(spec[0].x, 0.0);
+        else if (k == N) v = make_double2(spec[0].y, 0.0);
+        else v = spec[(k % R) * C + k / R];
+        out[k] = v;
+    }
+}
+
+__global__ void k_copy(const double *__restrict__ src, double *__restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_fill(double *__restrict__ dst, double v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = v;
+}
+
+}  // namespace tsf

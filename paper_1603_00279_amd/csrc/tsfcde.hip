@@ -1,0 +1,754 @@
+// tsfcde.hip -- host runtime and C ABI of the TSFCDE time-level solver.
+//
+// One time level (Algorithm 2 of Gu et al., arXiv:1603.00279):
+//   1. history H = kappa * sum_{s<j} c_{j-s}^(j) (u^{s+1} - u^s)   (Lemma 1, (3.3))
+//   2. y = A u^j through the circulant embedding, fused with
+//      g = (eta/sigma) u^j - ((1-sigma)/sigma) y - H + f  (= B u^j - H + f),
+//      r0 = g - A x0, rt = r0                                  ((3.1), (3.3))
+//   3. preconditioned CGS on A u^{j+1} = g with the Strang circulant P (3.7),
+//      12 kernels per iteration, device-resident scalars, convergence flag
+//      polled between chunks of iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/tsfcde.h"
+#include "kernels.hpp"
+
+using namespace tsf;
+
+namespace {
+
+constexpr int PMAX_LOG2 = 12;  // longest in-LDS transform: 4096
+constexpr int64_t NMAX = int64_t(1) << 24;
+constexpr int64_t PARTIAL_SLOTS = 16384;  // doubles per reduction site
+constexpr int NSITES = 4;
+
+struct RT {  // real transform of length L = 2N as an R x C complex transform
+    int64_t L = 0, N = 0, R = 0, C = 0;
+    Tw2 tw{};
+    double2 *lo = nullptr, *hi = nullptr;
+    int64_t nlo = 0, nhi = 0;
+    int shift = 0;
+};
+
+int ilog2(int64_t v) {
+    int l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+
+void rt_init(RT &rt, int64_t L) {
+    rt.L = L;
+    rt.N = L / 2;
+    const int lg = ilog2(rt.N);
+    rt.R = int64_t(1) << (lg / 2);
+    rt.C = rt.N / rt.R;
+    rt.shift = (ilog2(L) + 1) / 2;
+    rt.nlo = int64_t(1) << rt.shift;
+    rt.nhi = (L >> rt.shift) + 1;
+}
+
+struct Layout {
+    size_t off_U, off_vec, off_tmp, off_w, off_g0, off_cbase, off_buf, off_specA, off_specP, off_tw, off_tw2A, off_tw2P,
+        off_part, off_sc, total;
+};
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int NVEC = 10;  // H g r rt u p q phat vhat uhat
+
+Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P) {
+    Layout l{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = al(o + bytes);
+        return at;
+    };
+    l.off_U = take(sizeof(double) * (size_t)(M + 1) * n);
+    l.off_vec = take(sizeof(double) * (size_t)NVEC * n);
+    l.off_tmp = take(sizeof(double) * (size_t)std::max<int64_t>(A.L, n));
+    l.off_w = take(sizeof(double) * (size_t)(n + 2));
+    l.off_g0 = take(sizeof(double) * (size_t)(n + 2));
+    l.off_cbase = take(sizeof(double) * (size_t)(M + 2));
+    l.off_buf = take(sizeof(double2) * (size_t)A.N);
+    l.off_specA = take(sizeof(double2) * (size_t)A.N);
+    l.off_specP = take(sizeof(double2) * (size_t)P.N);
+    l.off_tw = take(sizeof(double2) * (size_t)((int64_t(1) << (PMAX_LOG2 + 1)) - 2));
+    l.off_tw2A = take(sizeof(double2) * (size_t)(A.nlo + A.nhi));
+    l.off_tw2P = take(sizeof(double2) * (size_t)(P.nlo + P.nhi));
+    l.off_part = take(sizeof(double) * (size_t)PARTIAL_SLOTS * NSITES);
+    l.off_sc = take(sizeof(DevScalars));
+    l.total = o;
+    return l;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int validate(const tsfcde_problem *p) {
+    if (!p) return TSFCDE_EINVAL;
+    if (!(p->alpha > 0.0 && p->alpha <= 1.0)) return TSFCDE_EINVAL;
+    if (!(p->beta > 1.0 && p->beta <= 2.0)) return TSFCDE_EINVAL;
+    if (!(p->b > p->a) || !std::isfinite(p->a) || !std::isfinite(p->b)) return TSFCDE_EINVAL;
+    if (!(p->T > 0.0) || !std::isfinite(p->T)) return TSFCDE_EINVAL;
+    if (p->n < 2 || p->M < 1) return TSFCDE_EINVAL;
+    if ((!p->gamma && !p->gamma_at) || (!p->dplus && !p->dplus_at) || (!p->dminus && !p->dminus_at))
+        return TSFCDE_EINVAL;
+    if (p->precision != TSFCDE_FP64) return TSFCDE_EINVAL;
+    if (p->warm_start != TSFCDE_WS_ZERO && p->warm_start != TSFCDE_WS_PREV) return TSFCDE_EINVAL;
+    if (!std::isfinite(p->rtol)) return TSFCDE_EINVAL;
+    if (!is_pow2(p->n) || p->n < 16 || p->n > NMAX) return TSFCDE_EUNSUPPORTED;
+    return TSFCDE_OK;
+}
+
+struct ProfRec {
+    bool on = false;
+    int64_t launches = 0;
+    double ms = 0.0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+
+}  // namespace
+
+struct tsfcde_plan_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double alpha, beta, a, b, T, h, tau, sigma, kappa, hb;
+    int64_t n, M, level = 0;
+    double rtol;
+    int maxit, warm, flags;
+    std::vector<double> gam, dp, dm, eta, cbase, clast;
+    RT A, P;
+    Layout lay;
+    char *ws;
+    double *U, *H, *g, *r, *rt, *u, *p, *q, *phat, *vhat, *uhat, *tmp, *w, *g0, *cb, *part;
+    double2 *buf, *specA, *specP, *tw_all;
+    DevScalars *sc;
+    DevScalars *h_sc = nullptr;  // pinned mirror for polling
+    int last_iters = 8;
+    ProfRec prof[4];
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+#define HIPCHK(x)                                           \
+    do {                                                    \
+        hipError_t e_ = (x);                                \
+        if (e_ != hipSuccess) return TSFCDE_EDEVICE;        \
+    } while (0)
+
+hipEvent_t get_event(tsfcde_plan_s *pl) {
+    if (!pl->event_pool.empty()) {
+        hipEvent_t e = pl->event_pool.back();
+        pl->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct ProfScope {
+    tsfcde_plan_s *pl;
+    int cls;
+    hipEvent_t e0 = nullptr;
+    ProfScope(tsfcde_plan_s *p, int c) : pl(p), cls(c) {
+        if (pl->prof[cls].on) {
+            e0 = get_event(pl);
+            if (e0) (void)hipEventRecord(e0, pl->stream);
+        }
+    }
+    ~ProfScope() {
+        if (e0) {
+            hipEvent_t e1 = get_event(pl);
+            if (e1) {
+                (void)hipEventRecord(e1, pl->stream);
+                pl->prof[cls].pending.emplace_back(e0, e1);
+            } else {
+                pl->event_pool.push_back(e0);
+            }
+        }
+    }
+};
+
+// Called after the stream is known to be idle.
+void harvest(tsfcde_plan_s *pl) {
+    for (auto &pr : pl->prof) {
+        for (auto &ev : pr.pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) {
+                pr.ms += ms;
+                pr.launches += 1;
+            }
+            pl->event_pool.push_back(ev.first);
+            pl->event_pool.push_back(ev.second);
+        }
+        pr.pending.clear();
+    }
+}
+
+// ---- kernel launch dispatch by transform size ------------------------------
+
+template <int R, int DIR, class In, class Out>
+hipError_t launch_col_t(tsfcde_plan_s *pl, int64_t C, const In &in, const Out &out, int pred) {
+    constexpr int B = ColGeo<R>::B;
+    const int64_t grid = (C + B - 1) / B;
+    ProfScope ps(pl, 1);
+    hipLaunchKernelGGL((k_col<R, DIR, In, Out>), dim3((unsigned)grid), dim3(256), 0, pl->stream, C, in, out,
+                       pl->tw_all, pl->sc, pred);
+    return hipGetLastError();
+}
+
+template <int DIR, class In, class Out>
+hipError_t launch_col(tsfcde_plan_s *pl, const RT &rt, const In &in, const Out &out, int pred) {
+    switch (rt.R) {
+#define TSF_CASE(P) \
+    case P: return launch_col_t<P, DIR>(pl, rt.C, in, out, pred);
+        TSF_CASE(2) TSF_CASE(4) TSF_CASE(8) TSF_CASE(16) TSF_CASE(32) TSF_CASE(64) TSF_CASE(128) TSF_CASE(256)
+        TSF_CASE(512) TSF_CASE(1024) TSF_CASE(2048) TSF_CASE(4096)
+#undef TSF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int C_, int MODE>
+hipError_t launch_mid_t(tsfcde_plan_s *pl, const RT &rt, const double2 *spec, double2 *spec_out,
+                        const SymParams &sp, int pred) {
+    ProfScope ps(pl, 2);
+    hipLaunchKernelGGL((k_mid<C_, MODE>), dim3((unsigned)(rt.R / 2)), dim3(MidGeo<C_>::NT), 0, pl->stream, rt.R,
+                       pl->buf, spec, spec_out, rt.tw, sp, pl->tw_all, pl->sc, pred);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_mid(tsfcde_plan_s *pl, const RT &rt, const double2 *spec, double2 *spec_out, const SymParams &sp,
+                      int pred) {
+    switch (rt.C) {
+#define TSF_CASE(P) \
+    case P: return launch_mid_t<P, MODE>(pl, rt, spec, spec_out, sp, pred);
+        TSF_CASE(2) TSF_CASE(4) TSF_CASE(8) TSF_CASE(16) TSF_CASE(32) TSF_CASE(64) TSF_CASE(128) TSF_CASE(256)
+        TSF_CASE(512) TSF_CASE(1024) TSF_CASE(2048) TSF_CASE(4096)
+#undef TSF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---- per-level symbols -------------------------------------------------------
+
+// s = -sigma for A and P, (1 - sigma) for B.  Product scale 1/(4N); solve scale 4N.
+SymParams symbol(const tsfcde_plan_s *pl, int64_t j, double s, const RT &rt, bool solve) {
+    SymParams sp;
+    sp.s0 = pl->eta[j];
+    sp.cre = s * (pl->dp[j] + pl->dm[j]) * pl->hb;
+    sp.cim = s * (pl->dp[j] - pl->dm[j]) * pl->hb;
+    sp.cq = s * pl->gam[j] / pl->h;
+    sp.scale = solve ? 4.0 * (double)rt.N : 1.0 / (4.0 * (double)rt.N);
+    return sp;
+}
+
+template <class Out>
+Out with_red(Out o, tsfcde_plan_s *pl, int site) {
+    o.partials = pl->part + (size_t)site * PARTIAL_SLOTS;
+    o.counter = &pl->sc->cnt[site];
+    return o;
+}
+
+OutSpec out_spec(tsfcde_plan_s *pl, const RT &rt) {
+    OutSpec o{pl->buf, rt.tw, rt.C};
+    o.partials = nullptr;
+    o.counter = nullptr;
+    return o;
+}
+
+InSpec in_spec(tsfcde_plan_s *pl, const RT &rt) { return InSpec{pl->buf, rt.tw, rt.C}; }
+
+// y-side of an operator: pass A with loader `in`, middle, pass C with store `out`.
+template <int MODE, class In, class Out>
+hipError_t run_op(tsfcde_plan_s *pl, const RT &rt, const double2 *spec, const SymParams &sp, const In &in,
+                  const Out &out, int pred) {
+    hipError_t e = launch_col<-1>(pl, rt, in, out_spec(pl, rt), pred);
+    if (e != hipSuccess) return e;
+    e = launch_mid<MODE>(pl, rt, spec, nullptr, sp, pred);
+    if (e != hipSuccess) return e;
+    return launch_col<1>(pl, rt, in_spec(pl, rt), out, pred);
+}
+
+int poll(tsfcde_plan_s *pl) {
+    HIPCHK(hipMemcpyAsync(pl->h_sc, pl->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, pl->stream));
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    harvest(pl);
+    return TSFCDE_OK;
+}
+
+// One CGS iteration (Templates-style preconditioned CGS, Sec. 3.2 "PCGS"):
+//  u = r + beta q ; p = u + beta (q + beta p)      [K1 prologue]
+//  phat = P^{-1} p                                [K1-K3]
+//  vhat = A phat ; alpha = rho / (rt . vhat)      [K4-K6]
+//  q = u - alpha vhat ; uhat = P^{-1} (u + q)     [K7-K9]
+//  x += alpha uhat ; r -= alpha A uhat            [K10-K12], rho' = rt . r
+hipError_t cgs_iteration(tsfcde_plan_s *pl, int64_t j, double *x) {
+    const int64_t n = pl->n;
+    const SymParams sP = symbol(pl, j, -pl->sigma, pl->P, true);
+    const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
+    hipError_t e;
+    {
+        InCgsUP in{pl->r, pl->u, pl->p, pl->q, n, pl->P.C, 0.0, false};
+        OutReal out{pl->phat, n, pl->P.C};
+        out.partials = nullptr;
+        out.counter = nullptr;
+        if ((e = run_op<1>(pl, pl->P, pl->specP, sP, in, out, 1)) != hipSuccess) return e;
+    }
+    {
+        InReal in{pl->phat, n, pl->A.C};
+        OutCgsDot out = with_red(OutCgsDot{pl->vhat, pl->rt, n, pl->A.C}, pl, 0);
+        if ((e = run_op<0>(pl, pl->A, pl->specA, sA, in, out, 1)) != hipSuccess) return e;
+    }
+    {
+        InCgsQ in{pl->u, pl->vhat, pl->q, n, pl->P.C, 0.0};
+        OutReal out{pl->uhat, n, pl->P.C};
+        out.partials = nullptr;
+        out.counter = nullptr;
+        if ((e = run_op<1>(pl, pl->P, pl->specP, sP, in, out, 1)) != hipSuccess) return e;
+    }
+    {
+        // alpha is read from the device scalars by both the loader and the store
+        InCgsX in{pl->uhat, x, n, pl->A.C, 0.0};
+        OutCgsR out = with_red(OutCgsR{pl->r, pl->rt, n, pl->A.C, 0.0}, pl, 1);
+        if ((e = run_op<0>(pl, pl->A, pl->specA, sA, in, out, 1)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int level_rhs(tsfcde_plan_s *pl, int64_t j, const double *d_f, double *x, int warm) {
+    const int64_t n = pl->n;
+    if (j >= 1) {
+        ProfScope ps(pl, 0);
+        const int64_t threads = n / 2;
+        hipLaunchKernelGGL(k_history, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, pl->stream, pl->U, n,
+                           (int)j, pl->cb, pl->clast[j], pl->kappa, pl->H);
+        HIPCHK(hipGetLastError());
+    }
+    const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
+    InReal in{pl->U + (size_t)j * n, n, pl->A.C};
+    OutRhs out{pl->U + (size_t)j * n, pl->H, d_f, pl->g, pl->r, pl->rt, x, n, pl->A.C,
+               pl->eta[j] / pl->sigma, (1.0 - pl->sigma) / pl->sigma, warm, j >= 1 ? 1 : 0};
+    out = with_red(out, pl, 2);
+    HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
+    return TSFCDE_OK;
+}
+
+int status_code(int st) {
+    if (st == ST_BREAKDOWN) return TSFCDE_EBREAKDOWN;
+    if (st == ST_NONFINITE) return TSFCDE_ENONFINITE;
+    return TSFCDE_OK;
+}
+
+constexpr int MAX_RESTARTS = 3;
+
+// y = A x and r = g - y, rt = r (restart from the current iterate).
+int restart_from_x(tsfcde_plan_s *pl, int64_t j, const double *x) {
+    const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
+    InReal in{x, pl->n, pl->A.C};
+    OutRestart out = with_red(OutRestart{pl->g, pl->r, pl->rt, pl->n, pl->A.C}, pl, 3);
+    HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
+    return poll(pl);
+}
+
+int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_stats *st) {
+    if (pl->level >= pl->M) return TSFCDE_EDONE;
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t j = pl->level, n = pl->n;
+    double *x = pl->U + (size_t)(j + 1) * n;
+    int rc = level_rhs(pl, j, d_f, x, pl->warm == TSFCDE_WS_PREV);
+    if (rc) return rc;
+    const bool verify = (pl->flags & TSFCDE_FLAG_VERIFY) != 0;
+    int code = TSFCDE_OK, restarts = 0, iters_seen = 0;
+    double relres_true = -1.0, last_true2 = HUGE_VAL;
+    int chunk = std::max(2, pl->last_iters);
+    {
+        ProfScope ps(pl, 3);
+        for (;;) {
+            // CGS until the device reports done or maxit is reached
+            for (;;) {
+                const int todo = std::min(chunk, pl->maxit - iters_seen);
+                if (todo <= 0) break;
+                for (int k = 0; k < todo; ++k) HIPCHK(cgs_iteration(pl, j, x));
+                if ((rc = poll(pl))) return rc;
+                iters_seen = pl->h_sc->iter;
+                if (pl->h_sc->done) break;
+                chunk = 2;
+            }
+            if (!pl->h_sc->done) {
+                code = TSFCDE_ENOCONV;
+                break;
+            }
+            const int stat = pl->h_sc->status;
+            if (stat == ST_NONFINITE) {
+                code = TSFCDE_ENONFINITE;
+                break;
+            }
+            if (stat == ST_BREAKDOWN && restarts >= MAX_RESTARTS) {
+                code = TSFCDE_EBREAKDOWN;
+                break;
+            }
+            if (stat == ST_OK && !verify) break;
+            // restart from x: recovers from a breakdown, or verifies the true
+            // residual |g - A x| against the recursive one and continues on a gap
+            if ((rc = restart_from_x(pl, j, x))) return rc;
+            relres_true = pl->h_sc->gnorm2 > 0 ? std::sqrt(pl->h_sc->aux0 / pl->h_sc->gnorm2) : 0.0;
+            if (pl->h_sc->done) {
+                code = status_code(pl->h_sc->status);
+                break;
+            }
+            if (stat == ST_OK) {
+                // true residual above tolerance: continue while it keeps falling
+                if (restarts >= MAX_RESTARTS || !(pl->h_sc->aux0 < 0.25 * last_true2)) break;
+                last_true2 = pl->h_sc->aux0;
+            }
+            ++restarts;
+            if (iters_seen >= pl->maxit) {
+                code = TSFCDE_ENOCONV;
+                break;
+            }
+            chunk = std::max(2, pl->last_iters / 2);
+        }
+    }
+    const DevScalars hs = *pl->h_sc;
+    pl->last_iters = std::max(1, hs.iter / (restarts + 1));
+    if (relres_true < 0 && (pl->flags & TSFCDE_FLAG_TRUE_RESIDUAL)) {
+        const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
+        InReal in{x, n, pl->A.C};
+        OutTrueRes out = with_red(OutTrueRes{pl->g, n, pl->A.C}, pl, 3);
+        HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
+        if ((rc = poll(pl))) return rc;
+        relres_true = pl->h_sc->gnorm2 > 0 ? std::sqrt(pl->h_sc->aux0 / pl->h_sc->gnorm2) : 0.0;
+    }
+    if (d_u_out) HIPCHK(hipMemcpyAsync(d_u_out, x, sizeof(double) * n, hipMemcpyDeviceToDevice, pl->stream));
+    pl->level = j + 1;
+    if (st) {
+        st->iters = hs.iter;
+        st->outer_iters = 1;
+        st->restarts = restarts;
+        st->status = code;
+        st->relres = hs.gnorm2 > 0 ? std::sqrt(hs.rnorm2 / hs.gnorm2) : 0.0;
+        st->relres_true = relres_true;
+        st->backward_err = -1.0;
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return code;
+}
+
+double sample(tsfcde_coef_fn fn, const double *arr, void *user, int64_t j, double t) {
+    return fn ? fn(t, user) : arr[j];
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsfcde_workspace_bytes(const tsfcde_problem *prob, size_t *bytes) {
+    int rc = validate(prob);
+    if (rc) return rc;
+    if (!bytes) return TSFCDE_EINVAL;
+    RT A, P;
+    rt_init(A, 2 * prob->n);
+    rt_init(P, prob->n);
+    *bytes = layout_for(prob->n, prob->M, A, P).total;
+    return TSFCDE_OK;
+}
+
+int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, void *stream, tsfcde_plan_t *out) {
+    if (!out) return TSFCDE_EINVAL;
+    *out = nullptr;
+    int rc = validate(prob);
+    if (rc) return rc;
+    if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255)) return TSFCDE_EINVAL;
+    const int64_t n = prob->n, M = prob->M;
+    tsfcde_plan_s *pl = new (std::nothrow) tsfcde_plan_s();
+    if (!pl) return TSFCDE_ENOMEM;
+    pl->alpha = prob->alpha;
+    pl->beta = prob->beta;
+    pl->a = prob->a;
+    pl->b = prob->b;
+    pl->T = prob->T;
+    pl->n = n;
+    pl->M = M;
+    pl->h = (prob->b - prob->a) / (double)(n + 1);
+    pl->tau = prob->T / (double)M;
+    pl->sigma = 1.0 - prob->alpha / 2.0;
+    pl->kappa = std::pow(pl->tau, -prob->alpha) / std::tgamma(2.0 - prob->alpha);
+    pl->hb = std::pow(pl->h, -prob->beta);
+    pl->rtol = prob->rtol > 0 ? prob->rtol : 1e-10;
+    pl->maxit = prob->maxit > 0 ? prob->maxit : 500;
+    pl->warm = prob->warm_start;
+    pl->flags = prob->flags;
+    // coefficients at t_{j+sigma}
+    pl->gam.resize(M);
+    pl->dp.resize(M);
+    pl->dm.resize(M);
+    for (int64_t j = 0; j < M; ++j) {
+        const double t = ((double)j + pl->sigma) * pl->tau;
+        pl->gam[j] = sample(prob->gamma, prob->gamma_at, prob->coef_user, j, t);
+        pl->dp[j] = sample(prob->dplus, prob->dplus_at, prob->coef_user, j, t);
+        pl->dm[j] = sample(prob->dminus, prob->dminus_at, prob->coef_user, j, t);
+        if (!std::isfinite(pl->gam[j]) || !std::isfinite(pl->dp[j]) || !std::isfinite(pl->dm[j]) ||
+            pl->dp[j] < 0.0 || pl->dm[j] < 0.0) {
+            delete pl;
+            return TSFCDE_EINVAL;
+        }
+    }
+    // L2-1sigma tables (Lemma 1)
+    {
+        const double al = prob->alpha, sg = pl->sigma;
+        std::vector<double> av(M + 2), bv(M + 2, 0.0);
+        av[0] = std::pow(sg, 1.0 - al);
+        for (int64_t l = 1; l <= M + 1; ++l) {
+            av[l] = std::pow(l + sg, 1.0 - al) - std::pow(l - 1 + sg, 1.0 - al);
+            bv[l] = (std::pow(l + sg, 2.0 - al) - std::pow(l - 1 + sg, 2.0 - al)) / (2.0 - al) -
+                    0.5 * (std::pow(l + sg, 1.0 - al) + std::pow(l - 1 + sg, 1.0 - al));
+        }
+        pl->eta.resize(M);
+        pl->cbase.assign(M + 2, 0.0);
+        pl->clast.assign(M + 1, 0.0);
+        for (int64_t j = 0; j < M; ++j) pl->eta[j] = pl->kappa * (j == 0 ? av[0] : av[0] + bv[1]);
+        for (int64_t m = 1; m <= M; ++m) pl->cbase[m] = av[m] + bv[m + 1] - bv[m];
+        for (int64_t j = 1; j <= M; ++j) pl->clast[j] = av[j] - bv[j];
+    }
+    rt_init(pl->A, 2 * n);
+    rt_init(pl->P, n);
+    pl->lay = layout_for(n, M, pl->A, pl->P);
+    if (bytes < pl->lay.total) {
+        delete pl;
+        return TSFCDE_ENOMEM;
+    }
+    if (hipGetDevice(&pl->device) != hipSuccess) {
+        delete pl;
+        return TSFCDE_EDEVICE;
+    }
+    pl->stream = reinterpret_cast<hipStream_t>(stream);
+    char *ws = reinterpret_cast<char *>(d_workspace);
+    pl->ws = ws;
+    const Layout &L = pl->lay;
+    pl->U = reinterpret_cast<double *>(ws + L.off_U);
+    double *vec = reinterpret_cast<double *>(ws + L.off_vec);
+    double **vp[NVEC] = {&pl->H, &pl->g, &pl->r, &pl->rt, &pl->u, &pl->p, &pl->q, &pl->phat, &pl->vhat, &pl->uhat};
+    for (int k = 0; k < NVEC; ++k) *vp[k] = vec + (size_t)k * n;
+    pl->tmp = reinterpret_cast<double *>(ws + L.off_tmp);
+    pl->w = reinterpret_cast<double *>(ws + L.off_w);
+    pl->g0 = reinterpret_cast<double *>(ws + L.off_g0);
+    pl->cb = reinterpret_cast<double *>(ws + L.off_cbase);
+    pl->buf = reinterpret_cast<double2 *>(ws + L.off_buf);
+    pl->specA = reinterpret_cast<double2 *>(ws + L.off_specA);
+    pl->specP = reinterpret_cast<double2 *>(ws + L.off_specP);
+    pl->tw_all = reinterpret_cast<double2 *>(ws + L.off_tw);
+    pl->A.lo = reinterpret_cast<double2 *>(ws + L.off_tw2A);
+    pl->A.hi = pl->A.lo + pl->A.nlo;
+    pl->P.lo = reinterpret_cast<double2 *>(ws + L.off_tw2P);
+    pl->P.hi = pl->P.lo + pl->P.nlo;
+    pl->A.tw = Tw2{pl->A.lo, pl->A.hi, pl->A.shift};
+    pl->P.tw = Tw2{pl->P.lo, pl->P.hi, pl->P.shift};
+    pl->part = reinterpret_cast<double *>(ws + L.off_part);
+    pl->sc = reinterpret_cast<DevScalars *>(ws + L.off_sc);
+
+    auto fail = [&](int code) {
+        if (pl->h_sc) (void)hipHostFree(pl->h_sc);
+        delete pl;
+        return code;
+    };
+    if (hipHostMalloc(reinterpret_cast<void **>(&pl->h_sc), sizeof(DevScalars)) != hipSuccess)
+        return fail(TSFCDE_EDEVICE);
+    // scalars: zero, rtol^2
+    std::memset(pl->h_sc, 0, sizeof(DevScalars));
+    pl->h_sc->rtol2 = pl->rtol * pl->rtol;
+    pl->h_sc->done = 1;
+    if (hipMemcpyAsync(pl->sc, pl->h_sc, sizeof(DevScalars), hipMemcpyHostToDevice, pl->stream) != hipSuccess)
+        return fail(TSFCDE_EDEVICE);
+    if (hipMemcpyAsync(pl->cb, pl->cbase.data(), sizeof(double) * (M + 1), hipMemcpyHostToDevice, pl->stream) !=
+        hipSuccess)
+        return fail(TSFCDE_EDEVICE);
+    // twiddle tables
+    hipLaunchKernelGGL(k_twiddle_packed, dim3(32), dim3(256), 0, pl->stream, pl->tw_all, PMAX_LOG2);
+    for (RT *rt : {&pl->A, &pl->P})
+        hipLaunchKernelGGL(k_twiddle_tw2, dim3(64), dim3(256), 0, pl->stream, rt->lo, rt->hi, rt->L, rt->shift,
+                           rt->nhi);
+    // WSGD weights omega_0..omega_n (Lemma 2, Lemma 3 recurrence)
+    hipLaunchKernelGGL(k_grunwald, dim3(1), dim3(1024), 0, pl->stream, prob->beta, n, pl->g0);
+    {
+        const double b2 = prob->beta * prob->beta;
+        const double l1 = (b2 + 3.0 * prob->beta + 2.0) / 12.0, l0 = (4.0 - b2) / 6.0,
+                     lm1 = (b2 - 3.0 * prob->beta + 2.0) / 12.0;
+        hipLaunchKernelGGL(k_wsgd, dim3(256), dim3(256), 0, pl->stream, pl->g0, n, l1, l0, lm1, pl->w);
+    }
+    if (hipGetLastError() != hipSuccess) return fail(TSFCDE_EDEVICE);
+    // spectra: embedding of W (length 2n) and Strang s(W) (length n)
+    {
+        hipLaunchKernelGGL(k_embed_column, dim3(512), dim3(256), 0, pl->stream, pl->w, n, pl->A.L, pl->tmp);
+        InReal in{pl->tmp, pl->A.L, pl->A.C};
+        if (launch_col<-1>(pl, pl->A, in, out_spec(pl, pl->A), 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
+        SymParams sp{};
+        if (launch_mid<2>(pl, pl->A, nullptr, pl->specA, sp, 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
+        hipLaunchKernelGGL(k_strang_column, dim3(512), dim3(256), 0, pl->stream, pl->w, n, pl->tmp);
+        InReal inP{pl->tmp, n, pl->P.C};
+        if (launch_col<-1>(pl, pl->P, inP, out_spec(pl, pl->P), 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
+        if (launch_mid<2>(pl, pl->P, nullptr, pl->specP, sp, 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
+    }
+    // u^0 = phi(x_i)
+    {
+        std::vector<double> u0(n, 0.0);
+        if (prob->phi)
+            for (int64_t i = 0; i < n; ++i) u0[i] = prob->phi(prob->a + (double)(i + 1) * pl->h, prob->phi_user);
+        if (hipMemcpyAsync(pl->U, u0.data(), sizeof(double) * n, hipMemcpyHostToDevice, pl->stream) != hipSuccess)
+            return fail(TSFCDE_EDEVICE);
+        if (hipStreamSynchronize(pl->stream) != hipSuccess) return fail(TSFCDE_EDEVICE);
+    }
+    pl->level = 0;
+    *out = pl;
+    return TSFCDE_OK;
+}
+
+int tsfcde_set_state(tsfcde_plan_t pl, int64_t level, const double *d_U) {
+    if (!pl || !d_U || level < 0 || level > pl->M) return TSFCDE_EINVAL;
+    HIPCHK(hipMemcpyAsync(pl->U, d_U, sizeof(double) * (size_t)(level + 1) * pl->n, hipMemcpyDeviceToDevice,
+                          pl->stream));
+    pl->level = level;
+    return TSFCDE_OK;
+}
+
+int tsfcde_step(tsfcde_plan_t pl, const double *d_f, double *d_u_out, tsfcde_stats *st) {
+    if (!pl) return TSFCDE_EINVAL;
+    return level_step(pl, d_f, d_u_out, st);
+}
+
+int tsfcde_solve(tsfcde_plan_t pl, const double *d_F, int64_t ldF, double *d_U_out, tsfcde_stats *per_level) {
+    if (!pl) return TSFCDE_EINVAL;
+    if (d_F && ldF < pl->n) return TSFCDE_EINVAL;
+    if (pl->level >= pl->M) return TSFCDE_EDONE;
+    while (pl->level < pl->M) {
+        const int64_t j = pl->level;
+        int rc = level_step(pl, d_F ? d_F + (size_t)j * ldF : nullptr, nullptr, per_level ? per_level + j : nullptr);
+        if (rc) return rc;
+    }
+    if (d_U_out)
+        HIPCHK(hipMemcpyAsync(d_U_out, pl->U, sizeof(double) * (size_t)(pl->M + 1) * pl->n, hipMemcpyDeviceToDevice,
+                              pl->stream));
+    return TSFCDE_OK;
+}
+
+int tsfcde_apply(tsfcde_plan_t pl, int32_t op, int64_t j, const double *d_x, double *d_y) {
+    if (!pl || !d_x || !d_y || j < 0 || j >= pl->M) return TSFCDE_EINVAL;
+    const int64_t n = pl->n;
+    if (op == TSFCDE_OP_A || op == TSFCDE_OP_B) {
+        const double s = op == TSFCDE_OP_A ? -pl->sigma : 1.0 - pl->sigma;
+        InReal in{d_x, n, pl->A.C};
+        OutReal out{d_y, n, pl->A.C};
+        out.partials = nullptr;
+        out.counter = nullptr;
+        HIPCHK(run_op<0>(pl, pl->A, pl->specA, symbol(pl, j, s, pl->A, false), in, out, 0));
+    } else if (op == TSFCDE_OP_PINV) {
+        InReal in{d_x, n, pl->P.C};
+        OutReal out{d_y, n, pl->P.C};
+        out.partials = nullptr;
+        out.counter = nullptr;
+        HIPCHK(run_op<1>(pl, pl->P, pl->specP, symbol(pl, j, -pl->sigma, pl->P, true), in, out, 0));
+    } else {
+        return TSFCDE_EINVAL;
+    }
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    harvest(pl);
+    return TSFCDE_OK;
+}
+
+int tsfcde_rhs(tsfcde_plan_t pl, int64_t j, const double *d_f, double *d_g) {
+    if (!pl || !d_g || j < 0 || j >= pl->M || j > pl->level) return TSFCDE_EINVAL;
+    int rc = level_rhs(pl, j, d_f, pl->uhat, 0);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(d_g, pl->g, sizeof(double) * pl->n, hipMemcpyDeviceToDevice, pl->stream));
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    harvest(pl);
+    return TSFCDE_OK;
+}
+
+int tsfcde_weights(tsfcde_plan_t pl, double *d_w) {
+    if (!pl || !d_w) return TSFCDE_EINVAL;
+    HIPCHK(hipMemcpyAsync(d_w, pl->w, sizeof(double) * (pl->n + 1), hipMemcpyDeviceToDevice, pl->stream));
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    return TSFCDE_OK;
+}
+
+int tsfcde_spectrum(tsfcde_plan_t pl, int32_t which, double *d_out) {
+    if (!pl || !d_out) return TSFCDE_EINVAL;
+    const RT *rt;
+    const double2 *spec;
+    if (which == TSFCDE_SPEC_EMBED) {
+        rt = &pl->A;
+        spec = pl->specA;
+    } else if (which == TSFCDE_SPEC_STRANG) {
+        rt = &pl->P;
+        spec = pl->specP;
+    } else {
+        return TSFCDE_EINVAL;
+    }
+    hipLaunchKernelGGL(k_spec_export, dim3(256), dim3(256), 0, pl->stream, spec, rt->R, rt->C,
+                       reinterpret_cast<double2 *>(d_out));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    return TSFCDE_OK;
+}
+
+const double *tsfcde_history(tsfcde_plan_t pl) { return pl ? pl->U : nullptr; }
+
+int64_t tsfcde_level(tsfcde_plan_t pl) { return pl ? pl->level : -1; }
+
+int tsfcde_profile(tsfcde_plan_t pl, int32_t cls, int32_t enable) {
+    if (!pl || cls < 0 || cls > 3) return TSFCDE_EINVAL;
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    harvest(pl);
+    pl->prof[cls].on = enable != 0;
+    pl->prof[cls].launches = 0;
+    pl->prof[cls].ms = 0.0;
+    return TSFCDE_OK;
+}
+
+int tsfcde_profile_read(tsfcde_plan_t pl, int32_t cls, int64_t *launches, double *ms) {
+    if (!pl || cls < 0 || cls > 3) return TSFCDE_EINVAL;
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    harvest(pl);
+    if (launches) *launches = pl->prof[cls].launches;
+    if (ms) *ms = pl->prof[cls].ms;
+    return TSFCDE_OK;
+}
+
+int tsfcde_destroy(tsfcde_plan_t pl) {
+    if (!pl) return TSFCDE_EINVAL;
+    (void)hipStreamSynchronize(pl->stream);
+    harvest(pl);
+    for (hipEvent_t e : pl->event_pool) (void)hipEventDestroy(e);
+    if (pl->h_sc) (void)hipHostFree(pl->h_sc);
+    delete pl;
+    return TSFCDE_OK;
+}
+
+const char *tsfcde_strerror(int s) {
+    switch (s) {
+        case TSFCDE_OK: return "ok";
+        case TSFCDE_EINVAL: return "invalid argument";
+        case TSFCDE_ENOMEM: return "workspace too small";
+        case TSFCDE_EDEVICE: return "HIP runtime error";
+        case TSFCDE_ENOCONV: return "Krylov iteration did not converge within maxit";
+        case TSFCDE_EBREAKDOWN: return "CGS breakdown";
+        case TSFCDE_ENONFINITE: return "non-finite value in the iteration";
+        case TSFCDE_EDONE: return "all time levels already computed";
+        case TSFCDE_EUNSUPPORTED: return "problem size not supported by this build";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/tsfcde.h declares, and rejects invalid problems on the host before any
+device work (no compute calls here)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_1603_00279_amd import _native
+    _native.lib()
+    return _native
+
+
+def test_header_symbols_exported(N):
+    names = N.header_symbols()
+    assert len(names) >= 15
+    L = N.lib()
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in N._SIGS, f"{name} has no ctypes signature"
+
+
+def _problem(N, **kw):
+    arr = np.ones(8)
+    keep = [arr]
+    dptr = ctypes.POINTER(ctypes.c_double)
+    p = N.tsfcde_problem(alpha=0.5, beta=1.5, a=0.0, b=1.0, T=1.0, n=64, M=8)
+    p.gamma_at = p.dplus_at = p.dminus_at = arr.ctypes.data_as(dptr)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p, keep
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("alpha", 0.0, -1), ("alpha", 1.2, -1), ("beta", 1.0, -1), ("beta", 2.5, -1),
+    ("b", 0.0, -1), ("T", 0.0, -1), ("M", 0, -1), ("n", 1, -1), ("warm_start", 7, -1),
+    ("precision", 3, -1), ("n", 100, -8), ("n", 8, -8),
+])
+def test_validation(N, field, value, code):
+    p, keep = _problem(N, **{field: value})
+    nb = ctypes.c_size_t(0)
+    assert N.lib().tsfcde_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == code
+
+
+def test_workspace_grows_with_history(N):
+    sizes = []
+    for M in (8, 16):
+        arr = np.ones(M)
+        dptr = ctypes.POINTER(ctypes.c_double)
+        p = N.tsfcde_problem(alpha=0.5, beta=1.5, a=0.0, b=1.0, T=1.0, n=1024, M=M)
+        p.gamma_at = p.dplus_at = p.dminus_at = arr.ctypes.data_as(dptr)
+        nb = ctypes.c_size_t(0)
+        assert N.lib().tsfcde_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == 0
+        sizes.append(nb.value)
+    # eight more stored levels of 1024 doubles
+    assert sizes[1] - sizes[0] == 8 * 1024 * 8
+
+
+def test_null_arguments_rejected(N):
+    L = N.lib()
+    assert L.tsfcde_plan(None, None, 0, None, None) == -1
+    assert L.tsfcde_step(None, None, None, None) == -1
+    assert L.tsfcde_destroy(None) == -1
+    assert L.tsfcde_level(None) == -1
+    p, keep = _problem(N)
+    h = ctypes.c_void_p()
+    # misaligned / missing workspace is refused before any device call
+    assert L.tsfcde_plan(ctypes.byref(p), None, 1 << 20, None, ctypes.byref(h)) == -1
+    assert L.tsfcde_plan(ctypes.byref(p), ctypes.c_void_p(8), 1 << 20, None, ctypes.byref(h)) == -1
+
+
+def test_strerror(N):
+    for code in range(-8, 1):
+        assert N.lib().tsfcde_strerror(code)
