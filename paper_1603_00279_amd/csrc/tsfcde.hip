@@ -29,6 +29,7 @@ constexpr int PMAX_LOG2 = 12;  // longest in-LDS transform: 4096
 constexpr int64_t NMAX = int64_t(1) << 24;
 constexpr int64_t PARTIAL_SLOTS = 16384;  // doubles per reduction site
 constexpr int NSITES = 4;
+constexpr int NPROF = 5;  // profiling classes, see tsfcde_profile
 
 struct RT {  // real transform of length L = 2N as an R x C complex transform
     int64_t L = 0, N = 0, R = 0, C = 0;
@@ -133,7 +134,7 @@ struct tsfcde_plan_s {
     DevScalars *sc;
     DevScalars *h_sc = nullptr;  // pinned mirror for polling
     int last_iters = 8;
-    ProfRec prof[4];
+    ProfRec prof[NPROF];
     std::vector<hipEvent_t> event_pool;
 };
 
@@ -222,7 +223,7 @@ hipError_t launch_col(tsfcde_plan_s *pl, const RT &rt, const In &in, const Out &
 template <int C_, int MODE>
 hipError_t launch_mid_t(tsfcde_plan_s *pl, const RT &rt, const double2 *spec, double2 *spec_out,
                         const SymParams &sp, int pred) {
-    ProfScope ps(pl, 2);
+    ProfScope ps(pl, MODE == 1 ? 4 : 2);
     hipLaunchKernelGGL((k_mid<C_, MODE>), dim3((unsigned)(rt.R / 2)), dim3(MidGeo<C_>::NT), 0, pl->stream, rt.R,
                        pl->buf, spec, spec_out, rt.tw, sp, pl->tw_all, pl->sc, pred);
     return hipGetLastError();
@@ -708,7 +709,7 @@ const double *tsfcde_history(tsfcde_plan_t pl) { return pl ? pl->U : nullptr; }
 int64_t tsfcde_level(tsfcde_plan_t pl) { return pl ? pl->level : -1; }
 
 int tsfcde_profile(tsfcde_plan_t pl, int32_t cls, int32_t enable) {
-    if (!pl || cls < 0 || cls > 3) return TSFCDE_EINVAL;
+    if (!pl || cls < 0 || cls >= NPROF) return TSFCDE_EINVAL;
     HIPCHK(hipStreamSynchronize(pl->stream));
     harvest(pl);
     pl->prof[cls].on = enable != 0;
@@ -718,7 +719,7 @@ int tsfcde_profile(tsfcde_plan_t pl, int32_t cls, int32_t enable) {
 }
 
 int tsfcde_profile_read(tsfcde_plan_t pl, int32_t cls, int64_t *launches, double *ms) {
-    if (!pl || cls < 0 || cls > 3) return TSFCDE_EINVAL;
+    if (!pl || cls < 0 || cls >= NPROF) return TSFCDE_EINVAL;
     HIPCHK(hipStreamSynchronize(pl->stream));
     harvest(pl);
     if (launches) *launches = pl->prof[cls].launches;
