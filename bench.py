@@ -41,7 +41,7 @@ def history_bytes(n, j):
     return 8 * n * (j + 1) + 8 * n if j >= 1 else 0
 
 
-KCLASS = {"history": 0, "col_passes": 1, "mid_matvec": 2, "cgs_chunks": 3, "mid_precond": 4}
+KCLASS = {"history": 0, "col_passes": 1, "mid_matvec": 2, "cgs_chunks": 3, "mid_precond": 4, "fused_cols": 5}
 
 
 def build_sources(prob, device):

@@ -179,7 +179,8 @@ int64_t tsfcde_level(tsfcde_plan_t plan);
  * every launch of one kernel class: 0 = history sum, 1 = FFT column passes,
  * 2 = middle passes of the Toeplitz products (row FFTs with the embedding
  * symbol multiply), 3 = whole Krylov iteration chunks, 4 = middle passes of
- * the preconditioner solves (row FFTs with the Strang symbol divide).  enable != 0 starts recording and clears the
+ * the preconditioner solves (row FFTs with the Strang symbol divide), 5 =
+ * fused column passes (preconditioner inverse + product forward).  enable != 0 starts recording and clears the
  * totals; tsfcde_profile_read synchronizes the stream and returns the number
  * of recorded launches and their summed duration in milliseconds. */
 int tsfcde_profile(tsfcde_plan_t plan, int32_t kernel_class, int32_t enable);

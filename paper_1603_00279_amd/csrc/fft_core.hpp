@@ -1,14 +1,16 @@
 // fft_core.hpp -- register/LDS Stockham FFT building blocks for gfx950.
 //
-// A transform of length P (power of two, 2..4096) is held by P/E lanes, each
-// lane owning E = min(P, 16) complex values.  Lane j holds the elements at
-// positions j + (P/E)*m, m = 0..E-1 ("canonical layout").  One Stockham
-// stage of radix RAD combines, for butterfly index bf, the inputs
-// bf + (P/RAD)*r; with bf = j + (P/E)*q these are exactly the lane's own
-// values v[q + (E/RAD)*r], so every stage starts from registers.  Outputs go
-// to LDS at the self-sorting position (bf/NS)*NS*RAD + bf%NS + r*NS and are
-// read back in canonical layout for the next stage; after the last stage the
-// canonical layout holds the transform in natural frequency order.
+// A transform of length P (power of two, 2..4096) is held by T = P/E lanes,
+// each lane owning E complex values (E is a tuning parameter: 4, 8 or 16;
+// fewer values per lane means more waves per SIMD to hide memory latency).
+// Lane j holds the elements at positions j + T*m, m = 0..E-1 ("canonical
+// layout").  One Stockham stage of radix RAD combines, for butterfly index
+// bf, the inputs bf + (P/RAD)*r; with bf = j + T*q these are exactly the
+// lane's own values v[q + (E/RAD)*r], so every stage starts from registers.
+// The outputs of a stage go to the self-sorting position
+// (bf/NS)*NS*RAD + bf%NS + r*NS: to LDS for all but the last stage, and to a
+// caller-supplied sink for the last one (global memory, or LDS in natural
+// frequency order).
 //
 // Twiddles come from a table tw_P[m] = exp(-2 pi i m / P) (FP64, built on the
 // device at plan time); the inverse transform uses conjugates.  Butterfly
@@ -42,7 +44,6 @@ template <int K, int DIR> __device__ __forceinline__ double2 rot16(double2 a) {
     else if constexpr (k == 8) return make_double2(-a.x, -a.y);
     else if constexpr (k == 12) return mul_i<-DIR>(a);
     else {
-        // cos/sin of 2 pi k/16 with the angle's sign fixed by DIR
         constexpr double cs[16] = {1, C1, H, S1, 0, -S1, -H, -C1, -1, -C1, -H, -S1, 0, S1, H, C1};
         constexpr double sn[16] = {0, S1, H, C1, 1, C1, H, S1, 0, -S1, -H, -C1, -1, -C1, -H, -S1};
         const double c = cs[k];
@@ -51,8 +52,8 @@ template <int K, int DIR> __device__ __forceinline__ double2 rot16(double2 a) {
     }
 }
 
-// In-place DFT of length R (2, 4, 8, 16) on a[0..R), natural order in and out,
-// kernel exp(DIR * 2 pi i jk / R).  Radix-2 decimation in time, fully unrolled.
+// In-place DFT of length R (1, 2, 4, 8, 16) on a[0..R), natural order in and
+// out, kernel exp(DIR * 2 pi i jk / R).  Radix-2 decimation in time, unrolled.
 template <int R, int DIR> struct Dft {
     static __device__ __forceinline__ void run(double2 *a) {
         if constexpr (R == 1) {
@@ -81,9 +82,10 @@ template <int R, int DIR> struct Dft {
     }
 };
 
-template <int P> struct Geo {
-    static constexpr int E = P >= 16 ? 16 : P;  // values per lane
-    static constexpr int T = P / E;             // lanes per transform
+// Geometry of a length-P transform at (at most) EMAX values per lane.
+template <int P, int EMAX> struct Geo {
+    static constexpr int E = P < EMAX ? P : EMAX;  // values per lane
+    static constexpr int T = P / E;               // lanes per transform
 };
 
 // LDS index padding: one spare slot every 16 elements breaks the bank
@@ -95,8 +97,10 @@ __host__ __device__ constexpr int lpad_size(int P) { return P + (P >> 4) + 1; }
 // (tables for P = 2, 4, 8, ... are stored back to back).
 __host__ __device__ constexpr int tw_offset(int P) { return P - 2; }
 
-template <int P, int E, int RAD, int NS, int DIR>
-__device__ __forceinline__ void stage_bfly(double2 (&v)[E], int j, const double2 *__restrict__ twP) {
+// twP[m * TS] = exp(-2 pi i m / P): the twiddle table of a length-P transform
+// (TS > 1 when a longer table, e.g. one staged in LDS, is shared).
+template <int P, int E, int RAD, int NS, int DIR, int TS>
+__device__ __forceinline__ void stage_bfly(double2 (&v)[E], int j, const double2 *twP) {
     constexpr int NB = E / RAD;
     constexpr int T = P / E;
 #pragma unroll
@@ -110,7 +114,7 @@ __device__ __forceinline__ void stage_bfly(double2 (&v)[E], int j, const double2
             constexpr int STRIDE = P / (NS * RAD);
 #pragma unroll
             for (int r = 1; r < RAD; ++r) {
-                double2 w = twP[r * k * STRIDE];
+                double2 w = twP[r * k * (STRIDE * TS)];
                 if (DIR > 0) w.y = -w.y;
                 a[r] = cmul(a[r], w);
             }
@@ -121,22 +125,32 @@ __device__ __forceinline__ void stage_bfly(double2 (&v)[E], int j, const double2
     }
 }
 
-// Full transform of length P on the canonical register layout.  `lds` points
-// at this transform's LDS slab; element position p lives at
-// lds[lpad(p) * LS], where LS is the interleave stride (several transforms
-// may share a slab, interleaved).  All lanes of the workgroup must call this
-// (it contains barriers); lanes with active == false only take part in the
-// barriers.
-template <int P, int NS, int DIR>
-__device__ __forceinline__ void fft_stages(double2 (&v)[Geo<P>::E], int j, bool active,
-                                           const double2 *__restrict__ twP, double2 *lds, int LS) {
-    if constexpr (NS < P) {
-        constexpr int E = Geo<P>::E;
-        constexpr int T = Geo<P>::T;
-        constexpr int REM = P / NS;
-        constexpr int RAD = REM >= 16 ? 16 : REM;
-        constexpr int NB = E / RAD;
-        stage_bfly<P, E, RAD, NS, DIR>(v, j, twP);
+// Runs the stages of a length-P transform from sub-length NS upwards on the
+// canonical register layout.  Intermediate results are exchanged through the
+// LDS slab `lds` (element p at lds[lpad(p) * LS]; several transforms may
+// share a slab, interleaved with stride LS).  The outputs of the last stage
+// are handed to sink(pos, value) (natural frequency order pos).  Every lane
+// of the workgroup must call this (it contains barriers); lanes with
+// active == false only take part in the barriers.
+template <int P, int E, int NS, int DIR, int TS, class Sink>
+__device__ __forceinline__ void fft_stages(double2 (&v)[E], int j, bool active, const double2 *twP, double2 *lds,
+                                           int LS, Sink &sink) {
+    constexpr int T = P / E;
+    constexpr int REM = P / NS;
+    constexpr int RAD = REM >= E ? E : REM;
+    constexpr int NB = E / RAD;
+    stage_bfly<P, E, RAD, NS, DIR, TS>(v, j, twP);
+    if constexpr (NS * RAD == P) {
+        if (active) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int bf = j + T * q;
+                const int base = (bf & ~(NS - 1)) * RAD + (bf & (NS - 1));
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) sink(base + r * NS, v[q + NB * r]);
+            }
+        }
+    } else {
         if (active) {
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
@@ -152,15 +166,38 @@ __device__ __forceinline__ void fft_stages(double2 (&v)[Geo<P>::E], int j, bool 
             for (int m = 0; m < E; ++m) v[m] = lds[lpad(j + T * m) * LS];
         }
         __syncthreads();
-        fft_stages<P, NS * RAD, DIR>(v, j, active, twP, lds, LS);
+        fft_stages<P, E, NS * RAD, DIR, TS>(v, j, active, twP, lds, LS, sink);
     }
 }
 
-template <int P, int DIR>
-__device__ __forceinline__ void fft(double2 (&v)[Geo<P>::E], int j, bool active,
-                                    const double2 *__restrict__ tw_all, double2 *lds, int LS) {
-    fft_stages<P, 1, DIR>(v, j, active, tw_all + tw_offset(P), lds, LS);
+// Transform with twiddles from the packed global table.
+template <int P, int E, int DIR, class Sink>
+__device__ __forceinline__ void fft(double2 (&v)[E], int j, bool active, const double2 *__restrict__ tw_all,
+                                    double2 *lds, int LS, Sink &sink) {
+    fft_stages<P, E, 1, DIR, 1>(v, j, active, tw_all + tw_offset(P), lds, LS, sink);
 }
+
+// Transform with twiddles from a table of length P * TS (typically staged in
+// LDS at kernel start, so no stage waits on a global load).
+template <int P, int E, int DIR, int TS, class Sink>
+__device__ __forceinline__ void fft_t(double2 (&v)[E], int j, bool active, const double2 *tw, double2 *lds, int LS,
+                                      Sink &sink) {
+    fft_stages<P, E, 1, DIR, TS>(v, j, active, tw, lds, LS, sink);
+}
+
+// Cooperative copy of the length-P twiddle table into LDS (P entries).
+template <int P>
+__device__ __forceinline__ void stage_twiddles(double2 *dst, const double2 *__restrict__ tw_all, int t, int nt) {
+    const double2 *src = tw_all + tw_offset(P);
+    for (int i = t; i < P; i += nt) dst[i] = src[i];
+}
+
+// Sink writing the transform in natural order into an LDS slab.
+struct LdsSink {
+    double2 *lds;
+    int LS;
+    __device__ __forceinline__ void operator()(int pos, double2 val) const { lds[lpad(pos) * LS] = val; }
+};
 
 // Two-level twiddle table for exp(-2 pi i m / L), m < L:
 // w(m) = hi[m >> shift] * lo[m & ((1 << shift) - 1)].

@@ -419,20 +419,47 @@ struct OutRestart {
 };
 
 // ---------------------------------------------------------------------------
-// Column pass: length-R FFTs down B adjacent columns per workgroup.
+// Values per lane of the FFT passes (4, 8 or 16); fewer values per lane give
+// more waves per SIMD.  Chosen per kernel family at build time.
 // ---------------------------------------------------------------------------
-template <int R> struct ColGeo {
-    static constexpr int E = Geo<R>::E;
-    static constexpr int T = Geo<R>::T;
-    static constexpr int B = 256 / T;
+#ifndef TSF_E_COL
+#define TSF_E_COL 8
+#endif
+#ifndef TSF_E_MID
+#define TSF_E_MID 8
+#endif
+#ifndef TSF_E_FUSE
+#define TSF_E_FUSE 8
+#endif
+
+// ---------------------------------------------------------------------------
+// Column pass: length-R FFTs down B adjacent columns per workgroup
+// (B*R <= 4096 complex values, i.e. 64 KiB, per workgroup).
+// ---------------------------------------------------------------------------
+template <int R, int EMAX> struct ColGeo {
+    static constexpr int E = Geo<R, EMAX>::E;
+    static constexpr int T = Geo<R, EMAX>::T;
+    static constexpr int B0 = 4096 / R;
+    static constexpr int B = (B0 * T > 1024) ? 1024 / T : B0;  // columns per workgroup
+    static constexpr int NT = B * T;                            // threads per workgroup
 };
 
-template <int R, int DIR, class In, class Out>
-__global__ void __launch_bounds__(256) k_col(int64_t C, In in, Out out, const double2 *__restrict__ tw_all,
-                                             DevScalars *sc, int pred) {
+template <class Out> struct ColSink {
+    Out *out;
+    int64_t c;
+    double *acc;
+    __device__ __forceinline__ void operator()(int pos, double2 val) const { out->store(pos, c, val, acc); }
+};
+
+template <int R, int EMAX, int DIR, class In, class Out>
+__global__ void __launch_bounds__((ColGeo<R, EMAX>::NT)) k_col(int64_t C, In in, Out out,
+                                                             const double2 *__restrict__ tw_all, DevScalars *sc,
+                                                             int pred) {
     if (pred && sc->done) return;
-    constexpr int E = ColGeo<R>::E, T = ColGeo<R>::T, B = ColGeo<R>::B;
+    using G = ColGeo<R, EMAX>;
+    constexpr int E = G::E, T = G::T, B = G::B;
     __shared__ double2 lds[lpad_size(R) * B];
+    __shared__ double2 twl[R];
     const int t = threadIdx.x;
     const int b = t % B, j = t / B;
     const int64_t c = (int64_t)blockIdx.x * B + b;
@@ -440,17 +467,18 @@ __global__ void __launch_bounds__(256) k_col(int64_t C, In in, Out out, const do
     in.prep(sc);
     out.prep(sc);
     double2 v[E];
-    if (active) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = in.load(j + T * m, c);
-    }
-    fft<R, DIR>(v, j, active, tw_all, lds + b, B);
+    for (int m = 0; m < E; ++m) v[m] = active ? in.load(j + T * m, c) : make_double2(0.0, 0.0);
+    // the first barrier inside the transform orders these writes before any use
+    stage_twiddles<R>(twl, tw_all, t, G::NT);
     double acc[Out::NACC > 0 ? Out::NACC : 1];
 #pragma unroll
     for (int a = 0; a < (Out::NACC > 0 ? Out::NACC : 1); ++a) acc[a] = 0.0;
-    if (active) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) out.store(j + T * m, c, v[m], acc);
+    ColSink<Out> sink{&out, c, acc};
+    if constexpr (R > E) {
+        fft_t<R, E, DIR, 1>(v, j, active, twl, lds + b, B, sink);
+    } else {
+        fft<R, E, DIR>(v, j, active, tw_all, lds + b, B, sink);
     }
     if constexpr (Out::NACC > 0) {
         double tot[Out::NACC];
@@ -458,6 +486,91 @@ __global__ void __launch_bounds__(256) k_col(int64_t C, In in, Out out, const do
             if (threadIdx.x == 0) out.final(tot, sc);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Fused column pass: inverse length-RP column FFTs of the preconditioner
+// transform (R_P x C) followed, for the same columns, by the forward
+// length-2RP column FFTs of the following Toeplitz product (R_A = 2R_P rows,
+// same C).  The packed preconditioner output z'[m] = y[2m] + i y[2m+1],
+// m = row*C + col, is exactly the nonzero half of the product's packed input,
+// so the solve's result never goes through memory.  `op` may apply a vector
+// update to it (x += alpha * uhat) and returns the product's input.
+// ---------------------------------------------------------------------------
+struct OpIdent {
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ double2 operator()(int, int64_t, double2 v) const { return v; }
+};
+
+struct OpCgsX {  // x += alpha * uhat at real indices 2m, 2m+1
+    double *x;
+    int64_t C;
+    double alpha;
+    __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
+    __device__ __forceinline__ double2 operator()(int row, int64_t col, double2 uh) const {
+        double2 *px = reinterpret_cast<double2 *>(x + 2 * (row * C + col));
+        double2 xv = *px;
+        *px = make_double2(fma(alpha, uh.x, xv.x), fma(alpha, uh.y, xv.y));
+        return uh;
+    }
+};
+
+struct BufSink {  // y[pos*C + c] = val * tw(2*pos*c)
+    double2 *y;
+    const Tw2 *tw;
+    int64_t C, c;
+    __device__ __forceinline__ void operator()(int pos, double2 val) const {
+        y[pos * C + c] = cmul(val, (*tw)(2 * (int64_t)pos * c));
+    }
+};
+
+template <int RP, int EMAX> struct FuseGeo {
+    static constexpr int RA = 2 * RP;
+    using GA = ColGeo<RA, EMAX>;
+    static constexpr int EA = GA::E, TA = GA::T, B = GA::B, NT = GA::NT;
+    static constexpr int EP = Geo<RP, EA>::E, TP = Geo<RP, EA>::T;
+};
+
+template <int RP, int EMAX, class Op>
+__global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, const double2 *__restrict__ bufP, Tw2 twP,
+                                                                double2 *__restrict__ bufA, Tw2 twA, Op op,
+                                                                const double2 *__restrict__ tw_all, DevScalars *sc,
+                                                                int pred) {
+    if (pred && sc->done) return;
+    using G = FuseGeo<RP, EMAX>;
+    constexpr int RA = G::RA, EA = G::EA, TA = G::TA, B = G::B, EP = G::EP, TP = G::TP;
+    __shared__ double2 lds[lpad_size(RA) * B];
+    __shared__ double2 twl[RA];
+    const int t = threadIdx.x;
+    const int b = t % B, j = t / B;
+    const int64_t c = (int64_t)blockIdx.x * B + b;
+    const bool colok = c < C;
+    const bool activeP = colok && j < TP;
+    op.prep(sc);
+    // inverse preconditioner column FFT (conjugate four-step twiddle first)
+    double2 vp[EP];
+#pragma unroll
+    for (int m = 0; m < EP; ++m) {
+        const int row = j + TP * m;
+        vp[m] = activeP ? cmul(bufP[row * C + c], cconj(twP(2 * (int64_t)row * c))) : make_double2(0.0, 0.0);
+    }
+    stage_twiddles<RA>(twl, tw_all, t, G::NT);
+    __syncthreads();
+    LdsSink lsink{lds + b, B};
+    fft_t<RP, EP, 1, 2>(vp, j, activeP, twl, lds + b, B, lsink);
+    __syncthreads();
+    // product input: rows < RP carry the solve's output, rows >= RP are zero
+    double2 va[EA];
+#pragma unroll
+    for (int m = 0; m < EA; ++m) {
+        const int row = j + TA * m;
+        double2 val = make_double2(0.0, 0.0);
+        if (colok && row < RP) val = op(row, c, lds[lpad(row) * B + b]);
+        va[m] = val;
+    }
+    __syncthreads();
+    BufSink bsink{bufA, &twA, C, c};
+    fft_t<RA, EA, -1, 1>(va, j, colok, twl, lds + b, B, bsink);
 }
 
 // ---------------------------------------------------------------------------
@@ -501,21 +614,34 @@ __device__ __forceinline__ void pair_update(double2 &za, double2 &zb, double2 w,
     }
 }
 
-template <int C_> struct MidGeo {
-    static constexpr int E = Geo<C_>::E;
-    static constexpr int T = Geo<C_>::T;
+template <int C_, int EMAX> struct MidGeo {
+    // two rows per workgroup, at most 1024 threads
+    static constexpr int E0 = Geo<C_, EMAX>::E;
+    static constexpr int E = (2 * (C_ / E0) > 1024) ? C_ / 512 : E0;
+    static constexpr int T = C_ / E;
     static constexpr int NT = (2 * T + 63) / 64 * 64;  // threads per workgroup
     static constexpr int LS = lpad_size(C_);
 };
 
-template <int C_, int MODE>
-__global__ void __launch_bounds__(MidGeo<C_>::NT) k_mid(int64_t R, double2 *Y, const double2 *spec, double2 *spec_out,
-                                                        Tw2 twL, SymParams sp, const double2 *__restrict__ tw_all,
-                                                        DevScalars *sc, int pred) {
+struct RowSink {  // Y[row*C + pos] = val
+    double2 *Y;
+    int64_t base;
+    __device__ __forceinline__ void operator()(int pos, double2 val) const { Y[base + pos] = val; }
+};
+
+template <int C_, int EMAX, int MODE>
+__global__ void __launch_bounds__((MidGeo<C_, EMAX>::NT)) k_mid(int64_t R, double2 *Y, const double2 *spec,
+                                                              double2 *spec_out, Tw2 twL, SymParams sp,
+                                                              const double2 *__restrict__ tw_all, DevScalars *sc,
+                                                              int pred) {
     if (pred && sc->done) return;
-    constexpr int E = MidGeo<C_>::E, T = MidGeo<C_>::T, LS = MidGeo<C_>::LS;
+    using G = MidGeo<C_, EMAX>;
+    constexpr int E = G::E, T = G::T, LS = G::LS;
     constexpr int64_t C = C_;
+    // stage twiddles in LDS when both rows and the table fit in 160 KiB
+    constexpr bool TWL = C_ > E && (2 * LS + C_) * 16 <= 163840;
     __shared__ double2 lds[2 * LS];
+    __shared__ double2 twl[TWL ? C_ : 1];
     const int wg = blockIdx.x;
     const int64_t ra = wg == 0 ? 0 : wg;
     const int64_t rb = wg == 0 ? R / 2 : R - wg;
@@ -525,31 +651,47 @@ __global__ void __launch_bounds__(MidGeo<C_>::NT) k_mid(int64_t R, double2 *Y, c
     const int64_t row = sel == 0 ? ra : rb;
     double2 *slab = lds + (sel < 2 ? sel : 0) * LS;
     double2 v[E];
-    if (active) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = Y[row * C + j + T * m];
+    for (int m = 0; m < E; ++m) v[m] = active ? Y[row * C + j + T * m] : make_double2(0.0, 0.0);
+    // Everything the pair step needs is fetched now, so its latency overlaps the
+    // row loads and the forward transform: spectrum values and untangle twiddles
+    // of this thread's pairs (rows ra, rb with ra != 0), and the stage twiddles.
+    constexpr int NPT = (C_ + G::NT - 1) / G::NT;
+    double2 pLa[NPT], pLb[NPT], pW[NPT];
+    if (wg != 0) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int k2 = t + G::NT * i;
+            pLa[i] = pLb[i] = pW[i] = make_double2(0.0, 0.0);
+            if (k2 < C_) {
+                if constexpr (MODE != 2) {
+                    pLa[i] = spec[ra * C + k2];
+                    pLb[i] = spec[rb * C + (C_ - 1 - k2)];
+                }
+                pW[i] = twL(ra + R * k2);
+            }
+        }
     }
-    fft<C_, -1>(v, j, active, tw_all, slab, 1);
-    if (active) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) slab[lpad(j + T * m)] = v[m];
+    LdsSink lsink{slab, 1};
+    if constexpr (TWL) {
+        stage_twiddles<C_>(twl, tw_all, t, G::NT);
+        fft_t<C_, E, -1, 1>(v, j, active, twl, slab, 1, lsink);
+    } else {
+        fft<C_, E, -1>(v, j, active, tw_all, slab, 1, lsink);
     }
     __syncthreads();
     double2 *s0 = lds, *s1 = lds + LS;
     const int nthr = blockDim.x;
     if (wg != 0) {
-        for (int k2 = t; k2 < C_; k2 += nthr) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int k2 = t + G::NT * i;
+            if (k2 >= C_) break;
             const int k2b = C_ - 1 - k2;
             double2 za = s0[lpad(k2)], zb = s1[lpad(k2b)];
-            const int64_t k = ra + R * k2;
             const int64_t pa = ra * C + k2, pb = rb * C + k2b;
-            double2 La = make_double2(0, 0), Lb = make_double2(0, 0);
-            if constexpr (MODE != 2) {
-                La = spec[pa];
-                Lb = spec[pb];
-            }
             double2 xa, xb;
-            pair_update<MODE>(za, zb, twL(k), La, Lb, sp, &xa, &xb);
+            pair_update<MODE>(za, zb, pW[i], pLa[i], pLb[i], sp, &xa, &xb);
             if constexpr (MODE == 2) {
                 spec_out[pa] = xa;
                 spec_out[pb] = xb;
@@ -617,15 +759,14 @@ __global__ void __launch_bounds__(MidGeo<C_>::NT) k_mid(int64_t R, double2 *Y, c
     }
     if constexpr (MODE == 2) return;
     __syncthreads();
-    if (active) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = slab[lpad(j + T * m)];
-    }
+    for (int m = 0; m < E; ++m) v[m] = active ? slab[lpad(j + T * m)] : make_double2(0.0, 0.0);
     __syncthreads();
-    fft<C_, 1>(v, j, active, tw_all, slab, 1);
-    if (active) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) Y[row * C + j + T * m] = v[m];
+    RowSink rsink{Y, row * C};
+    if constexpr (TWL) {
+        fft_t<C_, E, 1, 1>(v, j, active, twl, slab, 1, rsink);
+    } else {
+        fft<C_, E, 1>(v, j, active, tw_all, slab, 1, rsink);
     }
 }
 
@@ -642,23 +783,19 @@ __global__ void __launch_bounds__(256) k_history(const double *__restrict__ U, i
     double2 prev = *reinterpret_cast<const double2 *>(U + i);
     double2 acc = make_double2(0.0, 0.0);
     int s = 0;
-    // four levels in flight per step
-    for (; s + 4 <= j; s += 4) {
-        double2 x1 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1) * n + i);
-        double2 x2 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 2) * n + i);
-        double2 x3 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 3) * n + i);
-        double2 x4 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 4) * n + i);
-        const double c1 = s == 0 ? clast : cbase[j - s];
-        const double c2 = cbase[j - s - 1], c3 = cbase[j - s - 2], c4 = cbase[j - s - 3];
-        acc.x = fma(c1, x1.x - prev.x, acc.x);
-        acc.y = fma(c1, x1.y - prev.y, acc.y);
-        acc.x = fma(c2, x2.x - x1.x, acc.x);
-        acc.y = fma(c2, x2.y - x1.y, acc.y);
-        acc.x = fma(c3, x3.x - x2.x, acc.x);
-        acc.y = fma(c3, x3.y - x2.y, acc.y);
-        acc.x = fma(c4, x4.x - x3.x, acc.x);
-        acc.y = fma(c4, x4.y - x3.y, acc.y);
-        prev = x4;
+    // eight levels in flight per step
+    constexpr int U8 = 8;
+    for (; s + U8 <= j; s += U8) {
+        double2 x[U8];
+#pragma unroll
+        for (int q = 0; q < U8; ++q) x[q] = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1 + q) * n + i);
+#pragma unroll
+        for (int q = 0; q < U8; ++q) {
+            const double cq = (s + q == 0) ? clast : cbase[j - s - q];
+            acc.x = fma(cq, x[q].x - prev.x, acc.x);
+            acc.y = fma(cq, x[q].y - prev.y, acc.y);
+            prev = x[q];
+        }
     }
     for (; s < j; ++s) {
         double2 x1 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1) * n + i);

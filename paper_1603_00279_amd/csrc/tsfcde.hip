@@ -29,7 +29,7 @@ constexpr int PMAX_LOG2 = 12;  // longest in-LDS transform: 4096
 constexpr int64_t NMAX = int64_t(1) << 24;
 constexpr int64_t PARTIAL_SLOTS = 16384;  // doubles per reduction site
 constexpr int NSITES = 4;
-constexpr int NPROF = 5;  // profiling classes, see tsfcde_profile
+constexpr int NPROF = 6;  // profiling classes, see tsfcde_profile
 
 struct RT {  // real transform of length L = 2N as an R x C complex transform
     int64_t L = 0, N = 0, R = 0, C = 0;
@@ -45,20 +45,30 @@ int ilog2(int64_t v) {
     return l;
 }
 
-void rt_init(RT &rt, int64_t L) {
+// L = 2N real values as an R x C complex transform.
+void rt_init(RT &rt, int64_t L, int64_t R) {
     rt.L = L;
     rt.N = L / 2;
-    const int lg = ilog2(rt.N);
-    rt.R = int64_t(1) << (lg / 2);
-    rt.C = rt.N / rt.R;
+    rt.R = R;
+    rt.C = rt.N / R;
     rt.shift = (ilog2(L) + 1) / 2;
     rt.nlo = int64_t(1) << rt.shift;
     rt.nhi = (L >> rt.shift) + 1;
 }
 
+// Toeplitz products: L = 2n, N = n = R_A x C with R_A = 2^floor(log2(n)/2).
+// Preconditioner: L = n, N = n/2 = R_P x C with R_P = R_A/2 and the same C,
+// so the preconditioner's inverse column pass and the next product's forward
+// column pass work on the same columns (k_fuse).
+void rt_pair(RT &A, RT &P, int64_t n) {
+    const int64_t RA = int64_t(1) << (ilog2(n) / 2);
+    rt_init(A, 2 * n, RA);
+    rt_init(P, n, RA / 2);
+}
+
 struct Layout {
-    size_t off_U, off_vec, off_tmp, off_w, off_g0, off_cbase, off_buf, off_specA, off_specP, off_tw, off_tw2A, off_tw2P,
-        off_part, off_sc, total;
+    size_t off_U, off_vec, off_tmp, off_w, off_g0, off_cbase, off_buf, off_bufP, off_specA, off_specP, off_tw, off_tw2A,
+        off_tw2P, off_part, off_sc, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -80,6 +90,7 @@ Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P) {
     l.off_g0 = take(sizeof(double) * (size_t)(n + 2));
     l.off_cbase = take(sizeof(double) * (size_t)(M + 2));
     l.off_buf = take(sizeof(double2) * (size_t)A.N);
+    l.off_bufP = take(sizeof(double2) * (size_t)P.N);
     l.off_specA = take(sizeof(double2) * (size_t)A.N);
     l.off_specP = take(sizeof(double2) * (size_t)P.N);
     l.off_tw = take(sizeof(double2) * (size_t)((int64_t(1) << (PMAX_LOG2 + 1)) - 2));
@@ -130,7 +141,7 @@ struct tsfcde_plan_s {
     Layout lay;
     char *ws;
     double *U, *H, *g, *r, *rt, *u, *p, *q, *phat, *vhat, *uhat, *tmp, *w, *g0, *cb, *part;
-    double2 *buf, *specA, *specP, *tw_all;
+    double2 *buf, *bufP, *specA, *specP, *tw_all;
     DevScalars *sc;
     DevScalars *h_sc = nullptr;  // pinned mirror for polling
     int last_iters = 8;
@@ -198,13 +209,15 @@ void harvest(tsfcde_plan_s *pl) {
 
 // ---- kernel launch dispatch by transform size ------------------------------
 
+#define TSF_SIZES(X) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
 template <int R, int DIR, class In, class Out>
 hipError_t launch_col_t(tsfcde_plan_s *pl, int64_t C, const In &in, const Out &out, int pred) {
-    constexpr int B = ColGeo<R>::B;
-    const int64_t grid = (C + B - 1) / B;
+    using G = ColGeo<R, TSF_E_COL>;
+    const int64_t grid = (C + G::B - 1) / G::B;
     ProfScope ps(pl, 1);
-    hipLaunchKernelGGL((k_col<R, DIR, In, Out>), dim3((unsigned)grid), dim3(256), 0, pl->stream, C, in, out,
-                       pl->tw_all, pl->sc, pred);
+    hipLaunchKernelGGL((k_col<R, TSF_E_COL, DIR, In, Out>), dim3((unsigned)grid), dim3(G::NT), 0, pl->stream, C, in,
+                       out, pl->tw_all, pl->sc, pred);
     return hipGetLastError();
 }
 
@@ -213,30 +226,56 @@ hipError_t launch_col(tsfcde_plan_s *pl, const RT &rt, const In &in, const Out &
     switch (rt.R) {
 #define TSF_CASE(P) \
     case P: return launch_col_t<P, DIR>(pl, rt.C, in, out, pred);
-        TSF_CASE(2) TSF_CASE(4) TSF_CASE(8) TSF_CASE(16) TSF_CASE(32) TSF_CASE(64) TSF_CASE(128) TSF_CASE(256)
-        TSF_CASE(512) TSF_CASE(1024) TSF_CASE(2048) TSF_CASE(4096)
+        TSF_SIZES(TSF_CASE)
+#undef TSF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int RP, class Op>
+hipError_t launch_fuse_t(tsfcde_plan_s *pl, const Op &op, int pred) {
+    if constexpr (RP > 2048) {
+        return hipErrorInvalidValue;
+    } else {
+        using G = FuseGeo<RP, TSF_E_FUSE>;
+        const int64_t C = pl->A.C;
+        const int64_t grid = (C + G::B - 1) / G::B;
+        ProfScope ps(pl, 5);
+        hipLaunchKernelGGL((k_fuse<RP, TSF_E_FUSE, Op>), dim3((unsigned)grid), dim3(G::NT), 0, pl->stream, C,
+                           pl->bufP, pl->P.tw, pl->buf, pl->A.tw, op, pl->tw_all, pl->sc, pred);
+        return hipGetLastError();
+    }
+}
+
+// preconditioner inverse column pass fused with the next product's forward one
+template <class Op>
+hipError_t launch_fuse(tsfcde_plan_s *pl, const Op &op, int pred) {
+    switch (pl->P.R) {
+#define TSF_CASE(P) \
+    case P: return launch_fuse_t<P>(pl, op, pred);
+        TSF_SIZES(TSF_CASE)
 #undef TSF_CASE
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int C_, int MODE>
-hipError_t launch_mid_t(tsfcde_plan_s *pl, const RT &rt, const double2 *spec, double2 *spec_out,
+hipError_t launch_mid_t(tsfcde_plan_s *pl, const RT &rt, double2 *Y, const double2 *spec, double2 *spec_out,
                         const SymParams &sp, int pred) {
+    using G = MidGeo<C_, TSF_E_MID>;
     ProfScope ps(pl, MODE == 1 ? 4 : 2);
-    hipLaunchKernelGGL((k_mid<C_, MODE>), dim3((unsigned)(rt.R / 2)), dim3(MidGeo<C_>::NT), 0, pl->stream, rt.R,
-                       pl->buf, spec, spec_out, rt.tw, sp, pl->tw_all, pl->sc, pred);
+    hipLaunchKernelGGL((k_mid<C_, TSF_E_MID, MODE>), dim3((unsigned)(rt.R / 2)), dim3(G::NT), 0, pl->stream, rt.R,
+                       Y, spec, spec_out, rt.tw, sp, pl->tw_all, pl->sc, pred);
     return hipGetLastError();
 }
 
 template <int MODE>
-hipError_t launch_mid(tsfcde_plan_s *pl, const RT &rt, const double2 *spec, double2 *spec_out, const SymParams &sp,
-                      int pred) {
+hipError_t launch_mid(tsfcde_plan_s *pl, const RT &rt, double2 *Y, const double2 *spec, double2 *spec_out,
+                      const SymParams &sp, int pred) {
     switch (rt.C) {
 #define TSF_CASE(P) \
-    case P: return launch_mid_t<P, MODE>(pl, rt, spec, spec_out, sp, pred);
-        TSF_CASE(2) TSF_CASE(4) TSF_CASE(8) TSF_CASE(16) TSF_CASE(32) TSF_CASE(64) TSF_CASE(128) TSF_CASE(256)
-        TSF_CASE(512) TSF_CASE(1024) TSF_CASE(2048) TSF_CASE(4096)
+    case P: return launch_mid_t<P, MODE>(pl, rt, Y, spec, spec_out, sp, pred);
+        TSF_SIZES(TSF_CASE)
 #undef TSF_CASE
         default: return hipErrorInvalidValue;
     }
@@ -262,14 +301,16 @@ Out with_red(Out o, tsfcde_plan_s *pl, int site) {
     return o;
 }
 
+double2 *buf_of(tsfcde_plan_s *pl, const RT &rt) { return &rt == &pl->P ? pl->bufP : pl->buf; }
+
 OutSpec out_spec(tsfcde_plan_s *pl, const RT &rt) {
-    OutSpec o{pl->buf, rt.tw, rt.C};
+    OutSpec o{buf_of(pl, rt), rt.tw, rt.C};
     o.partials = nullptr;
     o.counter = nullptr;
     return o;
 }
 
-InSpec in_spec(tsfcde_plan_s *pl, const RT &rt) { return InSpec{pl->buf, rt.tw, rt.C}; }
+InSpec in_spec(tsfcde_plan_s *pl, const RT &rt) { return InSpec{buf_of(pl, rt), rt.tw, rt.C}; }
 
 // y-side of an operator: pass A with loader `in`, middle, pass C with store `out`.
 template <int MODE, class In, class Out>
@@ -277,7 +318,7 @@ hipError_t run_op(tsfcde_plan_s *pl, const RT &rt, const double2 *spec, const Sy
                   const Out &out, int pred) {
     hipError_t e = launch_col<-1>(pl, rt, in, out_spec(pl, rt), pred);
     if (e != hipSuccess) return e;
-    e = launch_mid<MODE>(pl, rt, spec, nullptr, sp, pred);
+    e = launch_mid<MODE>(pl, rt, buf_of(pl, rt), spec, nullptr, sp, pred);
     if (e != hipSuccess) return e;
     return launch_col<1>(pl, rt, in_spec(pl, rt), out, pred);
 }
@@ -289,43 +330,32 @@ int poll(tsfcde_plan_s *pl) {
     return TSFCDE_OK;
 }
 
-// One CGS iteration (Templates-style preconditioned CGS, Sec. 3.2 "PCGS"):
+// One CGS iteration (Templates-style preconditioned CGS, Sec. 3.2 "PCGS"),
+// ten kernels:
 //  u = r + beta q ; p = u + beta (q + beta p)      [K1 prologue]
-//  phat = P^{-1} p                                [K1-K3]
-//  vhat = A phat ; alpha = rho / (rt . vhat)      [K4-K6]
-//  q = u - alpha vhat ; uhat = P^{-1} (u + q)     [K7-K9]
-//  x += alpha uhat ; r -= alpha A uhat            [K10-K12], rho' = rt . r
+//  phat = P^{-1} p ; vhat = A phat               [K1, K2, K3 (fused), K4, K5]
+//  alpha = rho / (rt . vhat)                     [K5 epilogue]
+//  q = u - alpha vhat ; uhat = P^{-1} (u + q)     [K6 prologue, K7]
+//  x += alpha uhat ; r -= alpha A uhat            [K8 (fused), K9, K10], rho' = rt . r
 hipError_t cgs_iteration(tsfcde_plan_s *pl, int64_t j, double *x) {
     const int64_t n = pl->n;
     const SymParams sP = symbol(pl, j, -pl->sigma, pl->P, true);
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
     hipError_t e;
-    {
-        InCgsUP in{pl->r, pl->u, pl->p, pl->q, n, pl->P.C, 0.0, false};
-        OutReal out{pl->phat, n, pl->P.C};
-        out.partials = nullptr;
-        out.counter = nullptr;
-        if ((e = run_op<1>(pl, pl->P, pl->specP, sP, in, out, 1)) != hipSuccess) return e;
-    }
-    {
-        InReal in{pl->phat, n, pl->A.C};
-        OutCgsDot out = with_red(OutCgsDot{pl->vhat, pl->rt, n, pl->A.C}, pl, 0);
-        if ((e = run_op<0>(pl, pl->A, pl->specA, sA, in, out, 1)) != hipSuccess) return e;
-    }
-    {
-        InCgsQ in{pl->u, pl->vhat, pl->q, n, pl->P.C, 0.0};
-        OutReal out{pl->uhat, n, pl->P.C};
-        out.partials = nullptr;
-        out.counter = nullptr;
-        if ((e = run_op<1>(pl, pl->P, pl->specP, sP, in, out, 1)) != hipSuccess) return e;
-    }
-    {
-        // alpha is read from the device scalars by both the loader and the store
-        InCgsX in{pl->uhat, x, n, pl->A.C, 0.0};
-        OutCgsR out = with_red(OutCgsR{pl->r, pl->rt, n, pl->A.C, 0.0}, pl, 1);
-        if ((e = run_op<0>(pl, pl->A, pl->specA, sA, in, out, 1)) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    InCgsUP k1{pl->r, pl->u, pl->p, pl->q, n, pl->P.C, 0.0, false};
+    if ((e = launch_col<-1>(pl, pl->P, k1, out_spec(pl, pl->P), 1)) != hipSuccess) return e;
+    if ((e = launch_mid<1>(pl, pl->P, pl->bufP, pl->specP, nullptr, sP, 1)) != hipSuccess) return e;
+    if ((e = launch_fuse(pl, OpIdent{}, 1)) != hipSuccess) return e;
+    if ((e = launch_mid<0>(pl, pl->A, pl->buf, pl->specA, nullptr, sA, 1)) != hipSuccess) return e;
+    OutCgsDot k5 = with_red(OutCgsDot{pl->vhat, pl->rt, n, pl->A.C}, pl, 0);
+    if ((e = launch_col<1>(pl, pl->A, in_spec(pl, pl->A), k5, 1)) != hipSuccess) return e;
+    InCgsQ k6{pl->u, pl->vhat, pl->q, n, pl->P.C, 0.0};
+    if ((e = launch_col<-1>(pl, pl->P, k6, out_spec(pl, pl->P), 1)) != hipSuccess) return e;
+    if ((e = launch_mid<1>(pl, pl->P, pl->bufP, pl->specP, nullptr, sP, 1)) != hipSuccess) return e;
+    if ((e = launch_fuse(pl, OpCgsX{x, pl->A.C, 0.0}, 1)) != hipSuccess) return e;
+    if ((e = launch_mid<0>(pl, pl->A, pl->buf, pl->specA, nullptr, sA, 1)) != hipSuccess) return e;
+    OutCgsR k10 = with_red(OutCgsR{pl->r, pl->rt, n, pl->A.C, 0.0}, pl, 1);
+    return launch_col<1>(pl, pl->A, in_spec(pl, pl->A), k10, 1);
 }
 
 int level_rhs(tsfcde_plan_s *pl, int64_t j, const double *d_f, double *x, int warm) {
@@ -460,8 +490,7 @@ int tsfcde_workspace_bytes(const tsfcde_problem *prob, size_t *bytes) {
     if (rc) return rc;
     if (!bytes) return TSFCDE_EINVAL;
     RT A, P;
-    rt_init(A, 2 * prob->n);
-    rt_init(P, prob->n);
+    rt_pair(A, P, prob->n);
     *bytes = layout_for(prob->n, prob->M, A, P).total;
     return TSFCDE_OK;
 }
@@ -523,8 +552,7 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
         for (int64_t m = 1; m <= M; ++m) pl->cbase[m] = av[m] + bv[m + 1] - bv[m];
         for (int64_t j = 1; j <= M; ++j) pl->clast[j] = av[j] - bv[j];
     }
-    rt_init(pl->A, 2 * n);
-    rt_init(pl->P, n);
+    rt_pair(pl->A, pl->P, n);
     pl->lay = layout_for(n, M, pl->A, pl->P);
     if (bytes < pl->lay.total) {
         delete pl;
@@ -547,6 +575,7 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
     pl->g0 = reinterpret_cast<double *>(ws + L.off_g0);
     pl->cb = reinterpret_cast<double *>(ws + L.off_cbase);
     pl->buf = reinterpret_cast<double2 *>(ws + L.off_buf);
+    pl->bufP = reinterpret_cast<double2 *>(ws + L.off_bufP);
     pl->specA = reinterpret_cast<double2 *>(ws + L.off_specA);
     pl->specP = reinterpret_cast<double2 *>(ws + L.off_specP);
     pl->tw_all = reinterpret_cast<double2 *>(ws + L.off_tw);
@@ -595,11 +624,11 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
         InReal in{pl->tmp, pl->A.L, pl->A.C};
         if (launch_col<-1>(pl, pl->A, in, out_spec(pl, pl->A), 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
         SymParams sp{};
-        if (launch_mid<2>(pl, pl->A, nullptr, pl->specA, sp, 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
+        if (launch_mid<2>(pl, pl->A, pl->buf, nullptr, pl->specA, sp, 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
         hipLaunchKernelGGL(k_strang_column, dim3(512), dim3(256), 0, pl->stream, pl->w, n, pl->tmp);
         InReal inP{pl->tmp, n, pl->P.C};
         if (launch_col<-1>(pl, pl->P, inP, out_spec(pl, pl->P), 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
-        if (launch_mid<2>(pl, pl->P, nullptr, pl->specP, sp, 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
+        if (launch_mid<2>(pl, pl->P, pl->bufP, nullptr, pl->specP, sp, 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
     }
     // u^0 = phi(x_i)
     {
