@@ -58,6 +58,8 @@ extern "C" {
 #define TSFCDE_FP64 0            /* every step in FP64                       */
 #define TSFCDE_WS_ZERO 0         /* Krylov initial guess 0 (as in Sec. 4)    */
 #define TSFCDE_WS_PREV 1         /* initial guess u^j (previous level)       */
+#define TSFCDE_WS_EXTRAP 2       /* 3u^j - 3u^{j-1} + u^{j-2} (quadratic in t; u^j
+                                    for j = 1, 0 for j = 0)                  */
 #define TSFCDE_FLAG_TRUE_RESIDUAL 1 /* also compute |g - A u|/|g| per level  */
 #define TSFCDE_FLAG_VERIFY 2     /* on recursive convergence, recompute r = g - A x
                                     and restart CGS from x while the true residual
@@ -99,7 +101,7 @@ typedef struct tsfcde_problem {
     double rtol;       /* Krylov stop: |r_k|_2 <= rtol |g|_2 (<= 0: 1e-10)   */
     int32_t maxit;     /* CGS iterations per level (<= 0: 500)              */
     int32_t precision; /* TSFCDE_FP64                                       */
-    int32_t warm_start;/* TSFCDE_WS_ZERO or TSFCDE_WS_PREV                  */
+    int32_t warm_start;/* TSFCDE_WS_ZERO, _PREV or _EXTRAP                  */
     int32_t flags;     /* TSFCDE_FLAG_*                                     */
 } tsfcde_problem;
 

@@ -28,7 +28,7 @@ TSFCDE_EINVAL, TSFCDE_ENOMEM, TSFCDE_EDEVICE = -1, -2, -3
 TSFCDE_ENOCONV, TSFCDE_EBREAKDOWN, TSFCDE_ENONFINITE = -4, -5, -6
 TSFCDE_EDONE, TSFCDE_EUNSUPPORTED = -7, -8
 TSFCDE_FP64 = 0
-TSFCDE_WS_ZERO, TSFCDE_WS_PREV = 0, 1
+TSFCDE_WS_ZERO, TSFCDE_WS_PREV, TSFCDE_WS_EXTRAP = 0, 1, 2
 TSFCDE_FLAG_TRUE_RESIDUAL = 1
 TSFCDE_FLAG_VERIFY = 2
 TSFCDE_OP_A, TSFCDE_OP_B, TSFCDE_OP_PINV = 0, 1, 2

@@ -307,12 +307,15 @@ struct OutCgsR {
 //   g = (eta/sigma) u^j - ((1-sigma)/sigma) y - H + f     (= B u^j - H + f)
 //   x0 = u^j (warm) or 0;  r = g - A x0 ;  rt = r.
 // The last workgroup initialises the CGS scalars for the level.
+// warm: 0 -> x0 = 0; 1 -> x0 = u^j; 2 -> x0 = 3u^j - 3u^{j-1} + u^{j-2}
+// (quadratic extrapolation in t; r is then recomputed from x0 by a restart).
 struct OutRhs {
     const double *uj, *H, *f;
     double *g, *r, *rt, *x;
     int64_t nr, C;
     double c_u, c_y;  // eta/sigma, (1-sigma)/sigma
     int warm, has_hist;
+    const double *ujm1, *ujm2;  // u^{j-1}, u^{j-2} for warm == 2
     static constexpr int NACC = 2;
     __device__ void prep(const DevScalars *) {}
     __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
@@ -330,11 +333,19 @@ struct OutRhs {
                 gv.x += fv.x;
                 gv.y += fv.y;
             }
-            double2 rv = warm ? make_double2(gv.x - val.x, gv.y - val.y) : gv;
+            double2 rv = warm == 1 ? make_double2(gv.x - val.x, gv.y - val.y) : gv;
+            double2 xv = make_double2(0.0, 0.0);
+            if (warm == 1) {
+                xv = u;
+            } else if (warm == 2) {
+                const double2 a = *reinterpret_cast<const double2 *>(ujm1 + i);
+                const double2 b = *reinterpret_cast<const double2 *>(ujm2 + i);
+                xv = make_double2(fma(3.0, u.x - a.x, b.x), fma(3.0, u.y - a.y, b.y));
+            }
             *reinterpret_cast<double2 *>(g + i) = gv;
             *reinterpret_cast<double2 *>(r + i) = rv;
             *reinterpret_cast<double2 *>(rt + i) = rv;
-            *reinterpret_cast<double2 *>(x + i) = warm ? u : make_double2(0.0, 0.0);
+            *reinterpret_cast<double2 *>(x + i) = xv;
             acc[0] = fma(gv.x, gv.x, fma(gv.y, gv.y, acc[0]));
             acc[1] = fma(rv.x, rv.x, fma(rv.y, rv.y, acc[1]));
         }

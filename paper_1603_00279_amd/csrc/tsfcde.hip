@@ -114,7 +114,8 @@ int validate(const tsfcde_problem *p) {
     if ((!p->gamma && !p->gamma_at) || (!p->dplus && !p->dplus_at) || (!p->dminus && !p->dminus_at))
         return TSFCDE_EINVAL;
     if (p->precision != TSFCDE_FP64) return TSFCDE_EINVAL;
-    if (p->warm_start != TSFCDE_WS_ZERO && p->warm_start != TSFCDE_WS_PREV) return TSFCDE_EINVAL;
+    if (p->warm_start != TSFCDE_WS_ZERO && p->warm_start != TSFCDE_WS_PREV && p->warm_start != TSFCDE_WS_EXTRAP)
+        return TSFCDE_EINVAL;
     if (!std::isfinite(p->rtol)) return TSFCDE_EINVAL;
     if (!is_pow2(p->n) || p->n < 16 || p->n > NMAX) return TSFCDE_EUNSUPPORTED;
     return TSFCDE_OK;
@@ -163,8 +164,10 @@ hipEvent_t get_event(tsfcde_plan_s *pl) {
         pl->event_pool.pop_back();
         return e;
     }
+    // no system-scope fence: the timing marker must not flush L2 around the
+    // kernel it brackets
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
@@ -370,7 +373,8 @@ int level_rhs(tsfcde_plan_s *pl, int64_t j, const double *d_f, double *x, int wa
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
     InReal in{pl->U + (size_t)j * n, n, pl->A.C};
     OutRhs out{pl->U + (size_t)j * n, pl->H, d_f, pl->g, pl->r, pl->rt, x, n, pl->A.C,
-               pl->eta[j] / pl->sigma, (1.0 - pl->sigma) / pl->sigma, warm, j >= 1 ? 1 : 0};
+               pl->eta[j] / pl->sigma, (1.0 - pl->sigma) / pl->sigma, warm, j >= 1 ? 1 : 0,
+               j >= 2 ? pl->U + (size_t)(j - 1) * n : nullptr, j >= 2 ? pl->U + (size_t)(j - 2) * n : nullptr};
     out = with_red(out, pl, 2);
     HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
     return TSFCDE_OK;
@@ -384,13 +388,19 @@ int status_code(int st) {
 
 constexpr int MAX_RESTARTS = 3;
 
-// y = A x and r = g - y, rt = r (restart from the current iterate).
-int restart_from_x(tsfcde_plan_s *pl, int64_t j, const double *x) {
+// y = A x and r = g - y, rt = r (restart from the current iterate); queued
+// on the stream, no synchronisation.
+int restart_launch(tsfcde_plan_s *pl, int64_t j, const double *x) {
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
     InReal in{x, pl->n, pl->A.C};
     OutRestart out = with_red(OutRestart{pl->g, pl->r, pl->rt, pl->n, pl->A.C}, pl, 3);
     HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
-    return poll(pl);
+    return TSFCDE_OK;
+}
+
+int restart_from_x(tsfcde_plan_s *pl, int64_t j, const double *x) {
+    int rc = restart_launch(pl, j, x);
+    return rc ? rc : poll(pl);
 }
 
 int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_stats *st) {
@@ -398,8 +408,13 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
     auto t0 = std::chrono::steady_clock::now();
     const int64_t j = pl->level, n = pl->n;
     double *x = pl->U + (size_t)(j + 1) * n;
-    int rc = level_rhs(pl, j, d_f, x, pl->warm == TSFCDE_WS_PREV);
+    // initial guess: 0, u^j, or quadratic extrapolation (u^j below level 2)
+    int warm = 0;
+    if (pl->warm == TSFCDE_WS_PREV) warm = 1;
+    if (pl->warm == TSFCDE_WS_EXTRAP) warm = j >= 2 ? 2 : (j >= 1 ? 1 : 0);
+    int rc = level_rhs(pl, j, d_f, x, warm);
     if (rc) return rc;
+    if (warm == 2 && (rc = restart_launch(pl, j, x))) return rc;  // r0 = g - A x0
     const bool verify = (pl->flags & TSFCDE_FLAG_VERIFY) != 0;
     int code = TSFCDE_OK, restarts = 0, iters_seen = 0;
     double relres_true = -1.0, last_true2 = HUGE_VAL;

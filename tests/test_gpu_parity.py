@@ -138,7 +138,7 @@ def test_one_level_random_history(n):
     assert relerr(got, ref) < bound, (st, relerr(got, ref), bound)
 
 
-@pytest.mark.parametrize("warm", [0, 1])
+@pytest.mark.parametrize("warm", [0, 1, 2])
 def test_march_small_config(warm):
     """Plain method at alpha=0.5, beta=1.5, n=64, M=64: every level."""
     banner(f"march small warm={warm}")
@@ -240,3 +240,26 @@ def test_zero_source_zero_solution():
         U = host(s.history())
     assert np.all(U == 0.0)
     assert all(st["iters"] == 0 for st in stats)
+
+
+@pytest.mark.parametrize("n", [1024, 4096])
+def test_warm_starts_cut_iterations(n):
+    """Previous-level and extrapolated initial guesses converge to the same
+    levels (within the Krylov tolerance); extrapolation needs fewer CGS
+    iterations."""
+    banner(f"warm starts n={n}")
+    prob = W.config_large(n=n, M=16)
+    F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
+    runs = {}
+    for warm in (0, 1, 2):
+        with make(prob, rtol=1e-12, warm_start=warm) as s:
+            code, stats = s.solve(F)
+            runs[warm] = (host(s.history()), [st["iters"] for st in stats])
+    U0 = runs[0][0]
+    # each run stops at |r| <= 1e-12 |g|; two such solutions differ by at most
+    # ~2 cond(A) 1e-12, and cond(A) reaches ~2e6 here
+    for warm in (1, 2):
+        assert relerr(runs[warm][0], U0) < 1e-5
+    # u = t^2 P(x): extrapolation is nearly exact, u^j is not much better than 0
+    it0, it1, it2 = (sum(runs[w][1][2:]) for w in (0, 1, 2))
+    assert it2 < it0 and it1 <= it0 + 2, (it0, it1, it2)
