@@ -85,7 +85,9 @@ typedef struct tsfcde_problem {
     double beta;       /* space order, 1 < beta <= 2                        */
     double a, b;       /* space interval, a < b                             */
     double T;          /* final time, T > 0                                 */
-    int64_t n;         /* interior unknowns (this build: power of two >= 16) */
+    int64_t n;         /* interior unknowns, 4 <= n <= 2^24 (2^23 unless a
+                          power of two); powers of two >= 16 take the
+                          fastest path                                     */
     int64_t M;         /* time steps, M >= 1                                */
     /* gamma(t), d_+(t), d_-(t): either callbacks (called on the host during
      * tsfcde_plan at t_{j+sigma}, j = 0..M-1) or, when a callback is NULL,
@@ -137,7 +139,8 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
 int tsfcde_set_state(tsfcde_plan_t plan, int64_t level, const double *d_U);
 
 /* Advance one level j -> j+1 (Algorithm 2, one pass of its loop).
- * d_f: f(x_i, t_{j+sigma}) on the device (n values), or NULL for f = 0.
+ * d_f: f(x_i, t_{j+sigma}) on the device (n values, any 8-byte alignment), or
+ * NULL for f = 0.
  * d_u_out: optional device copy of u^{j+1} (n values) or NULL.
  * st: optional per-level statistics.  Returns TSFCDE_ENOCONV /
  * TSFCDE_EBREAKDOWN / TSFCDE_ENONFINITE with u^{j+1} set to the last iterate;
@@ -153,7 +156,8 @@ int tsfcde_solve(tsfcde_plan_t plan, const double *d_F, int64_t ldF, double *d_U
                  tsfcde_stats *per_level);
 
 /* y = op x at level j (0 <= j < M) for op in TSFCDE_OP_*; device vectors of
- * n values; d_x and d_y must not overlap the plan's workspace. */
+ * n values, 16-byte aligned; d_x and d_y must not overlap the plan's
+ * workspace. */
 int tsfcde_apply(tsfcde_plan_t plan, int32_t op, int64_t j, const double *d_x, double *d_y);
 
 /* Right-hand side g of (3.3) for level j from the stored levels u^0..u^j
@@ -164,15 +168,22 @@ int tsfcde_rhs(tsfcde_plan_t plan, int64_t j, const double *d_f, double *d_g);
 int tsfcde_weights(tsfcde_plan_t plan, double *d_w);
 
 /* Circulant spectra in natural frequency order as interleaved complex FP64:
- * TSFCDE_SPEC_EMBED: DFT_{2n} of the embedding column of W_beta,
- *   k = 0..n (n+1 complex values);
- * TSFCDE_SPEC_STRANG: DFT_n of the Strang column of W_beta, k = 0..n/2
- *   (n/2+1 complex values).  DFT sign: lambda_k = sum_m c_m e^{-2 pi i mk/L}. */
+ * TSFCDE_SPEC_EMBED: DFT_L of the embedding column of W_beta, L =
+ *   tsfcde_embedding_length (the power of two >= 2n), k = 0..L/2 (L/2+1
+ *   complex values);
+ * TSFCDE_SPEC_STRANG: DFT_n of the Strang column of W_beta, k = 0..floor(n/2)
+ *   (floor(n/2)+1 complex values).
+ * DFT sign: lambda_k = sum_m c_m e^{-2 pi i mk/L}. */
 int tsfcde_spectrum(tsfcde_plan_t plan, int32_t which, double *d_out);
 
-/* Device pointer to the stored levels U ((M+1) x n, row j = u^j), owned by
- * the plan; valid until tsfcde_destroy. */
+/* Device pointer to the stored levels U, owned by the plan and valid until
+ * tsfcde_destroy: M+1 rows of n values, row j = u^j, rows
+ * tsfcde_history_ld(plan) doubles apart (n rounded up to even). */
 const double *tsfcde_history(tsfcde_plan_t plan);
+int64_t tsfcde_history_ld(tsfcde_plan_t plan);
+
+/* Length L of the circulant embedding used for the Toeplitz products. */
+int64_t tsfcde_embedding_length(tsfcde_plan_t plan);
 
 /* Current level j (u^0..u^j are stored). */
 int64_t tsfcde_level(tsfcde_plan_t plan);

@@ -69,6 +69,8 @@ _SIGS = {
     "tsfcde_spectrum": (c_int32, [c_void_p, c_int32, c_void_p]),
     "tsfcde_history": (c_void_p, [c_void_p]),
     "tsfcde_level": (c_int64, [c_void_p]),
+    "tsfcde_history_ld": (c_int64, [c_void_p]),
+    "tsfcde_embedding_length": (c_int64, [c_void_p]),
     "tsfcde_profile": (c_int32, [c_void_p, c_int32, c_int32]),
     "tsfcde_profile_read": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
     "tsfcde_destroy": (c_int32, [c_void_p]),

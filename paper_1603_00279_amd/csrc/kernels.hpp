@@ -105,6 +105,18 @@ __device__ __forceinline__ bool block_reduce_last(double (&acc)[NACC], double *p
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
 
+// Element pair (i, i+1) of a real vector of nr values (i even).  Vectors of odd
+// length end with a lone element: the pair loads it with a zero partner, and
+// a store writes only the element that exists.
+__device__ __forceinline__ double2 ld2(const double *p, int64_t i, int64_t nr) {
+    if (i + 1 < nr) return *reinterpret_cast<const double2 *>(p + i);
+    return make_double2(i < nr ? p[i] : 0.0, 0.0);
+}
+__device__ __forceinline__ void st2(double *p, int64_t i, int64_t nr, double2 v) {
+    if (i + 1 < nr) *reinterpret_cast<double2 *>(p + i) = v;
+    else if (i < nr) p[i] = v.x;
+}
+
 // ---------------------------------------------------------------------------
 // Pass-A loaders (forward column pass).  load(row, col) returns packed
 // element m = row*C + col of the real input, z[m] = x[2m] + i x[2m+1].
@@ -114,9 +126,7 @@ struct InReal {  // plain real vector, zero beyond nr values
     int64_t nr, C;
     __device__ void prep(const DevScalars *) {}
     __device__ __forceinline__ double2 load(int row, int64_t col) const {
-        int64_t i = 2 * (row * C + col);
-        if (i >= nr) return make_double2(0.0, 0.0);
-        return *reinterpret_cast<const double2 *>(x + i);
+        return ld2(x, 2 * (row * C + col), nr);
     }
 };
 
@@ -136,19 +146,19 @@ struct InCgsUP {
     __device__ __forceinline__ double2 load(int row, int64_t col) {
         int64_t i = 2 * (row * C + col);
         if (i >= nr) return make_double2(0.0, 0.0);
-        double2 rv = *reinterpret_cast<const double2 *>(r + i);
+        double2 rv = ld2(r, i, nr);
         double2 uv, pv;
         if (first) {
             uv = rv;
             pv = rv;
         } else {
-            double2 qv = *reinterpret_cast<const double2 *>(q + i);
-            double2 po = *reinterpret_cast<const double2 *>(p + i);
+            double2 qv = ld2(q, i, nr);
+            double2 po = ld2(p, i, nr);
             uv = make_double2(fma(beta, qv.x, rv.x), fma(beta, qv.y, rv.y));
             pv = make_double2(fma(beta, fma(beta, po.x, qv.x), uv.x), fma(beta, fma(beta, po.y, qv.y), uv.y));
         }
-        *reinterpret_cast<double2 *>(u + i) = uv;
-        *reinterpret_cast<double2 *>(p + i) = pv;
+        st2(u, i, nr, uv);
+        st2(p, i, nr, pv);
         return pv;
     }
 };
@@ -163,10 +173,10 @@ struct InCgsQ {
     __device__ __forceinline__ double2 load(int row, int64_t col) {
         int64_t i = 2 * (row * C + col);
         if (i >= nr) return make_double2(0.0, 0.0);
-        double2 uv = *reinterpret_cast<const double2 *>(u + i);
-        double2 vv = *reinterpret_cast<const double2 *>(vhat + i);
+        double2 uv = ld2(u, i, nr);
+        double2 vv = ld2(vhat, i, nr);
         double2 qv = make_double2(fma(-alpha, vv.x, uv.x), fma(-alpha, vv.y, uv.y));
-        *reinterpret_cast<double2 *>(q + i) = qv;
+        st2(q, i, nr, qv);
         return make_double2(uv.x + qv.x, uv.y + qv.y);
     }
 };
@@ -181,9 +191,9 @@ struct InCgsX {
     __device__ __forceinline__ double2 load(int row, int64_t col) {
         int64_t i = 2 * (row * C + col);
         if (i >= nr) return make_double2(0.0, 0.0);
-        double2 uh = *reinterpret_cast<const double2 *>(uhat + i);
-        double2 xv = *reinterpret_cast<double2 *>(x + i);
-        *reinterpret_cast<double2 *>(x + i) = make_double2(fma(alpha, uh.x, xv.x), fma(alpha, uh.y, xv.y));
+        double2 uh = ld2(uhat, i, nr);
+        double2 xv = ld2(x, i, nr);
+        st2(x, i, nr, make_double2(fma(alpha, uh.x, xv.x), fma(alpha, uh.y, xv.y)));
         return uh;
     }
 };
@@ -222,8 +232,7 @@ struct OutReal {  // x[2m], x[2m+1] for 2m < nr
     static constexpr int NACC = 0;
     __device__ void prep(const DevScalars *) {}
     __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *) const {
-        int64_t i = 2 * (row * C + col);
-        if (i < nr) *reinterpret_cast<double2 *>(x + i) = val;
+        st2(x, 2 * (row * C + col), nr, val);
     }
     __device__ void final(const double *, DevScalars *) const {}
     double *partials;
@@ -240,8 +249,9 @@ struct OutCgsDot {
     __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
         int64_t i = 2 * (row * C + col);
         if (i < nr) {
-            *reinterpret_cast<double2 *>(vhat + i) = val;
-            double2 t = *reinterpret_cast<const double2 *>(rt + i);
+            if (i + 1 >= nr) val.y = 0.0;
+            st2(vhat, i, nr, val);
+            double2 t = ld2(rt, i, nr);
             acc[0] = fma(t.x, val.x, fma(t.y, val.y, acc[0]));
         }
     }
@@ -273,11 +283,12 @@ struct OutCgsR {
     __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
         int64_t i = 2 * (row * C + col);
         if (i < nr) {
-            double2 rv = *reinterpret_cast<const double2 *>(r + i);
+            if (i + 1 >= nr) val.y = 0.0;
+            double2 rv = ld2(r, i, nr);
             rv.x = fma(-alpha, val.x, rv.x);
             rv.y = fma(-alpha, val.y, rv.y);
-            *reinterpret_cast<double2 *>(r + i) = rv;
-            double2 t = *reinterpret_cast<const double2 *>(rt + i);
+            st2(r, i, nr, rv);
+            double2 t = ld2(rt, i, nr);
             acc[0] = fma(rv.x, rv.x, fma(rv.y, rv.y, acc[0]));
             acc[1] = fma(t.x, rv.x, fma(t.y, rv.y, acc[1]));
         }
@@ -321,15 +332,16 @@ struct OutRhs {
     __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
         int64_t i = 2 * (row * C + col);
         if (i < nr) {
-            double2 u = *reinterpret_cast<const double2 *>(uj + i);
+            if (i + 1 >= nr) val.y = 0.0;
+            double2 u = ld2(uj, i, nr);
             double2 gv = make_double2(fma(c_u, u.x, -c_y * val.x), fma(c_u, u.y, -c_y * val.y));
             if (has_hist) {
-                double2 hv = *reinterpret_cast<const double2 *>(H + i);
+                double2 hv = ld2(H, i, nr);
                 gv.x -= hv.x;
                 gv.y -= hv.y;
             }
             if (f) {
-                double2 fv = *reinterpret_cast<const double2 *>(f + i);
+                double2 fv = ld2(f, i, nr);
                 gv.x += fv.x;
                 gv.y += fv.y;
             }
@@ -338,14 +350,14 @@ struct OutRhs {
             if (warm == 1) {
                 xv = u;
             } else if (warm == 2) {
-                const double2 a = *reinterpret_cast<const double2 *>(ujm1 + i);
-                const double2 b = *reinterpret_cast<const double2 *>(ujm2 + i);
+                const double2 a = ld2(ujm1, i, nr);
+                const double2 b = ld2(ujm2, i, nr);
                 xv = make_double2(fma(3.0, u.x - a.x, b.x), fma(3.0, u.y - a.y, b.y));
             }
-            *reinterpret_cast<double2 *>(g + i) = gv;
-            *reinterpret_cast<double2 *>(r + i) = rv;
-            *reinterpret_cast<double2 *>(rt + i) = rv;
-            *reinterpret_cast<double2 *>(x + i) = xv;
+            st2(g, i, nr, gv);
+            st2(r, i, nr, rv);
+            st2(rt, i, nr, rv);
+            st2(x, i, nr, xv);
             acc[0] = fma(gv.x, gv.x, fma(gv.y, gv.y, acc[0]));
             acc[1] = fma(rv.x, rv.x, fma(rv.y, rv.y, acc[1]));
         }
@@ -381,7 +393,8 @@ struct OutTrueRes {
     __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
         int64_t i = 2 * (row * C + col);
         if (i < nr) {
-            double2 gv = *reinterpret_cast<const double2 *>(g + i);
+            if (i + 1 >= nr) val.y = 0.0;
+            double2 gv = ld2(g, i, nr);
             double dx = gv.x - val.x, dy = gv.y - val.y;
             acc[0] = fma(dx, dx, fma(dy, dy, acc[0]));
         }
@@ -403,10 +416,11 @@ struct OutRestart {
     __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
         int64_t i = 2 * (row * C + col);
         if (i < nr) {
-            double2 gv = *reinterpret_cast<const double2 *>(g + i);
+            if (i + 1 >= nr) val.y = 0.0;
+            double2 gv = ld2(g, i, nr);
             double2 rv = make_double2(gv.x - val.x, gv.y - val.y);
-            *reinterpret_cast<double2 *>(r + i) = rv;
-            *reinterpret_cast<double2 *>(rt + i) = rv;
+            st2(r, i, nr, rv);
+            st2(rt, i, nr, rv);
             acc[0] = fma(rv.x, rv.x, fma(rv.y, rv.y, acc[0]));
         }
     }
@@ -782,11 +796,136 @@ __global__ void __launch_bounds__((MidGeo<C_, EMAX>::NT)) k_mid(int64_t R, doubl
 }
 
 // ---------------------------------------------------------------------------
+// Complex transforms (Bluestein's chirp-z DFT of arbitrary length n, used to
+// build the Strang preconditioner when n is not a power of two).
+// ---------------------------------------------------------------------------
+// Complex loader: v[m] = z[m] (or zr[m] real) for m < nv, else 0, optionally
+// times conj(chirp[m]).
+struct InCplx {
+    const double2 *z;
+    const double *zr;
+    const double2 *chirp;
+    int64_t nv, C;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ double2 load(int row, int64_t col) const {
+        const int64_t m = row * C + col;
+        if (m >= nv) return make_double2(0.0, 0.0);
+        double2 v = z ? z[m] : make_double2(zr[m], 0.0);
+        return chirp ? cmul(v, cconj(chirp[m])) : v;
+    }
+};
+
+// Complex store: z[m] = val (optionally times conj(chirp[m])) for m < nv.
+struct OutCplx {
+    double2 *z;
+    const double2 *chirp;
+    int64_t nv, C;
+    static constexpr int NACC = 0;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *) const {
+        const int64_t m = row * C + col;
+        if (m < nv) z[m] = chirp ? cmul(val, cconj(chirp[m])) : val;
+    }
+    __device__ void final(const double *, DevScalars *) const {}
+    double *partials;
+    unsigned *counter;
+};
+
+template <int C_, int EMAX> struct RowGeo {
+    static constexpr int E0 = Geo<C_, EMAX>::E;
+    static constexpr int E = (C_ / E0 > 1024) ? C_ / 1024 : E0;
+    static constexpr int T = C_ / E;
+    static constexpr int NT = (T + 63) / 64 * 64;
+    static constexpr int LS = lpad_size(C_);
+};
+
+// One row of a complex R x C transform per workgroup.  MODE 3: forward row
+// FFT, multiply by the stored spectrum (native order), inverse row FFT (the
+// middle of a circular convolution).  MODE 4: forward row FFT, spectrum out.
+template <int C_, int EMAX, int MODE>
+__global__ void __launch_bounds__((RowGeo<C_, EMAX>::NT)) k_row(double2 *Y, const double2 *spec, double2 *spec_out,
+                                                                const double2 *__restrict__ tw_all) {
+    using G = RowGeo<C_, EMAX>;
+    constexpr int E = G::E, T = G::T;
+    __shared__ double2 lds[G::LS];
+    const int64_t row = blockIdx.x;
+    const int j = threadIdx.x;
+    const bool active = j < T;
+    double2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = active ? Y[row * C_ + j + T * m] : make_double2(0.0, 0.0);
+    LdsSink lsink{lds, 1};
+    fft<C_, E, -1>(v, j, active, tw_all, lds, 1, lsink);
+    __syncthreads();
+    if constexpr (MODE == 4) {
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) spec_out[row * C_ + j + T * m] = lds[lpad(j + T * m)];
+        }
+        return;
+    } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            v[m] = active ? cmul(lds[lpad(j + T * m)], spec[row * C_ + j + T * m]) : make_double2(0.0, 0.0);
+        __syncthreads();
+        RowSink rsink{Y, row * C_};
+        fft<C_, E, 1>(v, j, active, tw_all, lds, 1, rsink);
+    }
+}
+
+// Chirp b_m = exp(i pi m^2 / n), m < n (m^2 reduced modulo 2n exactly).
+__global__ void k_chirp(double2 *b, int64_t n) {
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < n; m += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = (m * m) % (2 * n);
+        double sn, cs;
+        sincospi((double)q / (double)n, &sn, &cs);
+        b[m] = make_double2(cs, sn);
+    }
+}
+
+// Circular arrangement of the chirp for a length-L convolution:
+// bb[l] = bb[L-l] = scale * b_l (1 <= l < n), bb[0] = scale * b_0, else 0.
+__global__ void k_chirp_embed(const double2 *b, int64_t n, int64_t L, double scale, double2 *bb) {
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < L; m += (int64_t)gridDim.x * blockDim.x) {
+        double2 v = make_double2(0.0, 0.0);
+        if (m < n) v = cscale(b[m], scale);
+        else if (L - m < n) v = cscale(b[L - m], scale);
+        bb[m] = v;
+    }
+}
+
+// Strang preconditioner at one level: w_k = conj(1 / lambda_k) with
+// lambda_k = s0 + cre Re(Ls_k) + i (cim Im(Ls_k) + cq sin(2 pi k / n)).
+__global__ void k_pc_column(const double2 *Ls, int64_t n, SymParams sp, double2 *w) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * (double)k / (double)n, &sn, &cs);
+        const double2 L = Ls[k];
+        const double2 lam = make_double2(fma(sp.cre, L.x, sp.s0), fma(sp.cim, L.y, sp.cq * sn));
+        const double d = 1.0 / fma(lam.x, lam.x, lam.y * lam.y);
+        w[k] = make_double2(lam.x * d, lam.y * d);  // conj(1/lam) = lam / |lam|^2
+    }
+}
+
+// First column of the length-L embedding of the circulant with first column
+// p_m = Re(Wt_m) / n (the inverse Strang circulant): lag l -> p[l mod n].
+__global__ void k_pc_embed(const double2 *Wt, int64_t n, int64_t L, double *e) {
+    const double inv = 1.0 / (double)n;
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < L; m += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (m < n) v = Wt[m].x * inv;
+        else if (L - m < n) v = Wt[n - (L - m)].x * inv;
+        e[m] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // History sum of (3.3):  H = kappa * sum_{s=0}^{j-1} c_{j-s}^(j) (u^{s+1} - u^s)
 // with c_j^(j) = clast (s = 0) and c_m^(j) = cbase[m] (1 <= m <= j-1).
-// Each lane streams two adjacent unknowns through all stored levels.
+// Each lane streams two adjacent unknowns through all stored levels (rows of
+// U are ldu >= n doubles apart, ldu even; an odd n reads the zero pad).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_history(const double *__restrict__ U, int64_t n, int j,
+__global__ void __launch_bounds__(256) k_history(const double *__restrict__ U, int64_t n, int64_t ldu, int j,
                                                  const double *__restrict__ cbase, double clast, double kappa,
                                                  double *__restrict__ H) {
     const int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
@@ -799,7 +938,7 @@ __global__ void __launch_bounds__(256) k_history(const double *__restrict__ U, i
     for (; s + U8 <= j; s += U8) {
         double2 x[U8];
 #pragma unroll
-        for (int q = 0; q < U8; ++q) x[q] = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1 + q) * n + i);
+        for (int q = 0; q < U8; ++q) x[q] = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1 + q) * ldu + i);
 #pragma unroll
         for (int q = 0; q < U8; ++q) {
             const double cq = (s + q == 0) ? clast : cbase[j - s - q];
@@ -809,7 +948,7 @@ __global__ void __launch_bounds__(256) k_history(const double *__restrict__ U, i
         }
     }
     for (; s < j; ++s) {
-        double2 x1 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1) * n + i);
+        double2 x1 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1) * ldu + i);
         const double c1 = s == 0 ? clast : cbase[j - s];
         acc.x = fma(c1, x1.x - prev.x, acc.x);
         acc.y = fma(c1, x1.y - prev.y, acc.y);

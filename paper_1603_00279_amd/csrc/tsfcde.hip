@@ -56,26 +56,46 @@ void rt_init(RT &rt, int64_t L, int64_t R) {
     rt.nhi = (L >> rt.shift) + 1;
 }
 
-// Toeplitz products: L = 2n, N = n = R_A x C with R_A = 2^floor(log2(n)/2).
-// Preconditioner: L = n, N = n/2 = R_P x C with R_P = R_A/2 and the same C,
-// so the preconditioner's inverse column pass and the next product's forward
-// column pass work on the same columns (k_fuse).
-void rt_pair(RT &A, RT &P, int64_t n) {
-    const int64_t RA = int64_t(1) << (ilog2(n) / 2);
-    rt_init(A, 2 * n, RA);
-    rt_init(P, n, RA / 2);
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Toeplitz products: L = next power of two >= 2n (a circulant embedding of
+// any length >= 2n is exact, and its W^T part has the conjugate spectrum),
+// N = L/2 = R_A x C with R_A = 2^floor(log2(N)/2).
+// Power-of-two n >= 16: the Strang preconditioner is an n-point real
+// transform, N = n/2 = R_P x C with R_P = R_A/2 and the same C, so its inverse
+// column pass and the next product's forward column pass share columns
+// (k_fuse).  Any other n: the preconditioner's inverse circulant is built per
+// level with Bluestein's chirp-z DFT (complex transform B of length L) and
+// applied as a Toeplitz product through the same embedding as A.
+bool rt_setup(RT &A, RT &P, RT &B, int64_t n) {
+    const int64_t L = int64_t(1) << ilog2(2 * n);
+    const int64_t NA = L / 2;
+    const int64_t RA = int64_t(1) << (ilog2(NA) / 2);
+    rt_init(A, L, RA);
+    const bool p2 = is_pow2(n) && n >= 16;
+    if (p2) {
+        rt_init(P, n, RA / 2);
+    } else {
+        const int64_t NB = L;
+        rt_init(B, 2 * NB, int64_t(1) << (ilog2(NB) / 2));
+    }
+    return p2;
 }
 
 struct Layout {
     size_t off_U, off_vec, off_tmp, off_w, off_g0, off_cbase, off_buf, off_bufP, off_specA, off_specP, off_tw, off_tw2A,
-        off_tw2P, off_part, off_sc, total;
+        off_tw2P, off_part, off_sc, off_bufB, off_Bhat, off_chirp, off_Ls, off_wv, off_Wt, off_specPj, off_tw2B, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr int NVEC = 10;  // H g r rt u p q phat vhat uhat
+constexpr int NVEC = 11;  // H g r rt u p q phat vhat uhat fbuf
 
-Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P) {
+// internal row stride: n rounded up to even, so every row starts 16-byte aligned
+int64_t ld_of(int64_t n) { return n + (n & 1); }
+
+Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P, const RT &B, bool p2) {
+    const int64_t ld = ld_of(n);
     Layout l{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -83,26 +103,33 @@ Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P) {
         o = al(o + bytes);
         return at;
     };
-    l.off_U = take(sizeof(double) * (size_t)(M + 1) * n);
-    l.off_vec = take(sizeof(double) * (size_t)NVEC * n);
+    l.off_U = take(sizeof(double) * (size_t)(M + 1) * ld);
+    l.off_vec = take(sizeof(double) * (size_t)NVEC * ld);
     l.off_tmp = take(sizeof(double) * (size_t)std::max<int64_t>(A.L, n));
     l.off_w = take(sizeof(double) * (size_t)(n + 2));
     l.off_g0 = take(sizeof(double) * (size_t)(n + 2));
     l.off_cbase = take(sizeof(double) * (size_t)(M + 2));
     l.off_buf = take(sizeof(double2) * (size_t)A.N);
-    l.off_bufP = take(sizeof(double2) * (size_t)P.N);
+    l.off_bufP = take(sizeof(double2) * (size_t)(p2 ? P.N : 0));
     l.off_specA = take(sizeof(double2) * (size_t)A.N);
-    l.off_specP = take(sizeof(double2) * (size_t)P.N);
+    l.off_specP = take(sizeof(double2) * (size_t)(p2 ? P.N : 0));
     l.off_tw = take(sizeof(double2) * (size_t)((int64_t(1) << (PMAX_LOG2 + 1)) - 2));
     l.off_tw2A = take(sizeof(double2) * (size_t)(A.nlo + A.nhi));
-    l.off_tw2P = take(sizeof(double2) * (size_t)(P.nlo + P.nhi));
+    l.off_tw2P = take(sizeof(double2) * (size_t)(p2 ? P.nlo + P.nhi : 0));
     l.off_part = take(sizeof(double) * (size_t)PARTIAL_SLOTS * NSITES);
     l.off_sc = take(sizeof(DevScalars));
+    const size_t nb = p2 ? 0 : (size_t)B.N, nn = p2 ? 0 : (size_t)n;
+    l.off_bufB = take(sizeof(double2) * nb);
+    l.off_Bhat = take(sizeof(double2) * nb);
+    l.off_chirp = take(sizeof(double2) * nn);
+    l.off_Ls = take(sizeof(double2) * nn);
+    l.off_wv = take(sizeof(double2) * nn);
+    l.off_Wt = take(sizeof(double2) * nn);
+    l.off_specPj = take(sizeof(double2) * (p2 ? 0 : (size_t)A.N));
+    l.off_tw2B = take(sizeof(double2) * (p2 ? 0 : (size_t)(B.nlo + B.nhi)));
     l.total = o;
     return l;
 }
-
-bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 int validate(const tsfcde_problem *p) {
     if (!p) return TSFCDE_EINVAL;
@@ -117,7 +144,7 @@ int validate(const tsfcde_problem *p) {
     if (p->warm_start != TSFCDE_WS_ZERO && p->warm_start != TSFCDE_WS_PREV && p->warm_start != TSFCDE_WS_EXTRAP)
         return TSFCDE_EINVAL;
     if (!std::isfinite(p->rtol)) return TSFCDE_EINVAL;
-    if (!is_pow2(p->n) || p->n < 16 || p->n > NMAX) return TSFCDE_EUNSUPPORTED;
+    if (p->n < 4 || p->n > (is_pow2(p->n) ? NMAX : NMAX / 2)) return TSFCDE_EUNSUPPORTED;
     return TSFCDE_OK;
 }
 
@@ -134,15 +161,18 @@ struct tsfcde_plan_s {
     int device = 0;
     hipStream_t stream = nullptr;
     double alpha, beta, a, b, T, h, tau, sigma, kappa, hb;
-    int64_t n, M, level = 0;
+    int64_t n, M, ldn, level = 0;
+    bool p2 = true;      // power-of-two fast path (fused preconditioner)
+    int64_t pj_level = -1;  // level whose inverse-Strang spectrum specPj holds
     double rtol;
     int maxit, warm, flags;
     std::vector<double> gam, dp, dm, eta, cbase, clast;
-    RT A, P;
+    RT A, P, B;
     Layout lay;
     char *ws;
-    double *U, *H, *g, *r, *rt, *u, *p, *q, *phat, *vhat, *uhat, *tmp, *w, *g0, *cb, *part;
+    double *U, *H, *g, *r, *rt, *u, *p, *q, *phat, *vhat, *uhat, *fbuf, *tmp, *w, *g0, *cb, *part;
     double2 *buf, *bufP, *specA, *specP, *tw_all;
+    double2 *bufB, *Bhat, *chirp, *Ls, *wv, *Wt, *specPj;
     DevScalars *sc;
     DevScalars *h_sc = nullptr;  // pinned mirror for polling
     int last_iters = 8;
@@ -284,6 +314,25 @@ hipError_t launch_mid(tsfcde_plan_s *pl, const RT &rt, double2 *Y, const double2
     }
 }
 
+template <int C_, int MODE>
+hipError_t launch_row_t(tsfcde_plan_s *pl, double2 *Y, const double2 *spec, double2 *spec_out) {
+    using G = RowGeo<C_, TSF_E_MID>;
+    hipLaunchKernelGGL((k_row<C_, TSF_E_MID, MODE>), dim3((unsigned)pl->B.R), dim3(G::NT), 0, pl->stream, Y, spec,
+                       spec_out, pl->tw_all);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_row(tsfcde_plan_s *pl, double2 *Y, const double2 *spec, double2 *spec_out) {
+    switch (pl->B.C) {
+#define TSF_CASE(P) \
+    case P: return launch_row_t<P, MODE>(pl, Y, spec, spec_out);
+        TSF_SIZES(TSF_CASE)
+#undef TSF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // ---- per-level symbols -------------------------------------------------------
 
 // s = -sigma for A and P, (1 - sigma) for B.  Product scale 1/(4N); solve scale 4N.
@@ -326,6 +375,46 @@ hipError_t run_op(tsfcde_plan_s *pl, const RT &rt, const double2 *spec, const Sy
     return launch_col<1>(pl, rt, in_spec(pl, rt), out, pred);
 }
 
+// dst[k] = sum_{m<n} src_m exp(-2 pi i m k / n), k < n, for any n (Bluestein):
+// src times conj(chirp), circular convolution of length L with the chirp
+// (spectrum Bhat, 1/L folded in), times conj(chirp).
+hipError_t bluestein(tsfcde_plan_s *pl, const double2 *zc, const double *zr, double2 *dst) {
+    const RT &B = pl->B;
+    OutSpec o{pl->bufB, B.tw, B.C};
+    o.partials = nullptr;
+    o.counter = nullptr;
+    hipError_t e = launch_col<-1>(pl, B, InCplx{zc, zr, pl->chirp, pl->n, B.C}, o, 0);
+    if (e != hipSuccess) return e;
+    if ((e = launch_row<3>(pl, pl->bufB, pl->Bhat, nullptr)) != hipSuccess) return e;
+    OutCplx oc{dst, pl->chirp, pl->n, B.C};
+    oc.partials = nullptr;
+    oc.counter = nullptr;
+    return launch_col<1>(pl, B, InSpec{pl->bufB, B.tw, B.C}, oc, 0);
+}
+
+// Inverse Strang circulant of level j (general n): p = IDFT_n(1/lambda_P) and
+// the DFT of its length-L embedding, in the product transform's native order.
+hipError_t precond_level(tsfcde_plan_s *pl, int64_t j) {
+    if (pl->p2 || pl->pj_level == j) return hipSuccess;
+    const int64_t n = pl->n;
+    const SymParams sp = symbol(pl, j, -pl->sigma, pl->A, false);
+    hipLaunchKernelGGL(k_pc_column, dim3(256), dim3(256), 0, pl->stream, pl->Ls, n, sp, pl->wv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = bluestein(pl, pl->wv, nullptr, pl->Wt)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pc_embed, dim3(256), dim3(256), 0, pl->stream, pl->Wt, n, pl->A.L, pl->tmp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_col<-1>(pl, pl->A, InReal{pl->tmp, pl->A.L, pl->A.C}, out_spec(pl, pl->A), 0)) != hipSuccess)
+        return e;
+    SymParams none{};
+    if ((e = launch_mid<2>(pl, pl->A, pl->buf, nullptr, pl->specPj, none, 0)) != hipSuccess) return e;
+    pl->pj_level = j;
+    return hipSuccess;
+}
+
+// Symbol that multiplies by a stored spectrum as it is.
+SymParams unit_symbol(const RT &rt) { return SymParams{0.0, 1.0, 1.0, 0.0, 1.0 / (4.0 * (double)rt.N)}; }
+
 int poll(tsfcde_plan_s *pl) {
     HIPCHK(hipMemcpyAsync(pl->h_sc, pl->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, pl->stream));
     HIPCHK(hipStreamSynchronize(pl->stream));
@@ -361,20 +450,48 @@ hipError_t cgs_iteration(tsfcde_plan_s *pl, int64_t j, double *x) {
     return launch_col<1>(pl, pl->A, in_spec(pl, pl->A), k10, 1);
 }
 
-int level_rhs(tsfcde_plan_s *pl, int64_t j, const double *d_f, double *x, int warm) {
+// The same iteration for general n: the preconditioner solve is a Toeplitz
+// product with the level's inverse-Strang spectrum (12 kernels).
+hipError_t cgs_iteration_general(tsfcde_plan_s *pl, int64_t j, double *x) {
     const int64_t n = pl->n;
+    const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
+    const SymParams sI = unit_symbol(pl->A);
+    const int64_t C = pl->A.C;
+    hipError_t e;
+    OutReal o1{pl->phat, n, C};
+    o1.partials = nullptr;
+    o1.counter = nullptr;
+    if ((e = run_op<0>(pl, pl->A, pl->specPj, sI, InCgsUP{pl->r, pl->u, pl->p, pl->q, n, C, 0.0, false}, o1, 1)))
+        return e;
+    OutCgsDot o2 = with_red(OutCgsDot{pl->vhat, pl->rt, n, C}, pl, 0);
+    if ((e = run_op<0>(pl, pl->A, pl->specA, sA, InReal{pl->phat, n, C}, o2, 1))) return e;
+    OutReal o3{pl->uhat, n, C};
+    o3.partials = nullptr;
+    o3.counter = nullptr;
+    if ((e = run_op<0>(pl, pl->A, pl->specPj, sI, InCgsQ{pl->u, pl->vhat, pl->q, n, C, 0.0}, o3, 1))) return e;
+    OutCgsR o4 = with_red(OutCgsR{pl->r, pl->rt, n, C, 0.0}, pl, 1);
+    return run_op<0>(pl, pl->A, pl->specA, sA, InCgsX{pl->uhat, x, n, C, 0.0}, o4, 1);
+}
+
+int level_rhs(tsfcde_plan_s *pl, int64_t j, const double *d_f, double *x, int warm) {
+    const int64_t n = pl->n, ld = pl->ldn;
     if (j >= 1) {
         ProfScope ps(pl, 0);
-        const int64_t threads = n / 2;
-        hipLaunchKernelGGL(k_history, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, pl->stream, pl->U, n,
+        const int64_t threads = (n + 1) / 2;
+        hipLaunchKernelGGL(k_history, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, pl->stream, pl->U, n, ld,
                            (int)j, pl->cb, pl->clast[j], pl->kappa, pl->H);
         HIPCHK(hipGetLastError());
     }
+    if (d_f && (reinterpret_cast<uintptr_t>(d_f) & 15)) {  // pairs are read as 16-byte loads
+        hipLaunchKernelGGL(k_copy, dim3(256), dim3(256), 0, pl->stream, d_f, pl->fbuf, n);
+        HIPCHK(hipGetLastError());
+        d_f = pl->fbuf;
+    }
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
-    InReal in{pl->U + (size_t)j * n, n, pl->A.C};
-    OutRhs out{pl->U + (size_t)j * n, pl->H, d_f, pl->g, pl->r, pl->rt, x, n, pl->A.C,
+    InReal in{pl->U + (size_t)j * ld, n, pl->A.C};
+    OutRhs out{pl->U + (size_t)j * ld, pl->H, d_f, pl->g, pl->r, pl->rt, x, n, pl->A.C,
                pl->eta[j] / pl->sigma, (1.0 - pl->sigma) / pl->sigma, warm, j >= 1 ? 1 : 0,
-               j >= 2 ? pl->U + (size_t)(j - 1) * n : nullptr, j >= 2 ? pl->U + (size_t)(j - 2) * n : nullptr};
+               j >= 2 ? pl->U + (size_t)(j - 1) * ld : nullptr, j >= 2 ? pl->U + (size_t)(j - 2) * ld : nullptr};
     out = with_red(out, pl, 2);
     HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
     return TSFCDE_OK;
@@ -407,7 +524,7 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
     if (pl->level >= pl->M) return TSFCDE_EDONE;
     auto t0 = std::chrono::steady_clock::now();
     const int64_t j = pl->level, n = pl->n;
-    double *x = pl->U + (size_t)(j + 1) * n;
+    double *x = pl->U + (size_t)(j + 1) * pl->ldn;
     // initial guess: 0, u^j, or quadratic extrapolation (u^j below level 2)
     int warm = 0;
     if (pl->warm == TSFCDE_WS_PREV) warm = 1;
@@ -415,6 +532,7 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
     int rc = level_rhs(pl, j, d_f, x, warm);
     if (rc) return rc;
     if (warm == 2 && (rc = restart_launch(pl, j, x))) return rc;  // r0 = g - A x0
+    HIPCHK(precond_level(pl, j));
     const bool verify = (pl->flags & TSFCDE_FLAG_VERIFY) != 0;
     int code = TSFCDE_OK, restarts = 0, iters_seen = 0;
     double relres_true = -1.0, last_true2 = HUGE_VAL;
@@ -426,7 +544,8 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
             for (;;) {
                 const int todo = std::min(chunk, pl->maxit - iters_seen);
                 if (todo <= 0) break;
-                for (int k = 0; k < todo; ++k) HIPCHK(cgs_iteration(pl, j, x));
+                for (int k = 0; k < todo; ++k)
+                    HIPCHK(pl->p2 ? cgs_iteration(pl, j, x) : cgs_iteration_general(pl, j, x));
                 if ((rc = poll(pl))) return rc;
                 iters_seen = pl->h_sc->iter;
                 if (pl->h_sc->done) break;
@@ -504,9 +623,9 @@ int tsfcde_workspace_bytes(const tsfcde_problem *prob, size_t *bytes) {
     int rc = validate(prob);
     if (rc) return rc;
     if (!bytes) return TSFCDE_EINVAL;
-    RT A, P;
-    rt_pair(A, P, prob->n);
-    *bytes = layout_for(prob->n, prob->M, A, P).total;
+    RT A, P, B;
+    const bool p2 = rt_setup(A, P, B, prob->n);
+    *bytes = layout_for(prob->n, prob->M, A, P, B, p2).total;
     return TSFCDE_OK;
 }
 
@@ -567,8 +686,9 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
         for (int64_t m = 1; m <= M; ++m) pl->cbase[m] = av[m] + bv[m + 1] - bv[m];
         for (int64_t j = 1; j <= M; ++j) pl->clast[j] = av[j] - bv[j];
     }
-    rt_pair(pl->A, pl->P, n);
-    pl->lay = layout_for(n, M, pl->A, pl->P);
+    pl->p2 = rt_setup(pl->A, pl->P, pl->B, n);
+    pl->ldn = ld_of(n);
+    pl->lay = layout_for(n, M, pl->A, pl->P, pl->B, pl->p2);
     if (bytes < pl->lay.total) {
         delete pl;
         return TSFCDE_ENOMEM;
@@ -583,8 +703,9 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
     const Layout &L = pl->lay;
     pl->U = reinterpret_cast<double *>(ws + L.off_U);
     double *vec = reinterpret_cast<double *>(ws + L.off_vec);
-    double **vp[NVEC] = {&pl->H, &pl->g, &pl->r, &pl->rt, &pl->u, &pl->p, &pl->q, &pl->phat, &pl->vhat, &pl->uhat};
-    for (int k = 0; k < NVEC; ++k) *vp[k] = vec + (size_t)k * n;
+    double **vp[NVEC] = {&pl->H, &pl->g, &pl->r, &pl->rt, &pl->u, &pl->p, &pl->q, &pl->phat, &pl->vhat, &pl->uhat,
+                         &pl->fbuf};
+    for (int k = 0; k < NVEC; ++k) *vp[k] = vec + (size_t)k * pl->ldn;
     pl->tmp = reinterpret_cast<double *>(ws + L.off_tmp);
     pl->w = reinterpret_cast<double *>(ws + L.off_w);
     pl->g0 = reinterpret_cast<double *>(ws + L.off_g0);
@@ -600,6 +721,16 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
     pl->P.hi = pl->P.lo + pl->P.nlo;
     pl->A.tw = Tw2{pl->A.lo, pl->A.hi, pl->A.shift};
     pl->P.tw = Tw2{pl->P.lo, pl->P.hi, pl->P.shift};
+    pl->bufB = reinterpret_cast<double2 *>(ws + L.off_bufB);
+    pl->Bhat = reinterpret_cast<double2 *>(ws + L.off_Bhat);
+    pl->chirp = reinterpret_cast<double2 *>(ws + L.off_chirp);
+    pl->Ls = reinterpret_cast<double2 *>(ws + L.off_Ls);
+    pl->wv = reinterpret_cast<double2 *>(ws + L.off_wv);
+    pl->Wt = reinterpret_cast<double2 *>(ws + L.off_Wt);
+    pl->specPj = reinterpret_cast<double2 *>(ws + L.off_specPj);
+    pl->B.lo = reinterpret_cast<double2 *>(ws + L.off_tw2B);
+    pl->B.hi = pl->B.lo + pl->B.nlo;
+    pl->B.tw = Tw2{pl->B.lo, pl->B.hi, pl->B.shift};
     pl->part = reinterpret_cast<double *>(ws + L.off_part);
     pl->sc = reinterpret_cast<DevScalars *>(ws + L.off_sc);
 
@@ -616,12 +747,14 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
     pl->h_sc->done = 1;
     if (hipMemcpyAsync(pl->sc, pl->h_sc, sizeof(DevScalars), hipMemcpyHostToDevice, pl->stream) != hipSuccess)
         return fail(TSFCDE_EDEVICE);
+    // stored levels and vectors start at zero (the pad of an odd-length row stays zero)
+    if (hipMemsetAsync(ws + L.off_U, 0, L.off_tmp - L.off_U, pl->stream) != hipSuccess) return fail(TSFCDE_EDEVICE);
     if (hipMemcpyAsync(pl->cb, pl->cbase.data(), sizeof(double) * (M + 1), hipMemcpyHostToDevice, pl->stream) !=
         hipSuccess)
         return fail(TSFCDE_EDEVICE);
     // twiddle tables
     hipLaunchKernelGGL(k_twiddle_packed, dim3(32), dim3(256), 0, pl->stream, pl->tw_all, PMAX_LOG2);
-    for (RT *rt : {&pl->A, &pl->P})
+    for (RT *rt : {&pl->A, pl->p2 ? &pl->P : &pl->B})
         hipLaunchKernelGGL(k_twiddle_tw2, dim3(64), dim3(256), 0, pl->stream, rt->lo, rt->hi, rt->L, rt->shift,
                            rt->nhi);
     // WSGD weights omega_0..omega_n (Lemma 2, Lemma 3 recurrence)
@@ -641,9 +774,27 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
         SymParams sp{};
         if (launch_mid<2>(pl, pl->A, pl->buf, nullptr, pl->specA, sp, 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
         hipLaunchKernelGGL(k_strang_column, dim3(512), dim3(256), 0, pl->stream, pl->w, n, pl->tmp);
-        InReal inP{pl->tmp, n, pl->P.C};
-        if (launch_col<-1>(pl, pl->P, inP, out_spec(pl, pl->P), 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
-        if (launch_mid<2>(pl, pl->P, pl->bufP, nullptr, pl->specP, sp, 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
+        if (pl->p2) {
+            InReal inP{pl->tmp, n, pl->P.C};
+            if (launch_col<-1>(pl, pl->P, inP, out_spec(pl, pl->P), 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
+            if (launch_mid<2>(pl, pl->P, pl->bufP, nullptr, pl->specP, sp, 0) != hipSuccess)
+                return fail(TSFCDE_EDEVICE);
+        } else {
+            // Bluestein set-up: chirp, the spectrum of its circular arrangement
+            // (with the 1/L of the inverse transform folded in), then the Strang
+            // spectrum lambda = DFT_n(strang column).
+            const RT &B = pl->B;
+            hipLaunchKernelGGL(k_chirp, dim3(256), dim3(256), 0, pl->stream, pl->chirp, n);
+            hipLaunchKernelGGL(k_chirp_embed, dim3(256), dim3(256), 0, pl->stream, pl->chirp, n, B.N,
+                               1.0 / (double)B.N, pl->Bhat);
+            OutSpec o{pl->bufB, B.tw, B.C};
+            o.partials = nullptr;
+            o.counter = nullptr;
+            if (launch_col<-1>(pl, B, InCplx{pl->Bhat, nullptr, nullptr, B.N, B.C}, o, 0) != hipSuccess)
+                return fail(TSFCDE_EDEVICE);
+            if (launch_row<4>(pl, pl->bufB, nullptr, pl->Bhat) != hipSuccess) return fail(TSFCDE_EDEVICE);
+            if (bluestein(pl, nullptr, pl->tmp, pl->Ls) != hipSuccess) return fail(TSFCDE_EDEVICE);
+        }
     }
     // u^0 = phi(x_i)
     {
@@ -652,6 +803,7 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
             for (int64_t i = 0; i < n; ++i) u0[i] = prob->phi(prob->a + (double)(i + 1) * pl->h, prob->phi_user);
         if (hipMemcpyAsync(pl->U, u0.data(), sizeof(double) * n, hipMemcpyHostToDevice, pl->stream) != hipSuccess)
             return fail(TSFCDE_EDEVICE);
+        if (hipGetLastError() != hipSuccess) return fail(TSFCDE_EDEVICE);
         if (hipStreamSynchronize(pl->stream) != hipSuccess) return fail(TSFCDE_EDEVICE);
     }
     pl->level = 0;
@@ -661,8 +813,8 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
 
 int tsfcde_set_state(tsfcde_plan_t pl, int64_t level, const double *d_U) {
     if (!pl || !d_U || level < 0 || level > pl->M) return TSFCDE_EINVAL;
-    HIPCHK(hipMemcpyAsync(pl->U, d_U, sizeof(double) * (size_t)(level + 1) * pl->n, hipMemcpyDeviceToDevice,
-                          pl->stream));
+    HIPCHK(hipMemcpy2DAsync(pl->U, sizeof(double) * pl->ldn, d_U, sizeof(double) * pl->n, sizeof(double) * pl->n,
+                            (size_t)(level + 1), hipMemcpyDeviceToDevice, pl->stream));
     pl->level = level;
     return TSFCDE_OK;
 }
@@ -682,13 +834,15 @@ int tsfcde_solve(tsfcde_plan_t pl, const double *d_F, int64_t ldF, double *d_U_o
         if (rc) return rc;
     }
     if (d_U_out)
-        HIPCHK(hipMemcpyAsync(d_U_out, pl->U, sizeof(double) * (size_t)(pl->M + 1) * pl->n, hipMemcpyDeviceToDevice,
-                              pl->stream));
+        HIPCHK(hipMemcpy2DAsync(d_U_out, sizeof(double) * pl->n, pl->U, sizeof(double) * pl->ldn,
+                                sizeof(double) * pl->n, (size_t)(pl->M + 1), hipMemcpyDeviceToDevice, pl->stream));
     return TSFCDE_OK;
 }
 
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 int tsfcde_apply(tsfcde_plan_t pl, int32_t op, int64_t j, const double *d_x, double *d_y) {
-    if (!pl || !d_x || !d_y || j < 0 || j >= pl->M) return TSFCDE_EINVAL;
+    if (!pl || !d_x || !d_y || j < 0 || j >= pl->M || !aligned16(d_x) || !aligned16(d_y)) return TSFCDE_EINVAL;
     const int64_t n = pl->n;
     if (op == TSFCDE_OP_A || op == TSFCDE_OP_B) {
         const double s = op == TSFCDE_OP_A ? -pl->sigma : 1.0 - pl->sigma;
@@ -697,12 +851,19 @@ int tsfcde_apply(tsfcde_plan_t pl, int32_t op, int64_t j, const double *d_x, dou
         out.partials = nullptr;
         out.counter = nullptr;
         HIPCHK(run_op<0>(pl, pl->A, pl->specA, symbol(pl, j, s, pl->A, false), in, out, 0));
-    } else if (op == TSFCDE_OP_PINV) {
+    } else if (op == TSFCDE_OP_PINV && pl->p2) {
         InReal in{d_x, n, pl->P.C};
         OutReal out{d_y, n, pl->P.C};
         out.partials = nullptr;
         out.counter = nullptr;
         HIPCHK(run_op<1>(pl, pl->P, pl->specP, symbol(pl, j, -pl->sigma, pl->P, true), in, out, 0));
+    } else if (op == TSFCDE_OP_PINV) {
+        HIPCHK(precond_level(pl, j));
+        InReal in{d_x, n, pl->A.C};
+        OutReal out{d_y, n, pl->A.C};
+        out.partials = nullptr;
+        out.counter = nullptr;
+        HIPCHK(run_op<0>(pl, pl->A, pl->specPj, unit_symbol(pl->A), in, out, 0));
     } else {
         return TSFCDE_EINVAL;
     }
@@ -712,7 +873,7 @@ int tsfcde_apply(tsfcde_plan_t pl, int32_t op, int64_t j, const double *d_x, dou
 }
 
 int tsfcde_rhs(tsfcde_plan_t pl, int64_t j, const double *d_f, double *d_g) {
-    if (!pl || !d_g || j < 0 || j >= pl->M || j > pl->level) return TSFCDE_EINVAL;
+    if (!pl || !d_g || j < 0 || j >= pl->M || j > pl->level || !aligned16(d_g)) return TSFCDE_EINVAL;
     int rc = level_rhs(pl, j, d_f, pl->uhat, 0);
     if (rc) return rc;
     HIPCHK(hipMemcpyAsync(d_g, pl->g, sizeof(double) * pl->n, hipMemcpyDeviceToDevice, pl->stream));
@@ -730,25 +891,28 @@ int tsfcde_weights(tsfcde_plan_t pl, double *d_w) {
 
 int tsfcde_spectrum(tsfcde_plan_t pl, int32_t which, double *d_out) {
     if (!pl || !d_out) return TSFCDE_EINVAL;
-    const RT *rt;
-    const double2 *spec;
     if (which == TSFCDE_SPEC_EMBED) {
-        rt = &pl->A;
-        spec = pl->specA;
+        hipLaunchKernelGGL(k_spec_export, dim3(256), dim3(256), 0, pl->stream, pl->specA, pl->A.R, pl->A.C,
+                           reinterpret_cast<double2 *>(d_out));
+    } else if (which == TSFCDE_SPEC_STRANG && pl->p2) {
+        hipLaunchKernelGGL(k_spec_export, dim3(256), dim3(256), 0, pl->stream, pl->specP, pl->P.R, pl->P.C,
+                           reinterpret_cast<double2 *>(d_out));
     } else if (which == TSFCDE_SPEC_STRANG) {
-        rt = &pl->P;
-        spec = pl->specP;
+        HIPCHK(hipMemcpyAsync(d_out, pl->Ls, sizeof(double2) * (size_t)(pl->n / 2 + 1), hipMemcpyDeviceToDevice,
+                              pl->stream));
     } else {
         return TSFCDE_EINVAL;
     }
-    hipLaunchKernelGGL(k_spec_export, dim3(256), dim3(256), 0, pl->stream, spec, rt->R, rt->C,
-                       reinterpret_cast<double2 *>(d_out));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(pl->stream));
     return TSFCDE_OK;
 }
 
 const double *tsfcde_history(tsfcde_plan_t pl) { return pl ? pl->U : nullptr; }
+
+int64_t tsfcde_history_ld(tsfcde_plan_t pl) { return pl ? pl->ldn : -1; }
+
+int64_t tsfcde_embedding_length(tsfcde_plan_t pl) { return pl ? pl->A.L : -1; }
 
 int64_t tsfcde_level(tsfcde_plan_t pl) { return pl ? pl->level : -1; }
 

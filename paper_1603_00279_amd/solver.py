@@ -104,10 +104,12 @@ class TimeLevelSolver:
         return int(self._lib.tsfcde_level(self._plan))
 
     def history(self) -> torch.Tensor:
-        """View of the stored levels U ((M+1) x n) inside the workspace."""
+        """View of the stored levels U ((M+1) x n, row stride ld) inside the workspace."""
         ptr = self._lib.tsfcde_history(self._plan)
+        ld = int(self._lib.tsfcde_history_ld(self._plan))
         off = ptr - self._ws.data_ptr()
-        return self._ws[off: off + 8 * (self.M + 1) * self.n].view(torch.float64).view(self.M + 1, self.n)
+        flat = self._ws[off: off + 8 * (self.M + 1) * ld].view(torch.float64)
+        return flat.view(self.M + 1, ld)[:, : self.n]
 
     def set_state(self, level: int, U: torch.Tensor):
         U = U.contiguous()
@@ -147,8 +149,12 @@ class TimeLevelSolver:
         N.check(self._lib.tsfcde_weights(self._plan, _dptr(w)), "tsfcde_weights")
         return w
 
+    @property
+    def embedding_length(self) -> int:
+        return int(self._lib.tsfcde_embedding_length(self._plan))
+
     def spectrum(self, which: int) -> torch.Tensor:
-        cnt = self.n + 1 if which == N.TSFCDE_SPEC_EMBED else self.n // 2 + 1
+        cnt = self.embedding_length // 2 + 1 if which == N.TSFCDE_SPEC_EMBED else self.n // 2 + 1
         out = torch.empty(2 * cnt, dtype=torch.float64, device=self.device)
         N.check(self._lib.tsfcde_spectrum(self._plan, which, _dptr(out)), "tsfcde_spectrum")
         return torch.view_as_complex(out.view(cnt, 2))

@@ -37,7 +37,7 @@ def _problem(N, **kw):
 @pytest.mark.parametrize("field,value,code", [
     ("alpha", 0.0, -1), ("alpha", 1.2, -1), ("beta", 1.0, -1), ("beta", 2.5, -1),
     ("b", 0.0, -1), ("T", 0.0, -1), ("M", 0, -1), ("n", 1, -1), ("warm_start", 7, -1),
-    ("precision", 3, -1), ("n", 100, -8), ("n", 8, -8),
+    ("precision", 3, -1), ("n", 3, -8), ("n", (1 << 23) + 1, -8), ("n", (1 << 24) + 2, -8),
 ])
 def test_validation(N, field, value, code):
     p, keep = _problem(N, **{field: value})
@@ -75,3 +75,11 @@ def test_null_arguments_rejected(N):
 def test_strerror(N):
     for code in range(-8, 1):
         assert N.lib().tsfcde_strerror(code)
+
+
+@pytest.mark.parametrize("n", [4, 5, 8, 100, 1023, 1 << 20, (1 << 23) - 1, 1 << 24])
+def test_general_sizes_accepted(N, n):
+    p, keep = _problem(N, n=n)
+    nb = ctypes.c_size_t(0)
+    assert N.lib().tsfcde_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == 0
+    assert nb.value >= 8 * 9 * n

@@ -228,7 +228,7 @@ def test_error_paths():
     with pytest.raises(P.TsfcdeError):
         P.TimeLevelSolver(alpha=0.5, beta=1.5, n=64, M=2, gamma_at=[0, 0], dplus_at=[1, -1], dminus_at=[1, 1])
     with pytest.raises(P.TsfcdeError):
-        P.TimeLevelSolver(alpha=0.5, beta=1.5, n=100, M=2, gamma_at=[0, 0], dplus_at=[1, 1], dminus_at=[1, 1])
+        P.TimeLevelSolver(alpha=0.5, beta=1.5, n=3, M=2, gamma_at=[0, 0], dplus_at=[1, 1], dminus_at=[1, 1])
 
 
 def test_zero_source_zero_solution():
@@ -263,3 +263,72 @@ def test_warm_starts_cut_iterations(n):
     # u = t^2 P(x): extrapolation is nearly exact, u^j is not much better than 0
     it0, it1, it2 = (sum(runs[w][1][2:]) for w in (0, 1, 2))
     assert it2 < it0 and it1 <= it0 + 2, (it0, it1, it2)
+
+
+# ---------------------------------------------------------------------------
+# General n (not a power of two): odd lengths, the paper's own grids
+# n = N - 1, and the Bluestein-built inverse Strang preconditioner.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [5, 31, 63, 100, 127, 1000, 1023])
+def test_general_n_operators(n):
+    import paper_1603_00279_amd as P
+    banner(f"general-n operators n={n}")
+    prob = W.config_large(n=n, M=6, alpha=0.6, beta=1.5)
+    x = np.random.default_rng(n).standard_normal(n)
+    with make(prob) as s:
+        assert s.embedding_length >= 2 * n
+        emb = host(s.spectrum(P.TSFCDE_SPEC_EMBED))
+        strang = host(s.spectrum(P.TSFCDE_SPEC_STRANG))
+        for j in (0, 3):
+            yA = host(s.apply(P.TSFCDE_OP_A, j, t64(x)))
+            yB = host(s.apply(P.TSFCDE_OP_B, j, t64(x)))
+            yP = host(s.apply(P.TSFCDE_OP_PINV, j, t64(x)))
+            assert relerr(yA, O.level_A(prob, j) @ x) < 1e-12
+            assert relerr(yB, O.level_B(prob, j) @ x) < 1e-12
+            Pm = O.preconditioner_matrix(prob, j)
+            berr = np.linalg.norm(Pm @ yP - x) / (np.linalg.norm(Pm, 2) * np.linalg.norm(yP))
+            assert berr < 64 * 2.2e-16, berr
+    L = 2 * n
+    while L & (L - 1):
+        L += 1
+    assert np.max(np.abs(emb - np.fft.fft(O.embedding_column(1.5, n, L))[: L // 2 + 1])) < 1e-13 * np.abs(emb).max()
+    w = O.wsgd_weights(1.5, n + 1)
+    col = O.strang_column(lambda m: w[m + 1] if m >= -1 else 0.0, n)
+    ref = O.circulant_eigenvalues(col)[: n // 2 + 1]
+    assert np.max(np.abs(strang - ref)) < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,M", [(7, 5), (63, 16), (255, 10), (1000, 8)])
+def test_general_n_march(n, M):
+    banner(f"general-n march n={n}")
+    prob = W.config_large(n=n, M=M, alpha=0.45, beta=1.65)
+    Uref = O.march(prob)
+    F = t64(np.stack([prob.source_level(j) for j in range(M)]))
+    with make(prob, rtol=1e-13) as s:
+        s.solve(F)
+        U = host(s.history())
+    for j in range(1, M + 1):
+        assert relerr(U[j], Uref[j]) < 1e-10, (j, relerr(U[j], Uref[j]))
+
+
+@pytest.mark.parametrize("example,alpha,beta,N,col,ref", [
+    (1, 0.1, 1.8, 32, "l2", 2.7954e-4),   # Table 1
+    (1, 0.9, 1.8, 64, "c", 8.7173e-5),    # Table 1
+    (2, 0.5, 1.3, 32, "c", 5.6897e-4),    # Table 5
+])
+def test_paper_grids_on_gpu(example, alpha, beta, N, col, ref):
+    """The paper's own grids (n = N - 1 interior points, tau = h): the GPU
+    march reproduces the printed errors as closely as the oracle does, and
+    matches the oracle level by level."""
+    banner(f"paper grid example {example} N={N}")
+    make_p = W.example1 if example == 1 else W.example2
+    prob = make_p(alpha, beta, N)
+    Uref = O.march(prob)
+    F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
+    with make(prob, rtol=1e-13) as s:
+        s.solve(F)
+        U = host(s.history())
+    assert relerr(U, Uref) < 1e-10
+    l2, cn = O.error_norms(prob, U)
+    got = l2 if col == "l2" else cn
+    assert abs(got / ref - 1) < 0.005, (got, ref)
