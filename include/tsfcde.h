@@ -203,6 +203,39 @@ int tsfcde_profile_read(tsfcde_plan_t plan, int32_t kernel_class, int64_t *launc
 /* Release the plan (host state only; the caller frees the workspace). */
 int tsfcde_destroy(tsfcde_plan_t plan);
 
+/* ---- batched form ----------------------------------------------------
+ * Many independent instances of (1.1) (any n, alpha, beta, coefficients,
+ * same M) advanced level by level together.  Every level runs as grouped
+ * launches: instances with the same embedding length share each kernel launch
+ * (one workgroup row per instance), each instance follows Algorithm 2 with
+ * its own CGS recurrence and stops on its own convergence flag.  All
+ * instances use the general-n preconditioner path.  Results equal those of
+ * single-instance plans of the same problems. */
+typedef struct tsfcde_batch_s *tsfcde_batch_t;
+
+/* Workspace for `count` instances (all with the same M). */
+int tsfcde_batch_workspace_bytes(const tsfcde_problem *probs, int32_t count, size_t *bytes);
+
+/* Plan the batch in one caller-owned, 256-byte aligned device workspace;
+ * solver options (rtol, maxit, warm_start) are taken per instance for rtol
+ * and from probs[0] for maxit and warm_start. */
+int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_workspace, size_t bytes, void *stream,
+                      tsfcde_batch_t *out);
+
+/* Member i as a plan handle, for tsfcde_set_state / tsfcde_history /
+ * tsfcde_apply; step the batch only with tsfcde_batch_step (after
+ * tsfcde_set_state on every member, tsfcde_batch_set_level re-synchronises). */
+tsfcde_plan_t tsfcde_batch_member(tsfcde_batch_t batch, int32_t i);
+int tsfcde_batch_set_level(tsfcde_batch_t batch, int64_t level);
+
+/* Advance every instance one level.  d_f: host array of `count` device
+ * pointers (f at t_{j+sigma} of each instance; an entry or the array may be
+ * NULL for f = 0).  stats: `count` entries or NULL.  Returns the first
+ * failing instance's code (all instances still advance). */
+int tsfcde_batch_step(tsfcde_batch_t batch, const double *const *d_f, tsfcde_stats *stats);
+
+int tsfcde_batch_destroy(tsfcde_batch_t batch);
+
 /* Static description of a status code. */
 const char *tsfcde_strerror(int status);
 

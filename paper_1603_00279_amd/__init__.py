@@ -12,4 +12,4 @@ from ._native import (  # noqa: F401
     TSFCDE_FLAG_TRUE_RESIDUAL, TSFCDE_FLAG_VERIFY, TSFCDE_OP_A, TSFCDE_OP_B, TSFCDE_OP_PINV, TSFCDE_SPEC_EMBED,
     TSFCDE_SPEC_STRANG, TsfcdeError, lib, header_symbols,
 )
-from .solver import TimeLevelSolver  # noqa: F401
+from .solver import BatchSolver, TimeLevelSolver  # noqa: F401

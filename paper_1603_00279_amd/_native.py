@@ -74,6 +74,13 @@ _SIGS = {
     "tsfcde_profile": (c_int32, [c_void_p, c_int32, c_int32]),
     "tsfcde_profile_read": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
     "tsfcde_destroy": (c_int32, [c_void_p]),
+    "tsfcde_batch_workspace_bytes": (c_int32, [POINTER(tsfcde_problem), c_int32, POINTER(c_size_t)]),
+    "tsfcde_plan_batch": (c_int32, [POINTER(tsfcde_problem), c_int32, c_void_p, c_size_t, c_void_p,
+                                    POINTER(c_void_p)]),
+    "tsfcde_batch_member": (c_void_p, [c_void_p, c_int32]),
+    "tsfcde_batch_set_level": (c_int32, [c_void_p, c_int64]),
+    "tsfcde_batch_step": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(tsfcde_stats)]),
+    "tsfcde_batch_destroy": (c_int32, [c_void_p]),
     "tsfcde_strerror": (c_char_p, [c_int32]),
 }
 

@@ -477,9 +477,8 @@ template <class Out> struct ColSink {
 };
 
 template <int R, int EMAX, int DIR, class In, class Out>
-__global__ void __launch_bounds__((ColGeo<R, EMAX>::NT)) k_col(int64_t C, In in, Out out,
-                                                             const double2 *__restrict__ tw_all, DevScalars *sc,
-                                                             int pred) {
+__device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double2 *__restrict__ tw_all, DevScalars *sc,
+                                         int pred) {
     if (pred && sc->done) return;
     using G = ColGeo<R, EMAX>;
     constexpr int E = G::E, T = G::T, B = G::B;
@@ -511,6 +510,30 @@ __global__ void __launch_bounds__((ColGeo<R, EMAX>::NT)) k_col(int64_t C, In in,
             if (threadIdx.x == 0) out.final(tot, sc);
         }
     }
+}
+
+template <int R, int EMAX, int DIR, class In, class Out>
+__global__ void __launch_bounds__((ColGeo<R, EMAX>::NT)) k_col(int64_t C, In in, Out out,
+                                                             const double2 *__restrict__ tw_all, DevScalars *sc,
+                                                             int pred) {
+    col_body<R, EMAX, DIR, In, Out>(C, in, out, tw_all, sc, pred);
+}
+
+// Batched form: one launch for a group of instances with the same transform
+// geometry; blockIdx.y selects the instance, whose loader, store and scalars
+// come from a descriptor in device memory.
+template <class In, class Out> struct ColDesc {
+    int64_t C;
+    In in;
+    Out out;
+    DevScalars *sc;
+};
+
+template <int R, int EMAX, int DIR, class In, class Out>
+__global__ void __launch_bounds__((ColGeo<R, EMAX>::NT)) k_col_b(const ColDesc<In, Out> *__restrict__ d,
+                                                               const double2 *__restrict__ tw_all, int pred) {
+    const ColDesc<In, Out> D = d[blockIdx.y];
+    col_body<R, EMAX, DIR, In, Out>(D.C, D.in, D.out, tw_all, D.sc, pred);
 }
 
 // ---------------------------------------------------------------------------
@@ -655,10 +678,8 @@ struct RowSink {  // Y[row*C + pos] = val
 };
 
 template <int C_, int EMAX, int MODE>
-__global__ void __launch_bounds__((MidGeo<C_, EMAX>::NT)) k_mid(int64_t R, double2 *Y, const double2 *spec,
-                                                              double2 *spec_out, Tw2 twL, SymParams sp,
-                                                              const double2 *__restrict__ tw_all, DevScalars *sc,
-                                                              int pred) {
+__device__ __forceinline__ void mid_body(int64_t R, double2 *Y, const double2 *spec, double2 *spec_out, Tw2 twL,
+                                         SymParams sp, const double2 *__restrict__ tw_all, DevScalars *sc, int pred) {
     if (pred && sc->done) return;
     using G = MidGeo<C_, EMAX>;
     constexpr int E = G::E, T = G::T, LS = G::LS;
@@ -795,6 +816,31 @@ __global__ void __launch_bounds__((MidGeo<C_, EMAX>::NT)) k_mid(int64_t R, doubl
     }
 }
 
+template <int C_, int EMAX, int MODE>
+__global__ void __launch_bounds__((MidGeo<C_, EMAX>::NT)) k_mid(int64_t R, double2 *Y, const double2 *spec,
+                                                              double2 *spec_out, Tw2 twL, SymParams sp,
+                                                              const double2 *__restrict__ tw_all, DevScalars *sc,
+                                                              int pred) {
+    mid_body<C_, EMAX, MODE>(R, Y, spec, spec_out, twL, sp, tw_all, sc, pred);
+}
+
+struct MidDesc {
+    int64_t R;
+    double2 *Y;
+    const double2 *spec;
+    double2 *spec_out;
+    Tw2 twL;
+    SymParams sp;
+    DevScalars *sc;
+};
+
+template <int C_, int EMAX, int MODE>
+__global__ void __launch_bounds__((MidGeo<C_, EMAX>::NT)) k_mid_b(const MidDesc *__restrict__ d,
+                                                                const double2 *__restrict__ tw_all, int pred) {
+    const MidDesc D = d[blockIdx.y];
+    mid_body<C_, EMAX, MODE>(D.R, D.Y, D.spec, D.spec_out, D.twL, D.sp, tw_all, D.sc, pred);
+}
+
 // ---------------------------------------------------------------------------
 // Complex transforms (Bluestein's chirp-z DFT of arbitrary length n, used to
 // build the Strang preconditioner when n is not a power of two).
@@ -843,8 +889,8 @@ template <int C_, int EMAX> struct RowGeo {
 // FFT, multiply by the stored spectrum (native order), inverse row FFT (the
 // middle of a circular convolution).  MODE 4: forward row FFT, spectrum out.
 template <int C_, int EMAX, int MODE>
-__global__ void __launch_bounds__((RowGeo<C_, EMAX>::NT)) k_row(double2 *Y, const double2 *spec, double2 *spec_out,
-                                                                const double2 *__restrict__ tw_all) {
+__device__ __forceinline__ void row_body(double2 *Y, const double2 *spec, double2 *spec_out,
+                                         const double2 *__restrict__ tw_all) {
     using G = RowGeo<C_, EMAX>;
     constexpr int E = G::E, T = G::T;
     __shared__ double2 lds[G::LS];
@@ -871,6 +917,25 @@ __global__ void __launch_bounds__((RowGeo<C_, EMAX>::NT)) k_row(double2 *Y, cons
         RowSink rsink{Y, row * C_};
         fft<C_, E, 1>(v, j, active, tw_all, lds, 1, rsink);
     }
+}
+
+template <int C_, int EMAX, int MODE>
+__global__ void __launch_bounds__((RowGeo<C_, EMAX>::NT)) k_row(double2 *Y, const double2 *spec, double2 *spec_out,
+                                                                const double2 *__restrict__ tw_all) {
+    row_body<C_, EMAX, MODE>(Y, spec, spec_out, tw_all);
+}
+
+struct RowDesc {
+    double2 *Y;
+    const double2 *spec;
+    double2 *spec_out;
+};
+
+template <int C_, int EMAX, int MODE>
+__global__ void __launch_bounds__((RowGeo<C_, EMAX>::NT)) k_row_b(const RowDesc *__restrict__ d,
+                                                                  const double2 *__restrict__ tw_all) {
+    const RowDesc D = d[blockIdx.y];
+    row_body<C_, EMAX, MODE>(D.Y, D.spec, D.spec_out, tw_all);
 }
 
 // Chirp b_m = exp(i pi m^2 / n), m < n (m^2 reduced modulo 2n exactly).
@@ -955,6 +1020,77 @@ __global__ void __launch_bounds__(256) k_history(const double *__restrict__ U, i
         prev = x1;
     }
     *reinterpret_cast<double2 *>(H + i) = make_double2(kappa * acc.x, kappa * acc.y);
+}
+
+// Batched element-wise kernels: descriptor per instance (blockIdx.y), a
+// grid-stride loop over that instance's length in blockIdx.x.
+struct HistDesc {
+    const double *U;
+    int64_t n, ldu;
+    const double *cbase;
+    double clast, kappa;
+    double *H;
+    int j;
+};
+
+__global__ void __launch_bounds__(256) k_history_b(const HistDesc *__restrict__ d) {
+    const HistDesc D = d[blockIdx.y];
+    if (D.j < 1) return;
+    for (int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); i < D.n;
+         i += 2 * (int64_t)gridDim.x * blockDim.x) {
+        double2 prev = *reinterpret_cast<const double2 *>(D.U + i);
+        double2 acc = make_double2(0.0, 0.0);
+        for (int s = 0; s < D.j; ++s) {
+            const double2 x1 = *reinterpret_cast<const double2 *>(D.U + (int64_t)(s + 1) * D.ldu + i);
+            const double c1 = s == 0 ? D.clast : D.cbase[D.j - s];
+            acc.x = fma(c1, x1.x - prev.x, acc.x);
+            acc.y = fma(c1, x1.y - prev.y, acc.y);
+            prev = x1;
+        }
+        *reinterpret_cast<double2 *>(D.H + i) = make_double2(D.kappa * acc.x, D.kappa * acc.y);
+    }
+}
+
+struct PcDesc {
+    const double2 *Ls;
+    double2 *w;
+    const double2 *Wt;
+    double *e;
+    int64_t n, L;
+    SymParams sp;
+};
+
+__global__ void k_pc_column_b(const PcDesc *__restrict__ d) {
+    const PcDesc D = d[blockIdx.y];
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < D.n; k += (int64_t)gridDim.x * blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * (double)k / (double)D.n, &sn, &cs);
+        const double2 L = D.Ls[k];
+        const double2 lam = make_double2(fma(D.sp.cre, L.x, D.sp.s0), fma(D.sp.cim, L.y, D.sp.cq * sn));
+        const double q = 1.0 / fma(lam.x, lam.x, lam.y * lam.y);
+        D.w[k] = make_double2(lam.x * q, lam.y * q);
+    }
+}
+
+__global__ void k_pc_embed_b(const PcDesc *__restrict__ d) {
+    const PcDesc D = d[blockIdx.y];
+    const double inv = 1.0 / (double)D.n;
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < D.L; m += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (m < D.n) v = D.Wt[m].x * inv;
+        else if (D.L - m < D.n) v = D.Wt[D.n - (D.L - m)].x * inv;
+        D.e[m] = v;
+    }
+}
+
+// Convergence state of every instance of a batch, gathered for one host read:
+// out[i] = (done, status, iter, 0).
+__global__ void k_gather_done(DevScalars *const *__restrict__ scs, int count, int4 *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        const DevScalars *s = scs[i];
+        out[i] = make_int4(s->done, s->status, s->iter, 0);
+    }
 }
 
 // ---------------------------------------------------------------------------

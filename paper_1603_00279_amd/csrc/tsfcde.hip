@@ -67,12 +67,12 @@ bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 // (k_fuse).  Any other n: the preconditioner's inverse circulant is built per
 // level with Bluestein's chirp-z DFT (complex transform B of length L) and
 // applied as a Toeplitz product through the same embedding as A.
-bool rt_setup(RT &A, RT &P, RT &B, int64_t n) {
+bool rt_setup(RT &A, RT &P, RT &B, int64_t n, bool force_general = false) {
     const int64_t L = int64_t(1) << ilog2(2 * n);
     const int64_t NA = L / 2;
     const int64_t RA = int64_t(1) << (ilog2(NA) / 2);
     rt_init(A, L, RA);
-    const bool p2 = is_pow2(n) && n >= 16;
+    const bool p2 = is_pow2(n) && n >= 16 && !force_general;
     if (p2) {
         rt_init(P, n, RA / 2);
     } else {
@@ -619,17 +619,22 @@ double sample(tsfcde_coef_fn fn, const double *arr, void *user, int64_t j, doubl
 
 extern "C" {
 
-int tsfcde_workspace_bytes(const tsfcde_problem *prob, size_t *bytes) {
+static int workspace_bytes_impl(const tsfcde_problem *prob, bool force_general, size_t *bytes) {
     int rc = validate(prob);
     if (rc) return rc;
     if (!bytes) return TSFCDE_EINVAL;
     RT A, P, B;
-    const bool p2 = rt_setup(A, P, B, prob->n);
+    const bool p2 = rt_setup(A, P, B, prob->n, force_general);
     *bytes = layout_for(prob->n, prob->M, A, P, B, p2).total;
     return TSFCDE_OK;
 }
 
-int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, void *stream, tsfcde_plan_t *out) {
+int tsfcde_workspace_bytes(const tsfcde_problem *prob, size_t *bytes) {
+    return workspace_bytes_impl(prob, false, bytes);
+}
+
+static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t bytes, void *stream,
+                       bool force_general, tsfcde_plan_t *out) {
     if (!out) return TSFCDE_EINVAL;
     *out = nullptr;
     int rc = validate(prob);
@@ -686,7 +691,7 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
         for (int64_t m = 1; m <= M; ++m) pl->cbase[m] = av[m] + bv[m + 1] - bv[m];
         for (int64_t j = 1; j <= M; ++j) pl->clast[j] = av[j] - bv[j];
     }
-    pl->p2 = rt_setup(pl->A, pl->P, pl->B, n);
+    pl->p2 = rt_setup(pl->A, pl->P, pl->B, n, force_general);
     pl->ldn = ld_of(n);
     pl->lay = layout_for(n, M, pl->A, pl->P, pl->B, pl->p2);
     if (bytes < pl->lay.total) {
@@ -811,6 +816,10 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
     return TSFCDE_OK;
 }
 
+int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, void *stream, tsfcde_plan_t *out) {
+    return plan_create(prob, d_workspace, bytes, stream, false, out);
+}
+
 int tsfcde_set_state(tsfcde_plan_t pl, int64_t level, const double *d_U) {
     if (!pl || !d_U || level < 0 || level > pl->M) return TSFCDE_EINVAL;
     HIPCHK(hipMemcpy2DAsync(pl->U, sizeof(double) * pl->ldn, d_U, sizeof(double) * pl->n, sizeof(double) * pl->n,
@@ -839,7 +848,7 @@ int tsfcde_solve(tsfcde_plan_t pl, const double *d_F, int64_t ldF, double *d_U_o
     return TSFCDE_OK;
 }
 
-bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 int tsfcde_apply(tsfcde_plan_t pl, int32_t op, int64_t j, const double *d_x, double *d_y) {
     if (!pl || !d_x || !d_y || j < 0 || j >= pl->M || !aligned16(d_x) || !aligned16(d_y)) return TSFCDE_EINVAL;
@@ -958,6 +967,509 @@ const char *tsfcde_strerror(int s) {
         case TSFCDE_EUNSUPPORTED: return "problem size not supported by this build";
         default: return "unknown status";
     }
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched form: many independent instances advanced one level at a time with
+// grouped launches.  Instances with the same embedding length L share a
+// transform geometry and form a group; every kernel of the level runs once per
+// group, blockIdx.y selecting the instance, whose vectors, spectra, symbol and
+// CGS scalars come from device descriptors rebuilt once per level.  Each
+// instance stops on its own convergence flag (its later launches exit at once).
+// All instances take the general path (Bluestein-built inverse Strang
+// preconditioner), so they run the same kernel sequence.
+// ===========================================================================
+struct DoneRec {
+    int done, status, iter, pad;
+    double rnorm2, gnorm2;
+};
+
+namespace tsf {
+__global__ void k_gather_state(DevScalars *const *__restrict__ scs, int count, DoneRec *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        const DevScalars *s = scs[i];
+        DoneRec r;
+        r.done = s->done;
+        r.status = s->status;
+        r.iter = s->iter;
+        r.pad = 0;
+        r.rnorm2 = s->rnorm2;
+        r.gnorm2 = s->gnorm2;
+        out[i] = r;
+    }
+}
+}  // namespace tsf
+
+namespace {
+
+struct BatchGroup {
+    int64_t L = 0;
+    RT A, B;
+    std::vector<int> members;
+};
+
+// bump allocator mirroring a pinned host staging area onto a device area
+struct Stage {
+    char *host = nullptr, *dev = nullptr;
+    size_t cap = 0, used = 0;
+    template <class T> T *put(const std::vector<T> &v) {
+        const size_t off = used;
+        const size_t bytes = sizeof(T) * v.size();
+        used = (used + bytes + 255) & ~size_t(255);
+        if (used > cap) return nullptr;
+        std::memcpy(host + off, v.data(), bytes);
+        return reinterpret_cast<T *>(dev + off);
+    }
+};
+
+}  // namespace
+
+struct tsfcde_batch_s {
+    hipStream_t stream = nullptr;
+    int count = 0;
+    int64_t M = 0, level = 0;
+    int maxit = 500, warm = 0;
+    std::vector<tsfcde_plan_s *> plans;
+    std::vector<BatchGroup> groups;
+    Stage st;
+    DevScalars **d_scs = nullptr;
+    DoneRec *d_done = nullptr, *h_done = nullptr;
+    int last_iters = 8;
+};
+
+namespace {
+
+template <int R, int DIR, class In, class Out>
+hipError_t blaunch_col_t(tsfcde_batch_s *bt, int64_t C, const ColDesc<In, Out> *d, int cnt, int pred) {
+    using G = ColGeo<R, TSF_E_COL>;
+    hipLaunchKernelGGL((k_col_b<R, TSF_E_COL, DIR, In, Out>), dim3((unsigned)((C + G::B - 1) / G::B), cnt),
+                       dim3(G::NT), 0, bt->stream, d, bt->plans[0]->tw_all, pred);
+    return hipGetLastError();
+}
+
+template <int DIR, class In, class Out>
+hipError_t blaunch_col(tsfcde_batch_s *bt, const RT &rt, const ColDesc<In, Out> *d, int cnt, int pred) {
+    if (!d) return hipErrorOutOfMemory;
+    switch (rt.R) {
+#define TSF_CASE(P) \
+    case P: return blaunch_col_t<P, DIR>(bt, rt.C, d, cnt, pred);
+        TSF_SIZES(TSF_CASE)
+#undef TSF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int C_, int MODE>
+hipError_t blaunch_mid_t(tsfcde_batch_s *bt, const RT &rt, const MidDesc *d, int cnt, int pred) {
+    using G = MidGeo<C_, TSF_E_MID>;
+    hipLaunchKernelGGL((k_mid_b<C_, TSF_E_MID, MODE>), dim3((unsigned)(rt.R / 2), cnt), dim3(G::NT), 0, bt->stream,
+                       d, bt->plans[0]->tw_all, pred);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t blaunch_mid(tsfcde_batch_s *bt, const RT &rt, const MidDesc *d, int cnt, int pred) {
+    if (!d) return hipErrorOutOfMemory;
+    switch (rt.C) {
+#define TSF_CASE(P) \
+    case P: return blaunch_mid_t<P, MODE>(bt, rt, d, cnt, pred);
+        TSF_SIZES(TSF_CASE)
+#undef TSF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int C_>
+hipError_t blaunch_row_t(tsfcde_batch_s *bt, const RT &rt, const RowDesc *d, int cnt) {
+    using G = RowGeo<C_, TSF_E_MID>;
+    hipLaunchKernelGGL((k_row_b<C_, TSF_E_MID, 3>), dim3((unsigned)rt.R, cnt), dim3(G::NT), 0, bt->stream, d,
+                       bt->plans[0]->tw_all);
+    return hipGetLastError();
+}
+
+hipError_t blaunch_row(tsfcde_batch_s *bt, const RT &rt, const RowDesc *d, int cnt) {
+    if (!d) return hipErrorOutOfMemory;
+    switch (rt.C) {
+#define TSF_CASE(P) \
+    case P: return blaunch_row_t<P>(bt, rt, d, cnt);
+        TSF_SIZES(TSF_CASE)
+#undef TSF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class In, class Out> ColDesc<In, Out> cdesc(tsfcde_plan_s *pl, int64_t C, In in, Out out) {
+    return ColDesc<In, Out>{C, in, out, pl->sc};
+}
+
+template <class Out> Out nored(Out o) {
+    o.partials = nullptr;
+    o.counter = nullptr;
+    return o;
+}
+
+// The descriptors of one group for level j, staged for upload.
+struct GroupDesc {
+    ColDesc<InReal, OutSpec> *rhsA, *rstA, *r2cA, *s4;
+    ColDesc<InSpec, OutRhs> *rhsC;
+    ColDesc<InSpec, OutRestart> *rstC;
+    MidDesc *midA, *midR2C, *midP;
+    ColDesc<InCplx, OutSpec> *bsA;
+    RowDesc *bsRow;
+    ColDesc<InSpec, OutCplx> *bsC;
+    ColDesc<InCgsUP, OutSpec> *s1;
+    ColDesc<InSpec, OutReal> *s3, *s9;
+    ColDesc<InSpec, OutCgsDot> *s6;
+    ColDesc<InCgsQ, OutSpec> *s7;
+    ColDesc<InCgsX, OutSpec> *s10;
+    ColDesc<InSpec, OutCgsR> *s12;
+};
+
+bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const double *const *d_f, int warm,
+                 GroupDesc &D) {
+    std::vector<ColDesc<InReal, OutSpec>> rhsA, rstA, r2cA, s4;
+    std::vector<ColDesc<InSpec, OutRhs>> rhsC;
+    std::vector<ColDesc<InSpec, OutRestart>> rstC;
+    std::vector<MidDesc> midA, midR2C, midP;
+    std::vector<ColDesc<InCplx, OutSpec>> bsA;
+    std::vector<RowDesc> bsRow;
+    std::vector<ColDesc<InSpec, OutCplx>> bsC;
+    std::vector<ColDesc<InCgsUP, OutSpec>> s1;
+    std::vector<ColDesc<InSpec, OutReal>> s3, s9;
+    std::vector<ColDesc<InSpec, OutCgsDot>> s6;
+    std::vector<ColDesc<InCgsQ, OutSpec>> s7;
+    std::vector<ColDesc<InCgsX, OutSpec>> s10;
+    std::vector<ColDesc<InSpec, OutCgsR>> s12;
+    for (int idx : g.members) {
+        tsfcde_plan_s *pl = bt->plans[idx];
+        const int64_t n = pl->n, ld = pl->ldn, C = pl->A.C, CB = pl->B.C;
+        double *x = pl->U + (size_t)(j + 1) * ld;
+        const double *f = d_f ? d_f[idx] : nullptr;
+        const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
+        const SymParams sI = unit_symbol(pl->A);
+        OutSpec osA = out_spec(pl, pl->A);
+        InSpec isA = in_spec(pl, pl->A);
+        // right-hand side through A u^j
+        rhsA.push_back(cdesc(pl, C, InReal{pl->U + (size_t)j * ld, n, C}, osA));
+        OutRhs orhs{pl->U + (size_t)j * ld, pl->H, f, pl->g, pl->r, pl->rt, x, n, C, pl->eta[j] / pl->sigma,
+                    (1.0 - pl->sigma) / pl->sigma, warm, j >= 1 ? 1 : 0,
+                    j >= 2 ? pl->U + (size_t)(j - 1) * ld : nullptr, j >= 2 ? pl->U + (size_t)(j - 2) * ld : nullptr};
+        rhsC.push_back(cdesc(pl, C, isA, with_red(orhs, pl, 2)));
+        midA.push_back(MidDesc{pl->A.R, pl->buf, pl->specA, nullptr, pl->A.tw, sA, pl->sc});
+        // restart from an extrapolated guess
+        rstA.push_back(cdesc(pl, C, InReal{x, n, C}, osA));
+        rstC.push_back(cdesc(pl, C, isA, with_red(OutRestart{pl->g, pl->r, pl->rt, n, C}, pl, 3)));
+        // inverse Strang circulant of level j: Bluestein DFT and embedding spectrum
+        OutSpec osB{pl->bufB, pl->B.tw, CB};
+        bsA.push_back(cdesc(pl, CB, InCplx{pl->wv, nullptr, pl->chirp, n, CB}, nored(osB)));
+        bsRow.push_back(RowDesc{pl->bufB, pl->Bhat, nullptr});
+        bsC.push_back(cdesc(pl, CB, InSpec{pl->bufB, pl->B.tw, CB}, nored(OutCplx{pl->Wt, pl->chirp, n, CB})));
+        r2cA.push_back(cdesc(pl, C, InReal{pl->tmp, pl->A.L, C}, osA));
+        midR2C.push_back(MidDesc{pl->A.R, pl->buf, nullptr, pl->specPj, pl->A.tw, SymParams{}, pl->sc});
+        midP.push_back(MidDesc{pl->A.R, pl->buf, pl->specPj, nullptr, pl->A.tw, sI, pl->sc});
+        // CGS iteration
+        s1.push_back(cdesc(pl, C, InCgsUP{pl->r, pl->u, pl->p, pl->q, n, C, 0.0, false}, osA));
+        s3.push_back(cdesc(pl, C, isA, nored(OutReal{pl->phat, n, C})));
+        s4.push_back(cdesc(pl, C, InReal{pl->phat, n, C}, osA));
+        s6.push_back(cdesc(pl, C, isA, with_red(OutCgsDot{pl->vhat, pl->rt, n, C}, pl, 0)));
+        s7.push_back(cdesc(pl, C, InCgsQ{pl->u, pl->vhat, pl->q, n, C, 0.0}, osA));
+        s9.push_back(cdesc(pl, C, isA, nored(OutReal{pl->uhat, n, C})));
+        s10.push_back(cdesc(pl, C, InCgsX{pl->uhat, x, n, C, 0.0}, osA));
+        s12.push_back(cdesc(pl, C, isA, with_red(OutCgsR{pl->r, pl->rt, n, C, 0.0}, pl, 1)));
+    }
+    Stage &S = bt->st;
+    D.rhsA = S.put(rhsA);
+    D.rhsC = S.put(rhsC);
+    D.midA = S.put(midA);
+    D.rstA = S.put(rstA);
+    D.rstC = S.put(rstC);
+    D.bsA = S.put(bsA);
+    D.bsRow = S.put(bsRow);
+    D.bsC = S.put(bsC);
+    D.r2cA = S.put(r2cA);
+    D.midR2C = S.put(midR2C);
+    D.midP = S.put(midP);
+    D.s1 = S.put(s1);
+    D.s3 = S.put(s3);
+    D.s4 = S.put(s4);
+    D.s6 = S.put(s6);
+    D.s7 = S.put(s7);
+    D.s9 = S.put(s9);
+    D.s10 = S.put(s10);
+    D.s12 = S.put(s12);
+    return S.used <= S.cap;
+}
+
+int batch_poll(tsfcde_batch_s *bt) {
+    hipLaunchKernelGGL(k_gather_state, dim3((bt->count + 255) / 256), dim3(256), 0, bt->stream, bt->d_scs, bt->count,
+                       bt->d_done);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(bt->h_done, bt->d_done, sizeof(DoneRec) * bt->count, hipMemcpyDeviceToHost, bt->stream));
+    HIPCHK(hipStreamSynchronize(bt->stream));
+    return TSFCDE_OK;
+}
+
+#define BCHK(x)                                             \
+    do {                                                    \
+        hipError_t e_ = (x);                                \
+        if (e_ != hipSuccess) return TSFCDE_EDEVICE;        \
+    } while (0)
+
+int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats) {
+    if (bt->level >= bt->M) return TSFCDE_EDONE;
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t j = bt->level;
+    const int cnt = bt->count;
+    // sources that are not 16-byte aligned go through each plan's own buffer
+    std::vector<const double *> fptr(cnt, nullptr);
+    for (int i = 0; i < cnt; ++i) {
+        const double *f = d_f ? d_f[i] : nullptr;
+        tsfcde_plan_s *pl = bt->plans[i];
+        if (f && (reinterpret_cast<uintptr_t>(f) & 15)) {
+            hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, bt->stream, f, pl->fbuf, pl->n);
+            f = pl->fbuf;
+        }
+        fptr[i] = f;
+    }
+    const int warm = bt->warm == TSFCDE_WS_PREV ? 1 : (bt->warm == TSFCDE_WS_EXTRAP ? (j >= 2 ? 2 : (j >= 1)) : 0);
+    // descriptors of the level
+    bt->st.used = 0;
+    std::vector<HistDesc> hist;
+    std::vector<PcDesc> pc;
+    int64_t nmax = 0, Lmax = 0;
+    for (tsfcde_plan_s *pl : bt->plans) {
+        hist.push_back(HistDesc{pl->U, pl->n, pl->ldn, pl->cb, j >= 1 ? pl->clast[j] : 0.0, pl->kappa, pl->H, (int)j});
+        pc.push_back(PcDesc{pl->Ls, pl->wv, pl->Wt, pl->tmp, pl->n, pl->A.L, symbol(pl, j, -pl->sigma, pl->A, false)});
+        nmax = std::max(nmax, pl->n);
+        Lmax = std::max(Lmax, pl->A.L);
+    }
+    HistDesc *dh = bt->st.put(hist);
+    PcDesc *dpc = bt->st.put(pc);
+    std::vector<GroupDesc> gd(bt->groups.size());
+    for (size_t g = 0; g < bt->groups.size(); ++g)
+        if (!stage_group(bt, bt->groups[g], j, fptr.data(), warm, gd[g])) return TSFCDE_ENOMEM;
+    if (!dh || !dpc || bt->st.used > bt->st.cap) return TSFCDE_ENOMEM;
+    BCHK(hipMemcpyAsync(bt->st.dev, bt->st.host, bt->st.used, hipMemcpyHostToDevice, bt->stream));
+    // history sums, right-hand sides, initial guesses
+    if (j >= 1) {
+        const unsigned gx = (unsigned)std::min<int64_t>(1024, ((nmax + 1) / 2 + 255) / 256);
+        hipLaunchKernelGGL(k_history_b, dim3(gx, cnt), dim3(256), 0, bt->stream, dh);
+        BCHK(hipGetLastError());
+    }
+    for (size_t g = 0; g < bt->groups.size(); ++g) {
+        const BatchGroup &G = bt->groups[g];
+        const int c = (int)G.members.size();
+        BCHK(blaunch_col<-1>(bt, G.A, gd[g].rhsA, c, 0));
+        BCHK(blaunch_mid<0>(bt, G.A, gd[g].midA, c, 0));
+        BCHK(blaunch_col<1>(bt, G.A, gd[g].rhsC, c, 0));
+        if (warm == 2) {
+            BCHK(blaunch_col<-1>(bt, G.A, gd[g].rstA, c, 0));
+            BCHK(blaunch_mid<0>(bt, G.A, gd[g].midA, c, 0));
+            BCHK(blaunch_col<1>(bt, G.A, gd[g].rstC, c, 0));
+        }
+    }
+    // inverse Strang circulants of the level
+    hipLaunchKernelGGL(k_pc_column_b, dim3((unsigned)std::min<int64_t>(256, (nmax + 255) / 256), cnt), dim3(256), 0,
+                       bt->stream, dpc);
+    BCHK(hipGetLastError());
+    for (size_t g = 0; g < bt->groups.size(); ++g) {
+        const BatchGroup &G = bt->groups[g];
+        const int c = (int)G.members.size();
+        BCHK(blaunch_col<-1>(bt, G.B, gd[g].bsA, c, 0));
+        BCHK(blaunch_row(bt, G.B, gd[g].bsRow, c));
+        BCHK(blaunch_col<1>(bt, G.B, gd[g].bsC, c, 0));
+    }
+    hipLaunchKernelGGL(k_pc_embed_b, dim3((unsigned)std::min<int64_t>(256, (Lmax + 255) / 256), cnt), dim3(256), 0,
+                       bt->stream, dpc);
+    BCHK(hipGetLastError());
+    for (size_t g = 0; g < bt->groups.size(); ++g) {
+        const BatchGroup &G = bt->groups[g];
+        const int c = (int)G.members.size();
+        BCHK(blaunch_col<-1>(bt, G.A, gd[g].r2cA, c, 0));
+        BCHK(blaunch_mid<2>(bt, G.A, gd[g].midR2C, c, 0));
+    }
+    for (tsfcde_plan_s *pl : bt->plans) pl->pj_level = j;
+    // CGS, every instance on its own convergence flag
+    int iters_seen = 0, chunk = std::max(2, bt->last_iters);
+    for (;;) {
+        const int todo = std::min(chunk, bt->maxit - iters_seen);
+        if (todo <= 0) break;
+        for (int k = 0; k < todo; ++k) {
+            for (size_t g = 0; g < bt->groups.size(); ++g) {
+                const BatchGroup &G = bt->groups[g];
+                const int c = (int)G.members.size();
+                const GroupDesc &D = gd[g];
+                BCHK(blaunch_col<-1>(bt, G.A, D.s1, c, 1));
+                BCHK(blaunch_mid<0>(bt, G.A, D.midP, c, 1));
+                BCHK(blaunch_col<1>(bt, G.A, D.s3, c, 1));
+                BCHK(blaunch_col<-1>(bt, G.A, D.s4, c, 1));
+                BCHK(blaunch_mid<0>(bt, G.A, D.midA, c, 1));
+                BCHK(blaunch_col<1>(bt, G.A, D.s6, c, 1));
+                BCHK(blaunch_col<-1>(bt, G.A, D.s7, c, 1));
+                BCHK(blaunch_mid<0>(bt, G.A, D.midP, c, 1));
+                BCHK(blaunch_col<1>(bt, G.A, D.s9, c, 1));
+                BCHK(blaunch_col<-1>(bt, G.A, D.s10, c, 1));
+                BCHK(blaunch_mid<0>(bt, G.A, D.midA, c, 1));
+                BCHK(blaunch_col<1>(bt, G.A, D.s12, c, 1));
+            }
+        }
+        int rc = batch_poll(bt);
+        if (rc) return rc;
+        bool all = true;
+        int maxiter = 0;
+        for (int i = 0; i < cnt; ++i) {
+            all = all && bt->h_done[i].done;
+            maxiter = std::max(maxiter, bt->h_done[i].iter);
+        }
+        iters_seen = maxiter;
+        if (all) break;
+        chunk = 2;
+    }
+    int code = TSFCDE_OK, maxiter = 0;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < cnt; ++i) {
+        const DoneRec &r = bt->h_done[i];
+        int ci = !r.done ? TSFCDE_ENOCONV : status_code(r.status);
+        if (ci && !code) code = ci;
+        maxiter = std::max(maxiter, r.iter);
+        bt->plans[i]->level = j + 1;
+        if (stats) {
+            tsfcde_stats &s = stats[i];
+            s.iters = r.iter;
+            s.outer_iters = 1;
+            s.restarts = 0;
+            s.status = ci;
+            s.relres = r.gnorm2 > 0 ? std::sqrt(r.rnorm2 / r.gnorm2) : 0.0;
+            s.relres_true = -1.0;
+            s.backward_err = -1.0;
+            s.seconds = secs;
+        }
+    }
+    bt->last_iters = std::max(1, maxiter);
+    bt->level = j + 1;
+    return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsfcde_batch_workspace_bytes(const tsfcde_problem *probs, int32_t count, size_t *bytes) {
+    if (!probs || count < 1 || !bytes) return TSFCDE_EINVAL;
+    size_t tot = 0;
+    for (int i = 0; i < count; ++i) {
+        size_t b = 0;
+        int rc = workspace_bytes_impl(&probs[i], true, &b);
+        if (rc) return rc;
+        if (probs[i].M != probs[0].M) return TSFCDE_EINVAL;
+        tot += al(b);
+    }
+    // descriptors (per level), scalar pointers, gathered states
+    tot += al((size_t)count * 8192 + (1 << 20)) + al(sizeof(void *) * count) + al(sizeof(DoneRec) * count);
+    *bytes = tot;
+    return TSFCDE_OK;
+}
+
+int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_workspace, size_t bytes, void *stream,
+                      tsfcde_batch_t *out) {
+    if (!out) return TSFCDE_EINVAL;
+    *out = nullptr;
+    size_t need = 0;
+    int rc = tsfcde_batch_workspace_bytes(probs, count, &need);
+    if (rc) return rc;
+    if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255)) return TSFCDE_EINVAL;
+    if (bytes < need) return TSFCDE_ENOMEM;
+    tsfcde_batch_s *bt = new (std::nothrow) tsfcde_batch_s();
+    if (!bt) return TSFCDE_ENOMEM;
+    bt->stream = reinterpret_cast<hipStream_t>(stream);
+    bt->count = count;
+    bt->M = probs[0].M;
+    bt->maxit = probs[0].maxit > 0 ? probs[0].maxit : 500;
+    bt->warm = probs[0].warm_start;
+    char *ws = reinterpret_cast<char *>(d_workspace);
+    size_t off = 0;
+    auto fail = [&](int code) {
+        for (tsfcde_plan_s *pl : bt->plans) tsfcde_destroy(pl);
+        if (bt->st.host) (void)hipHostFree(bt->st.host);
+        if (bt->h_done) (void)hipHostFree(bt->h_done);
+        delete bt;
+        return code;
+    };
+    for (int i = 0; i < count; ++i) {
+        size_t b = 0;
+        workspace_bytes_impl(&probs[i], true, &b);
+        tsfcde_plan_t pl = nullptr;
+        rc = plan_create(&probs[i], ws + off, b, stream, true, &pl);
+        if (rc) return fail(rc);
+        bt->plans.push_back(pl);
+        off += al(b);
+    }
+    bt->st.cap = (size_t)count * 8192 + (1 << 20);
+    bt->st.dev = ws + off;
+    off += al(bt->st.cap);
+    bt->d_scs = reinterpret_cast<DevScalars **>(ws + off);
+    off += al(sizeof(void *) * count);
+    bt->d_done = reinterpret_cast<DoneRec *>(ws + off);
+    if (hipHostMalloc(reinterpret_cast<void **>(&bt->st.host), bt->st.cap) != hipSuccess) return fail(TSFCDE_EDEVICE);
+    if (hipHostMalloc(reinterpret_cast<void **>(&bt->h_done), sizeof(DoneRec) * count) != hipSuccess)
+        return fail(TSFCDE_EDEVICE);
+    std::vector<DevScalars *> scs;
+    for (tsfcde_plan_s *pl : bt->plans) scs.push_back(pl->sc);
+    std::memcpy(bt->st.host, scs.data(), sizeof(void *) * count);
+    if (hipMemcpyAsync(bt->d_scs, bt->st.host, sizeof(void *) * count, hipMemcpyHostToDevice, bt->stream) !=
+        hipSuccess)
+        return fail(TSFCDE_EDEVICE);
+    if (hipStreamSynchronize(bt->stream) != hipSuccess) return fail(TSFCDE_EDEVICE);
+    // groups by embedding length
+    for (int i = 0; i < count; ++i) {
+        tsfcde_plan_s *pl = bt->plans[i];
+        auto it = std::find_if(bt->groups.begin(), bt->groups.end(),
+                               [&](const BatchGroup &g) { return g.L == pl->A.L; });
+        if (it == bt->groups.end()) {
+            BatchGroup g;
+            g.L = pl->A.L;
+            g.A = pl->A;
+            g.B = pl->B;
+            bt->groups.push_back(g);
+            it = bt->groups.end() - 1;
+        }
+        it->members.push_back(i);
+    }
+    *out = bt;
+    return TSFCDE_OK;
+}
+
+tsfcde_plan_t tsfcde_batch_member(tsfcde_batch_t bt, int32_t i) {
+    if (!bt || i < 0 || i >= bt->count) return nullptr;
+    return bt->plans[i];
+}
+
+int tsfcde_batch_step(tsfcde_batch_t bt, const double *const *d_f, tsfcde_stats *stats) {
+    if (!bt) return TSFCDE_EINVAL;
+    for (tsfcde_plan_s *pl : bt->plans)
+        if (pl->level != bt->level) return TSFCDE_EINVAL;
+    return batch_step(bt, d_f, stats);
+}
+
+int tsfcde_batch_set_level(tsfcde_batch_t bt, int64_t level) {
+    if (!bt || level < 0 || level > bt->M) return TSFCDE_EINVAL;
+    for (tsfcde_plan_s *pl : bt->plans)
+        if (pl->level != level) return TSFCDE_EINVAL;
+    bt->level = level;
+    return TSFCDE_OK;
+}
+
+int tsfcde_batch_destroy(tsfcde_batch_t bt) {
+    if (!bt) return TSFCDE_EINVAL;
+    (void)hipStreamSynchronize(bt->stream);
+    for (tsfcde_plan_s *pl : bt->plans) tsfcde_destroy(pl);
+    if (bt->st.host) (void)hipHostFree(bt->st.host);
+    if (bt->h_done) (void)hipHostFree(bt->h_done);
+    delete bt;
+    return TSFCDE_OK;
 }
 
 }  // extern "C"

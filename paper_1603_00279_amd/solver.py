@@ -168,3 +168,96 @@ class TimeLevelSolver:
         N.check(self._lib.tsfcde_profile_read(self._plan, kernel_class, ctypes.byref(cnt), ctypes.byref(ms)),
                 "tsfcde_profile_read")
         return cnt.value, ms.value
+
+
+class BatchSolver:
+    """Many independent instances advanced level by level with grouped
+    launches (tsfcde_plan_batch / tsfcde_batch_step).  ``problems`` are
+    objects with alpha, beta, n, M, a, b, T, coefficient_samples() and
+    initial_vector(); all share M."""
+
+    def __init__(self, problems, *, rtol: float = 1e-10, maxit: int = 500, warm_start: int = N.TSFCDE_WS_ZERO,
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+        self._lib = N.lib()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.count = len(problems)
+        self.M = problems[0].M
+        self.ns = [p.n for p in problems]
+        dptr = ctypes.POINTER(ctypes.c_double)
+        self._keep = []
+        arr = (N.tsfcde_problem * self.count)()
+        for i, prob in enumerate(problems):
+            g, dp, dm = (np.ascontiguousarray(v, dtype=np.float64) for v in prob.coefficient_samples())
+            self._keep += [g, dp, dm]
+            arr[i] = N.tsfcde_problem(
+                alpha=prob.alpha, beta=prob.beta, a=prob.a, b=prob.b, T=prob.T, n=prob.n, M=prob.M,
+                gamma=N.COEF_FN(), dplus=N.COEF_FN(), dminus=N.COEF_FN(), coef_user=None,
+                gamma_at=g.ctypes.data_as(dptr), dplus_at=dp.ctypes.data_as(dptr), dminus_at=dm.ctypes.data_as(dptr),
+                phi=N.IC_FN(), phi_user=None, rtol=rtol, maxit=maxit, precision=N.TSFCDE_FP64,
+                warm_start=warm_start, flags=0)
+        self._arr = arr
+        nbytes = ctypes.c_size_t(0)
+        N.check(self._lib.tsfcde_batch_workspace_bytes(arr, self.count, ctypes.byref(nbytes)),
+                "tsfcde_batch_workspace_bytes")
+        self.workspace_bytes = nbytes.value
+        self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            N.check(self._lib.tsfcde_plan_batch(arr, self.count, ctypes.c_void_p(base + off), self.workspace_bytes,
+                                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)),
+                    "tsfcde_plan_batch")
+        self._batch = handle
+        for i, prob in enumerate(problems):
+            u0 = torch.as_tensor(prob.initial_vector(), dtype=torch.float64, device=self.device)
+            N.check(self._lib.tsfcde_set_state(self.member(i), 0, ctypes.c_void_p(u0.data_ptr())), "tsfcde_set_state")
+        torch.cuda.synchronize(self.device)
+
+    def member(self, i: int):
+        return self._lib.tsfcde_batch_member(self._batch, i)
+
+    def history(self, i: int) -> torch.Tensor:
+        """Copy of instance i's stored levels ((M+1) x n)."""
+        h = self.member(i)
+        ptr = self._lib.tsfcde_history(h)
+        ld = int(self._lib.tsfcde_history_ld(h))
+        n = self.ns[i]
+        off = ptr - self._ws.data_ptr()
+        flat = self._ws[off: off + 8 * (self.M + 1) * ld].view(torch.float64)
+        return flat.view(self.M + 1, ld)[:, :n].clone()
+
+    def reset(self, u0s):
+        """Set every instance back to level 0 with the given initial vectors."""
+        for i, u0 in enumerate(u0s):
+            N.check(self._lib.tsfcde_set_state(self.member(i), 0, ctypes.c_void_p(u0.data_ptr())), "tsfcde_set_state")
+        N.check(self._lib.tsfcde_batch_set_level(self._batch, 0), "tsfcde_batch_set_level")
+
+    def step(self, fs=None, raise_on_error=True):
+        """fs: list of device tensors (f of each instance at this level) or None."""
+        ptrs = None
+        if fs is not None:
+            ptrs = (ctypes.c_void_p * self.count)(*[f.data_ptr() if f is not None else None for f in fs])
+        stats = (N.tsfcde_stats * self.count)()
+        code = self._lib.tsfcde_batch_step(self._batch, ptrs, stats)
+        if raise_on_error:
+            N.check(code, "tsfcde_batch_step")
+        return code, [st.as_dict() for st in stats]
+
+    def close(self):
+        if getattr(self, "_batch", None):
+            self._lib.tsfcde_batch_destroy(self._batch)
+            self._batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
