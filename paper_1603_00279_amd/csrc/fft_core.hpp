@@ -129,7 +129,8 @@ __device__ __forceinline__ void stage_bfly(double2 (&v)[E], int j, const double2
 // canonical register layout.  Intermediate results are exchanged through the
 // LDS slab `lds` (element p at lds[lpad(p) * LS]; several transforms may
 // share a slab, interleaved with stride LS).  The outputs of the last stage
-// are handed to sink(pos, value) (natural frequency order pos).  Every lane
+// are handed to sink(pos, value, slot) (natural frequency order pos; slot is
+// the register index m of the value, see LastStage).  Every lane
 // of the workgroup must call this (it contains barriers); lanes with
 // active == false only take part in the barriers.
 template <int P, int E, int NS, int DIR, int TS, class Sink>
@@ -147,7 +148,7 @@ __device__ __forceinline__ void fft_stages(double2 (&v)[E], int j, bool active, 
                 const int bf = j + T * q;
                 const int base = (bf & ~(NS - 1)) * RAD + (bf & (NS - 1));
 #pragma unroll
-                for (int r = 0; r < RAD; ++r) sink(base + r * NS, v[q + NB * r]);
+                for (int r = 0; r < RAD; ++r) sink(base + r * NS, v[q + NB * r], q + NB * r);
             }
         }
     } else {
@@ -169,6 +170,25 @@ __device__ __forceinline__ void fft_stages(double2 (&v)[E], int j, bool active, 
         fft_stages<P, E, NS * RAD, DIR, TS>(v, j, active, twP, lds, LS, sink);
     }
 }
+
+// Where the last stage of a length-P transform at E values per lane puts its
+// outputs: value slot m of lane j goes to natural-order position pos(j, m).
+// Callers use it to fetch, before the transform starts, the operands that the
+// sink will combine with each output (so no load waits behind the stores).
+template <int P, int E> struct LastStage {
+    static constexpr int rad_at(int ns) { return (P / ns >= E) ? E : P / ns; }
+    static constexpr int ns_last() {
+        int ns = 1;
+        while (ns * rad_at(ns) < P) ns *= rad_at(ns);
+        return ns;
+    }
+    static constexpr int NS = ns_last(), RAD = rad_at(NS), NB = E / RAD, T = P / E;
+    static __device__ __forceinline__ int pos(int j, int m) {
+        const int q = m % NB, r = m / NB;
+        const int bf = j + T * q;
+        return (bf & ~(NS - 1)) * RAD + (bf & (NS - 1)) + r * NS;
+    }
+};
 
 // Transform with twiddles from the packed global table.
 template <int P, int E, int DIR, class Sink>
@@ -196,7 +216,7 @@ __device__ __forceinline__ void stage_twiddles(double2 *dst, const double2 *__re
 struct LdsSink {
     double2 *lds;
     int LS;
-    __device__ __forceinline__ void operator()(int pos, double2 val) const { lds[lpad(pos) * LS] = val; }
+    __device__ __forceinline__ void operator()(int pos, double2 val, int) const { lds[lpad(pos) * LS] = val; }
 };
 
 // Two-level twiddle table for exp(-2 pi i m / L), m < L:
@@ -207,6 +227,11 @@ struct Tw2 {
     int shift;
     __device__ __forceinline__ double2 operator()(int64_t m) const {
         return cmul(hi[m >> shift], lo[m & ((int64_t(1) << shift) - 1)]);
+    }
+    // the two table entries of w(m), loaded without combining them
+    __device__ __forceinline__ void fetch(int64_t m, double2 *hl) const {
+        hl[0] = hi[m >> shift];
+        hl[1] = lo[m & ((int64_t(1) << shift) - 1)];
     }
 };
 

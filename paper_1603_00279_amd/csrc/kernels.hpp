@@ -30,7 +30,6 @@ struct DevScalars {
     double rho, rho_prev, alpha, beta, rtv, rnorm2, gnorm2, tol2;
     double aux0, aux1, rtol2, pad0;
     int iter, done, status, fresh;  // fresh: next CGS iteration starts from r (u = p = r)
-    unsigned int cnt[8];  // arrival counters of the last-workgroup reductions
 };
 
 enum : int { ST_OK = 0, ST_BREAKDOWN = 1, ST_NONFINITE = 2 };
@@ -43,14 +42,17 @@ struct SymParams {
 };
 
 // ---------------------------------------------------------------------------
-// Reductions: wave64 shuffles, then LDS across waves, then the last workgroup
-// sums the per-workgroup partials in index order.
+// Reductions in two launches: each workgroup of a pass sums its lanes (wave64
+// shuffles, then LDS across waves) and stores one partial per accumulator;
+// a one-workgroup finishing kernel then sums the partials in index order.
+// The kernel boundary makes the partials visible, so no device-scope fence
+// (which on gfx950 writes back and invalidates the XCD's L2) is needed.  The
+// finishing kernel runs with the pass's own thread count, so the summation
+// order is fixed by the pass geometry alone and results are reproducible.
 // ---------------------------------------------------------------------------
 template <int NACC>
-__device__ __forceinline__ bool block_reduce_last(double (&acc)[NACC], double *partials, unsigned *counter,
-                                                  double (&tot)[NACC]) {
+__device__ __forceinline__ void block_partial(double (&acc)[NACC], double *partials) {
     __shared__ double red[NACC][16];
-    __shared__ int is_last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwave = (blockDim.x + 63) >> 6;
 #pragma unroll
@@ -66,25 +68,25 @@ __device__ __forceinline__ bool block_reduce_last(double (&acc)[NACC], double *p
         for (int a = 0; a < NACC; ++a) {
             double s = 0.0;
             for (int w = 0; w < nwave; ++w) s += red[a][w];
-            __hip_atomic_store(&partials[(size_t)blockIdx.x * NACC + a], s, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            partials[(size_t)blockIdx.x * NACC + a] = s;
         }
-        __threadfence();
-        unsigned prev = atomicAdd(counter, 1u);
-        is_last = (prev == gridDim.x - 1);
     }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
+}
+
+// Sum of nparts partials (every thread of the workgroup takes part; the
+// result is valid in thread 0).
+template <int NACC>
+__device__ __forceinline__ void reduce_partials(const double *partials, int nparts, double (&tot)[NACC]) {
+    __shared__ double red[NACC][16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwave = (blockDim.x + 63) >> 6;
     double loc[NACC];
 #pragma unroll
     for (int a = 0; a < NACC; ++a) loc[a] = 0.0;
-    for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
 #pragma unroll
-        for (int a = 0; a < NACC; ++a)
-            loc[a] += __hip_atomic_load(&partials[(size_t)i * NACC + a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int a = 0; a < NACC; ++a) loc[a] += partials[(size_t)i * NACC + a];
     }
-    __syncthreads();
 #pragma unroll
     for (int a = 0; a < NACC; ++a) {
         double v = loc[a];
@@ -99,8 +101,6 @@ __device__ __forceinline__ bool block_reduce_last(double (&acc)[NACC], double *p
         for (int w = 0; w < nwave; ++w) s += red[a][w];
         tot[a] = s;
     }
-    if (threadIdx.x == 0) *counter = 0u;
-    return true;
 }
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
@@ -118,16 +118,22 @@ __device__ __forceinline__ void st2(double *p, int64_t i, int64_t nr, double2 v)
 }
 
 // ---------------------------------------------------------------------------
-// Pass-A loaders (forward column pass).  load(row, col) returns packed
-// element m = row*C + col of the real input, z[m] = x[2m] + i x[2m+1].
+// Pass-A loaders (forward column pass).  They return packed element
+// m = row*C + col of the real input, z[m] = x[2m] + i x[2m+1], in two phases:
+// fetch(row, col, raw) only issues the NL loads of the element, and
+// finish(row, col, raw) combines them, makes the loader's own stores and
+// returns z[m].  A pass fetches all its elements before finishing any, so no
+// load waits behind a store that might alias it.
 // ---------------------------------------------------------------------------
 struct InReal {  // plain real vector, zero beyond nr values
     const double *x;
     int64_t nr, C;
+    static constexpr int NL = 1;
     __device__ void prep(const DevScalars *) {}
-    __device__ __forceinline__ double2 load(int row, int64_t col) const {
-        return ld2(x, 2 * (row * C + col), nr);
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
+        raw[0] = ld2(x, 2 * (row * C + col), nr);
     }
+    __device__ __forceinline__ double2 finish(int, int64_t, const double2 *raw) const { return raw[0]; }
 };
 
 // CGS: u = r + beta q ; p = u + beta (q + beta p) (first iteration: u = p = r);
@@ -143,17 +149,27 @@ struct InCgsUP {
         first = sc->fresh != 0;
         beta = sc->beta;
     }
-    __device__ __forceinline__ double2 load(int row, int64_t col) {
+    static constexpr int NL = 3;
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
+        int64_t i = 2 * (row * C + col);
+        if (i >= nr) return;
+        raw[0] = ld2(r, i, nr);
+        if (!first) {
+            raw[1] = ld2(q, i, nr);
+            raw[2] = ld2(p, i, nr);
+        }
+    }
+    __device__ __forceinline__ double2 finish(int row, int64_t col, const double2 *raw) const {
         int64_t i = 2 * (row * C + col);
         if (i >= nr) return make_double2(0.0, 0.0);
-        double2 rv = ld2(r, i, nr);
+        double2 rv = raw[0];
         double2 uv, pv;
         if (first) {
             uv = rv;
             pv = rv;
         } else {
-            double2 qv = ld2(q, i, nr);
-            double2 po = ld2(p, i, nr);
+            double2 qv = raw[1];
+            double2 po = raw[2];
             uv = make_double2(fma(beta, qv.x, rv.x), fma(beta, qv.y, rv.y));
             pv = make_double2(fma(beta, fma(beta, po.x, qv.x), uv.x), fma(beta, fma(beta, po.y, qv.y), uv.y));
         }
@@ -170,11 +186,18 @@ struct InCgsQ {
     int64_t nr, C;
     double alpha;
     __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
-    __device__ __forceinline__ double2 load(int row, int64_t col) {
+    static constexpr int NL = 2;
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
+        int64_t i = 2 * (row * C + col);
+        if (i >= nr) return;
+        raw[0] = ld2(u, i, nr);
+        raw[1] = ld2(vhat, i, nr);
+    }
+    __device__ __forceinline__ double2 finish(int row, int64_t col, const double2 *raw) const {
         int64_t i = 2 * (row * C + col);
         if (i >= nr) return make_double2(0.0, 0.0);
-        double2 uv = ld2(u, i, nr);
-        double2 vv = ld2(vhat, i, nr);
+        double2 uv = raw[0];
+        double2 vv = raw[1];
         double2 qv = make_double2(fma(-alpha, vv.x, uv.x), fma(-alpha, vv.y, uv.y));
         st2(q, i, nr, qv);
         return make_double2(uv.x + qv.x, uv.y + qv.y);
@@ -188,11 +211,18 @@ struct InCgsX {
     int64_t nr, C;
     double alpha;
     __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
-    __device__ __forceinline__ double2 load(int row, int64_t col) {
+    static constexpr int NL = 2;
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
+        int64_t i = 2 * (row * C + col);
+        if (i >= nr) return;
+        raw[0] = ld2(uhat, i, nr);
+        raw[1] = ld2(x, i, nr);
+    }
+    __device__ __forceinline__ double2 finish(int row, int64_t col, const double2 *raw) const {
         int64_t i = 2 * (row * C + col);
         if (i >= nr) return make_double2(0.0, 0.0);
-        double2 uh = ld2(uhat, i, nr);
-        double2 xv = ld2(x, i, nr);
+        double2 uh = raw[0];
+        double2 xv = raw[1];
         st2(x, i, nr, make_double2(fma(alpha, uh.x, xv.x), fma(alpha, uh.y, xv.y)));
         return uh;
     }
@@ -203,14 +233,16 @@ struct OutSpec {
     double2 *y;
     Tw2 tw;  // table for exp(-2 pi i m / L), L = 2N
     int64_t C;
-    static constexpr int NACC = 0;
+    static constexpr int NACC = 0, NPRE = 2;
     __device__ void prep(const DevScalars *) {}
-    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *) const {
-        y[row * C + col] = cmul(val, tw(2 * (int64_t)row * col));
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *pre) const {
+        tw.fetch(2 * (int64_t)row * col, pre);
+    }
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *, const double2 *pre) const {
+        y[row * C + col] = cmul(val, cmul(pre[0], pre[1]));
     }
     __device__ void final(const double *, DevScalars *) const {}
     double *partials;
-    unsigned *counter;
 };
 
 // ---------------------------------------------------------------------------
@@ -220,23 +252,28 @@ struct InSpec {
     const double2 *y;
     Tw2 tw;
     int64_t C;
+    static constexpr int NL = 3;
     __device__ void prep(const DevScalars *) {}
-    __device__ __forceinline__ double2 load(int row, int64_t col) const {
-        return cmul(y[row * C + col], cconj(tw(2 * (int64_t)row * col)));
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
+        raw[0] = y[row * C + col];
+        tw.fetch(2 * (int64_t)row * col, raw + 1);
+    }
+    __device__ __forceinline__ double2 finish(int, int64_t, const double2 *raw) const {
+        return cmul(raw[0], cconj(cmul(raw[1], raw[2])));
     }
 };
 
 struct OutReal {  // x[2m], x[2m+1] for 2m < nr
     double *x;
     int64_t nr, C;
-    static constexpr int NACC = 0;
+    static constexpr int NACC = 0, NPRE = 0;
     __device__ void prep(const DevScalars *) {}
-    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *) const {
+    __device__ __forceinline__ void fetch(int, int64_t, double2 *) const {}
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *, const double2 *) const {
         st2(x, 2 * (row * C + col), nr, val);
     }
     __device__ void final(const double *, DevScalars *) const {}
     double *partials;
-    unsigned *counter;
 };
 
 // vhat = A phat; accumulates rt . vhat; the last workgroup sets alpha = rho / (rt . vhat).
@@ -244,14 +281,18 @@ struct OutCgsDot {
     double *vhat;
     const double *rt;
     int64_t nr, C;
-    static constexpr int NACC = 1;
+    static constexpr int NACC = 1, NPRE = 1;
     __device__ void prep(const DevScalars *) {}
-    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *pre) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) pre[0] = ld2(rt, i, nr);
+    }
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc, const double2 *pre) const {
         int64_t i = 2 * (row * C + col);
         if (i < nr) {
             if (i + 1 >= nr) val.y = 0.0;
             st2(vhat, i, nr, val);
-            double2 t = ld2(rt, i, nr);
+            double2 t = pre[0];
             acc[0] = fma(t.x, val.x, fma(t.y, val.y, acc[0]));
         }
     }
@@ -268,7 +309,6 @@ struct OutCgsDot {
         sc->alpha = a;
     }
     double *partials;
-    unsigned *counter;
 };
 
 // r = r - alpha (A uhat); accumulates r.r and rt.r; the last workgroup advances
@@ -278,17 +318,24 @@ struct OutCgsR {
     const double *rt;
     int64_t nr, C;
     double alpha;
-    static constexpr int NACC = 2;
+    static constexpr int NACC = 2, NPRE = 2;
     __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
-    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *pre) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) {
+            pre[0] = ld2(r, i, nr);
+            pre[1] = ld2(rt, i, nr);
+        }
+    }
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc, const double2 *pre) const {
         int64_t i = 2 * (row * C + col);
         if (i < nr) {
             if (i + 1 >= nr) val.y = 0.0;
-            double2 rv = ld2(r, i, nr);
+            double2 rv = pre[0];
             rv.x = fma(-alpha, val.x, rv.x);
             rv.y = fma(-alpha, val.y, rv.y);
             st2(r, i, nr, rv);
-            double2 t = ld2(rt, i, nr);
+            double2 t = pre[1];
             acc[0] = fma(rv.x, rv.x, fma(rv.y, rv.y, acc[0]));
             acc[1] = fma(t.x, rv.x, fma(t.y, rv.y, acc[1]));
         }
@@ -311,7 +358,6 @@ struct OutCgsR {
         }
     }
     double *partials;
-    unsigned *counter;
 };
 
 // Right-hand side of (3.3) from y = A u^j:
@@ -327,21 +373,31 @@ struct OutRhs {
     double c_u, c_y;  // eta/sigma, (1-sigma)/sigma
     int warm, has_hist;
     const double *ujm1, *ujm2;  // u^{j-1}, u^{j-2} for warm == 2
-    static constexpr int NACC = 2;
+    // u^j, H and f are fetched ahead; the extrapolation's two older levels
+    // are read in the store (once per level, and it keeps the pass unspilled)
+    static constexpr int NACC = 2, NPRE = 3;
     __device__ void prep(const DevScalars *) {}
-    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *pre) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) {
+            pre[0] = ld2(uj, i, nr);
+            if (has_hist) pre[1] = ld2(H, i, nr);
+            if (f) pre[2] = ld2(f, i, nr);
+        }
+    }
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc, const double2 *pre) const {
         int64_t i = 2 * (row * C + col);
         if (i < nr) {
             if (i + 1 >= nr) val.y = 0.0;
-            double2 u = ld2(uj, i, nr);
+            double2 u = pre[0];
             double2 gv = make_double2(fma(c_u, u.x, -c_y * val.x), fma(c_u, u.y, -c_y * val.y));
             if (has_hist) {
-                double2 hv = ld2(H, i, nr);
+                double2 hv = pre[1];
                 gv.x -= hv.x;
                 gv.y -= hv.y;
             }
             if (f) {
-                double2 fv = ld2(f, i, nr);
+                double2 fv = pre[2];
                 gv.x += fv.x;
                 gv.y += fv.y;
             }
@@ -381,27 +437,29 @@ struct OutRhs {
         }
     }
     double *partials;
-    unsigned *counter;
 };
 
 // |g - A x|^2 into aux0.
 struct OutTrueRes {
     const double *g;
     int64_t nr, C;
-    static constexpr int NACC = 1;
+    static constexpr int NACC = 1, NPRE = 1;
     __device__ void prep(const DevScalars *) {}
-    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *pre) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) pre[0] = ld2(g, i, nr);
+    }
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc, const double2 *pre) const {
         int64_t i = 2 * (row * C + col);
         if (i < nr) {
             if (i + 1 >= nr) val.y = 0.0;
-            double2 gv = ld2(g, i, nr);
+            double2 gv = pre[0];
             double dx = gv.x - val.x, dy = gv.y - val.y;
             acc[0] = fma(dx, dx, fma(dy, dy, acc[0]));
         }
     }
     __device__ void final(const double *tot, DevScalars *sc) const { sc->aux0 = tot[0]; }
     double *partials;
-    unsigned *counter;
 };
 
 // Restart of CGS from the current iterate x (true-residual verification and
@@ -411,13 +469,17 @@ struct OutRestart {
     const double *g;
     double *r, *rt;
     int64_t nr, C;
-    static constexpr int NACC = 1;
+    static constexpr int NACC = 1, NPRE = 1;
     __device__ void prep(const DevScalars *) {}
-    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc) const {
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *pre) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) pre[0] = ld2(g, i, nr);
+    }
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc, const double2 *pre) const {
         int64_t i = 2 * (row * C + col);
         if (i < nr) {
             if (i + 1 >= nr) val.y = 0.0;
-            double2 gv = ld2(g, i, nr);
+            double2 gv = pre[0];
             double2 rv = make_double2(gv.x - val.x, gv.y - val.y);
             st2(r, i, nr, rv);
             st2(rt, i, nr, rv);
@@ -440,7 +502,6 @@ struct OutRestart {
         }
     }
     double *partials;
-    unsigned *counter;
 };
 
 // ---------------------------------------------------------------------------
@@ -469,11 +530,14 @@ template <int R, int EMAX> struct ColGeo {
     static constexpr int NT = B * T;                            // threads per workgroup
 };
 
-template <class Out> struct ColSink {
+template <class Out, int NP> struct ColSink {
     Out *out;
     int64_t c;
     double *acc;
-    __device__ __forceinline__ void operator()(int pos, double2 val) const { out->store(pos, c, val, acc); }
+    const double2 (*pre)[NP];
+    __device__ __forceinline__ void operator()(int pos, double2 val, int slot) const {
+        out->store(pos, c, val, acc, pre[slot]);
+    }
 };
 
 template <int R, int EMAX, int DIR, class In, class Out>
@@ -490,26 +554,43 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
     const bool active = c < C;
     in.prep(sc);
     out.prep(sc);
+    // every load of the pass is issued before the first store: the inputs,
+    // then the operands the last stage's stores combine with each output
+    double2 raw[E][In::NL];
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+        if (active) in.fetch(j + T * m, c, raw[m]);
+    constexpr int NP = Out::NPRE > 0 ? Out::NPRE : 1;
+    double2 pre[E][NP];
+    if constexpr (Out::NPRE > 0) {
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            if (active) out.fetch(LastStage<R, E>::pos(j, m), c, pre[m]);
+    }
     double2 v[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = active ? in.load(j + T * m, c) : make_double2(0.0, 0.0);
+    for (int m = 0; m < E; ++m) v[m] = active ? in.finish(j + T * m, c, raw[m]) : make_double2(0.0, 0.0);
     // the first barrier inside the transform orders these writes before any use
     stage_twiddles<R>(twl, tw_all, t, G::NT);
     double acc[Out::NACC > 0 ? Out::NACC : 1];
 #pragma unroll
     for (int a = 0; a < (Out::NACC > 0 ? Out::NACC : 1); ++a) acc[a] = 0.0;
-    ColSink<Out> sink{&out, c, acc};
+    ColSink<Out, NP> sink{&out, c, acc, pre};
     if constexpr (R > E) {
         fft_t<R, E, DIR, 1>(v, j, active, twl, lds + b, B, sink);
     } else {
         fft<R, E, DIR>(v, j, active, tw_all, lds + b, B, sink);
     }
-    if constexpr (Out::NACC > 0) {
-        double tot[Out::NACC];
-        if (block_reduce_last<Out::NACC>(acc, out.partials, out.counter, tot)) {
-            if (threadIdx.x == 0) out.final(tot, sc);
-        }
-    }
+    if constexpr (Out::NACC > 0) block_partial<Out::NACC>(acc, out.partials);
+}
+
+// Finishing kernel of a reducing pass (one workgroup of the pass's size NT).
+template <int NT, class Out>
+__global__ void __launch_bounds__(NT) k_final(Out out, int nparts, DevScalars *sc, int pred) {
+    if (pred && sc->done) return;
+    double tot[Out::NACC];
+    reduce_partials<Out::NACC>(out.partials, nparts, tot);
+    if (threadIdx.x == 0) out.final(tot, sc);
 }
 
 template <int R, int EMAX, int DIR, class In, class Out>
@@ -536,6 +617,15 @@ __global__ void __launch_bounds__((ColGeo<R, EMAX>::NT)) k_col_b(const ColDesc<I
     col_body<R, EMAX, DIR, In, Out>(D.C, D.in, D.out, tw_all, D.sc, pred);
 }
 
+template <int NT, class In, class Out>
+__global__ void __launch_bounds__(NT) k_final_b(const ColDesc<In, Out> *__restrict__ d, int nparts, int pred) {
+    const ColDesc<In, Out> &D = d[blockIdx.y];
+    if (pred && D.sc->done) return;
+    double tot[Out::NACC];
+    reduce_partials<Out::NACC>(D.out.partials, nparts, tot);
+    if (threadIdx.x == 0) D.out.final(tot, D.sc);
+}
+
 // ---------------------------------------------------------------------------
 // Fused column pass: inverse length-RP column FFTs of the preconditioner
 // transform (R_P x C) followed, for the same columns, by the forward
@@ -546,29 +636,34 @@ __global__ void __launch_bounds__((ColGeo<R, EMAX>::NT)) k_col_b(const ColDesc<I
 // update to it (x += alpha * uhat) and returns the product's input.
 // ---------------------------------------------------------------------------
 struct OpIdent {
+    static constexpr bool FETCH = false;
     __device__ void prep(const DevScalars *) {}
-    __device__ __forceinline__ double2 operator()(int, int64_t, double2 v) const { return v; }
+    __device__ __forceinline__ void fetch(int, int64_t, double2 &) const {}
+    __device__ __forceinline__ double2 operator()(int, int64_t, double2 v, double2) const { return v; }
 };
 
-struct OpCgsX {  // x += alpha * uhat at real indices 2m, 2m+1
+struct OpCgsX {  // x += alpha * uhat at real indices 2m, 2m+1 (x fetched at kernel start)
+    static constexpr bool FETCH = true;
     double *x;
     int64_t C;
     double alpha;
     __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
-    __device__ __forceinline__ double2 operator()(int row, int64_t col, double2 uh) const {
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 &xv) const {
+        xv = *reinterpret_cast<const double2 *>(x + 2 * (row * C + col));
+    }
+    __device__ __forceinline__ double2 operator()(int row, int64_t col, double2 uh, double2 xv) const {
         double2 *px = reinterpret_cast<double2 *>(x + 2 * (row * C + col));
-        double2 xv = *px;
         *px = make_double2(fma(alpha, uh.x, xv.x), fma(alpha, uh.y, xv.y));
         return uh;
     }
 };
 
-struct BufSink {  // y[pos*C + c] = val * tw(2*pos*c)
+template <int NS_> struct BufSink {  // y[pos*C + c] = val * tw(2*pos*c), table entries fetched per slot
     double2 *y;
-    const Tw2 *tw;
+    const double2 (*tw)[2];
     int64_t C, c;
-    __device__ __forceinline__ void operator()(int pos, double2 val) const {
-        y[pos * C + c] = cmul(val, (*tw)(2 * (int64_t)pos * c));
+    __device__ __forceinline__ void operator()(int pos, double2 val, int slot) const {
+        y[pos * C + c] = cmul(val, cmul(tw[slot][0], tw[slot][1]));
     }
 };
 
@@ -596,12 +691,32 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
     const bool activeP = colok && j < TP;
     op.prep(sc);
     // inverse preconditioner column FFT (conjugate four-step twiddle first)
-    double2 vp[EP];
+    double2 rp[EP][3];
 #pragma unroll
     for (int m = 0; m < EP; ++m) {
         const int row = j + TP * m;
-        vp[m] = activeP ? cmul(bufP[row * C + c], cconj(twP(2 * (int64_t)row * c))) : make_double2(0.0, 0.0);
+        if (activeP) {
+            rp[m][0] = bufP[row * C + c];
+            twP.fetch(2 * (int64_t)row * c, rp[m] + 1);
+        }
     }
+    // operands of the update and of the product's four-step twiddle, fetched now
+    double2 xo[EA];
+    if constexpr (Op::FETCH) {
+#pragma unroll
+        for (int m = 0; m < EA; ++m) {
+            const int row = j + TA * m;
+            if (colok && row < RP) op.fetch(row, c, xo[m]);
+        }
+    }
+    double2 twa[EA][2];
+#pragma unroll
+    for (int m = 0; m < EA; ++m)
+        if (colok) twA.fetch(2 * (int64_t)LastStage<RA, EA>::pos(j, m) * c, twa[m]);
+    double2 vp[EP];
+#pragma unroll
+    for (int m = 0; m < EP; ++m)
+        vp[m] = activeP ? cmul(rp[m][0], cconj(cmul(rp[m][1], rp[m][2]))) : make_double2(0.0, 0.0);
     stage_twiddles<RA>(twl, tw_all, t, G::NT);
     __syncthreads();
     LdsSink lsink{lds + b, B};
@@ -613,11 +728,11 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
     for (int m = 0; m < EA; ++m) {
         const int row = j + TA * m;
         double2 val = make_double2(0.0, 0.0);
-        if (colok && row < RP) val = op(row, c, lds[lpad(row) * B + b]);
+        if (colok && row < RP) val = op(row, c, lds[lpad(row) * B + b], Op::FETCH ? xo[m] : val);
         va[m] = val;
     }
     __syncthreads();
-    BufSink bsink{bufA, &twA, C, c};
+    BufSink<EA> bsink{bufA, twa, C, c};
     fft_t<RA, EA, -1, 1>(va, j, colok, twl, lds + b, B, bsink);
 }
 
@@ -674,7 +789,7 @@ template <int C_, int EMAX> struct MidGeo {
 struct RowSink {  // Y[row*C + pos] = val
     double2 *Y;
     int64_t base;
-    __device__ __forceinline__ void operator()(int pos, double2 val) const { Y[base + pos] = val; }
+    __device__ __forceinline__ void operator()(int pos, double2 val, int) const { Y[base + pos] = val; }
 };
 
 template <int C_, int EMAX, int MODE>
@@ -852,12 +967,18 @@ struct InCplx {
     const double *zr;
     const double2 *chirp;
     int64_t nv, C;
+    static constexpr int NL = 2;
     __device__ void prep(const DevScalars *) {}
-    __device__ __forceinline__ double2 load(int row, int64_t col) const {
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
+        const int64_t m = row * C + col;
+        if (m >= nv) return;
+        raw[0] = z ? z[m] : make_double2(zr[m], 0.0);
+        if (chirp) raw[1] = chirp[m];
+    }
+    __device__ __forceinline__ double2 finish(int row, int64_t col, const double2 *raw) const {
         const int64_t m = row * C + col;
         if (m >= nv) return make_double2(0.0, 0.0);
-        double2 v = z ? z[m] : make_double2(zr[m], 0.0);
-        return chirp ? cmul(v, cconj(chirp[m])) : v;
+        return chirp ? cmul(raw[0], cconj(raw[1])) : raw[0];
     }
 };
 
@@ -866,15 +987,18 @@ struct OutCplx {
     double2 *z;
     const double2 *chirp;
     int64_t nv, C;
-    static constexpr int NACC = 0;
+    static constexpr int NACC = 0, NPRE = 1;
     __device__ void prep(const DevScalars *) {}
-    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *) const {
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *pre) const {
         const int64_t m = row * C + col;
-        if (m < nv) z[m] = chirp ? cmul(val, cconj(chirp[m])) : val;
+        if (m < nv && chirp) pre[0] = chirp[m];
+    }
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *, const double2 *pre) const {
+        const int64_t m = row * C + col;
+        if (m < nv) z[m] = chirp ? cmul(val, cconj(pre[0])) : val;
     }
     __device__ void final(const double *, DevScalars *) const {}
     double *partials;
-    unsigned *counter;
 };
 
 template <int C_, int EMAX> struct RowGeo {

@@ -251,6 +251,9 @@ hipError_t launch_col_t(tsfcde_plan_s *pl, int64_t C, const In &in, const Out &o
     ProfScope ps(pl, 1);
     hipLaunchKernelGGL((k_col<R, TSF_E_COL, DIR, In, Out>), dim3((unsigned)grid), dim3(G::NT), 0, pl->stream, C, in,
                        out, pl->tw_all, pl->sc, pred);
+    if constexpr (Out::NACC > 0) {
+        hipLaunchKernelGGL((k_final<G::NT, Out>), dim3(1), dim3(G::NT), 0, pl->stream, out, (int)grid, pl->sc, pred);
+    }
     return hipGetLastError();
 }
 
@@ -349,7 +352,6 @@ SymParams symbol(const tsfcde_plan_s *pl, int64_t j, double s, const RT &rt, boo
 template <class Out>
 Out with_red(Out o, tsfcde_plan_s *pl, int site) {
     o.partials = pl->part + (size_t)site * PARTIAL_SLOTS;
-    o.counter = &pl->sc->cnt[site];
     return o;
 }
 
@@ -358,7 +360,6 @@ double2 *buf_of(tsfcde_plan_s *pl, const RT &rt) { return &rt == &pl->P ? pl->bu
 OutSpec out_spec(tsfcde_plan_s *pl, const RT &rt) {
     OutSpec o{buf_of(pl, rt), rt.tw, rt.C};
     o.partials = nullptr;
-    o.counter = nullptr;
     return o;
 }
 
@@ -382,13 +383,11 @@ hipError_t bluestein(tsfcde_plan_s *pl, const double2 *zc, const double *zr, dou
     const RT &B = pl->B;
     OutSpec o{pl->bufB, B.tw, B.C};
     o.partials = nullptr;
-    o.counter = nullptr;
     hipError_t e = launch_col<-1>(pl, B, InCplx{zc, zr, pl->chirp, pl->n, B.C}, o, 0);
     if (e != hipSuccess) return e;
     if ((e = launch_row<3>(pl, pl->bufB, pl->Bhat, nullptr)) != hipSuccess) return e;
     OutCplx oc{dst, pl->chirp, pl->n, B.C};
     oc.partials = nullptr;
-    oc.counter = nullptr;
     return launch_col<1>(pl, B, InSpec{pl->bufB, B.tw, B.C}, oc, 0);
 }
 
@@ -460,14 +459,12 @@ hipError_t cgs_iteration_general(tsfcde_plan_s *pl, int64_t j, double *x) {
     hipError_t e;
     OutReal o1{pl->phat, n, C};
     o1.partials = nullptr;
-    o1.counter = nullptr;
     if ((e = run_op<0>(pl, pl->A, pl->specPj, sI, InCgsUP{pl->r, pl->u, pl->p, pl->q, n, C, 0.0, false}, o1, 1)))
         return e;
     OutCgsDot o2 = with_red(OutCgsDot{pl->vhat, pl->rt, n, C}, pl, 0);
     if ((e = run_op<0>(pl, pl->A, pl->specA, sA, InReal{pl->phat, n, C}, o2, 1))) return e;
     OutReal o3{pl->uhat, n, C};
     o3.partials = nullptr;
-    o3.counter = nullptr;
     if ((e = run_op<0>(pl, pl->A, pl->specPj, sI, InCgsQ{pl->u, pl->vhat, pl->q, n, C, 0.0}, o3, 1))) return e;
     OutCgsR o4 = with_red(OutCgsR{pl->r, pl->rt, n, C, 0.0}, pl, 1);
     return run_op<0>(pl, pl->A, pl->specA, sA, InCgsX{pl->uhat, x, n, C, 0.0}, o4, 1);
@@ -794,7 +791,6 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
                                1.0 / (double)B.N, pl->Bhat);
             OutSpec o{pl->bufB, B.tw, B.C};
             o.partials = nullptr;
-            o.counter = nullptr;
             if (launch_col<-1>(pl, B, InCplx{pl->Bhat, nullptr, nullptr, B.N, B.C}, o, 0) != hipSuccess)
                 return fail(TSFCDE_EDEVICE);
             if (launch_row<4>(pl, pl->bufB, nullptr, pl->Bhat) != hipSuccess) return fail(TSFCDE_EDEVICE);
@@ -858,20 +854,17 @@ int tsfcde_apply(tsfcde_plan_t pl, int32_t op, int64_t j, const double *d_x, dou
         InReal in{d_x, n, pl->A.C};
         OutReal out{d_y, n, pl->A.C};
         out.partials = nullptr;
-        out.counter = nullptr;
         HIPCHK(run_op<0>(pl, pl->A, pl->specA, symbol(pl, j, s, pl->A, false), in, out, 0));
     } else if (op == TSFCDE_OP_PINV && pl->p2) {
         InReal in{d_x, n, pl->P.C};
         OutReal out{d_y, n, pl->P.C};
         out.partials = nullptr;
-        out.counter = nullptr;
         HIPCHK(run_op<1>(pl, pl->P, pl->specP, symbol(pl, j, -pl->sigma, pl->P, true), in, out, 0));
     } else if (op == TSFCDE_OP_PINV) {
         HIPCHK(precond_level(pl, j));
         InReal in{d_x, n, pl->A.C};
         OutReal out{d_y, n, pl->A.C};
         out.partials = nullptr;
-        out.counter = nullptr;
         HIPCHK(run_op<0>(pl, pl->A, pl->specPj, unit_symbol(pl->A), in, out, 0));
     } else {
         return TSFCDE_EINVAL;
@@ -1045,8 +1038,12 @@ namespace {
 template <int R, int DIR, class In, class Out>
 hipError_t blaunch_col_t(tsfcde_batch_s *bt, int64_t C, const ColDesc<In, Out> *d, int cnt, int pred) {
     using G = ColGeo<R, TSF_E_COL>;
-    hipLaunchKernelGGL((k_col_b<R, TSF_E_COL, DIR, In, Out>), dim3((unsigned)((C + G::B - 1) / G::B), cnt),
-                       dim3(G::NT), 0, bt->stream, d, bt->plans[0]->tw_all, pred);
+    const int64_t grid = (C + G::B - 1) / G::B;
+    hipLaunchKernelGGL((k_col_b<R, TSF_E_COL, DIR, In, Out>), dim3((unsigned)grid, cnt), dim3(G::NT), 0, bt->stream,
+                       d, bt->plans[0]->tw_all, pred);
+    if constexpr (Out::NACC > 0) {
+        hipLaunchKernelGGL((k_final_b<G::NT, In, Out>), dim3(1, cnt), dim3(G::NT), 0, bt->stream, d, (int)grid, pred);
+    }
     return hipGetLastError();
 }
 
@@ -1107,7 +1104,6 @@ template <class In, class Out> ColDesc<In, Out> cdesc(tsfcde_plan_s *pl, int64_t
 
 template <class Out> Out nored(Out o) {
     o.partials = nullptr;
-    o.counter = nullptr;
     return o;
 }
 
