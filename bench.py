@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the warm-started forms")
     ap.add_argument("--profile-class", default="mid_matvec", choices=sorted(KCLASS))
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run three plain device copies of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -117,6 +119,14 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration > 0:
+        src = torch.rand(args.copy_calibration << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.copy_calibration} MiB")
+        del src, dst
     prob = W.config_large(n=args.n, M=args.M)
     levels = args.levels if args.levels > 0 else prob.M
     log(f"workload n={prob.n} M={prob.M} levels/step={levels} alpha={prob.alpha} beta={prob.beta}")

@@ -43,7 +43,8 @@ struct SymParams {
 
 // ---------------------------------------------------------------------------
 // Reductions in two launches: each workgroup of a pass sums its lanes (wave64
-// shuffles, then LDS across waves) and stores one partial per accumulator;
+// shuffles, then LDS across waves) and stores one partial per accumulator
+// (indexed by the tile it covers);
 // a one-workgroup finishing kernel then sums the partials in index order.
 // The kernel boundary makes the partials visible, so no device-scope fence
 // (which on gfx950 writes back and invalidates the XCD's L2) is needed.  The
@@ -51,7 +52,7 @@ struct SymParams {
 // order is fixed by the pass geometry alone and results are reproducible.
 // ---------------------------------------------------------------------------
 template <int NACC>
-__device__ __forceinline__ void block_partial(double (&acc)[NACC], double *partials) {
+__device__ __forceinline__ void block_partial(double (&acc)[NACC], double *partials, int64_t slot) {
     __shared__ double red[NACC][16];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwave = (blockDim.x + 63) >> 6;
@@ -68,7 +69,7 @@ __device__ __forceinline__ void block_partial(double (&acc)[NACC], double *parti
         for (int a = 0; a < NACC; ++a) {
             double s = 0.0;
             for (int w = 0; w < nwave; ++w) s += red[a][w];
-            partials[(size_t)blockIdx.x * NACC + a] = s;
+            partials[(size_t)slot * NACC + a] = s;
         }
     }
 }
@@ -104,6 +105,17 @@ __device__ __forceinline__ void reduce_partials(const double *partials, int npar
 }
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
+
+// Workgroups are dispatched to the chip's eight XCDs round-robin by index, and
+// each XCD has its own L2.  Column tiles narrower than a 128-byte line share
+// lines with their neighbours; this permutation gives each XCD a contiguous
+// run of tiles so that neighbours meet in the same L2 (identity when the
+// grid is not a multiple of eight).
+constexpr int XCDS = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t grid) {
+    if (grid % XCDS) return bid;
+    return (bid % XCDS) * (grid / XCDS) + bid / XCDS;
+}
 
 // Element pair (i, i+1) of a real vector of nr values (i even).  Vectors of odd
 // length end with a lone element: the pair loads it with a zero partner, and
@@ -550,7 +562,8 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
     __shared__ double2 twl[R];
     const int t = threadIdx.x;
     const int b = t % B, j = t / B;
-    const int64_t c = (int64_t)blockIdx.x * B + b;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t c = tile * B + b;
     const bool active = c < C;
     in.prep(sc);
     out.prep(sc);
@@ -581,7 +594,7 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
     } else {
         fft<R, E, DIR>(v, j, active, tw_all, lds + b, B, sink);
     }
-    if constexpr (Out::NACC > 0) block_partial<Out::NACC>(acc, out.partials);
+    if constexpr (Out::NACC > 0) block_partial<Out::NACC>(acc, out.partials, tile);
 }
 
 // Finishing kernel of a reducing pass (one workgroup of the pass's size NT).
@@ -686,7 +699,7 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
     __shared__ double2 twl[RA];
     const int t = threadIdx.x;
     const int b = t % B, j = t / B;
-    const int64_t c = (int64_t)blockIdx.x * B + b;
+    const int64_t c = xcd_tile(blockIdx.x, gridDim.x) * B + b;
     const bool colok = c < C;
     const bool activeP = colok && j < TP;
     op.prep(sc);
