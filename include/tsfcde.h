@@ -56,6 +56,19 @@ extern "C" {
 
 /* ---- options -------------------------------------------------------- */
 #define TSFCDE_FP64 0            /* every step in FP64                       */
+#define TSFCDE_FP32_REFINED 1    /* FP64 iterative refinement around an inner
+                                    CGS whose vectors, transform buffers and
+                                    spectra are stored in FP32 (the right-hand
+                                    side, the history, the refinement residual
+                                    and all Krylov scalars stay FP64).  Used at
+                                    a level only while 2^-24 log2(L) |A|/eta
+                                    < 0.1, with |A|/eta bounded through Remark
+                                    3.1; other levels, and levels whose
+                                    refinement stalls, run the FP64 CGS.  The
+                                    stopping test is the true FP64 residual
+                                    |g - A u| <= rtol |g|.                    */
+#define TSFCDE_FP32_REFINED_FELL_BACK 2 /* stats only: refinement started, then
+                                    the level finished with the FP64 CGS     */
 #define TSFCDE_WS_ZERO 0         /* Krylov initial guess 0 (as in Sec. 4)    */
 #define TSFCDE_WS_PREV 1         /* initial guess u^j (previous level)       */
 #define TSFCDE_WS_EXTRAP 2       /* 3u^j - 3u^{j-1} + u^{j-2} (quadratic in t; u^j
@@ -65,6 +78,9 @@ extern "C" {
                                     and restart CGS from x while the true residual
                                     is above rtol |g| and still falling (at most 3
                                     restarts); also restarts once per breakdown  */
+#define TSFCDE_FLAG_FORCE_FP32 4 /* FP32_REFINED at every level, whatever the
+                                    rounding-error model predicts (to measure
+                                    where the refinement stops converging)   */
 
 /* operators for tsfcde_apply */
 #define TSFCDE_OP_A 0            /* y = A^(j+sigma) x      (3.3)            */
@@ -102,20 +118,31 @@ typedef struct tsfcde_problem {
     void *phi_user;
     double rtol;       /* Krylov stop: |r_k|_2 <= rtol |g|_2 (<= 0: 1e-10)   */
     int32_t maxit;     /* CGS iterations per level (<= 0: 500)              */
-    int32_t precision; /* TSFCDE_FP64                                       */
+    int32_t precision; /* TSFCDE_FP64 or TSFCDE_FP32_REFINED                */
     int32_t warm_start;/* TSFCDE_WS_ZERO, _PREV or _EXTRAP                  */
     int32_t flags;     /* TSFCDE_FLAG_*                                     */
 } tsfcde_problem;
 
 typedef struct tsfcde_stats {
-    int32_t iters;        /* CGS iterations of this level                    */
-    int32_t outer_iters;  /* refinement sweeps (1 for the plain FP64 path)   */
+    int32_t iters;        /* CGS iterations of this level (inner FP32 ones
+                             plus any FP64 ones)                             */
+    int32_t outer_iters;  /* refinement residuals computed (1 for FP64)      */
     int32_t restarts;     /* CGS restarts (breakdown or true-residual gap)   */
     int32_t status;       /* TSFCDE_OK or the level's error code             */
-    double relres;        /* recursive |r_k|_2 / |g|_2 at exit               */
-    double relres_true;   /* |g - A u|_2/|g|_2 (FLAG_TRUE_RESIDUAL), else -1 */
-    double backward_err;  /* reserved (-1)                                   */
+    double relres;        /* |r|_2 / |g|_2 at exit (the true residual once the
+                             level's answer has been checked)                */
+    double relres_true;   /* |g - A u|_2/|g|_2 of the returned u             */
+    double backward_err;  /* |g - A u|_2 / (|A|_2 |u|_2 + |g|_2), with |A|_2
+                             bounded above by eta + sigma(|gamma|/h +
+                             (d_+ + d_-) h^-beta sum_k |omega_k|).  A level
+                             whose CGS stops on its recursive residual is
+                             accepted when this is <= 1e-13 (or its true
+                             residual meets rtol); otherwise CGS restarts
+                             from u, at most 3 times                        */
     double seconds;       /* host wall time of the level                     */
+    int32_t precision_used; /* TSFCDE_FP64, TSFCDE_FP32_REFINED, or
+                             TSFCDE_FP32_REFINED_FELL_BACK                   */
+    int32_t reserved;
 } tsfcde_stats;
 
 typedef struct tsfcde_plan_s *tsfcde_plan_t;

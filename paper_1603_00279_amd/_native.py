@@ -28,9 +28,12 @@ TSFCDE_EINVAL, TSFCDE_ENOMEM, TSFCDE_EDEVICE = -1, -2, -3
 TSFCDE_ENOCONV, TSFCDE_EBREAKDOWN, TSFCDE_ENONFINITE = -4, -5, -6
 TSFCDE_EDONE, TSFCDE_EUNSUPPORTED = -7, -8
 TSFCDE_FP64 = 0
+TSFCDE_FP32_REFINED = 1
+TSFCDE_FP32_REFINED_FELL_BACK = 2
 TSFCDE_WS_ZERO, TSFCDE_WS_PREV, TSFCDE_WS_EXTRAP = 0, 1, 2
 TSFCDE_FLAG_TRUE_RESIDUAL = 1
 TSFCDE_FLAG_VERIFY = 2
+TSFCDE_FLAG_FORCE_FP32 = 4
 TSFCDE_OP_A, TSFCDE_OP_B, TSFCDE_OP_PINV = 0, 1, 2
 TSFCDE_SPEC_EMBED, TSFCDE_SPEC_STRANG = 0, 1
 
@@ -51,6 +54,7 @@ class tsfcde_stats(ctypes.Structure):
     _fields_ = [
         ("iters", c_int32), ("outer_iters", c_int32), ("restarts", c_int32), ("status", c_int32),
         ("relres", c_double), ("relres_true", c_double), ("backward_err", c_double), ("seconds", c_double),
+        ("precision_used", c_int32), ("reserved", c_int32),
     ]
 
     def as_dict(self):

@@ -129,6 +129,29 @@ __device__ __forceinline__ void st2(double *p, int64_t i, int64_t nr, double2 v)
     else if (i < nr) p[i] = v.x;
 }
 
+// The same for vectors stored in FP32 (values are widened on load and rounded
+// to nearest on store; all arithmetic stays in FP64 registers).
+__device__ __forceinline__ double2 ld2(const float *p, int64_t i, int64_t nr) {
+    if (i + 1 < nr) {
+        const float2 v = *reinterpret_cast<const float2 *>(p + i);
+        return make_double2(v.x, v.y);
+    }
+    return make_double2(i < nr ? (double)p[i] : 0.0, 0.0);
+}
+__device__ __forceinline__ void st2(float *p, int64_t i, int64_t nr, double2 v) {
+    if (i + 1 < nr) *reinterpret_cast<float2 *>(p + i) = make_float2((float)v.x, (float)v.y);
+    else if (i < nr) p[i] = (float)v.x;
+}
+
+// Complex buffer element m stored in FP64 or FP32.
+__device__ __forceinline__ double2 ldc(const double2 *p, int64_t m) { return p[m]; }
+__device__ __forceinline__ double2 ldc(const float2 *p, int64_t m) {
+    const float2 v = p[m];
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void stc(double2 *p, int64_t m, double2 v) { p[m] = v; }
+__device__ __forceinline__ void stc(float2 *p, int64_t m, double2 v) { p[m] = make_float2((float)v.x, (float)v.y); }
+
 // ---------------------------------------------------------------------------
 // Pass-A loaders (forward column pass).  They return packed element
 // m = row*C + col of the real input, z[m] = x[2m] + i x[2m+1], in two phases:
@@ -137,8 +160,8 @@ __device__ __forceinline__ void st2(double *p, int64_t i, int64_t nr, double2 v)
 // returns z[m].  A pass fetches all its elements before finishing any, so no
 // load waits behind a store that might alias it.
 // ---------------------------------------------------------------------------
-struct InReal {  // plain real vector, zero beyond nr values
-    const double *x;
+template <class S> struct InRealT {  // plain real vector, zero beyond nr values
+    const S *x;
     int64_t nr, C;
     static constexpr int NL = 1;
     __device__ void prep(const DevScalars *) {}
@@ -147,13 +170,14 @@ struct InReal {  // plain real vector, zero beyond nr values
     }
     __device__ __forceinline__ double2 finish(int, int64_t, const double2 *raw) const { return raw[0]; }
 };
+using InReal = InRealT<double>;
 
 // CGS: u = r + beta q ; p = u + beta (q + beta p) (first iteration: u = p = r);
 // writes u and p, transforms p.
-struct InCgsUP {
-    const double *r;
-    double *u, *p;
-    const double *q;
+template <class S> struct InCgsUPT {
+    const S *r;
+    S *u, *p;
+    const S *q;
     int64_t nr, C;
     double beta;
     bool first;
@@ -190,11 +214,12 @@ struct InCgsUP {
         return pv;
     }
 };
+using InCgsUP = InCgsUPT<double>;
 
 // CGS: q = u - alpha vhat (written); transforms u + q.
-struct InCgsQ {
-    const double *u, *vhat;
-    double *q;
+template <class S> struct InCgsQT {
+    const S *u, *vhat;
+    S *q;
     int64_t nr, C;
     double alpha;
     __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
@@ -215,11 +240,12 @@ struct InCgsQ {
         return make_double2(uv.x + qv.x, uv.y + qv.y);
     }
 };
+using InCgsQ = InCgsQT<double>;
 
 // CGS: x = x + alpha uhat (written); transforms uhat.
-struct InCgsX {
-    const double *uhat;
-    double *x;
+template <class S> struct InCgsXT {
+    const S *uhat;
+    S *x;
     int64_t nr, C;
     double alpha;
     __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
@@ -239,10 +265,11 @@ struct InCgsX {
         return uh;
     }
 };
+using InCgsX = InCgsXT<double>;
 
 // Pass-A store: spectrum buffer y[row*C + col] = val * W_N^(row*col).
-struct OutSpec {
-    double2 *y;
+template <class CS> struct OutSpecT {
+    CS *y;
     Tw2 tw;  // table for exp(-2 pi i m / L), L = 2N
     int64_t C;
     static constexpr int NACC = 0, NPRE = 2;
@@ -251,32 +278,34 @@ struct OutSpec {
         tw.fetch(2 * (int64_t)row * col, pre);
     }
     __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *, const double2 *pre) const {
-        y[row * C + col] = cmul(val, cmul(pre[0], pre[1]));
+        stc(y, row * C + col, cmul(val, cmul(pre[0], pre[1])));
     }
     __device__ void final(const double *, DevScalars *) const {}
     double *partials;
 };
+using OutSpec = OutSpecT<double2>;
 
 // ---------------------------------------------------------------------------
 // Pass-C loader and stores (inverse column pass).
 // ---------------------------------------------------------------------------
-struct InSpec {
-    const double2 *y;
+template <class CS> struct InSpecT {
+    const CS *y;
     Tw2 tw;
     int64_t C;
     static constexpr int NL = 3;
     __device__ void prep(const DevScalars *) {}
     __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
-        raw[0] = y[row * C + col];
+        raw[0] = ldc(y, row * C + col);
         tw.fetch(2 * (int64_t)row * col, raw + 1);
     }
     __device__ __forceinline__ double2 finish(int, int64_t, const double2 *raw) const {
         return cmul(raw[0], cconj(cmul(raw[1], raw[2])));
     }
 };
+using InSpec = InSpecT<double2>;
 
-struct OutReal {  // x[2m], x[2m+1] for 2m < nr
-    double *x;
+template <class S> struct OutRealT {  // x[2m], x[2m+1] for 2m < nr
+    S *x;
     int64_t nr, C;
     static constexpr int NACC = 0, NPRE = 0;
     __device__ void prep(const DevScalars *) {}
@@ -287,11 +316,12 @@ struct OutReal {  // x[2m], x[2m+1] for 2m < nr
     __device__ void final(const double *, DevScalars *) const {}
     double *partials;
 };
+using OutReal = OutRealT<double>;
 
 // vhat = A phat; accumulates rt . vhat; the last workgroup sets alpha = rho / (rt . vhat).
-struct OutCgsDot {
-    double *vhat;
-    const double *rt;
+template <class S> struct OutCgsDotT {
+    S *vhat;
+    const S *rt;
     int64_t nr, C;
     static constexpr int NACC = 1, NPRE = 1;
     __device__ void prep(const DevScalars *) {}
@@ -322,12 +352,13 @@ struct OutCgsDot {
     }
     double *partials;
 };
+using OutCgsDot = OutCgsDotT<double>;
 
 // r = r - alpha (A uhat); accumulates r.r and rt.r; the last workgroup advances
 // the recurrence scalars and tests |r| <= rtol |g|.
-struct OutCgsR {
-    double *r;
-    const double *rt;
+template <class S> struct OutCgsRT {
+    S *r;
+    const S *rt;
     int64_t nr, C;
     double alpha;
     static constexpr int NACC = 2, NPRE = 2;
@@ -371,6 +402,7 @@ struct OutCgsR {
     }
     double *partials;
 };
+using OutCgsR = OutCgsRT<double>;
 
 // Right-hand side of (3.3) from y = A u^j:
 //   g = (eta/sigma) u^j - ((1-sigma)/sigma) y - H + f     (= B u^j - H + f)
@@ -478,14 +510,18 @@ struct OutTrueRes {
 // breakdown recovery): y = A x, r = g - y, rt = r; the last workgroup resets
 // the recurrence and records |r|^2 in aux0.
 struct OutRestart {
-    const double *g;
+    const double *g, *x;
     double *r, *rt;
     int64_t nr, C;
-    static constexpr int NACC = 1, NPRE = 1;
+    double anorm, bwtol;  // bound on |A|_2; accept x at backward error <= bwtol (0: never)
+    static constexpr int NACC = 2, NPRE = 2;
     __device__ void prep(const DevScalars *) {}
     __device__ __forceinline__ void fetch(int row, int64_t col, double2 *pre) const {
         int64_t i = 2 * (row * C + col);
-        if (i < nr) pre[0] = ld2(g, i, nr);
+        if (i < nr) {
+            pre[0] = ld2(g, i, nr);
+            pre[1] = ld2(x, i, nr);
+        }
     }
     __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc, const double2 *pre) const {
         int64_t i = 2 * (row * C + col);
@@ -496,10 +532,15 @@ struct OutRestart {
             st2(r, i, nr, rv);
             st2(rt, i, nr, rv);
             acc[0] = fma(rv.x, rv.x, fma(rv.y, rv.y, acc[0]));
+            acc[1] = fma(pre[1].x, pre[1].x, fma(pre[1].y, pre[1].y, acc[1]));
         }
     }
+    // aux0 = |g - A x|^2 (true residual), aux1 = |x|^2.  x is accepted (done)
+    // when |g - A x| <= rtol |g|, or when the normwise backward error
+    // |g - A x| / (|A| |x| + |g|) is at most bwtol.
     __device__ void final(const double *tot, DevScalars *sc) const {
         sc->aux0 = tot[0];
+        sc->aux1 = tot[1];
         sc->rnorm2 = tot[0];
         sc->rho = tot[0];
         sc->rho_prev = 1.0;
@@ -507,7 +548,85 @@ struct OutRestart {
         sc->alpha = 0.0;
         sc->fresh = 1;
         sc->status = ST_OK;
-        sc->done = (tot[0] <= sc->tol2) ? 1 : 0;
+        const double den = anorm * sqrt(tot[1]) + sqrt(sc->gnorm2);
+        const bool bw_ok = bwtol > 0.0 && sqrt(tot[0]) <= bwtol * den;
+        sc->done = (tot[0] <= sc->tol2 || bw_ok) ? 1 : 0;
+        if (!finite(tot[0])) {
+            sc->status = ST_NONFINITE;
+            sc->done = 1;
+        }
+    }
+    double *partials;
+};
+
+// Iterative refinement (FP64 outer loop around an FP32-stored inner solve):
+// x += d (the inner solve's correction, FP32) in FP64; transforms x.
+struct InIR {
+    double *x;
+    const float *d;
+    int64_t nr, C;
+    static constexpr int NL = 2;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
+        int64_t i = 2 * (row * C + col);
+        if (i >= nr) return;
+        raw[0] = ld2(x, i, nr);
+        raw[1] = ld2(d, i, nr);
+    }
+    __device__ __forceinline__ double2 finish(int row, int64_t col, const double2 *raw) const {
+        int64_t i = 2 * (row * C + col);
+        if (i >= nr) return make_double2(0.0, 0.0);
+        const double2 xv = make_double2(raw[0].x + raw[1].x, raw[0].y + raw[1].y);
+        st2(x, i, nr, xv);
+        return xv;
+    }
+};
+
+// Outer residual r = g - A x in FP64: |r|^2 and |x|^2 accumulate in FP64, r is
+// handed to the inner solve rounded to FP32 (r = rt = r, d = 0).  The last
+// workgroup's epilogue stops the level when |r| <= rtol |g|, and otherwise
+// starts the inner CGS with tolerance irtol |r|.
+struct OutIR {
+    const double *g, *x;
+    float *r, *rt, *d;
+    int64_t nr, C;
+    double irtol2;
+    static constexpr int NACC = 2, NPRE = 2;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *pre) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) {
+            pre[0] = ld2(g, i, nr);
+            pre[1] = ld2(x, i, nr);
+        }
+    }
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc, const double2 *pre) const {
+        int64_t i = 2 * (row * C + col);
+        if (i < nr) {
+            if (i + 1 >= nr) val.y = 0.0;
+            const double2 gv = pre[0];
+            const double2 rv = make_double2(gv.x - val.x, gv.y - val.y);
+            st2(r, i, nr, rv);
+            st2(rt, i, nr, rv);
+            st2(d, i, nr, make_double2(0.0, 0.0));
+            acc[0] = fma(rv.x, rv.x, fma(rv.y, rv.y, acc[0]));
+            acc[1] = fma(pre[1].x, pre[1].x, fma(pre[1].y, pre[1].y, acc[1]));
+        }
+    }
+    // aux1 = |g - A x|^2, aux0 = |x|^2
+    __device__ void final(const double *tot, DevScalars *sc) const {
+        sc->aux1 = tot[0];
+        sc->aux0 = tot[1];
+        sc->rnorm2 = tot[0];
+        sc->rho = tot[0];
+        sc->rho_prev = 1.0;
+        sc->beta = 0.0;
+        sc->alpha = 0.0;
+        sc->tol2 = irtol2 * tot[0];
+        sc->iter = 0;
+        sc->fresh = 1;
+        sc->status = ST_OK;
+        sc->done = (tot[0] <= sc->rtol2 * sc->gnorm2) ? 1 : 0;
         if (!finite(tot[0])) {
             sc->status = ST_NONFINITE;
             sc->done = 1;
@@ -655,28 +774,30 @@ struct OpIdent {
     __device__ __forceinline__ double2 operator()(int, int64_t, double2 v, double2) const { return v; }
 };
 
-struct OpCgsX {  // x += alpha * uhat at real indices 2m, 2m+1 (x fetched at kernel start)
+template <class S> struct OpCgsXT {  // x += alpha * uhat at real indices 2m, 2m+1 (x fetched at kernel start)
     static constexpr bool FETCH = true;
-    double *x;
+    S *x;
     int64_t C;
     double alpha;
     __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
     __device__ __forceinline__ void fetch(int row, int64_t col, double2 &xv) const {
-        xv = *reinterpret_cast<const double2 *>(x + 2 * (row * C + col));
+        const int64_t i = 2 * (row * C + col);
+        xv = ld2(x, i, i + 2);
     }
     __device__ __forceinline__ double2 operator()(int row, int64_t col, double2 uh, double2 xv) const {
-        double2 *px = reinterpret_cast<double2 *>(x + 2 * (row * C + col));
-        *px = make_double2(fma(alpha, uh.x, xv.x), fma(alpha, uh.y, xv.y));
+        const int64_t i = 2 * (row * C + col);
+        st2(x, i, i + 2, make_double2(fma(alpha, uh.x, xv.x), fma(alpha, uh.y, xv.y)));
         return uh;
     }
 };
+using OpCgsX = OpCgsXT<double>;
 
-template <int NS_> struct BufSink {  // y[pos*C + c] = val * tw(2*pos*c), table entries fetched per slot
-    double2 *y;
+template <int NS_, class CS> struct BufSink {  // y[pos*C + c] = val * tw(2*pos*c), table entries fetched per slot
+    CS *y;
     const double2 (*tw)[2];
     int64_t C, c;
     __device__ __forceinline__ void operator()(int pos, double2 val, int slot) const {
-        y[pos * C + c] = cmul(val, cmul(tw[slot][0], tw[slot][1]));
+        stc(y, pos * C + c, cmul(val, cmul(tw[slot][0], tw[slot][1])));
     }
 };
 
@@ -687,9 +808,9 @@ template <int RP, int EMAX> struct FuseGeo {
     static constexpr int EP = Geo<RP, EA>::E, TP = Geo<RP, EA>::T;
 };
 
-template <int RP, int EMAX, class Op>
-__global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, const double2 *__restrict__ bufP, Tw2 twP,
-                                                                double2 *__restrict__ bufA, Tw2 twA, Op op,
+template <int RP, int EMAX, class Op, class CS>
+__global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, const CS *__restrict__ bufP, Tw2 twP,
+                                                                CS *__restrict__ bufA, Tw2 twA, Op op,
                                                                 const double2 *__restrict__ tw_all, DevScalars *sc,
                                                                 int pred) {
     if (pred && sc->done) return;
@@ -709,7 +830,7 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
     for (int m = 0; m < EP; ++m) {
         const int row = j + TP * m;
         if (activeP) {
-            rp[m][0] = bufP[row * C + c];
+            rp[m][0] = ldc(bufP, row * C + c);
             twP.fetch(2 * (int64_t)row * c, rp[m] + 1);
         }
     }
@@ -745,7 +866,7 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
         va[m] = val;
     }
     __syncthreads();
-    BufSink<EA> bsink{bufA, twa, C, c};
+    BufSink<EA, CS> bsink{bufA, twa, C, c};
     fft_t<RA, EA, -1, 1>(va, j, colok, twl, lds + b, B, bsink);
 }
 
@@ -799,14 +920,15 @@ template <int C_, int EMAX> struct MidGeo {
     static constexpr int LS = lpad_size(C_);
 };
 
-struct RowSink {  // Y[row*C + pos] = val
-    double2 *Y;
+template <class CS> struct RowSinkT {  // Y[row*C + pos] = val
+    CS *Y;
     int64_t base;
-    __device__ __forceinline__ void operator()(int pos, double2 val, int) const { Y[base + pos] = val; }
+    __device__ __forceinline__ void operator()(int pos, double2 val, int) const { stc(Y, base + pos, val); }
 };
+using RowSink = RowSinkT<double2>;
 
-template <int C_, int EMAX, int MODE>
-__device__ __forceinline__ void mid_body(int64_t R, double2 *Y, const double2 *spec, double2 *spec_out, Tw2 twL,
+template <int C_, int EMAX, int MODE, class CS>
+__device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, double2 *spec_out, Tw2 twL,
                                          SymParams sp, const double2 *__restrict__ tw_all, DevScalars *sc, int pred) {
     if (pred && sc->done) return;
     using G = MidGeo<C_, EMAX>;
@@ -826,7 +948,7 @@ __device__ __forceinline__ void mid_body(int64_t R, double2 *Y, const double2 *s
     double2 *slab = lds + (sel < 2 ? sel : 0) * LS;
     double2 v[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = active ? Y[row * C + j + T * m] : make_double2(0.0, 0.0);
+    for (int m = 0; m < E; ++m) v[m] = active ? ldc(Y, row * C + j + T * m) : make_double2(0.0, 0.0);
     // Everything the pair step needs is fetched now, so its latency overlaps the
     // row loads and the forward transform: spectrum values and untangle twiddles
     // of this thread's pairs (rows ra, rb with ra != 0), and the stage twiddles.
@@ -839,8 +961,8 @@ __device__ __forceinline__ void mid_body(int64_t R, double2 *Y, const double2 *s
             pLa[i] = pLb[i] = pW[i] = make_double2(0.0, 0.0);
             if (k2 < C_) {
                 if constexpr (MODE != 2) {
-                    pLa[i] = spec[ra * C + k2];
-                    pLb[i] = spec[rb * C + (C_ - 1 - k2)];
+                    pLa[i] = ldc(spec, ra * C + k2);
+                    pLb[i] = ldc(spec, rb * C + (C_ - 1 - k2));
                 }
                 pW[i] = twL(ra + R * k2);
             }
@@ -886,12 +1008,12 @@ __device__ __forceinline__ void mid_body(int64_t R, double2 *Y, const double2 *s
                 double2 La = make_double2(0, 0), Lb = make_double2(0, 0);
                 if constexpr (MODE != 2) {
                     if (k2 == 0) {
-                        const double2 L0 = spec[0];
+                        const double2 L0 = ldc(spec, 0);
                         La = make_double2(L0.x, 0.0);  // lambda_0
                         Lb = make_double2(L0.y, 0.0);  // lambda_N
                     } else {
-                        La = spec[k2];
-                        Lb = spec[k2b];
+                        La = ldc(spec, k2);
+                        Lb = ldc(spec, k2b);
                     }
                 }
                 const double2 w = k2 == 0 ? make_double2(1.0, 0.0) : twL(k);
@@ -916,8 +1038,8 @@ __device__ __forceinline__ void mid_body(int64_t R, double2 *Y, const double2 *s
                 const int64_t pa = (R / 2) * C + k2, pb = (R / 2) * C + k2b;
                 double2 La = make_double2(0, 0), Lb = make_double2(0, 0);
                 if constexpr (MODE != 2) {
-                    La = spec[pa];
-                    Lb = spec[pb];
+                    La = ldc(spec, pa);
+                    Lb = ldc(spec, pb);
                 }
                 double2 xa, xb;
                 pair_update<MODE>(za, zb, twL(k), La, Lb, sp, &xa, &xb);
@@ -936,7 +1058,7 @@ __device__ __forceinline__ void mid_body(int64_t R, double2 *Y, const double2 *s
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = active ? slab[lpad(j + T * m)] : make_double2(0.0, 0.0);
     __syncthreads();
-    RowSink rsink{Y, row * C};
+    RowSinkT<CS> rsink{Y, row * C};
     if constexpr (TWL) {
         fft_t<C_, E, 1, 1>(v, j, active, twl, slab, 1, rsink);
     } else {
@@ -944,12 +1066,12 @@ __device__ __forceinline__ void mid_body(int64_t R, double2 *Y, const double2 *s
     }
 }
 
-template <int C_, int EMAX, int MODE>
-__global__ void __launch_bounds__((MidGeo<C_, EMAX>::NT)) k_mid(int64_t R, double2 *Y, const double2 *spec,
+template <int C_, int EMAX, int MODE, class CS>
+__global__ void __launch_bounds__((MidGeo<C_, EMAX>::NT)) k_mid(int64_t R, CS *Y, const CS *spec,
                                                               double2 *spec_out, Tw2 twL, SymParams sp,
                                                               const double2 *__restrict__ tw_all, DevScalars *sc,
                                                               int pred) {
-    mid_body<C_, EMAX, MODE>(R, Y, spec, spec_out, twL, sp, tw_all, sc, pred);
+    mid_body<C_, EMAX, MODE, CS>(R, Y, spec, spec_out, twL, sp, tw_all, sc, pred);
 }
 
 struct MidDesc {
@@ -966,7 +1088,7 @@ template <int C_, int EMAX, int MODE>
 __global__ void __launch_bounds__((MidGeo<C_, EMAX>::NT)) k_mid_b(const MidDesc *__restrict__ d,
                                                                 const double2 *__restrict__ tw_all, int pred) {
     const MidDesc D = d[blockIdx.y];
-    mid_body<C_, EMAX, MODE>(D.R, D.Y, D.spec, D.spec_out, D.twL, D.sp, tw_all, D.sc, pred);
+    mid_body<C_, EMAX, MODE, double2>(D.R, D.Y, D.spec, D.spec_out, D.twL, D.sp, tw_all, D.sc, pred);
 }
 
 // ---------------------------------------------------------------------------
@@ -1073,6 +1195,12 @@ __global__ void __launch_bounds__((RowGeo<C_, EMAX>::NT)) k_row_b(const RowDesc 
                                                                   const double2 *__restrict__ tw_all) {
     const RowDesc D = d[blockIdx.y];
     row_body<C_, EMAX, MODE>(D.Y, D.spec, D.spec_out, tw_all);
+}
+
+// FP32 copy (round to nearest) of a complex FP64 array.
+__global__ void k_to_f32(const double2 *src, float2 *dst, int64_t m) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
+        dst[k] = make_float2((float)src[k].x, (float)src[k].y);
 }
 
 // Chirp b_m = exp(i pi m^2 / n), m < n (m^2 reduced modulo 2n exactly).
@@ -1340,7 +1468,8 @@ __global__ void k_copy(const double *__restrict__ src, double *__restrict__ dst,
         dst[i] = src[i];
 }
 
-__global__ void k_fill(double *__restrict__ dst, double v, int64_t n) {
+template <class S>
+__global__ void k_fill(S *__restrict__ dst, S v, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = v;
 }

@@ -30,6 +30,11 @@ constexpr int64_t NMAX = int64_t(1) << 24;
 constexpr int64_t PARTIAL_SLOTS = 16384;  // doubles per reduction site
 constexpr int NSITES = 4;
 constexpr int NPROF = 6;  // profiling classes, see tsfcde_profile
+// CGS's recursive residual can drift far from the true one after a
+// near-breakdown (a tiny rt . vhat in an early step), so a converged level is
+// accepted only when its normwise backward error is at most BW_TOL; otherwise
+// CGS restarts from x.
+constexpr double BW_TOL = 1e-13;
 
 struct RT {  // real transform of length L = 2N as an R x C complex transform
     int64_t L = 0, N = 0, R = 0, C = 0;
@@ -83,18 +88,20 @@ bool rt_setup(RT &A, RT &P, RT &B, int64_t n, bool force_general = false) {
 }
 
 struct Layout {
-    size_t off_U, off_vec, off_tmp, off_w, off_g0, off_cbase, off_buf, off_bufP, off_specA, off_specP, off_tw, off_tw2A,
-        off_tw2P, off_part, off_sc, off_bufB, off_Bhat, off_chirp, off_Ls, off_wv, off_Wt, off_specPj, off_tw2B, total;
+    size_t off_U, off_vec, off_v32, off_tmp, off_w, off_g0, off_cbase, off_buf, off_bufP, off_specA, off_specP, off_tw, off_tw2A,
+        off_tw2P, off_part, off_sc, off_bufB, off_Bhat, off_chirp, off_Ls, off_wv, off_Wt, off_specPj, off_tw2B,
+        off_buf32, off_bufP32, off_specA32, off_specP32, off_specPj32, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int NVEC = 11;  // H g r rt u p q phat vhat uhat fbuf
+constexpr int NV32 = 9;   // FP32 inner solve: r rt u p q phat vhat uhat d
 
 // internal row stride: n rounded up to even, so every row starts 16-byte aligned
 int64_t ld_of(int64_t n) { return n + (n & 1); }
 
-Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P, const RT &B, bool p2) {
+Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P, const RT &B, bool p2, bool fp32) {
     const int64_t ld = ld_of(n);
     Layout l{};
     size_t o = 0;
@@ -105,6 +112,7 @@ Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P, const RT &B, b
     };
     l.off_U = take(sizeof(double) * (size_t)(M + 1) * ld);
     l.off_vec = take(sizeof(double) * (size_t)NVEC * ld);
+    l.off_v32 = take(sizeof(float) * (size_t)(fp32 ? NV32 * ld : 0));
     l.off_tmp = take(sizeof(double) * (size_t)std::max<int64_t>(A.L, n));
     l.off_w = take(sizeof(double) * (size_t)(n + 2));
     l.off_g0 = take(sizeof(double) * (size_t)(n + 2));
@@ -127,6 +135,13 @@ Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P, const RT &B, b
     l.off_Wt = take(sizeof(double2) * nn);
     l.off_specPj = take(sizeof(double2) * (p2 ? 0 : (size_t)A.N));
     l.off_tw2B = take(sizeof(double2) * (p2 ? 0 : (size_t)(B.nlo + B.nhi)));
+    // FP32 copies of the inner solve's transform buffers and spectra
+    const size_t f = fp32 ? 1 : 0;
+    l.off_buf32 = take(sizeof(float2) * f * (size_t)A.N);
+    l.off_bufP32 = take(sizeof(float2) * f * (size_t)(p2 ? P.N : 0));
+    l.off_specA32 = take(sizeof(float2) * f * (size_t)A.N);
+    l.off_specP32 = take(sizeof(float2) * f * (size_t)(p2 ? P.N : 0));
+    l.off_specPj32 = take(sizeof(float2) * f * (size_t)(p2 ? 0 : A.N));
     l.total = o;
     return l;
 }
@@ -140,7 +155,7 @@ int validate(const tsfcde_problem *p) {
     if (p->n < 2 || p->M < 1) return TSFCDE_EINVAL;
     if ((!p->gamma && !p->gamma_at) || (!p->dplus && !p->dplus_at) || (!p->dminus && !p->dminus_at))
         return TSFCDE_EINVAL;
-    if (p->precision != TSFCDE_FP64) return TSFCDE_EINVAL;
+    if (p->precision != TSFCDE_FP64 && p->precision != TSFCDE_FP32_REFINED) return TSFCDE_EINVAL;
     if (p->warm_start != TSFCDE_WS_ZERO && p->warm_start != TSFCDE_WS_PREV && p->warm_start != TSFCDE_WS_EXTRAP)
         return TSFCDE_EINVAL;
     if (!std::isfinite(p->rtol)) return TSFCDE_EINVAL;
@@ -176,6 +191,13 @@ struct tsfcde_plan_s {
     DevScalars *sc;
     DevScalars *h_sc = nullptr;  // pinned mirror for polling
     int last_iters = 8;
+    // FP32-refined form: FP32-stored inner CGS inside an FP64 refinement loop
+    bool fp32 = false;
+    std::vector<double> kbound;  // per level: bound on |A| / eta (Remark 3.1)
+    std::vector<double> anorm;   // per level: upper bound on |A|_2 (backward error)
+    float *r32, *rt32, *u32, *p32, *q32, *phat32, *vhat32, *uhat32, *d32;
+    float2 *buf32, *bufP32, *specA32, *specP32, *specPj32;
+    int last_inner = 8;
     ProfRec prof[NPROF];
     std::vector<hipEvent_t> event_pool;
 };
@@ -268,8 +290,8 @@ hipError_t launch_col(tsfcde_plan_s *pl, const RT &rt, const In &in, const Out &
     }
 }
 
-template <int RP, class Op>
-hipError_t launch_fuse_t(tsfcde_plan_s *pl, const Op &op, int pred) {
+template <int RP, class Op, class CS>
+hipError_t launch_fuse_t(tsfcde_plan_s *pl, const Op &op, const CS *bufP, CS *bufA, int pred) {
     if constexpr (RP > 2048) {
         return hipErrorInvalidValue;
     } else {
@@ -277,40 +299,40 @@ hipError_t launch_fuse_t(tsfcde_plan_s *pl, const Op &op, int pred) {
         const int64_t C = pl->A.C;
         const int64_t grid = (C + G::B - 1) / G::B;
         ProfScope ps(pl, 5);
-        hipLaunchKernelGGL((k_fuse<RP, TSF_E_FUSE, Op>), dim3((unsigned)grid), dim3(G::NT), 0, pl->stream, C,
-                           pl->bufP, pl->P.tw, pl->buf, pl->A.tw, op, pl->tw_all, pl->sc, pred);
+        hipLaunchKernelGGL((k_fuse<RP, TSF_E_FUSE, Op, CS>), dim3((unsigned)grid), dim3(G::NT), 0, pl->stream, C,
+                           bufP, pl->P.tw, bufA, pl->A.tw, op, pl->tw_all, pl->sc, pred);
         return hipGetLastError();
     }
 }
 
 // preconditioner inverse column pass fused with the next product's forward one
-template <class Op>
-hipError_t launch_fuse(tsfcde_plan_s *pl, const Op &op, int pred) {
+template <class Op, class CS>
+hipError_t launch_fuse(tsfcde_plan_s *pl, const Op &op, const CS *bufP, CS *bufA, int pred) {
     switch (pl->P.R) {
 #define TSF_CASE(P) \
-    case P: return launch_fuse_t<P>(pl, op, pred);
+    case P: return launch_fuse_t<P>(pl, op, bufP, bufA, pred);
         TSF_SIZES(TSF_CASE)
 #undef TSF_CASE
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int C_, int MODE>
-hipError_t launch_mid_t(tsfcde_plan_s *pl, const RT &rt, double2 *Y, const double2 *spec, double2 *spec_out,
+template <int C_, int MODE, class CS>
+hipError_t launch_mid_t(tsfcde_plan_s *pl, const RT &rt, CS *Y, const CS *spec, double2 *spec_out,
                         const SymParams &sp, int pred) {
     using G = MidGeo<C_, TSF_E_MID>;
     ProfScope ps(pl, MODE == 1 ? 4 : 2);
-    hipLaunchKernelGGL((k_mid<C_, TSF_E_MID, MODE>), dim3((unsigned)(rt.R / 2)), dim3(G::NT), 0, pl->stream, rt.R,
-                       Y, spec, spec_out, rt.tw, sp, pl->tw_all, pl->sc, pred);
+    hipLaunchKernelGGL((k_mid<C_, TSF_E_MID, MODE, CS>), dim3((unsigned)(rt.R / 2)), dim3(G::NT), 0, pl->stream,
+                       rt.R, Y, spec, spec_out, rt.tw, sp, pl->tw_all, pl->sc, pred);
     return hipGetLastError();
 }
 
-template <int MODE>
-hipError_t launch_mid(tsfcde_plan_s *pl, const RT &rt, double2 *Y, const double2 *spec, double2 *spec_out,
+template <int MODE, class CS>
+hipError_t launch_mid(tsfcde_plan_s *pl, const RT &rt, CS *Y, const CS *spec, double2 *spec_out,
                       const SymParams &sp, int pred) {
     switch (rt.C) {
 #define TSF_CASE(P) \
-    case P: return launch_mid_t<P, MODE>(pl, rt, Y, spec, spec_out, sp, pred);
+    case P: return launch_mid_t<P, MODE, CS>(pl, rt, Y, spec, spec_out, sp, pred);
         TSF_SIZES(TSF_CASE)
 #undef TSF_CASE
         default: return hipErrorInvalidValue;
@@ -365,13 +387,31 @@ OutSpec out_spec(tsfcde_plan_s *pl, const RT &rt) {
 
 InSpec in_spec(tsfcde_plan_s *pl, const RT &rt) { return InSpec{buf_of(pl, rt), rt.tw, rt.C}; }
 
+template <class CS> OutSpecT<CS> out_spec_on(CS *buf, const RT &rt) {
+    OutSpecT<CS> o{buf, rt.tw, rt.C};
+    o.partials = nullptr;
+    return o;
+}
+template <class CS> InSpecT<CS> in_spec_on(const CS *buf, const RT &rt) { return InSpecT<CS>{buf, rt.tw, rt.C}; }
+
+// run_op on an explicit transform buffer (any storage type)
+template <int MODE, class CS, class In, class Out>
+hipError_t run_op_on(tsfcde_plan_s *pl, const RT &rt, CS *buf, const CS *spec, const SymParams &sp, const In &in,
+                     const Out &out, int pred) {
+    hipError_t e = launch_col<-1>(pl, rt, in, out_spec_on(buf, rt), pred);
+    if (e != hipSuccess) return e;
+    e = launch_mid<MODE>(pl, rt, buf, spec, (double2 *)nullptr, sp, pred);
+    if (e != hipSuccess) return e;
+    return launch_col<1>(pl, rt, in_spec_on<CS>(buf, rt), out, pred);
+}
+
 // y-side of an operator: pass A with loader `in`, middle, pass C with store `out`.
 template <int MODE, class In, class Out>
 hipError_t run_op(tsfcde_plan_s *pl, const RT &rt, const double2 *spec, const SymParams &sp, const In &in,
                   const Out &out, int pred) {
     hipError_t e = launch_col<-1>(pl, rt, in, out_spec(pl, rt), pred);
     if (e != hipSuccess) return e;
-    e = launch_mid<MODE>(pl, rt, buf_of(pl, rt), spec, nullptr, sp, pred);
+    e = launch_mid<MODE>(pl, rt, buf_of(pl, rt), spec, (double2 *)nullptr, sp, pred);
     if (e != hipSuccess) return e;
     return launch_col<1>(pl, rt, in_spec(pl, rt), out, pred);
 }
@@ -406,7 +446,12 @@ hipError_t precond_level(tsfcde_plan_s *pl, int64_t j) {
     if ((e = launch_col<-1>(pl, pl->A, InReal{pl->tmp, pl->A.L, pl->A.C}, out_spec(pl, pl->A), 0)) != hipSuccess)
         return e;
     SymParams none{};
-    if ((e = launch_mid<2>(pl, pl->A, pl->buf, nullptr, pl->specPj, none, 0)) != hipSuccess) return e;
+    if ((e = launch_mid<2>(pl, pl->A, pl->buf, (const double2 *)nullptr, pl->specPj, none, 0)) != hipSuccess)
+        return e;
+    if (pl->fp32) {
+        hipLaunchKernelGGL(k_to_f32, dim3(512), dim3(256), 0, pl->stream, pl->specPj, pl->specPj32, pl->A.N);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     pl->pj_level = j;
     return hipSuccess;
 }
@@ -421,53 +466,79 @@ int poll(tsfcde_plan_s *pl) {
     return TSFCDE_OK;
 }
 
+// Vectors and transform buffers of one CGS solve: the FP64 ones of the plan, or
+// the FP32-stored ones of the inner solve of the refinement loop.
+template <class S, class CS> struct Bufs {
+    S *r, *rt, *u, *p, *q, *phat, *vhat, *uhat;
+    CS *buf, *bufP;
+    const CS *specA, *specP, *specPj;
+};
+
+Bufs<double, double2> bufs64(tsfcde_plan_s *pl) {
+    return {pl->r, pl->rt, pl->u, pl->p, pl->q, pl->phat, pl->vhat, pl->uhat,
+            pl->buf, pl->bufP, pl->specA, pl->specP, pl->specPj};
+}
+
+Bufs<float, float2> bufs32(tsfcde_plan_s *pl) {
+    return {pl->r32, pl->rt32, pl->u32, pl->p32, pl->q32, pl->phat32, pl->vhat32, pl->uhat32,
+            pl->buf32, pl->bufP32, pl->specA32, pl->specP32, pl->specPj32};
+}
+
 // One CGS iteration (Templates-style preconditioned CGS, Sec. 3.2 "PCGS"),
-// ten kernels:
+// ten kernels (plus the two finishing kernels of the reductions):
 //  u = r + beta q ; p = u + beta (q + beta p)      [K1 prologue]
 //  phat = P^{-1} p ; vhat = A phat               [K1, K2, K3 (fused), K4, K5]
 //  alpha = rho / (rt . vhat)                     [K5 epilogue]
 //  q = u - alpha vhat ; uhat = P^{-1} (u + q)     [K6 prologue, K7]
 //  x += alpha uhat ; r -= alpha A uhat            [K8 (fused), K9, K10], rho' = rt . r
-hipError_t cgs_iteration(tsfcde_plan_s *pl, int64_t j, double *x) {
+template <class S, class CS>
+hipError_t cgs_iteration(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x) {
     const int64_t n = pl->n;
     const SymParams sP = symbol(pl, j, -pl->sigma, pl->P, true);
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
     hipError_t e;
-    InCgsUP k1{pl->r, pl->u, pl->p, pl->q, n, pl->P.C, 0.0, false};
-    if ((e = launch_col<-1>(pl, pl->P, k1, out_spec(pl, pl->P), 1)) != hipSuccess) return e;
-    if ((e = launch_mid<1>(pl, pl->P, pl->bufP, pl->specP, nullptr, sP, 1)) != hipSuccess) return e;
-    if ((e = launch_fuse(pl, OpIdent{}, 1)) != hipSuccess) return e;
-    if ((e = launch_mid<0>(pl, pl->A, pl->buf, pl->specA, nullptr, sA, 1)) != hipSuccess) return e;
-    OutCgsDot k5 = with_red(OutCgsDot{pl->vhat, pl->rt, n, pl->A.C}, pl, 0);
-    if ((e = launch_col<1>(pl, pl->A, in_spec(pl, pl->A), k5, 1)) != hipSuccess) return e;
-    InCgsQ k6{pl->u, pl->vhat, pl->q, n, pl->P.C, 0.0};
-    if ((e = launch_col<-1>(pl, pl->P, k6, out_spec(pl, pl->P), 1)) != hipSuccess) return e;
-    if ((e = launch_mid<1>(pl, pl->P, pl->bufP, pl->specP, nullptr, sP, 1)) != hipSuccess) return e;
-    if ((e = launch_fuse(pl, OpCgsX{x, pl->A.C, 0.0}, 1)) != hipSuccess) return e;
-    if ((e = launch_mid<0>(pl, pl->A, pl->buf, pl->specA, nullptr, sA, 1)) != hipSuccess) return e;
-    OutCgsR k10 = with_red(OutCgsR{pl->r, pl->rt, n, pl->A.C, 0.0}, pl, 1);
-    return launch_col<1>(pl, pl->A, in_spec(pl, pl->A), k10, 1);
+    InCgsUPT<S> k1{b.r, b.u, b.p, b.q, n, pl->P.C, 0.0, false};
+    if ((e = launch_col<-1>(pl, pl->P, k1, out_spec_on(b.bufP, pl->P), 1)) != hipSuccess) return e;
+    if ((e = launch_mid<1>(pl, pl->P, b.bufP, b.specP, (double2 *)nullptr, sP, 1)) != hipSuccess) return e;
+    if ((e = launch_fuse(pl, OpIdent{}, b.bufP, b.buf, 1)) != hipSuccess) return e;
+    if ((e = launch_mid<0>(pl, pl->A, b.buf, b.specA, (double2 *)nullptr, sA, 1)) != hipSuccess) return e;
+    OutCgsDotT<S> k5 = with_red(OutCgsDotT<S>{b.vhat, b.rt, n, pl->A.C}, pl, 0);
+    if ((e = launch_col<1>(pl, pl->A, in_spec_on<CS>(b.buf, pl->A), k5, 1)) != hipSuccess) return e;
+    InCgsQT<S> k6{b.u, b.vhat, b.q, n, pl->P.C, 0.0};
+    if ((e = launch_col<-1>(pl, pl->P, k6, out_spec_on(b.bufP, pl->P), 1)) != hipSuccess) return e;
+    if ((e = launch_mid<1>(pl, pl->P, b.bufP, b.specP, (double2 *)nullptr, sP, 1)) != hipSuccess) return e;
+    if ((e = launch_fuse(pl, OpCgsXT<S>{x, pl->A.C, 0.0}, b.bufP, b.buf, 1)) != hipSuccess) return e;
+    if ((e = launch_mid<0>(pl, pl->A, b.buf, b.specA, (double2 *)nullptr, sA, 1)) != hipSuccess) return e;
+    OutCgsRT<S> k10 = with_red(OutCgsRT<S>{b.r, b.rt, n, pl->A.C, 0.0}, pl, 1);
+    return launch_col<1>(pl, pl->A, in_spec_on<CS>(b.buf, pl->A), k10, 1);
 }
 
 // The same iteration for general n: the preconditioner solve is a Toeplitz
 // product with the level's inverse-Strang spectrum (12 kernels).
-hipError_t cgs_iteration_general(tsfcde_plan_s *pl, int64_t j, double *x) {
+template <class S, class CS>
+hipError_t cgs_iteration_general(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x) {
     const int64_t n = pl->n;
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
     const SymParams sI = unit_symbol(pl->A);
     const int64_t C = pl->A.C;
     hipError_t e;
-    OutReal o1{pl->phat, n, C};
+    OutRealT<S> o1{b.phat, n, C};
     o1.partials = nullptr;
-    if ((e = run_op<0>(pl, pl->A, pl->specPj, sI, InCgsUP{pl->r, pl->u, pl->p, pl->q, n, C, 0.0, false}, o1, 1)))
+    if ((e = run_op_on<0>(pl, pl->A, b.buf, b.specPj, sI, InCgsUPT<S>{b.r, b.u, b.p, b.q, n, C, 0.0, false}, o1,
+                          1)))
         return e;
-    OutCgsDot o2 = with_red(OutCgsDot{pl->vhat, pl->rt, n, C}, pl, 0);
-    if ((e = run_op<0>(pl, pl->A, pl->specA, sA, InReal{pl->phat, n, C}, o2, 1))) return e;
-    OutReal o3{pl->uhat, n, C};
+    OutCgsDotT<S> o2 = with_red(OutCgsDotT<S>{b.vhat, b.rt, n, C}, pl, 0);
+    if ((e = run_op_on<0>(pl, pl->A, b.buf, b.specA, sA, InRealT<S>{b.phat, n, C}, o2, 1))) return e;
+    OutRealT<S> o3{b.uhat, n, C};
     o3.partials = nullptr;
-    if ((e = run_op<0>(pl, pl->A, pl->specPj, sI, InCgsQ{pl->u, pl->vhat, pl->q, n, C, 0.0}, o3, 1))) return e;
-    OutCgsR o4 = with_red(OutCgsR{pl->r, pl->rt, n, C, 0.0}, pl, 1);
-    return run_op<0>(pl, pl->A, pl->specA, sA, InCgsX{pl->uhat, x, n, C, 0.0}, o4, 1);
+    if ((e = run_op_on<0>(pl, pl->A, b.buf, b.specPj, sI, InCgsQT<S>{b.u, b.vhat, b.q, n, C, 0.0}, o3, 1))) return e;
+    OutCgsRT<S> o4 = with_red(OutCgsRT<S>{b.r, b.rt, n, C, 0.0}, pl, 1);
+    return run_op_on<0>(pl, pl->A, b.buf, b.specA, sA, InCgsXT<S>{b.uhat, x, n, C, 0.0}, o4, 1);
+}
+
+template <class S, class CS>
+hipError_t cgs_iter(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x) {
+    return pl->p2 ? cgs_iteration(pl, j, b, x) : cgs_iteration_general(pl, j, b, x);
 }
 
 int level_rhs(tsfcde_plan_s *pl, int64_t j, const double *d_f, double *x, int warm) {
@@ -504,17 +575,202 @@ constexpr int MAX_RESTARTS = 3;
 
 // y = A x and r = g - y, rt = r (restart from the current iterate); queued
 // on the stream, no synchronisation.
-int restart_launch(tsfcde_plan_s *pl, int64_t j, const double *x) {
+// r = g - A x, rt = r and a fresh CGS state; x itself is accepted when it
+// meets rtol or, with bwtol > 0, the backward-error test.
+int restart_launch(tsfcde_plan_s *pl, int64_t j, const double *x, double bwtol) {
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
     InReal in{x, pl->n, pl->A.C};
-    OutRestart out = with_red(OutRestart{pl->g, pl->r, pl->rt, pl->n, pl->A.C}, pl, 3);
+    OutRestart out =
+        with_red(OutRestart{pl->g, x, pl->r, pl->rt, pl->n, pl->A.C, pl->anorm[j], bwtol}, pl, 3);
     HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
     return TSFCDE_OK;
 }
 
-int restart_from_x(tsfcde_plan_s *pl, int64_t j, const double *x) {
-    int rc = restart_launch(pl, j, x);
+int restart_from_x(tsfcde_plan_s *pl, int64_t j, const double *x, double bwtol) {
+    int rc = restart_launch(pl, j, x, bwtol);
     return rc ? rc : poll(pl);
+}
+
+// FP64 CGS on A x = g from the state the device scalars describe (after the
+// right-hand side or a restart): chunks of iterations between polls, then
+// breakdown recovery and, with TSFCDE_FLAG_VERIFY, true-residual checks.
+struct SolveOut {
+    int code = TSFCDE_OK, restarts = 0, iters = 0;
+    double relres_true = -1.0, backward_err = -1.0;
+};
+
+// Normwise backward error |g - A x| / (|A| |x| + |g|) from the last restart
+// pass (aux0 = |g - A x|^2, aux1 = |x|^2), with |A|_2 bounded from above.
+double backward_error(const tsfcde_plan_s *pl, int64_t j) {
+    const DevScalars &h = *pl->h_sc;
+    const double den = pl->anorm[j] * std::sqrt(h.aux1) + std::sqrt(h.gnorm2);
+    return den > 0 ? std::sqrt(h.aux0) / den : 0.0;
+}
+
+
+int fp64_cgs(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so) {
+    const bool verify = (pl->flags & TSFCDE_FLAG_VERIFY) != 0;
+    const Bufs<double, double2> b64 = bufs64(pl);
+    int rc, iters_seen = 0;
+    double last_true2 = HUGE_VAL;
+    int chunk = std::max(2, pl->last_iters);
+    for (;;) {
+        // CGS until the device reports done or maxit is reached
+        for (;;) {
+            const int todo = std::min(chunk, pl->maxit - iters_seen);
+            if (todo <= 0) break;
+            for (int k = 0; k < todo; ++k)
+                HIPCHK(cgs_iter(pl, j, b64, x));
+            if ((rc = poll(pl))) return rc;
+            iters_seen = pl->h_sc->iter;
+            if (pl->h_sc->done) break;
+            chunk = 2;
+        }
+        if (!pl->h_sc->done) {
+            so.code = TSFCDE_ENOCONV;
+            break;
+        }
+        const int stat = pl->h_sc->status;
+        if (stat == ST_NONFINITE) {
+            so.code = TSFCDE_ENONFINITE;
+            break;
+        }
+        if (stat == ST_BREAKDOWN && so.restarts >= MAX_RESTARTS) {
+            so.code = TSFCDE_EBREAKDOWN;
+            break;
+        }
+        // restart from x: recovers from a breakdown, and checks a converged
+        // level (backward error; with TSFCDE_FLAG_VERIFY also the true
+        // residual against rtol |g|), continuing CGS from x when it fails
+        if ((rc = restart_from_x(pl, j, x, verify ? 0.0 : BW_TOL))) return rc;
+        so.relres_true = pl->h_sc->gnorm2 > 0 ? std::sqrt(pl->h_sc->aux0 / pl->h_sc->gnorm2) : 0.0;
+        so.backward_err = backward_error(pl, j);
+        if (pl->h_sc->done) {
+            so.code = status_code(pl->h_sc->status);
+            break;
+        }
+        if (stat == ST_OK) {
+            if (verify) {
+                // true residual above tolerance: continue while it keeps falling
+                if (so.restarts >= MAX_RESTARTS || !(pl->h_sc->aux0 < 0.25 * last_true2)) break;
+                last_true2 = pl->h_sc->aux0;
+            } else if (so.restarts >= MAX_RESTARTS) {
+                break;  // x stays as it is
+            }
+        }
+        ++so.restarts;
+        if (iters_seen >= pl->maxit) {
+            so.code = TSFCDE_ENOCONV;
+            break;
+        }
+        chunk = std::max(2, pl->last_iters / 2);
+    }
+    so.iters = pl->h_sc->iter;
+    pl->last_iters = std::max(1, so.iters / (so.restarts + 1));
+    return TSFCDE_OK;
+}
+
+// FP32-refined form.  The level's rounding-error model: an FP32-stored
+// transform of a vector v errs by about eps32 * log2(L) * |v| in every
+// frequency, and A multiplies that error by up to |A| while a smooth
+// correction d has |A d| near eta |d|, so the inner products are useful only
+// while eps32 * log2(L) * |A| / eta is well below one.  |A| / eta is bounded
+// by Remark 3.1 (|lambda(W)| <= 2 |omega_1|) and |eig(Q)| <= 2.
+constexpr double EPS32 = 5.9604644775390625e-08;  // 2^-24
+constexpr double IR_MODEL_LIMIT = 0.1;
+constexpr int IR_MAX_OUTER = 30;
+constexpr int IR_INNER_MAXIT = 64;
+
+bool level_uses_fp32(const tsfcde_plan_s *pl, int64_t j) {
+    if (!pl->fp32) return false;
+    if (pl->flags & TSFCDE_FLAG_FORCE_FP32) return true;
+    return EPS32 * (double)ilog2(pl->A.L) * pl->kbound[j] < IR_MODEL_LIMIT;
+}
+
+// Inner tolerance: what the FP32-stored operator can resolve, at least 1e-5.
+double ir_inner_rtol(const tsfcde_plan_s *pl, int64_t j) {
+    return std::min(0.5, std::max(1e-5, 8.0 * EPS32 * pl->kbound[j]));
+}
+
+// Iterative refinement: r = g - A x in FP64 (x += d folded into the same
+// pass), then the FP32-stored inner CGS solves A d = r to the inner
+// tolerance, and again until |g - A x| <= rtol |g|.  The stopping test is the
+// true FP64 residual.  On a non-finite inner result, or when a sweep no longer
+// halves the residual, the level continues with the FP64 CGS from x.
+int ir_solve(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so, int &outer, bool &fell_back) {
+    const int64_t n = pl->n;
+    const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
+    const double irtol = ir_inner_rtol(pl, j);
+    const Bufs<float, float2> b32 = bufs32(pl);
+    int rc, inner_total = 0, slow = 0;
+    double prev2 = HUGE_VAL;
+    outer = 0;
+    fell_back = false;
+    // no correction is pending when a level starts
+    hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, pl->stream, pl->d32, 0.0f, n);
+    HIPCHK(hipGetLastError());
+    for (;;) {
+        InIR in{x, pl->d32, n, pl->A.C};
+        OutIR out = with_red(OutIR{pl->g, x, pl->r32, pl->rt32, pl->d32, n, pl->A.C, irtol * irtol}, pl, 2);
+        HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
+        if ((rc = poll(pl))) return rc;
+        ++outer;
+        const double res2 = pl->h_sc->aux1;
+        so.relres_true = pl->h_sc->gnorm2 > 0 ? std::sqrt(res2 / pl->h_sc->gnorm2) : 0.0;
+        {
+            const double den = pl->anorm[j] * std::sqrt(pl->h_sc->aux0) + std::sqrt(pl->h_sc->gnorm2);
+            so.backward_err = den > 0 ? std::sqrt(res2) / den : 0.0;
+        }
+        if (pl->h_sc->status == ST_NONFINITE) {
+            so.code = TSFCDE_ENONFINITE;
+            break;
+        }
+        if (pl->h_sc->done) break;
+        slow = res2 > 0.25 * prev2 ? slow + 1 : 0;
+        prev2 = res2;
+        if (slow >= 2 || outer > IR_MAX_OUTER || inner_total >= pl->maxit) {
+            fell_back = true;
+            break;
+        }
+        // inner FP32-stored CGS on A d = r (d = 0, rt = r set by the pass above)
+        int seen = 0, chunk = std::max(2, pl->last_inner);
+        // a sweep ends at the inner tolerance or after IR_INNER_MAXIT steps: a
+        // stalled inner CGS is restarted by the next sweep with a fresh rt
+        const int budget = std::min(IR_INNER_MAXIT, pl->maxit - inner_total);
+        for (;;) {
+            const int todo = std::min(chunk, budget - seen);
+            if (todo <= 0) break;
+            for (int k = 0; k < todo; ++k) HIPCHK(cgs_iter(pl, j, b32, pl->d32));
+            if ((rc = poll(pl))) return rc;
+            seen = pl->h_sc->iter;
+            if (pl->h_sc->done) break;
+            chunk = 2;
+        }
+        inner_total += seen;
+        pl->last_inner = std::max(2, seen);
+        if (pl->h_sc->status == ST_NONFINITE) {
+            fell_back = true;
+            break;
+        }
+    }
+    so.iters = inner_total;
+    if (fell_back && so.code == TSFCDE_OK) {
+        // continue in FP64 from x (the pending correction d is dropped)
+        if ((rc = restart_from_x(pl, j, x, (pl->flags & TSFCDE_FLAG_VERIFY) ? 0.0 : BW_TOL))) return rc;
+        if (!pl->h_sc->done) {
+            const int base = pl->h_sc->iter;  // the restart keeps the inner count
+            SolveOut f;
+            if ((rc = fp64_cgs(pl, j, x, f))) return rc;
+            so.code = f.code;
+            so.restarts = f.restarts;
+            so.iters += f.iters - base;
+            so.relres_true = f.relres_true;
+            so.backward_err = f.backward_err;
+        } else {
+            so.code = status_code(pl->h_sc->status);
+        }
+    }
+    return TSFCDE_OK;
 }
 
 int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_stats *st) {
@@ -528,63 +784,21 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
     if (pl->warm == TSFCDE_WS_EXTRAP) warm = j >= 2 ? 2 : (j >= 1 ? 1 : 0);
     int rc = level_rhs(pl, j, d_f, x, warm);
     if (rc) return rc;
-    if (warm == 2 && (rc = restart_launch(pl, j, x))) return rc;  // r0 = g - A x0
     HIPCHK(precond_level(pl, j));
-    const bool verify = (pl->flags & TSFCDE_FLAG_VERIFY) != 0;
-    int code = TSFCDE_OK, restarts = 0, iters_seen = 0;
-    double relres_true = -1.0, last_true2 = HUGE_VAL;
-    int chunk = std::max(2, pl->last_iters);
+    SolveOut so;
+    int outer = 1;
+    bool fp32 = level_uses_fp32(pl, j), fell_back = false;
     {
         ProfScope ps(pl, 3);
-        for (;;) {
-            // CGS until the device reports done or maxit is reached
-            for (;;) {
-                const int todo = std::min(chunk, pl->maxit - iters_seen);
-                if (todo <= 0) break;
-                for (int k = 0; k < todo; ++k)
-                    HIPCHK(pl->p2 ? cgs_iteration(pl, j, x) : cgs_iteration_general(pl, j, x));
-                if ((rc = poll(pl))) return rc;
-                iters_seen = pl->h_sc->iter;
-                if (pl->h_sc->done) break;
-                chunk = 2;
-            }
-            if (!pl->h_sc->done) {
-                code = TSFCDE_ENOCONV;
-                break;
-            }
-            const int stat = pl->h_sc->status;
-            if (stat == ST_NONFINITE) {
-                code = TSFCDE_ENONFINITE;
-                break;
-            }
-            if (stat == ST_BREAKDOWN && restarts >= MAX_RESTARTS) {
-                code = TSFCDE_EBREAKDOWN;
-                break;
-            }
-            if (stat == ST_OK && !verify) break;
-            // restart from x: recovers from a breakdown, or verifies the true
-            // residual |g - A x| against the recursive one and continues on a gap
-            if ((rc = restart_from_x(pl, j, x))) return rc;
-            relres_true = pl->h_sc->gnorm2 > 0 ? std::sqrt(pl->h_sc->aux0 / pl->h_sc->gnorm2) : 0.0;
-            if (pl->h_sc->done) {
-                code = status_code(pl->h_sc->status);
-                break;
-            }
-            if (stat == ST_OK) {
-                // true residual above tolerance: continue while it keeps falling
-                if (restarts >= MAX_RESTARTS || !(pl->h_sc->aux0 < 0.25 * last_true2)) break;
-                last_true2 = pl->h_sc->aux0;
-            }
-            ++restarts;
-            if (iters_seen >= pl->maxit) {
-                code = TSFCDE_ENOCONV;
-                break;
-            }
-            chunk = std::max(2, pl->last_iters / 2);
+        if (fp32) {
+            if ((rc = ir_solve(pl, j, x, so, outer, fell_back))) return rc;
+        } else {
+            if (warm == 2 && (rc = restart_launch(pl, j, x, 0.0))) return rc;  // r0 = g - A x0
+            if ((rc = fp64_cgs(pl, j, x, so))) return rc;
         }
     }
     const DevScalars hs = *pl->h_sc;
-    pl->last_iters = std::max(1, hs.iter / (restarts + 1));
+    double relres_true = so.relres_true;
     if (relres_true < 0 && (pl->flags & TSFCDE_FLAG_TRUE_RESIDUAL)) {
         const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
         InReal in{x, n, pl->A.C};
@@ -596,16 +810,18 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
     if (d_u_out) HIPCHK(hipMemcpyAsync(d_u_out, x, sizeof(double) * n, hipMemcpyDeviceToDevice, pl->stream));
     pl->level = j + 1;
     if (st) {
-        st->iters = hs.iter;
-        st->outer_iters = 1;
-        st->restarts = restarts;
-        st->status = code;
-        st->relres = hs.gnorm2 > 0 ? std::sqrt(hs.rnorm2 / hs.gnorm2) : 0.0;
+        st->iters = so.iters;
+        st->outer_iters = fp32 ? outer : 1;
+        st->restarts = so.restarts;
+        st->status = so.code;
+        st->relres = (fp32 && !fell_back) ? relres_true
+                                           : (hs.gnorm2 > 0 ? std::sqrt(hs.rnorm2 / hs.gnorm2) : 0.0);
         st->relres_true = relres_true;
-        st->backward_err = -1.0;
+        st->backward_err = so.backward_err;
+        st->precision_used = fp32 ? (fell_back ? TSFCDE_FP32_REFINED_FELL_BACK : TSFCDE_FP32_REFINED) : TSFCDE_FP64;
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
-    return code;
+    return so.code;
 }
 
 double sample(tsfcde_coef_fn fn, const double *arr, void *user, int64_t j, double t) {
@@ -622,7 +838,7 @@ static int workspace_bytes_impl(const tsfcde_problem *prob, bool force_general, 
     if (!bytes) return TSFCDE_EINVAL;
     RT A, P, B;
     const bool p2 = rt_setup(A, P, B, prob->n, force_general);
-    *bytes = layout_for(prob->n, prob->M, A, P, B, p2).total;
+    *bytes = layout_for(prob->n, prob->M, A, P, B, p2, prob->precision == TSFCDE_FP32_REFINED).total;
     return TSFCDE_OK;
 }
 
@@ -690,7 +906,37 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
     }
     pl->p2 = rt_setup(pl->A, pl->P, pl->B, n, force_general);
     pl->ldn = ld_of(n);
-    pl->lay = layout_for(n, M, pl->A, pl->P, pl->B, pl->p2);
+    // |A|_2 <= eta + sigma (|gamma|/h + (d+ + d-) h^-beta sum_k |omega_k|): A is
+    // eta I - sigma L with |Q|_2 <= 2 and |W|_2 <= max(|W|_1, |W|_inf) <= sum |omega_k|
+    {
+        const double b = prob->beta;
+        const double l1 = (b * b + 3.0 * b + 2.0) / 12.0, l0 = (4.0 - b * b) / 6.0, lm1 = (b * b - 3.0 * b + 2.0) / 12.0;
+        double gkm2 = 0.0, gkm1 = 0.0, gk = 1.0, sabs = 0.0;  // g_{k-2}, g_{k-1}, g_k (Lemma 3 recurrence)
+        for (int64_t k = 0; k <= n; ++k) {
+            if (k > 0) {
+                gkm2 = gkm1;
+                gkm1 = gk;
+                gk = (1.0 - (b + 1.0) / (double)k) * gkm1;
+            }
+            const double om = l1 * gk + (k >= 1 ? l0 * gkm1 : 0.0) + (k >= 2 ? lm1 * gkm2 : 0.0);
+            sabs += std::fabs(om);
+        }
+        pl->anorm.resize(M);
+        for (int64_t j = 0; j < M; ++j)
+            pl->anorm[j] = pl->eta[j] + pl->sigma * (std::fabs(pl->gam[j]) / pl->h + (pl->dp[j] + pl->dm[j]) * pl->hb * sabs);
+    }
+    pl->fp32 = prob->precision == TSFCDE_FP32_REFINED;
+    pl->lay = layout_for(n, M, pl->A, pl->P, pl->B, pl->p2, pl->fp32);
+    if (pl->fp32) {
+        // |A| / eta <= 1 + sigma (|gamma|/h + (d+ + d-) h^-beta 2|omega_1|) / eta  (Remark 3.1, eig(Q))
+        const double b = prob->beta;
+        const double om1 = std::fabs(-b * (b * b + 3.0 * b + 2.0) / 12.0 + (4.0 - b * b) / 6.0);
+        pl->kbound.resize(M);
+        for (int64_t j = 0; j < M; ++j)
+            pl->kbound[j] = 1.0 + pl->sigma *
+                                      (std::fabs(pl->gam[j]) / pl->h + (pl->dp[j] + pl->dm[j]) * pl->hb * 2.0 * om1) /
+                                      pl->eta[j];
+    }
     if (bytes < pl->lay.total) {
         delete pl;
         return TSFCDE_ENOMEM;
@@ -735,6 +981,17 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
     pl->B.tw = Tw2{pl->B.lo, pl->B.hi, pl->B.shift};
     pl->part = reinterpret_cast<double *>(ws + L.off_part);
     pl->sc = reinterpret_cast<DevScalars *>(ws + L.off_sc);
+    {
+        float *v32 = reinterpret_cast<float *>(ws + L.off_v32);
+        float **vq[NV32] = {&pl->r32, &pl->rt32, &pl->u32, &pl->p32, &pl->q32,
+                            &pl->phat32, &pl->vhat32, &pl->uhat32, &pl->d32};
+        for (int k = 0; k < NV32; ++k) *vq[k] = pl->fp32 ? v32 + (size_t)k * pl->ldn : nullptr;
+        pl->buf32 = reinterpret_cast<float2 *>(ws + L.off_buf32);
+        pl->bufP32 = reinterpret_cast<float2 *>(ws + L.off_bufP32);
+        pl->specA32 = reinterpret_cast<float2 *>(ws + L.off_specA32);
+        pl->specP32 = reinterpret_cast<float2 *>(ws + L.off_specP32);
+        pl->specPj32 = reinterpret_cast<float2 *>(ws + L.off_specPj32);
+    }
 
     auto fail = [&](int code) {
         if (pl->h_sc) (void)hipHostFree(pl->h_sc);
@@ -774,12 +1031,13 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
         InReal in{pl->tmp, pl->A.L, pl->A.C};
         if (launch_col<-1>(pl, pl->A, in, out_spec(pl, pl->A), 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
         SymParams sp{};
-        if (launch_mid<2>(pl, pl->A, pl->buf, nullptr, pl->specA, sp, 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
+        if (launch_mid<2>(pl, pl->A, pl->buf, (const double2 *)nullptr, pl->specA, sp, 0) != hipSuccess)
+            return fail(TSFCDE_EDEVICE);
         hipLaunchKernelGGL(k_strang_column, dim3(512), dim3(256), 0, pl->stream, pl->w, n, pl->tmp);
         if (pl->p2) {
             InReal inP{pl->tmp, n, pl->P.C};
             if (launch_col<-1>(pl, pl->P, inP, out_spec(pl, pl->P), 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
-            if (launch_mid<2>(pl, pl->P, pl->bufP, nullptr, pl->specP, sp, 0) != hipSuccess)
+            if (launch_mid<2>(pl, pl->P, pl->bufP, (const double2 *)nullptr, pl->specP, sp, 0) != hipSuccess)
                 return fail(TSFCDE_EDEVICE);
         } else {
             // Bluestein set-up: chirp, the spectrum of its circular arrangement
@@ -796,6 +1054,13 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
             if (launch_row<4>(pl, pl->bufB, nullptr, pl->Bhat) != hipSuccess) return fail(TSFCDE_EDEVICE);
             if (bluestein(pl, nullptr, pl->tmp, pl->Ls) != hipSuccess) return fail(TSFCDE_EDEVICE);
         }
+    }
+    // FP32 copies of the spectra for the inner solve of the FP32-refined form
+    if (pl->fp32) {
+        hipLaunchKernelGGL(k_to_f32, dim3(512), dim3(256), 0, pl->stream, pl->specA, pl->specA32, pl->A.N);
+        if (pl->p2)
+            hipLaunchKernelGGL(k_to_f32, dim3(512), dim3(256), 0, pl->stream, pl->specP, pl->specP32, pl->P.N);
+        if (hipGetLastError() != hipSuccess) return fail(TSFCDE_EDEVICE);
     }
     // u^0 = phi(x_i)
     {
@@ -976,7 +1241,7 @@ const char *tsfcde_strerror(int s) {
 // ===========================================================================
 struct DoneRec {
     int done, status, iter, pad;
-    double rnorm2, gnorm2;
+    double rnorm2, gnorm2, aux0, aux1;
 };
 
 namespace tsf {
@@ -991,6 +1256,8 @@ __global__ void k_gather_state(DevScalars *const *__restrict__ scs, int count, D
         r.pad = 0;
         r.rnorm2 = s->rnorm2;
         r.gnorm2 = s->gnorm2;
+        r.aux0 = s->aux0;
+        r.aux1 = s->aux1;
         out[i] = r;
     }
 }
@@ -1111,7 +1378,7 @@ template <class Out> Out nored(Out o) {
 struct GroupDesc {
     ColDesc<InReal, OutSpec> *rhsA, *rstA, *r2cA, *s4;
     ColDesc<InSpec, OutRhs> *rhsC;
-    ColDesc<InSpec, OutRestart> *rstC;
+    ColDesc<InSpec, OutRestart> *rstC, *vfyC;
     MidDesc *midA, *midR2C, *midP;
     ColDesc<InCplx, OutSpec> *bsA;
     RowDesc *bsRow;
@@ -1128,7 +1395,7 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
                  GroupDesc &D) {
     std::vector<ColDesc<InReal, OutSpec>> rhsA, rstA, r2cA, s4;
     std::vector<ColDesc<InSpec, OutRhs>> rhsC;
-    std::vector<ColDesc<InSpec, OutRestart>> rstC;
+    std::vector<ColDesc<InSpec, OutRestart>> rstC, vfyC;
     std::vector<MidDesc> midA, midR2C, midP;
     std::vector<ColDesc<InCplx, OutSpec>> bsA;
     std::vector<RowDesc> bsRow;
@@ -1157,7 +1424,9 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
         midA.push_back(MidDesc{pl->A.R, pl->buf, pl->specA, nullptr, pl->A.tw, sA, pl->sc});
         // restart from an extrapolated guess
         rstA.push_back(cdesc(pl, C, InReal{x, n, C}, osA));
-        rstC.push_back(cdesc(pl, C, isA, with_red(OutRestart{pl->g, pl->r, pl->rt, n, C}, pl, 3)));
+        rstC.push_back(cdesc(pl, C, isA, with_red(OutRestart{pl->g, x, pl->r, pl->rt, n, C, pl->anorm[j], 0.0}, pl, 3)));
+        // acceptance check of a converged instance (backward error)
+        vfyC.push_back(cdesc(pl, C, isA, with_red(OutRestart{pl->g, x, pl->r, pl->rt, n, C, pl->anorm[j], BW_TOL}, pl, 3)));
         // inverse Strang circulant of level j: Bluestein DFT and embedding spectrum
         OutSpec osB{pl->bufB, pl->B.tw, CB};
         bsA.push_back(cdesc(pl, CB, InCplx{pl->wv, nullptr, pl->chirp, n, CB}, nored(osB)));
@@ -1182,6 +1451,7 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
     D.midA = S.put(midA);
     D.rstA = S.put(rstA);
     D.rstC = S.put(rstC);
+    D.vfyC = S.put(vfyC);
     D.bsA = S.put(bsA);
     D.bsRow = S.put(bsRow);
     D.bsC = S.put(bsC);
@@ -1288,59 +1558,96 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
         BCHK(blaunch_mid<2>(bt, G.A, gd[g].midR2C, c, 0));
     }
     for (tsfcde_plan_s *pl : bt->plans) pl->pj_level = j;
-    // CGS, every instance on its own convergence flag
-    int iters_seen = 0, chunk = std::max(2, bt->last_iters);
+    // CGS, every instance on its own convergence flag; then every instance's
+    // answer is checked (backward error) and the ones that fail restart from x
+    int iters_seen = 0, chunk = std::max(2, bt->last_iters), rounds = 0;
+    std::vector<int> restarts(cnt, 0);
     for (;;) {
-        const int todo = std::min(chunk, bt->maxit - iters_seen);
-        if (todo <= 0) break;
-        for (int k = 0; k < todo; ++k) {
-            for (size_t g = 0; g < bt->groups.size(); ++g) {
-                const BatchGroup &G = bt->groups[g];
-                const int c = (int)G.members.size();
-                const GroupDesc &D = gd[g];
-                BCHK(blaunch_col<-1>(bt, G.A, D.s1, c, 1));
-                BCHK(blaunch_mid<0>(bt, G.A, D.midP, c, 1));
-                BCHK(blaunch_col<1>(bt, G.A, D.s3, c, 1));
-                BCHK(blaunch_col<-1>(bt, G.A, D.s4, c, 1));
-                BCHK(blaunch_mid<0>(bt, G.A, D.midA, c, 1));
-                BCHK(blaunch_col<1>(bt, G.A, D.s6, c, 1));
-                BCHK(blaunch_col<-1>(bt, G.A, D.s7, c, 1));
-                BCHK(blaunch_mid<0>(bt, G.A, D.midP, c, 1));
-                BCHK(blaunch_col<1>(bt, G.A, D.s9, c, 1));
-                BCHK(blaunch_col<-1>(bt, G.A, D.s10, c, 1));
-                BCHK(blaunch_mid<0>(bt, G.A, D.midA, c, 1));
-                BCHK(blaunch_col<1>(bt, G.A, D.s12, c, 1));
+        for (;;) {
+            const int todo = std::min(chunk, bt->maxit - iters_seen);
+            if (todo <= 0) break;
+            for (int k = 0; k < todo; ++k) {
+                for (size_t g = 0; g < bt->groups.size(); ++g) {
+                    const BatchGroup &G = bt->groups[g];
+                    const int c = (int)G.members.size();
+                    const GroupDesc &D = gd[g];
+                    BCHK(blaunch_col<-1>(bt, G.A, D.s1, c, 1));
+                    BCHK(blaunch_mid<0>(bt, G.A, D.midP, c, 1));
+                    BCHK(blaunch_col<1>(bt, G.A, D.s3, c, 1));
+                    BCHK(blaunch_col<-1>(bt, G.A, D.s4, c, 1));
+                    BCHK(blaunch_mid<0>(bt, G.A, D.midA, c, 1));
+                    BCHK(blaunch_col<1>(bt, G.A, D.s6, c, 1));
+                    BCHK(blaunch_col<-1>(bt, G.A, D.s7, c, 1));
+                    BCHK(blaunch_mid<0>(bt, G.A, D.midP, c, 1));
+                    BCHK(blaunch_col<1>(bt, G.A, D.s9, c, 1));
+                    BCHK(blaunch_col<-1>(bt, G.A, D.s10, c, 1));
+                    BCHK(blaunch_mid<0>(bt, G.A, D.midA, c, 1));
+                    BCHK(blaunch_col<1>(bt, G.A, D.s12, c, 1));
+                }
             }
+            int rc = batch_poll(bt);
+            if (rc) return rc;
+            bool all = true;
+            int maxiter = 0;
+            for (int i = 0; i < cnt; ++i) {
+                all = all && bt->h_done[i].done;
+                maxiter = std::max(maxiter, bt->h_done[i].iter);
+            }
+            iters_seen = maxiter;
+            if (all) break;
+            chunk = 2;
+        }
+        // the instances that stopped on a breakdown or on the recursive
+        // residual are checked; non-finite and unconverged ones keep their state
+        std::vector<char> check(cnt, 0);
+        bool any = false;
+        for (int i = 0; i < cnt; ++i) {
+            const DoneRec &r = bt->h_done[i];
+            check[i] = r.done && r.status != ST_NONFINITE && restarts[i] <= MAX_RESTARTS;
+            any = any || check[i];
+        }
+        if (!any) break;
+        for (size_t g = 0; g < bt->groups.size(); ++g) {
+            const BatchGroup &G = bt->groups[g];
+            const int c = (int)G.members.size();
+            BCHK(blaunch_col<-1>(bt, G.A, gd[g].rstA, c, 0));
+            BCHK(blaunch_mid<0>(bt, G.A, gd[g].midA, c, 0));
+            BCHK(blaunch_col<1>(bt, G.A, gd[g].vfyC, c, 0));
         }
         int rc = batch_poll(bt);
         if (rc) return rc;
         bool all = true;
-        int maxiter = 0;
         for (int i = 0; i < cnt; ++i) {
+            if (!bt->h_done[i].done) ++restarts[i];
             all = all && bt->h_done[i].done;
-            maxiter = std::max(maxiter, bt->h_done[i].iter);
         }
-        iters_seen = maxiter;
-        if (all) break;
+        ++rounds;
+        if (all || rounds > MAX_RESTARTS || iters_seen >= bt->maxit) break;
         chunk = 2;
     }
     int code = TSFCDE_OK, maxiter = 0;
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int i = 0; i < cnt; ++i) {
         const DoneRec &r = bt->h_done[i];
-        int ci = !r.done ? TSFCDE_ENOCONV : status_code(r.status);
+        tsfcde_plan_s *pl = bt->plans[i];
+        // an instance whose last check failed after all restarts keeps x (as
+        // the single-instance path does); one that never converged is ENOCONV
+        const bool checked = rounds > 0 && r.status == ST_OK;
+        int ci = (!r.done && !(checked && restarts[i] > MAX_RESTARTS)) ? TSFCDE_ENOCONV : status_code(r.status);
         if (ci && !code) code = ci;
         maxiter = std::max(maxiter, r.iter);
-        bt->plans[i]->level = j + 1;
+        pl->level = j + 1;
         if (stats) {
             tsfcde_stats &s = stats[i];
             s.iters = r.iter;
             s.outer_iters = 1;
-            s.restarts = 0;
+            s.restarts = restarts[i];
             s.status = ci;
             s.relres = r.gnorm2 > 0 ? std::sqrt(r.rnorm2 / r.gnorm2) : 0.0;
-            s.relres_true = -1.0;
-            s.backward_err = -1.0;
+            s.relres_true = rounds > 0 && r.gnorm2 > 0 ? std::sqrt(r.aux0 / r.gnorm2) : -1.0;
+            const double den = pl->anorm[j] * std::sqrt(r.aux1) + std::sqrt(r.gnorm2);
+            s.backward_err = rounds > 0 ? (den > 0 ? std::sqrt(r.aux0) / den : 0.0) : -1.0;
+            s.precision_used = TSFCDE_FP64;
             s.seconds = secs;
         }
     }
@@ -1360,6 +1667,7 @@ int tsfcde_batch_workspace_bytes(const tsfcde_problem *probs, int32_t count, siz
         size_t b = 0;
         int rc = workspace_bytes_impl(&probs[i], true, &b);
         if (rc) return rc;
+        if (probs[i].precision != TSFCDE_FP64) return TSFCDE_EUNSUPPORTED;  // the batch runs the FP64 form
         if (probs[i].M != probs[0].M) return TSFCDE_EINVAL;
         tot += al(b);
     }

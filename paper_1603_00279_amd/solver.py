@@ -177,7 +177,8 @@ class BatchSolver:
     initial_vector(); all share M."""
 
     def __init__(self, problems, *, rtol: float = 1e-10, maxit: int = 500, warm_start: int = N.TSFCDE_WS_ZERO,
-                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+                 precision: int = N.TSFCDE_FP64, device: Optional[torch.device] = None,
+                 stream: Optional[torch.cuda.Stream] = None):
         self._lib = N.lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -194,7 +195,7 @@ class BatchSolver:
                 alpha=prob.alpha, beta=prob.beta, a=prob.a, b=prob.b, T=prob.T, n=prob.n, M=prob.M,
                 gamma=N.COEF_FN(), dplus=N.COEF_FN(), dminus=N.COEF_FN(), coef_user=None,
                 gamma_at=g.ctypes.data_as(dptr), dplus_at=dp.ctypes.data_as(dptr), dminus_at=dm.ctypes.data_as(dptr),
-                phi=N.IC_FN(), phi_user=None, rtol=rtol, maxit=maxit, precision=N.TSFCDE_FP64,
+                phi=N.IC_FN(), phi_user=None, rtol=rtol, maxit=maxit, precision=precision,
                 warm_start=warm_start, flags=0)
         self._arr = arr
         nbytes = ctypes.c_size_t(0)

@@ -332,3 +332,27 @@ def test_paper_grids_on_gpu(example, alpha, beta, N, col, ref):
     l2, cn = O.error_norms(prob, U)
     got = l2 if col == "l2" else cn
     assert abs(got / ref - 1) < 0.005, (got, ref)
+
+
+def test_near_breakdown_level_is_rechecked():
+    """alpha = 0.5, beta = 1.5, n = 256, M = 8 with default flags: the first
+    CGS step at level 0 nearly breaks down (rt . vhat tiny, |alpha| ~ 2e5),
+    after which the recursive residual reaches 1e-11 while the true one
+    stays near 3e-2 (the same happens to textbook PCGS in dense FP64 on the
+    CPU).  Every converged level is accepted only at a backward error of at
+    most 1e-13, so level 0 restarts from x and all levels match the oracle."""
+    banner("near breakdown n=256")
+    prob = W.config_small(n=256, M=8)
+    Uref = O.march(prob)
+    F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
+    with make(prob, rtol=1e-10) as s:
+        code, stats = s.solve(F)
+        U = host(s.history())
+    assert code == 0
+    assert stats[0]["restarts"] >= 1
+    for j in range(1, prob.M + 1):
+        st = stats[j - 1]
+        assert 0 <= st["backward_err"] <= 1e-13, (j, st)
+        c1 = np.linalg.cond(O.level_A(prob, j - 1), 1)
+        bound = 2 * c1 * st["relres_true"] + 8 * 2.2e-16 * c1
+        assert relerr(U[j], Uref[j]) < bound, (j, relerr(U[j], Uref[j]), bound)
