@@ -73,6 +73,11 @@ extern "C" {
 #define TSFCDE_WS_PREV 1         /* initial guess u^j (previous level)       */
 #define TSFCDE_WS_EXTRAP 2       /* 3u^j - 3u^{j-1} + u^{j-2} (quadratic in t; u^j
                                     for j = 1, 0 for j = 0)                  */
+#define TSFCDE_WS_NET 3          /* learned guess (tsfcde_plan_set_net) from
+                                    level 2 on, u^j for j = 1, 0 for j = 0;
+                                    the previous-level guess replaces it when
+                                    its true residual |g - A x0| is not below
+                                    that of u^j                              */
 #define TSFCDE_FLAG_TRUE_RESIDUAL 1 /* also compute |g - A u|/|g| per level  */
 #define TSFCDE_FLAG_VERIFY 2     /* on recursive convergence, recompute r = g - A x
                                     and restart CGS from x while the true residual
@@ -142,7 +147,8 @@ typedef struct tsfcde_stats {
     double seconds;       /* host wall time of the level                     */
     int32_t precision_used; /* TSFCDE_FP64, TSFCDE_FP32_REFINED, or
                              TSFCDE_FP32_REFINED_FELL_BACK                   */
-    int32_t reserved;
+    int32_t guess;        /* initial guess used: TSFCDE_WS_ZERO, _PREV,
+                             _EXTRAP or _NET                                 */
 } tsfcde_stats;
 
 typedef struct tsfcde_plan_s *tsfcde_plan_t;
@@ -262,6 +268,70 @@ int tsfcde_batch_set_level(tsfcde_batch_t batch, int64_t level);
 int tsfcde_batch_step(tsfcde_batch_t batch, const double *const *d_f, tsfcde_stats *stats);
 
 int tsfcde_batch_destroy(tsfcde_batch_t batch);
+
+/* ---- learned warm start ----------------------------------------------
+ * A four-layer 1-D convolutional network (7 -> 32 -> 32 -> 32 -> 1 channels,
+ * width 5, zero padding, tanh after the first three) predicts level j+1 from
+ * levels j, j-1, j-2 as a correction to quadratic extrapolation in t:
+ *   x0 = 3(u^j - u^{j-1}) + u^{j-2} + s * y,
+ * with y the network output for the channels (e1/s, e2/s, alpha, beta,
+ * asinh q_gamma, log1p q_+, log1p q_-), e1 = u^j - u^{j-1},
+ * e2 = u^j - 2u^{j-1} + u^{j-2}, s = RMS(e2) (1 if e2 = 0), and the level
+ * coefficients q_gamma = sigma gamma_j / (h eta_j),
+ * q_+- = sigma D_+-,j h^-beta / eta_j (the terms of sigma L_j in (3.3)
+ * relative to eta_j).  Weights are bfloat16 (rounded from FP32 master
+ * weights), everything else FP32; s and x0 are FP64.  Parameters form one
+ * FP32 vector, layer by layer W[c_out][c_in][5] then b[c_out]. */
+typedef struct tsfcde_net_s *tsfcde_net_t;
+
+typedef struct tsfcde_net_sample {
+    const double *u_next;   /* u^{j+1} on the device (training target) or NULL */
+    const double *u0, *u1, *u2; /* u^j, u^{j-1}, u^{j-2} on the device       */
+    float feat[5];          /* alpha, beta, asinh q_gamma, log1p q_+, log1p q_- */
+    float pad;
+} tsfcde_net_sample;
+
+/* Number of FP32 parameters (11617). */
+int32_t tsfcde_net_param_count(void);
+
+/* Device workspace of a network able to take batches of up to max_batch
+ * samples of up to max_points = batch * n grid points in all. */
+int tsfcde_net_workspace_bytes(int64_t max_points, int32_t max_batch, size_t *bytes);
+
+/* Network in a caller-owned, 256-byte aligned device workspace, all
+ * parameters zero (so that, before training, x0 is the extrapolation). */
+int tsfcde_net_create(void *d_workspace, size_t bytes, int64_t max_points, int32_t max_batch, void *stream,
+                      tsfcde_net_t *out);
+
+/* Copy the FP32 master parameters in (host array of
+ * tsfcde_net_param_count() floats; resets the optimiser) or out. */
+int tsfcde_net_set_params(tsfcde_net_t net, const float *h_params);
+int tsfcde_net_get_params(tsfcde_net_t net, float *h_params);
+
+/* Channels 2..6 of level j of a plan (the values a plan with TSFCDE_WS_NET
+ * uses, so that training samples and inference agree). */
+int tsfcde_level_features(tsfcde_plan_t plan, int64_t j, float *h_feat5);
+
+/* One training step on `count` samples of n points (every u_next set):
+ * loss = mean over samples and points of (y - y*)^2 with
+ * y* = (u^{j+1} - 3(u^j - u^{j-1}) - u^{j-2}) / s, its gradient by the
+ * network's backward kernels, then one Adam update (lr; beta1 = 0.9,
+ * beta2 = 0.999, eps = 1e-8, bias-corrected).  h_samples: host array.
+ * loss_out (host, nullable) receives the loss before the update.
+ * h_grad_out (host, nullable; param_count floats) receives the gradient; with
+ * lr == 0 no update is made.  Synchronises the stream. */
+int tsfcde_net_train_step(tsfcde_net_t net, const tsfcde_net_sample *h_samples, int32_t count, int64_t n, float lr,
+                          double *loss_out, float *h_grad_out);
+
+/* Prediction x0 (device, n doubles) for one sample (u_next ignored). */
+int tsfcde_net_predict(tsfcde_net_t net, const tsfcde_net_sample *h_sample, int64_t n, double *d_x0);
+
+/* Use `net` for TSFCDE_WS_NET guesses of this plan (n <= the net's
+ * max_points; the net must outlive its use and run on the plan's stream).
+ * NULL detaches it (levels then take the previous-level guess). */
+int tsfcde_plan_set_net(tsfcde_plan_t plan, tsfcde_net_t net);
+
+int tsfcde_net_destroy(tsfcde_net_t net);
 
 /* Static description of a status code. */
 const char *tsfcde_strerror(int status);

@@ -30,7 +30,7 @@ TSFCDE_EDONE, TSFCDE_EUNSUPPORTED = -7, -8
 TSFCDE_FP64 = 0
 TSFCDE_FP32_REFINED = 1
 TSFCDE_FP32_REFINED_FELL_BACK = 2
-TSFCDE_WS_ZERO, TSFCDE_WS_PREV, TSFCDE_WS_EXTRAP = 0, 1, 2
+TSFCDE_WS_ZERO, TSFCDE_WS_PREV, TSFCDE_WS_EXTRAP, TSFCDE_WS_NET = 0, 1, 2, 3
 TSFCDE_FLAG_TRUE_RESIDUAL = 1
 TSFCDE_FLAG_VERIFY = 2
 TSFCDE_FLAG_FORCE_FP32 = 4
@@ -54,11 +54,18 @@ class tsfcde_stats(ctypes.Structure):
     _fields_ = [
         ("iters", c_int32), ("outer_iters", c_int32), ("restarts", c_int32), ("status", c_int32),
         ("relres", c_double), ("relres_true", c_double), ("backward_err", c_double), ("seconds", c_double),
-        ("precision_used", c_int32), ("reserved", c_int32),
+        ("precision_used", c_int32), ("guess", c_int32),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class tsfcde_net_sample(ctypes.Structure):
+    _fields_ = [
+        ("u_next", c_void_p), ("u0", c_void_p), ("u1", c_void_p), ("u2", c_void_p),
+        ("feat", ctypes.c_float * 5), ("pad", ctypes.c_float),
+    ]
 
 
 _SIGS = {
@@ -86,6 +93,17 @@ _SIGS = {
     "tsfcde_batch_step": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(tsfcde_stats)]),
     "tsfcde_batch_destroy": (c_int32, [c_void_p]),
     "tsfcde_strerror": (c_char_p, [c_int32]),
+    "tsfcde_net_param_count": (c_int32, []),
+    "tsfcde_net_workspace_bytes": (c_int32, [c_int64, c_int32, POINTER(c_size_t)]),
+    "tsfcde_net_create": (c_int32, [c_void_p, c_size_t, c_int64, c_int32, c_void_p, POINTER(c_void_p)]),
+    "tsfcde_net_set_params": (c_int32, [c_void_p, POINTER(ctypes.c_float)]),
+    "tsfcde_net_get_params": (c_int32, [c_void_p, POINTER(ctypes.c_float)]),
+    "tsfcde_level_features": (c_int32, [c_void_p, c_int64, POINTER(ctypes.c_float)]),
+    "tsfcde_net_train_step": (c_int32, [c_void_p, POINTER(tsfcde_net_sample), c_int32, c_int64, ctypes.c_float,
+                                        POINTER(c_double), POINTER(ctypes.c_float)]),
+    "tsfcde_net_predict": (c_int32, [c_void_p, POINTER(tsfcde_net_sample), c_int64, c_void_p]),
+    "tsfcde_plan_set_net": (c_int32, [c_void_p, c_void_p]),
+    "tsfcde_net_destroy": (c_int32, [c_void_p]),
 }
 
 _LIB = None

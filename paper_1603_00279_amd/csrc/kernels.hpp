@@ -28,7 +28,7 @@ namespace tsf {
 // ---------------------------------------------------------------------------
 struct DevScalars {
     double rho, rho_prev, alpha, beta, rtv, rnorm2, gnorm2, tol2;
-    double aux0, aux1, rtol2, pad0;
+    double aux0, aux1, rtol2, r0sq;  // r0sq: |g - A x0|^2 of the right-hand side's initial guess
     int iter, done, status, fresh;  // fresh: next CGS iteration starts from r (u = p = r)
 };
 
@@ -473,6 +473,7 @@ struct OutRhs {
         sc->iter = 0;
         sc->fresh = 1;
         sc->aux0 = tot[1];
+        sc->r0sq = tot[1];
         sc->status = ST_OK;
         sc->done = (tot[1] <= sc->tol2) ? 1 : 0;
         if (!finite(tot[0]) || !finite(tot[1])) {

@@ -20,6 +20,7 @@
 
 #include "../../include/tsfcde.h"
 #include "kernels.hpp"
+#include "warmnet.hpp"
 
 using namespace tsf;
 
@@ -156,7 +157,8 @@ int validate(const tsfcde_problem *p) {
     if ((!p->gamma && !p->gamma_at) || (!p->dplus && !p->dplus_at) || (!p->dminus && !p->dminus_at))
         return TSFCDE_EINVAL;
     if (p->precision != TSFCDE_FP64 && p->precision != TSFCDE_FP32_REFINED) return TSFCDE_EINVAL;
-    if (p->warm_start != TSFCDE_WS_ZERO && p->warm_start != TSFCDE_WS_PREV && p->warm_start != TSFCDE_WS_EXTRAP)
+    if (p->warm_start != TSFCDE_WS_ZERO && p->warm_start != TSFCDE_WS_PREV && p->warm_start != TSFCDE_WS_EXTRAP &&
+        p->warm_start != TSFCDE_WS_NET)
         return TSFCDE_EINVAL;
     if (!std::isfinite(p->rtol)) return TSFCDE_EINVAL;
     if (p->n < 4 || p->n > (is_pow2(p->n) ? NMAX : NMAX / 2)) return TSFCDE_EUNSUPPORTED;
@@ -198,9 +200,215 @@ struct tsfcde_plan_s {
     float *r32, *rt32, *u32, *p32, *q32, *phat32, *vhat32, *uhat32, *d32;
     float2 *buf32, *bufP32, *specA32, *specP32, *specPj32;
     int last_inner = 8;
+    tsfcde_net_s *net = nullptr;  // learned warm start (TSFCDE_WS_NET)
     ProfRec prof[NPROF];
     std::vector<hipEvent_t> event_pool;
 };
+
+
+// ===========================================================================
+// Learned warm start: network state, training step and prediction.
+// ===========================================================================
+namespace {
+
+struct NetLayer {
+    int ci, co;
+};
+constexpr NetLayer NET_LAYERS[net::NLAYER] = {
+    {net::CIN, net::WIDTH}, {net::WIDTH, net::WIDTH}, {net::WIDTH, net::WIDTH}, {net::WIDTH, 1}};
+constexpr int net_param_count() {
+    int t = 0;
+    for (int l = 0; l < net::NLAYER; ++l) t += NET_LAYERS[l].co * NET_LAYERS[l].ci * net::KS + NET_LAYERS[l].co;
+    return t;
+}
+constexpr int64_t net_layer_off(int l) {
+    int64_t o = 0;
+    for (int i = 0; i < l; ++i) o += NET_LAYERS[i].co * NET_LAYERS[i].ci * net::KS + NET_LAYERS[i].co;
+    return o;
+}
+constexpr int NET_P = net_param_count();
+static_assert(NET_P == 11617, "parameter count");
+constexpr int NET_WG_MAX = 1024;  // workgroups of a weight-gradient pass
+constexpr int NET_NE_MAX = net::WIDTH * net::WIDTH * net::KS + net::WIDTH;
+constexpr int NET_LOSS_WG = 256;
+static_assert(sizeof(tsfcde_net_sample) == sizeof(net::Sample), "sample layout");
+
+struct NetLayout {
+    size_t theta, m, v, grad, wbf, wt, wb, X, act, y, ystar, dy, dz0, dz1, part, s, lpart, smp, total;
+};
+
+NetLayout net_layout(int64_t mp, int32_t mb) {
+    NetLayout l{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = al(o + bytes);
+        return at;
+    };
+    l.theta = take(4 * (size_t)NET_P);
+    l.m = take(4 * (size_t)NET_P);
+    l.v = take(4 * (size_t)NET_P);
+    l.grad = take(4 * (size_t)NET_P);
+    l.wbf = take(2 * (size_t)NET_P);
+    l.wt = take(4 * (size_t)NET_P);
+    l.wb = take(4 * (size_t)NET_P);
+    l.X = take(4 * (size_t)net::CIN * mp);
+    l.act = take(4 * (size_t)3 * net::WIDTH * mp);
+    l.y = take(4 * (size_t)mp);
+    l.ystar = take(4 * (size_t)mp);
+    l.dy = take(4 * (size_t)mp);
+    l.dz0 = take(4 * (size_t)net::WIDTH * mp);
+    l.dz1 = take(4 * (size_t)net::WIDTH * mp);
+    l.part = take(4 * (size_t)NET_WG_MAX * NET_NE_MAX);
+    l.s = take(8 * (size_t)mb);
+    l.lpart = take(8 * (size_t)NET_LOSS_WG);
+    l.smp = take(sizeof(net::Sample) * (size_t)mb);
+    l.total = o;
+    return l;
+}
+
+}  // namespace
+
+struct tsfcde_net_s {
+    hipStream_t stream = nullptr;
+    int64_t max_points = 0;
+    int32_t max_batch = 0;
+    float *theta, *m, *v, *grad, *wt, *wb, *X, *act, *y, *ystar, *dy, *dz0, *dz1, *part;
+    uint16_t *wbf;
+    double *s, *lpart;
+    net::Sample *smp;
+    bool widened = false;
+    int64_t step = 0;
+};
+
+namespace {
+
+#define NCHK(x)                                      \
+    do {                                             \
+        if ((x) != hipSuccess) return TSFCDE_EDEVICE; \
+    } while (0)
+
+// bfloat16 weights -> the FP32 orders the convolutions read
+int net_widen(tsfcde_net_s *nt) {
+    if (nt->widened) return TSFCDE_OK;
+    for (int l = 0; l < net::NLAYER; ++l) {
+        const NetLayer &L = NET_LAYERS[l];
+        const int64_t off = net_layer_off(l);
+        hipLaunchKernelGGL(net::k_net_widen, dim3(32), dim3(256), 0, nt->stream, nt->wbf + off, L.ci, L.co,
+                           nt->wt + off, l > 0 ? nt->wb + off : (float *)nullptr);
+    }
+    NCHK(hipGetLastError());
+    nt->widened = true;
+    return TSFCDE_OK;
+}
+
+// Inputs (and targets) of `count` samples already in nt->smp; then the
+// forward pass.  Activations: act + l * WIDTH * count * n for layers 1..3.
+int net_forward(tsfcde_net_s *nt, int count, int64_t n, bool targets) {
+    int rc = net_widen(nt);
+    if (rc) return rc;
+    hipLaunchKernelGGL(net::k_net_scale<256>, dim3(count), dim3(256), 0, nt->stream, nt->smp, n, nt->s);
+    const unsigned gx = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(net::k_net_inputs, dim3(gx, count), dim3(256), 0, nt->stream, nt->smp, n, nt->s, nt->X,
+                       targets ? nt->ystar : (float *)nullptr);
+    const size_t A = (size_t)net::WIDTH * count * n;
+    float *a1 = nt->act, *a2 = nt->act + A, *a3 = nt->act + 2 * A;
+    auto grid = [&](int tx) { return dim3((unsigned)((n + tx - 1) / tx), (unsigned)count); };
+    using G0 = net::ConvGeo<net::CIN, net::WIDTH>;
+    using G1 = net::ConvGeo<net::WIDTH, net::WIDTH>;
+    using G3 = net::ConvGeo<net::WIDTH, 1>;
+    const int64_t o0 = net_layer_off(0), o1 = net_layer_off(1), o2 = net_layer_off(2), o3 = net_layer_off(3);
+    hipLaunchKernelGGL((net::k_conv<net::CIN, net::WIDTH, 0>), grid(G0::TX), dim3(G0::NT), 0, nt->stream, nt->X,
+                       nt->wt + o0, nt->theta + o0 + net::WIDTH * net::CIN * net::KS, (const float *)nullptr, a1, n);
+    hipLaunchKernelGGL((net::k_conv<net::WIDTH, net::WIDTH, 0>), grid(G1::TX), dim3(G1::NT), 0, nt->stream, a1,
+                       nt->wt + o1, nt->theta + o1 + net::WIDTH * net::WIDTH * net::KS, (const float *)nullptr, a2, n);
+    hipLaunchKernelGGL((net::k_conv<net::WIDTH, net::WIDTH, 0>), grid(G1::TX), dim3(G1::NT), 0, nt->stream, a2,
+                       nt->wt + o2, nt->theta + o2 + net::WIDTH * net::WIDTH * net::KS, (const float *)nullptr, a3, n);
+    hipLaunchKernelGGL((net::k_conv<net::WIDTH, 1, 1>), grid(G3::TX), dim3(G3::NT), 0, nt->stream, a3, nt->wt + o3,
+                       nt->theta + o3 + net::WIDTH * net::KS, (const float *)nullptr, nt->y, n);
+    NCHK(hipGetLastError());
+    return TSFCDE_OK;
+}
+
+template <int CI, int CO>
+int net_wgrad(tsfcde_net_s *nt, const float *dz, const float *a, int count, int64_t n, int64_t off) {
+    using G = net::WgradGeo<CI, CO>;
+    const int64_t tiles = (n + G::TX - 1) / G::TX;
+    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, NET_WG_MAX / count));
+    hipLaunchKernelGGL((net::k_net_wgrad<CI, CO>), dim3(gx, count), dim3(G::NT), 0, nt->stream, dz, a, n, nt->part);
+    hipLaunchKernelGGL(net::k_net_wgrad_reduce, dim3((G::NE + 255) / 256), dim3(256), 0, nt->stream, nt->part,
+                       gx * count, G::NE, nt->grad + off);
+    NCHK(hipGetLastError());
+    return TSFCDE_OK;
+}
+
+// Loss partials and the gradient of the loss in nt->grad (after net_forward
+// with targets).
+int net_backward(tsfcde_net_s *nt, int count, int64_t n) {
+    const int64_t total = (int64_t)count * n;
+    hipLaunchKernelGGL(net::k_net_loss<256>, dim3(NET_LOSS_WG), dim3(256), 0, nt->stream, nt->y, nt->ystar, total,
+                       nt->dy, nt->lpart);
+    const size_t A = (size_t)net::WIDTH * count * n;
+    float *a1 = nt->act, *a2 = nt->act + A, *a3 = nt->act + 2 * A;
+    auto grid = [&](int tx) { return dim3((unsigned)((n + tx - 1) / tx), (unsigned)count); };
+    using GB3 = net::ConvGeo<1, net::WIDTH>;
+    using GB = net::ConvGeo<net::WIDTH, net::WIDTH>;
+    const int64_t o0 = net_layer_off(0), o1 = net_layer_off(1), o2 = net_layer_off(2), o3 = net_layer_off(3);
+    int rc;
+    // layer 3 (32 -> 1, linear): dZ3 = dy
+    if ((rc = net_wgrad<net::WIDTH, 1>(nt, nt->dy, a3, count, n, o3))) return rc;
+    hipLaunchKernelGGL((net::k_conv<1, net::WIDTH, 2>), grid(GB3::TX), dim3(GB3::NT), 0, nt->stream, nt->dy,
+                       nt->wb + o3, (const float *)nullptr, a3, nt->dz0, n);
+    // layer 2 (32 -> 32): dZ = dz0
+    if ((rc = net_wgrad<net::WIDTH, net::WIDTH>(nt, nt->dz0, a2, count, n, o2))) return rc;
+    hipLaunchKernelGGL((net::k_conv<net::WIDTH, net::WIDTH, 2>), grid(GB::TX), dim3(GB::NT), 0, nt->stream, nt->dz0,
+                       nt->wb + o2, (const float *)nullptr, a2, nt->dz1, n);
+    // layer 1 (32 -> 32): dZ = dz1
+    if ((rc = net_wgrad<net::WIDTH, net::WIDTH>(nt, nt->dz1, a1, count, n, o1))) return rc;
+    hipLaunchKernelGGL((net::k_conv<net::WIDTH, net::WIDTH, 2>), grid(GB::TX), dim3(GB::NT), 0, nt->stream, nt->dz1,
+                       nt->wb + o1, (const float *)nullptr, a1, nt->dz0, n);
+    // layer 0 (7 -> 32): dZ = dz0, inputs X
+    if ((rc = net_wgrad<net::CIN, net::WIDTH>(nt, nt->dz0, nt->X, count, n, o0))) return rc;
+    NCHK(hipGetLastError());
+    return TSFCDE_OK;
+}
+
+int net_upload(tsfcde_net_s *nt, const tsfcde_net_sample *h, int count) {
+    NCHK(hipMemcpyAsync(nt->smp, h, sizeof(net::Sample) * (size_t)count, hipMemcpyHostToDevice, nt->stream));
+    // the host array must stay valid until the copy is done
+    NCHK(hipStreamSynchronize(nt->stream));
+    return TSFCDE_OK;
+}
+
+// x0 for one sample into d_x0 (on the network's stream).
+int net_predict(tsfcde_net_s *nt, const tsfcde_net_sample &smp, int64_t n, double *d_x0) {
+    if (n > nt->max_points) return TSFCDE_EINVAL;
+    int rc = net_upload(nt, &smp, 1);
+    if (rc) return rc;
+    if ((rc = net_forward(nt, 1, n, false))) return rc;
+    net::Sample S;
+    std::memcpy(&S, &smp, sizeof(S));
+    hipLaunchKernelGGL(net::k_net_output, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0,
+                       nt->stream, S, n, nt->s, nt->y, d_x0);
+    NCHK(hipGetLastError());
+    return TSFCDE_OK;
+}
+
+// Channels 2..6 of level j (alpha, beta and the level's coefficients of
+// sigma L_j relative to eta_j).
+void level_features(const tsfcde_plan_s *pl, int64_t j, float *f) {
+    const double e = pl->eta[j];
+    const double qg = pl->sigma * pl->gam[j] / (pl->h * e);
+    const double qp = pl->sigma * pl->dp[j] * pl->hb / e;
+    const double qm = pl->sigma * pl->dm[j] * pl->hb / e;
+    f[0] = (float)pl->alpha;
+    f[1] = (float)pl->beta;
+    f[2] = (float)std::asinh(qg);
+    f[3] = (float)std::log1p(qp);
+    f[4] = (float)std::log1p(qm);
+}
+
+}  // namespace
 
 namespace {
 
@@ -782,8 +990,28 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
     int warm = 0;
     if (pl->warm == TSFCDE_WS_PREV) warm = 1;
     if (pl->warm == TSFCDE_WS_EXTRAP) warm = j >= 2 ? 2 : (j >= 1 ? 1 : 0);
+    const bool use_net = pl->warm == TSFCDE_WS_NET && pl->net && j >= 2;
+    if (pl->warm == TSFCDE_WS_NET) warm = j >= 1 ? 1 : 0;
     int rc = level_rhs(pl, j, d_f, x, warm);
     if (rc) return rc;
+    int guess = warm == 2 ? TSFCDE_WS_EXTRAP : (warm == 1 ? TSFCDE_WS_PREV : TSFCDE_WS_ZERO);
+    if (use_net) {
+        // the network's guess, kept only if its true residual is below that of
+        // u^j (which the right-hand side pass left in r0sq)
+        const double *Uj = pl->U + (size_t)j * pl->ldn;
+        tsfcde_net_sample smp{nullptr, Uj, Uj - pl->ldn, Uj - 2 * pl->ldn, {0, 0, 0, 0, 0}, 0.0f};
+        level_features(pl, j, smp.feat);
+        if ((rc = net_predict(pl->net, smp, n, x))) return rc;
+        if ((rc = restart_from_x(pl, j, x, 0.0))) return rc;
+        const double rnet = pl->h_sc->aux0, rprev = pl->h_sc->r0sq;
+        if (std::isfinite(rnet) && rnet < rprev) {
+            guess = TSFCDE_WS_NET;
+        } else {
+            HIPCHK(hipMemcpyAsync(x, Uj, sizeof(double) * n, hipMemcpyDeviceToDevice, pl->stream));
+            if ((rc = restart_launch(pl, j, x, 0.0))) return rc;
+        }
+        warm = 2;  // the CGS state is set by a restart pass, as for extrapolation
+    }
     HIPCHK(precond_level(pl, j));
     SolveOut so;
     int outer = 1;
@@ -793,7 +1021,7 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
         if (fp32) {
             if ((rc = ir_solve(pl, j, x, so, outer, fell_back))) return rc;
         } else {
-            if (warm == 2 && (rc = restart_launch(pl, j, x, 0.0))) return rc;  // r0 = g - A x0
+            if (warm == 2 && !use_net && (rc = restart_launch(pl, j, x, 0.0))) return rc;  // r0 = g - A x0
             if ((rc = fp64_cgs(pl, j, x, so))) return rc;
         }
     }
@@ -819,6 +1047,7 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
         st->relres_true = relres_true;
         st->backward_err = so.backward_err;
         st->precision_used = fp32 ? (fell_back ? TSFCDE_FP32_REFINED_FELL_BACK : TSFCDE_FP32_REFINED) : TSFCDE_FP64;
+        st->guess = guess;
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return so.code;
@@ -1199,6 +1428,132 @@ int tsfcde_profile_read(tsfcde_plan_t pl, int32_t cls, int64_t *launches, double
     harvest(pl);
     if (launches) *launches = pl->prof[cls].launches;
     if (ms) *ms = pl->prof[cls].ms;
+    return TSFCDE_OK;
+}
+
+
+int32_t tsfcde_net_param_count(void) { return NET_P; }
+
+int tsfcde_net_workspace_bytes(int64_t max_points, int32_t max_batch, size_t *bytes) {
+    if (!bytes || max_points < 1 || max_batch < 1 || max_batch > NET_WG_MAX) return TSFCDE_EINVAL;
+    *bytes = net_layout(max_points, max_batch).total;
+    return TSFCDE_OK;
+}
+
+int tsfcde_net_create(void *d_workspace, size_t bytes, int64_t max_points, int32_t max_batch, void *stream,
+                      tsfcde_net_t *out) {
+    if (!out || !d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255)) return TSFCDE_EINVAL;
+    *out = nullptr;
+    if (max_points < 1 || max_batch < 1 || max_batch > NET_WG_MAX) return TSFCDE_EINVAL;
+    const NetLayout L = net_layout(max_points, max_batch);
+    if (bytes < L.total) return TSFCDE_ENOMEM;
+    tsfcde_net_s *nt = new (std::nothrow) tsfcde_net_s();
+    if (!nt) return TSFCDE_ENOMEM;
+    char *ws = reinterpret_cast<char *>(d_workspace);
+    nt->stream = reinterpret_cast<hipStream_t>(stream);
+    nt->max_points = max_points;
+    nt->max_batch = max_batch;
+    nt->theta = reinterpret_cast<float *>(ws + L.theta);
+    nt->m = reinterpret_cast<float *>(ws + L.m);
+    nt->v = reinterpret_cast<float *>(ws + L.v);
+    nt->grad = reinterpret_cast<float *>(ws + L.grad);
+    nt->wbf = reinterpret_cast<uint16_t *>(ws + L.wbf);
+    nt->wt = reinterpret_cast<float *>(ws + L.wt);
+    nt->wb = reinterpret_cast<float *>(ws + L.wb);
+    nt->X = reinterpret_cast<float *>(ws + L.X);
+    nt->act = reinterpret_cast<float *>(ws + L.act);
+    nt->y = reinterpret_cast<float *>(ws + L.y);
+    nt->ystar = reinterpret_cast<float *>(ws + L.ystar);
+    nt->dy = reinterpret_cast<float *>(ws + L.dy);
+    nt->dz0 = reinterpret_cast<float *>(ws + L.dz0);
+    nt->dz1 = reinterpret_cast<float *>(ws + L.dz1);
+    nt->part = reinterpret_cast<float *>(ws + L.part);
+    nt->s = reinterpret_cast<double *>(ws + L.s);
+    nt->lpart = reinterpret_cast<double *>(ws + L.lpart);
+    nt->smp = reinterpret_cast<net::Sample *>(ws + L.smp);
+    // parameters, optimiser state and the bfloat16 copy start at zero
+    if (hipMemsetAsync(ws, 0, L.X, nt->stream) != hipSuccess || hipStreamSynchronize(nt->stream) != hipSuccess) {
+        delete nt;
+        return TSFCDE_EDEVICE;
+    }
+    *out = nt;
+    return TSFCDE_OK;
+}
+
+int tsfcde_net_set_params(tsfcde_net_t nt, const float *h) {
+    if (!nt || !h) return TSFCDE_EINVAL;
+    NCHK(hipMemcpyAsync(nt->theta, h, 4 * (size_t)NET_P, hipMemcpyHostToDevice, nt->stream));
+    hipLaunchKernelGGL(net::k_net_round, dim3((NET_P + 255) / 256), dim3(256), 0, nt->stream, nt->theta, nt->wbf,
+                       NET_P);
+    hipLaunchKernelGGL(k_fill<float>, dim3(64), dim3(256), 0, nt->stream, nt->m, 0.0f, (int64_t)NET_P);
+    hipLaunchKernelGGL(k_fill<float>, dim3(64), dim3(256), 0, nt->stream, nt->v, 0.0f, (int64_t)NET_P);
+    NCHK(hipGetLastError());
+    NCHK(hipStreamSynchronize(nt->stream));
+    nt->widened = false;
+    nt->step = 0;
+    return TSFCDE_OK;
+}
+
+int tsfcde_net_get_params(tsfcde_net_t nt, float *h) {
+    if (!nt || !h) return TSFCDE_EINVAL;
+    NCHK(hipMemcpyAsync(h, nt->theta, 4 * (size_t)NET_P, hipMemcpyDeviceToHost, nt->stream));
+    NCHK(hipStreamSynchronize(nt->stream));
+    return TSFCDE_OK;
+}
+
+int tsfcde_level_features(tsfcde_plan_t pl, int64_t j, float *f) {
+    if (!pl || !f || j < 0 || j >= pl->M) return TSFCDE_EINVAL;
+    level_features(pl, j, f);
+    return TSFCDE_OK;
+}
+
+int tsfcde_net_train_step(tsfcde_net_t nt, const tsfcde_net_sample *h, int32_t count, int64_t n, float lr,
+                          double *loss_out, float *h_grad) {
+    if (!nt || !h || count < 1 || count > nt->max_batch || n < 1 || (int64_t)count * n > nt->max_points)
+        return TSFCDE_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (!h[i].u_next || !h[i].u0 || !h[i].u1 || !h[i].u2) return TSFCDE_EINVAL;
+    int rc = net_upload(nt, h, count);
+    if (rc) return rc;
+    if ((rc = net_forward(nt, count, n, true))) return rc;
+    if ((rc = net_backward(nt, count, n))) return rc;
+    if (lr != 0.0f) {
+        nt->step += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.0f - std::pow(b1, (float)nt->step), c2 = 1.0f - std::pow(b2, (float)nt->step);
+        hipLaunchKernelGGL(net::k_net_adam, dim3((NET_P + 255) / 256), dim3(256), 0, nt->stream, nt->theta, nt->m,
+                           nt->v, nt->grad, nt->wbf, NET_P, lr, b1, b2, 1e-8f, c1, c2);
+        NCHK(hipGetLastError());
+        nt->widened = false;
+    }
+    double lp[NET_LOSS_WG];
+    NCHK(hipMemcpyAsync(lp, nt->lpart, sizeof(lp), hipMemcpyDeviceToHost, nt->stream));
+    if (h_grad) NCHK(hipMemcpyAsync(h_grad, nt->grad, 4 * (size_t)NET_P, hipMemcpyDeviceToHost, nt->stream));
+    NCHK(hipStreamSynchronize(nt->stream));
+    if (loss_out) {
+        double t = 0.0;
+        for (double v : lp) t += v;
+        *loss_out = t / ((double)count * (double)n);
+    }
+    return TSFCDE_OK;
+}
+
+int tsfcde_net_predict(tsfcde_net_t nt, const tsfcde_net_sample *h, int64_t n, double *d_x0) {
+    if (!nt || !h || !d_x0 || !h->u0 || !h->u1 || !h->u2 || n < 1) return TSFCDE_EINVAL;
+    return net_predict(nt, *h, n, d_x0);
+}
+
+int tsfcde_plan_set_net(tsfcde_plan_t pl, tsfcde_net_t nt) {
+    if (!pl) return TSFCDE_EINVAL;
+    if (nt && (pl->n > nt->max_points || nt->stream != pl->stream)) return TSFCDE_EINVAL;
+    pl->net = nt;
+    return TSFCDE_OK;
+}
+
+int tsfcde_net_destroy(tsfcde_net_t nt) {
+    if (!nt) return TSFCDE_EINVAL;
+    (void)hipStreamSynchronize(nt->stream);
+    delete nt;
     return TSFCDE_OK;
 }
 

@@ -1,0 +1,315 @@
+// warmnet.hpp -- kernels of the learned Krylov warm start.
+//
+// A four-layer 1-D convolutional network (7 -> 32 -> 32 -> 32 -> 1 channels,
+// width 5, zero padding, tanh after the first three layers) predicts the next
+// time level as a correction to quadratic extrapolation in t:
+//   x0 = 3 (u^j - u^{j-1}) + u^{j-2} + s * y,
+// where y is the network output for the inputs
+//   e1 / s, e2 / s  (e1 = u^j - u^{j-1}, e2 = u^j - 2u^{j-1} + u^{j-2},
+//                    s = RMS of e2 over the grid, 1 if e2 vanishes),
+// and five channels constant in x that describe the level (alpha, beta and
+// the sizes of the convection and two diffusion terms of sigma L_j relative
+// to eta_j, see (3.3)).
+//
+// Precision: weights in bfloat16 (rounded to nearest even from FP32 master
+// weights kept for the optimiser), biases, activations and every
+// accumulation in FP32; the extrapolation and the scale s in FP64.
+//
+// Layout: activations of a batch of B samples as [B][channels][n] (FP32);
+// parameters as one flat vector, layer by layer W[c_out][c_in][5] then
+// b[c_out] (the same order as the CPU reference of the network).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsf {
+namespace net {
+
+constexpr int CIN = 7, WIDTH = 32, KS = 5, HALF = 2, NLAYER = 4;
+
+struct Sample {              // one training or inference sample
+    const double *un;        // u^{j+1} (target), may be null
+    const double *u0, *u1, *u2;  // u^j, u^{j-1}, u^{j-2}
+    float feat[5];           // channels 2..6
+    float pad;
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {  // round to nearest, ties to even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Block sum of a double (every thread passes its part; result valid in thread 0).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[NT / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+    return s;
+}
+
+// s_b = RMS of e2 over the grid (1 when it vanishes), one workgroup per sample.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_net_scale(const Sample *__restrict__ smp, int64_t n, double *s_out) {
+    const Sample S = smp[blockIdx.x];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += NT) {
+        const double e2 = S.u0[i] - 2.0 * S.u1[i] + S.u2[i];
+        acc = fma(e2, e2, acc);
+    }
+    const double tot = block_sum<NT>(acc);
+    if (threadIdx.x == 0) {
+        const double s = sqrt(tot / (double)n);
+        s_out[blockIdx.x] = s > 0.0 ? s : 1.0;
+    }
+}
+
+// Network inputs X[b][c][i] and, when the sample has u^{j+1}, the target
+// Y*[b][i] = (u^{j+1} - base) / s.
+__global__ void k_net_inputs(const Sample *__restrict__ smp, int64_t n, const double *__restrict__ s,
+                             float *__restrict__ X, float *__restrict__ Ystar) {
+    const int b = blockIdx.y;
+    const Sample S = smp[b];
+    const double inv = 1.0 / s[b];
+    float *Xb = X + (size_t)b * CIN * n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double a0 = S.u0[i], a1 = S.u1[i], a2 = S.u2[i];
+        const double e1 = a0 - a1, e2 = a0 - 2.0 * a1 + a2;
+        Xb[i] = (float)(e1 * inv);
+        Xb[n + i] = (float)(e2 * inv);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) Xb[(2 + c) * n + i] = S.feat[c];
+        if (Ystar && S.un) {
+            const double base = fma(3.0, a0 - a1, a2);
+            Ystar[(size_t)b * n + i] = (float)((S.un[i] - base) * inv);
+        }
+    }
+}
+
+// x0 = base + s y for one sample (FP64 out).
+__global__ void k_net_output(Sample S, int64_t n, const double *__restrict__ s, const float *__restrict__ y,
+                             double *__restrict__ x0) {
+    const double sc = s[0];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double base = fma(3.0, S.u0[i] - S.u1[i], S.u2[i]);
+        x0[i] = fma(sc, (double)y[i], base);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Convolution out[b][co][p] = sum_ci sum_k W[co][ci][k] in[b][ci][p + k - 2]
+// (zero outside 0 <= p + k - 2 < n), then an epilogue:
+//   EPI 0: + bias, tanh;  EPI 1: + bias;  EPI 2: times (1 - act^2) (the
+//   backward pass through tanh, act = the layer's stored activation).
+// A workgroup covers TX positions of one sample; thread t takes position
+// t % TX and output channels [OPT * (t / TX), +OPT).  Lanes of a wave share
+// the channel group, so weight reads from LDS are broadcasts.
+// The weights come in as `Wt[ci][k][co]` (FP32, already widened from
+// bfloat16, see k_net_widen) so each thread reads its OPT channels together.
+// ---------------------------------------------------------------------------
+template <int CI, int CO> struct ConvGeo {
+    static constexpr int OPT = CO < 8 ? CO : 8;
+    static constexpr int G = CO / OPT;
+    static constexpr int TX = G >= 4 ? 64 : (G == 2 ? 128 : 256);
+    static constexpr int NT = TX * G;
+};
+
+template <int CI, int CO, int EPI>
+__global__ void __launch_bounds__((ConvGeo<CI, CO>::NT)) k_conv(const float *__restrict__ in,
+                                                               const float *__restrict__ Wt,
+                                                               const float *__restrict__ bias,
+                                                               const float *__restrict__ act, float *__restrict__ out,
+                                                               int64_t n) {
+    using G = ConvGeo<CI, CO>;
+    constexpr int TX = G::TX, OPT = G::OPT, NT = G::NT;
+    __shared__ float tile[CI][TX + 2 * HALF];
+    __shared__ float wl[CI * KS * CO];
+    const int b = blockIdx.y;
+    const int64_t p0 = (int64_t)blockIdx.x * TX;
+    const float *inb = in + (size_t)b * CI * n;
+    for (int idx = threadIdx.x; idx < CI * (TX + 2 * HALF); idx += NT) {
+        const int ci = idx / (TX + 2 * HALF), q = idx % (TX + 2 * HALF);
+        const int64_t p = p0 + q - HALF;
+        tile[ci][q] = (p >= 0 && p < n) ? inb[(size_t)ci * n + p] : 0.0f;
+    }
+    for (int idx = threadIdx.x; idx < CI * KS * CO; idx += NT) wl[idx] = Wt[idx];
+    __syncthreads();
+    const int tp = threadIdx.x % TX, cg = threadIdx.x / TX;
+    const int64_t p = p0 + tp;
+    float acc[OPT];
+#pragma unroll
+    for (int o = 0; o < OPT; ++o) acc[o] = 0.0f;
+    for (int ci = 0; ci < CI; ++ci) {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const float x = tile[ci][tp + k];
+            const float *w = wl + (ci * KS + k) * CO + cg * OPT;
+#pragma unroll
+            for (int o = 0; o < OPT; ++o) acc[o] = fmaf(w[o], x, acc[o]);
+        }
+    }
+    if (p < n) {
+        float *ob = out + (size_t)b * CO * n;
+#pragma unroll
+        for (int o = 0; o < OPT; ++o) {
+            const int co = cg * OPT + o;
+            float v = acc[o];
+            if constexpr (EPI == 0) v = tanhf(v + bias[co]);
+            else if constexpr (EPI == 1) v = v + bias[co];
+            else {
+                const float a = act[(size_t)b * CO * n + (size_t)co * n + p];
+                v = v * (1.0f - a * a);
+            }
+            ob[(size_t)co * n + p] = v;
+        }
+    }
+}
+
+// Widen a layer's bfloat16 weights W[co][ci][k] to FP32 in the order the
+// convolution reads: forward Wt[ci][k][co]; for the backward pass through the
+// data (a convolution from co channels to ci channels with the taps reversed)
+// Wb[co][k][ci] = W[co][ci][KS-1-k].
+__global__ void k_net_widen(const uint16_t *__restrict__ W, int ci_n, int co_n, float *__restrict__ Wt,
+                            float *__restrict__ Wb) {
+    const int tot = ci_n * co_n * KS;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
+        const int co = idx / (ci_n * KS), ci = (idx / KS) % ci_n, k = idx % KS;
+        const float w = bf16_to_f32(W[idx]);
+        Wt[(ci * KS + k) * co_n + co] = w;
+        if (Wb) Wb[(co * KS + (KS - 1 - k)) * ci_n + ci] = w;
+    }
+}
+
+// dY = 2 (y - y*) / (B n); per-workgroup partial sums of (y - y*)^2.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_net_loss(const float *__restrict__ y, const float *__restrict__ ystar,
+                                                 int64_t total, float *__restrict__ dy, double *__restrict__ part) {
+    double acc = 0.0;
+    const float sc = (float)(2.0 / (double)total);
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < total; i += (int64_t)gridDim.x * NT) {
+        const float d = y[i] - ystar[i];
+        dy[i] = sc * d;
+        acc = fma((double)d, (double)d, acc);
+    }
+    const double s = block_sum<NT>(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Weight and bias gradients of one layer:
+//   dW[co][ci][k] = sum_b sum_p dZ[b][co][p] a[b][ci][p + k - 2],
+//   db[co]        = sum_b sum_p dZ[b][co][p].
+// Thread (ci, cb) accumulates a block of COB output channels x KS taps for
+// input channel ci (and, for ci = 0, the biases of its channels) over the
+// positions of its workgroup; the partial sums of every workgroup are summed
+// in a fixed order by k_net_wgrad_reduce.
+// ---------------------------------------------------------------------------
+template <int CI, int CO> struct WgradGeo {
+    static constexpr int COB = CO < 4 ? CO : 4;
+    static constexpr int NTH = CI * (CO / COB);
+    static constexpr int NT = NTH <= 64 ? 64 : (NTH <= 128 ? 128 : 256);
+    static constexpr int TX = 128;
+    static constexpr int NE = CO * CI * KS + CO;  // entries per layer
+};
+
+template <int CI, int CO>
+__global__ void __launch_bounds__((WgradGeo<CI, CO>::NT)) k_net_wgrad(const float *__restrict__ dz,
+                                                                     const float *__restrict__ a, int64_t n,
+                                                                     float *__restrict__ part) {
+    using G = WgradGeo<CI, CO>;
+    constexpr int TX = G::TX, COB = G::COB, NT = G::NT;
+    __shared__ float ta[CI][TX + 2 * HALF];
+    __shared__ float tz[CO][TX];
+    const int b = blockIdx.y;
+    const float *ab = a + (size_t)b * CI * n;
+    const float *zb = dz + (size_t)b * CO * n;
+    const int t = threadIdx.x;
+    const bool own = t < G::NTH;
+    const int ci = own ? t % CI : 0, cb = own ? t / CI : 0;
+    float acc[COB][KS];
+    float accb[COB];
+#pragma unroll
+    for (int o = 0; o < COB; ++o) {
+        accb[o] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) acc[o][k] = 0.0f;
+    }
+    for (int64_t p0 = (int64_t)blockIdx.x * TX; p0 < n; p0 += (int64_t)gridDim.x * TX) {
+        __syncthreads();
+        for (int idx = t; idx < CI * (TX + 2 * HALF); idx += NT) {
+            const int c = idx / (TX + 2 * HALF), q = idx % (TX + 2 * HALF);
+            const int64_t p = p0 + q - HALF;
+            ta[c][q] = (p >= 0 && p < n) ? ab[(size_t)c * n + p] : 0.0f;
+        }
+        for (int idx = t; idx < CO * TX; idx += NT) {
+            const int c = idx / TX, q = idx % TX;
+            const int64_t p = p0 + q;
+            tz[c][q] = p < n ? zb[(size_t)c * n + p] : 0.0f;
+        }
+        __syncthreads();
+        if (own) {
+            for (int q = 0; q < TX; ++q) {
+                float av[KS];
+#pragma unroll
+                for (int k = 0; k < KS; ++k) av[k] = ta[ci][q + k];
+#pragma unroll
+                for (int o = 0; o < COB; ++o) {
+                    const float z = tz[cb * COB + o][q];
+                    accb[o] += z;
+#pragma unroll
+                    for (int k = 0; k < KS; ++k) acc[o][k] = fmaf(z, av[k], acc[o][k]);
+                }
+            }
+        }
+    }
+    if (own) {
+        float *pw = part + (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * G::NE;
+#pragma unroll
+        for (int o = 0; o < COB; ++o) {
+            const int co = cb * COB + o;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) pw[(co * CI + ci) * KS + k] = acc[o][k];
+            if (ci == 0) pw[CO * CI * KS + co] = accb[o];
+        }
+    }
+}
+
+// grad[e] = sum over workgroups w (in index order) of part[w][e].
+__global__ void k_net_wgrad_reduce(const float *__restrict__ part, int nwg, int ne, float *__restrict__ grad) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    float s = 0.0f;
+    for (int w = 0; w < nwg; ++w) s += part[(size_t)w * ne + e];
+    grad[e] = s;
+}
+
+// Adam (Kingma and Ba 2015, Algorithm 1) on the FP32 master parameters, then
+// the bfloat16 copy the convolutions read.
+__global__ void k_net_adam(float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v,
+                           const float *__restrict__ g, uint16_t *__restrict__ wbf, int count, float lr, float b1,
+                           float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float th = theta[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    theta[i] = th;
+    wbf[i] = f32_to_bf16(th);
+}
+
+__global__ void k_net_round(const float *__restrict__ theta, uint16_t *__restrict__ wbf, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) wbf[i] = f32_to_bf16(theta[i]);
+}
+
+}  // namespace net
+}  // namespace tsf

@@ -1,0 +1,186 @@
+"""GPU parity of the learned warm start: the network's forward pass,
+gradients and Adam update against the FP64 CPU reference of the same network
+(weights rounded to bfloat16 on both sides), its use inside a plan
+(TSFCDE_WS_NET), and what training gains over the previous-level guess."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle.warmnet_oracle as NO
+import workloads as W
+from gpu_util import banner, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    import paper_1603_00279_amd as P
+    P.lib()
+
+
+def _params(rng, scale=1.0):
+    """Random parameters with fan-in scaling (layer outputs of order one)."""
+    out = []
+    for ci, co in NO.LAYERS:
+        out.append((rng.normal(0, scale / np.sqrt(ci * NO.KS), (co, ci, NO.KS)), rng.normal(0, 0.1, co)))
+    return NO.pack(out).astype(np.float32)
+
+
+def _levels(rng, n, smooth=True):
+    """Four consecutive levels u^{j-2}, u^{j-1}, u^j, u^{j+1} (FP64, device)."""
+    x = np.linspace(0, 1, n + 2)[1:-1]
+    base = x ** 2 * (1 - x) ** 2
+    us = []
+    for k in range(4):
+        t = 0.3 + 0.05 * k
+        u = base * (t ** 2 + 0.3 * t ** 3) + 1e-3 * rng.normal(size=n) * (0.2 if smooth else 1.0) * t
+        us.append(u)
+    return us
+
+
+def _sample(P, dev_levels, feat, target=True):
+    from paper_1603_00279_amd import _native as N
+    u2, u1, u0, un = dev_levels
+    s = N.tsfcde_net_sample()
+    s.u_next = ctypes.c_void_p(un.data_ptr()) if target else None
+    s.u0, s.u1, s.u2 = (ctypes.c_void_p(v.data_ptr()) for v in (u0, u1, u2))
+    for c in range(5):
+        s.feat[c] = float(feat[c])
+    return s
+
+
+def _oracle_case(us, feat):
+    u2, u1, u0, un = us
+    X, base, s = NO.inputs(u0, u1, u2, np.asarray(feat, dtype=np.float32).astype(np.float64))
+    return X, base, s, NO.target(un, base, s)
+
+
+def test_forward_matches_oracle():
+    import paper_1603_00279_amd as P
+    banner("net forward")
+    rng = np.random.default_rng(7)
+    n = 777  # several tiles of every kernel and a ragged tail
+    us = _levels(rng, n)
+    feat = rng.normal(size=5).astype(np.float32)
+    theta = _params(rng)
+    with P.WarmStartNet(max_points=4096, max_batch=4) as net:
+        net.set_params(theta)
+        dev = [torch.as_tensor(u, device="cuda") for u in us]
+        x0 = net.predict(_sample(P, dev, feat, target=False), n).cpu().numpy()
+    th = NO.weights_bf16(theta.astype(np.float64))
+    X, base, s, _ = _oracle_case(us, feat)
+    y_ref, _ = NO.forward(th, X)
+    y_gpu = (x0 - base) / s
+    assert np.max(np.abs(y_gpu - y_ref)) <= 2e-5 * max(1.0, np.max(np.abs(y_ref))), np.max(np.abs(y_gpu - y_ref))
+
+
+@pytest.mark.parametrize("count,n", [(1, 64), (3, 333), (5, 1000)])
+def test_gradient_matches_oracle(count, n):
+    """Loss and gradient of the training step (lr = 0: no update) against the
+    FP64 reference; FP32 accumulation over count * n points."""
+    import paper_1603_00279_amd as P
+    banner(f"net gradient count={count} n={n}")
+    rng = np.random.default_rng(11 + count)
+    theta = _params(rng)
+    cases, samples, keep = [], [], []
+    for b in range(count):
+        us = _levels(rng, n, smooth=False)
+        feat = rng.normal(size=5).astype(np.float32)
+        dev = [torch.as_tensor(u, device="cuda") for u in us]
+        keep.append(dev)
+        samples.append(_sample(P, dev, feat))
+        X, base, s, ystar = _oracle_case(us, feat)
+        cases.append((X, ystar))
+    with P.WarmStartNet(max_points=count * n, max_batch=count) as net:
+        net.set_params(theta)
+        loss, grad = net.train_step(samples, n, 0.0, want_grad=True)
+        assert np.array_equal(net.get_params(), theta)  # lr = 0 leaves the parameters
+    th = NO.weights_bf16(theta.astype(np.float64))
+    loss_ref, g_ref = NO.loss_and_grad(th, cases)
+    assert abs(loss - loss_ref) <= 1e-5 * loss_ref, (loss, loss_ref)
+    o = 0
+    for ci, co in NO.LAYERS:
+        m = co * ci * NO.KS + co
+        gl, rl = grad[o:o + m].astype(np.float64), g_ref[o:o + m]
+        assert np.linalg.norm(gl - rl) <= 1e-4 * np.linalg.norm(rl) + 1e-9, (ci, co, np.linalg.norm(gl - rl),
+                                                                             np.linalg.norm(rl))
+        o += m
+
+
+def test_adam_steps_match_oracle():
+    import paper_1603_00279_amd as P
+    banner("net adam")
+    rng = np.random.default_rng(5)
+    n = 256
+    theta = _params(rng)
+    us = _levels(rng, n, smooth=False)
+    feat = rng.normal(size=5).astype(np.float32)
+    dev = [torch.as_tensor(u, device="cuda") for u in us]
+    smp = [_sample(P, dev, feat)]
+    lr = 1e-3
+    with P.WarmStartNet(max_points=n, max_batch=1) as net:
+        net.set_params(theta)
+        _, g1 = net.train_step(smp, n, lr, want_grad=True)
+        th1 = net.get_params()
+        _, g2 = net.train_step(smp, n, lr, want_grad=True)
+        th2 = net.get_params()
+    m = v = np.zeros(theta.size)
+    r1, m, v = NO.adam_step(theta.astype(np.float64), m, v, g1.astype(np.float64), 1, lr)
+    r2, m, v = NO.adam_step(th1.astype(np.float64), m, v, g2.astype(np.float64), 2, lr)
+    assert np.max(np.abs(th1 - r1)) <= 1e-6 * max(1.0, np.max(np.abs(r1)))
+    assert np.max(np.abs(th2 - r2)) <= 2e-6 * max(1.0, np.max(np.abs(r2)))
+    assert np.max(np.abs(th1 - theta)) > 0.5 * lr  # the first step moves by about lr
+
+
+def test_zero_network_reproduces_extrapolation():
+    """With all parameters zero the prediction is the quadratic
+    extrapolation exactly, so a TSFCDE_WS_NET march equals the
+    TSFCDE_WS_EXTRAP march bit for bit wherever the network's guess wins."""
+    import paper_1603_00279_amd as P
+    from paper_1603_00279_amd import warmnet as WN
+    banner("zero net = extrapolation")
+    prob = W.config_large(n=1000, M=10)
+    F = WN.device_sources(prob, torch.device("cuda"))
+    with P.TimeLevelSolver.from_problem(prob, warm_start=P.TSFCDE_WS_EXTRAP) as s:
+        s.solve(F)
+        Ue = s.history().cpu().numpy()
+    with P.WarmStartNet(max_points=prob.n, max_batch=1) as net, \
+            P.TimeLevelSolver.from_problem(prob, warm_start=P.TSFCDE_WS_NET) as s:
+        net.attach(s)
+        code, stats = s.solve(F)
+        Un = s.history().cpu().numpy()
+    guesses = [st["guess"] for st in stats]
+    assert guesses[0] == P.TSFCDE_WS_ZERO and guesses[1] == P.TSFCDE_WS_PREV
+    assert all(g == P.TSFCDE_WS_NET for g in guesses[2:]), guesses
+    assert np.array_equal(Ue, Un)
+
+
+def test_training_reduces_loss_and_beats_previous_level():
+    """A short training run on solver trajectories (n = 1024) lowers the loss,
+    and on held-out (alpha, beta) the learned guess needs fewer CGS
+    iterations than the previous-level guess (it never does worse: the true
+    residual picks between the two)."""
+    import paper_1603_00279_amd as P
+    from paper_1603_00279_amd import warmnet as WN
+    banner("net training")
+    n, M = 1024, 24
+    train_set = W.warmstart_instances(12, n, M, seed=101)
+    data = WN.Trajectories(train_set)
+    with P.WarmStartNet(max_points=16 * n, max_batch=16) as net:
+        net.set_params(_params(np.random.default_rng(0), 0.5))
+        losses = WN.train(net, data, steps=300, batch=16, lr=2e-3, seed=1)
+        first, last = np.mean(losses[:20]), np.mean(losses[-20:])
+        assert last < 0.5 * first, (first, last)
+        held = W.warmstart_instances(2, n, M, seed=202, held_out=True)
+        it_prev, it_net = [], []
+        for prob in held:
+            ip, _ = WN.march_iterations(prob, P.TSFCDE_WS_PREV)
+            inn, g = WN.march_iterations(prob, P.TSFCDE_WS_NET, net)
+            it_prev += ip[2:]
+            it_net += inn[2:]
+    data.close()
+    assert np.mean(it_net) < np.mean(it_prev), (np.mean(it_net), np.mean(it_prev))

@@ -17,5 +17,7 @@ from .problems import (  # noqa: F401
     config_small,
     config_large,
     batched_instances,
+    warmstart_instances,
+    HELD_OUT,
     SEED_BASE,
 )

@@ -292,3 +292,35 @@ def batched_instances(count: int = 512, M: int = 128, nmin: int = 1 << 10, nmax:
                            solution=sol, name=f"batch[{k}](n={n})",
                            meta={"c_plus": cp, "c_minus": cm, "g": g, "A": A}))
     return out
+
+
+HELD_OUT = ((0.45, 0.6), (1.45, 1.6))  # (alpha, beta) rectangle kept out of training
+
+
+def warmstart_instances(count: int, n: int, M: int, seed: int = SEED_BASE + 4, held_out: bool = False):
+    """Instances for the learned warm start: the batched family's parameter
+    distributions at one grid size n, with (alpha, beta) outside the held-out
+    rectangle HELD_OUT (training) or inside it (held-out evaluation).
+    Rejection sampling keeps the two sets disjoint for any seed."""
+    rng = np.random.default_rng(seed)
+    (a0, a1), (b0, b1) = HELD_OUT
+    out = []
+    while len(out) < count:
+        if held_out:
+            alpha, beta = float(rng.uniform(a0, a1)), float(rng.uniform(b0, b1))
+        else:
+            alpha, beta = float(rng.uniform(0.1, 0.95)), float(rng.uniform(1.1, 1.95))
+            if a0 <= alpha <= a1 and b0 <= beta <= b1:
+                continue
+        cp, cm = (float(v) for v in rng.uniform(0.2, 2.0, size=2))
+        g = float(rng.uniform(-1.0, 1.0))
+        A = float(rng.uniform(0.5, 2.0))
+        k = len(out)
+        sol = ManufacturedSolution([(A, 2.0)], _x2_one_minus_x2())
+        out.append(Problem(alpha=alpha, beta=beta, n=n, M=M,
+                           gamma=(lambda t, g=g: g * (1.0 + t)),
+                           dplus=(lambda t, c=cp: c * (1.0 + t)),
+                           dminus=(lambda t, c=cm: c * (1.0 + t)),
+                           solution=sol, name=f"warm[{k}](n={n})",
+                           meta={"c_plus": cp, "c_minus": cm, "g": g, "A": A}))
+    return out
