@@ -273,7 +273,8 @@ int tsfcde_batch_destroy(tsfcde_batch_t batch);
  * A four-layer 1-D convolutional network (7 -> 32 -> 32 -> 32 -> 1 channels,
  * width 5, zero padding, tanh after the first three) predicts level j+1 from
  * levels j, j-1, j-2 as a correction to quadratic extrapolation in t:
- *   x0 = 3(u^j - u^{j-1}) + u^{j-2} + s * y,
+ *   x0 = 3(u^j - u^{j-1}) + u^{j-2} + y * e2
+ * (smooth, and zero where u is fixed in time, as at the Dirichlet boundary),
  * with y the network output for the channels (e1/s, e2/s, alpha, beta,
  * asinh q_gamma, log1p q_+, log1p q_-), e1 = u^j - u^{j-1},
  * e2 = u^j - 2u^{j-1} + u^{j-2}, s = RMS(e2) (1 if e2 = 0), and the level
@@ -313,9 +314,10 @@ int tsfcde_net_get_params(tsfcde_net_t net, float *h_params);
 int tsfcde_level_features(tsfcde_plan_t plan, int64_t j, float *h_feat5);
 
 /* One training step on `count` samples of n points (every u_next set):
- * loss = mean over samples and points of (y - y*)^2 with
- * y* = (u^{j+1} - 3(u^j - u^{j-1}) - u^{j-2}) / s, its gradient by the
- * network's backward kernels, then one Adam update (lr; beta1 = 0.9,
+ * loss = mean over samples of the relative error of the correction,
+ * sum_p (y_p e2_p - d_p)^2 / (sum_p d_p^2 + n 1e-12 s^2), with
+ * d = u^{j+1} - 3(u^j - u^{j-1}) - u^{j-2} (zero correction scores 1), its
+ * gradient by the network's backward kernels, then one Adam update (lr; beta1 = 0.9,
  * beta2 = 0.999, eps = 1e-8, bias-corrected).  h_samples: host array.
  * loss_out (host, nullable) receives the loss before the update.
  * h_grad_out (host, nullable; param_count floats) receives the gradient; with

@@ -234,7 +234,7 @@ constexpr int NET_LOSS_WG = 256;
 static_assert(sizeof(tsfcde_net_sample) == sizeof(net::Sample), "sample layout");
 
 struct NetLayout {
-    size_t theta, m, v, grad, wbf, wt, wb, X, act, y, ystar, dy, dz0, dz1, part, s, lpart, smp, total;
+    size_t theta, m, v, grad, wbf, wt, wb, X, act, y, ystar, dy, dz0, dz1, part, s, den, lpart, smp, total;
 };
 
 NetLayout net_layout(int64_t mp, int32_t mb) {
@@ -261,6 +261,7 @@ NetLayout net_layout(int64_t mp, int32_t mb) {
     l.dz1 = take(4 * (size_t)net::WIDTH * mp);
     l.part = take(4 * (size_t)NET_WG_MAX * NET_NE_MAX);
     l.s = take(8 * (size_t)mb);
+    l.den = take(8 * (size_t)mb);
     l.lpart = take(8 * (size_t)NET_LOSS_WG);
     l.smp = take(sizeof(net::Sample) * (size_t)mb);
     l.total = o;
@@ -275,7 +276,7 @@ struct tsfcde_net_s {
     int32_t max_batch = 0;
     float *theta, *m, *v, *grad, *wt, *wb, *X, *act, *y, *ystar, *dy, *dz0, *dz1, *part;
     uint16_t *wbf;
-    double *s, *lpart;
+    double *s, *den, *lpart;
     net::Sample *smp;
     bool widened = false;
     int64_t step = 0;
@@ -345,9 +346,9 @@ int net_wgrad(tsfcde_net_s *nt, const float *dz, const float *a, int count, int6
 // Loss partials and the gradient of the loss in nt->grad (after net_forward
 // with targets).
 int net_backward(tsfcde_net_s *nt, int count, int64_t n) {
-    const int64_t total = (int64_t)count * n;
-    hipLaunchKernelGGL(net::k_net_loss<256>, dim3(NET_LOSS_WG), dim3(256), 0, nt->stream, nt->y, nt->ystar, total,
-                       nt->dy, nt->lpart);
+    hipLaunchKernelGGL(net::k_net_den<256>, dim3(count), dim3(256), 0, nt->stream, nt->ystar, n, nt->den);
+    hipLaunchKernelGGL(net::k_net_loss<256>, dim3(NET_LOSS_WG), dim3(256), 0, nt->stream, nt->y, nt->ystar, nt->X,
+                       nt->den, count, n, nt->dy, nt->lpart);
     const size_t A = (size_t)net::WIDTH * count * n;
     float *a1 = nt->act, *a2 = nt->act + A, *a3 = nt->act + 2 * A;
     auto grid = [&](int tx) { return dim3((unsigned)((n + tx - 1) / tx), (unsigned)count); };
@@ -389,7 +390,7 @@ int net_predict(tsfcde_net_s *nt, const tsfcde_net_sample &smp, int64_t n, doubl
     net::Sample S;
     std::memcpy(&S, &smp, sizeof(S));
     hipLaunchKernelGGL(net::k_net_output, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0,
-                       nt->stream, S, n, nt->s, nt->y, d_x0);
+                       nt->stream, S, n, nt->y, d_x0);
     NCHK(hipGetLastError());
     return TSFCDE_OK;
 }
@@ -1469,6 +1470,7 @@ int tsfcde_net_create(void *d_workspace, size_t bytes, int64_t max_points, int32
     nt->dz1 = reinterpret_cast<float *>(ws + L.dz1);
     nt->part = reinterpret_cast<float *>(ws + L.part);
     nt->s = reinterpret_cast<double *>(ws + L.s);
+    nt->den = reinterpret_cast<double *>(ws + L.den);
     nt->lpart = reinterpret_cast<double *>(ws + L.lpart);
     nt->smp = reinterpret_cast<net::Sample *>(ws + L.smp);
     // parameters, optimiser state and the bfloat16 copy start at zero
@@ -1533,7 +1535,7 @@ int tsfcde_net_train_step(tsfcde_net_t nt, const tsfcde_net_sample *h, int32_t c
     if (loss_out) {
         double t = 0.0;
         for (double v : lp) t += v;
-        *loss_out = t / ((double)count * (double)n);
+        *loss_out = t / (double)count;
     }
     return TSFCDE_OK;
 }

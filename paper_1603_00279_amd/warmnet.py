@@ -115,18 +115,27 @@ def device_sources(prob, device) -> torch.Tensor:
 
 class Trajectories:
     """Whole marches of many instances of one grid size, solved together by
-    the batched form; their stored levels are the training data."""
+    the batched form; their stored levels are the training data.  Each
+    level's sources are formed for all instances at once from the
+    separable manufactured source (profiles x coefficients)."""
 
-    def __init__(self, problems, rtol: float = 1e-10, warm_start: int = N.TSFCDE_WS_EXTRAP):
+    def __init__(self, problems, rtol: float = 1e-10, warm_start: int = N.TSFCDE_WS_EXTRAP, log=None):
         assert len({p.n for p in problems}) == 1 and len({p.M for p in problems}) == 1
         self.problems = problems
         self.n, self.M = problems[0].n, problems[0].M
         self.batch = BatchSolver(problems, rtol=rtol, warm_start=warm_start)
         dev = self.batch.device
-        srcs = [device_sources(p, dev) for p in problems]
+        profs, coefs = zip(*(p.source_profiles() for p in problems))
+        prof = torch.as_tensor(np.stack(profs), dtype=torch.float64, device=dev)      # (count, 4, n)
+        coef = torch.as_tensor(np.stack(coefs), dtype=torch.float64, device=dev)      # (count, M, 4)
+        self.iters = []
         for j in range(self.M):
-            self.batch.step([F[j] for F in srcs])
-        del srcs
+            Fj = torch.bmm(coef[:, j:j + 1, :].contiguous(), prof)[:, 0, :].contiguous()  # (count, n)
+            _, stats = self.batch.step([Fj[i] for i in range(len(problems))])
+            self.iters.append(float(np.mean([st["iters"] for st in stats])))
+            if log and (j % max(1, self.M // 8) == 0 or j == self.M - 1):
+                log(f"trajectories: level {j + 1}/{self.M}, mean CGS iterations {self.iters[-1]:.2f}")
+        del prof, coef
         lib = N.lib()
         self.members = [self.batch.member(i) for i in range(len(problems))]
         self.hist = [int(lib.tsfcde_history(h)) for h in self.members]
@@ -142,6 +151,17 @@ class Trajectories:
 
     def close(self):
         self.batch.close()
+
+
+def initial_params(seed: int = 0) -> np.ndarray:
+    """Fan-in scaled random hidden layers and a zero output layer, so that an
+    untrained network predicts the quadratic extrapolation exactly."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in ((7, 32), (32, 32), (32, 32), (32, 1)):
+        w = rng.normal(0, 1.0 / np.sqrt(ci * 5), co * ci * 5) if co > 1 else np.zeros(co * ci * 5)
+        parts.append(np.concatenate([w, np.zeros(co)]))
+    return np.concatenate(parts).astype(np.float32)
 
 
 def train(net: WarmStartNet, data: Trajectories, steps: int, batch: int, lr: float = 1e-3, seed: int = 0,
@@ -171,3 +191,84 @@ def march_iterations(prob, warm_start: int, net: Optional[WarmStartNet] = None, 
         code, stats = s.solve(F)
         N.check(code, "march")
         return [st["iters"] for st in stats], [st["guess"] for st in stats]
+
+
+def main(argv=None):
+    """Train on solver trajectories and compare the guesses on held-out
+    (alpha, beta).  Defaults: 2000 trajectories at n = 2^14, M = 256;
+    held-out evaluation at n = 2^14 and 2^18."""
+    import argparse
+    import json
+    import sys
+    import time
+
+    import workloads as W
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--count", type=int, default=2000)
+    ap.add_argument("--n", type=int, default=1 << 14)
+    ap.add_argument("--M", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-final", type=float, default=1e-5)
+    ap.add_argument("--eval-n", type=int, nargs="*", default=[1 << 14, 1 << 18])
+    ap.add_argument("--eval-count", type=int, default=4)
+    ap.add_argument("--out", default="warmnet_params.npz")
+    ap.add_argument("--report", default=None)
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(f"[warmnet] {msg}", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    train_set = W.warmstart_instances(args.count, args.n, args.M)
+    data = Trajectories(train_set, log=log)
+    t_gen = time.perf_counter() - t0
+    log(f"{args.count} trajectories in {t_gen:.1f} s")
+    report = {"train": {"count": args.count, "n": args.n, "M": args.M, "steps": args.steps, "batch": args.batch,
+                        "lr": args.lr, "trajectory_seconds": t_gen}}
+    with WarmStartNet(max_points=args.batch * args.n, max_batch=args.batch) as net:
+        net.set_params(initial_params(0))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        losses = train(net, data, args.steps, args.batch, args.lr, seed=1, lr_final=args.lr_final, log=log)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t1
+        report["train"].update({"seconds": t_train, "loss_first": float(np.mean(losses[:50])),
+                                "loss_last": float(np.mean(losses[-50:]))})
+        data.close()
+        theta = net.get_params()
+        np.savez(args.out, theta=theta, losses=np.asarray(losses))
+        log(f"trained in {t_train:.1f} s; loss {report['train']['loss_first']:.3e} -> "
+            f"{report['train']['loss_last']:.3e}; parameters in {args.out}")
+        report["eval"] = {}
+        for n in args.eval_n:
+            held = W.warmstart_instances(args.eval_count, n, args.M, seed=W.SEED_BASE + 40 + n % 97, held_out=True)
+            big = WarmStartNet(max_points=n, max_batch=1)
+            big.set_params(theta)
+            res = {"prev": [], "extrap": [], "net": [], "net_levels_using_net": 0, "levels": 0}
+            for prob in held:
+                F = device_sources(prob, big.device)
+                for key, ws, nt in (("prev", N.TSFCDE_WS_PREV, None), ("extrap", N.TSFCDE_WS_EXTRAP, None),
+                                    ("net", N.TSFCDE_WS_NET, big)):
+                    it, g = march_iterations(prob, ws, nt, F=F)
+                    res[key] += it[2:]
+                    if key == "net":
+                        res["net_levels_using_net"] += sum(1 for x in g[2:] if x == N.TSFCDE_WS_NET)
+                        res["levels"] += len(g) - 2
+                del F
+            big.close()
+            summary = {k: float(np.mean(v)) for k, v in res.items() if isinstance(v, list)}
+            summary["net_share"] = res["net_levels_using_net"] / max(1, res["levels"])
+            report["eval"][str(n)] = summary
+            log(f"held-out n={n}: mean CGS iterations prev {summary['prev']:.2f}, extrap {summary['extrap']:.2f}, "
+                f"net {summary['net']:.2f} (net guess kept at {100 * summary['net_share']:.0f}% of levels)")
+    if args.report:
+        with open(args.report, "w") as fh:
+            json.dump(report, fh, indent=1)
+    print(json.dumps(report), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -72,10 +72,11 @@ def test_forward_matches_oracle():
         dev = [torch.as_tensor(u, device="cuda") for u in us]
         x0 = net.predict(_sample(P, dev, feat, target=False), n).cpu().numpy()
     th = NO.weights_bf16(theta.astype(np.float64))
-    X, base, s, _ = _oracle_case(us, feat)
-    y_ref, _ = NO.forward(th, X)
-    y_gpu = (x0 - base) / s
-    assert np.max(np.abs(y_gpu - y_ref)) <= 2e-5 * max(1.0, np.max(np.abs(y_ref))), np.max(np.abs(y_gpu - y_ref))
+    u2, u1, u0, _ = us
+    x0_ref = NO.predict(th, u0, u1, u2, feat.astype(np.float64))
+    base = 3.0 * (u0 - u1) + u2
+    corr_ref, corr = x0_ref - base, x0 - base
+    assert np.max(np.abs(corr - corr_ref)) <= 2e-5 * np.max(np.abs(corr_ref)), np.max(np.abs(corr - corr_ref))
 
 
 @pytest.mark.parametrize("count,n", [(1, 64), (3, 333), (5, 1000)])

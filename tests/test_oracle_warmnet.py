@@ -22,14 +22,14 @@ def test_backward_matches_central_differences():
     theta = _rand_theta(rng, 0.2)
     n = 11
     X = rng.normal(size=(N.CIN, n))
-    ystar = rng.normal(size=n)
+    t = rng.normal(size=n)
 
     def f(th):
         y, _ = N.forward(th, X)
-        return N.loss(y, ystar)
+        return N.loss(y, X[1], t)
 
     y, acts = N.forward(theta, X)
-    g = N.backward(theta, acts, 2.0 * (y - ystar) / n)
+    g = N.backward(theta, acts, N.loss_dy(y, X[1], t))
     idx = rng.choice(theta.size, 60, replace=False)
     # every layer's weights and biases among the probes
     offs = np.cumsum([0] + [co * ci * N.KS + co for ci, co in N.LAYERS])
@@ -109,3 +109,31 @@ def test_level_features_by_hand():
     qg = 0.75 * -1.0 / (0.25 * 2.0)
     qp = 0.75 * 1.0 * 0.25 ** -1.5 / 2.0
     assert np.allclose(f, [0.5, 1.5, math.asinh(qg), math.log1p(qp), math.log1p(qp / 2)], rtol=1e-15)
+
+
+def test_loss_of_zero_correction_is_one_and_derivative_by_differences():
+    rng = np.random.default_rng(5)
+    n = 9
+    x1, t, y = rng.normal(size=(3, n))
+    assert math.isclose(N.loss(np.zeros(n), x1, t), 1.0, rel_tol=1e-10)
+    d = N.loss_dy(y, x1, t)
+    h = 1e-7
+    for p in range(n):
+        e = np.zeros(n)
+        e[p] = h
+        fd = (N.loss(y + e, x1, t) - N.loss(y - e, x1, t)) / (2 * h)
+        assert abs(fd - d[p]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_correction_vanishes_with_the_second_difference():
+    """Where e2 = 0 (u fixed in time, e.g. at a Dirichlet boundary) the
+    prediction is the extrapolation, whatever the parameters."""
+    rng = np.random.default_rng(6)
+    n = 12
+    u = rng.normal(size=(3, n))
+    u[:, :3] = 1.5  # the first three points constant in time
+    theta = rng.normal(0, 0.3, N.param_count())
+    x0 = N.predict(theta, u[2], u[1], u[0], rng.normal(size=5))
+    base = 3.0 * (u[2] - u[1]) + u[0]
+    assert np.array_equal(x0[:3], base[:3])
+    assert not np.allclose(x0[3:], base[3:])
