@@ -55,6 +55,160 @@ def build_sources(prob, device):
     return F
 
 
+def committed_traffic(kclass, n):
+    """HBM bytes per launch of the profiled kernel from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE scaled by a plain copy), if there is one
+    for this kernel and size."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kclass}_n{n}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    return {"bytes_per_launch": d["fetch_bytes"] + d["write_bytes"], "source": os.path.relpath(path, ROOT)}
+
+
+def timed_march(solver, F, u0, levels, torch):
+    """Wall time and per-level stats of one march from level 0."""
+    solver.set_state(0, u0.view(1, -1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [solver.step(F[j]) for j in range(levels)]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, stats
+
+
+def forms(args, P, W, prob, F, u0, levels, plain_value, dev):
+    """The other forms, each beside the plain FP64 path on its own workload."""
+    import numpy as np
+    import torch
+    res = {}
+    # warm starts on the headline workload
+    for ws, name in ((P.TSFCDE_WS_PREV, "previous_level"), (P.TSFCDE_WS_EXTRAP, "extrapolated")):
+        with P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, warm_start=ws) as sw:
+            dt, st = timed_march(sw, F, u0, levels, torch)
+        res[name] = {"workload": "headline", "value": levels / dt, "unit": "level-solves/s",
+                     "cgs_iterations_mean": float(np.mean([x["iters"] for x in st])),
+                     "speedup_vs_plain": (levels / dt) / plain_value}
+        log(f"form {name}: {levels / dt:.1f} level-solves/s")
+    # FP32-refined: on the headline workload the rounding-error model keeps
+    # FP64; inside the envelope it refines in FP32
+    with P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, precision=P.TSFCDE_FP32_REFINED) as sw:
+        dt, st = timed_march(sw, F, u0, levels, torch)
+    share = float(np.mean([x["precision_used"] == P.TSFCDE_FP32_REFINED for x in st]))
+    res["fp32_refined"] = {"workload": "headline", "value": levels / dt, "unit": "level-solves/s",
+                           "levels_refined_in_fp32": share, "speedup_vs_plain": (levels / dt) / plain_value}
+    small = W.config_large(n=args.fp32_n, M=args.M)
+    Fs = build_sources(small, dev)
+    rates = {}
+    for prec in (P.TSFCDE_FP64, P.TSFCDE_FP32_REFINED):
+        with P.TimeLevelSolver.from_problem(small, rtol=args.rtol, precision=prec) as sw:
+            us = sw.history()[0].clone()
+            timed_march(sw, Fs, us, small.M, torch)  # warm-up
+            dt, st = timed_march(sw, Fs, us, small.M, torch)
+            rates[prec] = (small.M / dt, st)
+    st32 = rates[P.TSFCDE_FP32_REFINED][1]
+    res["fp32_refined_in_envelope"] = {
+        "workload": f"n={small.n}, M={small.M}, headline coefficients",
+        "value": rates[P.TSFCDE_FP32_REFINED][0], "plain_value": rates[P.TSFCDE_FP64][0], "unit": "level-solves/s",
+        "speedup_vs_plain": rates[P.TSFCDE_FP32_REFINED][0] / rates[P.TSFCDE_FP64][0],
+        "levels_refined_in_fp32": float(np.mean([x["precision_used"] == P.TSFCDE_FP32_REFINED for x in st32])),
+        "true_relres_max": float(max(x["relres_true"] for x in st32)),
+        "inner_iterations_mean": float(np.mean([x["iters"] for x in st32])),
+        "outer_sweeps_mean": float(np.mean([x["outer_iters"] for x in st32]))}
+    del Fs
+    log(f"form fp32_refined: headline {res['fp32_refined']['value']:.1f} (fp32 share {share:.2f}); "
+        f"n={small.n}: {res['fp32_refined_in_envelope']['speedup_vs_plain']:.2f}x plain")
+    res["batched"] = batched_form(args, P, W, dev)
+    res["learned"] = learned_form(args, P, W, dev)
+    return res
+
+
+def batched_form(args, P, W, dev):
+    """512 instances of uneven n, alpha, beta (n log-uniform in [2^10, 2^16],
+    M = 128) advanced together; the plain comparison runs single-instance
+    plans one after another on a sample of the instances."""
+    import numpy as np
+    import torch
+    from paper_1603_00279_amd import warmnet as WN
+    probs = W.batched_instances(count=args.batch_count, M=args.batch_M)
+    ns = [p.n for p in probs]
+    profs, coefs = zip(*(p.source_profiles() for p in probs))
+    groups = {}
+    for i, p in enumerate(probs):
+        groups.setdefault(p.n, []).append(i)
+    prof = [torch.as_tensor(a, dtype=torch.float64, device=dev) for a in profs]
+    coef = [torch.as_tensor(c, dtype=torch.float64, device=dev) for c in coefs]
+    Fall = [c @ pr for c, pr in zip(coef, prof)]  # (M x n) per instance
+    out = {"workload": f"{len(probs)} instances, n log-uniform in [2^10, 2^16] (sum {sum(ns)}), M={args.batch_M}"}
+    for ws, key in ((P.TSFCDE_WS_ZERO, "zero_guess"), (P.TSFCDE_WS_EXTRAP, "extrapolated")):
+        with P.BatchSolver(probs, rtol=args.rtol, warm_start=ws) as bs:
+            zeros = [torch.zeros(n, dtype=torch.float64, device=dev) for n in ns]
+            bs.reset(zeros)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its = []
+            for j in range(args.batch_M):
+                code, st = bs.step([Fi[j] for Fi in Fall])
+                its.append(np.mean([x["iters"] for x in st]))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        out[key] = {"value": len(probs) * args.batch_M / dt, "unit": "instance-levels/s",
+                    "unknown_levels_per_s": sum(ns) * args.batch_M / dt, "cgs_iterations_mean": float(np.mean(its))}
+        log(f"batched ({key}): {out[key]['value']:.0f} instance-levels/s")
+    sub = list(range(0, len(probs), max(1, len(probs) // 32)))
+    tot = 0.0
+    for i in sub:
+        with P.TimeLevelSolver.from_problem(probs[i], rtol=args.rtol) as s1:
+            u0 = s1.history()[0].clone()
+            dt, _ = timed_march(s1, Fall[i], u0, args.batch_M, torch)
+            tot += dt
+    seq = len(sub) * args.batch_M / tot
+    out["sequential_single_plans"] = {"value": seq, "unit": "instance-levels/s",
+                                      "sample": f"{len(sub)} of the instances, one plan after another"}
+    out["speedup_vs_plain"] = out["zero_guess"]["value"] / seq
+    log(f"batched: {out['speedup_vs_plain']:.1f}x sequential single-instance plans")
+    return out
+
+
+def learned_form(args, P, W, dev):
+    """The learned warm start with the committed parameters (trained by
+    paper_1603_00279_amd.warmnet on 2000 trajectories at n = 2^14, M = 256)
+    on held-out (alpha, beta) at n = 2^14, against the previous-level and
+    extrapolated guesses."""
+    import numpy as np
+    import torch
+    from paper_1603_00279_amd import warmnet as WN
+    path = os.path.join(ROOT, "paper_1603_00279_amd", "data", "warmnet_c4.npz")
+    theta = np.load(path)["theta"]
+    n, M = 1 << 14, 256
+    held = W.warmstart_instances(2, n, M, seed=W.SEED_BASE + 77, held_out=True)
+    out = {"workload": f"held-out (alpha, beta), n={n}, M={M}, Example-2 time dependence", "parameters":
+           os.path.relpath(path, ROOT)}
+    with P.WarmStartNet(max_points=n, max_batch=1) as net:
+        net.set_params(theta)
+        for ws, key in ((P.TSFCDE_WS_ZERO, "plain"), (P.TSFCDE_WS_PREV, "previous_level"),
+                        (P.TSFCDE_WS_EXTRAP, "extrapolated"), (P.TSFCDE_WS_NET, "network")):
+            tot, its, kept = 0.0, [], []
+            for prob in held:
+                F = WN.device_sources(prob, dev)
+                with P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, warm_start=ws) as s1:
+                    if ws == P.TSFCDE_WS_NET:
+                        net.attach(s1)
+                    u0 = s1.history()[0].clone()
+                    timed_march(s1, F, u0, M, torch)
+                    dt, st = timed_march(s1, F, u0, M, torch)
+                tot += dt
+                its += [x["iters"] for x in st[2:]]
+                kept += [x["guess"] == P.TSFCDE_WS_NET for x in st[2:]]
+            out[key] = {"value": len(held) * M / tot, "unit": "level-solves/s",
+                        "cgs_iterations_mean": float(np.mean(its))}
+            if ws == P.TSFCDE_WS_NET:
+                out[key]["levels_using_network_guess"] = float(np.mean(kept))
+            log(f"learned form ({key}): {out[key]['value']:.1f} level-solves/s, {np.mean(its):.2f} iterations")
+    out["speedup_vs_plain"] = out["network"]["value"] / out["plain"]["value"]
+    return out
+
+
 def cpu_baseline(n_full, M_full, budget_s=12.0):
     """Time the CPU oracle (dense LU per level, FP64) on a bounded sample."""
     import numpy as np
@@ -103,6 +257,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the warm-started forms")
     ap.add_argument("--profile-class", default="mid_matvec", choices=sorted(KCLASS))
+    ap.add_argument("--fp32-n", type=int, default=2048, help="grid of the FP32-refined form inside its envelope")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-M", type=int, default=128)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run three plain device copies of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -207,25 +364,12 @@ def main():
                      "algorithmic_bytes_per_launch": per_launch},
         "cgs_iterations": {"mean": float(np.mean(iters)), "min": int(min(iters)), "max": int(max(iters))},
     }
-    # the same march with the warm-started forms (one timed step each)
+    traffic = committed_traffic(args.profile_class, n)
+    if traffic is not None:
+        out["roofline"]["traffic"] = traffic["bytes_per_launch"]
+        out["roofline"]["traffic_source"] = traffic["source"]
     if not args.no_forms:
-        forms = {}
-        for ws, name in ((P.TSFCDE_WS_PREV, "previous_level"), (P.TSFCDE_WS_EXTRAP, "extrapolated")):
-            sw = P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, warm_start=ws)
-            stw = []
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            sw.set_state(0, u0.view(1, -1))
-            for j in range(levels):
-                stw.append(sw.step(F[j]))
-            torch.cuda.synchronize()
-            dtw = time.perf_counter() - t1
-            forms[name] = {"value": levels / dtw, "unit": "level-solves/s",
-                           "cgs_iterations_mean": float(np.mean([st["iters"] for st in stw])),
-                           "speedup_vs_plain": (levels / dtw) / value}
-            sw.close()
-            log(f"form {name}: {levels / dtw:.1f} level-solves/s")
-        out["forms"] = forms
+        out["forms"] = forms(args, P, W, prob, F, u0, levels, value, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(n, prob.M)

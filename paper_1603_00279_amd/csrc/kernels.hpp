@@ -30,9 +30,18 @@ struct DevScalars {
     double rho, rho_prev, alpha, beta, rtv, rnorm2, gnorm2, tol2;
     double aux0, aux1, rtol2, r0sq;  // r0sq: |g - A x0|^2 of the right-hand side's initial guess
     int iter, done, status, fresh;  // fresh: next CGS iteration starts from r (u = p = r)
+    int better;   // the last restart's |g - A x|^2 was below r0sq
+    int netkept;  // the learned guess was kept at this level (set by k_keep_better)
 };
 
 enum : int { ST_OK = 0, ST_BREAKDOWN = 1, ST_NONFINITE = 2 };
+
+// Predication of a launch on the device scalars: pred 0 always runs, pred 1
+// skips once the solve is done, pred 2 skips when the last restart found its
+// guess better than the right-hand side's (a second restart is then moot).
+__device__ __forceinline__ bool skip(int pred, const DevScalars *sc) {
+    return (pred == 1 && sc->done) || (pred == 2 && sc->better);
+}
 
 // Symbol of one level: S(k) = s0 + cre*Re(L_k) + i*(cim*Im(L_k) + cq*sin(2 pi k / L)),
 // where L_k is the stored spectrum of W_beta (embedding or Strang).  For a
@@ -542,6 +551,7 @@ struct OutRestart {
     __device__ void final(const double *tot, DevScalars *sc) const {
         sc->aux0 = tot[0];
         sc->aux1 = tot[1];
+        sc->better = (tot[0] < sc->r0sq) ? 1 : 0;  // isfinite by comparison
         sc->rnorm2 = tot[0];
         sc->rho = tot[0];
         sc->rho_prev = 1.0;
@@ -675,7 +685,7 @@ template <class Out, int NP> struct ColSink {
 template <int R, int EMAX, int DIR, class In, class Out>
 __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double2 *__restrict__ tw_all, DevScalars *sc,
                                          int pred) {
-    if (pred && sc->done) return;
+    if (skip(pred, sc)) return;
     using G = ColGeo<R, EMAX>;
     constexpr int E = G::E, T = G::T, B = G::B;
     __shared__ double2 lds[lpad_size(R) * B];
@@ -720,7 +730,7 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
 // Finishing kernel of a reducing pass (one workgroup of the pass's size NT).
 template <int NT, class Out>
 __global__ void __launch_bounds__(NT) k_final(Out out, int nparts, DevScalars *sc, int pred) {
-    if (pred && sc->done) return;
+    if (skip(pred, sc)) return;
     double tot[Out::NACC];
     reduce_partials<Out::NACC>(out.partials, nparts, tot);
     if (threadIdx.x == 0) out.final(tot, sc);
@@ -753,7 +763,7 @@ __global__ void __launch_bounds__((ColGeo<R, EMAX>::NT)) k_col_b(const ColDesc<I
 template <int NT, class In, class Out>
 __global__ void __launch_bounds__(NT) k_final_b(const ColDesc<In, Out> *__restrict__ d, int nparts, int pred) {
     const ColDesc<In, Out> &D = d[blockIdx.y];
-    if (pred && D.sc->done) return;
+    if (skip(pred, D.sc)) return;
     double tot[Out::NACC];
     reduce_partials<Out::NACC>(D.out.partials, nparts, tot);
     if (threadIdx.x == 0) D.out.final(tot, D.sc);
@@ -814,7 +824,7 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
                                                                 CS *__restrict__ bufA, Tw2 twA, Op op,
                                                                 const double2 *__restrict__ tw_all, DevScalars *sc,
                                                                 int pred) {
-    if (pred && sc->done) return;
+    if (skip(pred, sc)) return;
     using G = FuseGeo<RP, EMAX>;
     constexpr int RA = G::RA, EA = G::EA, TA = G::TA, B = G::B, EP = G::EP, TP = G::TP;
     __shared__ double2 lds[lpad_size(RA) * B];
@@ -931,7 +941,7 @@ using RowSink = RowSinkT<double2>;
 template <int C_, int EMAX, int MODE, class CS>
 __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, double2 *spec_out, Tw2 twL,
                                          SymParams sp, const double2 *__restrict__ tw_all, DevScalars *sc, int pred) {
-    if (pred && sc->done) return;
+    if (skip(pred, sc)) return;
     using G = MidGeo<C_, EMAX>;
     constexpr int E = G::E, T = G::T, LS = G::LS;
     constexpr int64_t C = C_;
@@ -1196,6 +1206,17 @@ __global__ void __launch_bounds__((RowGeo<C_, EMAX>::NT)) k_row_b(const RowDesc 
                                                                   const double2 *__restrict__ tw_all) {
     const RowDesc D = d[blockIdx.y];
     row_body<C_, EMAX, MODE>(D.Y, D.spec, D.spec_out, tw_all);
+}
+
+// x = fallback where the device scalars say the last restart's x did not
+// beat the right-hand side's initial guess (learned warm start).
+__global__ void k_keep_better(double *__restrict__ x, const double *__restrict__ fallback, int64_t n,
+                              DevScalars *sc) {
+    const int keep = sc->better;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->netkept = keep;  // no block reads netkept
+    if (keep) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = fallback[i];
 }
 
 // FP32 copy (round to nearest) of a complex FP64 array.

@@ -231,6 +231,7 @@ static_assert(NET_P == 11617, "parameter count");
 constexpr int NET_WG_MAX = 1024;  // workgroups of a weight-gradient pass
 constexpr int NET_NE_MAX = net::WIDTH * net::WIDTH * net::KS + net::WIDTH;
 constexpr int NET_LOSS_WG = 256;
+constexpr int NET_SCALE_PARTS = 64;  // workgroups per sample of the scale reduction
 static_assert(sizeof(tsfcde_net_sample) == sizeof(net::Sample), "sample layout");
 
 struct NetLayout {
@@ -260,7 +261,7 @@ NetLayout net_layout(int64_t mp, int32_t mb) {
     l.dz0 = take(4 * (size_t)net::WIDTH * mp);
     l.dz1 = take(4 * (size_t)net::WIDTH * mp);
     l.part = take(4 * (size_t)NET_WG_MAX * NET_NE_MAX);
-    l.s = take(8 * (size_t)mb);
+    l.s = take(8 * (size_t)mb * NET_SCALE_PARTS);
     l.den = take(8 * (size_t)mb);
     l.lpart = take(8 * (size_t)NET_LOSS_WG);
     l.smp = take(sizeof(net::Sample) * (size_t)mb);
@@ -305,12 +306,15 @@ int net_widen(tsfcde_net_s *nt) {
 
 // Inputs (and targets) of `count` samples already in nt->smp; then the
 // forward pass.  Activations: act + l * WIDTH * count * n for layers 1..3.
-int net_forward(tsfcde_net_s *nt, int count, int64_t n, bool targets) {
+int net_forward(tsfcde_net_s *nt, int count, int64_t n, bool targets, const net::Sample *one = nullptr) {
     int rc = net_widen(nt);
     if (rc) return rc;
-    hipLaunchKernelGGL(net::k_net_scale<256>, dim3(count), dim3(256), 0, nt->stream, nt->smp, n, nt->s);
+    const net::Sample *smp = one ? nullptr : nt->smp;
+    const net::Sample none = one ? *one : net::Sample{};
+    const int sx = (int)std::max<int64_t>(1, std::min<int64_t>(NET_SCALE_PARTS, (n + 4095) / 4096));
+    hipLaunchKernelGGL(net::k_net_scale<256>, dim3(sx, count), dim3(256), 0, nt->stream, smp, none, n, nt->s);
     const unsigned gx = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
-    hipLaunchKernelGGL(net::k_net_inputs, dim3(gx, count), dim3(256), 0, nt->stream, nt->smp, n, nt->s, nt->X,
+    hipLaunchKernelGGL(net::k_net_inputs, dim3(gx, count), dim3(256), 0, nt->stream, smp, none, n, nt->s, sx, nt->X,
                        targets ? nt->ystar : (float *)nullptr);
     const size_t A = (size_t)net::WIDTH * count * n;
     float *a1 = nt->act, *a2 = nt->act + A, *a3 = nt->act + 2 * A;
@@ -381,14 +385,14 @@ int net_upload(tsfcde_net_s *nt, const tsfcde_net_sample *h, int count) {
     return TSFCDE_OK;
 }
 
-// x0 for one sample into d_x0 (on the network's stream).
+// x0 for one sample into d_x0 (on the network's stream; the sample goes to
+// the kernels by value, so nothing waits on the host).
 int net_predict(tsfcde_net_s *nt, const tsfcde_net_sample &smp, int64_t n, double *d_x0) {
     if (n > nt->max_points) return TSFCDE_EINVAL;
-    int rc = net_upload(nt, &smp, 1);
-    if (rc) return rc;
-    if ((rc = net_forward(nt, 1, n, false))) return rc;
     net::Sample S;
     std::memcpy(&S, &smp, sizeof(S));
+    int rc = net_forward(nt, 1, n, false, &S);
+    if (rc) return rc;
     hipLaunchKernelGGL(net::k_net_output, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0,
                        nt->stream, S, n, nt->y, d_x0);
     NCHK(hipGetLastError());
@@ -786,12 +790,12 @@ constexpr int MAX_RESTARTS = 3;
 // on the stream, no synchronisation.
 // r = g - A x, rt = r and a fresh CGS state; x itself is accepted when it
 // meets rtol or, with bwtol > 0, the backward-error test.
-int restart_launch(tsfcde_plan_s *pl, int64_t j, const double *x, double bwtol) {
+int restart_launch(tsfcde_plan_s *pl, int64_t j, const double *x, double bwtol, int pred = 0) {
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
     InReal in{x, pl->n, pl->A.C};
     OutRestart out =
         with_red(OutRestart{pl->g, x, pl->r, pl->rt, pl->n, pl->A.C, pl->anorm[j], bwtol}, pl, 3);
-    HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
+    HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, pred));
     return TSFCDE_OK;
 }
 
@@ -919,9 +923,15 @@ int ir_solve(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so, int &outer, 
     hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, pl->stream, pl->d32, 0.0f, n);
     HIPCHK(hipGetLastError());
     for (;;) {
+        // outer residual, then at once the first chunk of the inner solve: the
+        // residual pass sets `done` when the level has converged, which
+        // predicates the inner kernels off, so one poll serves both
         InIR in{x, pl->d32, n, pl->A.C};
         OutIR out = with_red(OutIR{pl->g, x, pl->r32, pl->rt32, pl->d32, n, pl->A.C, irtol * irtol}, pl, 2);
         HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
+        const int budget = std::min(IR_INNER_MAXIT, pl->maxit - inner_total);
+        int chunk = std::min(std::max(2, pl->last_inner), std::max(0, budget));
+        for (int k = 0; k < chunk; ++k) HIPCHK(cgs_iter(pl, j, b32, pl->d32));
         if ((rc = poll(pl))) return rc;
         ++outer;
         const double res2 = pl->h_sc->aux1;
@@ -930,30 +940,25 @@ int ir_solve(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so, int &outer, 
             const double den = pl->anorm[j] * std::sqrt(pl->h_sc->aux0) + std::sqrt(pl->h_sc->gnorm2);
             so.backward_err = den > 0 ? std::sqrt(res2) / den : 0.0;
         }
-        if (pl->h_sc->status == ST_NONFINITE) {
+        if (!std::isfinite(res2)) {
             so.code = TSFCDE_ENONFINITE;
             break;
         }
-        if (pl->h_sc->done) break;
+        if (res2 <= pl->h_sc->rtol2 * pl->h_sc->gnorm2) break;  // converged; the inner chunk did not run
         slow = res2 > 0.25 * prev2 ? slow + 1 : 0;
         prev2 = res2;
         if (slow >= 2 || outer > IR_MAX_OUTER || inner_total >= pl->maxit) {
             fell_back = true;
             break;
         }
-        // inner FP32-stored CGS on A d = r (d = 0, rt = r set by the pass above)
-        int seen = 0, chunk = std::max(2, pl->last_inner);
-        // a sweep ends at the inner tolerance or after IR_INNER_MAXIT steps: a
-        // stalled inner CGS is restarted by the next sweep with a fresh rt
-        const int budget = std::min(IR_INNER_MAXIT, pl->maxit - inner_total);
-        for (;;) {
-            const int todo = std::min(chunk, budget - seen);
-            if (todo <= 0) break;
+        // the inner FP32-stored CGS on A d = r continues until its tolerance
+        // or the sweep's iteration budget
+        int seen = pl->h_sc->iter;
+        while (!pl->h_sc->done && seen < budget) {
+            const int todo = std::min(2, budget - seen);
             for (int k = 0; k < todo; ++k) HIPCHK(cgs_iter(pl, j, b32, pl->d32));
             if ((rc = poll(pl))) return rc;
             seen = pl->h_sc->iter;
-            if (pl->h_sc->done) break;
-            chunk = 2;
         }
         inner_total += seen;
         pl->last_inner = std::max(2, seen);
@@ -998,19 +1003,20 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
     int guess = warm == 2 ? TSFCDE_WS_EXTRAP : (warm == 1 ? TSFCDE_WS_PREV : TSFCDE_WS_ZERO);
     if (use_net) {
         // the network's guess, kept only if its true residual is below that of
-        // u^j (which the right-hand side pass left in r0sq)
+        // u^j (which the right-hand side pass left in r0sq); decided on the
+        // device: the restart pass records the comparison, k_keep_better puts
+        // u^j back when the network lost, and a second restart pass sets the
+        // CGS state for whichever guess stayed
         const double *Uj = pl->U + (size_t)j * pl->ldn;
         tsfcde_net_sample smp{nullptr, Uj, Uj - pl->ldn, Uj - 2 * pl->ldn, {0, 0, 0, 0, 0}, 0.0f};
         level_features(pl, j, smp.feat);
         if ((rc = net_predict(pl->net, smp, n, x))) return rc;
-        if ((rc = restart_from_x(pl, j, x, 0.0))) return rc;
-        const double rnet = pl->h_sc->aux0, rprev = pl->h_sc->r0sq;
-        if (std::isfinite(rnet) && rnet < rprev) {
-            guess = TSFCDE_WS_NET;
-        } else {
-            HIPCHK(hipMemcpyAsync(x, Uj, sizeof(double) * n, hipMemcpyDeviceToDevice, pl->stream));
-            if ((rc = restart_launch(pl, j, x, 0.0))) return rc;
-        }
+        if ((rc = restart_launch(pl, j, x, 0.0))) return rc;
+        hipLaunchKernelGGL(k_keep_better, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0,
+                           pl->stream, x, Uj, n, pl->sc);
+        HIPCHK(hipGetLastError());
+        if ((rc = restart_launch(pl, j, x, 0.0, 2))) return rc;  // only when u^j was put back
+        guess = TSFCDE_WS_NET;  // replaced below by what the device decided
         warm = 2;  // the CGS state is set by a restart pass, as for extrapolation
     }
     HIPCHK(precond_level(pl, j));
@@ -1048,7 +1054,7 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
         st->relres_true = relres_true;
         st->backward_err = so.backward_err;
         st->precision_used = fp32 ? (fell_back ? TSFCDE_FP32_REFINED_FELL_BACK : TSFCDE_FP32_REFINED) : TSFCDE_FP64;
-        st->guess = guess;
+        st->guess = use_net ? (hs.netkept ? TSFCDE_WS_NET : TSFCDE_WS_PREV) : guess;
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return so.code;

@@ -56,28 +56,38 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 // s_b = RMS of e2 over the grid (1 when it vanishes), one workgroup per sample.
+// The samples come from a device array `smp`, or, when it is null, from the
+// single sample `one` passed by value (inference needs no upload).
+// s_b = RMS of e2 over the grid (1 when it vanishes): workgroup (x, b) sums
+// a slice of sample b into part[b][x]; k_net_inputs adds the slices up.
 template <int NT>
-__global__ void __launch_bounds__(NT) k_net_scale(const Sample *__restrict__ smp, int64_t n, double *s_out) {
-    const Sample S = smp[blockIdx.x];
+__global__ void __launch_bounds__(NT) k_net_scale(const Sample *__restrict__ smp, Sample one, int64_t n,
+                                                  double *part) {
+    const int b = blockIdx.y;
+    const Sample S = smp ? smp[b] : one;
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += NT) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
         const double e2 = S.u0[i] - 2.0 * S.u1[i] + S.u2[i];
         acc = fma(e2, e2, acc);
     }
     const double tot = block_sum<NT>(acc);
-    if (threadIdx.x == 0) {
-        const double s = sqrt(tot / (double)n);
-        s_out[blockIdx.x] = s > 0.0 ? s : 1.0;
-    }
+    if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = tot;
+}
+
+__device__ __forceinline__ double net_scale(const double *part, int nparts, int b, int64_t n) {
+    double t = 0.0;
+    for (int k = 0; k < nparts; ++k) t += part[(size_t)b * nparts + k];
+    const double s = sqrt(t / (double)n);
+    return s > 0.0 ? s : 1.0;
 }
 
 // Network inputs X[b][c][i] and, when the sample has u^{j+1}, the target
-// Y*[b][i] = (u^{j+1} - base) / s.
-__global__ void k_net_inputs(const Sample *__restrict__ smp, int64_t n, const double *__restrict__ s,
-                             float *__restrict__ X, float *__restrict__ Ystar) {
+// Y*[b][i] = (u^{j+1} - base) / s (every thread forms s from the slices).
+__global__ void k_net_inputs(const Sample *__restrict__ smp, Sample one, int64_t n, const double *__restrict__ part,
+                             int nparts, float *__restrict__ X, float *__restrict__ Ystar) {
     const int b = blockIdx.y;
-    const Sample S = smp[b];
-    const double inv = 1.0 / s[b];
+    const Sample S = smp ? smp[b] : one;
+    const double inv = 1.0 / net_scale(part, nparts, b, n);
     float *Xb = X + (size_t)b * CIN * n;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double a0 = S.u0[i], a1 = S.u1[i], a2 = S.u2[i];
