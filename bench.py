@@ -82,7 +82,20 @@ def forms(args, P, W, prob, F, u0, levels, plain_value, dev):
     import numpy as np
     import torch
     res = {}
-    # warm starts on the headline workload
+    if args.form in ("all", "warm"):
+        warm_forms(args, P, prob, F, u0, levels, plain_value, res)
+    if args.form in ("all", "fp32"):
+        fp32_forms(args, P, W, prob, F, u0, levels, plain_value, dev, res)
+    if args.form in ("all", "batched"):
+        res["batched"] = batched_form(args, P, W, dev)
+    if args.form in ("all", "learned"):
+        res["learned"] = learned_form(args, P, W, dev)
+    return res
+
+
+def warm_forms(args, P, prob, F, u0, levels, plain_value, res):
+    import numpy as np
+    import torch
     for ws, name in ((P.TSFCDE_WS_PREV, "previous_level"), (P.TSFCDE_WS_EXTRAP, "extrapolated")):
         with P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, warm_start=ws) as sw:
             dt, st = timed_march(sw, F, u0, levels, torch)
@@ -90,8 +103,13 @@ def forms(args, P, W, prob, F, u0, levels, plain_value, dev):
                      "cgs_iterations_mean": float(np.mean([x["iters"] for x in st])),
                      "speedup_vs_plain": (levels / dt) / plain_value}
         log(f"form {name}: {levels / dt:.1f} level-solves/s")
-    # FP32-refined: on the headline workload the rounding-error model keeps
-    # FP64; inside the envelope it refines in FP32
+
+
+def fp32_forms(args, P, W, prob, F, u0, levels, plain_value, dev, res):
+    """FP32-refined: on the headline workload the rounding-error model keeps
+    FP64; inside the envelope it refines in FP32."""
+    import numpy as np
+    import torch
     with P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, precision=P.TSFCDE_FP32_REFINED) as sw:
         dt, st = timed_march(sw, F, u0, levels, torch)
     share = float(np.mean([x["precision_used"] == P.TSFCDE_FP32_REFINED for x in st]))
@@ -118,9 +136,6 @@ def forms(args, P, W, prob, F, u0, levels, plain_value, dev):
     del Fs
     log(f"form fp32_refined: headline {res['fp32_refined']['value']:.1f} (fp32 share {share:.2f}); "
         f"n={small.n}: {res['fp32_refined_in_envelope']['speedup_vs_plain']:.2f}x plain")
-    res["batched"] = batched_form(args, P, W, dev)
-    res["learned"] = learned_form(args, P, W, dev)
-    return res
 
 
 def batched_form(args, P, W, dev):
@@ -258,6 +273,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the warm-started forms")
     ap.add_argument("--profile-class", default="mid_matvec", choices=sorted(KCLASS))
     ap.add_argument("--fp32-n", type=int, default=2048, help="grid of the FP32-refined form inside its envelope")
+    ap.add_argument("--form", default="all", choices=["all", "warm", "fp32", "batched", "learned"],
+                    help="which of the other forms to run (for profiling one of them)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-M", type=int, default=128)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

@@ -8,6 +8,7 @@
 //   3. preconditioned CGS on A u^{j+1} = g with the Strang circulant P (3.7),
 //      12 kernels per iteration, device-resident scalars, convergence flag
 //      polled between chunks of iterations.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -479,13 +480,30 @@ void harvest(tsfcde_plan_s *pl) {
 
 #define TSF_SIZES(X) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
+// Launch on the plan's stream; while profiling class `cls` is on, the start
+// and end events ride on the dispatch itself (hipExtLaunchKernelGGL), so the
+// measured interval is the kernel's own run, without the gap an event
+// recorded between kernels would add.
+template <typename K, typename... Args>
+void launch_timed(tsfcde_plan_s *pl, int cls, K kernel, dim3 grid, dim3 block, Args... args) {
+    if (pl->prof[cls].on) {
+        hipEvent_t e0 = get_event(pl), e1 = e0 ? get_event(pl) : nullptr;
+        if (e0 && e1) {
+            hipExtLaunchKernelGGL(kernel, grid, block, 0, pl->stream, e0, e1, 0, args...);
+            pl->prof[cls].pending.emplace_back(e0, e1);
+            return;
+        }
+        if (e0) pl->event_pool.push_back(e0);
+    }
+    hipLaunchKernelGGL(kernel, grid, block, 0, pl->stream, args...);
+}
+
 template <int R, int DIR, class In, class Out>
 hipError_t launch_col_t(tsfcde_plan_s *pl, int64_t C, const In &in, const Out &out, int pred) {
     using G = ColGeo<R, TSF_E_COL>;
     const int64_t grid = (C + G::B - 1) / G::B;
-    ProfScope ps(pl, 1);
-    hipLaunchKernelGGL((k_col<R, TSF_E_COL, DIR, In, Out>), dim3((unsigned)grid), dim3(G::NT), 0, pl->stream, C, in,
-                       out, pl->tw_all, pl->sc, pred);
+    launch_timed(pl, 1, k_col<R, TSF_E_COL, DIR, In, Out>, dim3((unsigned)grid), dim3(G::NT), C, in, out,
+                 (const double2 *)pl->tw_all, pl->sc, pred);
     if constexpr (Out::NACC > 0) {
         hipLaunchKernelGGL((k_final<G::NT, Out>), dim3(1), dim3(G::NT), 0, pl->stream, out, (int)grid, pl->sc, pred);
     }
@@ -511,9 +529,8 @@ hipError_t launch_fuse_t(tsfcde_plan_s *pl, const Op &op, const CS *bufP, CS *bu
         using G = FuseGeo<RP, TSF_E_FUSE>;
         const int64_t C = pl->A.C;
         const int64_t grid = (C + G::B - 1) / G::B;
-        ProfScope ps(pl, 5);
-        hipLaunchKernelGGL((k_fuse<RP, TSF_E_FUSE, Op, CS>), dim3((unsigned)grid), dim3(G::NT), 0, pl->stream, C,
-                           bufP, pl->P.tw, bufA, pl->A.tw, op, pl->tw_all, pl->sc, pred);
+        launch_timed(pl, 5, k_fuse<RP, TSF_E_FUSE, Op, CS>, dim3((unsigned)grid), dim3(G::NT), C, bufP, pl->P.tw,
+                     bufA, pl->A.tw, op, (const double2 *)pl->tw_all, pl->sc, pred);
         return hipGetLastError();
     }
 }
@@ -534,9 +551,8 @@ template <int C_, int MODE, class CS>
 hipError_t launch_mid_t(tsfcde_plan_s *pl, const RT &rt, CS *Y, const CS *spec, double2 *spec_out,
                         const SymParams &sp, int pred) {
     using G = MidGeo<C_, TSF_E_MID>;
-    ProfScope ps(pl, MODE == 1 ? 4 : 2);
-    hipLaunchKernelGGL((k_mid<C_, TSF_E_MID, MODE, CS>), dim3((unsigned)(rt.R / 2)), dim3(G::NT), 0, pl->stream,
-                       rt.R, Y, spec, spec_out, rt.tw, sp, pl->tw_all, pl->sc, pred);
+    launch_timed(pl, MODE == 1 ? 4 : 2, k_mid<C_, TSF_E_MID, MODE, CS>, dim3((unsigned)(rt.R / 2)), dim3(G::NT), rt.R,
+                 Y, spec, spec_out, rt.tw, sp, (const double2 *)pl->tw_all, pl->sc, pred);
     return hipGetLastError();
 }
 
@@ -757,10 +773,9 @@ hipError_t cgs_iter(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x) {
 int level_rhs(tsfcde_plan_s *pl, int64_t j, const double *d_f, double *x, int warm) {
     const int64_t n = pl->n, ld = pl->ldn;
     if (j >= 1) {
-        ProfScope ps(pl, 0);
         const int64_t threads = (n + 1) / 2;
-        hipLaunchKernelGGL(k_history, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, pl->stream, pl->U, n, ld,
-                           (int)j, pl->cb, pl->clast[j], pl->kappa, pl->H);
+        launch_timed(pl, 0, k_history, dim3((unsigned)((threads + 255) / 256)), dim3(256), (const double *)pl->U, n, ld,
+                     (int)j, (const double *)pl->cb, pl->clast[j], pl->kappa, pl->H);
         HIPCHK(hipGetLastError());
     }
     if (d_f && (reinterpret_cast<uintptr_t>(d_f) & 15)) {  // pairs are read as 16-byte loads
