@@ -415,15 +415,18 @@ using OutCgsR = OutCgsRT<double>;
 
 // Right-hand side of (3.3) from y = A u^j:
 //   g = (eta/sigma) u^j - ((1-sigma)/sigma) y - H + f     (= B u^j - H + f)
+// with H = P + kappa c_1 u^j (P the history kernels' partial sum), i.e.
+//   g = (eta/sigma - kappa c_1) u^j - ((1-sigma)/sigma) y - P + f,
+// c_u holding the first coefficient and H pointing at P;
 //   x0 = u^j (warm) or 0;  r = g - A x0 ;  rt = r.
-// The last workgroup initialises the CGS scalars for the level.
+// The finishing kernel initialises the CGS scalars for the level.
 // warm: 0 -> x0 = 0; 1 -> x0 = u^j; 2 -> x0 = 3u^j - 3u^{j-1} + u^{j-2}
 // (quadratic extrapolation in t; r is then recomputed from x0 by a restart).
 struct OutRhs {
     const double *uj, *H, *f;
     double *g, *r, *rt, *x;
     int64_t nr, C;
-    double c_u, c_y;  // eta/sigma, (1-sigma)/sigma
+    double c_u, c_y;  // eta/sigma - kappa c_1 (or eta/sigma at level 0), (1-sigma)/sigma
     int warm, has_hist;
     const double *ujm1, *ujm2;  // u^{j-1}, u^{j-2} for warm == 2
     // u^j, H and f are fetched ahead; the extrapolation's two older levels
@@ -1274,39 +1277,59 @@ __global__ void k_pc_embed(const double2 *Wt, int64_t n, int64_t L, double *e) {
 // ---------------------------------------------------------------------------
 // History sum of (3.3):  H = kappa * sum_{s=0}^{j-1} c_{j-s}^(j) (u^{s+1} - u^s)
 // with c_j^(j) = clast (s = 0) and c_m^(j) = cbase[m] (1 <= m <= j-1).
-// Each lane streams two adjacent unknowns through all stored levels (rows of
+// The kernels form every term but the newest level's,
+//   P = kappa * [ sum_{s=0}^{j-2} c_{j-s} (u^{s+1} - u^s) - c_1 u^{j-1} ],
+// so that H = P + kappa c_1 u^j: P needs only u^0..u^{j-1} and can be summed
+// while level j-1 is being solved, and the right-hand side folds
+// kappa c_1 u^j into its coefficient of u^j.
+// Each lane streams two adjacent unknowns through the stored levels (rows of
 // U are ldu >= n doubles apart, ldu even; an odd n reads the zero pad).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_history(const double *__restrict__ U, int64_t n, int64_t ldu, int j,
-                                                 const double *__restrict__ cbase, double clast, double kappa,
-                                                 double *__restrict__ H) {
-    const int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-    if (i >= n) return;
+__device__ __forceinline__ double hist_c(int s, int j, const double *cbase, double clast) {
+    return s == 0 ? clast : cbase[j - s];
+}
+
+__device__ __forceinline__ void history_pair(const double *__restrict__ U, int64_t ldu, int j,
+                                             const double *__restrict__ cbase, double clast, double kappa,
+                                             double *__restrict__ H, int64_t i) {
     double2 prev = *reinterpret_cast<const double2 *>(U + i);
     double2 acc = make_double2(0.0, 0.0);
     int s = 0;
+    const int full = j - 1;  // complete differences s = 0..j-2
     // eight levels in flight per step
     constexpr int U8 = 8;
-    for (; s + U8 <= j; s += U8) {
+    for (; s + U8 <= full; s += U8) {
         double2 x[U8];
 #pragma unroll
         for (int q = 0; q < U8; ++q) x[q] = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1 + q) * ldu + i);
 #pragma unroll
         for (int q = 0; q < U8; ++q) {
-            const double cq = (s + q == 0) ? clast : cbase[j - s - q];
+            const double cq = hist_c(s + q, j, cbase, clast);
             acc.x = fma(cq, x[q].x - prev.x, acc.x);
             acc.y = fma(cq, x[q].y - prev.y, acc.y);
             prev = x[q];
         }
     }
-    for (; s < j; ++s) {
+    for (; s < full; ++s) {
         double2 x1 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1) * ldu + i);
-        const double c1 = s == 0 ? clast : cbase[j - s];
+        const double c1 = hist_c(s, j, cbase, clast);
         acc.x = fma(c1, x1.x - prev.x, acc.x);
         acc.y = fma(c1, x1.y - prev.y, acc.y);
         prev = x1;
     }
+    const double cl = hist_c(j - 1, j, cbase, clast);  // prev = u^{j-1}
+    acc.x = fma(-cl, prev.x, acc.x);
+    acc.y = fma(-cl, prev.y, acc.y);
     *reinterpret_cast<double2 *>(H + i) = make_double2(kappa * acc.x, kappa * acc.y);
+}
+
+__global__ void __launch_bounds__(256) k_history(const double *__restrict__ U, int64_t n, int64_t ldu, int j,
+                                                 const double *__restrict__ cbase, double clast, double kappa,
+                                                 double *__restrict__ H) {
+    // grid-stride over pairs: a small grid runs as a background job beside the solve
+    for (int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); i < n;
+         i += 2 * (int64_t)gridDim.x * blockDim.x)
+        history_pair(U, ldu, j, cbase, clast, kappa, H, i);
 }
 
 // Batched element-wise kernels: descriptor per instance (blockIdx.y), a
@@ -1327,13 +1350,16 @@ __global__ void __launch_bounds__(256) k_history_b(const HistDesc *__restrict__ 
          i += 2 * (int64_t)gridDim.x * blockDim.x) {
         double2 prev = *reinterpret_cast<const double2 *>(D.U + i);
         double2 acc = make_double2(0.0, 0.0);
-        for (int s = 0; s < D.j; ++s) {
+        for (int s = 0; s < D.j - 1; ++s) {  // the same partial sum as k_history
             const double2 x1 = *reinterpret_cast<const double2 *>(D.U + (int64_t)(s + 1) * D.ldu + i);
-            const double c1 = s == 0 ? D.clast : D.cbase[D.j - s];
+            const double c1 = hist_c(s, D.j, D.cbase, D.clast);
             acc.x = fma(c1, x1.x - prev.x, acc.x);
             acc.y = fma(c1, x1.y - prev.y, acc.y);
             prev = x1;
         }
+        const double cl = hist_c(D.j - 1, D.j, D.cbase, D.clast);
+        acc.x = fma(-cl, prev.x, acc.x);
+        acc.y = fma(-cl, prev.y, acc.y);
         *reinterpret_cast<double2 *>(D.H + i) = make_double2(D.kappa * acc.x, D.kappa * acc.y);
     }
 }

@@ -97,7 +97,7 @@ struct Layout {
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr int NVEC = 11;  // H g r rt u p q phat vhat uhat fbuf
+constexpr int NVEC = 12;  // H g r rt u p q phat vhat uhat fbuf H2
 constexpr int NV32 = 9;   // FP32 inner solve: r rt u p q phat vhat uhat d
 
 // internal row stride: n rounded up to even, so every row starts 16-byte aligned
@@ -188,7 +188,12 @@ struct tsfcde_plan_s {
     RT A, P, B;
     Layout lay;
     char *ws;
-    double *U, *H, *g, *r, *rt, *u, *p, *q, *phat, *vhat, *uhat, *fbuf, *tmp, *w, *g0, *cb, *part;
+    double *U, *H, *g, *r, *rt, *u, *p, *q, *phat, *vhat, *uhat, *fbuf, *tmp, *w, *g0, *cb, *part, *H2;
+    // history partial sums: level j's in hbuf(j); the next level's is summed on
+    // the side stream `hs` while the current level is solved
+    hipStream_t hs = nullptr;
+    hipEvent_t ev_main = nullptr, ev_hist[2] = {nullptr, nullptr};
+    int64_t hist_pending = -1;  // level whose partial sum was queued on hs
     double2 *buf, *bufP, *specA, *specP, *tw_all;
     double2 *bufB, *Bhat, *chirp, *Ls, *wv, *Wt, *specPj;
     DevScalars *sc;
@@ -463,7 +468,12 @@ struct ProfScope {
 // Called after the stream is known to be idle.
 void harvest(tsfcde_plan_s *pl) {
     for (auto &pr : pl->prof) {
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> keep;
         for (auto &ev : pr.pending) {
+            if (hipEventQuery(ev.second) == hipErrorNotReady) {  // still running on another stream
+                keep.push_back(ev);
+                continue;
+            }
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) {
                 pr.ms += ms;
@@ -472,7 +482,7 @@ void harvest(tsfcde_plan_s *pl) {
             pl->event_pool.push_back(ev.first);
             pl->event_pool.push_back(ev.second);
         }
-        pr.pending.clear();
+        pr.pending.swap(keep);
     }
 }
 
@@ -485,17 +495,22 @@ void harvest(tsfcde_plan_s *pl) {
 // measured interval is the kernel's own run, without the gap an event
 // recorded between kernels would add.
 template <typename K, typename... Args>
-void launch_timed(tsfcde_plan_s *pl, int cls, K kernel, dim3 grid, dim3 block, Args... args) {
+void launch_timed_on(tsfcde_plan_s *pl, hipStream_t st, int cls, K kernel, dim3 grid, dim3 block, Args... args) {
     if (pl->prof[cls].on) {
         hipEvent_t e0 = get_event(pl), e1 = e0 ? get_event(pl) : nullptr;
         if (e0 && e1) {
-            hipExtLaunchKernelGGL(kernel, grid, block, 0, pl->stream, e0, e1, 0, args...);
+            hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
             pl->prof[cls].pending.emplace_back(e0, e1);
             return;
         }
         if (e0) pl->event_pool.push_back(e0);
     }
-    hipLaunchKernelGGL(kernel, grid, block, 0, pl->stream, args...);
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
+
+template <typename K, typename... Args>
+void launch_timed(tsfcde_plan_s *pl, int cls, K kernel, dim3 grid, dim3 block, Args... args) {
+    launch_timed_on(pl, pl->stream, cls, kernel, grid, block, args...);
 }
 
 template <int R, int DIR, class In, class Out>
@@ -770,14 +785,63 @@ hipError_t cgs_iter(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x) {
     return pl->p2 ? cgs_iteration(pl, j, b, x) : cgs_iteration_general(pl, j, b, x);
 }
 
+double *hbuf(tsfcde_plan_s *pl, int64_t j) { return (j & 1) ? pl->H2 : pl->H; }
+
+// kappa c_1^(j): the weight of u^j in the history sum of level j (j >= 1)
+double hist_c1(const tsfcde_plan_s *pl, int64_t j) { return pl->kappa * (j == 1 ? pl->clast[1] : pl->cbase[1]); }
+
+#ifndef TSF_HIST_SIDE_WG
+#define TSF_HIST_SIDE_WG 256
+#endif
+// On the main stream the partial sum takes the whole chip; on the side stream
+// it runs beside the solve on a small grid (TSF_HIST_SIDE_WG workgroups).
+hipError_t launch_history(tsfcde_plan_s *pl, hipStream_t st, int64_t j) {
+    const int64_t n = pl->n, threads = (n + 1) / 2;
+    int64_t wg = (threads + 255) / 256;
+    if (st != pl->stream) wg = std::min<int64_t>(wg, TSF_HIST_SIDE_WG);
+    launch_timed_on(pl, st, 0, k_history, dim3((unsigned)wg), dim3(256), (const double *)pl->U, n, pl->ldn, (int)j,
+                    (const double *)pl->cb, pl->clast[j], pl->kappa, hbuf(pl, j));
+    return hipGetLastError();
+}
+
+// The side stream is idle and holds no pending partial sum (before anything
+// other than a level step touches U or the history buffers).
+int history_quiesce(tsfcde_plan_s *pl) {
+    if (pl->hs) HIPCHK(hipStreamSynchronize(pl->hs));
+    pl->hist_pending = -1;
+    return TSFCDE_OK;
+}
+
+// The partial history sum of level j in hbuf(j): waited for if the side
+// stream already summed it during level j-1, else summed now.  Then the next
+// level's (it needs u^0..u^j, all final now) is queued on the side stream,
+// after everything the main stream has queued, including the right-hand side
+// that last read the buffer it will overwrite.
+int history_for(tsfcde_plan_s *pl, int64_t j) {
+    if (pl->hist_pending >= 0)  // whatever the side stream queued is finished before the buffers are used
+        HIPCHK(hipStreamWaitEvent(pl->stream, pl->ev_hist[pl->hist_pending & 1], 0));
+    if (j >= 1 && pl->hist_pending != j) HIPCHK(launch_history(pl, pl->stream, j));
+    pl->hist_pending = -1;
+    if (j + 1 < pl->M) {
+        if (!pl->hs) {
+            HIPCHK(hipStreamCreateWithFlags(&pl->hs, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&pl->ev_main, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&pl->ev_hist[0], hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&pl->ev_hist[1], hipEventDisableTiming));
+        }
+        HIPCHK(hipEventRecord(pl->ev_main, pl->stream));
+        HIPCHK(hipStreamWaitEvent(pl->hs, pl->ev_main, 0));
+        HIPCHK(launch_history(pl, pl->hs, j + 1));
+        HIPCHK(hipEventRecord(pl->ev_hist[(j + 1) & 1], pl->hs));
+        pl->hist_pending = j + 1;
+    }
+    return TSFCDE_OK;
+}
+
 int level_rhs(tsfcde_plan_s *pl, int64_t j, const double *d_f, double *x, int warm) {
     const int64_t n = pl->n, ld = pl->ldn;
-    if (j >= 1) {
-        const int64_t threads = (n + 1) / 2;
-        launch_timed(pl, 0, k_history, dim3((unsigned)((threads + 255) / 256)), dim3(256), (const double *)pl->U, n, ld,
-                     (int)j, (const double *)pl->cb, pl->clast[j], pl->kappa, pl->H);
-        HIPCHK(hipGetLastError());
-    }
+    int rc = history_for(pl, j);
+    if (rc) return rc;
     if (d_f && (reinterpret_cast<uintptr_t>(d_f) & 15)) {  // pairs are read as 16-byte loads
         hipLaunchKernelGGL(k_copy, dim3(256), dim3(256), 0, pl->stream, d_f, pl->fbuf, n);
         HIPCHK(hipGetLastError());
@@ -785,8 +849,9 @@ int level_rhs(tsfcde_plan_s *pl, int64_t j, const double *d_f, double *x, int wa
     }
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
     InReal in{pl->U + (size_t)j * ld, n, pl->A.C};
-    OutRhs out{pl->U + (size_t)j * ld, pl->H, d_f, pl->g, pl->r, pl->rt, x, n, pl->A.C,
-               pl->eta[j] / pl->sigma, (1.0 - pl->sigma) / pl->sigma, warm, j >= 1 ? 1 : 0,
+    OutRhs out{pl->U + (size_t)j * ld, hbuf(pl, j), d_f, pl->g, pl->r, pl->rt, x, n, pl->A.C,
+               pl->eta[j] / pl->sigma - (j >= 1 ? hist_c1(pl, j) : 0.0), (1.0 - pl->sigma) / pl->sigma, warm,
+               j >= 1 ? 1 : 0,
                j >= 2 ? pl->U + (size_t)(j - 1) * ld : nullptr, j >= 2 ? pl->U + (size_t)(j - 2) * ld : nullptr};
     out = with_red(out, pl, 2);
     HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
@@ -1203,7 +1268,7 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
     pl->U = reinterpret_cast<double *>(ws + L.off_U);
     double *vec = reinterpret_cast<double *>(ws + L.off_vec);
     double **vp[NVEC] = {&pl->H, &pl->g, &pl->r, &pl->rt, &pl->u, &pl->p, &pl->q, &pl->phat, &pl->vhat, &pl->uhat,
-                         &pl->fbuf};
+                         &pl->fbuf, &pl->H2};
     for (int k = 0; k < NVEC; ++k) *vp[k] = vec + (size_t)k * pl->ldn;
     pl->tmp = reinterpret_cast<double *>(ws + L.off_tmp);
     pl->w = reinterpret_cast<double *>(ws + L.off_w);
@@ -1334,6 +1399,7 @@ int tsfcde_plan(const tsfcde_problem *prob, void *d_workspace, size_t bytes, voi
 
 int tsfcde_set_state(tsfcde_plan_t pl, int64_t level, const double *d_U) {
     if (!pl || !d_U || level < 0 || level > pl->M) return TSFCDE_EINVAL;
+    if (int rc = history_quiesce(pl)) return rc;  // no partial sum reads U while it changes
     HIPCHK(hipMemcpy2DAsync(pl->U, sizeof(double) * pl->ldn, d_U, sizeof(double) * pl->n, sizeof(double) * pl->n,
                             (size_t)(level + 1), hipMemcpyDeviceToDevice, pl->stream));
     pl->level = level;
@@ -1583,7 +1649,11 @@ int tsfcde_net_destroy(tsfcde_net_t nt) {
 int tsfcde_destroy(tsfcde_plan_t pl) {
     if (!pl) return TSFCDE_EINVAL;
     (void)hipStreamSynchronize(pl->stream);
+    (void)history_quiesce(pl);
     harvest(pl);
+    if (pl->hs) (void)hipStreamDestroy(pl->hs);
+    for (hipEvent_t e : {pl->ev_main, pl->ev_hist[0], pl->ev_hist[1]})
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : pl->event_pool) (void)hipEventDestroy(e);
     if (pl->h_sc) (void)hipHostFree(pl->h_sc);
     delete pl;
@@ -1795,8 +1865,9 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
         InSpec isA = in_spec(pl, pl->A);
         // right-hand side through A u^j
         rhsA.push_back(cdesc(pl, C, InReal{pl->U + (size_t)j * ld, n, C}, osA));
-        OutRhs orhs{pl->U + (size_t)j * ld, pl->H, f, pl->g, pl->r, pl->rt, x, n, C, pl->eta[j] / pl->sigma,
-                    (1.0 - pl->sigma) / pl->sigma, warm, j >= 1 ? 1 : 0,
+        OutRhs orhs{pl->U + (size_t)j * ld, pl->H, f, pl->g, pl->r, pl->rt, x, n, C,
+                    pl->eta[j] / pl->sigma - (j >= 1 ? hist_c1(pl, j) : 0.0), (1.0 - pl->sigma) / pl->sigma, warm,
+                    j >= 1 ? 1 : 0,
                     j >= 2 ? pl->U + (size_t)(j - 1) * ld : nullptr, j >= 2 ? pl->U + (size_t)(j - 2) * ld : nullptr};
         rhsC.push_back(cdesc(pl, C, isA, with_red(orhs, pl, 2)));
         midA.push_back(MidDesc{pl->A.R, pl->buf, pl->specA, nullptr, pl->A.tw, sA, pl->sc});
