@@ -21,7 +21,12 @@ exact for such t-dependence.  The network predicts the remainder.
 * Network:
   - four 1-D convolutions 7 -> 32 -> 32 -> 32 -> 1, width 5, zero padding;
   - tanh after the first three;
-  - weights rounded to bfloat16, biases kept in FP32.
+  - weights rounded to bfloat16; the inputs of the two hidden 32 -> 32
+    layers (tanh outputs) rounded to bfloat16 too (first to FP32, as the
+    device holds them); the input and output layers take their inputs
+    unrounded; biases, products and sums in higher precision.  The backward
+    pass differentiates that computation with the rounding taken as the
+    identity, so the weight gradient uses the rounded inputs.
 * Prediction: x0 = 3(u^j - u^{j-1}) + u^{j-2} + y e2.  The correction is
   the network output times the local second difference e2.  It is smooth,
   and it vanishes where the Dirichlet condition of (1.1) fixes u, so it adds
@@ -57,6 +62,7 @@ import numpy as np
 CIN, WIDTH, KS = 7, 32, 5
 LAYERS = [(CIN, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH, 1)]  # (c_in, c_out)
 HALF = KS // 2
+ROUNDED = (1, 2)  # layers whose inputs are rounded to bfloat16 (the hidden ones)
 
 
 def param_count() -> int:
@@ -135,13 +141,15 @@ def conv(a: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
     return out
 
 
-def forward(theta: np.ndarray, X: np.ndarray):
-    """Network output y (n,) and the activations needed by backward."""
+def forward(theta: np.ndarray, X: np.ndarray, rnd=bf16_round):
+    """Network output y (n,) and the activations needed by backward.  rnd is
+    applied to every convolution's input (bfloat16 rounding; the identity
+    gives the exact-arithmetic network the chain-rule pin uses)."""
     layers = unpack(theta)
     acts = [X]
     a = X
     for li, (W, b) in enumerate(layers):
-        z = conv(a, W, b)
+        z = conv(rnd(a) if li in ROUNDED else a, W, b)
         a = np.tanh(z) if li < len(layers) - 1 else z
         acts.append(a)
     return a[0], acts
@@ -160,8 +168,10 @@ def loss_dy(y: np.ndarray, x1: np.ndarray, t: np.ndarray) -> np.ndarray:
     return 2.0 * (y * x1 - t) * x1 / (np.sum(t * t) + t.size * EPS_D)
 
 
-def backward(theta: np.ndarray, acts, dy: np.ndarray) -> np.ndarray:
-    """Gradient of sum_p dy[p] * y[p] with respect to the parameters."""
+def backward(theta: np.ndarray, acts, dy: np.ndarray, rnd=bf16_round) -> np.ndarray:
+    """Gradient of sum_p dy[p] * y[p] with respect to the parameters (the
+    rounding rnd taken as the identity, its output used in the weight
+    gradient)."""
     layers = unpack(theta)
     grads = [None] * len(layers)
     dz = dy[None, :].astype(np.float64)  # d/dz of the last (linear) layer
@@ -170,7 +180,7 @@ def backward(theta: np.ndarray, acts, dy: np.ndarray) -> np.ndarray:
         a_in = acts[li]
         ci, n = a_in.shape
         ap = np.zeros((ci, n + 2 * HALF))
-        ap[:, HALF:HALF + n] = a_in
+        ap[:, HALF:HALF + n] = rnd(a_in) if li in ROUNDED else a_in
         dW = np.empty_like(W)
         for k in range(KS):
             dW[:, :, k] = dz @ ap[:, k:k + n].T

@@ -238,10 +238,15 @@ constexpr int NET_WG_MAX = 1024;  // workgroups of a weight-gradient pass
 constexpr int NET_NE_MAX = net::WIDTH * net::WIDTH * net::KS + net::WIDTH;
 constexpr int NET_LOSS_WG = 256;
 constexpr int NET_SCALE_PARTS = 64;  // workgroups per sample of the scale reduction
+// bfloat16 weights of the three 32-output layers in the matrix-core order
+// (k = tap * CIP + ci, input channels padded to CIP = 8 or 32)
+constexpr int NET_CIP0 = 8;
+constexpr int NET_WM_OFF[3] = {0, 32 * net::KS * NET_CIP0, 32 * net::KS * NET_CIP0 + 32 * net::KS * net::WIDTH};
+constexpr int NET_WM_TOTAL = NET_WM_OFF[2] + 32 * net::KS * net::WIDTH;
 static_assert(sizeof(tsfcde_net_sample) == sizeof(net::Sample), "sample layout");
 
 struct NetLayout {
-    size_t theta, m, v, grad, wbf, wt, wb, X, act, y, ystar, dy, dz0, dz1, part, s, den, lpart, smp, total;
+    size_t theta, m, v, grad, wbf, wt, wb, wm, X, act, y, ystar, dy, dz0, dz1, part, s, den, lpart, smp, total;
 };
 
 NetLayout net_layout(int64_t mp, int32_t mb) {
@@ -259,6 +264,7 @@ NetLayout net_layout(int64_t mp, int32_t mb) {
     l.wbf = take(2 * (size_t)NET_P);
     l.wt = take(4 * (size_t)NET_P);
     l.wb = take(4 * (size_t)NET_P);
+    l.wm = take(2 * (size_t)NET_WM_TOTAL);
     l.X = take(4 * (size_t)net::CIN * mp);
     l.act = take(4 * (size_t)3 * net::WIDTH * mp);
     l.y = take(4 * (size_t)mp);
@@ -282,7 +288,7 @@ struct tsfcde_net_s {
     int64_t max_points = 0;
     int32_t max_batch = 0;
     float *theta, *m, *v, *grad, *wt, *wb, *X, *act, *y, *ystar, *dy, *dz0, *dz1, *part;
-    uint16_t *wbf;
+    uint16_t *wbf, *wm;
     double *s, *den, *lpart;
     net::Sample *smp;
     bool widened = false;
@@ -304,6 +310,9 @@ int net_widen(tsfcde_net_s *nt) {
         const int64_t off = net_layer_off(l);
         hipLaunchKernelGGL(net::k_net_widen, dim3(32), dim3(256), 0, nt->stream, nt->wbf + off, L.ci, L.co,
                            nt->wt + off, l > 0 ? nt->wb + off : (float *)nullptr);
+        if (l == 1 || l == 2)
+            hipLaunchKernelGGL(net::k_net_widen_mfma, dim3(32), dim3(256), 0, nt->stream, nt->wbf + off, L.ci,
+                               net::WIDTH, nt->wm + NET_WM_OFF[l]);
     }
     NCHK(hipGetLastError());
     nt->widened = true;
@@ -317,7 +326,7 @@ int net_forward(tsfcde_net_s *nt, int count, int64_t n, bool targets, const net:
     if (rc) return rc;
     const net::Sample *smp = one ? nullptr : nt->smp;
     const net::Sample none = one ? *one : net::Sample{};
-    const int sx = (int)std::max<int64_t>(1, std::min<int64_t>(NET_SCALE_PARTS, (n + 4095) / 4096));
+    const int sx = (int)std::max<int64_t>(1, std::min<int64_t>(NET_SCALE_PARTS, (n + 255) / 256));
     hipLaunchKernelGGL(net::k_net_scale<256>, dim3(sx, count), dim3(256), 0, nt->stream, smp, none, n, nt->s);
     const unsigned gx = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
     hipLaunchKernelGGL(net::k_net_inputs, dim3(gx, count), dim3(256), 0, nt->stream, smp, none, n, nt->s, sx, nt->X,
@@ -325,28 +334,29 @@ int net_forward(tsfcde_net_s *nt, int count, int64_t n, bool targets, const net:
     const size_t A = (size_t)net::WIDTH * count * n;
     float *a1 = nt->act, *a2 = nt->act + A, *a3 = nt->act + 2 * A;
     auto grid = [&](int tx) { return dim3((unsigned)((n + tx - 1) / tx), (unsigned)count); };
-    using G0 = net::ConvGeo<net::CIN, net::WIDTH>;
-    using G1 = net::ConvGeo<net::WIDTH, net::WIDTH>;
     using G3 = net::ConvGeo<net::WIDTH, 1>;
     const int64_t o0 = net_layer_off(0), o1 = net_layer_off(1), o2 = net_layer_off(2), o3 = net_layer_off(3);
+    // input layer in FP32, the two hidden layers on the matrix cores
+    using G0 = net::ConvGeo<net::CIN, net::WIDTH>;
     hipLaunchKernelGGL((net::k_conv<net::CIN, net::WIDTH, 0>), grid(G0::TX), dim3(G0::NT), 0, nt->stream, nt->X,
                        nt->wt + o0, nt->theta + o0 + net::WIDTH * net::CIN * net::KS, (const float *)nullptr, a1, n);
-    hipLaunchKernelGGL((net::k_conv<net::WIDTH, net::WIDTH, 0>), grid(G1::TX), dim3(G1::NT), 0, nt->stream, a1,
-                       nt->wt + o1, nt->theta + o1 + net::WIDTH * net::WIDTH * net::KS, (const float *)nullptr, a2, n);
-    hipLaunchKernelGGL((net::k_conv<net::WIDTH, net::WIDTH, 0>), grid(G1::TX), dim3(G1::NT), 0, nt->stream, a2,
-                       nt->wt + o2, nt->theta + o2 + net::WIDTH * net::WIDTH * net::KS, (const float *)nullptr, a3, n);
+    constexpr int MT = 32 * net::MFMA_WAVES;
+    hipLaunchKernelGGL((net::k_conv_mfma<net::WIDTH, net::WIDTH>), grid(MT), dim3(64 * net::MFMA_WAVES), 0, nt->stream, a1,
+                       nt->wm + NET_WM_OFF[1], nt->theta + o1 + net::WIDTH * net::WIDTH * net::KS, a2, n);
+    hipLaunchKernelGGL((net::k_conv_mfma<net::WIDTH, net::WIDTH>), grid(MT), dim3(64 * net::MFMA_WAVES), 0, nt->stream, a2,
+                       nt->wm + NET_WM_OFF[2], nt->theta + o2 + net::WIDTH * net::WIDTH * net::KS, a3, n);
     hipLaunchKernelGGL((net::k_conv<net::WIDTH, 1, 1>), grid(G3::TX), dim3(G3::NT), 0, nt->stream, a3, nt->wt + o3,
                        nt->theta + o3 + net::WIDTH * net::KS, (const float *)nullptr, nt->y, n);
     NCHK(hipGetLastError());
     return TSFCDE_OK;
 }
 
-template <int CI, int CO>
+template <int CI, int CO, bool ROUND>
 int net_wgrad(tsfcde_net_s *nt, const float *dz, const float *a, int count, int64_t n, int64_t off) {
     using G = net::WgradGeo<CI, CO>;
     const int64_t tiles = (n + G::TX - 1) / G::TX;
     const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, NET_WG_MAX / count));
-    hipLaunchKernelGGL((net::k_net_wgrad<CI, CO>), dim3(gx, count), dim3(G::NT), 0, nt->stream, dz, a, n, nt->part);
+    hipLaunchKernelGGL((net::k_net_wgrad<CI, CO, ROUND>), dim3(gx, count), dim3(G::NT), 0, nt->stream, dz, a, n, nt->part);
     hipLaunchKernelGGL(net::k_net_wgrad_reduce, dim3((G::NE + 255) / 256), dim3(256), 0, nt->stream, nt->part,
                        gx * count, G::NE, nt->grad + off);
     NCHK(hipGetLastError());
@@ -367,19 +377,19 @@ int net_backward(tsfcde_net_s *nt, int count, int64_t n) {
     const int64_t o0 = net_layer_off(0), o1 = net_layer_off(1), o2 = net_layer_off(2), o3 = net_layer_off(3);
     int rc;
     // layer 3 (32 -> 1, linear): dZ3 = dy
-    if ((rc = net_wgrad<net::WIDTH, 1>(nt, nt->dy, a3, count, n, o3))) return rc;
+    if ((rc = net_wgrad<net::WIDTH, 1, false>(nt, nt->dy, a3, count, n, o3))) return rc;
     hipLaunchKernelGGL((net::k_conv<1, net::WIDTH, 2>), grid(GB3::TX), dim3(GB3::NT), 0, nt->stream, nt->dy,
                        nt->wb + o3, (const float *)nullptr, a3, nt->dz0, n);
     // layer 2 (32 -> 32): dZ = dz0
-    if ((rc = net_wgrad<net::WIDTH, net::WIDTH>(nt, nt->dz0, a2, count, n, o2))) return rc;
+    if ((rc = net_wgrad<net::WIDTH, net::WIDTH, true>(nt, nt->dz0, a2, count, n, o2))) return rc;
     hipLaunchKernelGGL((net::k_conv<net::WIDTH, net::WIDTH, 2>), grid(GB::TX), dim3(GB::NT), 0, nt->stream, nt->dz0,
                        nt->wb + o2, (const float *)nullptr, a2, nt->dz1, n);
     // layer 1 (32 -> 32): dZ = dz1
-    if ((rc = net_wgrad<net::WIDTH, net::WIDTH>(nt, nt->dz1, a1, count, n, o1))) return rc;
+    if ((rc = net_wgrad<net::WIDTH, net::WIDTH, true>(nt, nt->dz1, a1, count, n, o1))) return rc;
     hipLaunchKernelGGL((net::k_conv<net::WIDTH, net::WIDTH, 2>), grid(GB::TX), dim3(GB::NT), 0, nt->stream, nt->dz1,
                        nt->wb + o1, (const float *)nullptr, a1, nt->dz0, n);
     // layer 0 (7 -> 32): dZ = dz0, inputs X
-    if ((rc = net_wgrad<net::CIN, net::WIDTH>(nt, nt->dz0, nt->X, count, n, o0))) return rc;
+    if ((rc = net_wgrad<net::CIN, net::WIDTH, false>(nt, nt->dz0, nt->X, count, n, o0))) return rc;
     NCHK(hipGetLastError());
     return TSFCDE_OK;
 }
@@ -1548,6 +1558,7 @@ int tsfcde_net_create(void *d_workspace, size_t bytes, int64_t max_points, int32
     nt->wbf = reinterpret_cast<uint16_t *>(ws + L.wbf);
     nt->wt = reinterpret_cast<float *>(ws + L.wt);
     nt->wb = reinterpret_cast<float *>(ws + L.wb);
+    nt->wm = reinterpret_cast<uint16_t *>(ws + L.wm);
     nt->X = reinterpret_cast<float *>(ws + L.X);
     nt->act = reinterpret_cast<float *>(ws + L.act);
     nt->y = reinterpret_cast<float *>(ws + L.y);

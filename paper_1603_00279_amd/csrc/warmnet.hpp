@@ -12,9 +12,14 @@
 // the sizes of the convection and two diffusion terms of sigma L_j relative
 // to eta_j, see (3.3)).
 //
-// Precision: weights in bfloat16 (rounded to nearest even from FP32 master
-// weights kept for the optimiser), biases, activations and every
-// accumulation in FP32; the extrapolation and the scale s in FP64.
+// Precision: bfloat16 weights (rounded to nearest even from FP32 master
+// weights kept for the optimiser) and FP32 accumulation everywhere.  The two
+// hidden 32 -> 32 layers run on the matrix cores (v_mfma_f32_32x32x8_bf16),
+// so their inputs (tanh outputs in [-1, 1]) are rounded to bfloat16 too; the
+// input layer (whose first channel grows like the level index, which bfloat16
+// would quantise in steps of up to 1/2) and the output layer take FP32 inputs
+// on FP32 vector FMAs, as do the backward passes.  Biases, activations and
+// gradients are FP32; the extrapolation and the scale s FP64.
 //
 // Layout: activations of a batch of B samples as [B][channels][n] (FP32);
 // parameters as one flat vector, layer by layer W[c_out][c_in][5] then
@@ -41,6 +46,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {  // round to nearest,
     u += 0x7FFFu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
+__device__ __forceinline__ float round_bf16(float f) { return bf16_to_f32(f32_to_bf16(f)); }
 
 // Block sum of a double (every thread passes its part; result valid in thread 0).
 template <int NT>
@@ -74,11 +80,21 @@ __global__ void __launch_bounds__(NT) k_net_scale(const Sample *__restrict__ smp
     if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = tot;
 }
 
+// s of sample b from its slices, formed once per workgroup (the first wave
+// reads the slices, thread 0 adds them in slice order and shares the result).
 __device__ __forceinline__ double net_scale(const double *part, int nparts, int b, int64_t n) {
-    double t = 0.0;
-    for (int k = 0; k < nparts; ++k) t += part[(size_t)b * nparts + k];
-    const double s = sqrt(t / (double)n);
-    return s > 0.0 ? s : 1.0;
+    __shared__ double sl[64];
+    __shared__ double sv;
+    if (threadIdx.x < 64) sl[threadIdx.x] = (int)threadIdx.x < nparts ? part[(size_t)b * nparts + threadIdx.x] : 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < nparts; ++k) t += sl[k];
+        const double s = sqrt(t / (double)n);
+        sv = s > 0.0 ? s : 1.0;
+    }
+    __syncthreads();
+    return sv;
 }
 
 // Network inputs X[b][c][i] and, when the sample has u^{j+1}, the target
@@ -112,6 +128,26 @@ __global__ void k_net_output(Sample S, int64_t n, const float *__restrict__ y, d
     }
 }
 
+// Cooperative load of TOT tile elements by NT threads: element e = it*NT + t
+// is src(e) (a global load, or 0), stored by put(e, value).  The pass count
+// is a compile-time constant, so every load of the tile is in flight before
+// the first LDS store.
+template <int TOT, int NT, class Src, class Put>
+__device__ __forceinline__ void tile_load(Src src, Put put) {
+    constexpr int IT = (TOT + NT - 1) / NT;
+    float v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = it * NT + (int)threadIdx.x;
+        v[it] = e < TOT ? src(e) : 0.0f;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = it * NT + (int)threadIdx.x;
+        if (e < TOT) put(e, v[it]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Convolution out[b][co][p] = sum_ci sum_k W[co][ci][k] in[b][ci][p + k - 2]
 // (zero outside 0 <= p + k - 2 < n), then an epilogue:
@@ -126,11 +162,11 @@ __global__ void k_net_output(Sample S, int64_t n, const float *__restrict__ y, d
 template <int CI, int CO> struct ConvGeo {
     static constexpr int OPT = CO < 8 ? CO : 8;
     static constexpr int G = CO / OPT;
-    static constexpr int TX = G >= 4 ? 64 : (G == 2 ? 128 : 256);
+    static constexpr int TX = G >= 4 ? 64 : (G == 2 ? 128 : 64);
     static constexpr int NT = TX * G;
 };
 
-template <int CI, int CO, int EPI>
+template <int CI, int CO, int EPI, bool ROUND = false>
 __global__ void __launch_bounds__((ConvGeo<CI, CO>::NT)) k_conv(const float *__restrict__ in,
                                                                const float *__restrict__ Wt,
                                                                const float *__restrict__ bias,
@@ -143,12 +179,14 @@ __global__ void __launch_bounds__((ConvGeo<CI, CO>::NT)) k_conv(const float *__r
     const int b = blockIdx.y;
     const int64_t p0 = (int64_t)blockIdx.x * TX;
     const float *inb = in + (size_t)b * CI * n;
-    for (int idx = threadIdx.x; idx < CI * (TX + 2 * HALF); idx += NT) {
-        const int ci = idx / (TX + 2 * HALF), q = idx % (TX + 2 * HALF);
-        const int64_t p = p0 + q - HALF;
-        tile[ci][q] = (p >= 0 && p < n) ? inb[(size_t)ci * n + p] : 0.0f;
-    }
-    for (int idx = threadIdx.x; idx < CI * KS * CO; idx += NT) wl[idx] = Wt[idx];
+    constexpr int TW = TX + 2 * HALF;
+    tile_load<CI * TW, NT>(
+        [&](int e) {
+            const int64_t p = p0 + e % TW - HALF;
+            return (p >= 0 && p < n) ? inb[(size_t)(e / TW) * n + p] : 0.0f;
+        },
+        [&](int e, float v) { tile[e / TW][e % TW] = ROUND ? round_bf16(v) : v; });
+    tile_load<CI * KS * CO, NT>([&](int e) { return Wt[e]; }, [&](int e, float v) { wl[e] = v; });
     __syncthreads();
     const int tp = threadIdx.x % TX, cg = threadIdx.x / TX;
     const int64_t p = p0 + tp;
@@ -249,7 +287,7 @@ template <int CI, int CO> struct WgradGeo {
     static constexpr int NE = CO * CI * KS + CO;  // entries per layer
 };
 
-template <int CI, int CO>
+template <int CI, int CO, bool ROUND>
 __global__ void __launch_bounds__((WgradGeo<CI, CO>::NT)) k_net_wgrad(const float *__restrict__ dz,
                                                                      const float *__restrict__ a, int64_t n,
                                                                      float *__restrict__ part) {
@@ -273,16 +311,19 @@ __global__ void __launch_bounds__((WgradGeo<CI, CO>::NT)) k_net_wgrad(const floa
     }
     for (int64_t p0 = (int64_t)blockIdx.x * TX; p0 < n; p0 += (int64_t)gridDim.x * TX) {
         __syncthreads();
-        for (int idx = t; idx < CI * (TX + 2 * HALF); idx += NT) {
-            const int c = idx / (TX + 2 * HALF), q = idx % (TX + 2 * HALF);
-            const int64_t p = p0 + q - HALF;
-            ta[c][q] = (p >= 0 && p < n) ? ab[(size_t)c * n + p] : 0.0f;
-        }
-        for (int idx = t; idx < CO * TX; idx += NT) {
-            const int c = idx / TX, q = idx % TX;
-            const int64_t p = p0 + q;
-            tz[c][q] = p < n ? zb[(size_t)c * n + p] : 0.0f;
-        }
+        constexpr int TW = TX + 2 * HALF;
+        tile_load<CI * TW, NT>(
+            [&](int e) {
+                const int64_t p = p0 + e % TW - HALF;
+                return (p >= 0 && p < n) ? ab[(size_t)(e / TW) * n + p] : 0.0f;
+            },
+            [&](int e, float v) { ta[e / TW][e % TW] = ROUND ? round_bf16(v) : v; });  // as the forward pass saw it
+        tile_load<CO * TX, NT>(
+            [&](int e) {
+                const int64_t p = p0 + e % TX;
+                return p < n ? zb[(size_t)(e / TX) * n + p] : 0.0f;
+            },
+            [&](int e, float v) { tz[e / TX][e % TX] = v; });
         __syncthreads();
         if (own) {
             for (int q = 0; q < TX; ++q) {
@@ -318,6 +359,80 @@ __global__ void k_net_wgrad_reduce(const float *__restrict__ part, int nwg, int 
     float s = 0.0f;
     for (int w = 0; w < nwg; ++w) s += part[(size_t)w * ne + e];
     grad[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Forward convolution to 32 channels on the matrix cores.  As a product,
+//   out[co][p] = sum_k Wm[co][k] * T[k][p],  k = tap * CIP + ci (tap-major),
+// with T[k][p] = bf16(in[ci][p + tap - 2]) (zero outside the grid and for the
+// padding channels ci >= CI) and Wm the bfloat16 weights in that k order.
+// A wave computes 32 channels x 32 positions with v_mfma_f32_32x32x8_bf16:
+//   A (32 x 8): lane l holds Wm[l % 32][kb*8 + 4(l/32) + t], t = 0..3,
+//   B (8 x 32): lane l holds T[kb*8 + 4(l/32) + t][l % 32],
+//   D (32 x 32): lane l, register r holds out[8(r/4) + 4(l/32) + r%4][l % 32],
+// (layout checked on the device against a CPU product).  Four consecutive k
+// share a tap and are four adjacent channels, so the input tile is kept in
+// LDS channel-last and every B operand is one 8-byte read.  Epilogue: bias,
+// tanh, FP32 store (coalesced along positions).
+// ---------------------------------------------------------------------------
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int MFMA_WAVES = 2;  // waves (of 32 positions each) per workgroup
+
+template <int CI, int CIP>
+__global__ void __launch_bounds__(64 * MFMA_WAVES) k_conv_mfma(const float *__restrict__ in,
+                                                               const uint16_t *__restrict__ Wm,
+                                                               const float *__restrict__ bias, float *__restrict__ out,
+                                                               int64_t n) {
+    constexpr int NT = 64 * MFMA_WAVES, TX = 32 * MFMA_WAVES, K = KS * CIP, KB = K / 8;
+    constexpr int RS = CIP + 4;  // padded LDS row (bf16 units)
+    static_assert(CIP % 8 == 0 || CIP == 8, "channel padding");
+    __shared__ __align__(16) uint16_t tin[(TX + 2 * HALF) * RS];
+    const int b = blockIdx.y;
+    const int64_t p0 = (int64_t)blockIdx.x * TX;
+    const float *inb = in + (size_t)b * CI * n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, c32 = lane & 31;
+    // the wave's weights (A operands) straight from global memory
+    bf16x4 aw[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) aw[kb] = *reinterpret_cast<const bf16x4 *>(Wm + c32 * K + kb * 8 + 4 * h);
+    constexpr int TW = TX + 2 * HALF;
+    tile_load<CIP * TW, NT>(
+        [&](int e) {
+            const int ci = e / TW;
+            const int64_t p = p0 + e % TW - HALF;
+            return (ci < CI && p >= 0 && p < n) ? inb[(size_t)ci * n + p] : 0.0f;
+        },
+        [&](int e, float v) { tin[(e % TW) * RS + e / TW] = f32_to_bf16(v); });
+    __syncthreads();
+    const int pw = wave * 32 + c32;  // this lane's position column within the tile
+    f32x16 acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        const int k0 = kb * 8 + 4 * h, tap = k0 / CIP, ci0 = k0 % CIP;
+        const bf16x4 bv = *reinterpret_cast<const bf16x4 *>(tin + (pw + tap) * RS + ci0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aw[kb], bv, acc, 0, 0, 0);
+    }
+    const int64_t p = p0 + pw;
+    if (p < n) {
+        float *ob = out + (size_t)b * 32 * n;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int co = 8 * (r / 4) + 4 * h + (r % 4);
+            ob[(size_t)co * n + p] = tanhf(acc[r] + bias[co]);
+        }
+    }
+}
+
+// bfloat16 weights W[co][ci][k] (32 outputs) -> Wm[co][k * CIP + ci], zero for
+// the padding channels.
+__global__ void k_net_widen_mfma(const uint16_t *__restrict__ W, int ci_n, int cip, uint16_t *__restrict__ Wm) {
+    const int tot = 32 * KS * cip;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
+        const int co = idx / (KS * cip), rem = idx % (KS * cip), k = rem / cip, ci = rem % cip;
+        Wm[idx] = ci < ci_n ? W[(co * ci_n + ci) * KS + k] : (uint16_t)0;
+    }
 }
 
 // Adam (Kingma and Ba 2015, Algorithm 1) on the FP32 master parameters, then

@@ -24,12 +24,14 @@ def test_backward_matches_central_differences():
     X = rng.normal(size=(N.CIN, n))
     t = rng.normal(size=n)
 
+    exact = lambda a: a  # noqa: E731  (the chain rule, without the piecewise-constant rounding)
+
     def f(th):
-        y, _ = N.forward(th, X)
+        y, _ = N.forward(th, X, exact)
         return N.loss(y, X[1], t)
 
-    y, acts = N.forward(theta, X)
-    g = N.backward(theta, acts, N.loss_dy(y, X[1], t))
+    y, acts = N.forward(theta, X, exact)
+    g = N.backward(theta, acts, N.loss_dy(y, X[1], t), exact)
     idx = rng.choice(theta.size, 60, replace=False)
     # every layer's weights and biases among the probes
     offs = np.cumsum([0] + [co * ci * N.KS + co for ci, co in N.LAYERS])
@@ -137,3 +139,26 @@ def test_correction_vanishes_with_the_second_difference():
     base = 3.0 * (u[2] - u[1]) + u[0]
     assert np.array_equal(x0[:3], base[:3])
     assert not np.allclose(x0[3:], base[3:])
+
+
+def test_rounded_network_is_the_exact_one_on_rounded_inputs():
+    """With bfloat16 rounding, each layer computes what the exact network
+    computes on that layer's (for the hidden layers, rounded) input, checked
+    layer by layer; the output layer's weight gradient uses its input as is."""
+    rng = np.random.default_rng(8)
+    theta = N.weights_bf16(rng.normal(0, 0.3, N.param_count()))
+    X = rng.normal(size=(N.CIN, 13))
+    y, acts = N.forward(theta, X)
+    layers = N.unpack(theta)
+    for li, (W, b) in enumerate(layers):
+        z = N.conv(N.bf16_round(acts[li]) if li in N.ROUNDED else acts[li], W, b)
+        ref = np.tanh(z) if li < len(layers) - 1 else z
+        assert np.array_equal(acts[li + 1], ref)
+    dy = rng.normal(size=13)
+    g = N.backward(theta, acts, dy)
+    W3, _ = layers[3]
+    a3 = np.zeros((32, 13 + 4))
+    a3[:, 2:15] = acts[3]  # the output layer takes its input unrounded
+    dW3 = np.stack([dy @ a3[:, k:k + 13].T for k in range(N.KS)], axis=-1)
+    o3 = N.param_count() - (32 * N.KS + 1)
+    assert np.allclose(g[o3:o3 + 32 * N.KS].reshape(1, 32, N.KS), dW3[None], rtol=1e-12, atol=0)
