@@ -33,12 +33,29 @@ def log(msg):
 
 # Algorithmic HBM bytes per launch of each kernel class, FP64, for n unknowns
 # (reads + writes the kernel must make, counting each vector once):
-#   history at level j: reads u^0..u^j (8n(j+1)), writes H (8n)
+#   history: one sweep per block of HB levels (reads u^0..u^{b-1}, writes the
+#     block's sums) and a catch-up per later level (reads the newest levels of
+#     the block and its sum, writes P); see history_bytes
 #   matvec middle pass (k_mid, product mode): reads the N = n complex buffer
 #     (16n) and the stored spectrum (16n), writes the buffer (16n): 48n
 #   preconditioner middle pass (k_mid, solve mode): the same on N = n/2: 24n
-def history_bytes(n, j):
-    return 8 * n * (j + 1) + 8 * n if j >= 1 else 0
+HB = 8  # levels per history block (one sweep over the stored levels per block)
+
+
+def history_bytes(n, M, levels):
+    """Algorithmic HBM bytes and launches of the history kernels over levels
+    0..levels-1: at a block's first level b the sweep reads u^0..u^{b-1} and
+    writes the block's sums; at a later level L of the block the catch-up
+    reads u^{b-1}..u^{L-1} and the block sum Q_L and writes P_L."""
+    total, launches = 0, 0
+    for L in range(1, levels):
+        b = 1 + HB * ((L - 1) // HB)
+        if L == b:
+            total += 8 * n * (b + min(HB, M - b))
+        else:
+            total += 8 * n * ((L - b + 1) + 2)
+        launches += 1
+    return total, launches
 
 
 KCLASS = {"history": 0, "col_passes": 1, "mid_matvec": 2, "cgs_chunks": 3, "mid_precond": 4, "fused_cols": 5}
@@ -272,6 +289,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the warm-started forms")
     ap.add_argument("--profile-class", default="mid_matvec", choices=sorted(KCLASS))
+    ap.add_argument("--profile-period", type=int, default=7,
+                    help="events on every k-th launch of the profiled class (1 = all)")
     ap.add_argument("--fp32-n", type=int, default=2048, help="grid of the FP32-refined form inside its envelope")
     ap.add_argument("--form", default="all", choices=["all", "warm", "fp32", "batched", "learned"],
                     help="which of the other forms to run (for profiling one of them)")
@@ -322,7 +341,11 @@ def main():
         log(f"warmup step {w + 1}/{args.warmup} done")
 
     cls = KCLASS[args.profile_class]
-    s.profile(cls, True)
+    # events on a sample of the class's launches: a launch that carries them
+    # idles the stream for a few microseconds on either side (the history sum,
+    # one launch per level of growing size, is timed at every launch)
+    period = 1 if args.profile_class == "history" else args.profile_period
+    s.profile(cls, True, period)
     stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -332,6 +355,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     launches, kms = s.profile_read(cls)
+    issued = s.profile_issued(cls)
     s.profile(cls, False)
 
     total_levels = levels * args.steps
@@ -340,8 +364,8 @@ def main():
     n = prob.n
     # roofline of the dominant kernel (HBM-bound; algorithmic bytes per launch)
     if args.profile_class == "history":
-        bytes_step = sum(history_bytes(n, j) for j in range(levels))
-        per_launch = bytes_step / max(1, levels - 1)
+        bytes_step, nl_step = history_bytes(n, prob.M, levels)
+        per_launch = bytes_step / max(1, nl_step)
     elif args.profile_class == "mid_matvec":
         per_launch = 48 * n   # buffer in (16n) + spectrum (16n) + buffer out (16n)
     elif args.profile_class == "mid_precond":
@@ -355,7 +379,8 @@ def main():
         real = args.steps * (2 * sum(iters) + levels)
     elif args.profile_class == "mid_precond":
         real = args.steps * 2 * sum(iters)
-    avg_ms = kms / max(1, real)
+    # mean over the sampled launches, scaled to every issued launch, per working launch
+    avg_ms = kms / max(1, launches) * issued / max(1, real)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if launches else float("nan")
     peak = 8000.0
     out = {
@@ -377,7 +402,8 @@ def main():
                    "warm_start": "previous level" if args.warm_start else "zero"},
         "roofline": {"bound": "hbm", "kernel": args.profile_class, "achieved": achieved, "peak": peak,
                      "unit": "GB/s", "frac": achieved / peak, "traffic": None,
-                     "launches": launches, "working_launches": real, "avg_launch_us": 1e3 * avg_ms,
+                     "sampled_launches": launches, "sample_period": period, "issued_launches": issued,
+                     "working_launches": real, "avg_launch_us": 1e3 * avg_ms,
                      "algorithmic_bytes_per_launch": per_launch},
         "cgs_iterations": {"mean": float(np.mean(iters)), "min": int(min(iters)), "max": int(max(iters))},
     }

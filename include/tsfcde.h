@@ -226,12 +226,19 @@ int64_t tsfcde_level(tsfcde_plan_t plan);
  * 2 = middle passes of the Toeplitz products (row FFTs with the embedding
  * symbol multiply), 3 = whole Krylov iteration chunks, 4 = middle passes of
  * the preconditioner solves (row FFTs with the Strang symbol divide), 5 =
- * fused column passes (preconditioner inverse + product forward).  enable != 0 starts recording and clears the
- * totals; tsfcde_profile_read synchronizes the stream and returns the number
- * of recorded launches and their summed duration in milliseconds. */
+ * fused column passes (preconditioner inverse + product forward).
+ * enable > 0 starts recording and clears the totals: the events ride on every
+ * enable-th launch of the class (1 = every launch; a launch that carries
+ * events costs the stream a few microseconds of idle time, so a sample keeps
+ * throughput measurements honest).  enable = 0 stops; enable < 0 is
+ * TSFCDE_EINVAL.  tsfcde_profile_read synchronizes the stream and returns the
+ * number of recorded (sampled) launches and their summed duration in
+ * milliseconds; tsfcde_profile_issued returns how many launches of the class
+ * were issued, sampled or not, since recording started. */
 int tsfcde_profile(tsfcde_plan_t plan, int32_t kernel_class, int32_t enable);
 int tsfcde_profile_read(tsfcde_plan_t plan, int32_t kernel_class, int64_t *launches,
                         double *milliseconds);
+int tsfcde_profile_issued(tsfcde_plan_t plan, int32_t kernel_class, int64_t *issued);
 
 /* Release the plan (host state only; the caller frees the workspace). */
 int tsfcde_destroy(tsfcde_plan_t plan);

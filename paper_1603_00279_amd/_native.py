@@ -84,6 +84,7 @@ _SIGS = {
     "tsfcde_embedding_length": (c_int64, [c_void_p]),
     "tsfcde_profile": (c_int32, [c_void_p, c_int32, c_int32]),
     "tsfcde_profile_read": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
+    "tsfcde_profile_issued": (c_int32, [c_void_p, c_int32, POINTER(c_int64)]),
     "tsfcde_destroy": (c_int32, [c_void_p]),
     "tsfcde_batch_workspace_bytes": (c_int32, [POINTER(tsfcde_problem), c_int32, POINTER(c_size_t)]),
     "tsfcde_plan_batch": (c_int32, [POINTER(tsfcde_problem), c_int32, c_void_p, c_size_t, c_void_p,

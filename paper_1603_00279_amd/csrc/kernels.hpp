@@ -39,6 +39,10 @@ enum : int { ST_OK = 0, ST_BREAKDOWN = 1, ST_NONFINITE = 2 };
 // Predication of a launch on the device scalars: pred 0 always runs, pred 1
 // skips once the solve is done, pred 2 skips when the last restart found its
 // guess better than the right-hand side's (a second restart is then moot).
+// The scalars were written by the previous kernel, so reading them misses the
+// caches; kernels test the predicate after issuing their own loads (all in
+// bounds whatever the outcome) and before their first barrier or store, so the
+// two latencies overlap.  The test is uniform over the workgroup.
 __device__ __forceinline__ bool skip(int pred, const DevScalars *sc) {
     return (pred == 1 && sc->done) || (pred == 2 && sc->better);
 }
@@ -198,11 +202,11 @@ template <class S> struct InCgsUPT {
     __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
         int64_t i = 2 * (row * C + col);
         if (i >= nr) return;
+        // q and p are loaded even on a fresh start (their values are then
+        // unused): the loads need not wait for the flag
         raw[0] = ld2(r, i, nr);
-        if (!first) {
-            raw[1] = ld2(q, i, nr);
-            raw[2] = ld2(p, i, nr);
-        }
+        raw[1] = ld2(q, i, nr);
+        raw[2] = ld2(p, i, nr);
     }
     __device__ __forceinline__ double2 finish(int row, int64_t col, const double2 *raw) const {
         int64_t i = 2 * (row * C + col);
@@ -688,7 +692,6 @@ template <class Out, int NP> struct ColSink {
 template <int R, int EMAX, int DIR, class In, class Out>
 __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double2 *__restrict__ tw_all, DevScalars *sc,
                                          int pred) {
-    if (skip(pred, sc)) return;
     using G = ColGeo<R, EMAX>;
     constexpr int E = G::E, T = G::T, B = G::B;
     __shared__ double2 lds[lpad_size(R) * B];
@@ -713,6 +716,7 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
         for (int m = 0; m < E; ++m)
             if (active) out.fetch(LastStage<R, E>::pos(j, m), c, pre[m]);
     }
+    if (skip(pred, sc)) return;
     double2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = active ? in.finish(j + T * m, c, raw[m]) : make_double2(0.0, 0.0);
@@ -733,10 +737,10 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
 // Finishing kernel of a reducing pass (one workgroup of the pass's size NT).
 template <int NT, class Out>
 __global__ void __launch_bounds__(NT) k_final(Out out, int nparts, DevScalars *sc, int pred) {
-    if (skip(pred, sc)) return;
+    const bool sk = skip(pred, sc);
     double tot[Out::NACC];
     reduce_partials<Out::NACC>(out.partials, nparts, tot);
-    if (threadIdx.x == 0) out.final(tot, sc);
+    if (!sk && threadIdx.x == 0) out.final(tot, sc);
 }
 
 template <int R, int EMAX, int DIR, class In, class Out>
@@ -766,10 +770,10 @@ __global__ void __launch_bounds__((ColGeo<R, EMAX>::NT)) k_col_b(const ColDesc<I
 template <int NT, class In, class Out>
 __global__ void __launch_bounds__(NT) k_final_b(const ColDesc<In, Out> *__restrict__ d, int nparts, int pred) {
     const ColDesc<In, Out> &D = d[blockIdx.y];
-    if (skip(pred, D.sc)) return;
+    const bool sk = skip(pred, D.sc);
     double tot[Out::NACC];
     reduce_partials<Out::NACC>(D.out.partials, nparts, tot);
-    if (threadIdx.x == 0) D.out.final(tot, D.sc);
+    if (!sk && threadIdx.x == 0) D.out.final(tot, D.sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -827,7 +831,6 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
                                                                 CS *__restrict__ bufA, Tw2 twA, Op op,
                                                                 const double2 *__restrict__ tw_all, DevScalars *sc,
                                                                 int pred) {
-    if (skip(pred, sc)) return;
     using G = FuseGeo<RP, EMAX>;
     constexpr int RA = G::RA, EA = G::EA, TA = G::TA, B = G::B, EP = G::EP, TP = G::TP;
     __shared__ double2 lds[lpad_size(RA) * B];
@@ -861,6 +864,7 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
 #pragma unroll
     for (int m = 0; m < EA; ++m)
         if (colok) twA.fetch(2 * (int64_t)LastStage<RA, EA>::pos(j, m) * c, twa[m]);
+    if (skip(pred, sc)) return;
     double2 vp[EP];
 #pragma unroll
     for (int m = 0; m < EP; ++m)
@@ -944,7 +948,6 @@ using RowSink = RowSinkT<double2>;
 template <int C_, int EMAX, int MODE, class CS>
 __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, double2 *spec_out, Tw2 twL,
                                          SymParams sp, const double2 *__restrict__ tw_all, DevScalars *sc, int pred) {
-    if (skip(pred, sc)) return;
     using G = MidGeo<C_, EMAX>;
     constexpr int E = G::E, T = G::T, LS = G::LS;
     constexpr int64_t C = C_;
@@ -982,6 +985,7 @@ __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, doubl
             }
         }
     }
+    if (skip(pred, sc)) return;
     LdsSink lsink{slab, 1};
     if constexpr (TWL) {
         stage_twiddles<C_>(twl, tw_all, t, G::NT);
@@ -1275,13 +1279,25 @@ __global__ void k_pc_embed(const double2 *Wt, int64_t n, int64_t L, double *e) {
 }
 
 // ---------------------------------------------------------------------------
-// History sum of (3.3):  H = kappa * sum_{s=0}^{j-1} c_{j-s}^(j) (u^{s+1} - u^s)
-// with c_j^(j) = clast (s = 0) and c_m^(j) = cbase[m] (1 <= m <= j-1).
+// History sum of (3.3):  H_L = kappa * sum_{s=0}^{L-1} c_{L-s}^(L) (u^{s+1} - u^s)
+// with c_L^(L) = clast[L] (s = 0) and c_m^(L) = cbase[m] (1 <= m <= L-1).
 // The kernels form every term but the newest level's,
-//   P = kappa * [ sum_{s=0}^{j-2} c_{j-s} (u^{s+1} - u^s) - c_1 u^{j-1} ],
-// so that H = P + kappa c_1 u^j: P needs only u^0..u^{j-1} and can be summed
-// while level j-1 is being solved, and the right-hand side folds
-// kappa c_1 u^j into its coefficient of u^j.
+//   P_L = kappa * [ sum_{s=0}^{L-2} c_{L-s} (u^{s+1} - u^s) - c_1 u^{L-1} ],
+// so that H_L = P_L + kappa c_1 u^L and the right-hand side folds
+// kappa c_1 u^L into its coefficient of u^L.
+//
+// Blocked evaluation.  The weights depend on L - s only (and on L through the
+// s = 0 weight), so one pass over the stored levels can serve several future
+// levels.  Levels are grouped in blocks of HB from level 1; for a block that
+// starts at level b and a level L of it,
+//   P_L = Q_L + kappa * [ sum_{s=b-1}^{L-2} c_{L-s} (u^{s+1} - u^s) - c_1 u^{L-1} ]   (L > b),
+//   Q_L = kappa * sum_{s=0}^{b-2} c_{L-s}^(L) (u^{s+1} - u^s),      P_b = Q_b - kappa c_1^(b) u^{b-1}.
+// The sweep (k_hist_sweep) reads u^0..u^{b-1} once and writes Q_L for every
+// level of the block (P_b for the first); the catch-up (k_hist_catch) of level
+// L > b reads the L - b + 1 newest levels u^{b-1}..u^{L-1} and Q_L and writes
+// P_L.  Per level that is about 1/HB of the stored levels instead of all of
+// them.  The arithmetic of each element does not depend on the grid, so
+// every path (side stream, main stream, batch) gives bitwise the same sums.
 // Each lane streams two adjacent unknowns through the stored levels (rows of
 // U are ldu >= n doubles apart, ldu even; an odd n reads the zero pad).
 // ---------------------------------------------------------------------------
@@ -1289,79 +1305,116 @@ __device__ __forceinline__ double hist_c(int s, int j, const double *cbase, doub
     return s == 0 ? clast : cbase[j - s];
 }
 
-__device__ __forceinline__ void history_pair(const double *__restrict__ U, int64_t ldu, int j,
-                                             const double *__restrict__ cbase, double clast, double kappa,
-                                             double *__restrict__ H, int64_t i) {
+constexpr int HB = 8;  // levels per history block
+
+struct HistBlock {
+    double clast[HB];  // clast[b + l]: the s = 0 weight of level b + l
+    double c1b;        // c_1^(b)
+    int b, nl;         // first level of the block, levels in it (<= HB)
+};
+
+__device__ __forceinline__ void hist_sweep_pair(const double *__restrict__ U, int64_t ldu,
+                                                const double *__restrict__ cbase, const HistBlock &hb, double kappa,
+                                                double *__restrict__ Q, int64_t i) {
     double2 prev = *reinterpret_cast<const double2 *>(U + i);
-    double2 acc = make_double2(0.0, 0.0);
+    double2 acc[HB];
+#pragma unroll
+    for (int l = 0; l < HB; ++l) acc[l] = make_double2(0.0, 0.0);
+    const int b = hb.b, nl = hb.nl;
+    auto add = [&](int s, double2 x) {
+        const double2 d = make_double2(x.x - prev.x, x.y - prev.y);
+#pragma unroll
+        for (int l = 0; l < HB; ++l) {
+            if (l < nl) {
+                const double c = s == 0 ? hb.clast[l] : cbase[b + l - s];
+                acc[l].x = fma(c, d.x, acc[l].x);
+                acc[l].y = fma(c, d.y, acc[l].y);
+            }
+        }
+        prev = x;
+    };
     int s = 0;
-    const int full = j - 1;  // complete differences s = 0..j-2
-    // eight levels in flight per step
-    constexpr int U8 = 8;
+    const int full = b - 1;  // differences s = 0..b-2
+    constexpr int U8 = 8;    // eight levels in flight per step
     for (; s + U8 <= full; s += U8) {
         double2 x[U8];
 #pragma unroll
         for (int q = 0; q < U8; ++q) x[q] = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1 + q) * ldu + i);
 #pragma unroll
-        for (int q = 0; q < U8; ++q) {
-            const double cq = hist_c(s + q, j, cbase, clast);
-            acc.x = fma(cq, x[q].x - prev.x, acc.x);
-            acc.y = fma(cq, x[q].y - prev.y, acc.y);
-            prev = x[q];
-        }
+        for (int q = 0; q < U8; ++q) add(s + q, x[q]);
     }
-    for (; s < full; ++s) {
-        double2 x1 = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1) * ldu + i);
-        const double c1 = hist_c(s, j, cbase, clast);
-        acc.x = fma(c1, x1.x - prev.x, acc.x);
-        acc.y = fma(c1, x1.y - prev.y, acc.y);
-        prev = x1;
-    }
-    const double cl = hist_c(j - 1, j, cbase, clast);  // prev = u^{j-1}
-    acc.x = fma(-cl, prev.x, acc.x);
-    acc.y = fma(-cl, prev.y, acc.y);
-    *reinterpret_cast<double2 *>(H + i) = make_double2(kappa * acc.x, kappa * acc.y);
+    for (; s < full; ++s) add(s, *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1) * ldu + i));
+    acc[0].x = fma(-hb.c1b, prev.x, acc[0].x);  // prev = u^{b-1}
+    acc[0].y = fma(-hb.c1b, prev.y, acc[0].y);
+#pragma unroll
+    for (int l = 0; l < HB; ++l)
+        if (l < nl)
+            *reinterpret_cast<double2 *>(Q + (int64_t)l * ldu + i) = make_double2(kappa * acc[l].x, kappa * acc[l].y);
 }
 
-__global__ void __launch_bounds__(256) k_history(const double *__restrict__ U, int64_t n, int64_t ldu, int j,
-                                                 const double *__restrict__ cbase, double clast, double kappa,
-                                                 double *__restrict__ H) {
-    // grid-stride over pairs: a small grid runs as a background job beside the solve
+__device__ __forceinline__ void hist_catch_pair(const double *__restrict__ U, int64_t ldu,
+                                                const double *__restrict__ cbase, int b, int L, double clastL,
+                                                double c1L, double kappa, const double *__restrict__ QL,
+                                                double *__restrict__ P, int64_t i) {
+    double2 prev = *reinterpret_cast<const double2 *>(U + (int64_t)(b - 1) * ldu + i);
+    const double2 q = *reinterpret_cast<const double2 *>(QL + i);
+    double2 acc = make_double2(0.0, 0.0);
+    for (int s = b - 1; s <= L - 2; ++s) {
+        const double2 x = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1) * ldu + i);
+        const double c = hist_c(s, L, cbase, clastL);
+        acc.x = fma(c, x.x - prev.x, acc.x);
+        acc.y = fma(c, x.y - prev.y, acc.y);
+        prev = x;
+    }
+    acc.x = fma(-c1L, prev.x, acc.x);  // prev = u^{L-1}
+    acc.y = fma(-c1L, prev.y, acc.y);
+    *reinterpret_cast<double2 *>(P + i) = make_double2(fma(kappa, acc.x, q.x), fma(kappa, acc.y, q.y));
+}
+
+// Grid-stride over pairs: a small grid runs as a background job beside the solve.
+__global__ void __launch_bounds__(256) k_hist_sweep(const double *__restrict__ U, int64_t n, int64_t ldu,
+                                                    const double *__restrict__ cbase, HistBlock hb, double kappa,
+                                                    double *__restrict__ Q) {
     for (int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); i < n;
          i += 2 * (int64_t)gridDim.x * blockDim.x)
-        history_pair(U, ldu, j, cbase, clast, kappa, H, i);
+        hist_sweep_pair(U, ldu, cbase, hb, kappa, Q, i);
+}
+
+__global__ void __launch_bounds__(256) k_hist_catch(const double *__restrict__ U, int64_t n, int64_t ldu,
+                                                    const double *__restrict__ cbase, int b, int L, double clastL,
+                                                    double c1L, double kappa, const double *__restrict__ QL,
+                                                    double *__restrict__ P) {
+    for (int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); i < n;
+         i += 2 * (int64_t)gridDim.x * blockDim.x)
+        hist_catch_pair(U, ldu, cbase, b, L, clastL, c1L, kappa, QL, P, i);
 }
 
 // Batched element-wise kernels: descriptor per instance (blockIdx.y), a
-// grid-stride loop over that instance's length in blockIdx.x.
+// grid-stride loop over that instance's length in blockIdx.x.  An instance
+// with nothing to do at this level has n = 0.
 struct HistDesc {
     const double *U;
     int64_t n, ldu;
     const double *cbase;
-    double clast, kappa;
-    double *H;
-    int j;
+    HistBlock hb;     // sweep
+    int L;            // catch-up level
+    double clastL, c1L, kappa;
+    const double *QL;
+    double *out;      // Q (sweep) or P (catch-up)
 };
 
-__global__ void __launch_bounds__(256) k_history_b(const HistDesc *__restrict__ d) {
-    const HistDesc D = d[blockIdx.y];
-    if (D.j < 1) return;
+__global__ void __launch_bounds__(256) k_hist_sweep_b(const HistDesc *__restrict__ d) {
+    const HistDesc &D = d[blockIdx.y];
     for (int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); i < D.n;
-         i += 2 * (int64_t)gridDim.x * blockDim.x) {
-        double2 prev = *reinterpret_cast<const double2 *>(D.U + i);
-        double2 acc = make_double2(0.0, 0.0);
-        for (int s = 0; s < D.j - 1; ++s) {  // the same partial sum as k_history
-            const double2 x1 = *reinterpret_cast<const double2 *>(D.U + (int64_t)(s + 1) * D.ldu + i);
-            const double c1 = hist_c(s, D.j, D.cbase, D.clast);
-            acc.x = fma(c1, x1.x - prev.x, acc.x);
-            acc.y = fma(c1, x1.y - prev.y, acc.y);
-            prev = x1;
-        }
-        const double cl = hist_c(D.j - 1, D.j, D.cbase, D.clast);
-        acc.x = fma(-cl, prev.x, acc.x);
-        acc.y = fma(-cl, prev.y, acc.y);
-        *reinterpret_cast<double2 *>(D.H + i) = make_double2(D.kappa * acc.x, D.kappa * acc.y);
-    }
+         i += 2 * (int64_t)gridDim.x * blockDim.x)
+        hist_sweep_pair(D.U, D.ldu, D.cbase, D.hb, D.kappa, D.out, i);
+}
+
+__global__ void __launch_bounds__(256) k_hist_catch_b(const HistDesc *__restrict__ d) {
+    const HistDesc &D = d[blockIdx.y];
+    for (int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); i < D.n;
+         i += 2 * (int64_t)gridDim.x * blockDim.x)
+        hist_catch_pair(D.U, D.ldu, D.cbase, D.hb.b, D.L, D.clastL, D.c1L, D.kappa, D.QL, D.out, i);
 }
 
 struct PcDesc {

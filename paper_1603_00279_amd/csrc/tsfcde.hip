@@ -97,7 +97,7 @@ struct Layout {
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr int NVEC = 12;  // H g r rt u p q phat vhat uhat fbuf H2
+constexpr int NVEC = 11 + HB;  // H g r rt u p q phat vhat uhat fbuf, then the HB block sums Hq
 constexpr int NV32 = 9;   // FP32 inner solve: r rt u p q phat vhat uhat d
 
 // internal row stride: n rounded up to even, so every row starts 16-byte aligned
@@ -168,6 +168,8 @@ int validate(const tsfcde_problem *p) {
 
 struct ProfRec {
     bool on = false;
+    int64_t period = 1;  // events ride on every period-th launch of the class
+    int64_t issued = 0;  // launches of the class since profiling was switched on
     int64_t launches = 0;
     double ms = 0.0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -188,12 +190,15 @@ struct tsfcde_plan_s {
     RT A, P, B;
     Layout lay;
     char *ws;
-    double *U, *H, *g, *r, *rt, *u, *p, *q, *phat, *vhat, *uhat, *fbuf, *tmp, *w, *g0, *cb, *part, *H2;
-    // history partial sums: level j's in hbuf(j); the next level's is summed on
-    // the side stream `hs` while the current level is solved
+    double *U, *H, *g, *r, *rt, *u, *p, *q, *phat, *vhat, *uhat, *fbuf, *tmp, *w, *g0, *cb, *part, *Hq;
+    // history partial sums: Hq holds the HB block sums Q of block hist_block
+    // (the first level's complete), H the catch-up P of a later level; the
+    // next block's sweep runs on the side stream `hs` while the last level of
+    // the current block is solved
     hipStream_t hs = nullptr;
-    hipEvent_t ev_main = nullptr, ev_hist[2] = {nullptr, nullptr};
-    int64_t hist_pending = -1;  // level whose partial sum was queued on hs
+    hipEvent_t ev_main = nullptr, ev_hist = nullptr;
+    int64_t hist_block = -1;    // block whose sums Hq holds (or is being summed into on hs)
+    bool hist_pending = false;  // that sweep was queued on hs and not yet waited for
     double2 *buf, *bufP, *specA, *specP, *tw_all;
     double2 *bufB, *Bhat, *chirp, *Ls, *wv, *Wt, *specPj;
     DevScalars *sc;
@@ -501,16 +506,18 @@ void harvest(tsfcde_plan_s *pl) {
 #define TSF_SIZES(X) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
 // Launch on the plan's stream; while profiling class `cls` is on, the start
-// and end events ride on the dispatch itself (hipExtLaunchKernelGGL), so the
-// measured interval is the kernel's own run, without the gap an event
-// recorded between kernels would add.
+// and end events ride on every period-th dispatch of the class itself
+// (hipExtLaunchKernelGGL), so the measured interval is the kernel's own run.
+// A dispatch that carries events is separated from its neighbours by a few
+// microseconds of idle time; sampling keeps that cost off most launches.
 template <typename K, typename... Args>
 void launch_timed_on(tsfcde_plan_s *pl, hipStream_t st, int cls, K kernel, dim3 grid, dim3 block, Args... args) {
-    if (pl->prof[cls].on) {
+    ProfRec &pr = pl->prof[cls];
+    if (pr.on && pr.issued++ % pr.period == 0) {
         hipEvent_t e0 = get_event(pl), e1 = e0 ? get_event(pl) : nullptr;
         if (e0 && e1) {
             hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
-            pl->prof[cls].pending.emplace_back(e0, e1);
+            pr.pending.emplace_back(e0, e1);
             return;
         }
         if (e0) pl->event_pool.push_back(e0);
@@ -795,56 +802,92 @@ hipError_t cgs_iter(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x) {
     return pl->p2 ? cgs_iteration(pl, j, b, x) : cgs_iteration_general(pl, j, b, x);
 }
 
-double *hbuf(tsfcde_plan_s *pl, int64_t j) { return (j & 1) ? pl->H2 : pl->H; }
-
 // kappa c_1^(j): the weight of u^j in the history sum of level j (j >= 1)
 double hist_c1(const tsfcde_plan_s *pl, int64_t j) { return pl->kappa * (j == 1 ? pl->clast[1] : pl->cbase[1]); }
+
+// First level of the history block of level L >= 1 (blocks of HB levels from level 1).
+int64_t hist_block_of(int64_t L) { return 1 + HB * ((L - 1) / HB); }
+
+HistBlock hist_block_params(const tsfcde_plan_s *pl, int64_t b) {
+    HistBlock hb{};
+    hb.b = (int)b;
+    hb.nl = (int)std::min<int64_t>(HB, pl->M - b);
+    for (int l = 0; l < hb.nl; ++l) hb.clast[l] = pl->clast[b + l];
+    hb.c1b = b == 1 ? pl->clast[1] : pl->cbase[1];
+    return hb;
+}
+
+// Where the right-hand side of level j >= 1 finds P_j.
+const double *hist_src(const tsfcde_plan_s *pl, int64_t j) { return j == hist_block_of(j) ? pl->Hq : pl->H; }
 
 #ifndef TSF_HIST_SIDE_WG
 #define TSF_HIST_SIDE_WG 256
 #endif
-// On the main stream the partial sum takes the whole chip; on the side stream
-// it runs beside the solve on a small grid (TSF_HIST_SIDE_WG workgroups).
-hipError_t launch_history(tsfcde_plan_s *pl, hipStream_t st, int64_t j) {
+// On the main stream the sweep takes the whole chip; on the side stream it
+// runs beside the solve on a small grid (TSF_HIST_SIDE_WG workgroups).
+hipError_t launch_sweep(tsfcde_plan_s *pl, hipStream_t st, int64_t b) {
     const int64_t n = pl->n, threads = (n + 1) / 2;
     int64_t wg = (threads + 255) / 256;
     if (st != pl->stream) wg = std::min<int64_t>(wg, TSF_HIST_SIDE_WG);
-    launch_timed_on(pl, st, 0, k_history, dim3((unsigned)wg), dim3(256), (const double *)pl->U, n, pl->ldn, (int)j,
-                    (const double *)pl->cb, pl->clast[j], pl->kappa, hbuf(pl, j));
+    launch_timed_on(pl, st, 0, k_hist_sweep, dim3((unsigned)wg), dim3(256), (const double *)pl->U, n, pl->ldn,
+                    (const double *)pl->cb, hist_block_params(pl, b), pl->kappa, pl->Hq);
     return hipGetLastError();
 }
 
-// The side stream is idle and holds no pending partial sum (before anything
-// other than a level step touches U or the history buffers).
+hipError_t launch_catch(tsfcde_plan_s *pl, int64_t L) {
+    const int64_t n = pl->n, threads = (n + 1) / 2, b = hist_block_of(L);
+    const int64_t wg = (threads + 255) / 256;
+    launch_timed(pl, 0, k_hist_catch, dim3((unsigned)wg), dim3(256), (const double *)pl->U, n, pl->ldn,
+                 (const double *)pl->cb, (int)b, (int)L, pl->clast[L], L == 1 ? pl->clast[1] : pl->cbase[1],
+                 pl->kappa, (const double *)(pl->Hq + (size_t)(L - b) * pl->ldn), pl->H);
+    return hipGetLastError();
+}
+
+// The side stream is idle and holds no block sums (before anything other
+// than a level step touches U or the history buffers).
 int history_quiesce(tsfcde_plan_s *pl) {
     if (pl->hs) HIPCHK(hipStreamSynchronize(pl->hs));
-    pl->hist_pending = -1;
+    pl->hist_pending = false;
+    pl->hist_block = -1;
     return TSFCDE_OK;
 }
 
-// The partial history sum of level j in hbuf(j): waited for if the side
-// stream already summed it during level j-1, else summed now.  Then the next
-// level's (it needs u^0..u^j, all final now) is queued on the side stream,
-// after everything the main stream has queued, including the right-hand side
-// that last read the buffer it will overwrite.
+// P_j ready for the right-hand side of level j: the block's sums (waited for
+// if the side stream summed them, else summed now from u^0..u^{b-1}, which
+// are final), then the catch-up of a level past the block's first.
 int history_for(tsfcde_plan_s *pl, int64_t j) {
-    if (pl->hist_pending >= 0)  // whatever the side stream queued is finished before the buffers are used
-        HIPCHK(hipStreamWaitEvent(pl->stream, pl->ev_hist[pl->hist_pending & 1], 0));
-    if (j >= 1 && pl->hist_pending != j) HIPCHK(launch_history(pl, pl->stream, j));
-    pl->hist_pending = -1;
-    if (j + 1 < pl->M) {
-        if (!pl->hs) {
-            HIPCHK(hipStreamCreateWithFlags(&pl->hs, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&pl->ev_main, hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&pl->ev_hist[0], hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&pl->ev_hist[1], hipEventDisableTiming));
-        }
-        HIPCHK(hipEventRecord(pl->ev_main, pl->stream));
-        HIPCHK(hipStreamWaitEvent(pl->hs, pl->ev_main, 0));
-        HIPCHK(launch_history(pl, pl->hs, j + 1));
-        HIPCHK(hipEventRecord(pl->ev_hist[(j + 1) & 1], pl->hs));
-        pl->hist_pending = j + 1;
+    if (j < 1) return TSFCDE_OK;
+    const int64_t b = hist_block_of(j);
+    if (pl->hist_pending) {  // whatever the side stream queued is finished before the buffers are used
+        HIPCHK(hipStreamWaitEvent(pl->stream, pl->ev_hist, 0));
+        pl->hist_pending = false;
     }
+    if (pl->hist_block != b) {
+        HIPCHK(launch_sweep(pl, pl->stream, b));
+        pl->hist_block = b;
+    }
+    if (j > b) HIPCHK(launch_catch(pl, j));
+    return TSFCDE_OK;
+}
+
+// After the right-hand side of level j is queued: when level j + 1 starts a
+// block, its sweep (u^0..u^j, all final) goes to the side stream, behind
+// everything the main stream has queued, including the right-hand side and
+// catch-up that last read the block buffers it overwrites.
+int history_next(tsfcde_plan_s *pl, int64_t j) {
+    const int64_t b = j + 1;
+    if (b >= pl->M || hist_block_of(b) != b || pl->hist_block == b) return TSFCDE_OK;
+    if (!pl->hs) {
+        HIPCHK(hipStreamCreateWithFlags(&pl->hs, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&pl->ev_main, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&pl->ev_hist, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(pl->ev_main, pl->stream));
+    HIPCHK(hipStreamWaitEvent(pl->hs, pl->ev_main, 0));
+    HIPCHK(launch_sweep(pl, pl->hs, b));
+    HIPCHK(hipEventRecord(pl->ev_hist, pl->hs));
+    pl->hist_block = b;
+    pl->hist_pending = true;
     return TSFCDE_OK;
 }
 
@@ -859,13 +902,14 @@ int level_rhs(tsfcde_plan_s *pl, int64_t j, const double *d_f, double *x, int wa
     }
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
     InReal in{pl->U + (size_t)j * ld, n, pl->A.C};
-    OutRhs out{pl->U + (size_t)j * ld, hbuf(pl, j), d_f, pl->g, pl->r, pl->rt, x, n, pl->A.C,
+    OutRhs out{pl->U + (size_t)j * ld, j >= 1 ? hist_src(pl, j) : nullptr, d_f, pl->g, pl->r, pl->rt, x, n,
+               pl->A.C,
                pl->eta[j] / pl->sigma - (j >= 1 ? hist_c1(pl, j) : 0.0), (1.0 - pl->sigma) / pl->sigma, warm,
                j >= 1 ? 1 : 0,
                j >= 2 ? pl->U + (size_t)(j - 1) * ld : nullptr, j >= 2 ? pl->U + (size_t)(j - 2) * ld : nullptr};
     out = with_red(out, pl, 2);
     HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
-    return TSFCDE_OK;
+    return history_next(pl, j);
 }
 
 int status_code(int st) {
@@ -1277,9 +1321,10 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
     const Layout &L = pl->lay;
     pl->U = reinterpret_cast<double *>(ws + L.off_U);
     double *vec = reinterpret_cast<double *>(ws + L.off_vec);
-    double **vp[NVEC] = {&pl->H, &pl->g, &pl->r, &pl->rt, &pl->u, &pl->p, &pl->q, &pl->phat, &pl->vhat, &pl->uhat,
-                         &pl->fbuf, &pl->H2};
-    for (int k = 0; k < NVEC; ++k) *vp[k] = vec + (size_t)k * pl->ldn;
+    double **vp[11] = {&pl->H, &pl->g, &pl->r, &pl->rt, &pl->u, &pl->p, &pl->q, &pl->phat, &pl->vhat, &pl->uhat,
+                       &pl->fbuf};
+    for (int k = 0; k < 11; ++k) *vp[k] = vec + (size_t)k * pl->ldn;
+    pl->Hq = vec + (size_t)11 * pl->ldn;
     pl->tmp = reinterpret_cast<double *>(ws + L.off_tmp);
     pl->w = reinterpret_cast<double *>(ws + L.off_w);
     pl->g0 = reinterpret_cast<double *>(ws + L.off_g0);
@@ -1511,10 +1556,12 @@ int64_t tsfcde_embedding_length(tsfcde_plan_t pl) { return pl ? pl->A.L : -1; }
 int64_t tsfcde_level(tsfcde_plan_t pl) { return pl ? pl->level : -1; }
 
 int tsfcde_profile(tsfcde_plan_t pl, int32_t cls, int32_t enable) {
-    if (!pl || cls < 0 || cls >= NPROF) return TSFCDE_EINVAL;
+    if (!pl || cls < 0 || cls >= NPROF || enable < 0) return TSFCDE_EINVAL;
     HIPCHK(hipStreamSynchronize(pl->stream));
     harvest(pl);
     pl->prof[cls].on = enable != 0;
+    pl->prof[cls].period = enable > 0 ? enable : 1;
+    pl->prof[cls].issued = 0;
     pl->prof[cls].launches = 0;
     pl->prof[cls].ms = 0.0;
     return TSFCDE_OK;
@@ -1526,6 +1573,12 @@ int tsfcde_profile_read(tsfcde_plan_t pl, int32_t cls, int64_t *launches, double
     harvest(pl);
     if (launches) *launches = pl->prof[cls].launches;
     if (ms) *ms = pl->prof[cls].ms;
+    return TSFCDE_OK;
+}
+
+int tsfcde_profile_issued(tsfcde_plan_t pl, int32_t cls, int64_t *issued) {
+    if (!pl || cls < 0 || cls >= NPROF || !issued) return TSFCDE_EINVAL;
+    *issued = pl->prof[cls].issued;
     return TSFCDE_OK;
 }
 
@@ -1663,7 +1716,7 @@ int tsfcde_destroy(tsfcde_plan_t pl) {
     (void)history_quiesce(pl);
     harvest(pl);
     if (pl->hs) (void)hipStreamDestroy(pl->hs);
-    for (hipEvent_t e : {pl->ev_main, pl->ev_hist[0], pl->ev_hist[1]})
+    for (hipEvent_t e : {pl->ev_main, pl->ev_hist})
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : pl->event_pool) (void)hipEventDestroy(e);
     if (pl->h_sc) (void)hipHostFree(pl->h_sc);
@@ -1876,7 +1929,7 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
         InSpec isA = in_spec(pl, pl->A);
         // right-hand side through A u^j
         rhsA.push_back(cdesc(pl, C, InReal{pl->U + (size_t)j * ld, n, C}, osA));
-        OutRhs orhs{pl->U + (size_t)j * ld, pl->H, f, pl->g, pl->r, pl->rt, x, n, C,
+        OutRhs orhs{pl->U + (size_t)j * ld, j >= 1 ? hist_src(pl, j) : nullptr, f, pl->g, pl->r, pl->rt, x, n, C,
                     pl->eta[j] / pl->sigma - (j >= 1 ? hist_c1(pl, j) : 0.0), (1.0 - pl->sigma) / pl->sigma, warm,
                     j >= 1 ? 1 : 0,
                     j >= 2 ? pl->U + (size_t)(j - 1) * ld : nullptr, j >= 2 ? pl->U + (size_t)(j - 2) * ld : nullptr};
@@ -1963,27 +2016,55 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
     const int warm = bt->warm == TSFCDE_WS_PREV ? 1 : (bt->warm == TSFCDE_WS_EXTRAP ? (j >= 2 ? 2 : (j >= 1)) : 0);
     // descriptors of the level
     bt->st.used = 0;
-    std::vector<HistDesc> hist;
+    // history: the block's sweep for members whose block sums are not those of
+    // block b (on the batch stream: the same sums as the single-instance
+    // path), then the catch-up of a level past the block's first
+    std::vector<HistDesc> hsweep, hcatch;
     std::vector<PcDesc> pc;
     int64_t nmax = 0, Lmax = 0;
+    const int64_t hb0 = j >= 1 ? hist_block_of(j) : 0;
     for (tsfcde_plan_s *pl : bt->plans) {
-        hist.push_back(HistDesc{pl->U, pl->n, pl->ldn, pl->cb, j >= 1 ? pl->clast[j] : 0.0, pl->kappa, pl->H, (int)j});
+        if (j >= 1) {
+            if (pl->hist_pending) {
+                if (int rc = history_quiesce(pl)) return rc;
+            }
+            HistDesc d{pl->U, pl->n, pl->ldn, pl->cb, hist_block_params(pl, hb0), (int)j, pl->clast[j],
+                       j == 1 ? pl->clast[1] : pl->cbase[1], pl->kappa, nullptr, nullptr};
+            if (pl->hist_block != hb0) {
+                d.out = pl->Hq;
+                hsweep.push_back(d);
+                pl->hist_block = hb0;
+            }
+            if (j > hb0) {
+                d.QL = pl->Hq + (size_t)(j - hb0) * pl->ldn;
+                d.out = pl->H;
+                hcatch.push_back(d);
+            }
+        }
         pc.push_back(PcDesc{pl->Ls, pl->wv, pl->Wt, pl->tmp, pl->n, pl->A.L, symbol(pl, j, -pl->sigma, pl->A, false)});
         nmax = std::max(nmax, pl->n);
         Lmax = std::max(Lmax, pl->A.L);
     }
-    HistDesc *dh = bt->st.put(hist);
+    HistDesc *dhs = hsweep.empty() ? nullptr : bt->st.put(hsweep);
+    HistDesc *dhc = hcatch.empty() ? nullptr : bt->st.put(hcatch);
     PcDesc *dpc = bt->st.put(pc);
     std::vector<GroupDesc> gd(bt->groups.size());
     for (size_t g = 0; g < bt->groups.size(); ++g)
         if (!stage_group(bt, bt->groups[g], j, fptr.data(), warm, gd[g])) return TSFCDE_ENOMEM;
-    if (!dh || !dpc || bt->st.used > bt->st.cap) return TSFCDE_ENOMEM;
+    if ((!hsweep.empty() && !dhs) || (!hcatch.empty() && !dhc) || !dpc || bt->st.used > bt->st.cap)
+        return TSFCDE_ENOMEM;
     BCHK(hipMemcpyAsync(bt->st.dev, bt->st.host, bt->st.used, hipMemcpyHostToDevice, bt->stream));
     // history sums, right-hand sides, initial guesses
     if (j >= 1) {
         const unsigned gx = (unsigned)std::min<int64_t>(1024, ((nmax + 1) / 2 + 255) / 256);
-        hipLaunchKernelGGL(k_history_b, dim3(gx, cnt), dim3(256), 0, bt->stream, dh);
-        BCHK(hipGetLastError());
+        if (!hsweep.empty()) {
+            hipLaunchKernelGGL(k_hist_sweep_b, dim3(gx, (unsigned)hsweep.size()), dim3(256), 0, bt->stream, dhs);
+            BCHK(hipGetLastError());
+        }
+        if (!hcatch.empty()) {
+            hipLaunchKernelGGL(k_hist_catch_b, dim3(gx, (unsigned)hcatch.size()), dim3(256), 0, bt->stream, dhc);
+            BCHK(hipGetLastError());
+        }
     }
     for (size_t g = 0; g < bt->groups.size(); ++g) {
         const BatchGroup &G = bt->groups[g];
@@ -2171,7 +2252,7 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
         bt->plans.push_back(pl);
         off += al(b);
     }
-    bt->st.cap = (size_t)count * 8192 + (1 << 20);
+    bt->st.cap = (size_t)count * 12288 + (1 << 20);
     bt->st.dev = ws + off;
     off += al(bt->st.cap);
     bt->d_scs = reinterpret_cast<DevScalars **>(ws + off);

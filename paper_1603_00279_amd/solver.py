@@ -159,8 +159,17 @@ class TimeLevelSolver:
         N.check(self._lib.tsfcde_spectrum(self._plan, which, _dptr(out)), "tsfcde_spectrum")
         return torch.view_as_complex(out.view(cnt, 2))
 
-    def profile(self, kernel_class: int, enable: bool = True):
-        N.check(self._lib.tsfcde_profile(self._plan, kernel_class, int(enable)), "tsfcde_profile")
+    def profile(self, kernel_class: int, enable: bool = True, period: int = 1):
+        """Start (enable) or stop recording one kernel class; events ride on
+        every ``period``-th launch of the class."""
+        if period < 1:
+            raise ValueError("period must be >= 1")
+        N.check(self._lib.tsfcde_profile(self._plan, kernel_class, period if enable else 0), "tsfcde_profile")
+
+    def profile_issued(self, kernel_class: int) -> int:
+        cnt = ctypes.c_int64(0)
+        N.check(self._lib.tsfcde_profile_issued(self._plan, kernel_class, ctypes.byref(cnt)), "tsfcde_profile_issued")
+        return cnt.value
 
     def profile_read(self, kernel_class: int):
         cnt = ctypes.c_int64(0)

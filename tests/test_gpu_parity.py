@@ -261,8 +261,9 @@ def test_warm_starts_cut_iterations(n):
     for warm in (1, 2):
         assert relerr(runs[warm][0], U0) < 1e-5
     # u = t^2 P(x): extrapolation is nearly exact, u^j is not much better than 0
+    # (CGS counts move by a few under rounding-level changes of g, hence 5%)
     it0, it1, it2 = (sum(runs[w][1][2:]) for w in (0, 1, 2))
-    assert it2 < it0 and it1 <= it0 + 2, (it0, it1, it2)
+    assert it2 < it0 and it1 <= 1.05 * it0, (it0, it1, it2)
 
 
 # ---------------------------------------------------------------------------
@@ -356,3 +357,28 @@ def test_near_breakdown_level_is_rechecked():
         c1 = np.linalg.cond(O.level_A(prob, j - 1), 1)
         bound = 2 * c1 * st["relres_true"] + 8 * 2.2e-16 * c1
         assert relerr(U[j], Uref[j]) < bound, (j, relerr(U[j], Uref[j]), bound)
+
+
+def test_sampled_profiling_counts_and_leaves_results():
+    """Events on every 3rd launch of the product middle passes: the issued
+    count is every launch of the class, the sampled count is one in three, the
+    durations are positive, and the march is bitwise the unprofiled one."""
+    banner("sampled profiling")
+    prob = W.config_large(n=1024, M=6)
+    F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
+    with make(prob) as s:
+        s.solve(F)
+        U0 = host(s.history())
+    with make(prob) as s:
+        with pytest.raises(ValueError):
+            s.profile(2, True, 0)
+        s.profile(2, True, 3)
+        _, stats = s.solve(F)
+        launches, ms = s.profile_read(2)
+        issued = s.profile_issued(2)
+        s.profile(2, False)
+        U1 = host(s.history())
+    iters = sum(st["iters"] for st in stats)
+    assert issued >= 2 * iters + prob.M  # two products per iteration, one per right-hand side
+    assert launches == (issued + 2) // 3 and ms > 0.0
+    assert np.array_equal(U0, U1)
