@@ -13,7 +13,9 @@
 // frequency order).
 //
 // Twiddles come from a table tw_P[m] = exp(-2 pi i m / P) (FP64, built on the
-// device at plan time); the inverse transform uses conjugates.  Butterfly
+// device at plan time) for the power-of-two multiples of a butterfly's base
+// angle, and as products of two of those for the rest; the inverse transform
+// uses conjugates.  Butterfly
 // constants are exact algebraic values of cos/sin(2 pi k/16).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -112,11 +114,22 @@ __device__ __forceinline__ void stage_bfly(double2 (&v)[E], int j, const double2
             const int bf = j + T * q;
             const int k = bf & (NS - 1);
             constexpr int STRIDE = P / (NS * RAD);
+            // w^r for the power-of-two r from the table, the others as
+            // products of two of those (w^3 = w^2 w, w^5 = w^4 w, ...): fewer
+            // table reads for about one more rounding per derived twiddle
+            double2 w[RAD];
+#pragma unroll
+            for (int r = 1; r < RAD; r *= 2) w[r] = twP[r * k * (STRIDE * TS)];
+#pragma unroll
+            for (int r = 3; r < RAD; ++r) {
+                const int hb = 1 << (31 - __builtin_clz(r));
+                if (hb != r) w[r] = cmul(w[hb], w[r - hb]);
+            }
 #pragma unroll
             for (int r = 1; r < RAD; ++r) {
-                double2 w = twP[r * k * (STRIDE * TS)];
-                if (DIR > 0) w.y = -w.y;
-                a[r] = cmul(a[r], w);
+                double2 wr = w[r];
+                if (DIR > 0) wr.y = -wr.y;
+                a[r] = cmul(a[r], wr);
             }
         }
         Dft<RAD, DIR>::run(a);
