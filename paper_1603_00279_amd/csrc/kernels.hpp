@@ -39,10 +39,8 @@ enum : int { ST_OK = 0, ST_BREAKDOWN = 1, ST_NONFINITE = 2 };
 // Predication of a launch on the device scalars: pred 0 always runs, pred 1
 // skips once the solve is done, pred 2 skips when the last restart found its
 // guess better than the right-hand side's (a second restart is then moot).
-// The scalars were written by the previous kernel, so reading them misses the
-// caches; kernels test the predicate after issuing their own loads (all in
-// bounds whatever the outcome) and before their first barrier or store, so the
-// two latencies overlap.  The test is uniform over the workgroup.
+// Kernels test it before their first load: a skipped workgroup (a converged
+// level, or a converged instance of a batch) then costs almost nothing.
 __device__ __forceinline__ bool skip(int pred, const DevScalars *sc) {
     return (pred == 1 && sc->done) || (pred == 2 && sc->better);
 }
@@ -202,11 +200,11 @@ template <class S> struct InCgsUPT {
     __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
         int64_t i = 2 * (row * C + col);
         if (i >= nr) return;
-        // q and p are loaded even on a fresh start (their values are then
-        // unused): the loads need not wait for the flag
         raw[0] = ld2(r, i, nr);
-        raw[1] = ld2(q, i, nr);
-        raw[2] = ld2(p, i, nr);
+        if (!first) {
+            raw[1] = ld2(q, i, nr);
+            raw[2] = ld2(p, i, nr);
+        }
     }
     __device__ __forceinline__ double2 finish(int row, int64_t col, const double2 *raw) const {
         int64_t i = 2 * (row * C + col);
@@ -692,6 +690,7 @@ template <class Out, int NP> struct ColSink {
 template <int R, int EMAX, int DIR, class In, class Out>
 __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double2 *__restrict__ tw_all, DevScalars *sc,
                                          int pred) {
+    if (skip(pred, sc)) return;
     using G = ColGeo<R, EMAX>;
     constexpr int E = G::E, T = G::T, B = G::B;
     __shared__ double2 lds[lpad_size(R) * B];
@@ -716,7 +715,6 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
         for (int m = 0; m < E; ++m)
             if (active) out.fetch(LastStage<R, E>::pos(j, m), c, pre[m]);
     }
-    if (skip(pred, sc)) return;
     double2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = active ? in.finish(j + T * m, c, raw[m]) : make_double2(0.0, 0.0);
@@ -737,10 +735,10 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
 // Finishing kernel of a reducing pass (one workgroup of the pass's size NT).
 template <int NT, class Out>
 __global__ void __launch_bounds__(NT) k_final(Out out, int nparts, DevScalars *sc, int pred) {
-    const bool sk = skip(pred, sc);
+    if (skip(pred, sc)) return;
     double tot[Out::NACC];
     reduce_partials<Out::NACC>(out.partials, nparts, tot);
-    if (!sk && threadIdx.x == 0) out.final(tot, sc);
+    if (threadIdx.x == 0) out.final(tot, sc);
 }
 
 template <int R, int EMAX, int DIR, class In, class Out>
@@ -770,10 +768,10 @@ __global__ void __launch_bounds__((ColGeo<R, EMAX>::NT)) k_col_b(const ColDesc<I
 template <int NT, class In, class Out>
 __global__ void __launch_bounds__(NT) k_final_b(const ColDesc<In, Out> *__restrict__ d, int nparts, int pred) {
     const ColDesc<In, Out> &D = d[blockIdx.y];
-    const bool sk = skip(pred, D.sc);
+    if (skip(pred, D.sc)) return;
     double tot[Out::NACC];
     reduce_partials<Out::NACC>(D.out.partials, nparts, tot);
-    if (!sk && threadIdx.x == 0) D.out.final(tot, D.sc);
+    if (threadIdx.x == 0) D.out.final(tot, D.sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -831,6 +829,7 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
                                                                 CS *__restrict__ bufA, Tw2 twA, Op op,
                                                                 const double2 *__restrict__ tw_all, DevScalars *sc,
                                                                 int pred) {
+    if (skip(pred, sc)) return;
     using G = FuseGeo<RP, EMAX>;
     constexpr int RA = G::RA, EA = G::EA, TA = G::TA, B = G::B, EP = G::EP, TP = G::TP;
     __shared__ double2 lds[lpad_size(RA) * B];
@@ -864,7 +863,6 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
 #pragma unroll
     for (int m = 0; m < EA; ++m)
         if (colok) twA.fetch(2 * (int64_t)LastStage<RA, EA>::pos(j, m) * c, twa[m]);
-    if (skip(pred, sc)) return;
     double2 vp[EP];
 #pragma unroll
     for (int m = 0; m < EP; ++m)
@@ -948,6 +946,7 @@ using RowSink = RowSinkT<double2>;
 template <int C_, int EMAX, int MODE, class CS>
 __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, double2 *spec_out, Tw2 twL,
                                          SymParams sp, const double2 *__restrict__ tw_all, DevScalars *sc, int pred) {
+    if (skip(pred, sc)) return;
     using G = MidGeo<C_, EMAX>;
     constexpr int E = G::E, T = G::T, LS = G::LS;
     constexpr int64_t C = C_;
@@ -985,7 +984,6 @@ __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, doubl
             }
         }
     }
-    if (skip(pred, sc)) return;
     LdsSink lsink{slab, 1};
     if constexpr (TWL) {
         stage_twiddles<C_>(twl, tw_all, t, G::NT);

@@ -2201,6 +2201,10 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
 
 extern "C" {
 
+// Bytes of the per-level descriptor staging area of a batch of `count`
+// instances (the workspace size and the layout both use this).
+size_t batch_staging_bytes(int32_t count) { return (size_t)count * 12288 + (1 << 20); }
+
 int tsfcde_batch_workspace_bytes(const tsfcde_problem *probs, int32_t count, size_t *bytes) {
     if (!probs || count < 1 || !bytes) return TSFCDE_EINVAL;
     size_t tot = 0;
@@ -2213,7 +2217,7 @@ int tsfcde_batch_workspace_bytes(const tsfcde_problem *probs, int32_t count, siz
         tot += al(b);
     }
     // descriptors (per level), scalar pointers, gathered states
-    tot += al((size_t)count * 8192 + (1 << 20)) + al(sizeof(void *) * count) + al(sizeof(DoneRec) * count);
+    tot += al(batch_staging_bytes(count)) + al(sizeof(void *) * count) + al(sizeof(DoneRec) * count);
     *bytes = tot;
     return TSFCDE_OK;
 }
@@ -2252,12 +2256,14 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
         bt->plans.push_back(pl);
         off += al(b);
     }
-    bt->st.cap = (size_t)count * 12288 + (1 << 20);
+    bt->st.cap = batch_staging_bytes(count);
     bt->st.dev = ws + off;
     off += al(bt->st.cap);
     bt->d_scs = reinterpret_cast<DevScalars **>(ws + off);
     off += al(sizeof(void *) * count);
     bt->d_done = reinterpret_cast<DoneRec *>(ws + off);
+    off += al(sizeof(DoneRec) * count);
+    if (off > need) return fail(TSFCDE_EINVAL);  // the layout outgrew tsfcde_batch_workspace_bytes
     if (hipHostMalloc(reinterpret_cast<void **>(&bt->st.host), bt->st.cap) != hipSuccess) return fail(TSFCDE_EDEVICE);
     if (hipHostMalloc(reinterpret_cast<void **>(&bt->h_done), sizeof(DoneRec) * count) != hipSuccess)
         return fail(TSFCDE_EDEVICE);
