@@ -51,7 +51,7 @@ __all__ = [
     "l21s_kappa", "eta", "matrix_Q", "toeplitz_W", "level_scalars", "level_L", "level_A",
     "level_B", "history_term", "rhs", "level_solve", "march", "error_norms",
     "strang_column", "circulant", "preconditioner_matrix", "circulant_eigenvalues",
-    "embedding_column", "apply_A_rows", "rhs_rows", "caputo_l21s",
+    "embedding_column", "apply_A_rows", "apply_P_rows", "rhs_rows", "caputo_l21s",
 ]
 
 
@@ -338,6 +338,26 @@ def apply_A_rows(prob, j: int, u: np.ndarray, rows: np.ndarray, which: str = "A"
         wtu = float(np.dot(w[lo - i + 1:n - i + 1], u[lo:n]))
         Lu = gam / (2.0 * h) * qu + dp / h ** beta * wu + dm / h ** beta * wtu
         out[r] = e * u[i] - sigma * Lu if which == "A" else e * u[i] + (1.0 - sigma) * Lu
+    return out
+
+
+def apply_P_rows(prob, j: int, y: np.ndarray, rows: np.ndarray) -> np.ndarray:
+    """(P^(j+sigma) y)_i of the Strang preconditioner (3.7) for the given
+    0-based rows: a circulant with first column c acts as
+    (C y)_i = sum_k c_{(i-k) mod n} y_k, its transpose with c_{(k-i) mod n}."""
+    e, gam, dp, dm = level_scalars(prob, j)
+    n, h, beta, sigma = prob.n, prob.h, prob.beta, prob.sigma
+    cQ = strang_column(_Q_lag, n)
+    cW = strang_column(_W_lag(beta, n), n)
+    k = np.arange(n)
+    out = np.empty(len(rows))
+    for r, i in enumerate(rows):
+        i = int(i)
+        fwd = (i - k) % n
+        bwd = (k - i) % n
+        Ly = (gam / (2.0 * h) * float(np.dot(cQ[fwd], y)) + dp / h ** beta * float(np.dot(cW[fwd], y))
+              + dm / h ** beta * float(np.dot(cW[bwd], y)))
+        out[r] = e * y[i] - sigma * Ly
     return out
 
 

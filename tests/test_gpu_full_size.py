@@ -1,0 +1,147 @@
+"""GPU parity at the full size of the headline march, n = 2^20 (product
+transform 1024 x 1024, preconditioner transform 512 x 1024: the launch
+geometry bench.py times), on outputs the oracle evaluates one by one, and
+size-independent properties of whole levels.
+
+Tolerances are absolute, per sampled row, against the row's scale
+  S = (eta + sigma (|gamma|/h + (d+ + d-) h^-beta sum|omega|)) * max|x|,
+an upper bound of sum_k |A_ik x_k|.  An FFT product of length L in FP64
+carries errors of order eps * log2(L) * S (about 5e-15 S here); the bar is
+1e-12 S.  A misplaced twiddle or permutation gives errors of order S.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_util import banner, host, need_gpu, t64
+
+pytestmark = pytest.mark.gpu
+
+N_FULL = 1 << 20
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    import paper_1603_00279_amd as P  # noqa: F401  (fails loudly if the library is missing)
+    P.lib()
+
+
+def make(prob, **kw):
+    import paper_1603_00279_amd as P
+    return P.TimeLevelSolver.from_problem(prob, **kw)
+
+
+def sample_rows(n, seed, k=48):
+    """Both ends, the tile and row boundaries of a 1024-wide transform, the
+    middle, and k random rows."""
+    fixed = [0, 1, 2, 511, 512, 1023, 1024, 1025, 2047, n // 2 - 1, n // 2, n // 2 + 1, n - 1025, n - 2, n - 1]
+    rnd = np.random.default_rng(seed).integers(0, n, size=k)
+    return np.unique(np.concatenate([fixed, rnd]))
+
+
+def row_scale(prob, j, x):
+    e, gam, dp, dm = O.level_scalars(prob, j)
+    wsum = float(np.sum(np.abs(O.wsgd_weights(prob.beta, prob.n + 1))))
+    return (abs(e) + prob.sigma * (abs(gam) / prob.h + (dp + dm) * prob.h ** (-prob.beta) * wsum)) * float(
+        np.max(np.abs(x)))
+
+
+def test_spectra_full_size():
+    """Both stored spectra against the library FFT of the oracle's columns
+    (every frequency)."""
+    import paper_1603_00279_amd as P
+    banner("spectra n=2^20")
+    prob = W.config_large(n=N_FULL, M=4)
+    with make(prob) as s:
+        L = s.embedding_length
+        emb = host(s.spectrum(P.TSFCDE_SPEC_EMBED))
+        strang = host(s.spectrum(P.TSFCDE_SPEC_STRANG))
+    n, beta = prob.n, prob.beta
+    ref_emb = np.fft.fft(O.embedding_column(beta, n, L))[: L // 2 + 1]
+    w = O.wsgd_weights(beta, n + 1)
+    col = O.strang_column(lambda m: w[m + 1] if m >= -1 else 0.0, n)
+    ref_str = O.circulant_eigenvalues(col)[: n // 2 + 1]
+    assert np.max(np.abs(emb - ref_emb)) <= 1e-13 * np.max(np.abs(ref_emb))
+    assert np.max(np.abs(strang - ref_str)) <= 1e-13 * np.max(np.abs(ref_str))
+
+
+def test_products_full_size():
+    import paper_1603_00279_amd as P
+    banner("apply A/B n=2^20")
+    prob = W.config_large(n=N_FULL, M=8)
+    rng = np.random.default_rng(20)
+    x = rng.standard_normal(prob.n)
+    rows = sample_rows(prob.n, 1)
+    with make(prob) as s:
+        for j in (0, 5):
+            yA = host(s.apply(P.TSFCDE_OP_A, j, t64(x)))
+            yB = host(s.apply(P.TSFCDE_OP_B, j, t64(x)))
+            S = row_scale(prob, j, x)
+            dA = np.abs(yA[rows] - O.apply_A_rows(prob, j, x, rows, "A"))
+            dB = np.abs(yB[rows] - O.apply_A_rows(prob, j, x, rows, "B"))
+            assert dA.max() <= 1e-12 * S, (j, dA.max() / S)
+            assert dB.max() <= 1e-12 * S, (j, dB.max() / S)
+
+
+def test_preconditioner_solve_full_size():
+    """y = P^-1 x through the FFT solve; the oracle's rows of P y give back x
+    (a backward-error check, which does not depend on cond(P))."""
+    import paper_1603_00279_amd as P
+    banner("apply Pinv n=2^20")
+    prob = W.config_large(n=N_FULL, M=8)
+    x = np.random.default_rng(21).standard_normal(prob.n)
+    rows = sample_rows(prob.n, 2, k=24)
+    with make(prob) as s:
+        for j in (0, 7):
+            y = host(s.apply(P.TSFCDE_OP_PINV, j, t64(x)))
+            d = np.abs(O.apply_P_rows(prob, j, y, rows) - x[rows])
+            assert d.max() <= 1e-12 * row_scale(prob, j, y), (j, d.max() / row_scale(prob, j, y))
+
+
+@pytest.mark.parametrize("j", [1, 3, 9])
+def test_rhs_full_size(j):
+    """Right-hand side with a random stored history: level 1 and 9 start a
+    history block (one sweep), level 3 adds a catch-up to its block's sum."""
+    banner(f"rhs n=2^20 j={j}")
+    prob = W.config_large(n=N_FULL, M=12, alpha=0.4)
+    rng = np.random.default_rng(100 + j)
+    U = rng.standard_normal((j + 1, prob.n))
+    f = rng.standard_normal(prob.n)
+    rows = sample_rows(prob.n, 3 + j)
+    with make(prob) as s:
+        s.set_state(j, t64(U))
+        g = host(s.rhs(j, t64(f)))
+    ref = O.rhs_rows(prob, U, j, f, rows)
+    # history: kappa sum_s |c_{j-s}| |u^{s+1} - u^s| <= kappa * sum|c| * 2 max|U|
+    c = O.l21s_c(prob.alpha, j)
+    hist = O.l21s_kappa(prob.alpha, prob.tau) * float(np.sum(np.abs(c))) * 2.0 * float(np.max(np.abs(U)))
+    S = row_scale(prob, j, U[j]) + hist + float(np.max(np.abs(f)))
+    d = np.abs(g[rows] - ref)
+    assert d.max() <= 1e-12 * S, d.max() / S
+
+
+def test_levels_full_size():
+    """The first four levels of the headline march (n = 2^20, M = 512) with
+    the true-residual check.  A level is accepted when its true relative
+    residual is within the Krylov tolerance or, where FP64 cannot reach that
+    (an FFT product carries errors of order eps |A| |x|, and |A| ~ h^-beta ~
+    1e11 here), when its normwise backward error is at most 1e-13.  The
+    oracle's rows of g - A u^{j+1} must then be rounding-sized against the
+    row scale S (a componentwise backward-error check)."""
+    import paper_1603_00279_amd as P
+    banner("levels n=2^20 M=512")
+    prob = W.config_large(n=N_FULL, M=512)
+    rows = sample_rows(prob.n, 5)
+    F = [prob.source_level(j) for j in range(4)]
+    with make(prob, rtol=1e-10, flags=P.TSFCDE_FLAG_VERIFY) as s:
+        stats = [s.step(t64(F[j])) for j in range(4)]
+        U = host(s.history()[:5])
+    for j in range(4):
+        st = stats[j]
+        assert st["code"] == P.TSFCDE_OK and st["iters"] > 0, st
+        assert st["relres_true"] <= 1e-10 or 0.0 <= st["backward_err"] <= 1e-13, st
+        r = O.rhs_rows(prob, U, j, F[j], rows) - O.apply_A_rows(prob, j, U[j + 1], rows, "A")
+        S = row_scale(prob, j, U[j + 1])
+        assert np.abs(r).max() <= 1e-12 * S, (j, np.abs(r).max() / S)

@@ -178,6 +178,19 @@ def test_rowwise_matches_dense():
         assert np.allclose(O.rhs_rows(prob, U, j, f, rows), O.rhs(prob, U, j, f), rtol=1e-13, atol=1e-10)
 
 
+@pytest.mark.parametrize("n", [57, 64])
+def test_preconditioner_rows_match_dense(n):
+    """Row-by-row P y (circulant and transposed circulant by index arithmetic)
+    against the dense Strang preconditioner, odd and even n (the even Strang
+    column takes lag n/2 from the lower triangle)."""
+    prob = W.config_large(n=n, M=6, beta=1.4)
+    y = np.random.default_rng(n).standard_normal(n)
+    rows = np.arange(n)
+    for j in (0, 3):
+        ref = O.preconditioner_matrix(prob, j) @ y
+        assert np.allclose(O.apply_P_rows(prob, j, y, rows), ref, rtol=1e-13, atol=1e-10)
+
+
 def test_history_enters_with_minus_sign():
     # (3.1): the history sum is subtracted.  With the opposite sign the scheme
     # stops converging; the manufactured error grows by orders of magnitude.
