@@ -958,7 +958,10 @@ __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, doubl
     const int64_t ra = wg == 0 ? 0 : wg;
     const int64_t rb = wg == 0 ? R / 2 : R - wg;
     const int t = threadIdx.x;
-    const int sel = t / T, j = t % T;
+    // rows of 2 * 8^k run their last (radix-2) stage on registers, with the
+    // row's logical lanes placed so that partners share a row of 16 lanes
+    constexpr bool PAIR = Paired<C_, E>::OK;
+    const int sel = t / T, j = PAIR ? paired_lane<T>(t % T) : t % T;
     const bool active = sel < 2;
     const int64_t row = sel == 0 ? ra : rb;
     double2 *slab = lds + (sel < 2 ? sel : 0) * LS;
@@ -987,9 +990,9 @@ __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, doubl
     LdsSink lsink{slab, 1};
     if constexpr (TWL) {
         stage_twiddles<C_>(twl, tw_all, t, G::NT);
-        fft_t<C_, E, -1, 1>(v, j, active, twl, slab, 1, lsink);
+        fft_t<C_, E, -1, 1, LdsSink, PAIR>(v, j, active, twl, slab, 1, lsink);
     } else {
-        fft<C_, E, -1>(v, j, active, tw_all, slab, 1, lsink);
+        fft<C_, E, -1, LdsSink, PAIR>(v, j, active, tw_all, slab, 1, lsink);
     }
     __syncthreads();
     double2 *s0 = lds, *s1 = lds + LS;
@@ -1076,9 +1079,9 @@ __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, doubl
     __syncthreads();
     RowSinkT<CS> rsink{Y, row * C};
     if constexpr (TWL) {
-        fft_t<C_, E, 1, 1>(v, j, active, twl, slab, 1, rsink);
+        fft_t<C_, E, 1, 1, RowSinkT<CS>, PAIR>(v, j, active, twl, slab, 1, rsink);
     } else {
-        fft<C_, E, 1>(v, j, active, tw_all, slab, 1, rsink);
+        fft<C_, E, 1, RowSinkT<CS>, PAIR>(v, j, active, tw_all, slab, 1, rsink);
     }
 }
 
