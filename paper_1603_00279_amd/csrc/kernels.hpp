@@ -32,6 +32,10 @@ struct DevScalars {
     int iter, done, status, fresh;  // fresh: next CGS iteration starts from r (u = p = r)
     int better;   // the last restart's |g - A x|^2 was below r0sq
     int netkept;  // the learned guess was kept at this level (set by k_keep_better)
+    // rho of the iterations of a chunk whose finishing steps are folded into
+    // the next pass (see InCgsUPT::fold): rho_i sits in rho2[i & 1] for i >= 1
+    // (rho_0 in rho), so a pass never reads the slot it writes
+    double rho2[2];
 };
 
 enum : int { ST_OK = 0, ST_BREAKDOWN = 1, ST_NONFINITE = 2 };
@@ -44,6 +48,14 @@ enum : int { ST_OK = 0, ST_BREAKDOWN = 1, ST_NONFINITE = 2 };
 __device__ __forceinline__ bool skip(int pred, const DevScalars *sc) {
     return (pred == 1 && sc->done) || (pred == 2 && sc->better);
 }
+
+// Loaders that can fold the previous pass's finishing step (see InCgsUPT).
+template <class T, class = void> struct HasFold {
+    static constexpr bool value = false;
+};
+template <class T> struct HasFold<T, decltype(void(static_cast<T *>(nullptr)->fold(static_cast<DevScalars *>(nullptr))))> {
+    static constexpr bool value = true;
+};
 
 // Symbol of one level: S(k) = s0 + cre*Re(L_k) + i*(cim*Im(L_k) + cq*sin(2 pi k / L)),
 // where L_k is the stored spectrum of W_beta (embedding or Strang).  For a
@@ -85,8 +97,8 @@ __device__ __forceinline__ void block_partial(double (&acc)[NACC], double *parti
     }
 }
 
-// Sum of nparts partials (every thread of the workgroup takes part; the
-// result is valid in thread 0).
+// Sum of nparts partials (every thread of the workgroup takes part, and every
+// thread gets the same totals).
 template <int NACC>
 __device__ __forceinline__ void reduce_partials(const double *partials, int nparts, double (&tot)[NACC]) {
     __shared__ double red[NACC][16];
@@ -192,9 +204,49 @@ template <class S> struct InCgsUPT {
     int64_t nr, C;
     double beta;
     bool first;
+    // Folded finishing step of the previous iteration's last pass (fpart set):
+    // its partials (|r|^2, rt.r) summed here, in the order and with the thread
+    // count of k_final, so the result is bitwise the same.  ci >= 1 is the
+    // iteration's index in its chunk.
+    const double *fpart = nullptr;
+    int fnparts = 0, ci = 0;
     __device__ void prep(const DevScalars *sc) {
-        first = sc->fresh != 0;
+        first = fpart ? false : sc->fresh != 0;
         beta = sc->beta;
+    }
+    // Every thread calls; returns true (uniformly) when the solve is done.
+    // Workgroup 0 stores what OutCgsRT::final stores; rho goes to a parity slot.
+    __device__ bool fold(DevScalars *sc) {
+        if (!fpart) return false;
+        double tot[2];
+        reduce_partials<2>(fpart, fnparts, tot);
+        const double rho_old = ci == 1 ? sc->rho : sc->rho2[(ci - 1) & 1];
+        const double b = tot[1] / rho_old;
+        int status = ST_OK, done = 0;
+        if (!finite(tot[0]) || !finite(tot[1])) {
+            status = ST_NONFINITE;
+            done = 1;
+        } else if (tot[0] <= sc->tol2) {
+            done = 1;
+        } else if (tot[1] == 0.0) {
+            status = ST_BREAKDOWN;
+            done = 1;
+        }
+        if (threadIdx.x == 0 && blockIdx.x == 0) {
+            sc->rnorm2 = tot[0];
+            sc->rho_prev = rho_old;
+            sc->rho2[ci & 1] = tot[1];
+            sc->beta = b;
+            sc->iter += 1;
+            sc->fresh = 0;
+            if (done) {
+                sc->rho = tot[1];  // the state a poll and a restart read
+                sc->done = 1;
+                if (status != ST_OK) sc->status = status;
+            }
+        }
+        beta = b;
+        return done != 0;
     }
     static constexpr int NL = 3;
     __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
@@ -233,7 +285,32 @@ template <class S> struct InCgsQT {
     S *q;
     int64_t nr, C;
     double alpha;
+    // Folded finishing step of the iteration's rt.vhat pass (fpart set; ci is
+    // the iteration's index in its chunk), as in InCgsUPT.
+    const double *fpart = nullptr;
+    int fnparts = 0, ci = 0;
     __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
+    __device__ bool fold(DevScalars *sc) {
+        if (!fpart) return false;
+        double tot[1];
+        reduce_partials<1>(fpart, fnparts, tot);
+        const double rho = ci == 0 ? sc->rho : sc->rho2[ci & 1];
+        const double a = rho / tot[0];
+        int status = ST_OK;
+        if (tot[0] == 0.0) status = ST_BREAKDOWN;
+        else if (!finite(a)) status = ST_NONFINITE;
+        if (threadIdx.x == 0 && blockIdx.x == 0) {
+            sc->rtv = tot[0];
+            sc->alpha = a;
+            if (status != ST_OK) {
+                sc->rho = rho;
+                sc->status = status;
+                sc->done = 1;
+            }
+        }
+        alpha = a;
+        return status != ST_OK;
+    }
     static constexpr int NL = 2;
     __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
         int64_t i = 2 * (row * C + col);
@@ -396,7 +473,7 @@ template <class S> struct OutCgsRT {
     }
     __device__ void final(const double *tot, DevScalars *sc) const {
         sc->rnorm2 = tot[0];
-        sc->rho_prev = sc->rho;
+        sc->rho_prev = ci == 0 ? sc->rho : sc->rho2[ci & 1];
         sc->rho = tot[1];
         sc->beta = tot[1] / sc->rho_prev;
         sc->iter += 1;
@@ -412,6 +489,7 @@ template <class S> struct OutCgsRT {
         }
     }
     double *partials;
+    int ci = 0;  // index in its chunk of the iteration this finishes (0: rho_old is rho)
 };
 using OutCgsR = OutCgsRT<double>;
 
@@ -714,6 +792,11 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
 #pragma unroll
         for (int m = 0; m < E; ++m)
             if (active) out.fetch(LastStage<R, E>::pos(j, m), c, pre[m]);
+    }
+    // a folded finishing step runs while the loads are in flight; the solve
+    // may end there (the decision is the same in every workgroup)
+    if constexpr (HasFold<In>::value) {
+        if (in.fold(sc)) return;
     }
     double2 v[E];
 #pragma unroll

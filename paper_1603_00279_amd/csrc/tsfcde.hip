@@ -530,26 +530,72 @@ void launch_timed(tsfcde_plan_s *pl, int cls, K kernel, dim3 grid, dim3 block, A
     launch_timed_on(pl, pl->stream, cls, kernel, grid, block, args...);
 }
 
+// finish = false leaves a reducing pass's finishing kernel to the caller
+// (a later pass folds it in, or it is launched with launch_final).
 template <int R, int DIR, class In, class Out>
-hipError_t launch_col_t(tsfcde_plan_s *pl, int64_t C, const In &in, const Out &out, int pred) {
+hipError_t launch_col_t(tsfcde_plan_s *pl, int64_t C, const In &in, const Out &out, int pred, bool finish) {
     using G = ColGeo<R, TSF_E_COL>;
     const int64_t grid = (C + G::B - 1) / G::B;
     launch_timed(pl, 1, k_col<R, TSF_E_COL, DIR, In, Out>, dim3((unsigned)grid), dim3(G::NT), C, in, out,
                  (const double2 *)pl->tw_all, pl->sc, pred);
     if constexpr (Out::NACC > 0) {
-        hipLaunchKernelGGL((k_final<G::NT, Out>), dim3(1), dim3(G::NT), 0, pl->stream, out, (int)grid, pl->sc, pred);
+        if (finish)
+            hipLaunchKernelGGL((k_final<G::NT, Out>), dim3(1), dim3(G::NT), 0, pl->stream, out, (int)grid, pl->sc,
+                               pred);
     }
     return hipGetLastError();
 }
 
+// Finishing kernel of a column pass of `rt` launched without its own.
+template <int R, class Out>
+hipError_t launch_final_t(tsfcde_plan_s *pl, int64_t C, const Out &out, int pred) {
+    using G = ColGeo<R, TSF_E_COL>;
+    hipLaunchKernelGGL((k_final<G::NT, Out>), dim3(1), dim3(G::NT), 0, pl->stream, out, (int)((C + G::B - 1) / G::B),
+                       pl->sc, pred);
+    return hipGetLastError();
+}
+
 template <int DIR, class In, class Out>
-hipError_t launch_col(tsfcde_plan_s *pl, const RT &rt, const In &in, const Out &out, int pred) {
+hipError_t launch_col(tsfcde_plan_s *pl, const RT &rt, const In &in, const Out &out, int pred, bool finish = true) {
     switch (rt.R) {
 #define TSF_CASE(P) \
-    case P: return launch_col_t<P, DIR>(pl, rt.C, in, out, pred);
+    case P: return launch_col_t<P, DIR>(pl, rt.C, in, out, pred, finish);
         TSF_SIZES(TSF_CASE)
 #undef TSF_CASE
         default: return hipErrorInvalidValue;
+    }
+}
+
+template <class Out>
+hipError_t launch_final(tsfcde_plan_s *pl, const RT &rt, const Out &out, int pred) {
+    switch (rt.R) {
+#define TSF_CASE(P) \
+    case P: return launch_final_t<P>(pl, rt.C, out, pred);
+        TSF_SIZES(TSF_CASE)
+#undef TSF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Threads per workgroup of a column pass of `rt`.
+int col_nt(const RT &rt) {
+    switch (rt.R) {
+#define TSF_CASE(P) \
+    case P: return ColGeo<P, TSF_E_COL>::NT;
+        TSF_SIZES(TSF_CASE)
+#undef TSF_CASE
+        default: return 0;
+    }
+}
+
+// Workgroups of a column pass of `rt` (the partials its reduction leaves).
+int col_grid(const RT &rt) {
+    switch (rt.R) {
+#define TSF_CASE(P) \
+    case P: return (int)((rt.C + ColGeo<P, TSF_E_COL>::B - 1) / ColGeo<P, TSF_E_COL>::B);
+        TSF_SIZES(TSF_CASE)
+#undef TSF_CASE
+        default: return 0;
     }
 }
 
@@ -752,26 +798,50 @@ Bufs<float, float2> bufs32(tsfcde_plan_s *pl) {
 //  alpha = rho / (rt . vhat)                     [K5 epilogue]
 //  q = u - alpha vhat ; uhat = P^{-1} (u + q)     [K6 prologue, K7]
 //  x += alpha uhat ; r -= alpha A uhat            [K8 (fused), K9, K10], rho' = rt . r
+// One CGS iteration (power-of-two n).  With fold, the finishing steps of the
+// two reducing passes are folded into the passes that follow them: the
+// rt.vhat sum into this iteration's q pass, the residual sums into the next
+// iteration's u,p pass (ci >= 1, its index in the chunk).  The caller then
+// ends the chunk with finish_chunk.
 template <class S, class CS>
-hipError_t cgs_iteration(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x) {
+hipError_t cgs_iteration(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x, int ci = 0, bool fold = false) {
     const int64_t n = pl->n;
     const SymParams sP = symbol(pl, j, -pl->sigma, pl->P, true);
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
     hipError_t e;
     InCgsUPT<S> k1{b.r, b.u, b.p, b.q, n, pl->P.C, 0.0, false};
+    if (fold && ci >= 1) {
+        k1.fpart = pl->part + (size_t)1 * PARTIAL_SLOTS;
+        k1.fnparts = col_grid(pl->A);
+        k1.ci = ci;
+    }
     if ((e = launch_col<-1>(pl, pl->P, k1, out_spec_on(b.bufP, pl->P), 1)) != hipSuccess) return e;
     if ((e = launch_mid<1>(pl, pl->P, b.bufP, b.specP, (double2 *)nullptr, sP, 1)) != hipSuccess) return e;
     if ((e = launch_fuse(pl, OpIdent{}, b.bufP, b.buf, 1)) != hipSuccess) return e;
     if ((e = launch_mid<0>(pl, pl->A, b.buf, b.specA, (double2 *)nullptr, sA, 1)) != hipSuccess) return e;
     OutCgsDotT<S> k5 = with_red(OutCgsDotT<S>{b.vhat, b.rt, n, pl->A.C}, pl, 0);
-    if ((e = launch_col<1>(pl, pl->A, in_spec_on<CS>(b.buf, pl->A), k5, 1)) != hipSuccess) return e;
+    if ((e = launch_col<1>(pl, pl->A, in_spec_on<CS>(b.buf, pl->A), k5, 1, !fold)) != hipSuccess) return e;
     InCgsQT<S> k6{b.u, b.vhat, b.q, n, pl->P.C, 0.0};
+    if (fold) {
+        k6.fpart = pl->part;  // site 0
+        k6.fnparts = col_grid(pl->A);
+        k6.ci = ci;
+    }
     if ((e = launch_col<-1>(pl, pl->P, k6, out_spec_on(b.bufP, pl->P), 1)) != hipSuccess) return e;
     if ((e = launch_mid<1>(pl, pl->P, b.bufP, b.specP, (double2 *)nullptr, sP, 1)) != hipSuccess) return e;
     if ((e = launch_fuse(pl, OpCgsXT<S>{x, pl->A.C, 0.0}, b.bufP, b.buf, 1)) != hipSuccess) return e;
     if ((e = launch_mid<0>(pl, pl->A, b.buf, b.specA, (double2 *)nullptr, sA, 1)) != hipSuccess) return e;
     OutCgsRT<S> k10 = with_red(OutCgsRT<S>{b.r, b.rt, n, pl->A.C, 0.0}, pl, 1);
-    return launch_col<1>(pl, pl->A, in_spec_on<CS>(b.buf, pl->A), k10, 1);
+    return launch_col<1>(pl, pl->A, in_spec_on<CS>(b.buf, pl->A), k10, 1, !fold);
+}
+
+// End of a folded chunk of `len` iterations: the finishing kernel of the last
+// residual pass, which no later pass folds in.
+template <class S, class CS>
+hipError_t finish_chunk(tsfcde_plan_s *pl, const Bufs<S, CS> &b, int len) {
+    OutCgsRT<S> k10 = with_red(OutCgsRT<S>{b.r, b.rt, pl->n, pl->A.C, 0.0}, pl, 1);
+    k10.ci = len - 1;
+    return launch_final(pl, pl->A, k10, 1);
 }
 
 // The same iteration for general n: the preconditioner solve is a Toeplitz
@@ -800,6 +870,23 @@ hipError_t cgs_iteration_general(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS>
 template <class S, class CS>
 hipError_t cgs_iter(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x) {
     return pl->p2 ? cgs_iteration(pl, j, b, x) : cgs_iteration_general(pl, j, b, x);
+}
+
+// `len` CGS iterations; on the power-of-two path with their finishing steps
+// folded (two launches fewer per iteration), the same arithmetic bit for bit:
+// the folding passes (preconditioner transform) sum the partials with the
+// thread count of the product transform's finishing kernel, so folding is
+// used where the two column geometries have the same thread count.
+template <class S, class CS>
+hipError_t cgs_chunk(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x, int len) {
+    hipError_t e = hipSuccess;
+    if (!pl->p2 || col_nt(pl->P) != col_nt(pl->A)) {
+        for (int k = 0; k < len && e == hipSuccess; ++k) e = cgs_iter(pl, j, b, x);
+        return e;
+    }
+    for (int k = 0; k < len; ++k)
+        if ((e = cgs_iteration(pl, j, b, x, k, true)) != hipSuccess) return e;
+    return len > 0 ? finish_chunk(pl, b, len) : hipSuccess;
 }
 
 // kappa c_1^(j): the weight of u^j in the history sum of level j (j >= 1)
@@ -966,8 +1053,7 @@ int fp64_cgs(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so) {
         for (;;) {
             const int todo = std::min(chunk, pl->maxit - iters_seen);
             if (todo <= 0) break;
-            for (int k = 0; k < todo; ++k)
-                HIPCHK(cgs_iter(pl, j, b64, x));
+            HIPCHK(cgs_chunk(pl, j, b64, x, todo));
             if ((rc = poll(pl))) return rc;
             iters_seen = pl->h_sc->iter;
             if (pl->h_sc->done) break;
