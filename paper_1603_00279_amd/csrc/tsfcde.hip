@@ -1151,7 +1151,7 @@ int ir_solve(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so, int &outer, 
         HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, 0));
         const int budget = std::min(IR_INNER_MAXIT, pl->maxit - inner_total);
         int chunk = std::min(std::max(2, pl->last_inner), std::max(0, budget));
-        for (int k = 0; k < chunk; ++k) HIPCHK(cgs_iter(pl, j, b32, pl->d32));
+        HIPCHK(cgs_chunk(pl, j, b32, pl->d32, chunk));
         if ((rc = poll(pl))) return rc;
         ++outer;
         const double res2 = pl->h_sc->aux1;
@@ -1176,7 +1176,7 @@ int ir_solve(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so, int &outer, 
         int seen = pl->h_sc->iter;
         while (!pl->h_sc->done && seen < budget) {
             const int todo = std::min(2, budget - seen);
-            for (int k = 0; k < todo; ++k) HIPCHK(cgs_iter(pl, j, b32, pl->d32));
+            HIPCHK(cgs_chunk(pl, j, b32, pl->d32, todo));
             if ((rc = poll(pl))) return rc;
             seen = pl->h_sc->iter;
         }
