@@ -147,18 +147,19 @@ __device__ __forceinline__ void stage_bfly(double2 (&v)[E], int j, const double2
 // of the workgroup must call this (it contains barriers); lanes with
 // active == false only take part in the barriers.
 // Exchange of one value between partner lanes of a wave, register to register
-// (DPP, no LDS): lanes l and l ^ 8 for T >= 16 (row rotation by 8 within each
-// row of 16 lanes), lanes l and l ^ 1 for T = 2 (quad permutation [1,0,3,2]).
+// (DPP, no LDS): lanes l and l ^ 8 for SD = 8 (row rotation by 8 within each
+// row of 16 lanes), lanes l and l ^ 1 for SD = 1 (quad permutation [1,0,3,2]).
 // Every lane of the wave must execute it.
-template <int T> __device__ __forceinline__ double swap_lane_pair(double x) {
-    constexpr int CTRL = T >= 16 ? 0x128 : 0xB1;
+template <int SD> __device__ __forceinline__ double swap_lane_pair(double x) {
+    static_assert(SD == 1 || SD == 8, "partner lanes 1 or 8 apart");
+    constexpr int CTRL = SD == 8 ? 0x128 : 0xB1;
     const long long b = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-template <int T> __device__ __forceinline__ double2 swap_lane_pair(double2 v) {
-    return make_double2(swap_lane_pair<T>(v.x), swap_lane_pair<T>(v.y));
+template <int SD> __device__ __forceinline__ double2 swap_lane_pair(double2 v) {
+    return make_double2(swap_lane_pair<SD>(v.x), swap_lane_pair<SD>(v.y));
 }
 
 // Paired layout of a length-P transform at E = 8 values per lane whose last
@@ -166,10 +167,11 @@ template <int T> __device__ __forceinline__ double2 swap_lane_pair(double2 v) {
 // stage combines the outputs of logical lanes j and j + T/2.  When those two
 // logical lanes sit in partner hardware lanes (paired_lane), the stage runs on
 // registers with a lane swap instead of a round trip through LDS between two
-// barriers.  For T >= 16 the hardware lanes of each row of 16 hold 8
-// consecutive logical lanes and their 8 partners, so every group of 8 lanes
-// still reads or writes one whole 128-byte line of a row; for T = 2 the
-// mapping is the identity.
+// barriers.  In a row transform (one transform per T lanes) with T >= 16 the
+// hardware lanes of each row of 16 hold 8 consecutive logical lanes and their
+// 8 partners, so every group of 8 lanes still reads or writes one whole
+// 128-byte line of a row; for T = 2 the mapping is the identity and the
+// partners are adjacent (swap distance 1).
 template <int P, int E> struct Paired {
     static constexpr bool pow8(int q) {
         while (q > 1 && q % 8 == 0) q /= 8;
@@ -186,7 +188,7 @@ template <int T> __device__ __forceinline__ int paired_lane(int u) {
 // stage (sub-length T/2), slot r of logical lane j < T/2 holds position
 // p = j + (T/2) r and slot r of lane j + T/2 holds p + P/2; the butterfly is
 // y_p = x_p + w^p x_{p+P/2}, y_{p+P/2} = x_p - w^p x_{p+P/2}, w = exp(DIR 2 pi i / P).
-template <int P, int E, int DIR, int TS, class Sink>
+template <int P, int E, int DIR, int TS, int SD, class Sink>
 __device__ __forceinline__ void pair_stage(double2 (&v)[E], int j, bool active, const double2 *twP, Sink &sink) {
     constexpr int T = P / E, H = T / 2;
     const bool hi = j >= H;
@@ -197,15 +199,16 @@ __device__ __forceinline__ void pair_stage(double2 (&v)[E], int j, bool active, 
         double2 w = twP[p * TS];
         if (DIR > 0) w.y = -w.y;
         const double2 sv = hi ? cmul(v[r], w) : v[r];  // what this lane contributes
-        const double2 o = swap_lane_pair<T>(sv);      // the partner's contribution
+        const double2 o = swap_lane_pair<SD>(sv);     // the partner's contribution
         const double2 y = hi ? csub(o, sv) : cadd(v[r], o);
         if (active) sink(hi ? p + P / 2 : p, y, r);
     }
 }
 
-// PAIR: the transform runs in the paired layout (see Paired); the caller's
-// lanes must follow paired_lane and every lane of each wave must call.
-template <int P, int E, int NS, int DIR, int TS, class Sink, bool PAIR = false>
+// PAIR != 0: the transform runs in the paired layout (see Paired), with
+// partner lanes PAIR (1 or 8) hardware lanes apart; every lane of each wave
+// must call.
+template <int P, int E, int NS, int DIR, int TS, class Sink, int PAIR = 0>
 __device__ __forceinline__ void fft_stages(double2 (&v)[E], int j, bool active, const double2 *twP, double2 *lds,
                                            int LS, Sink &sink) {
     constexpr int T = P / E;
@@ -215,7 +218,7 @@ __device__ __forceinline__ void fft_stages(double2 (&v)[E], int j, bool active, 
     stage_bfly<P, E, RAD, NS, DIR, TS>(v, j, twP);
     if constexpr (PAIR && NS * RAD * 2 == P) {
         static_assert(RAD == E && NB == 1 && NS == T / 2, "paired layout: radix-8 stage before the radix-2 one");
-        pair_stage<P, E, DIR, TS>(v, j, active, twP, sink);
+        pair_stage<P, E, DIR, TS, PAIR>(v, j, active, twP, sink);
     } else if constexpr (NS * RAD == P) {
         if (active) {
 #pragma unroll
@@ -266,7 +269,7 @@ template <int P, int E> struct LastStage {
 };
 
 // Transform with twiddles from the packed global table.
-template <int P, int E, int DIR, class Sink, bool PAIR = false>
+template <int P, int E, int DIR, class Sink, int PAIR = 0>
 __device__ __forceinline__ void fft(double2 (&v)[E], int j, bool active, const double2 *__restrict__ tw_all,
                                     double2 *lds, int LS, Sink &sink) {
     fft_stages<P, E, 1, DIR, 1, Sink, PAIR>(v, j, active, tw_all + tw_offset(P), lds, LS, sink);
@@ -274,7 +277,7 @@ __device__ __forceinline__ void fft(double2 (&v)[E], int j, bool active, const d
 
 // Transform with twiddles from a table of length P * TS (typically staged in
 // LDS at kernel start, so no stage waits on a global load).
-template <int P, int E, int DIR, int TS, class Sink, bool PAIR = false>
+template <int P, int E, int DIR, int TS, class Sink, int PAIR = 0>
 __device__ __forceinline__ void fft_t(double2 (&v)[E], int j, bool active, const double2 *tw, double2 *lds, int LS,
                                       Sink &sink) {
     fft_stages<P, E, 1, DIR, TS, Sink, PAIR>(v, j, active, tw, lds, LS, sink);

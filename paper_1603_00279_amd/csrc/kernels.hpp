@@ -1043,7 +1043,7 @@ __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, doubl
     const int t = threadIdx.x;
     // rows of 2 * 8^k run their last (radix-2) stage on registers, with the
     // row's logical lanes placed so that partners share a row of 16 lanes
-    constexpr bool PAIR = Paired<C_, E>::OK;
+    constexpr int PAIR = Paired<C_, E>::OK ? (T >= 16 ? 8 : 1) : 0;
     const int sel = t / T, j = PAIR ? paired_lane<T>(t % T) : t % T;
     const bool active = sel < 2;
     const int64_t row = sel == 0 ? ra : rb;
