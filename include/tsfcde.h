@@ -86,6 +86,10 @@ extern "C" {
 #define TSFCDE_FLAG_FORCE_FP32 4 /* FP32_REFINED at every level, whatever the
                                     rounding-error model predicts (to measure
                                     where the refinement stops converging)   */
+#define TSFCDE_FLAG_NO_FOLD 8    /* launch the Krylov reductions' finishing
+                                    kernels separately instead of folding them
+                                    into the passes that follow (diagnostic:
+                                    the results are bitwise the same)        */
 
 /* operators for tsfcde_apply */
 #define TSFCDE_OP_A 0            /* y = A^(j+sigma) x      (3.3)            */

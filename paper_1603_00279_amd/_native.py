@@ -34,6 +34,7 @@ TSFCDE_WS_ZERO, TSFCDE_WS_PREV, TSFCDE_WS_EXTRAP, TSFCDE_WS_NET = 0, 1, 2, 3
 TSFCDE_FLAG_TRUE_RESIDUAL = 1
 TSFCDE_FLAG_VERIFY = 2
 TSFCDE_FLAG_FORCE_FP32 = 4
+TSFCDE_FLAG_NO_FOLD = 8
 TSFCDE_OP_A, TSFCDE_OP_B, TSFCDE_OP_PINV = 0, 1, 2
 TSFCDE_SPEC_EMBED, TSFCDE_SPEC_STRANG = 0, 1
 

@@ -880,7 +880,7 @@ hipError_t cgs_iter(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x) {
 template <class S, class CS>
 hipError_t cgs_chunk(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x, int len) {
     hipError_t e = hipSuccess;
-    if (!pl->p2 || col_nt(pl->P) != col_nt(pl->A)) {
+    if (!pl->p2 || col_nt(pl->P) != col_nt(pl->A) || (pl->flags & TSFCDE_FLAG_NO_FOLD)) {
         for (int k = 0; k < len && e == hipSuccess; ++k) e = cgs_iter(pl, j, b, x);
         return e;
     }

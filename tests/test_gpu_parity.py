@@ -382,3 +382,24 @@ def test_sampled_profiling_counts_and_leaves_results():
     assert issued >= 2 * iters + prob.M  # two products per iteration, one per right-hand side
     assert launches == (issued + 2) // 3 and ms > 0.0
     assert np.array_equal(U0, U1)
+
+
+@pytest.mark.parametrize("n,fp32", [(128, False), (1024, False), (4096, False), (2048, True)])
+def test_folded_finishing_is_bitwise_unfolded(n, fp32):
+    """The finishing steps of the Krylov reductions folded into the passes
+    that follow them give the same march bit for bit, with the same
+    iteration counts, as separate finishing kernels (TSFCDE_FLAG_NO_FOLD),
+    for the FP64 solve and the FP32 inner solve of the refined form."""
+    import paper_1603_00279_amd as P
+    banner(f"folded finishing n={n} fp32={fp32}")
+    prob = W.config_large(n=n, M=10)
+    F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
+    kw = dict(precision=P.TSFCDE_FP32_REFINED) if fp32 else {}
+    base = P.TSFCDE_FLAG_FORCE_FP32 if fp32 else 0
+    runs = []
+    for flags in (base, base | P.TSFCDE_FLAG_NO_FOLD):
+        with make(prob, rtol=1e-10, flags=flags, **kw) as s:
+            code, stats = s.solve(F)
+            runs.append((host(s.history()), [(st["iters"], st["outer_iters"]) for st in stats]))
+    assert runs[0][1] == runs[1][1]
+    assert np.array_equal(runs[0][0], runs[1][0])
