@@ -65,3 +65,22 @@ def test_batch_uneven_convergence_and_zero_source():
     assert np.all(U0 == 0.0)
     assert all(row[0] == 0 for row in its)
     assert len({it for row in its for it in row[1:]}) > 1
+
+
+def test_batch_crosses_history_blocks():
+    """19 levels: the history sums of the batch run in blocks of 8 levels
+    (sweeps at levels 1, 9 and 17, catch-ups in between); every level
+    matches the oracle's march."""
+    import paper_1603_00279_amd as P
+    banner("batch, 19 levels")
+    probs = _instances(4, 19, 40, 300, seed=23)
+    Fs = [t64(np.stack([p.source_level(j) for j in range(p.M)])) for p in probs]
+    with P.BatchSolver(probs, rtol=1e-13) as bs:
+        for j in range(probs[0].M):
+            code, stats = bs.step([F[j] for F in Fs])
+            assert code == 0, stats
+        Ub = [host(bs.history(i)) for i in range(len(probs))]
+    for i, prob in enumerate(probs):
+        Uref = O.march(prob)
+        for j in range(1, prob.M + 1):
+            assert relerr(Ub[i][j], Uref[j]) < 1e-10, (i, prob.n, j, relerr(Ub[i][j], Uref[j]))

@@ -403,3 +403,22 @@ def test_folded_finishing_is_bitwise_unfolded(n, fp32):
             runs.append((host(s.history()), [(st["iters"], st["outer_iters"]) for st in stats]))
     assert runs[0][1] == runs[1][1]
     assert np.array_equal(runs[0][0], runs[1][0])
+
+
+def test_rhs_out_of_order_after_march():
+    """Right-hand sides asked for after a march, out of order and twice: an
+    older level re-sums its history block, a repeated call gives the same
+    vector bit for bit, and every one matches the oracle."""
+    banner("rhs out of order")
+    prob = W.config_large(n=256, M=20, alpha=0.6, beta=1.7)
+    F = [prob.source_level(j) for j in range(prob.M)]
+    with make(prob, rtol=1e-13) as s:
+        s.solve(t64(np.stack(F)))
+        U = host(s.history())
+        got = {}
+        for j in (17, 19, 10, 10, 3, 19, 9):
+            g = host(s.rhs(j, t64(F[j])))
+            if j in got:
+                assert np.array_equal(g, got[j]), j
+            got[j] = g
+            assert relerr(g, O.rhs(prob, U, j, F[j])) < 1e-12, j
