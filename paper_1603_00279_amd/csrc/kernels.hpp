@@ -16,8 +16,9 @@
 //   pass C (k_col, inverse): conjugate twiddle, inverse length-R FFTs down the
 //     columns, unpack to real.
 // Vector updates of the Krylov iteration are fused into pass A (prologue) and
-// pass C (epilogue); dot products are reduced per workgroup and finished by
-// the last workgroup to arrive, in a fixed order (deterministic results).
+// pass C (epilogue); dot products are reduced per workgroup and finished, in
+// a fixed order (deterministic results), by a one-workgroup kernel or inside
+// the pass that follows (see InCgsUPT::fold).
 #pragma once
 #include "fft_core.hpp"
 
