@@ -301,7 +301,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (how the march would shard "
+                                   "over several GPUs is described, not implemented)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 

@@ -52,7 +52,7 @@ extern "C" {
 #define TSFCDE_EBREAKDOWN (-5)   /* CGS breakdown (rho or r~'v = 0)          */
 #define TSFCDE_ENONFINITE (-6)   /* NaN/Inf met in the iteration             */
 #define TSFCDE_EDONE (-7)        /* all M levels already computed            */
-#define TSFCDE_EUNSUPPORTED (-8) /* valid problem outside this build's sizes */
+#define TSFCDE_EUNSUPPORTED (-8) /* valid problem outside the supported sizes or forms */
 
 /* ---- options -------------------------------------------------------- */
 #define TSFCDE_FP64 0            /* every step in FP64                       */

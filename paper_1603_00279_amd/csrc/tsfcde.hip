@@ -1820,7 +1820,7 @@ const char *tsfcde_strerror(int s) {
         case TSFCDE_EBREAKDOWN: return "CGS breakdown";
         case TSFCDE_ENONFINITE: return "non-finite value in the iteration";
         case TSFCDE_EDONE: return "all time levels already computed";
-        case TSFCDE_EUNSUPPORTED: return "problem size not supported by this build";
+        case TSFCDE_EUNSUPPORTED: return "valid problem outside the supported sizes or forms";
         default: return "unknown status";
     }
 }
