@@ -37,17 +37,23 @@ struct DevScalars {
     // the next pass (see InCgsUPT::fold): rho_i sits in rho2[i & 1] for i >= 1
     // (rho_0 in rho), so a pass never reads the slot it writes
     double rho2[2];
+    // residual checks: `checked` says the current done state was confirmed by
+    // a restart pass (cleared by the right-hand side); nchecks counts the
+    // acceptance checks of the level, prestat keeps the status CGS stopped with
+    int checked, nchecks, prestat;
 };
 
 enum : int { ST_OK = 0, ST_BREAKDOWN = 1, ST_NONFINITE = 2 };
 
 // Predication of a launch on the device scalars: pred 0 always runs, pred 1
 // skips once the solve is done, pred 2 skips when the last restart found its
-// guess better than the right-hand side's (a second restart is then moot).
+// guess better than the right-hand side's (a second restart is then moot),
+// pred 3 runs only when the solve is done and no residual check has
+// confirmed that yet (an acceptance check queued behind a chunk of CGS).
 // Kernels test it before their first load: a skipped workgroup (a converged
 // level, or a converged instance of a batch) then costs almost nothing.
 __device__ __forceinline__ bool skip(int pred, const DevScalars *sc) {
-    return (pred == 1 && sc->done) || (pred == 2 && sc->better);
+    return (pred == 1 && sc->done) || (pred == 2 && sc->better) || (pred == 3 && !(sc->done && !sc->checked));
 }
 
 // Loaders that can fold the previous pass's finishing step (see InCgsUPT).
@@ -568,6 +574,8 @@ struct OutRhs {
         sc->aux0 = tot[1];
         sc->r0sq = tot[1];
         sc->status = ST_OK;
+        sc->checked = 0;
+        sc->nchecks = 0;
         sc->done = (tot[1] <= sc->tol2) ? 1 : 0;
         if (!finite(tot[0]) || !finite(tot[1])) {
             sc->status = ST_NONFINITE;
@@ -633,6 +641,10 @@ struct OutRestart {
     // when |g - A x| <= rtol |g|, or when the normwise backward error
     // |g - A x| / (|A| |x| + |g|) is at most bwtol.
     __device__ void final(const double *tot, DevScalars *sc) const {
+        if (check) {  // an acceptance check: count it, keep how CGS stopped
+            sc->nchecks += 1;
+            sc->prestat = sc->status;
+        }
         sc->aux0 = tot[0];
         sc->aux1 = tot[1];
         sc->better = (tot[0] < sc->r0sq) ? 1 : 0;  // isfinite by comparison
@@ -650,8 +662,10 @@ struct OutRestart {
             sc->status = ST_NONFINITE;
             sc->done = 1;
         }
+        sc->checked = sc->done;
     }
     double *partials;
+    int check = 0;  // 1: an acceptance check of a converged solve (counted in nchecks)
 };
 
 // Iterative refinement (FP64 outer loop around an FP32-stored inner solve):

@@ -1011,11 +1011,12 @@ constexpr int MAX_RESTARTS = 3;
 // on the stream, no synchronisation.
 // r = g - A x, rt = r and a fresh CGS state; x itself is accepted when it
 // meets rtol or, with bwtol > 0, the backward-error test.
-int restart_launch(tsfcde_plan_s *pl, int64_t j, const double *x, double bwtol, int pred = 0) {
+int restart_launch(tsfcde_plan_s *pl, int64_t j, const double *x, double bwtol, int pred = 0, bool check = false) {
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
     InReal in{x, pl->n, pl->A.C};
     OutRestart out =
         with_red(OutRestart{pl->g, x, pl->r, pl->rt, pl->n, pl->A.C, pl->anorm[j], bwtol}, pl, 3);
+    out.check = check ? 1 : 0;
     HIPCHK(run_op<0>(pl, pl->A, pl->specA, sA, in, out, pred));
     return TSFCDE_OK;
 }
@@ -1044,49 +1045,56 @@ double backward_error(const tsfcde_plan_s *pl, int64_t j) {
 
 int fp64_cgs(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so) {
     const bool verify = (pl->flags & TSFCDE_FLAG_VERIFY) != 0;
+    // x is accepted at backward error BW_TOL; with TSFCDE_FLAG_VERIFY only at
+    // a true residual within rtol |g|
+    const double bwtol = verify ? 0.0 : BW_TOL;
     const Bufs<double, double2> b64 = bufs64(pl);
-    int rc, iters_seen = 0;
+    int rc, iters_seen = 0, checks_seen = 0;
     double last_true2 = HUGE_VAL;
     int chunk = std::max(2, pl->last_iters);
     for (;;) {
-        // CGS until the device reports done or maxit is reached
-        for (;;) {
-            const int todo = std::min(chunk, pl->maxit - iters_seen);
-            if (todo <= 0) break;
-            HIPCHK(cgs_chunk(pl, j, b64, x, todo));
-            if ((rc = poll(pl))) return rc;
-            iters_seen = pl->h_sc->iter;
-            if (pl->h_sc->done) break;
+        // a chunk of CGS, then the acceptance check, which the device runs
+        // only when the chunk ended the solve (one poll serves both): restart
+        // from x recovers from a breakdown and checks a converged level,
+        // continuing CGS from x when the check fails
+        const int todo = std::min(chunk, pl->maxit - iters_seen);
+        if (todo > 0) HIPCHK(cgs_chunk(pl, j, b64, x, todo));
+        if ((rc = restart_launch(pl, j, x, bwtol, 3, true))) return rc;
+        if ((rc = poll(pl))) return rc;
+        const DevScalars &h = *pl->h_sc;
+        iters_seen = h.iter;
+        const bool ran = h.nchecks > checks_seen;
+        checks_seen = h.nchecks;
+        if (!ran) {
+            if (h.done) {  // the level's first residual already met the tolerance
+                so.relres_true = h.gnorm2 > 0 ? std::sqrt(h.aux0 / h.gnorm2) : 0.0;
+                so.backward_err = backward_error(pl, j);
+                so.code = status_code(h.status);
+                break;
+            }
+            if (todo <= 0) {
+                so.code = TSFCDE_ENOCONV;
+                break;
+            }
             chunk = 2;
+            continue;
         }
-        if (!pl->h_sc->done) {
-            so.code = TSFCDE_ENOCONV;
+        so.relres_true = h.gnorm2 > 0 ? std::sqrt(h.aux0 / h.gnorm2) : 0.0;
+        so.backward_err = backward_error(pl, j);
+        if (h.done) {  // accepted, or non-finite
+            so.code = status_code(h.status);
             break;
         }
-        const int stat = pl->h_sc->status;
-        if (stat == ST_NONFINITE) {
-            so.code = TSFCDE_ENONFINITE;
-            break;
-        }
+        const int stat = h.prestat;  // how CGS stopped
         if (stat == ST_BREAKDOWN && so.restarts >= MAX_RESTARTS) {
             so.code = TSFCDE_EBREAKDOWN;
-            break;
-        }
-        // restart from x: recovers from a breakdown, and checks a converged
-        // level (backward error; with TSFCDE_FLAG_VERIFY also the true
-        // residual against rtol |g|), continuing CGS from x when it fails
-        if ((rc = restart_from_x(pl, j, x, verify ? 0.0 : BW_TOL))) return rc;
-        so.relres_true = pl->h_sc->gnorm2 > 0 ? std::sqrt(pl->h_sc->aux0 / pl->h_sc->gnorm2) : 0.0;
-        so.backward_err = backward_error(pl, j);
-        if (pl->h_sc->done) {
-            so.code = status_code(pl->h_sc->status);
             break;
         }
         if (stat == ST_OK) {
             if (verify) {
                 // true residual above tolerance: continue while it keeps falling
-                if (so.restarts >= MAX_RESTARTS || !(pl->h_sc->aux0 < 0.25 * last_true2)) break;
-                last_true2 = pl->h_sc->aux0;
+                if (so.restarts >= MAX_RESTARTS || !(h.aux0 < 0.25 * last_true2)) break;
+                last_true2 = h.aux0;
             } else if (so.restarts >= MAX_RESTARTS) {
                 break;  // x stays as it is
             }
