@@ -145,3 +145,26 @@ def test_levels_full_size():
         r = O.rhs_rows(prob, U, j, F[j], rows) - O.apply_A_rows(prob, j, U[j + 1], rows, "A")
         S = row_scale(prob, j, U[j + 1])
         assert np.abs(r).max() <= 1e-12 * S, (j, np.abs(r).max() / S)
+
+
+def test_general_n_full_size():
+    """n = 1000003 (odd, not a power of two): products through the length
+    2^21 embedding and the preconditioner solve through the per-level
+    inverse Strang circulant built by Bluestein's transform, on sampled rows."""
+    import paper_1603_00279_amd as P
+    n = 1000003
+    banner(f"general n={n}")
+    prob = W.config_large(n=n, M=6)
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal(n)
+    fixed = np.array([0, 1, 2, 1023, 1024, n // 2, n - 3, n - 2, n - 1])
+    rows = np.unique(np.concatenate([fixed, rng.integers(0, n, size=24)]))
+    with make(prob) as s:
+        for j in (0, 4):
+            yA = host(s.apply(P.TSFCDE_OP_A, j, t64(x)))
+            S = row_scale(prob, j, x)
+            dA = np.abs(yA[rows] - O.apply_A_rows(prob, j, x, rows, "A"))
+            assert dA.max() <= 1e-12 * S, (j, dA.max() / S)
+            y = host(s.apply(P.TSFCDE_OP_PINV, j, t64(x)))
+            d = np.abs(O.apply_P_rows(prob, j, y, rows) - x[rows])
+            assert d.max() <= 1e-12 * row_scale(prob, j, y), (j, d.max() / row_scale(prob, j, y))
