@@ -704,12 +704,12 @@ template <class CS> InSpecT<CS> in_spec_on(const CS *buf, const RT &rt) { return
 // run_op on an explicit transform buffer (any storage type)
 template <int MODE, class CS, class In, class Out>
 hipError_t run_op_on(tsfcde_plan_s *pl, const RT &rt, CS *buf, const CS *spec, const SymParams &sp, const In &in,
-                     const Out &out, int pred) {
+                     const Out &out, int pred, bool finish = true) {
     hipError_t e = launch_col<-1>(pl, rt, in, out_spec_on(buf, rt), pred);
     if (e != hipSuccess) return e;
     e = launch_mid<MODE>(pl, rt, buf, spec, (double2 *)nullptr, sp, pred);
     if (e != hipSuccess) return e;
-    return launch_col<1>(pl, rt, in_spec_on<CS>(buf, rt), out, pred);
+    return launch_col<1>(pl, rt, in_spec_on<CS>(buf, rt), out, pred, finish);
 }
 
 // y-side of an operator: pass A with loader `in`, middle, pass C with store `out`.
@@ -846,8 +846,11 @@ hipError_t finish_chunk(tsfcde_plan_s *pl, const Bufs<S, CS> &b, int len) {
 
 // The same iteration for general n: the preconditioner solve is a Toeplitz
 // product with the level's inverse-Strang spectrum (12 kernels).
+// One CGS iteration for any n (every transform on the product geometry), with
+// the finishing steps folded as in cgs_iteration when fold is set.
 template <class S, class CS>
-hipError_t cgs_iteration_general(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x) {
+hipError_t cgs_iteration_general(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x, int ci = 0,
+                                 bool fold = false) {
     const int64_t n = pl->n;
     const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
     const SymParams sI = unit_symbol(pl->A);
@@ -855,16 +858,26 @@ hipError_t cgs_iteration_general(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS>
     hipError_t e;
     OutRealT<S> o1{b.phat, n, C};
     o1.partials = nullptr;
-    if ((e = run_op_on<0>(pl, pl->A, b.buf, b.specPj, sI, InCgsUPT<S>{b.r, b.u, b.p, b.q, n, C, 0.0, false}, o1,
-                          1)))
-        return e;
+    InCgsUPT<S> i1{b.r, b.u, b.p, b.q, n, C, 0.0, false};
+    if (fold && ci >= 1) {
+        i1.fpart = pl->part + (size_t)1 * PARTIAL_SLOTS;
+        i1.fnparts = col_grid(pl->A);
+        i1.ci = ci;
+    }
+    if ((e = run_op_on<0>(pl, pl->A, b.buf, b.specPj, sI, i1, o1, 1))) return e;
     OutCgsDotT<S> o2 = with_red(OutCgsDotT<S>{b.vhat, b.rt, n, C}, pl, 0);
-    if ((e = run_op_on<0>(pl, pl->A, b.buf, b.specA, sA, InRealT<S>{b.phat, n, C}, o2, 1))) return e;
+    if ((e = run_op_on<0>(pl, pl->A, b.buf, b.specA, sA, InRealT<S>{b.phat, n, C}, o2, 1, !fold))) return e;
     OutRealT<S> o3{b.uhat, n, C};
     o3.partials = nullptr;
-    if ((e = run_op_on<0>(pl, pl->A, b.buf, b.specPj, sI, InCgsQT<S>{b.u, b.vhat, b.q, n, C, 0.0}, o3, 1))) return e;
+    InCgsQT<S> i3{b.u, b.vhat, b.q, n, C, 0.0};
+    if (fold) {
+        i3.fpart = pl->part;  // site 0
+        i3.fnparts = col_grid(pl->A);
+        i3.ci = ci;
+    }
+    if ((e = run_op_on<0>(pl, pl->A, b.buf, b.specPj, sI, i3, o3, 1))) return e;
     OutCgsRT<S> o4 = with_red(OutCgsRT<S>{b.r, b.rt, n, C, 0.0}, pl, 1);
-    return run_op_on<0>(pl, pl->A, b.buf, b.specA, sA, InCgsXT<S>{b.uhat, x, n, C, 0.0}, o4, 1);
+    return run_op_on<0>(pl, pl->A, b.buf, b.specA, sA, InCgsXT<S>{b.uhat, x, n, C, 0.0}, o4, 1, !fold);
 }
 
 template <class S, class CS>
@@ -872,20 +885,22 @@ hipError_t cgs_iter(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x) {
     return pl->p2 ? cgs_iteration(pl, j, b, x) : cgs_iteration_general(pl, j, b, x);
 }
 
-// `len` CGS iterations; on the power-of-two path with their finishing steps
-// folded (two launches fewer per iteration), the same arithmetic bit for bit:
-// the folding passes (preconditioner transform) sum the partials with the
-// thread count of the product transform's finishing kernel, so folding is
-// used where the two column geometries have the same thread count.
+// `len` CGS iterations with their finishing steps folded (two launches fewer
+// per iteration), the same arithmetic bit for bit: the folding passes sum the
+// partials with the thread count of the finishing kernel.  On the
+// power-of-two path the folding passes run on the preconditioner transform,
+// so folding needs its column geometry to have the product's thread count.
 template <class S, class CS>
 hipError_t cgs_chunk(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x, int len) {
     hipError_t e = hipSuccess;
-    if (!pl->p2 || col_nt(pl->P) != col_nt(pl->A) || (pl->flags & TSFCDE_FLAG_NO_FOLD)) {
+    if ((pl->flags & TSFCDE_FLAG_NO_FOLD) || (pl->p2 && col_nt(pl->P) != col_nt(pl->A))) {
         for (int k = 0; k < len && e == hipSuccess; ++k) e = cgs_iter(pl, j, b, x);
         return e;
     }
-    for (int k = 0; k < len; ++k)
-        if ((e = cgs_iteration(pl, j, b, x, k, true)) != hipSuccess) return e;
+    for (int k = 0; k < len; ++k) {
+        e = pl->p2 ? cgs_iteration(pl, j, b, x, k, true) : cgs_iteration_general(pl, j, b, x, k, true);
+        if (e != hipSuccess) return e;
+    }
     return len > 0 ? finish_chunk(pl, b, len) : hipSuccess;
 }
 
@@ -1904,28 +1919,53 @@ struct tsfcde_batch_s {
     DevScalars **d_scs = nullptr;
     DoneRec *d_done = nullptr, *h_done = nullptr;
     int last_iters = 8;
+    bool fold = true;  // finishing steps folded into later passes (TSFCDE_FLAG_NO_FOLD clears it)
 };
 
 namespace {
 
 template <int R, int DIR, class In, class Out>
-hipError_t blaunch_col_t(tsfcde_batch_s *bt, int64_t C, const ColDesc<In, Out> *d, int cnt, int pred) {
+hipError_t blaunch_col_t(tsfcde_batch_s *bt, int64_t C, const ColDesc<In, Out> *d, int cnt, int pred, bool finish) {
     using G = ColGeo<R, TSF_E_COL>;
     const int64_t grid = (C + G::B - 1) / G::B;
     hipLaunchKernelGGL((k_col_b<R, TSF_E_COL, DIR, In, Out>), dim3((unsigned)grid, cnt), dim3(G::NT), 0, bt->stream,
                        d, bt->plans[0]->tw_all, pred);
     if constexpr (Out::NACC > 0) {
-        hipLaunchKernelGGL((k_final_b<G::NT, In, Out>), dim3(1, cnt), dim3(G::NT), 0, bt->stream, d, (int)grid, pred);
+        if (finish)
+            hipLaunchKernelGGL((k_final_b<G::NT, In, Out>), dim3(1, cnt), dim3(G::NT), 0, bt->stream, d, (int)grid,
+                               pred);
     }
     return hipGetLastError();
 }
 
+template <int R, class In, class Out>
+hipError_t bfinal_t(tsfcde_batch_s *bt, int64_t C, const ColDesc<In, Out> *d, int cnt, int pred) {
+    using G = ColGeo<R, TSF_E_COL>;
+    hipLaunchKernelGGL((k_final_b<G::NT, In, Out>), dim3(1, cnt), dim3(G::NT), 0, bt->stream, d,
+                       (int)((C + G::B - 1) / G::B), pred);
+    return hipGetLastError();
+}
+
 template <int DIR, class In, class Out>
-hipError_t blaunch_col(tsfcde_batch_s *bt, const RT &rt, const ColDesc<In, Out> *d, int cnt, int pred) {
+hipError_t blaunch_col(tsfcde_batch_s *bt, const RT &rt, const ColDesc<In, Out> *d, int cnt, int pred,
+                       bool finish = true) {
     if (!d) return hipErrorOutOfMemory;
     switch (rt.R) {
 #define TSF_CASE(P) \
-    case P: return blaunch_col_t<P, DIR>(bt, rt.C, d, cnt, pred);
+    case P: return blaunch_col_t<P, DIR>(bt, rt.C, d, cnt, pred, finish);
+        TSF_SIZES(TSF_CASE)
+#undef TSF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Finishing kernel of a grouped column pass launched without its own.
+template <class In, class Out>
+hipError_t bfinal(tsfcde_batch_s *bt, const RT &rt, const ColDesc<In, Out> *d, int cnt, int pred) {
+    if (!d) return hipErrorOutOfMemory;
+    switch (rt.R) {
+#define TSF_CASE(P) \
+    case P: return bfinal_t<P>(bt, rt.C, d, cnt, pred);
         TSF_SIZES(TSF_CASE)
 #undef TSF_CASE
         default: return hipErrorInvalidValue;
@@ -1989,13 +2029,21 @@ struct GroupDesc {
     ColDesc<InCplx, OutSpec> *bsA;
     RowDesc *bsRow;
     ColDesc<InSpec, OutCplx> *bsC;
-    ColDesc<InCgsUP, OutSpec> *s1;
+    // CGS passes.  Folded finishing steps read and write parity slots that
+    // depend on the iteration's index ci in its chunk, so the two folding
+    // passes and the chunk's closing finishing kernel come in variants:
+    // s1[v]: v = 0 (ci = 0, no fold), 1 (ci = 1), 2 (even ci >= 2), 3 (odd ci >= 3);
+    // s7[v], s12[v]: v = 0 (ci = 0), 1 (odd ci), 2 (even ci >= 2).
+    ColDesc<InCgsUP, OutSpec> *s1[4];
     ColDesc<InSpec, OutReal> *s3, *s9;
     ColDesc<InSpec, OutCgsDot> *s6;
-    ColDesc<InCgsQ, OutSpec> *s7;
+    ColDesc<InCgsQ, OutSpec> *s7[3], *s7_plain;
     ColDesc<InCgsX, OutSpec> *s10;
-    ColDesc<InSpec, OutCgsR> *s12;
+    ColDesc<InSpec, OutCgsR> *s12[3];
 };
+
+int s1_variant(int ci) { return ci <= 1 ? ci : 2 + (ci & 1); }
+int s7_variant(int ci) { return ci == 0 ? 0 : ((ci & 1) ? 1 : 2); }
 
 bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const double *const *d_f, int warm,
                  GroupDesc &D) {
@@ -2006,12 +2054,13 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
     std::vector<ColDesc<InCplx, OutSpec>> bsA;
     std::vector<RowDesc> bsRow;
     std::vector<ColDesc<InSpec, OutCplx>> bsC;
-    std::vector<ColDesc<InCgsUP, OutSpec>> s1;
+    std::vector<ColDesc<InCgsUP, OutSpec>> s1[4];
     std::vector<ColDesc<InSpec, OutReal>> s3, s9;
     std::vector<ColDesc<InSpec, OutCgsDot>> s6;
-    std::vector<ColDesc<InCgsQ, OutSpec>> s7;
+    std::vector<ColDesc<InCgsQ, OutSpec>> s7[3], s7_plain;
     std::vector<ColDesc<InCgsX, OutSpec>> s10;
-    std::vector<ColDesc<InSpec, OutCgsR>> s12;
+    std::vector<ColDesc<InSpec, OutCgsR>> s12[3];
+    const int fnparts = col_grid(g.A);
     for (int idx : g.members) {
         tsfcde_plan_s *pl = bt->plans[idx];
         const int64_t n = pl->n, ld = pl->ldn, C = pl->A.C, CB = pl->B.C;
@@ -2043,14 +2092,31 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
         midR2C.push_back(MidDesc{pl->A.R, pl->buf, nullptr, pl->specPj, pl->A.tw, SymParams{}, pl->sc});
         midP.push_back(MidDesc{pl->A.R, pl->buf, pl->specPj, nullptr, pl->A.tw, sI, pl->sc});
         // CGS iteration
-        s1.push_back(cdesc(pl, C, InCgsUP{pl->r, pl->u, pl->p, pl->q, n, C, 0.0, false}, osA));
+        for (int v = 0; v < 4; ++v) {
+            InCgsUP in{pl->r, pl->u, pl->p, pl->q, n, C, 0.0, false};
+            if (v > 0) {  // representative chunk index of the variant: 1, 2, 3
+                in.fpart = pl->part + (size_t)1 * PARTIAL_SLOTS;
+                in.fnparts = fnparts;
+                in.ci = v;
+            }
+            s1[v].push_back(cdesc(pl, C, in, osA));
+        }
         s3.push_back(cdesc(pl, C, isA, nored(OutReal{pl->phat, n, C})));
         s4.push_back(cdesc(pl, C, InReal{pl->phat, n, C}, osA));
         s6.push_back(cdesc(pl, C, isA, with_red(OutCgsDot{pl->vhat, pl->rt, n, C}, pl, 0)));
-        s7.push_back(cdesc(pl, C, InCgsQ{pl->u, pl->vhat, pl->q, n, C, 0.0}, osA));
+        s7_plain.push_back(cdesc(pl, C, InCgsQ{pl->u, pl->vhat, pl->q, n, C, 0.0}, osA));
+        for (int v = 0; v < 3; ++v) {
+            InCgsQ in{pl->u, pl->vhat, pl->q, n, C, 0.0};
+            in.fpart = pl->part;  // site 0
+            in.fnparts = fnparts;
+            in.ci = v;  // 0, 1 (odd), 2 (even >= 2)
+            s7[v].push_back(cdesc(pl, C, in, osA));
+            OutCgsR out = with_red(OutCgsR{pl->r, pl->rt, n, C, 0.0}, pl, 1);
+            out.ci = v;
+            s12[v].push_back(cdesc(pl, C, isA, out));
+        }
         s9.push_back(cdesc(pl, C, isA, nored(OutReal{pl->uhat, n, C})));
         s10.push_back(cdesc(pl, C, InCgsX{pl->uhat, x, n, C, 0.0}, osA));
-        s12.push_back(cdesc(pl, C, isA, with_red(OutCgsR{pl->r, pl->rt, n, C, 0.0}, pl, 1)));
     }
     Stage &S = bt->st;
     D.rhsA = S.put(rhsA);
@@ -2065,14 +2131,17 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
     D.r2cA = S.put(r2cA);
     D.midR2C = S.put(midR2C);
     D.midP = S.put(midP);
-    D.s1 = S.put(s1);
+    for (int v = 0; v < 4; ++v) D.s1[v] = S.put(s1[v]);
     D.s3 = S.put(s3);
     D.s4 = S.put(s4);
     D.s6 = S.put(s6);
-    D.s7 = S.put(s7);
+    for (int v = 0; v < 3; ++v) {
+        D.s7[v] = S.put(s7[v]);
+        D.s12[v] = S.put(s12[v]);
+    }
+    D.s7_plain = S.put(s7_plain);
     D.s9 = S.put(s9);
     D.s10 = S.put(s10);
-    D.s12 = S.put(s12);
     return S.used <= S.cap;
 }
 
@@ -2201,24 +2270,36 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
         for (;;) {
             const int todo = std::min(chunk, bt->maxit - iters_seen);
             if (todo <= 0) break;
+            // with folding, the two reductions' finishing steps run inside the
+            // next passes and the chunk ends with one finishing kernel
+            const bool fold = bt->fold;
             for (int k = 0; k < todo; ++k) {
                 for (size_t g = 0; g < bt->groups.size(); ++g) {
                     const BatchGroup &G = bt->groups[g];
                     const int c = (int)G.members.size();
                     const GroupDesc &D = gd[g];
-                    BCHK(blaunch_col<-1>(bt, G.A, D.s1, c, 1));
+                    BCHK(blaunch_col<-1>(bt, G.A, D.s1[fold ? s1_variant(k) : 0], c, 1));
                     BCHK(blaunch_mid<0>(bt, G.A, D.midP, c, 1));
                     BCHK(blaunch_col<1>(bt, G.A, D.s3, c, 1));
                     BCHK(blaunch_col<-1>(bt, G.A, D.s4, c, 1));
                     BCHK(blaunch_mid<0>(bt, G.A, D.midA, c, 1));
-                    BCHK(blaunch_col<1>(bt, G.A, D.s6, c, 1));
-                    BCHK(blaunch_col<-1>(bt, G.A, D.s7, c, 1));
+                    BCHK(blaunch_col<1>(bt, G.A, D.s6, c, 1, !fold));
+                    if (fold) {
+                        BCHK(blaunch_col<-1>(bt, G.A, D.s7[s7_variant(k)], c, 1));
+                    } else {
+                        BCHK(blaunch_col<-1>(bt, G.A, D.s7_plain, c, 1));
+                    }
                     BCHK(blaunch_mid<0>(bt, G.A, D.midP, c, 1));
                     BCHK(blaunch_col<1>(bt, G.A, D.s9, c, 1));
                     BCHK(blaunch_col<-1>(bt, G.A, D.s10, c, 1));
                     BCHK(blaunch_mid<0>(bt, G.A, D.midA, c, 1));
-                    BCHK(blaunch_col<1>(bt, G.A, D.s12, c, 1));
+                    BCHK(blaunch_col<1>(bt, G.A, D.s12[0], c, 1, !fold));
                 }
+            }
+            if (fold && todo > 0) {
+                for (size_t g = 0; g < bt->groups.size(); ++g)
+                    BCHK(bfinal(bt, bt->groups[g].A, gd[g].s12[s7_variant(todo - 1)], (int)bt->groups[g].members.size(),
+                                1));
             }
             int rc = batch_poll(bt);
             if (rc) return rc;
@@ -2332,6 +2413,7 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
     bt->M = probs[0].M;
     bt->maxit = probs[0].maxit > 0 ? probs[0].maxit : 500;
     bt->warm = probs[0].warm_start;
+    bt->fold = (probs[0].flags & TSFCDE_FLAG_NO_FOLD) == 0;
     char *ws = reinterpret_cast<char *>(d_workspace);
     size_t off = 0;
     auto fail = [&](int code) {

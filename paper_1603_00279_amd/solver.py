@@ -186,7 +186,7 @@ class BatchSolver:
     initial_vector(); all share M."""
 
     def __init__(self, problems, *, rtol: float = 1e-10, maxit: int = 500, warm_start: int = N.TSFCDE_WS_ZERO,
-                 precision: int = N.TSFCDE_FP64, device: Optional[torch.device] = None,
+                 precision: int = N.TSFCDE_FP64, flags: int = 0, device: Optional[torch.device] = None,
                  stream: Optional[torch.cuda.Stream] = None):
         self._lib = N.lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -205,7 +205,7 @@ class BatchSolver:
                 gamma=N.COEF_FN(), dplus=N.COEF_FN(), dminus=N.COEF_FN(), coef_user=None,
                 gamma_at=g.ctypes.data_as(dptr), dplus_at=dp.ctypes.data_as(dptr), dminus_at=dm.ctypes.data_as(dptr),
                 phi=N.IC_FN(), phi_user=None, rtol=rtol, maxit=maxit, precision=precision,
-                warm_start=warm_start, flags=0)
+                warm_start=warm_start, flags=flags)
         self._arr = arr
         nbytes = ctypes.c_size_t(0)
         N.check(self._lib.tsfcde_batch_workspace_bytes(arr, self.count, ctypes.byref(nbytes)),

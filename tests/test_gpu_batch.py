@@ -84,3 +84,25 @@ def test_batch_crosses_history_blocks():
         Uref = O.march(prob)
         for j in range(1, prob.M + 1):
             assert relerr(Ub[i][j], Uref[j]) < 1e-10, (i, prob.n, j, relerr(Ub[i][j], Uref[j]))
+
+
+def test_batch_folded_finishing_is_bitwise_unfolded():
+    """The batch with the finishing steps folded into later passes gives the
+    same levels bit for bit as with separate finishing kernels
+    (TSFCDE_FLAG_NO_FOLD), over chunks long enough to use every variant."""
+    import paper_1603_00279_amd as P
+    banner("batch fold vs no fold")
+    probs = _instances(6, 10, 60, 2500, seed=29)
+    Fs = [t64(np.stack([p.source_level(j) for j in range(p.M)])) for p in probs]
+    runs = []
+    for flags in (0, P.TSFCDE_FLAG_NO_FOLD):
+        its = []
+        with P.BatchSolver(probs, rtol=1e-12, flags=flags) as bs:
+            for j in range(probs[0].M):
+                code, stats = bs.step([F[j] for F in Fs])
+                assert code == 0, stats
+                its.append([st["iters"] for st in stats])
+            runs.append(([host(bs.history(i)) for i in range(len(probs))], its))
+    assert runs[0][1] == runs[1][1]
+    for a, b in zip(runs[0][0], runs[1][0]):
+        assert np.array_equal(a, b)
