@@ -83,3 +83,21 @@ def test_general_sizes_accepted(N, n):
     nb = ctypes.c_size_t(0)
     assert N.lib().tsfcde_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == 0
     assert nb.value >= 8 * 9 * n
+
+
+def test_header_constants_match_binding(N):
+    """Every integer constant include/tsfcde.h defines has the same value in
+    the Python binding."""
+    import os
+    import re
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "tsfcde.h")
+    found = 0
+    for line in open(path):
+        m = re.match(r"#define (TSFCDE_\w+)\s+\(?(-?\d+)\)?", line)
+        if not m:
+            continue
+        name, value = m.group(1), int(m.group(2))
+        assert hasattr(N, name), name
+        assert getattr(N, name) == value, (name, getattr(N, name), value)
+        found += 1
+    assert found >= 20
