@@ -52,6 +52,8 @@ __all__ = [
     "level_B", "history_term", "rhs", "level_solve", "march", "error_norms",
     "strang_column", "circulant", "preconditioner_matrix", "circulant_eigenvalues",
     "embedding_column", "apply_A_rows", "apply_P_rows", "rhs_rows", "caputo_l21s",
+    "embedding_eigenvalues", "embedding_product", "strang_eigenvalues", "strang_solve", "rhs_fft",
+    "level_solve_pcgs",
 ]
 
 
@@ -371,3 +373,106 @@ def rhs_rows(prob, U: np.ndarray, j: int, f_j: np.ndarray, rows: np.ndarray) -> 
     for s in range(j):
         acc += c[j - s] * (U[s + 1][rows] - U[s][rows])
     return Bu - l21s_kappa(prob.alpha, prob.tau) * acc + f_j[rows]
+
+
+# ---------------------------------------------------------------------------
+# The paper's fast level solve for large n (Sec. 3.2 and Algorithm 2 with
+# PCGS): Toeplitz products through a circulant embedding and the Strang
+# preconditioner, both with the library FFT, and preconditioned CGS as in
+# Barrett et al., Templates (1994).  Plain NumPy, independent of the GPU path.
+# ---------------------------------------------------------------------------
+
+def embedding_eigenvalues(prob) -> np.ndarray:
+    """Eigenvalues of the circulant embedding of W (length L = the next power
+    of two >= 2n)."""
+    L = 1
+    while L < 2 * prob.n:
+        L *= 2
+    return circulant_eigenvalues(embedding_column(prob.beta, prob.n, L))
+
+
+def embedding_product(prob, j: int, x: np.ndarray, which: str = "A", lam=None) -> np.ndarray:
+    """A^(j+sigma) x (or B^(j+sigma) x) with W x and W^T x from a circulant
+    embedding of length L = the next power of two >= 2n: the embedding's
+    eigenvalues lam = DFT(column) (embedding_eigenvalues) act on the
+    zero-padded x, and W^T, the transpose of a real circulant, has the
+    eigenvalues conj(lam)."""
+    e, gam, dp, dm = level_scalars(prob, j)
+    n, h, beta, sigma = prob.n, prob.h, prob.beta, prob.sigma
+    if lam is None:
+        lam = embedding_eigenvalues(prob)
+    L = lam.size
+    X = np.fft.fft(np.concatenate([x, np.zeros(L - n)]))
+    wx = np.fft.ifft(lam * X).real[:n]
+    wtx = np.fft.ifft(np.conj(lam) * X).real[:n]
+    qx = np.concatenate([x[1:], [0.0]]) - np.concatenate([[0.0], x[:-1]])
+    Lx = gam / (2.0 * h) * qx + dp / h ** beta * wx + dm / h ** beta * wtx
+    return e * x - sigma * Lx if which == "A" else e * x + (1.0 - sigma) * Lx
+
+
+def strang_eigenvalues(prob, j: int) -> np.ndarray:
+    """Eigenvalues of the Strang preconditioner (3.7): eta_j - sigma (gamma/(2h)
+    lam(s(Q)) + D+/h^beta lam(s(W)) + D-/h^beta conj lam(s(W)))."""
+    e, gam, dp, dm = level_scalars(prob, j)
+    n, h, beta, sigma = prob.n, prob.h, prob.beta, prob.sigma
+    lq = circulant_eigenvalues(strang_column(_Q_lag, n))
+    lw = circulant_eigenvalues(strang_column(_W_lag(beta, n), n))
+    return e - sigma * (gam / (2.0 * h) * lq + dp / h ** beta * lw + dm / h ** beta * np.conj(lw))
+
+
+def strang_solve(prob, j: int, y: np.ndarray, lam=None) -> np.ndarray:
+    """(P^(j+sigma))^{-1} y, a division by the circulant's eigenvalues."""
+    if lam is None:
+        lam = strang_eigenvalues(prob, j)
+    return np.fft.ifft(np.fft.fft(y) / lam).real
+
+
+def rhs_fft(prob, U: np.ndarray, j: int, f_j: np.ndarray, lam=None) -> np.ndarray:
+    """g^(j) of (3.3) (same definition as ``rhs``) with B^(j+sigma) u^j
+    through the embedding product."""
+    g = embedding_product(prob, j, U[j], "B", lam) + f_j
+    if j == 0:
+        return g
+    c = l21s_c(prob.alpha, j)
+    acc = np.zeros(prob.n)
+    for s_ in range(j):
+        acc += c[j - s_] * (U[s_ + 1] - U[s_])
+    return g - l21s_kappa(prob.alpha, prob.tau) * acc
+
+
+def level_solve_pcgs(prob, U: np.ndarray, j: int, f_j: np.ndarray, rtol: float = 1e-10, maxit: int = 500):
+    """u^{j+1} by preconditioned CGS on A^(j+sigma) u = g (3.3) from x0 = 0,
+    stopped when the recursive residual falls to rtol |g| (Sec. 4).  Returns
+    (u, iterations)."""
+    lam_e = embedding_eigenvalues(prob)
+    lam_p = strang_eigenvalues(prob, j)
+    g = rhs_fft(prob, U, j, f_j, lam_e)
+    A = lambda v: embedding_product(prob, j, v, "A", lam_e)  # noqa: E731
+    Pinv = lambda v: strang_solve(prob, j, v, lam_p)  # noqa: E731
+    x = np.zeros(prob.n)
+    r = g.copy()
+    rt = r.copy()
+    gnorm = np.linalg.norm(g)
+    rho_old, q, p = 1.0, None, None
+    for it in range(1, maxit + 1):
+        rho = float(rt @ r)
+        if rho == 0.0:
+            return x, it
+        if it == 1:
+            u = r.copy()
+            p = u.copy()
+        else:
+            beta = rho / rho_old
+            u = r + beta * q
+            p = u + beta * (q + beta * p)
+        vhat = A(Pinv(p))
+        alpha = rho / float(rt @ vhat)
+        q = u - alpha * vhat
+        uhat = Pinv(u + q)
+        x = x + alpha * uhat
+        r = r - alpha * A(uhat)
+        if np.linalg.norm(r) <= rtol * gnorm:
+            return x, it
+        rho_old = rho
+    return x, maxit
+

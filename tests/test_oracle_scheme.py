@@ -204,3 +204,47 @@ def test_history_enters_with_minus_sign():
         Ubad[j + 1] = np.linalg.solve(O.level_A(prob, j), g)
     bad = O.error_norms(prob, Ubad)[0]
     assert good < 3e-4 < 30 * good < bad
+
+
+@pytest.mark.parametrize("n", [63, 64, 257])
+def test_fft_level_solve_matches_dense(n):
+    """The oracle's FFT route for large n against its dense one: embedding
+    products equal the dense A and B, the Strang solve inverts the dense
+    preconditioner, the right-hand side equals the dense one, and PCGS at a
+    tight tolerance reaches the LU solution."""
+    prob = W.config_large(n=n, M=8, alpha=0.6, beta=1.7)
+    rng = np.random.default_rng(n + 9)
+    U = rng.standard_normal((prob.M + 1, n))
+    x = rng.standard_normal(n)
+    for j in (0, 1, 5):
+        A = O.level_A(prob, j)
+        assert np.allclose(O.embedding_product(prob, j, x, "A"), A @ x, rtol=0, atol=1e-12 * np.abs(A @ x).max())
+        B = O.level_B(prob, j)
+        assert np.allclose(O.embedding_product(prob, j, x, "B"), B @ x, rtol=0, atol=1e-12 * np.abs(B @ x).max())
+        Pm = O.preconditioner_matrix(prob, j)
+        y = O.strang_solve(prob, j, x)
+        assert np.linalg.norm(Pm @ y - x) <= 1e-13 * np.linalg.norm(Pm, 2) * np.linalg.norm(y)
+        f = rng.standard_normal(n)
+        g = O.rhs(prob, U, j, f)
+        assert np.allclose(O.rhs_fft(prob, U, j, f), g, rtol=0, atol=1e-12 * np.abs(g).max())
+        u, its = O.level_solve_pcgs(prob, U, j, f, rtol=1e-13)
+        ref = O.level_solve(prob, U, j, f)
+        bound = max(1e-10, 8 * 2.2e-16 * np.linalg.cond(A, 1))
+        assert np.linalg.norm(u - ref) <= bound * np.linalg.norm(ref), (j, its)
+        assert its < 60
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.7, 1.8), (0.3, 1.2), (0.9, 1.99)])
+def test_symmetric_part_of_A_at_least_eta(alpha, beta):
+    """(A + A^T)/2 >= eta_j I: the central difference is skew, and the
+    shifted Grunwald part D_+ W + D_- W^T has a negative definite symmetric
+    part for 1 < beta < 2 (Sec. 3).  Hence |A^-1|_2 <= 1/eta_j, which turns a
+    true residual into a forward-error bound |u - u*|_2 <= |g - A u|_2 / eta_j."""
+    for n in (63, 256):
+        prob = W.config_large(n=n, M=512, alpha=alpha, beta=beta)
+        Q = O.matrix_Q(n)
+        assert np.array_equal(Q, -Q.T)
+        for j in (0, 1, 300):
+            A = O.level_A(prob, j)
+            e = O.level_scalars(prob, j)[0]
+            assert np.linalg.eigvalsh((A + A.T) / 2)[0] >= e * (1 - 1e-12)
