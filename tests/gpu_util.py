@@ -5,6 +5,8 @@ import numpy as np
 import pytest
 import torch
 
+import oracle as O
+
 
 def need_gpu():
     if not torch.cuda.is_available():
@@ -33,3 +35,21 @@ def relerr(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def sample_rows(n, seed, k=48, width=1024):
+    """Both ends, the tile and row boundaries of a `width`-wide transform,
+    the middle, and k random rows."""
+    fixed = [0, 1, 2, width // 2 - 1, width // 2, width - 1, width, width + 1, 2 * width - 1,
+             n // 2 - 1, n // 2, n // 2 + 1, n - width - 1, n - 2, n - 1]
+    rnd = np.random.default_rng(seed).integers(0, n, size=k)
+    return np.unique(np.concatenate([fixed, rnd]))
+
+
+def row_scale(prob, j, x):
+    """S = (eta + sigma (|gamma|/h + (d+ + d-) h^-beta sum|omega|)) max|x|,
+    an upper bound of sum_k |A_ik x_k| for every row i."""
+    e, gam, dp, dm = O.level_scalars(prob, j)
+    wsum = float(np.sum(np.abs(O.wsgd_weights(prob.beta, prob.n + 1))))
+    return (abs(e) + prob.sigma * (abs(gam) / prob.h + (dp + dm) * prob.h ** (-prob.beta) * wsum)) * float(
+        np.max(np.abs(x)))

@@ -17,7 +17,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from gpu_util import banner, host, need_gpu, t64
+from gpu_util import banner, host, need_gpu, row_scale, sample_rows, t64
 
 pytestmark = pytest.mark.gpu
 
@@ -35,21 +35,6 @@ def _gpu():
 def make(prob, **kw):
     import paper_1603_00279_amd as P
     return P.TimeLevelSolver.from_problem(prob, **kw)
-
-
-def sample_rows(n, seed, k=48):
-    """Both ends, the tile and row boundaries of a 1024-wide transform, the
-    middle, and k random rows."""
-    fixed = [0, 1, 2, 511, 512, 1023, 1024, 1025, 2047, n // 2 - 1, n // 2, n // 2 + 1, n - 1025, n - 2, n - 1]
-    rnd = np.random.default_rng(seed).integers(0, n, size=k)
-    return np.unique(np.concatenate([fixed, rnd]))
-
-
-def row_scale(prob, j, x):
-    e, gam, dp, dm = O.level_scalars(prob, j)
-    wsum = float(np.sum(np.abs(O.wsgd_weights(prob.beta, prob.n + 1))))
-    return (abs(e) + prob.sigma * (abs(gam) / prob.h + (dp + dm) * prob.h ** (-prob.beta) * wsum)) * float(
-        np.max(np.abs(x)))
 
 
 def test_spectra_full_size():
