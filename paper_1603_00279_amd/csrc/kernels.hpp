@@ -760,12 +760,15 @@ struct OutIR {
 
 // ---------------------------------------------------------------------------
 // Column pass: length-R FFTs down B adjacent columns per workgroup
-// (B*R <= 4096 complex values, i.e. 64 KiB, per workgroup).
+// (B*R <= TSF_COL_TILE complex values per workgroup, at least one column).
 // ---------------------------------------------------------------------------
+#ifndef TSF_COL_TILE
+#define TSF_COL_TILE 4096
+#endif
 template <int R, int EMAX> struct ColGeo {
     static constexpr int E = Geo<R, EMAX>::E;
     static constexpr int T = Geo<R, EMAX>::T;
-    static constexpr int B0 = 4096 / R;
+    static constexpr int B0 = TSF_COL_TILE / R > 0 ? TSF_COL_TILE / R : 1;
     static constexpr int B = (B0 * T > 1024) ? 1024 / T : B0;  // columns per workgroup
     static constexpr int NT = B * T;                            // threads per workgroup
 };
