@@ -78,8 +78,8 @@ struct SymParams {
 // a one-workgroup finishing kernel then sums the partials in index order.
 // The kernel boundary makes the partials visible, so no device-scope fence
 // (which on gfx950 writes back and invalidates the XCD's L2) is needed.  The
-// finishing kernel runs with the pass's own thread count, so the summation
-// order is fixed by the pass geometry alone and results are reproducible.
+// summation order is fixed by the pass geometry and a 256-wide layout of the
+// final sum, so results are reproducible.
 // ---------------------------------------------------------------------------
 template <int NACC>
 __device__ __forceinline__ void block_partial(double (&acc)[NACC], double *partials, int64_t slot) {
@@ -104,32 +104,39 @@ __device__ __forceinline__ void block_partial(double (&acc)[NACC], double *parti
     }
 }
 
-// Sum of nparts partials (every thread of the workgroup takes part, and every
-// thread gets the same totals).
+// Sum of nparts partials; every thread gets the same totals.  The order is
+// fixed by a 256-wide layout whatever the workgroup size (at least 256
+// threads): thread t < 256 adds partials t, t + 256, ... in turn, then the
+// 64-lane trees of waves 0..3 and their four sums.  A finishing kernel and a
+// pass of another thread count that folds the same step therefore agree bit
+// for bit.
+constexpr int RED_WIDTH = 256;
 template <int NACC>
 __device__ __forceinline__ void reduce_partials(const double *partials, int nparts, double (&tot)[NACC]) {
-    __shared__ double red[NACC][16];
+    __shared__ double red[NACC][RED_WIDTH / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nwave = (blockDim.x + 63) >> 6;
     double loc[NACC];
 #pragma unroll
     for (int a = 0; a < NACC; ++a) loc[a] = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    if (threadIdx.x < RED_WIDTH) {
+        for (int i = threadIdx.x; i < nparts; i += RED_WIDTH) {
 #pragma unroll
-        for (int a = 0; a < NACC; ++a) loc[a] += partials[(size_t)i * NACC + a];
+            for (int a = 0; a < NACC; ++a) loc[a] += partials[(size_t)i * NACC + a];
+        }
     }
 #pragma unroll
     for (int a = 0; a < NACC; ++a) {
         double v = loc[a];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) red[a][wave] = v;
+        if (lane == 0 && wave < RED_WIDTH / 64) red[a][wave] = v;
     }
     __syncthreads();
 #pragma unroll
     for (int a = 0; a < NACC; ++a) {
         double s = 0.0;
-        for (int w = 0; w < nwave; ++w) s += red[a][w];
+#pragma unroll
+        for (int w = 0; w < RED_WIDTH / 64; ++w) s += red[a][w];
         tot[a] = s;
     }
 }
@@ -759,18 +766,22 @@ struct OutIR {
 #endif
 
 // ---------------------------------------------------------------------------
-// Column pass: length-R FFTs down B adjacent columns per workgroup
-// (B*R <= TSF_COL_TILE complex values per workgroup, at least one column).
+// Column pass: length-R FFTs down B adjacent columns per workgroup, B * R =
+// 4096 values (64 KiB), except for columns of 512: four of them, so that the
+// 1024 columns of a 2^20-point problem's preconditioner transform give a
+// workgroup per CU (eight left half the CUs idle; measured 8% slower).
+// Narrower tiles split the 128-byte lines of a row (measured slower).
 // ---------------------------------------------------------------------------
-#ifndef TSF_COL_TILE
-#define TSF_COL_TILE 4096
-#endif
+constexpr int LDS_VALUES = 163840 / 16;  // complex doubles in a CU's LDS
 template <int R, int EMAX> struct ColGeo {
     static constexpr int E = Geo<R, EMAX>::E;
     static constexpr int T = Geo<R, EMAX>::T;
-    static constexpr int B0 = TSF_COL_TILE / R > 0 ? TSF_COL_TILE / R : 1;
+    static constexpr int B0 = R == 512 ? 4 : 4096 / R;
     static constexpr int B = (B0 * T > 1024) ? 1024 / T : B0;  // columns per workgroup
     static constexpr int NT = B * T;                            // threads per workgroup
+    // the partial sums reduce in a fixed 256-wide order (reduce_partials)
+    static_assert(NT >= 256 && NT <= 1024, "column pass workgroup size");
+    static_assert(lpad_size(R) * B + R <= LDS_VALUES - 64, "data slab and twiddle table fit in LDS");
 };
 
 template <class Out, int NP> struct ColSink {

@@ -577,17 +577,6 @@ hipError_t launch_final(tsfcde_plan_s *pl, const RT &rt, const Out &out, int pre
     }
 }
 
-// Threads per workgroup of a column pass of `rt`.
-int col_nt(const RT &rt) {
-    switch (rt.R) {
-#define TSF_CASE(P) \
-    case P: return ColGeo<P, TSF_E_COL>::NT;
-        TSF_SIZES(TSF_CASE)
-#undef TSF_CASE
-        default: return 0;
-    }
-}
-
 // Workgroups of a column pass of `rt` (the partials its reduction leaves).
 int col_grid(const RT &rt) {
     switch (rt.R) {
@@ -886,14 +875,12 @@ hipError_t cgs_iter(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x) {
 }
 
 // `len` CGS iterations with their finishing steps folded (two launches fewer
-// per iteration), the same arithmetic bit for bit: the folding passes sum the
-// partials with the thread count of the finishing kernel.  On the
-// power-of-two path the folding passes run on the preconditioner transform,
-// so folding needs its column geometry to have the product's thread count.
+// per iteration), the same arithmetic bit for bit: the partial sums reduce
+// in an order that does not depend on the reducing workgroup's size.
 template <class S, class CS>
 hipError_t cgs_chunk(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS> &b, S *x, int len) {
     hipError_t e = hipSuccess;
-    if ((pl->flags & TSFCDE_FLAG_NO_FOLD) || (pl->p2 && col_nt(pl->P) != col_nt(pl->A))) {
+    if (pl->flags & TSFCDE_FLAG_NO_FOLD) {
         for (int k = 0; k < len && e == hipSuccess; ++k) e = cgs_iter(pl, j, b, x);
         return e;
     }

@@ -384,14 +384,15 @@ def test_sampled_profiling_counts_and_leaves_results():
     assert np.array_equal(U0, U1)
 
 
-@pytest.mark.parametrize("n,fp32", [(256, False), (1024, False), (4096, False), (1000, False), (2048, True)])
+@pytest.mark.parametrize("n,fp32", [(128, False), (256, False), (1024, False), (4096, False), (1 << 18, False),
+                                    (1 << 20, False), (1000, False), (2048, True)])
 def test_folded_finishing_is_bitwise_unfolded(n, fp32):
     """The finishing steps of the Krylov reductions folded into the passes
     that follow them give the same march bit for bit, with the same
     iteration counts, as separate finishing kernels (TSFCDE_FLAG_NO_FOLD),
     for the FP64 solve (power-of-two and general n) and the FP32 inner solve
-    of the refined form (on the power-of-two path folding applies from
-    n = 256, where the two column geometries share a thread count)."""
+    of the refined form.  At n = 128, 2^18 and 2^20 the folding pass and the
+    finishing kernel run with different thread counts."""
     import paper_1603_00279_amd as P
     banner(f"folded finishing n={n} fp32={fp32}")
     prob = W.config_large(n=n, M=10)
