@@ -1,0 +1,29 @@
+"""Host-side parts of bench.py (CPU only): the refusal of more than one GPU,
+and the CPU-baseline record, which times the oracle on a bounded sample."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_cpu_baseline_record():
+    """A short sample: the FFT-PCGS oracle at n = 2^10 on the first levels,
+    the dense-LU oracle beside it; the fields the bench line carries."""
+    sys.path.insert(0, ROOT)
+    import bench
+    rec = bench.cpu_baseline(1 << 10, 16, 1e-10, budget_s=1.0, lu_budget_s=0.5)
+    assert rec["kind"] == "oracle" and rec["unit"] == "level-solves/s" and rec["cores"] == 1
+    assert rec["value"] > 0 and "FFT-PCGS oracle" in rec["sample"]
+    lu = rec["dense_lu"]
+    assert lu["levels"] >= 1 and lu["measured_n"] == 2048
+    assert abs(lu["value_extrapolated"] - lu["measured_value"] * (2048 / 1024) ** 3) <= 1e-9 * lu["value_extrapolated"]
