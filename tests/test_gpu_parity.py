@@ -154,10 +154,16 @@ def test_march_small_config(warm):
     assert max(its) <= 40
 
 
-@pytest.mark.parametrize("n,M,alpha,beta", [(256, 24, 0.7, 1.8), (1024, 12, 0.3, 1.2), (4096, 6, 0.9, 1.95)])
+@pytest.mark.parametrize("n,M,alpha,beta", [(256, 24, 0.7, 1.8), (1024, 12, 0.3, 1.2), (4096, 6, 0.9, 1.95),
+                                             (4, 1, 0.5, 1.5), (16, 8, 1.0, 2.0), (7, 5, 1.0, 1.5),
+                                             (17, 6, 0.1, 1.05)])
 def test_march_parity_sizes(n, M, alpha, beta):
     """Whole marches; per level the bar is 1e-10 or 8 eps cond_1(A_j) where
-    that is larger (cond_1 ~ 1e7 at n = 4096, beta = 1.95)."""
+    that is larger (cond_1 ~ 1e7 at n = 4096, beta = 1.95).  The edge cases:
+    the smallest n with a single level, alpha = 1 (Crank-Nicolson in time)
+    with beta = 2 (the classical second difference) on the smallest
+    power-of-two path, alpha = 1 on the general path, and alpha, beta near
+    their lower ends."""
     import paper_1603_00279_amd as P
     banner(f"march n={n} M={M}")
     prob = W.config_large(n=n, M=M, alpha=alpha, beta=beta)
