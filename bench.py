@@ -42,6 +42,17 @@ def log(msg):
 HB = 8  # levels per history block (one sweep over the stored levels per block)
 
 
+def path_bytes(n, M, levels, iters):
+    """Algorithmic HBM bytes of one march step, FP64, by the method's byte
+    model: a CGS iteration makes two Toeplitz products (three passes over the
+    transform: 12 * 8n each), two preconditioner solves (7 * 8n each) and the
+    fused vector updates and reductions (14 * 8n), 416n in all; a level adds
+    its right-hand side (one product shared with r0, f read, g written:
+    14 * 8n) and its share of the history sum (history_bytes)."""
+    hist, _ = history_bytes(n, M, levels)
+    return 416 * n * sum(iters) + 112 * n * levels + hist
+
+
 def history_bytes(n, M, levels):
     """Algorithmic HBM bytes and launches of the history kernels over levels
     0..levels-1: at a block's first level b the sweep reads u^0..u^{b-1} and
@@ -412,6 +423,11 @@ def main():
                                f"gamma=-(1+t)/2, d+=1+t, d-=(1+t)/2, zero initial guess, rtol={args.rtol}",
                    "n": n, "M": prob.M, "levels_per_step": levels, "rtol": args.rtol,
                    "warm_start": "previous level" if args.warm_start else "zero"},
+        "path_roofline": {"bound": "hbm", "bytes_per_step": path_bytes(n, prob.M, levels, iters),
+                          "achieved": path_bytes(n, prob.M, levels, iters) * args.steps / elapsed / 1e9,
+                          "peak": peak, "unit": "GB/s",
+                          "frac": path_bytes(n, prob.M, levels, iters) * args.steps / elapsed / 1e9 / peak,
+                          "model": "416n B per CGS iteration, 112n B per right-hand side, plus the history"},
         "roofline": {"bound": "hbm", "kernel": args.profile_class, "achieved": achieved, "peak": peak,
                      "unit": "GB/s", "frac": achieved / peak, "traffic": None,
                      "sampled_launches": launches, "sample_period": period, "issued_launches": issued,

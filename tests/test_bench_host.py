@@ -27,3 +27,14 @@ def test_cpu_baseline_record():
     lu = rec["dense_lu"]
     assert lu["levels"] >= 1 and lu["measured_n"] == 2048
     assert abs(lu["value_extrapolated"] - lu["measured_value"] * (2048 / 1024) ** 3) <= 1e-9 * lu["value_extrapolated"]
+
+
+def test_path_bytes_model():
+    """One level: k CGS iterations at 416n bytes each plus the right-hand side
+    at 112n; two levels add the first block's history sweep (u^0 read, the
+    block's sums written)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    n = 1000
+    assert bench.path_bytes(n, 16, 1, [7]) == 416 * n * 7 + 112 * n
+    assert bench.path_bytes(n, 16, 2, [7, 5]) == 416 * n * 12 + 112 * n * 2 + 8 * n * (1 + 8)
