@@ -936,11 +936,16 @@ template <int NS_, class CS> struct BufSink {  // y[pos*C + c] = val * tw(2*pos*
     }
 };
 
+#ifndef TSF_E_FUSE_P  // values per lane of the fused pass's preconditioner transform
+#define TSF_E_FUSE_P 8
+#endif
 template <int RP, int EMAX> struct FuseGeo {
     static constexpr int RA = 2 * RP;
     using GA = ColGeo<RA, EMAX>;
     static constexpr int EA = GA::E, TA = GA::T, B = GA::B, NT = GA::NT;
-    static constexpr int EP = Geo<RP, EA>::E, TP = Geo<RP, EA>::T;
+    static constexpr int EPM = TSF_E_FUSE_P < EA ? TSF_E_FUSE_P : EA;
+    static constexpr int EP = Geo<RP, EPM>::E, TP = Geo<RP, EPM>::T;
+    static_assert(TP <= TA, "the preconditioner transform's lanes fit in the workgroup");
 };
 
 template <int RP, int EMAX, class Op, class CS>
