@@ -764,6 +764,12 @@ struct OutIR {
 #ifndef TSF_E_FUSE
 #define TSF_E_FUSE 8
 #endif
+// Column passes of length 512 (single plans) run four columns of 64 lanes
+// at eight values per lane, four waves per CU at n = 2^20; four values per
+// lane double the waves and were 4-6% faster (measured).
+#ifndef TSF_E_COL_512
+#define TSF_E_COL_512 4
+#endif
 // The preconditioner's middle pass has half the rows of the product's (one
 // workgroup per CU at n = 2^20); four values per lane give it twice the
 // waves, which outweighs its unpaired last stage (5% faster, measured), for

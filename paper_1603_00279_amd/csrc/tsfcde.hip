@@ -532,11 +532,14 @@ void launch_timed(tsfcde_plan_s *pl, int cls, K kernel, dim3 grid, dim3 block, A
 
 // finish = false leaves a reducing pass's finishing kernel to the caller
 // (a later pass folds it in, or it is launched with launch_final).
+// Values per lane of a single plan's column pass of length R.
+template <int R> constexpr int col_e() { return R == 512 ? TSF_E_COL_512 : TSF_E_COL; }
+
 template <int R, int DIR, class In, class Out>
 hipError_t launch_col_t(tsfcde_plan_s *pl, int64_t C, const In &in, const Out &out, int pred, bool finish) {
-    using G = ColGeo<R, TSF_E_COL>;
+    using G = ColGeo<R, col_e<R>()>;
     const int64_t grid = (C + G::B - 1) / G::B;
-    launch_timed(pl, 1, k_col<R, TSF_E_COL, DIR, In, Out>, dim3((unsigned)grid), dim3(G::NT), C, in, out,
+    launch_timed(pl, 1, k_col<R, col_e<R>(), DIR, In, Out>, dim3((unsigned)grid), dim3(G::NT), C, in, out,
                  (const double2 *)pl->tw_all, pl->sc, pred);
     if constexpr (Out::NACC > 0) {
         if (finish)
@@ -549,7 +552,7 @@ hipError_t launch_col_t(tsfcde_plan_s *pl, int64_t C, const In &in, const Out &o
 // Finishing kernel of a column pass of `rt` launched without its own.
 template <int R, class Out>
 hipError_t launch_final_t(tsfcde_plan_s *pl, int64_t C, const Out &out, int pred) {
-    using G = ColGeo<R, TSF_E_COL>;
+    using G = ColGeo<R, col_e<R>()>;
     hipLaunchKernelGGL((k_final<G::NT, Out>), dim3(1), dim3(G::NT), 0, pl->stream, out, (int)((C + G::B - 1) / G::B),
                        pl->sc, pred);
     return hipGetLastError();
@@ -581,7 +584,7 @@ hipError_t launch_final(tsfcde_plan_s *pl, const RT &rt, const Out &out, int pre
 int col_grid(const RT &rt) {
     switch (rt.R) {
 #define TSF_CASE(P) \
-    case P: return (int)((rt.C + ColGeo<P, TSF_E_COL>::B - 1) / ColGeo<P, TSF_E_COL>::B);
+    case P: return (int)((rt.C + ColGeo<P, col_e<P>()>::B - 1) / ColGeo<P, col_e<P>()>::B);
         TSF_SIZES(TSF_CASE)
 #undef TSF_CASE
         default: return 0;
