@@ -770,6 +770,9 @@ struct OutIR {
 #ifndef TSF_E_COL_512
 #define TSF_E_COL_512 4
 #endif
+#ifndef TSF_E_COL_1024  // column passes of length 1024 (single plans)
+#define TSF_E_COL_1024 TSF_E_COL
+#endif
 // The preconditioner's middle pass has half the rows of the product's (one
 // workgroup per CU at n = 2^20); four values per lane give it twice the
 // waves, which outweighs its unpaired last stage (5% faster, measured), for

@@ -533,7 +533,9 @@ void launch_timed(tsfcde_plan_s *pl, int cls, K kernel, dim3 grid, dim3 block, A
 // finish = false leaves a reducing pass's finishing kernel to the caller
 // (a later pass folds it in, or it is launched with launch_final).
 // Values per lane of a single plan's column pass of length R.
-template <int R> constexpr int col_e() { return R == 512 ? TSF_E_COL_512 : TSF_E_COL; }
+template <int R> constexpr int col_e() {
+    return R == 512 ? TSF_E_COL_512 : (R == 1024 ? TSF_E_COL_1024 : TSF_E_COL);
+}
 
 template <int R, int DIR, class In, class Out>
 hipError_t launch_col_t(tsfcde_plan_s *pl, int64_t C, const In &in, const Out &out, int pred, bool finish) {
