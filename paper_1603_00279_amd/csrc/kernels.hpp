@@ -773,6 +773,9 @@ struct OutIR {
 #ifndef TSF_E_COL_1024  // column passes of length 1024 (single plans)
 #define TSF_E_COL_1024 TSF_E_COL
 #endif
+#ifndef TSF_E_COL_2048  // column passes of length 2048 (single plans)
+#define TSF_E_COL_2048 TSF_E_COL
+#endif
 // The preconditioner's middle pass has half the rows of the product's (one
 // workgroup per CU at n = 2^20); four values per lane give it twice the
 // waves, which outweighs its unpaired last stage (5% faster, measured), for
