@@ -593,6 +593,13 @@ int col_grid(const RT &rt) {
     }
 }
 
+// The product transform's reducing passes leave one partial per workgroup and
+// accumulator (at most two) in a site of PARTIAL_SLOTS doubles.
+bool partials_fit(const RT &A) {
+    const int g = col_grid(A);
+    return g > 0 && 2 * (int64_t)g <= PARTIAL_SLOTS;
+}
+
 template <int RP, class Op, class CS>
 hipError_t launch_fuse_t(tsfcde_plan_s *pl, const Op &op, const CS *bufP, CS *bufA, int pred) {
     if constexpr (RP > 2048) {
@@ -1311,6 +1318,7 @@ static int workspace_bytes_impl(const tsfcde_problem *prob, bool force_general, 
     if (!bytes) return TSFCDE_EINVAL;
     RT A, P, B;
     const bool p2 = rt_setup(A, P, B, prob->n, force_general);
+    if (!partials_fit(A)) return TSFCDE_EUNSUPPORTED;
     *bytes = layout_for(prob->n, prob->M, A, P, B, p2, prob->precision == TSFCDE_FP32_REFINED).total;
     return TSFCDE_OK;
 }
@@ -1326,6 +1334,11 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
     int rc = validate(prob);
     if (rc) return rc;
     if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255)) return TSFCDE_EINVAL;
+    {
+        RT A, P, B;
+        rt_setup(A, P, B, prob->n, force_general);
+        if (!partials_fit(A)) return TSFCDE_EUNSUPPORTED;
+    }
     const int64_t n = prob->n, M = prob->M;
     tsfcde_plan_s *pl = new (std::nothrow) tsfcde_plan_s();
     if (!pl) return TSFCDE_ENOMEM;
