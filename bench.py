@@ -53,6 +53,15 @@ def path_bytes(n, M, levels, iters):
     return 416 * n * sum(iters) + 112 * n * levels + hist
 
 
+def fused_bytes(n, M, levels, iters):
+    """The same march's bytes as the fused power-of-two path moves them: 45
+    units of 8n per CGS iteration (ten passes, the vector updates folded into
+    them), 20 units per level (right-hand side and acceptance products with
+    their epilogues), plus the history."""
+    hist, _ = history_bytes(n, M, levels)
+    return 360 * n * sum(iters) + 160 * n * levels + hist
+
+
 def history_bytes(n, M, levels):
     """Algorithmic HBM bytes and launches of the history kernels over levels
     0..levels-1: at a block's first level b the sweep reads u^0..u^{b-1} and
@@ -427,7 +436,9 @@ def main():
                           "achieved": path_bytes(n, prob.M, levels, iters) * args.steps / elapsed / 1e9,
                           "peak": peak, "unit": "GB/s",
                           "frac": path_bytes(n, prob.M, levels, iters) * args.steps / elapsed / 1e9 / peak,
-                          "model": "416n B per CGS iteration, 112n B per right-hand side, plus the history"},
+                          "model": "416n B per CGS iteration, 112n B per right-hand side, plus the history",
+                          "fused_bytes_per_step": fused_bytes(n, prob.M, levels, iters),
+                          "fused_frac": fused_bytes(n, prob.M, levels, iters) * args.steps / elapsed / 1e9 / peak},
         "roofline": {"bound": "hbm", "kernel": args.profile_class, "achieved": achieved, "peak": peak,
                      "unit": "GB/s", "frac": achieved / peak, "traffic": None,
                      "sampled_launches": launches, "sample_period": period, "issued_launches": issued,

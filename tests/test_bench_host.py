@@ -38,3 +38,12 @@ def test_path_bytes_model():
     n = 1000
     assert bench.path_bytes(n, 16, 1, [7]) == 416 * n * 7 + 112 * n
     assert bench.path_bytes(n, 16, 2, [7, 5]) == 416 * n * 12 + 112 * n * 2 + 8 * n * (1 + 8)
+
+
+def test_fused_bytes_model():
+    """The fused path: 45 units of 8n per CGS iteration, 20 per level, plus
+    the history (here none: one level)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    n = 1000
+    assert bench.fused_bytes(n, 16, 1, [7]) == 8 * n * (45 * 7 + 20)
