@@ -1450,6 +1450,22 @@ struct HistBlock {
     int b, nl;         // first level of the block, levels in it (<= HB)
 };
 
+// The sweep reads every stored level once per block; with TSF_HIST_NT its
+// loads carry the non-temporal hint, so that the stream does not displace the
+// solve's working set from the caches.
+#ifndef TSF_HIST_NT
+#define TSF_HIST_NT 0
+#endif
+__device__ __forceinline__ double2 ld_sweep(const double *p) {
+#if TSF_HIST_NT
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    const v2d v = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(p));
+    return make_double2(v.x, v.y);
+#else
+    return *reinterpret_cast<const double2 *>(p);
+#endif
+}
+
 __device__ __forceinline__ void hist_sweep_pair(const double *__restrict__ U, int64_t ldu,
                                                 const double *__restrict__ cbase, const HistBlock &hb, double kappa,
                                                 double *__restrict__ Q, int64_t i) {
@@ -1476,11 +1492,11 @@ __device__ __forceinline__ void hist_sweep_pair(const double *__restrict__ U, in
     for (; s + U8 <= full; s += U8) {
         double2 x[U8];
 #pragma unroll
-        for (int q = 0; q < U8; ++q) x[q] = *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1 + q) * ldu + i);
+        for (int q = 0; q < U8; ++q) x[q] = ld_sweep(U + (int64_t)(s + 1 + q) * ldu + i);
 #pragma unroll
         for (int q = 0; q < U8; ++q) add(s + q, x[q]);
     }
-    for (; s < full; ++s) add(s, *reinterpret_cast<const double2 *>(U + (int64_t)(s + 1) * ldu + i));
+    for (; s < full; ++s) add(s, ld_sweep(U + (int64_t)(s + 1) * ldu + i));
     acc[0].x = fma(-hb.c1b, prev.x, acc[0].x);  // prev = u^{b-1}
     acc[0].y = fma(-hb.c1b, prev.y, acc[0].y);
 #pragma unroll
