@@ -780,6 +780,9 @@ struct OutIR {
 // workgroup per CU at n = 2^20); four values per lane give it twice the
 // waves, which outweighs its unpaired last stage (5% faster, measured), for
 // rows of up to 1024 points.
+#ifndef TSF_E_MID_4096  // middle passes with rows of 4096 (single plans)
+#define TSF_E_MID_4096 TSF_E_MID
+#endif
 #ifndef TSF_E_MID_SOLVE  // middle pass of the preconditioner solve (single plans)
 #define TSF_E_MID_SOLVE 4
 #endif
@@ -1108,18 +1111,24 @@ __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, doubl
     // row loads and the forward transform: spectrum values and untangle twiddles
     // of this thread's pairs (rows ra, rb with ra != 0), and the stage twiddles.
     constexpr int NPT = (C_ + G::NT - 1) / G::NT;
-    double2 pLa[NPT], pLb[NPT], pW[NPT];
-    if (wg != 0) {
+    // rows of 4096 would hold these operands across the transform in more
+    // registers than a 1024-thread workgroup has; they load them in the pair
+    // step instead
+    constexpr bool PF = C_ <= 2048;
+    double2 pLa[PF ? NPT : 1], pLb[PF ? NPT : 1], pW[PF ? NPT : 1];
+    if constexpr (PF) {
+        if (wg != 0) {
 #pragma unroll
-        for (int i = 0; i < NPT; ++i) {
-            const int k2 = t + G::NT * i;
-            pLa[i] = pLb[i] = pW[i] = make_double2(0.0, 0.0);
-            if (k2 < C_) {
-                if constexpr (MODE != 2) {
-                    pLa[i] = ldc(spec, ra * C + k2);
-                    pLb[i] = ldc(spec, rb * C + (C_ - 1 - k2));
+            for (int i = 0; i < NPT; ++i) {
+                const int k2 = t + G::NT * i;
+                pLa[i] = pLb[i] = pW[i] = make_double2(0.0, 0.0);
+                if (k2 < C_) {
+                    if constexpr (MODE != 2) {
+                        pLa[i] = ldc(spec, ra * C + k2);
+                        pLb[i] = ldc(spec, rb * C + (C_ - 1 - k2));
+                    }
+                    pW[i] = twL(ra + R * k2);
                 }
-                pW[i] = twL(ra + R * k2);
             }
         }
     }
@@ -1142,7 +1151,13 @@ __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, doubl
             double2 za = s0[lpad(k2)], zb = s1[lpad(k2b)];
             const int64_t pa = ra * C + k2, pb = rb * C + k2b;
             double2 xa, xb;
-            pair_update<MODE>(za, zb, pW[i], pLa[i], pLb[i], sp, &xa, &xb);
+            if constexpr (PF) {
+                pair_update<MODE>(za, zb, pW[i], pLa[i], pLb[i], sp, &xa, &xb);
+            } else {
+                const double2 La = MODE != 2 ? ldc(spec, pa) : make_double2(0.0, 0.0);
+                const double2 Lb = MODE != 2 ? ldc(spec, pb) : make_double2(0.0, 0.0);
+                pair_update<MODE>(za, zb, twL(ra + R * k2), La, Lb, sp, &xa, &xb);
+            }
             if constexpr (MODE == 2) {
                 spec_out[pa] = xa;
                 spec_out[pb] = xb;
