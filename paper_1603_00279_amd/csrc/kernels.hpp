@@ -780,8 +780,11 @@ struct OutIR {
 // workgroup per CU at n = 2^20); four values per lane give it twice the
 // waves, which outweighs its unpaired last stage (5% faster, measured), for
 // rows of up to 1024 points.
+// Rows of 4096 at eight values per lane need 1024-thread workgroups (128
+// VGPRs a lane, spilling); sixteen values per lane give 512 threads with no
+// spill, and the pass ran 32% faster (measured at n = 2^24).
 #ifndef TSF_E_MID_4096  // middle passes with rows of 4096 (single plans)
-#define TSF_E_MID_4096 TSF_E_MID
+#define TSF_E_MID_4096 16
 #endif
 #ifndef TSF_E_MID_SOLVE  // middle pass of the preconditioner solve (single plans)
 #define TSF_E_MID_SOLVE 4
