@@ -776,6 +776,13 @@ struct OutIR {
 #ifndef TSF_E_COL_2048  // column passes of length 2048 (single plans)
 #define TSF_E_COL_2048 TSF_E_COL
 #endif
+// Columns of 4096 at eight values per lane fit one per workgroup (16-byte
+// row segments); at sixteen, two columns of 256 lanes, with the twiddles
+// read from the global table: 6% faster per iteration at n = 2^24 despite
+// register spills (measured; columns of 2048 gained nothing).
+#ifndef TSF_E_COL_4096  // column passes of length 4096 (single plans)
+#define TSF_E_COL_4096 16
+#endif
 // The preconditioner's middle pass has half the rows of the product's (one
 // workgroup per CU at n = 2^20); four values per lane give it twice the
 // waves, which outweighs its unpaired last stage (5% faster, measured), for
@@ -801,12 +808,16 @@ constexpr int LDS_VALUES = 163840 / 16;  // complex doubles in a CU's LDS
 template <int R, int EMAX> struct ColGeo {
     static constexpr int E = Geo<R, EMAX>::E;
     static constexpr int T = Geo<R, EMAX>::T;
-    static constexpr int B0 = R == 512 ? 4 : 4096 / R;
+    // at sixteen values per lane, columns of 2048 and 4096 take 8192 values
+    // per workgroup (four and two columns at 512 threads)
+    static constexpr int B0 = R == 512 ? 4 : (R >= 2048 && E >= 16 ? 8192 / R : 4096 / R);
     static constexpr int B = (B0 * T > 1024) ? 1024 / T : B0;  // columns per workgroup
     static constexpr int NT = B * T;                            // threads per workgroup
+    // the twiddle table is staged in LDS when it fits beside the data
+    static constexpr bool TWL = R > E && lpad_size(R) * B + R <= LDS_VALUES - 64;
     // the partial sums reduce in a fixed 256-wide order (reduce_partials)
     static_assert(NT >= 256 && NT <= 1024, "column pass workgroup size");
-    static_assert(lpad_size(R) * B + R <= LDS_VALUES - 64, "data slab and twiddle table fit in LDS");
+    static_assert(lpad_size(R) * B <= LDS_VALUES - 64, "data slab fits in LDS");
 };
 
 template <class Out, int NP> struct ColSink {
@@ -826,7 +837,7 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
     using G = ColGeo<R, EMAX>;
     constexpr int E = G::E, T = G::T, B = G::B;
     __shared__ double2 lds[lpad_size(R) * B];
-    __shared__ double2 twl[R];
+    __shared__ double2 twl[G::TWL ? R : 1];
     const int t = threadIdx.x;
     const int b = t % B, j = t / B;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -856,12 +867,12 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = active ? in.finish(j + T * m, c, raw[m]) : make_double2(0.0, 0.0);
     // the first barrier inside the transform orders these writes before any use
-    stage_twiddles<R>(twl, tw_all, t, G::NT);
+    if constexpr (G::TWL) stage_twiddles<R>(twl, tw_all, t, G::NT);
     double acc[Out::NACC > 0 ? Out::NACC : 1];
 #pragma unroll
     for (int a = 0; a < (Out::NACC > 0 ? Out::NACC : 1); ++a) acc[a] = 0.0;
     ColSink<Out, NP> sink{&out, c, acc, pre};
-    if constexpr (R > E) {
+    if constexpr (G::TWL) {
         fft_t<R, E, DIR, 1>(v, j, active, twl, lds + b, B, sink);
     } else {
         fft<R, E, DIR>(v, j, active, tw_all, lds + b, B, sink);

@@ -534,7 +534,11 @@ void launch_timed(tsfcde_plan_s *pl, int cls, K kernel, dim3 grid, dim3 block, A
 // (a later pass folds it in, or it is launched with launch_final).
 // Values per lane of a single plan's column pass of length R.
 template <int R> constexpr int col_e() {
-    return R == 512 ? TSF_E_COL_512 : (R == 1024 ? TSF_E_COL_1024 : (R == 2048 ? TSF_E_COL_2048 : TSF_E_COL));
+    return R == 512    ? TSF_E_COL_512
+           : R == 1024 ? TSF_E_COL_1024
+           : R == 2048 ? TSF_E_COL_2048
+           : R == 4096 ? TSF_E_COL_4096
+                       : TSF_E_COL;
 }
 
 template <int R, int DIR, class In, class Out>
