@@ -609,10 +609,11 @@ hipError_t launch_fuse_t(tsfcde_plan_s *pl, const Op &op, const CS *bufP, CS *bu
     if constexpr (RP > 2048) {
         return hipErrorInvalidValue;
     } else {
-        using G = FuseGeo<RP, TSF_E_FUSE>;
+        constexpr int EF = RP == 2048 ? TSF_E_FUSE_4096 : TSF_E_FUSE;
+        using G = FuseGeo<RP, EF>;
         const int64_t C = pl->A.C;
         const int64_t grid = (C + G::B - 1) / G::B;
-        launch_timed(pl, 5, k_fuse<RP, TSF_E_FUSE, Op, CS>, dim3((unsigned)grid), dim3(G::NT), C, bufP, pl->P.tw,
+        launch_timed(pl, 5, k_fuse<RP, EF, Op, CS>, dim3((unsigned)grid), dim3(G::NT), C, bufP, pl->P.tw,
                      bufA, pl->A.tw, op, (const double2 *)pl->tw_all, pl->sc, pred);
         return hipGetLastError();
     }
