@@ -609,7 +609,7 @@ hipError_t launch_fuse_t(tsfcde_plan_s *pl, const Op &op, const CS *bufP, CS *bu
     if constexpr (RP > 2048) {
         return hipErrorInvalidValue;
     } else {
-        constexpr int EF = RP == 2048 ? TSF_E_FUSE_4096 : TSF_E_FUSE;
+        constexpr int EF = RP == 2048 ? TSF_E_FUSE_4096 : (RP == 1024 ? TSF_E_FUSE_2048 : TSF_E_FUSE);
         using G = FuseGeo<RP, EF>;
         const int64_t C = pl->A.C;
         const int64_t grid = (C + G::B - 1) / G::B;
