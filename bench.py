@@ -10,7 +10,11 @@ stopped at |r_k| <= 1e-10 |g| from a zero initial guess (the plain method).
 One step = one whole march of M levels (right-hand side with the history sum
 and the preconditioned Krylov solve at every level).  value = levels solved
 per second over the timed steps.  Source vectors f(x_i, t_{j+sigma}) for all
-levels are built on the device before timing (inputs resident in HBM).
+levels are built on the device before timing (inputs resident in HBM), at
+the plan's own nodes and sampling instants.  Every timed level must pass the
+library's acceptance test; the line records the largest backward error and
+true residual, the restarts and the failed levels, and the script exits
+non-zero when a level failed.
 
 Prints one JSON line.
 """
@@ -81,15 +85,24 @@ def history_bytes(n, M, levels):
 KCLASS = {"history": 0, "col_passes": 1, "mid_matvec": 2, "cgs_chunks": 3, "mid_precond": 4, "fused_cols": 5}
 
 
-def build_sources(prob, device):
-    import numpy as np
+def build_sources(prob, solver):
+    """f at the plan's nodes x_i and instants t_{j+sigma} for every level: one
+    (M x 4) @ (4 x n) product of the manufactured source's separable form."""
     import torch
-    prof, coef = prob.source_profiles()
-    P = torch.as_tensor(prof, dtype=torch.float64, device=device)
-    Cf = torch.as_tensor(coef, dtype=torch.float64, device=device)
-    F = Cf @ P  # (M x 4) @ (4 x n): f(x_i, t_{j+sigma}) for every level
+    import workloads as W
+    F = W.device_sources(prob, solver.nodes(), solver.level_times(), solver.device)
     torch.cuda.synchronize()
     return F
+
+
+def acceptance(stats):
+    """Acceptance summary of a list of per-level stats: the largest backward
+    error and true residual met, total restarts, failed levels."""
+    bw = [st["backward_err"] for st in stats if st["backward_err"] >= 0]
+    tr = [st["relres_true"] for st in stats if st["relres_true"] >= 0]
+    return {"levels": len(stats), "failed_levels": sum(1 for st in stats if st["code"] != 0),
+            "max_backward_err": max(bw) if bw else None, "max_relres_true": max(tr) if tr else None,
+            "restarts": sum(st["restarts"] for st in stats)}
 
 
 def committed_traffic(kclass, n):
@@ -109,7 +122,7 @@ def timed_march(solver, F, u0, levels, torch):
     solver.set_state(0, u0.view(1, -1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = [solver.step(F[j]) for j in range(levels)]
+    stats = [solver.step(F[j], raise_on_error=False) for j in range(levels)]
     torch.cuda.synchronize()
     return time.perf_counter() - t0, stats
 
@@ -138,7 +151,7 @@ def warm_forms(args, P, prob, F, u0, levels, plain_value, res):
             dt, st = timed_march(sw, F, u0, levels, torch)
         res[name] = {"workload": "headline", "value": levels / dt, "unit": "level-solves/s",
                      "cgs_iterations_mean": float(np.mean([x["iters"] for x in st])),
-                     "speedup_vs_plain": (levels / dt) / plain_value}
+                     "speedup_vs_plain": (levels / dt) / plain_value, "acceptance": acceptance(st)}
         log(f"form {name}: {levels / dt:.1f} level-solves/s")
 
 
@@ -151,12 +164,17 @@ def fp32_forms(args, P, W, prob, F, u0, levels, plain_value, dev, res):
         dt, st = timed_march(sw, F, u0, levels, torch)
     share = float(np.mean([x["precision_used"] == P.TSFCDE_FP32_REFINED for x in st]))
     res["fp32_refined"] = {"workload": "headline", "value": levels / dt, "unit": "level-solves/s",
-                           "levels_refined_in_fp32": share, "speedup_vs_plain": (levels / dt) / plain_value}
+                           "levels_refined_in_fp32": share, "acceptance": acceptance(st),
+                           "note": "the rounding-error model keeps every level of this workload in FP64 "
+                                   "(eps32 log2(L) |A|/eta is far above 0.1 at n = 2^20), so this is the FP64 "
+                                   "path; no speedup is claimed"}
     small = W.config_large(n=args.fp32_n, M=args.M)
-    Fs = build_sources(small, dev)
     rates = {}
+    Fs = None
     for prec in (P.TSFCDE_FP64, P.TSFCDE_FP32_REFINED):
         with P.TimeLevelSolver.from_problem(small, rtol=args.rtol, precision=prec) as sw:
+            if Fs is None:
+                Fs = build_sources(small, sw)
             us = sw.history()[0].clone()
             timed_march(sw, Fs, us, small.M, torch)  # warm-up
             dt, st = timed_march(sw, Fs, us, small.M, torch)
@@ -167,7 +185,7 @@ def fp32_forms(args, P, W, prob, F, u0, levels, plain_value, dev, res):
         "value": rates[P.TSFCDE_FP32_REFINED][0], "plain_value": rates[P.TSFCDE_FP64][0], "unit": "level-solves/s",
         "speedup_vs_plain": rates[P.TSFCDE_FP32_REFINED][0] / rates[P.TSFCDE_FP64][0],
         "levels_refined_in_fp32": float(np.mean([x["precision_used"] == P.TSFCDE_FP32_REFINED for x in st32])),
-        "true_relres_max": float(max(x["relres_true"] for x in st32)),
+        "true_relres_max": float(max(x["relres_true"] for x in st32)), "acceptance": acceptance(st32),
         "inner_iterations_mean": float(np.mean([x["iters"] for x in st32])),
         "outer_sweeps_mean": float(np.mean([x["outer_iters"] for x in st32]))}
     del Fs
@@ -184,28 +202,28 @@ def batched_form(args, P, W, dev):
     from paper_1603_00279_amd import warmnet as WN
     probs = W.batched_instances(count=args.batch_count, M=args.batch_M)
     ns = [p.n for p in probs]
-    profs, coefs = zip(*(p.source_profiles() for p in probs))
-    groups = {}
-    for i, p in enumerate(probs):
-        groups.setdefault(p.n, []).append(i)
-    prof = [torch.as_tensor(a, dtype=torch.float64, device=dev) for a in profs]
-    coef = [torch.as_tensor(c, dtype=torch.float64, device=dev) for c in coefs]
-    Fall = [c @ pr for c, pr in zip(coef, prof)]  # (M x n) per instance
     out = {"workload": f"{len(probs)} instances, n log-uniform in [2^10, 2^16] (sum {sum(ns)}), M={args.batch_M}"}
+    Fall = None
     for ws, key in ((P.TSFCDE_WS_ZERO, "zero_guess"), (P.TSFCDE_WS_EXTRAP, "extrapolated")):
         with P.BatchSolver(probs, rtol=args.rtol, warm_start=ws) as bs:
+            if Fall is None:  # (M x n) per instance at its own nodes and instants
+                Fall = [W.device_sources(p, bs.nodes(i), bs.level_times(i), dev) for i, p in enumerate(probs)]
             zeros = [torch.zeros(n, dtype=torch.float64, device=dev) for n in ns]
             bs.reset(zeros)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            its = []
+            its, allst = [], []
             for j in range(args.batch_M):
-                code, st = bs.step([Fi[j] for Fi in Fall])
+                code, st = bs.step([Fi[j] for Fi in Fall], raise_on_error=False)
+                for x in st:
+                    x["code"] = x["status"]
+                allst += st
                 its.append(np.mean([x["iters"] for x in st]))
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
         out[key] = {"value": len(probs) * args.batch_M / dt, "unit": "instance-levels/s",
-                    "unknown_levels_per_s": sum(ns) * args.batch_M / dt, "cgs_iterations_mean": float(np.mean(its))}
+                    "unknown_levels_per_s": sum(ns) * args.batch_M / dt, "cgs_iterations_mean": float(np.mean(its)),
+                    "acceptance": acceptance(allst)}
         log(f"batched ({key}): {out[key]['value']:.0f} instance-levels/s")
     sub = list(range(0, len(probs), max(1, len(probs) // 32)))
     tot = 0.0
@@ -242,8 +260,8 @@ def learned_form(args, P, W, dev):
                         (P.TSFCDE_WS_EXTRAP, "extrapolated"), (P.TSFCDE_WS_NET, "network")):
             tot, its, kept = 0.0, [], []
             for prob in held:
-                F = WN.device_sources(prob, dev)
                 with P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, warm_start=ws) as s1:
+                    F = WN.device_sources(prob, s1)
                     if ws == P.TSFCDE_WS_NET:
                         net.attach(s1)
                     u0 = s1.history()[0].clone()
@@ -261,49 +279,76 @@ def learned_form(args, P, W, dev):
     return out
 
 
-def cpu_baseline(n_full, M_full, rtol, budget_s=15.0, lu_budget_s=6.0):
-    """Time the CPU oracle on a bounded sample of the same march: its FFT
-    route (embedding products, Strang solve, preconditioned CGS, Sec. 4) at
-    the full n on the first levels, one host thread.  Beside it, for context,
-    the dense-LU oracle on the first levels at n = 2048 with its (2048/n)^3
-    extrapolation."""
+def host_cores():
+    """CPU threads this process may run on."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(n_full, M_full, rtol, budget_s=15.0, lu_sizes=(64, 256, 1024, 2048, 4096), lu_reps=5):
+    """Time the CPU oracle on a bounded sample of the same march.
+
+    Value: the oracle's FFT route (embedding products, Strang solve,
+    preconditioned CGS, Sec. 4) at the full n on the first levels of the
+    march.  numpy's FFT and vector operations run on one thread whatever the
+    thread pools allow (a single 1-D transform is not split over cores), so
+    this leg uses one core.  Beside it, the dense-LU oracle (LAPACK dgesv
+    through numpy, BLAS on every host core) per level at n in lu_sizes with
+    M = 64: the median of lu_reps timings of its first levels, and its
+    (4096/n)^3 extrapolation to the full n."""
     import numpy as np
     import oracle as O
     import workloads as W
-    from threadpoolctl import threadpool_limits
+    from threadpoolctl import threadpool_info, threadpool_limits
+    cores = host_cores()
     with threadpool_limits(limits=1):
         prob = W.config_large(n=n_full, M=M_full)
-        U = [prob.initial_vector()]
+        U = [O.initial_level(prob)]
         its = []
         t0 = time.perf_counter()
         while len(its) < prob.M and time.perf_counter() - t0 < budget_s:
             j = len(its)
-            u, k = O.level_solve_pcgs(prob, np.array(U), j, prob.source_level(j), rtol=rtol)
+            u, k = O.level_solve_pcgs(prob, np.array(U), j, O.source_level(prob, j), rtol=rtol)
             U.append(u)
             its.append(k)
         dt = time.perf_counter() - t0
-        n_s = 2048
-        small = W.config_large(n=n_s, M=M_full)
-        V = np.zeros((small.M + 1, n_s))
-        V[0] = small.initial_vector()
-        t1 = time.perf_counter()
-        lu_levels = 0
-        while lu_levels < small.M and time.perf_counter() - t1 < lu_budget_s:
-            V[lu_levels + 1] = O.level_solve(small, V, lu_levels, small.source_level(lu_levels))
-            lu_levels += 1
-        lu_dt = time.perf_counter() - t1
-    lu_rate = lu_levels / lu_dt
+    sweep = []
+    with threadpool_limits(limits=cores):
+        blas = [f"{d.get('internal_api')} ({d.get('num_threads')} threads)" for d in threadpool_info()
+                if d.get("user_api") == "blas"]
+        for n_s in lu_sizes:
+            small = W.config_large(n=n_s, M=64)
+            per = 2 if n_s >= 4096 else 3
+            times = []
+            for _ in range(lu_reps):
+                V = np.zeros((small.M + 1, n_s))
+                V[0] = O.initial_level(small)
+                t1 = time.perf_counter()
+                for j in range(per):
+                    V[j + 1] = O.level_solve(small, V, j, O.source_level(small, j))
+                times.append((time.perf_counter() - t1) / per)
+            med = float(np.median(times))
+            sweep.append({"n": n_s, "seconds_per_level": med, "level_solves_per_s": 1.0 / med,
+                          "levels_timed": per, "repeats": lu_reps})
+            log(f"cpu baseline: dense LU n={n_s}: {1e3 * med:.1f} ms per level")
+    big = sweep[-1]
     return {
         "value": len(its) / dt,
         "unit": "level-solves/s",
         "cores": 1,
+        "host_cores": cores,
         "kind": "oracle",
-        "sample": (f"FFT-PCGS oracle (numpy FFT, one thread), first {len(its)} levels of the same march "
+        "sample": (f"FFT-PCGS oracle (numpy FFT, one thread: its transforms and vector operations are "
+                   f"single-threaded), first {len(its)} levels of the same march "
                    f"(n={n_full}, M={M_full}, rtol={rtol}, zero initial guess) in {dt:.1f}s, "
                    f"CGS iterations {its}"),
-        "dense_lu": {"value_extrapolated": lu_rate * (n_s / n_full) ** 3, "measured_value": lu_rate,
-                     "measured_n": n_s, "levels": lu_levels, "seconds": lu_dt,
-                     "note": "dense-LU oracle per level, one thread, extrapolated to the full n by (2048/n)^3"},
+        "dense_lu": {"cores": cores, "blas": blas, "M": 64, "sweep": sweep,
+                     "value_extrapolated": big["level_solves_per_s"] * (big["n"] / n_full) ** 3,
+                     "note": (f"dense-LU oracle per level (assembly of A and B plus dgesv), median of "
+                              f"{lu_reps}; at the full n only the ({big['n']}/n)^3 extrapolation of the "
+                              f"largest measured size")},
     }
 
 
@@ -319,6 +364,7 @@ def main():
     ap.add_argument("--warm-start", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the warm-started forms")
+    ap.add_argument("--no-large-leg", action="store_true", help="skip the n = 2^24 roofline leg")
     ap.add_argument("--profile-class", default="mid_matvec", choices=sorted(KCLASS))
     ap.add_argument("--profile-period", type=int, default=7,
                     help="events on every k-th launch of the profiled class (1 = all)")
@@ -355,21 +401,19 @@ def main():
     prob = W.config_large(n=args.n, M=args.M)
     levels = args.levels if args.levels > 0 else prob.M
     log(f"workload n={prob.n} M={prob.M} levels/step={levels} alpha={prob.alpha} beta={prob.beta}")
-    F = build_sources(prob, dev)
-    log("sources built")
     s = P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, warm_start=args.warm_start)
     u0 = s.history()[0].clone()
     log(f"plan ready, workspace {s.workspace_bytes / 2**30:.2f} GiB")
+    F = build_sources(prob, s)
+    log("sources built")
 
-    def one_step(stats_out=None):
+    def one_step(stats_out):
         s.set_state(0, u0.view(1, -1))
         for j in range(levels):
-            st = s.step(F[j])
-            if stats_out is not None:
-                stats_out.append(st)
+            stats_out.append(s.step(F[j], raise_on_error=False))
 
     for w in range(args.warmup):
-        one_step()
+        one_step([])
         log(f"warmup step {w + 1}/{args.warmup} done")
 
     cls = KCLASS[args.profile_class]
@@ -378,11 +422,11 @@ def main():
     # one launch per level of growing size, is timed at every launch)
     period = 1 if args.profile_class == "history" else args.profile_period
     s.profile(cls, True, period)
-    stats = []
+    all_stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        one_step(stats if k == 0 else None)
+        one_step(all_stats)
         log(f"timed step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -392,7 +436,10 @@ def main():
 
     total_levels = levels * args.steps
     value = total_levels / elapsed
+    stats = all_stats[:levels]  # the first timed march (all marches take the same iterations)
     iters = [st["iters"] for st in stats]
+    accept = acceptance(all_stats)
+    log(f"acceptance: {accept}")
     n = prob.n
     # roofline of the dominant kernel (HBM-bound; algorithmic bytes per launch)
     if args.profile_class == "history":
@@ -445,18 +492,57 @@ def main():
                      "working_launches": real, "avg_launch_us": 1e3 * avg_ms,
                      "algorithmic_bytes_per_launch": per_launch},
         "cgs_iterations": {"mean": float(np.mean(iters)), "min": int(min(iters)), "max": int(max(iters))},
+        "acceptance": accept,
     }
     traffic = committed_traffic(args.profile_class, n)
     if traffic is not None:
         out["roofline"]["traffic"] = traffic["bytes_per_launch"]
         out["roofline"]["traffic_source"] = traffic["source"]
+    s.close()
+    if not args.no_large_leg:
+        out["roofline_n2p24"] = large_leg(args, P, W, dev)
     if not args.no_forms:
         out["forms"] = forms(args, P, W, prob, F, u0, levels, value, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(n, prob.M, args.rtol)
     print(json.dumps(out), flush=True)
-    s.close()
+    if accept["failed_levels"]:
+        log(f"{accept['failed_levels']} timed levels failed the acceptance test")
+        sys.exit(3)
+
+
+def large_leg(args, P, W, dev, n=1 << 24, M=8):
+    """The product middle pass at n = 2^24 (transform buffers of 256 MiB, the
+    same as the Infinity Cache, spectrum and buffer 512 MiB together): a
+    march of M levels of the headline family with events on every 7th launch
+    of the class; working launches as in the headline leg."""
+    import numpy as np
+    import torch
+    prob = W.config_large(n=n, M=M)
+    with P.TimeLevelSolver.from_problem(prob, rtol=args.rtol) as sl:
+        F = build_sources(prob, sl)
+        u0 = sl.history()[0].clone()
+        timed_march(sl, F, u0, 2, torch)  # warm-up
+        sl.profile(KCLASS["mid_matvec"], True, 7)
+        dt, st = timed_march(sl, F, u0, M, torch)
+        launches, kms = sl.profile_read(KCLASS["mid_matvec"])
+        issued = sl.profile_issued(KCLASS["mid_matvec"])
+        sl.profile(KCLASS["mid_matvec"], False)
+    iters = [x["iters"] for x in st]
+    real = 2 * sum(iters) + M
+    avg_ms = kms / max(1, launches) * issued / max(1, real)
+    achieved = 48 * n / (avg_ms * 1e-3) / 1e9
+    cgs_bytes = 416 * n * sum(iters)
+    out = {"workload": f"n={n}, M={M}, headline coefficients and solution family, zero guess",
+           "kernel": "mid_matvec", "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+           "frac": achieved / 8000.0, "avg_launch_us": 1e3 * avg_ms, "algorithmic_bytes_per_launch": 48 * n,
+           "level_solves_per_s": M / dt, "cgs_iterations_mean": float(np.mean(iters)),
+           "path_frac_lower_bound": (path_bytes(n, M, M, iters)) / dt / 1e9 / 8000.0,
+           "cgs_iteration_bytes": cgs_bytes, "acceptance": acceptance(st)}
+    log(f"n=2^24 leg: mid_matvec {achieved:.0f} GB/s ({out['frac']:.3f}), {M / dt:.1f} level-solves/s")
+    del F
+    return out
 
 
 if __name__ == "__main__":

@@ -53,6 +53,11 @@ extern "C" {
 #define TSFCDE_ENONFINITE (-6)   /* NaN/Inf met in the iteration             */
 #define TSFCDE_EDONE (-7)        /* all M levels already computed            */
 #define TSFCDE_EUNSUPPORTED (-8) /* valid problem outside the supported sizes or forms */
+#define TSFCDE_EACCEPT (-9)      /* the level's iterate failed the acceptance test
+                                    (true residual <= rtol |g| or backward error
+                                    <= 1e-13; the first alone under
+                                    TSFCDE_FLAG_STRICT_RESIDUAL) after every
+                                    restart; solution/stats still set        */
 
 /* ---- options -------------------------------------------------------- */
 #define TSFCDE_FP64 0            /* every step in FP64                       */
@@ -82,7 +87,9 @@ extern "C" {
 #define TSFCDE_FLAG_VERIFY 2     /* on recursive convergence, recompute r = g - A x
                                     and restart CGS from x while the true residual
                                     is above rtol |g| and still falling (at most 3
-                                    restarts); also restarts once per breakdown  */
+                                    restarts), even when the backward error
+                                    already passes; also restarts once per
+                                    breakdown                                */
 #define TSFCDE_FLAG_FORCE_FP32 4 /* FP32_REFINED at every level, whatever the
                                     rounding-error model predicts (to measure
                                     where the refinement stops converging)   */
@@ -90,6 +97,9 @@ extern "C" {
                                     kernels separately instead of folding them
                                     into the passes that follow (diagnostic:
                                     the results are bitwise the same)        */
+#define TSFCDE_FLAG_STRICT_RESIDUAL 16 /* accept a level only at a true residual
+                                    |g - A u| <= rtol |g| (not at backward
+                                    error 1e-13); otherwise TSFCDE_EACCEPT   */
 
 /* operators for tsfcde_apply */
 #define TSFCDE_OP_A 0            /* y = A^(j+sigma) x      (3.3)            */
@@ -100,8 +110,12 @@ extern "C" {
 #define TSFCDE_SPEC_EMBED 0      /* DFT of the length-2n circulant embedding of W_beta */
 #define TSFCDE_SPEC_STRANG 1     /* DFT of the n-point Strang circulant s(W_beta)      */
 
+/* gamma(t), d_+(t), d_-(t) of problem (1.1) */
 typedef double (*tsfcde_coef_fn)(double t, void *user);
+/* phi(x), the initial condition of problem (1.1) */
 typedef double (*tsfcde_ic_fn)(double x, void *user);
+/* f(x, t), the source term of problem (1.1) */
+typedef double (*tsfcde_src_fn)(double x, double t, void *user);
 
 /* Problem statement (1.1) plus solver options.  The caller owns it; the
  * plan copies what it needs during tsfcde_plan. */
@@ -128,8 +142,13 @@ typedef struct tsfcde_problem {
     double rtol;       /* Krylov stop: |r_k|_2 <= rtol |g|_2 (<= 0: 1e-10)   */
     int32_t maxit;     /* CGS iterations per level (<= 0: 500)              */
     int32_t precision; /* TSFCDE_FP64 or TSFCDE_FP32_REFINED                */
-    int32_t warm_start;/* TSFCDE_WS_ZERO, _PREV or _EXTRAP                  */
+    int32_t warm_start;/* TSFCDE_WS_ZERO, _PREV, _EXTRAP or _NET            */
     int32_t flags;     /* TSFCDE_FLAG_*                                     */
+    /* f(x, t): callback on the host, evaluated at x_1..x_n and t_{j+sigma}
+     * by tsfcde_step / tsfcde_solve / tsfcde_batch_step for every level whose
+     * device source pointer is NULL; NULL here means f = 0 at such levels. */
+    tsfcde_src_fn f;
+    void *f_user;
 } tsfcde_problem;
 
 typedef struct tsfcde_stats {
@@ -147,7 +166,8 @@ typedef struct tsfcde_stats {
                              whose CGS stops on its recursive residual is
                              accepted when this is <= 1e-13 (or its true
                              residual meets rtol); otherwise CGS restarts
-                             from u, at most 3 times                        */
+                             from u, at most 3 times, and the level ends
+                             with TSFCDE_EACCEPT                            */
     double seconds;       /* host wall time of the level                     */
     int32_t precision_used; /* TSFCDE_FP64, TSFCDE_FP32_REFINED, or
                              TSFCDE_FP32_REFINED_FELL_BACK                   */
@@ -177,18 +197,24 @@ int tsfcde_set_state(tsfcde_plan_t plan, int64_t level, const double *d_U);
 
 /* Advance one level j -> j+1 (Algorithm 2, one pass of its loop).
  * d_f: f(x_i, t_{j+sigma}) on the device (n values, any 8-byte alignment), or
- * NULL for f = 0.
+ * NULL: then the problem's f callback is evaluated on the host at the plan's
+ * nodes x_1..x_n and t_{j+sigma} and copied to the device (f = 0 when the
+ * problem has no f callback).
  * d_u_out: optional device copy of u^{j+1} (n values) or NULL.
  * st: optional per-level statistics.  Returns TSFCDE_ENOCONV /
- * TSFCDE_EBREAKDOWN / TSFCDE_ENONFINITE with u^{j+1} set to the last iterate;
- * TSFCDE_EDONE when all M levels are done. */
+ * TSFCDE_EBREAKDOWN / TSFCDE_ENONFINITE / TSFCDE_EACCEPT with u^{j+1} set to
+ * the last iterate and the level counted as done; TSFCDE_EDONE when all M
+ * levels are done. */
 int tsfcde_step(tsfcde_plan_t plan, const double *d_f, double *d_u_out, tsfcde_stats *st);
 
-/* Run every remaining level.  d_F: device array whose row j (stride ldF
- * doubles, ldF >= n) holds f at t_{j+sigma} for absolute level j, or NULL for
- * f = 0.  d_U_out: optional device copy of U ((M+1) x n).  per_level:
- * optional host array of M stats (entries of already-computed levels are
- * left untouched).  Stops at the first level that fails and returns its code. */
+/* The time march of Algorithm 2 (its loop over j = level..M-1, each pass a
+ * tsfcde_step): u^{j+1} from (3.3) for every remaining level.  d_F: device
+ * array whose row j (stride ldF doubles, ldF >= n) holds f at t_{j+sigma} for
+ * absolute level j, or NULL to take f from the problem's f callback (f = 0
+ * without one).  d_U_out: optional device copy of U ((M+1) x n, row-major).
+ * per_level: optional host array of M stats (entries of already-computed
+ * levels are left untouched).  Stops after the first level that fails and
+ * returns its code. */
 int tsfcde_solve(tsfcde_plan_t plan, const double *d_F, int64_t ldF, double *d_U_out,
                  tsfcde_stats *per_level);
 
@@ -218,6 +244,15 @@ int tsfcde_spectrum(tsfcde_plan_t plan, int32_t which, double *d_out);
  * tsfcde_history_ld(plan) doubles apart (n rounded up to even). */
 const double *tsfcde_history(tsfcde_plan_t plan);
 int64_t tsfcde_history_ld(tsfcde_plan_t plan);
+
+/* t_{j+sigma} = (j + 1 - alpha/2) tau, the instant at which level j samples
+ * gamma, d_+-, f (Lemma 1, Sec. 2.1); NaN for a NULL plan or j outside
+ * 0..M-1. */
+double tsfcde_level_time(tsfcde_plan_t plan, int64_t j);
+
+/* The plan's interior nodes x_i = a + i h, i = 1..n, h = (b-a)/(n+1)
+ * (Sec. 2.1), into the host array h_x of n doubles. */
+int tsfcde_nodes(tsfcde_plan_t plan, double *h_x);
 
 /* Length L of the circulant embedding used for the Toeplitz products. */
 int64_t tsfcde_embedding_length(tsfcde_plan_t plan);
@@ -260,9 +295,14 @@ typedef struct tsfcde_batch_s *tsfcde_batch_t;
 /* Workspace for `count` instances (all with the same M). */
 int tsfcde_batch_workspace_bytes(const tsfcde_problem *probs, int32_t count, size_t *bytes);
 
-/* Plan the batch in one caller-owned, 256-byte aligned device workspace;
- * solver options (rtol, maxit, warm_start) are taken per instance for rtol
- * and from probs[0] for maxit and warm_start. */
+/* Plan `count` independent instances of problem (1.1) (each one what
+ * tsfcde_plan would make of it: Lemma 1 tables, Lemma 2 weights, the spectra
+ * of Sec. 3.2) in one caller-owned, 256-byte aligned device workspace of at
+ * least tsfcde_batch_workspace_bytes bytes, kept alive until
+ * tsfcde_batch_destroy.  Solver options are taken per instance for rtol and
+ * from probs[0] for maxit, warm_start and flags.  Every instance must have
+ * precision TSFCDE_FP64 (TSFCDE_EUNSUPPORTED otherwise) and the same M
+ * (TSFCDE_EINVAL). */
 int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_workspace, size_t bytes, void *stream,
                       tsfcde_batch_t *out);
 
@@ -272,10 +312,12 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
 tsfcde_plan_t tsfcde_batch_member(tsfcde_batch_t batch, int32_t i);
 int tsfcde_batch_set_level(tsfcde_batch_t batch, int64_t level);
 
-/* Advance every instance one level.  d_f: host array of `count` device
- * pointers (f at t_{j+sigma} of each instance; an entry or the array may be
- * NULL for f = 0).  stats: `count` entries or NULL.  Returns the first
- * failing instance's code (all instances still advance). */
+/* Advance every instance one level (one pass of Algorithm 2's loop each).
+ * d_f: host array of `count` device pointers (f at t_{j+sigma} of each
+ * instance); an entry or the array may be NULL, and that instance's f then
+ * comes from its f callback, as in tsfcde_step.  stats: `count` entries or
+ * NULL.  Returns the first failing instance's code (all instances still
+ * advance). */
 int tsfcde_batch_step(tsfcde_batch_t batch, const double *const *d_f, tsfcde_stats *stats);
 
 int tsfcde_batch_destroy(tsfcde_batch_t batch);

@@ -47,6 +47,7 @@ from typing import Iterable, Optional
 import numpy as np
 
 __all__ = [
+    "mesh_h", "time_step", "sigma_of", "t_sigma", "nodes", "initial_level", "source_level",
     "grunwald_weights", "wsgd_lambdas", "wsgd_weights", "l21s_a", "l21s_b", "l21s_c",
     "l21s_kappa", "eta", "matrix_Q", "toeplitz_W", "level_scalars", "level_L", "level_A",
     "level_B", "history_term", "rhs", "level_solve", "march", "error_norms",
@@ -55,6 +56,48 @@ __all__ = [
     "embedding_eigenvalues", "embedding_product", "strang_eigenvalues", "strang_solve", "rhs_fft",
     "level_solve_pcgs",
 ]
+
+
+# ---------------------------------------------------------------------------
+# The grid of Sec. 2.1 and the sampling instant of Lemma 1.
+# ---------------------------------------------------------------------------
+
+def mesh_h(prob) -> float:
+    """h = (b - a)/(n + 1): n interior nodes, the paper's N = n + 1
+    subintervals (Sec. 2.1)."""
+    return (prob.b - prob.a) / (prob.n + 1)
+
+
+def time_step(prob) -> float:
+    """tau = T/M (Sec. 2.1)."""
+    return prob.T / prob.M
+
+
+def sigma_of(alpha: float) -> float:
+    """sigma = 1 - alpha/2, the offset of the L2-1sigma formula (Lemma 1)."""
+    return 1.0 - alpha / 2.0
+
+
+def t_sigma(prob, j: int) -> float:
+    """t_{j+sigma} = (j + sigma) tau, where level j samples gamma, d_+-, f
+    (Lemma 1; the scheme's coefficients gamma^(j+sigma), D_+-^(j+sigma),
+    f^(j+sigma) of Sec. 2.1)."""
+    return (j + sigma_of(prob.alpha)) * time_step(prob)
+
+
+def nodes(prob) -> np.ndarray:
+    """Interior nodes x_i = a + i h, i = 1..n (Sec. 2.1)."""
+    return prob.a + mesh_h(prob) * np.arange(1, prob.n + 1, dtype=np.float64)
+
+
+def initial_level(prob) -> np.ndarray:
+    """u^0_i = phi(x_i) (Sec. 2.1)."""
+    return np.asarray(prob.phi(nodes(prob)), dtype=np.float64)
+
+
+def source_level(prob, j: int) -> np.ndarray:
+    """f(x_i, t_{j+sigma}) on the interior nodes ((3.1))."""
+    return np.asarray(prob.f(nodes(prob), t_sigma(prob, j)), dtype=np.float64)
 
 
 # ---------------------------------------------------------------------------
@@ -179,14 +222,14 @@ def toeplitz_W(beta: float, n: int) -> np.ndarray:
 
 def level_scalars(prob, j: int):
     """(eta_j, gamma^(j+sigma), D_+^(j+sigma), D_-^(j+sigma)) for level j."""
-    t = prob.t_sigma(j)
-    return eta(prob.alpha, prob.tau, j), prob.gamma(t), prob.dplus(t), prob.dminus(t)
+    t = t_sigma(prob, j)
+    return eta(prob.alpha, time_step(prob), j), prob.gamma(t), prob.dplus(t), prob.dminus(t)
 
 
 def level_L(prob, j: int) -> np.ndarray:
     """gamma/(2h) Q + D_+/h^beta W + D_-/h^beta W^T at t_{j+sigma}."""
     _, gam, dp, dm = level_scalars(prob, j)
-    n, h, beta = prob.n, prob.h, prob.beta
+    n, h, beta = prob.n, mesh_h(prob), prob.beta
     W = toeplitz_W(beta, n)
     return gam / (2.0 * h) * matrix_Q(n) + dp / h ** beta * W + dm / h ** beta * W.T
 
@@ -194,13 +237,13 @@ def level_L(prob, j: int) -> np.ndarray:
 def level_A(prob, j: int) -> np.ndarray:
     """A^(j+sigma) = eta_j I - sigma L  (3.3)."""
     e = level_scalars(prob, j)[0]
-    return e * np.eye(prob.n) - prob.sigma * level_L(prob, j)
+    return e * np.eye(prob.n) - sigma_of(prob.alpha) * level_L(prob, j)
 
 
 def level_B(prob, j: int) -> np.ndarray:
     """B^(j+sigma) = eta_j I + (1 - sigma) L  (3.3)."""
     e = level_scalars(prob, j)[0]
-    return e * np.eye(prob.n) + (1.0 - prob.sigma) * level_L(prob, j)
+    return e * np.eye(prob.n) + (1.0 - sigma_of(prob.alpha)) * level_L(prob, j)
 
 
 def history_term(prob, U: np.ndarray, j: int) -> np.ndarray:
@@ -213,7 +256,7 @@ def history_term(prob, U: np.ndarray, j: int) -> np.ndarray:
     c = l21s_c(prob.alpha, j)
     for s in range(j):
         acc += c[j - s] * (U[s + 1] - U[s])
-    return l21s_kappa(prob.alpha, prob.tau) * acc
+    return l21s_kappa(prob.alpha, time_step(prob)) * acc
 
 
 def rhs(prob, U: np.ndarray, j: int, f_j: np.ndarray) -> np.ndarray:
@@ -233,10 +276,10 @@ def march(prob, f_levels: Optional[Iterable[np.ndarray]] = None, levels: Optiona
     Returns U with U[j] = u^j on the interior nodes, j = 0..levels."""
     M = prob.M if levels is None else levels
     U = np.zeros((M + 1, prob.n))
-    U[0] = prob.initial_vector() if u0 is None else u0
+    U[0] = initial_level(prob) if u0 is None else u0
     flist = list(f_levels) if f_levels is not None else None
     for j in range(M):
-        f_j = flist[j] if flist is not None else prob.source_level(j)
+        f_j = flist[j] if flist is not None else source_level(prob, j)
         U[j + 1] = level_solve(prob, U, j, f_j)
     return U
 
@@ -244,12 +287,12 @@ def march(prob, f_levels: Optional[Iterable[np.ndarray]] = None, levels: Optiona
 def error_norms(prob, U: np.ndarray):
     """(max_j ||E^j||_0, max_{i,j} |E_i^j|) with ||v||_0 = sqrt(h sum v_i^2)
     (Sec. 2.2 and the tables of Sec. 4)."""
-    x = prob.x_interior()
+    x = nodes(prob)
     l2 = 0.0
     cmax = 0.0
     for j in range(U.shape[0]):
-        E = U[j] - prob.exact(x, j * prob.tau)
-        l2 = max(l2, math.sqrt(prob.h * float(E @ E)))
+        E = U[j] - prob.exact(x, j * time_step(prob))
+        l2 = max(l2, math.sqrt(mesh_h(prob) * float(E @ E)))
         cmax = max(cmax, float(np.max(np.abs(E))))
     return l2, cmax
 
@@ -292,10 +335,10 @@ def preconditioner_matrix(prob, j: int) -> np.ndarray:
     """P^(j+sigma) = eta_j I - sigma (gamma/(2h) s(Q) + D_+/h^beta s(W)
     + D_-/h^beta s(W)^T)  (3.7), as a dense matrix."""
     e, gam, dp, dm = level_scalars(prob, j)
-    n, h, beta = prob.n, prob.h, prob.beta
+    n, h, beta = prob.n, mesh_h(prob), prob.beta
     sQ = circulant(strang_column(_Q_lag, n))
     sW = circulant(strang_column(_W_lag(beta, n), n))
-    return e * np.eye(n) - prob.sigma * (gam / (2.0 * h) * sQ + dp / h ** beta * sW
+    return e * np.eye(n) - sigma_of(prob.alpha) * (gam / (2.0 * h) * sQ + dp / h ** beta * sW
                                          + dm / h ** beta * sW.T)
 
 
@@ -326,7 +369,7 @@ def apply_A_rows(prob, j: int, u: np.ndarray, rows: np.ndarray, which: str = "A"
     (Q u)_i = u_{i+1} - u_{i-1};  (W u)_i = sum_{m <= i+1} omega_{i-m+1} u_m;
     (W^T u)_i = sum_{m >= i-1} omega_{m-i+1} u_m."""
     e, gam, dp, dm = level_scalars(prob, j)
-    n, h, beta, sigma = prob.n, prob.h, prob.beta, prob.sigma
+    n, h, beta, sigma = prob.n, mesh_h(prob), prob.beta, sigma_of(prob.alpha)
     w = wsgd_weights(beta, n + 1)
     out = np.empty(len(rows))
     for r, i in enumerate(rows):
@@ -348,7 +391,7 @@ def apply_P_rows(prob, j: int, y: np.ndarray, rows: np.ndarray) -> np.ndarray:
     0-based rows: a circulant with first column c acts as
     (C y)_i = sum_k c_{(i-k) mod n} y_k, its transpose with c_{(k-i) mod n}."""
     e, gam, dp, dm = level_scalars(prob, j)
-    n, h, beta, sigma = prob.n, prob.h, prob.beta, prob.sigma
+    n, h, beta, sigma = prob.n, mesh_h(prob), prob.beta, sigma_of(prob.alpha)
     cQ = strang_column(_Q_lag, n)
     cW = strang_column(_W_lag(beta, n), n)
     k = np.arange(n)
@@ -372,7 +415,7 @@ def rhs_rows(prob, U: np.ndarray, j: int, f_j: np.ndarray, rows: np.ndarray) -> 
     acc = np.zeros(len(rows))
     for s in range(j):
         acc += c[j - s] * (U[s + 1][rows] - U[s][rows])
-    return Bu - l21s_kappa(prob.alpha, prob.tau) * acc + f_j[rows]
+    return Bu - l21s_kappa(prob.alpha, time_step(prob)) * acc + f_j[rows]
 
 
 # ---------------------------------------------------------------------------
@@ -398,7 +441,7 @@ def embedding_product(prob, j: int, x: np.ndarray, which: str = "A", lam=None) -
     zero-padded x, and W^T, the transpose of a real circulant, has the
     eigenvalues conj(lam)."""
     e, gam, dp, dm = level_scalars(prob, j)
-    n, h, beta, sigma = prob.n, prob.h, prob.beta, prob.sigma
+    n, h, beta, sigma = prob.n, mesh_h(prob), prob.beta, sigma_of(prob.alpha)
     if lam is None:
         lam = embedding_eigenvalues(prob)
     L = lam.size
@@ -414,7 +457,7 @@ def strang_eigenvalues(prob, j: int) -> np.ndarray:
     """Eigenvalues of the Strang preconditioner (3.7): eta_j - sigma (gamma/(2h)
     lam(s(Q)) + D+/h^beta lam(s(W)) + D-/h^beta conj lam(s(W)))."""
     e, gam, dp, dm = level_scalars(prob, j)
-    n, h, beta, sigma = prob.n, prob.h, prob.beta, prob.sigma
+    n, h, beta, sigma = prob.n, mesh_h(prob), prob.beta, sigma_of(prob.alpha)
     lq = circulant_eigenvalues(strang_column(_Q_lag, n))
     lw = circulant_eigenvalues(strang_column(_W_lag(beta, n), n))
     return e - sigma * (gam / (2.0 * h) * lq + dp / h ** beta * lw + dm / h ** beta * np.conj(lw))
@@ -437,7 +480,7 @@ def rhs_fft(prob, U: np.ndarray, j: int, f_j: np.ndarray, lam=None) -> np.ndarra
     acc = np.zeros(prob.n)
     for s_ in range(j):
         acc += c[j - s_] * (U[s_ + 1] - U[s_])
-    return g - l21s_kappa(prob.alpha, prob.tau) * acc
+    return g - l21s_kappa(prob.alpha, time_step(prob)) * acc
 
 
 def level_solve_pcgs(prob, U: np.ndarray, j: int, f_j: np.ndarray, rtol: float = 1e-10, maxit: int = 500):

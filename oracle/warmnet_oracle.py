@@ -59,6 +59,8 @@ import math
 
 import numpy as np
 
+from . import ids_oracle as O
+
 CIN, WIDTH, KS = 7, 32, 5
 LAYERS = [(CIN, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH, 1)]  # (c_in, c_out)
 HALF = KS // 2
@@ -107,7 +109,7 @@ def weights_bf16(theta: np.ndarray) -> np.ndarray:
 def level_features(prob, j: int, eta_j: float, gamma_j: float, dplus_j: float, dminus_j: float) -> np.ndarray:
     """Channels 2..6 at level j (alpha, beta and the three level coefficients
     of sigma L_j relative to eta_j)."""
-    s, h, beta = prob.sigma, prob.h, prob.beta
+    s, h, beta = O.sigma_of(prob.alpha), O.mesh_h(prob), prob.beta
     qg = s * gamma_j / (h * eta_j)
     qp = s * dplus_j * h ** (-beta) / eta_j
     qm = s * dminus_j * h ** (-beta) / eta_j

@@ -19,14 +19,15 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "tsfcde.h")
 
 COEF_FN = ctypes.CFUNCTYPE(c_double, c_double, c_void_p)
 IC_FN = ctypes.CFUNCTYPE(c_double, c_double, c_void_p)
+SRC_FN = ctypes.CFUNCTYPE(c_double, c_double, c_double, c_void_p)
 
 TSFCDE_OK = 0
 STATUS = {0: "TSFCDE_OK", -1: "TSFCDE_EINVAL", -2: "TSFCDE_ENOMEM", -3: "TSFCDE_EDEVICE",
           -4: "TSFCDE_ENOCONV", -5: "TSFCDE_EBREAKDOWN", -6: "TSFCDE_ENONFINITE",
-          -7: "TSFCDE_EDONE", -8: "TSFCDE_EUNSUPPORTED"}
+          -7: "TSFCDE_EDONE", -8: "TSFCDE_EUNSUPPORTED", -9: "TSFCDE_EACCEPT"}
 TSFCDE_EINVAL, TSFCDE_ENOMEM, TSFCDE_EDEVICE = -1, -2, -3
 TSFCDE_ENOCONV, TSFCDE_EBREAKDOWN, TSFCDE_ENONFINITE = -4, -5, -6
-TSFCDE_EDONE, TSFCDE_EUNSUPPORTED = -7, -8
+TSFCDE_EDONE, TSFCDE_EUNSUPPORTED, TSFCDE_EACCEPT = -7, -8, -9
 TSFCDE_FP64 = 0
 TSFCDE_FP32_REFINED = 1
 TSFCDE_FP32_REFINED_FELL_BACK = 2
@@ -35,6 +36,7 @@ TSFCDE_FLAG_TRUE_RESIDUAL = 1
 TSFCDE_FLAG_VERIFY = 2
 TSFCDE_FLAG_FORCE_FP32 = 4
 TSFCDE_FLAG_NO_FOLD = 8
+TSFCDE_FLAG_STRICT_RESIDUAL = 16
 TSFCDE_OP_A, TSFCDE_OP_B, TSFCDE_OP_PINV = 0, 1, 2
 TSFCDE_SPEC_EMBED, TSFCDE_SPEC_STRANG = 0, 1
 
@@ -47,7 +49,7 @@ class tsfcde_problem(ctypes.Structure):
         ("gamma_at", POINTER(c_double)), ("dplus_at", POINTER(c_double)), ("dminus_at", POINTER(c_double)),
         ("phi", IC_FN), ("phi_user", c_void_p),
         ("rtol", c_double), ("maxit", c_int32), ("precision", c_int32), ("warm_start", c_int32),
-        ("flags", c_int32),
+        ("flags", c_int32), ("f", SRC_FN), ("f_user", c_void_p),
     ]
 
 
@@ -83,6 +85,8 @@ _SIGS = {
     "tsfcde_level": (c_int64, [c_void_p]),
     "tsfcde_history_ld": (c_int64, [c_void_p]),
     "tsfcde_embedding_length": (c_int64, [c_void_p]),
+    "tsfcde_level_time": (c_double, [c_void_p, c_int64]),
+    "tsfcde_nodes": (c_int32, [c_void_p, POINTER(c_double)]),
     "tsfcde_profile": (c_int32, [c_void_p, c_int32, c_int32]),
     "tsfcde_profile_read": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
     "tsfcde_profile_issued": (c_int32, [c_void_p, c_int32, POINTER(c_int64)]),
@@ -115,7 +119,7 @@ def header_symbols(path: str = HEADER):
     """Names of the functions declared in include/tsfcde.h."""
     text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tsfcde_[a-z_]+)\s*\(", text)) - {"tsfcde_coef_fn", "tsfcde_ic_fn"})
+    return sorted(set(re.findall(r"\b(tsfcde_[a-z_]+)\s*\(", text)) - {"tsfcde_coef_fn", "tsfcde_ic_fn", "tsfcde_src_fn"})
 
 
 def lib():

@@ -212,6 +212,9 @@ struct tsfcde_plan_s {
     float2 *buf32, *bufP32, *specA32, *specP32, *specPj32;
     int last_inner = 8;
     tsfcde_net_s *net = nullptr;  // learned warm start (TSFCDE_WS_NET)
+    tsfcde_src_fn fcb = nullptr;  // f(x, t) for levels stepped without a device source
+    void *fuser = nullptr;
+    double *h_f = nullptr;        // pinned staging of those f values (n doubles)
     ProfRec prof[NPROF];
     std::vector<hipEvent_t> event_pool;
 };
@@ -1066,13 +1069,19 @@ double backward_error(const tsfcde_plan_s *pl, int64_t j) {
 
 int fp64_cgs(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so) {
     const bool verify = (pl->flags & TSFCDE_FLAG_VERIFY) != 0;
-    // x is accepted at backward error BW_TOL; with TSFCDE_FLAG_VERIFY only at
-    // a true residual within rtol |g|
-    const double bwtol = verify ? 0.0 : BW_TOL;
+    const bool strict = (pl->flags & TSFCDE_FLAG_STRICT_RESIDUAL) != 0;
+    // the device accepts x at backward error BW_TOL; with TSFCDE_FLAG_VERIFY
+    // (restarts while the true residual falls) or TSFCDE_FLAG_STRICT_RESIDUAL
+    // only at a true residual within rtol |g|
+    const double bwtol = (verify || strict) ? 0.0 : BW_TOL;
     const Bufs<double, double2> b64 = bufs64(pl);
     int rc, iters_seen = 0, checks_seen = 0;
     double last_true2 = HUGE_VAL;
     int chunk = std::max(2, pl->last_iters);
+    // set where the device's acceptance check (true residual within rtol |g|,
+    // or backward error within bwtol) passed x; a level that leaves the loop
+    // any other way with no error of its own is TSFCDE_EACCEPT
+    bool accepted = false;
     for (;;) {
         // a chunk of CGS, then the acceptance check, which the device runs
         // only when the chunk ended the solve (one poll serves both): restart
@@ -1091,6 +1100,7 @@ int fp64_cgs(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so) {
                 so.relres_true = h.gnorm2 > 0 ? std::sqrt(h.aux0 / h.gnorm2) : 0.0;
                 so.backward_err = backward_error(pl, j);
                 so.code = status_code(h.status);
+                accepted = so.code == TSFCDE_OK;
                 break;
             }
             if (todo <= 0) {
@@ -1104,6 +1114,7 @@ int fp64_cgs(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so) {
         so.backward_err = backward_error(pl, j);
         if (h.done) {  // accepted, or non-finite
             so.code = status_code(h.status);
+            accepted = so.code == TSFCDE_OK;
             break;
         }
         const int stat = h.prestat;  // how CGS stopped
@@ -1127,6 +1138,10 @@ int fp64_cgs(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so) {
         }
         chunk = std::max(2, pl->last_iters / 2);
     }
+    // with TSFCDE_FLAG_VERIFY alone, a level whose true residual stopped
+    // falling above rtol |g| is still accepted at backward error BW_TOL
+    if (!accepted && verify && !strict && so.backward_err >= 0.0 && so.backward_err <= BW_TOL) accepted = true;
+    if (so.code == TSFCDE_OK && !accepted) so.code = TSFCDE_EACCEPT;
     so.iters = pl->h_sc->iter;
     pl->last_iters = std::max(1, so.iters / (so.restarts + 1));
     return TSFCDE_OK;
@@ -1219,7 +1234,8 @@ int ir_solve(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so, int &outer, 
     so.iters = inner_total;
     if (fell_back && so.code == TSFCDE_OK) {
         // continue in FP64 from x (the pending correction d is dropped)
-        if ((rc = restart_from_x(pl, j, x, (pl->flags & TSFCDE_FLAG_VERIFY) ? 0.0 : BW_TOL))) return rc;
+        const bool no_bw = (pl->flags & (TSFCDE_FLAG_VERIFY | TSFCDE_FLAG_STRICT_RESIDUAL)) != 0;
+        if ((rc = restart_from_x(pl, j, x, no_bw ? 0.0 : BW_TOL))) return rc;
         if (!pl->h_sc->done) {
             const int base = pl->h_sc->iter;  // the restart keeps the inner count
             SolveOut f;
@@ -1236,10 +1252,37 @@ int ir_solve(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so, int &outer, 
     return TSFCDE_OK;
 }
 
+// t_{j+sigma} = (j + sigma) tau (Lemma 1)
+double level_time(const tsfcde_plan_s *pl, int64_t j) { return ((double)j + pl->sigma) * pl->tau; }
+
+// x_i = a + i h, i = 1..n (Sec. 2.1)
+double node(const tsfcde_plan_s *pl, int64_t i) { return pl->a + (double)i * pl->h; }
+
+// f(x_i, t_{j+sigma}) from the problem's callback into the plan's f buffer
+// (through a pinned staging array), for a level stepped without a device
+// source; *d_f stays NULL (f = 0) when there is no callback.
+int callback_source(tsfcde_plan_s *pl, int64_t j, const double **d_f) {
+    *d_f = nullptr;
+    if (!pl->fcb) return TSFCDE_OK;
+    if (!pl->h_f && hipHostMalloc(reinterpret_cast<void **>(&pl->h_f), sizeof(double) * (size_t)pl->n) != hipSuccess) {
+        pl->h_f = nullptr;
+        return TSFCDE_EDEVICE;
+    }
+    HIPCHK(hipStreamSynchronize(pl->stream));  // the last copy out of h_f has finished
+    const double t = level_time(pl, j);
+    for (int64_t i = 0; i < pl->n; ++i) pl->h_f[i] = pl->fcb(node(pl, i + 1), t, pl->fuser);
+    HIPCHK(hipMemcpyAsync(pl->fbuf, pl->h_f, sizeof(double) * (size_t)pl->n, hipMemcpyHostToDevice, pl->stream));
+    *d_f = pl->fbuf;
+    return TSFCDE_OK;
+}
+
 int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_stats *st) {
     if (pl->level >= pl->M) return TSFCDE_EDONE;
     auto t0 = std::chrono::steady_clock::now();
     const int64_t j = pl->level, n = pl->n;
+    if (!d_f) {
+        if (int rc = callback_source(pl, j, &d_f)) return rc;
+    }
     double *x = pl->U + (size_t)(j + 1) * pl->ldn;
     // initial guess: 0, u^j, or quadratic extrapolation (u^j below level 2)
     int warm = 0;
@@ -1363,12 +1406,14 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
     pl->maxit = prob->maxit > 0 ? prob->maxit : 500;
     pl->warm = prob->warm_start;
     pl->flags = prob->flags;
+    pl->fcb = prob->f;
+    pl->fuser = prob->f_user;
     // coefficients at t_{j+sigma}
     pl->gam.resize(M);
     pl->dp.resize(M);
     pl->dm.resize(M);
     for (int64_t j = 0; j < M; ++j) {
-        const double t = ((double)j + pl->sigma) * pl->tau;
+        const double t = level_time(pl, j);
         pl->gam[j] = sample(prob->gamma, prob->gamma_at, prob->coef_user, j, t);
         pl->dp[j] = sample(prob->dplus, prob->dplus_at, prob->coef_user, j, t);
         pl->dm[j] = sample(prob->dminus, prob->dminus_at, prob->coef_user, j, t);
@@ -1558,7 +1603,7 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
     {
         std::vector<double> u0(n, 0.0);
         if (prob->phi)
-            for (int64_t i = 0; i < n; ++i) u0[i] = prob->phi(prob->a + (double)(i + 1) * pl->h, prob->phi_user);
+            for (int64_t i = 0; i < n; ++i) u0[i] = prob->phi(node(pl, i + 1), prob->phi_user);
         if (hipMemcpyAsync(pl->U, u0.data(), sizeof(double) * n, hipMemcpyHostToDevice, pl->stream) != hipSuccess)
             return fail(TSFCDE_EDEVICE);
         if (hipGetLastError() != hipSuccess) return fail(TSFCDE_EDEVICE);
@@ -1673,6 +1718,17 @@ const double *tsfcde_history(tsfcde_plan_t pl) { return pl ? pl->U : nullptr; }
 int64_t tsfcde_history_ld(tsfcde_plan_t pl) { return pl ? pl->ldn : -1; }
 
 int64_t tsfcde_embedding_length(tsfcde_plan_t pl) { return pl ? pl->A.L : -1; }
+
+double tsfcde_level_time(tsfcde_plan_t pl, int64_t j) {
+    if (!pl || j < 0 || j >= pl->M) return std::nan("");
+    return level_time(pl, j);
+}
+
+int tsfcde_nodes(tsfcde_plan_t pl, double *h_x) {
+    if (!pl || !h_x) return TSFCDE_EINVAL;
+    for (int64_t i = 0; i < pl->n; ++i) h_x[i] = node(pl, i + 1);
+    return TSFCDE_OK;
+}
 
 int64_t tsfcde_level(tsfcde_plan_t pl) { return pl ? pl->level : -1; }
 
@@ -1841,6 +1897,7 @@ int tsfcde_destroy(tsfcde_plan_t pl) {
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : pl->event_pool) (void)hipEventDestroy(e);
     if (pl->h_sc) (void)hipHostFree(pl->h_sc);
+    if (pl->h_f) (void)hipHostFree(pl->h_f);
     delete pl;
     return TSFCDE_OK;
 }
@@ -1856,6 +1913,7 @@ const char *tsfcde_strerror(int s) {
         case TSFCDE_ENONFINITE: return "non-finite value in the iteration";
         case TSFCDE_EDONE: return "all time levels already computed";
         case TSFCDE_EUNSUPPORTED: return "valid problem outside the supported sizes or forms";
+        case TSFCDE_EACCEPT: return "the level's iterate failed the acceptance test after every restart";
         default: return "unknown status";
     }
 }
@@ -1932,6 +1990,7 @@ struct tsfcde_batch_s {
     DoneRec *d_done = nullptr, *h_done = nullptr;
     int last_iters = 8;
     bool fold = true;  // finishing steps folded into later passes (TSFCDE_FLAG_NO_FOLD clears it)
+    bool strict = false;  // TSFCDE_FLAG_STRICT_RESIDUAL: accept only at a true residual within rtol |g|
 };
 
 namespace {
@@ -2094,7 +2153,9 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
         rstA.push_back(cdesc(pl, C, InReal{x, n, C}, osA));
         rstC.push_back(cdesc(pl, C, isA, with_red(OutRestart{pl->g, x, pl->r, pl->rt, n, C, pl->anorm[j], 0.0}, pl, 3)));
         // acceptance check of a converged instance (backward error)
-        vfyC.push_back(cdesc(pl, C, isA, with_red(OutRestart{pl->g, x, pl->r, pl->rt, n, C, pl->anorm[j], BW_TOL}, pl, 3)));
+        vfyC.push_back(cdesc(pl, C, isA,
+                             with_red(OutRestart{pl->g, x, pl->r, pl->rt, n, C, pl->anorm[j], bt->strict ? 0.0 : BW_TOL},
+                                      pl, 3)));
         // inverse Strang circulant of level j: Bluestein DFT and embedding spectrum
         OutSpec osB{pl->bufB, pl->B.tw, CB};
         bsA.push_back(cdesc(pl, CB, InCplx{pl->wv, nullptr, pl->chirp, n, CB}, nored(osB)));
@@ -2185,6 +2246,9 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
         if (f && (reinterpret_cast<uintptr_t>(f) & 15)) {
             hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, bt->stream, f, pl->fbuf, pl->n);
             f = pl->fbuf;
+        }
+        if (!f) {
+            if (int rc = callback_source(pl, j, &f)) return rc;
         }
         fptr[i] = f;
     }
@@ -2278,6 +2342,9 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
     // answer is checked (backward error) and the ones that fail restart from x
     int iters_seen = 0, chunk = std::max(2, bt->last_iters), rounds = 0;
     std::vector<int> restarts(cnt, 0);
+    // accepted: the last acceptance check passed the instance's x; checked:
+    // it was checked at least once (it converged on its recursive residual)
+    std::vector<char> accepted(cnt, 0), checked(cnt, 0);
     for (;;) {
         for (;;) {
             const int todo = std::min(chunk, bt->maxit - iters_seen);
@@ -2346,6 +2413,10 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
         if (rc) return rc;
         bool all = true;
         for (int i = 0; i < cnt; ++i) {
+            if (check[i]) {
+                checked[i] = 1;
+                accepted[i] = bt->h_done[i].done && bt->h_done[i].status == ST_OK;
+            }
             if (!bt->h_done[i].done) ++restarts[i];
             all = all && bt->h_done[i].done;
         }
@@ -2358,10 +2429,11 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
     for (int i = 0; i < cnt; ++i) {
         const DoneRec &r = bt->h_done[i];
         tsfcde_plan_s *pl = bt->plans[i];
-        // an instance whose last check failed after all restarts keeps x (as
-        // the single-instance path does); one that never converged is ENOCONV
-        const bool checked = rounds > 0 && r.status == ST_OK;
-        int ci = (!r.done && !(checked && restarts[i] > MAX_RESTARTS)) ? TSFCDE_ENOCONV : status_code(r.status);
+        // an instance whose last check failed after all restarts keeps x and
+        // reports TSFCDE_EACCEPT (as the single-instance path does); one that
+        // never converged is TSFCDE_ENOCONV
+        int ci = status_code(r.status);
+        if (ci == TSFCDE_OK && !accepted[i]) ci = checked[i] ? TSFCDE_EACCEPT : TSFCDE_ENOCONV;
         if (ci && !code) code = ci;
         maxiter = std::max(maxiter, r.iter);
         pl->level = j + 1;
@@ -2426,6 +2498,7 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
     bt->maxit = probs[0].maxit > 0 ? probs[0].maxit : 500;
     bt->warm = probs[0].warm_start;
     bt->fold = (probs[0].flags & TSFCDE_FLAG_NO_FOLD) == 0;
+    bt->strict = (probs[0].flags & TSFCDE_FLAG_STRICT_RESIDUAL) != 0;
     char *ws = reinterpret_cast<char *>(d_workspace);
     size_t off = 0;
     auto fail = [&](int code) {

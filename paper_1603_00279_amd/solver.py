@@ -7,7 +7,7 @@ libtsfcde.so.
 from __future__ import annotations
 
 import ctypes
-from typing import Optional, Sequence
+from typing import Callable, Optional
 
 import numpy as np
 import torch
@@ -25,16 +25,67 @@ def _dptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _coef_fields(gamma, dplus, dminus, keep: list):
+    """ctypes fields of gamma, d_+, d_-: each either a callable of t (wrapped
+    as a C callback, which the library samples at its own t_{j+sigma}) or a
+    sequence of the M samples."""
+    out = {}
+    dptr = ctypes.POINTER(ctypes.c_double)
+    for name, v in (("gamma", gamma), ("dplus", dplus), ("dminus", dminus)):
+        if callable(v):
+            cb = N.COEF_FN(lambda t, _u, fn=v: float(fn(t)))
+            keep.append(cb)
+            out[name] = cb
+            out[name + "_at"] = None
+        else:
+            arr = np.ascontiguousarray(v, dtype=np.float64)
+            keep.append(arr)
+            out[name] = N.COEF_FN()
+            out[name + "_at"] = arr.ctypes.data_as(dptr)
+    return out
+
+
+def _problem(*, alpha, beta, n, M, a, b, T, gamma, dplus, dminus, phi, f, rtol, maxit, precision, warm_start,
+             flags, keep: list):
+    """A tsfcde_problem; the Python callables and arrays it points to are
+    appended to ``keep`` (they must outlive every library call that uses it)."""
+    fields = _coef_fields(gamma, dplus, dminus, keep)
+    if phi is not None:
+        phi_cb = N.IC_FN(lambda x, _u, fn=phi: float(fn(x)))
+        keep.append(phi_cb)
+    else:
+        phi_cb = N.IC_FN()
+    if f is not None:
+        f_cb = N.SRC_FN(lambda x, t, _u, fn=f: float(fn(x, t)))
+        keep.append(f_cb)
+    else:
+        f_cb = N.SRC_FN()
+    return N.tsfcde_problem(
+        alpha=alpha, beta=beta, a=a, b=b, T=T, n=int(n), M=int(M), coef_user=None, phi=phi_cb, phi_user=None,
+        rtol=rtol, maxit=maxit, precision=precision, warm_start=warm_start, flags=flags, f=f_cb, f_user=None,
+        **fields)
+
+
+def _scalar_phi(prob):
+    return lambda x: float(np.asarray(prob.phi(np.array([x], dtype=np.float64)))[0])
+
+
+def _scalar_f(prob):
+    return lambda x, t: float(np.asarray(prob.f(np.array([x], dtype=np.float64), t))[0])
+
+
 class TimeLevelSolver:
     """A plan of the TSFCDE time-level solver (problem (1.1), Algorithm 2).
 
-    Coefficients are given as samples at t_{j+sigma}, j = 0..M-1 (arrays of
-    length M).  The initial level u^0 is given with ``set_state(0, u0)`` (or
-    left at zero).
+    gamma, dplus, dminus: callables of t, sampled by the library at its own
+    t_{j+sigma}, or sequences of those M samples.  phi: optional callable of
+    x (the library evaluates it at its nodes; otherwise u^0 = 0 until
+    ``set_state``).  f: optional callable of (x, t), evaluated by the library
+    for every level stepped without a device source.
     """
 
-    def __init__(self, *, alpha: float, beta: float, n: int, M: int,
-                 gamma_at: Sequence[float], dplus_at: Sequence[float], dminus_at: Sequence[float],
+    def __init__(self, *, alpha: float, beta: float, n: int, M: int, gamma, dplus, dminus,
+                 phi: Optional[Callable] = None, f: Optional[Callable] = None,
                  a: float = 0.0, b: float = 1.0, T: float = 1.0, rtol: float = 1e-10, maxit: int = 500,
                  warm_start: int = N.TSFCDE_WS_ZERO, flags: int = 0, precision: int = N.TSFCDE_FP64,
                  device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
@@ -42,18 +93,13 @@ class TimeLevelSolver:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.n, self.M = int(n), int(M)
-        self._g = np.ascontiguousarray(gamma_at, dtype=np.float64)
-        self._dp = np.ascontiguousarray(dplus_at, dtype=np.float64)
-        self._dm = np.ascontiguousarray(dminus_at, dtype=np.float64)
-        if not (len(self._g) == len(self._dp) == len(self._dm) == self.M):
-            raise ValueError("coefficient samples must have length M")
-        dptr = ctypes.POINTER(ctypes.c_double)
-        self.problem = N.tsfcde_problem(
-            alpha=alpha, beta=beta, a=a, b=b, T=T, n=self.n, M=self.M,
-            gamma=N.COEF_FN(), dplus=N.COEF_FN(), dminus=N.COEF_FN(), coef_user=None,
-            gamma_at=self._g.ctypes.data_as(dptr), dplus_at=self._dp.ctypes.data_as(dptr),
-            dminus_at=self._dm.ctypes.data_as(dptr), phi=N.IC_FN(), phi_user=None,
-            rtol=rtol, maxit=maxit, precision=precision, warm_start=warm_start, flags=flags)
+        for v in (gamma, dplus, dminus):
+            if not callable(v) and len(v) != self.M:
+                raise ValueError("coefficient samples must have length M")
+        self._keep = []
+        self.problem = _problem(alpha=alpha, beta=beta, n=n, M=M, a=a, b=b, T=T, gamma=gamma, dplus=dplus,
+                                dminus=dminus, phi=phi, f=f, rtol=rtol, maxit=maxit, precision=precision,
+                                warm_start=warm_start, flags=flags, keep=self._keep)
         nbytes = ctypes.c_size_t(0)
         N.check(self._lib.tsfcde_workspace_bytes(ctypes.byref(self.problem), ctypes.byref(nbytes)),
                 "tsfcde_workspace_bytes")
@@ -71,14 +117,19 @@ class TimeLevelSolver:
 
     # ------------------------------------------------------------------
     @classmethod
-    def from_problem(cls, prob, **kw):
-        """Build from an object with alpha, beta, n, M, a, b, T and
-        ``coefficient_samples()`` / ``initial_vector()`` (see workloads)."""
-        g, dp, dm = prob.coefficient_samples()
-        s = cls(alpha=prob.alpha, beta=prob.beta, n=prob.n, M=prob.M, gamma_at=g, dplus_at=dp, dminus_at=dm,
-                a=prob.a, b=prob.b, T=prob.T, **kw)
-        u0 = torch.as_tensor(prob.initial_vector(), dtype=torch.float64, device=s.device)
-        s.set_state(0, u0.reshape(1, -1))
+    def from_problem(cls, prob, callbacks: bool = False, **kw):
+        """Build from a problem description (workloads.Problem: alpha, beta,
+        n, M, a, b, T and the callables gamma, dplus, dminus, phi(x), f(x, t)).
+        The coefficients go to the library as callbacks.  u^0 is phi at the
+        plan's nodes, set from one vectorised call; with ``callbacks`` phi and
+        f go to the library as scalar callbacks too (one host call per node,
+        for small n), and steps without a device source take f from there."""
+        s = cls(alpha=prob.alpha, beta=prob.beta, n=prob.n, M=prob.M, gamma=prob.gamma, dplus=prob.dplus,
+                dminus=prob.dminus, phi=_scalar_phi(prob) if callbacks else None,
+                f=_scalar_f(prob) if callbacks else None, a=prob.a, b=prob.b, T=prob.T, **kw)
+        if not callbacks:
+            u0 = torch.as_tensor(np.asarray(prob.phi(s.nodes()), dtype=np.float64), device=s.device)
+            s.set_state(0, u0.reshape(1, -1))
         return s
 
     def close(self):
@@ -149,6 +200,20 @@ class TimeLevelSolver:
         N.check(self._lib.tsfcde_weights(self._plan, _dptr(w)), "tsfcde_weights")
         return w
 
+    def level_time(self, j: int) -> float:
+        """t_{j+sigma} of level j as the plan samples it."""
+        return float(self._lib.tsfcde_level_time(self._plan, j))
+
+    def level_times(self) -> np.ndarray:
+        return np.array([self.level_time(j) for j in range(self.M)])
+
+    def nodes(self) -> np.ndarray:
+        """The plan's interior nodes x_1..x_n."""
+        x = np.empty(self.n, dtype=np.float64)
+        N.check(self._lib.tsfcde_nodes(self._plan, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                "tsfcde_nodes")
+        return x
+
     @property
     def embedding_length(self) -> int:
         return int(self._lib.tsfcde_embedding_length(self._plan))
@@ -182,30 +247,26 @@ class TimeLevelSolver:
 class BatchSolver:
     """Many independent instances advanced level by level with grouped
     launches (tsfcde_plan_batch / tsfcde_batch_step).  ``problems`` are
-    objects with alpha, beta, n, M, a, b, T, coefficient_samples() and
-    initial_vector(); all share M."""
+    problem descriptions as for TimeLevelSolver.from_problem, all with the
+    same M; coefficients go to the library as callbacks, u^0 is phi at each
+    member's nodes, and with ``callbacks`` f is a callback too."""
 
     def __init__(self, problems, *, rtol: float = 1e-10, maxit: int = 500, warm_start: int = N.TSFCDE_WS_ZERO,
-                 precision: int = N.TSFCDE_FP64, flags: int = 0, device: Optional[torch.device] = None,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 precision: int = N.TSFCDE_FP64, flags: int = 0, callbacks: bool = False,
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
         self._lib = N.lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.count = len(problems)
         self.M = problems[0].M
         self.ns = [p.n for p in problems]
-        dptr = ctypes.POINTER(ctypes.c_double)
         self._keep = []
         arr = (N.tsfcde_problem * self.count)()
         for i, prob in enumerate(problems):
-            g, dp, dm = (np.ascontiguousarray(v, dtype=np.float64) for v in prob.coefficient_samples())
-            self._keep += [g, dp, dm]
-            arr[i] = N.tsfcde_problem(
-                alpha=prob.alpha, beta=prob.beta, a=prob.a, b=prob.b, T=prob.T, n=prob.n, M=prob.M,
-                gamma=N.COEF_FN(), dplus=N.COEF_FN(), dminus=N.COEF_FN(), coef_user=None,
-                gamma_at=g.ctypes.data_as(dptr), dplus_at=dp.ctypes.data_as(dptr), dminus_at=dm.ctypes.data_as(dptr),
-                phi=N.IC_FN(), phi_user=None, rtol=rtol, maxit=maxit, precision=precision,
-                warm_start=warm_start, flags=flags)
+            arr[i] = _problem(alpha=prob.alpha, beta=prob.beta, n=prob.n, M=prob.M, a=prob.a, b=prob.b, T=prob.T,
+                              gamma=prob.gamma, dplus=prob.dplus, dminus=prob.dminus, phi=None,
+                              f=_scalar_f(prob) if callbacks else None, rtol=rtol, maxit=maxit,
+                              precision=precision, warm_start=warm_start, flags=flags, keep=self._keep)
         self._arr = arr
         nbytes = ctypes.c_size_t(0)
         N.check(self._lib.tsfcde_batch_workspace_bytes(arr, self.count, ctypes.byref(nbytes)),
@@ -221,12 +282,24 @@ class BatchSolver:
                     "tsfcde_plan_batch")
         self._batch = handle
         for i, prob in enumerate(problems):
-            u0 = torch.as_tensor(prob.initial_vector(), dtype=torch.float64, device=self.device)
+            u0 = torch.as_tensor(np.asarray(prob.phi(self.nodes(i)), dtype=np.float64), device=self.device)
             N.check(self._lib.tsfcde_set_state(self.member(i), 0, ctypes.c_void_p(u0.data_ptr())), "tsfcde_set_state")
         torch.cuda.synchronize(self.device)
 
     def member(self, i: int):
         return self._lib.tsfcde_batch_member(self._batch, i)
+
+    def nodes(self, i: int) -> np.ndarray:
+        """Member i's interior nodes."""
+        x = np.empty(self.ns[i], dtype=np.float64)
+        N.check(self._lib.tsfcde_nodes(self.member(i), x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                "tsfcde_nodes")
+        return x
+
+    def level_times(self, i: int) -> np.ndarray:
+        """Member i's sampling instants t_{j+sigma}, j = 0..M-1."""
+        h = self.member(i)
+        return np.array([float(self._lib.tsfcde_level_time(h, j)) for j in range(self.M)])
 
     def history(self, i: int) -> torch.Tensor:
         """Copy of instance i's stored levels ((M+1) x n)."""

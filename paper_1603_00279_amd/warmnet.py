@@ -106,11 +106,11 @@ def make_sample(plan_handle, hist_ptr: int, ld: int, j: int, target: bool = True
     return s
 
 
-def device_sources(prob, device) -> torch.Tensor:
-    """f(x_i, t_{j+sigma}) for every level, built on the device (M x n)."""
-    prof, coef = prob.source_profiles()
-    return torch.as_tensor(coef, dtype=torch.float64, device=device) @ torch.as_tensor(prof, dtype=torch.float64,
-                                                                                       device=device)
+def device_sources(prob, solver: TimeLevelSolver) -> torch.Tensor:
+    """f at the plan's nodes and sampling instants t_{j+sigma} for every
+    level, built on the device (M x n)."""
+    import workloads as W
+    return W.device_sources(prob, solver.nodes(), solver.level_times(), solver.device)
 
 
 class Trajectories:
@@ -125,7 +125,8 @@ class Trajectories:
         self.n, self.M = problems[0].n, problems[0].M
         self.batch = BatchSolver(problems, rtol=rtol, warm_start=warm_start)
         dev = self.batch.device
-        profs, coefs = zip(*(p.source_profiles() for p in problems))
+        profs, coefs = zip(*(p.source_matrix(self.batch.nodes(i), self.batch.level_times(i))
+                             for i, p in enumerate(problems)))
         prof = torch.as_tensor(np.stack(profs), dtype=torch.float64, device=dev)      # (count, 4, n)
         coef = torch.as_tensor(np.stack(coefs), dtype=torch.float64, device=dev)      # (count, M, 4)
         self.iters = []
@@ -187,7 +188,7 @@ def march_iterations(prob, warm_start: int, net: Optional[WarmStartNet] = None, 
     with TimeLevelSolver.from_problem(prob, rtol=rtol, warm_start=warm_start) as s:
         if net is not None:
             net.attach(s)
-        F = device_sources(prob, s.device) if F is None else F
+        F = device_sources(prob, s) if F is None else F
         code, stats = s.solve(F)
         N.check(code, "march")
         return [st["iters"] for st in stats], [st["guess"] for st in stats]
@@ -249,15 +250,13 @@ def main(argv=None):
             big.set_params(theta)
             res = {"prev": [], "extrap": [], "net": [], "net_levels_using_net": 0, "levels": 0}
             for prob in held:
-                F = device_sources(prob, big.device)
                 for key, ws, nt in (("prev", N.TSFCDE_WS_PREV, None), ("extrap", N.TSFCDE_WS_EXTRAP, None),
                                     ("net", N.TSFCDE_WS_NET, big)):
-                    it, g = march_iterations(prob, ws, nt, F=F)
+                    it, g = march_iterations(prob, ws, nt)
                     res[key] += it[2:]
                     if key == "net":
                         res["net_levels_using_net"] += sum(1 for x in g[2:] if x == N.TSFCDE_WS_NET)
                         res["levels"] += len(g) - 2
-                del F
             big.close()
             summary = {k: float(np.mean(v)) for k, v in res.items() if isinstance(v, list)}
             summary["net_share"] = res["net_levels_using_net"] / max(1, res["levels"])

@@ -25,10 +25,10 @@ def main():
     n = prob.n
     rng = np.random.default_rng(20160301)
     rows = np.unique(np.concatenate([[0, 1, 1023, 1024, n // 2, n - 2, n - 1], rng.integers(0, n, size=2048)]))
-    U = [prob.initial_vector()]
+    U = [O.initial_level(prob)]
     levels = []
     for j in range(2):
-        f = prob.source_level(j)
+        f = O.source_level(prob, j)
         u, its = O.level_solve_pcgs(prob, np.array(U), j, f, rtol=1e-12)
         g = O.rhs_fft(prob, np.array(U), j, f)
         r = g - O.embedding_product(prob, j, u, "A")

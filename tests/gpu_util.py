@@ -51,5 +51,31 @@ def row_scale(prob, j, x):
     an upper bound of sum_k |A_ik x_k| for every row i."""
     e, gam, dp, dm = O.level_scalars(prob, j)
     wsum = float(np.sum(np.abs(O.wsgd_weights(prob.beta, prob.n + 1))))
-    return (abs(e) + prob.sigma * (abs(gam) / prob.h + (dp + dm) * prob.h ** (-prob.beta) * wsum)) * float(
-        np.max(np.abs(x)))
+    h, sg = O.mesh_h(prob), O.sigma_of(prob.alpha)
+    return (abs(e) + sg * (abs(gam) / h + (dp + dm) * h ** (-prob.beta) * wsum)) * float(np.max(np.abs(x)))
+
+
+def sources(s, prob, levels=None):
+    """f of every level (rows) at the plan's own nodes and sampling instants
+    t_{j+sigma} (tsfcde_nodes, tsfcde_level_time), on the device; the oracle
+    samples its own.  Manufactured sources go through their separable form."""
+    import workloads as W
+    ts = s.level_times()[: (levels if levels is not None else s.M)]
+    x = s.nodes()
+    if prob.solution is not None and prob.f_fn is None:
+        return W.device_sources(prob, x, ts, dev())
+    return t64(np.stack([prob.f(x, t) for t in ts]))
+
+
+def batch_sources(bs, probs):
+    """sources() for every member of a BatchSolver (each at its own nodes and
+    instants)."""
+    import workloads as W
+    out = []
+    for i, prob in enumerate(probs):
+        x, ts = bs.nodes(i), bs.level_times(i)
+        if prob.solution is not None and prob.f_fn is None:
+            out.append(W.device_sources(prob, x, ts, dev()))
+        else:
+            out.append(t64(np.stack([prob.f(x, t) for t in ts])))
+    return out

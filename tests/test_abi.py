@@ -73,8 +73,45 @@ def test_null_arguments_rejected(N):
 
 
 def test_strerror(N):
-    for code in range(-8, 1):
-        assert N.lib().tsfcde_strerror(code)
+    for code in range(-9, 1):
+        assert N.lib().tsfcde_strerror(code) != b"unknown status", code
+
+
+def test_plan_queries_reject_null(N):
+    L = N.lib()
+    assert np.isnan(L.tsfcde_level_time(None, 0))
+    x = (ctypes.c_double * 4)()
+    assert L.tsfcde_nodes(None, x) == -1
+
+
+def test_struct_layouts_match_c(N, tmp_path):
+    """The ctypes structs have the C compiler's layout (offsets of every
+    field and sizes), checked against gcc on include/tsfcde.h."""
+    import os
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tsfcde.h"', "int main(void) {"]
+    for cname, cls in (("tsfcde_problem", N.tsfcde_problem), ("tsfcde_stats", N.tsfcde_stats),
+                       ("tsfcde_net_sample", N.tsfcde_net_sample)):
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               check=True).stdout.split("\n") if line)
+    for cname, cls in (("tsfcde_problem", N.tsfcde_problem), ("tsfcde_stats", N.tsfcde_stats),
+                       ("tsfcde_net_sample", N.tsfcde_net_sample)):
+        for fname, _ in cls._fields_:
+            assert int(out[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
+        assert int(out[cname]) == ctypes.sizeof(cls), cname
 
 
 @pytest.mark.parametrize("n", [4, 5, 8, 100, 1023, 1 << 20, (1 << 23) - 1, 1 << 24])

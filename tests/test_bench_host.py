@@ -18,15 +18,36 @@ def test_more_than_one_gpu_is_refused():
 
 def test_cpu_baseline_record():
     """A short sample: the FFT-PCGS oracle at n = 2^10 on the first levels,
-    the dense-LU oracle beside it; the fields the bench line carries."""
+    the dense-LU sweep beside it (median of repeats, every host core); the
+    fields the bench line carries."""
     sys.path.insert(0, ROOT)
     import bench
-    rec = bench.cpu_baseline(1 << 10, 16, 1e-10, budget_s=1.0, lu_budget_s=0.5)
+    rec = bench.cpu_baseline(1 << 10, 16, 1e-10, budget_s=1.0, lu_sizes=(64, 128), lu_reps=3)
     assert rec["kind"] == "oracle" and rec["unit"] == "level-solves/s" and rec["cores"] == 1
+    assert rec["host_cores"] == bench.host_cores() >= 1
     assert rec["value"] > 0 and "FFT-PCGS oracle" in rec["sample"]
     lu = rec["dense_lu"]
-    assert lu["levels"] >= 1 and lu["measured_n"] == 2048
-    assert abs(lu["value_extrapolated"] - lu["measured_value"] * (2048 / 1024) ** 3) <= 1e-9 * lu["value_extrapolated"]
+    assert lu["cores"] == rec["host_cores"] and [r["n"] for r in lu["sweep"]] == [64, 128]
+    for r in lu["sweep"]:
+        assert r["repeats"] == 3 and r["seconds_per_level"] > 0
+        assert abs(r["level_solves_per_s"] * r["seconds_per_level"] - 1) < 1e-12
+    big = lu["sweep"][-1]
+    assert abs(lu["value_extrapolated"] - big["level_solves_per_s"] * (128 / 1024) ** 3) <= 1e-9 * lu["value_extrapolated"]
+
+
+def test_acceptance_summary():
+    """The acceptance record of a march: failed levels by status code, the
+    largest backward error and true residual among the levels that computed
+    them (-1 = not computed), total restarts."""
+    sys.path.insert(0, ROOT)
+    import bench
+    st = [{"code": 0, "backward_err": 3e-14, "relres_true": 2e-9, "restarts": 0},
+          {"code": -9, "backward_err": 5e-12, "relres_true": 4e-7, "restarts": 3},
+          {"code": 0, "backward_err": -1.0, "relres_true": -1.0, "restarts": 1}]
+    a = bench.acceptance(st)
+    assert a == {"levels": 3, "failed_levels": 1, "max_backward_err": 5e-12, "max_relres_true": 4e-7,
+                 "restarts": 4}
+    assert bench.acceptance(st[2:])["max_backward_err"] is None
 
 
 def test_path_bytes_model():

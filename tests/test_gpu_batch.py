@@ -7,7 +7,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from gpu_util import banner, host, need_gpu, relerr, t64
+from gpu_util import banner, batch_sources, host, need_gpu, relerr, t64
 
 pytestmark = pytest.mark.gpu
 
@@ -29,8 +29,8 @@ def test_batch_matches_single_and_oracle(warm):
     banner(f"batch vs single, warm={warm}")
     probs = _instances(12, 6, 40, 3000, seed=11)
     assert len({p.n for p in probs}) > 6
-    Fs = [t64(np.stack([p.source_level(j) for j in range(p.M)])) for p in probs]
     with P.BatchSolver(probs, rtol=1e-13, warm_start=warm) as bs:
+        Fs = batch_sources(bs, probs)
         for j in range(probs[0].M):
             code, stats = bs.step([F[j] for F in Fs])
             assert code == 0, stats
@@ -53,8 +53,8 @@ def test_batch_uneven_convergence_and_zero_source():
     import paper_1603_00279_amd as P
     banner("batch uneven")
     probs = _instances(6, 4, 100, 2000, seed=5)
-    Fs = [t64(np.stack([p.source_level(j) for j in range(p.M)])) for p in probs]
     with P.BatchSolver(probs, rtol=1e-12) as bs:
+        Fs = batch_sources(bs, probs)
         bs.reset([torch.zeros(p.n, dtype=torch.float64, device="cuda") for p in probs])
         its = []
         for j in range(probs[0].M):
@@ -74,8 +74,8 @@ def test_batch_crosses_history_blocks():
     import paper_1603_00279_amd as P
     banner("batch, 19 levels")
     probs = _instances(4, 19, 40, 300, seed=23)
-    Fs = [t64(np.stack([p.source_level(j) for j in range(p.M)])) for p in probs]
     with P.BatchSolver(probs, rtol=1e-13) as bs:
+        Fs = batch_sources(bs, probs)
         for j in range(probs[0].M):
             code, stats = bs.step([F[j] for F in Fs])
             assert code == 0, stats
@@ -93,11 +93,12 @@ def test_batch_folded_finishing_is_bitwise_unfolded():
     import paper_1603_00279_amd as P
     banner("batch fold vs no fold")
     probs = _instances(6, 10, 60, 2500, seed=29)
-    Fs = [t64(np.stack([p.source_level(j) for j in range(p.M)])) for p in probs]
     runs = []
+    Fs = None
     for flags in (0, P.TSFCDE_FLAG_NO_FOLD):
         its = []
         with P.BatchSolver(probs, rtol=1e-12, flags=flags) as bs:
+            Fs = batch_sources(bs, probs) if Fs is None else Fs
             for j in range(probs[0].M):
                 code, stats = bs.step([F[j] for F in Fs])
                 assert code == 0, stats

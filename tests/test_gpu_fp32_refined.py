@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from gpu_util import banner, host, need_gpu, relerr, t64
+from gpu_util import banner, host, need_gpu, relerr, sources, t64
 
 pytestmark = pytest.mark.gpu
 EPS = 2.2e-16
@@ -22,10 +22,6 @@ def _gpu():
     P.lib()
 
 
-def _sources(prob):
-    return t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
-
-
 def test_refined_small_config_every_level_fp32():
     """alpha = 0.5, beta = 1.5, n = 64, M = 64: every level refines in FP32
     down to a true residual of 1e-13 and matches the oracle to 1e-10."""
@@ -34,7 +30,7 @@ def test_refined_small_config_every_level_fp32():
     prob = W.config_small()
     Uref = O.march(prob)
     with P.TimeLevelSolver.from_problem(prob, rtol=1e-13, precision=P.TSFCDE_FP32_REFINED) as s:
-        code, stats = s.solve(_sources(prob))
+        code, stats = s.solve(sources(s, prob))
         U = host(s.history())
     assert code == 0
     assert all(st["precision_used"] == P.TSFCDE_FP32_REFINED for st in stats)
@@ -54,7 +50,7 @@ def test_refined_matches_oracle(n, alpha, beta):
     prob = W.config_large(n=n, M=8, alpha=alpha, beta=beta)
     Uref = O.march(prob)
     with P.TimeLevelSolver.from_problem(prob, rtol=1e-13, precision=P.TSFCDE_FP32_REFINED) as s:
-        code, stats = s.solve(_sources(prob))
+        code, stats = s.solve(sources(s, prob))
         U = host(s.history())
     assert code == 0
     used = {st["precision_used"] for st in stats}
@@ -74,7 +70,7 @@ def test_refined_default_tolerance_stays_fp32(n):
     prob = W.config_small(n=n, M=8)
     Uref = O.march(prob)
     with P.TimeLevelSolver.from_problem(prob, rtol=1e-10, precision=P.TSFCDE_FP32_REFINED) as s:
-        code, stats = s.solve(_sources(prob))
+        code, stats = s.solve(sources(s, prob))
         U = host(s.history())
     assert code == 0
     assert all(st["precision_used"] == P.TSFCDE_FP32_REFINED for st in stats), [st["precision_used"] for st in stats]
@@ -94,8 +90,8 @@ def test_refined_forced_outside_envelope_falls_back():
     import paper_1603_00279_amd as P
     banner("fp32 refined forced n=2^14")
     prob = W.config_large(n=1 << 14, M=3)
-    F = _sources(prob)
     with P.TimeLevelSolver.from_problem(prob, rtol=1e-10) as s:
+        F = sources(s, prob)
         s.solve(F)
         U64 = host(s.history())
     with P.TimeLevelSolver.from_problem(prob, rtol=1e-10, precision=P.TSFCDE_FP32_REFINED,
@@ -115,7 +111,7 @@ def test_refined_policy_keeps_fp64_at_large_kappa():
     banner("fp32 refined policy n=2^14")
     prob = W.config_large(n=1 << 14, M=2)
     with P.TimeLevelSolver.from_problem(prob, rtol=1e-10, precision=P.TSFCDE_FP32_REFINED) as s:
-        code, stats = s.solve(_sources(prob))
+        code, stats = s.solve(sources(s, prob))
     assert code == 0
     assert all(st["precision_used"] == P.TSFCDE_FP64 for st in stats)
 

@@ -17,7 +17,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from gpu_util import banner, host, need_gpu, row_scale, sample_rows, t64
+from gpu_util import banner, host, need_gpu, row_scale, sample_rows, sources, t64
 
 pytestmark = pytest.mark.gpu
 
@@ -105,7 +105,7 @@ def test_rhs_full_size(j):
     ref = O.rhs_rows(prob, U, j, f, rows)
     # history: kappa sum_s |c_{j-s}| |u^{s+1} - u^s| <= kappa * sum|c| * 2 max|U|
     c = O.l21s_c(prob.alpha, j)
-    hist = O.l21s_kappa(prob.alpha, prob.tau) * float(np.sum(np.abs(c))) * 2.0 * float(np.max(np.abs(U)))
+    hist = O.l21s_kappa(prob.alpha, O.time_step(prob)) * float(np.sum(np.abs(c))) * 2.0 * float(np.max(np.abs(U)))
     S = row_scale(prob, j, U[j]) + hist + float(np.max(np.abs(f)))
     d = np.abs(g[rows] - ref)
     assert d.max() <= 1e-12 * S, d.max() / S
@@ -123,9 +123,10 @@ def test_levels_full_size():
     banner("levels n=2^20 M=512")
     prob = W.config_large(n=N_FULL, M=512)
     rows = sample_rows(prob.n, 5)
-    F = [prob.source_level(j) for j in range(4)]
+    F = [O.source_level(prob, j) for j in range(4)]  # the oracle's own sampling, for its rows of g
     with make(prob, rtol=1e-10, flags=P.TSFCDE_FLAG_VERIFY) as s:
-        stats = [s.step(t64(F[j])) for j in range(4)]
+        Fd = sources(s, prob, 4)  # the plan's
+        stats = [s.step(Fd[j]) for j in range(4)]
         U = host(s.history()[:5])
     for j in range(4):
         st = stats[j]
@@ -187,15 +188,15 @@ def test_levels_against_fft_pcgs_golden():
     prob = W.config_large(n=N_FULL, M=512)
     assert (gold["n"], gold["M"], gold["alpha"], gold["beta"]) == (prob.n, prob.M, prob.alpha, prob.beta)
     rows = np.array(gold["rows"])
-    u0 = prob.initial_vector()
-    F = [prob.source_level(j) for j in range(2)]
-    u1_ref, _ = O.level_solve_pcgs(prob, u0[None, :], 0, F[0], rtol=1e-12)
+    u0 = O.initial_level(prob)
+    u1_ref, _ = O.level_solve_pcgs(prob, u0[None, :], 0, O.source_level(prob, 0), rtol=1e-12)
     with make(prob, rtol=1e-10, flags=P.TSFCDE_FLAG_VERIFY) as s:
         L = s.embedding_length
-        st1 = s.step(t64(F[0]))
+        F = sources(s, prob, 2)
+        st1 = s.step(F[0])
         u1 = host(s.history()[1])
         s.set_state(1, t64(np.stack([u0, u1_ref])))
-        st2 = s.step(t64(F[1]))
+        st2 = s.step(F[1])
         u2 = host(s.history()[2])
     for j, (st, u, extra) in enumerate(((st1, u1, 0), (st2, u2, 2))):
         lev = gold["levels"][j]

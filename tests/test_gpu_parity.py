@@ -18,7 +18,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from gpu_util import banner, dev, host, need_gpu, relerr, t64
+from gpu_util import banner, dev, host, need_gpu, relerr, sources, t64
 
 pytestmark = pytest.mark.gpu
 
@@ -144,14 +144,21 @@ def test_march_small_config(warm):
     banner(f"march small warm={warm}")
     prob = W.config_small()
     Uref = O.march(prob)
-    F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
     with make(prob, rtol=1e-13, warm_start=warm) as s:
-        code, stats = s.solve(F)
+        code, stats = s.solve(sources(s, prob))
         U = host(s.history())
-    for j in range(prob.M + 1):
-        assert relerr(U[j], Uref[j]) < 1e-10 or np.linalg.norm(Uref[j]) == 0, j
+    worst = 0.0
+    for j in range(1, prob.M + 1):
+        e_norm = relerr(U[j], Uref[j])
+        e_elem = float(np.max(np.abs(U[j] - Uref[j])) / np.max(np.abs(Uref[j])))
+        worst = max(worst, e_norm, e_elem)
+        assert e_norm < 1e-10 and e_elem < 1e-10, (j, e_norm, e_elem)
     its = [st["iters"] for st in stats]
-    assert max(its) <= 40
+    print(f"[march small warm={warm}] worst per-level error {worst:.2e}, CGS iterations {min(its)}..{max(its)}",
+          flush=True)
+    # Sec. 4: a handful of PCGS iterations per level (6 to 10 at the paper's
+    # 1e-12; the tolerance here is 1e-13)
+    assert max(its) <= 12, its
 
 
 @pytest.mark.parametrize("n,M,alpha,beta", [(256, 24, 0.7, 1.8), (1024, 12, 0.3, 1.2), (4096, 6, 0.9, 1.95),
@@ -168,13 +175,19 @@ def test_march_parity_sizes(n, M, alpha, beta):
     banner(f"march n={n} M={M}")
     prob = W.config_large(n=n, M=M, alpha=alpha, beta=beta)
     Uref = O.march(prob)
-    F = t64(np.stack([prob.source_level(j) for j in range(M)]))
     with make(prob, rtol=1e-13, flags=P.TSFCDE_FLAG_VERIFY) as s:
-        code, stats = s.solve(F)
+        code, stats = s.solve(sources(s, prob), raise_on_error=False)
         U = host(s.history())
+    assert code == 0, (code, stats)
+    worst = []
     for j in range(1, M + 1):
         bound = max(1e-10, 8 * 2.2e-16 * np.linalg.cond(O.level_A(prob, j - 1), 1))
-        assert relerr(U[j], Uref[j]) < bound, (j, relerr(U[j], Uref[j]), bound)
+        e_norm = relerr(U[j], Uref[j])
+        e_elem = float(np.max(np.abs(U[j] - Uref[j])) / np.max(np.abs(Uref[j])))
+        worst.append((e_norm, e_elem, bound))
+        assert e_norm < bound and e_elem < bound, (j, e_norm, e_elem, bound)
+    print(f"[march n={n} M={M}] worst normwise {max(w[0] for w in worst):.2e}, elementwise "
+          f"{max(w[1] for w in worst):.2e}, largest bound {max(w[2] for w in worst):.2e}", flush=True)
 
 
 def test_paper_example2_level_errors():
@@ -184,9 +197,8 @@ def test_paper_example2_level_errors():
     banner("example2 n=64")
     base = W.example2(0.5, 1.5, 65)  # n = 64 interior points
     Uref = O.march(base)
-    F = t64(np.stack([base.source_level(j) for j in range(base.M)]))
     with make(base, rtol=1e-13) as s:
-        s.solve(F)
+        s.solve(sources(s, base))
         U = host(s.history())
     assert relerr(U, Uref) < 1e-10
     e_gpu = O.error_norms(base, U)
@@ -199,8 +211,8 @@ def test_determinism_and_resume():
     bitwise identically (deterministic reductions, no atomics in sums)."""
     banner("determinism")
     prob = W.config_large(n=1024, M=8)
-    F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
     with make(prob) as s1:
+        F = sources(s1, prob)
         s1.solve(F)
         U1 = host(s1.history())
     with make(prob) as s2:
@@ -219,11 +231,10 @@ def test_error_paths():
     banner("error paths")
     prob = W.config_large(n=64, M=3)
     with make(prob, maxit=1, rtol=1e-15) as s:
-        st = s.step(t64(prob.source_level(0)), raise_on_error=False)
+        st = s.step(sources(s, prob, 1)[0], raise_on_error=False)
         assert st["code"] == P.TSFCDE_ENOCONV and st["iters"] == 1
     with make(prob) as s:
-        F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
-        s.solve(F)
+        s.solve(sources(s, prob))
         assert s.level == prob.M
         st = s.step(None, raise_on_error=False)
         assert st["code"] == P.TSFCDE_EDONE
@@ -232,9 +243,12 @@ def test_error_paths():
         st = s.step(t64(bad), raise_on_error=False)
         assert st["code"] == P.TSFCDE_ENONFINITE
     with pytest.raises(P.TsfcdeError):
-        P.TimeLevelSolver(alpha=0.5, beta=1.5, n=64, M=2, gamma_at=[0, 0], dplus_at=[1, -1], dminus_at=[1, 1])
+        P.TimeLevelSolver(alpha=0.5, beta=1.5, n=64, M=2, gamma=[0, 0], dplus=[1, -1], dminus=[1, 1])
     with pytest.raises(P.TsfcdeError):
-        P.TimeLevelSolver(alpha=0.5, beta=1.5, n=3, M=2, gamma_at=[0, 0], dplus_at=[1, 1], dminus_at=[1, 1])
+        P.TimeLevelSolver(alpha=0.5, beta=1.5, n=3, M=2, gamma=[0, 0], dplus=[1, 1], dminus=[1, 1])
+    with pytest.raises(P.TsfcdeError):  # a negative diffusion coefficient met by the plan's own sampling
+        P.TimeLevelSolver(alpha=0.5, beta=1.5, n=64, M=4, gamma=lambda t: 0.0, dplus=lambda t: 1.0 - 2 * t,
+                          dminus=lambda t: 1.0)
 
 
 def test_zero_source_zero_solution():
@@ -255,11 +269,10 @@ def test_warm_starts_cut_iterations(n):
     iterations."""
     banner(f"warm starts n={n}")
     prob = W.config_large(n=n, M=16)
-    F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
     runs = {}
     for warm in (0, 1, 2):
         with make(prob, rtol=1e-12, warm_start=warm) as s:
-            code, stats = s.solve(F)
+            code, stats = s.solve(sources(s, prob))
             runs[warm] = (host(s.history()), [st["iters"] for st in stats])
     U0 = runs[0][0]
     # each run stops at |r| <= 1e-12 |g|; two such solutions differ by at most
@@ -310,9 +323,8 @@ def test_general_n_march(n, M):
     banner(f"general-n march n={n}")
     prob = W.config_large(n=n, M=M, alpha=0.45, beta=1.65)
     Uref = O.march(prob)
-    F = t64(np.stack([prob.source_level(j) for j in range(M)]))
     with make(prob, rtol=1e-13) as s:
-        s.solve(F)
+        s.solve(sources(s, prob))
         U = host(s.history())
     for j in range(1, M + 1):
         assert relerr(U[j], Uref[j]) < 1e-10, (j, relerr(U[j], Uref[j]))
@@ -331,9 +343,8 @@ def test_paper_grids_on_gpu(example, alpha, beta, N, col, ref):
     make_p = W.example1 if example == 1 else W.example2
     prob = make_p(alpha, beta, N)
     Uref = O.march(prob)
-    F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
     with make(prob, rtol=1e-13) as s:
-        s.solve(F)
+        s.solve(sources(s, prob))
         U = host(s.history())
     assert relerr(U, Uref) < 1e-10
     l2, cn = O.error_norms(prob, U)
@@ -351,9 +362,8 @@ def test_near_breakdown_level_is_rechecked():
     banner("near breakdown n=256")
     prob = W.config_small(n=256, M=8)
     Uref = O.march(prob)
-    F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
     with make(prob, rtol=1e-10) as s:
-        code, stats = s.solve(F)
+        code, stats = s.solve(sources(s, prob))
         U = host(s.history())
     assert code == 0
     assert stats[0]["restarts"] >= 1
@@ -371,8 +381,8 @@ def test_sampled_profiling_counts_and_leaves_results():
     durations are positive, and the march is bitwise the unprofiled one."""
     banner("sampled profiling")
     prob = W.config_large(n=1024, M=6)
-    F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
     with make(prob) as s:
+        F = sources(s, prob)
         s.solve(F)
         U0 = host(s.history())
     with make(prob) as s:
@@ -402,13 +412,12 @@ def test_folded_finishing_is_bitwise_unfolded(n, fp32):
     import paper_1603_00279_amd as P
     banner(f"folded finishing n={n} fp32={fp32}")
     prob = W.config_large(n=n, M=10)
-    F = t64(np.stack([prob.source_level(j) for j in range(prob.M)]))
     kw = dict(precision=P.TSFCDE_FP32_REFINED) if fp32 else {}
     base = P.TSFCDE_FLAG_FORCE_FP32 if fp32 else 0
     runs = []
     for flags in (base, base | P.TSFCDE_FLAG_NO_FOLD):
         with make(prob, rtol=1e-10, flags=flags, **kw) as s:
-            code, stats = s.solve(F)
+            code, stats = s.solve(sources(s, prob))
             runs.append((host(s.history()), [(st["iters"], st["outer_iters"]) for st in stats]))
     assert runs[0][1] == runs[1][1]
     assert np.array_equal(runs[0][0], runs[1][0])
@@ -420,9 +429,10 @@ def test_rhs_out_of_order_after_march():
     vector bit for bit, and every one matches the oracle."""
     banner("rhs out of order")
     prob = W.config_large(n=256, M=20, alpha=0.6, beta=1.7)
-    F = [prob.source_level(j) for j in range(prob.M)]
     with make(prob, rtol=1e-13) as s:
-        s.solve(t64(np.stack(F)))
+        Fd = sources(s, prob)
+        F = host(Fd)
+        s.solve(Fd)
         U = host(s.history())
         got = {}
         for j in (17, 19, 10, 10, 3, 19, 9):

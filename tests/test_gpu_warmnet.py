@@ -145,8 +145,8 @@ def test_zero_network_reproduces_extrapolation():
     from paper_1603_00279_amd import warmnet as WN
     banner("zero net = extrapolation")
     prob = W.config_large(n=1000, M=10)
-    F = WN.device_sources(prob, torch.device("cuda"))
     with P.TimeLevelSolver.from_problem(prob, warm_start=P.TSFCDE_WS_EXTRAP) as s:
+        F = WN.device_sources(prob, s)
         s.solve(F)
         Ue = s.history().cpu().numpy()
     with P.WarmStartNet(max_points=prob.n, max_batch=1) as net, \

@@ -65,9 +65,10 @@ def test_alpha1_beta2_is_crank_nicolson():
     # with central differences, assembled as a tridiagonal (banded) system.
     prob = W.config_small(n=40, M=16, alpha=1.0, beta=2.0)
     U = O.march(prob)
-    n, h, tau = prob.n, prob.h, prob.tau
-    x = prob.x_interior()
-    u = prob.initial_vector()
+    n = prob.n
+    h, tau = (prob.b - prob.a) / (n + 1), prob.T / prob.M
+    x = prob.a + h * np.arange(1, n + 1)
+    u = prob.phi(x)
     for j in range(prob.M):
         t = (j + 0.5) * tau
         g, d = prob.gamma(t), prob.dplus(t) + prob.dminus(t)
@@ -92,12 +93,13 @@ def _all_levels_at_once(prob, f_levels):
       - [gamma/(2h)(v_{i+1}-v_{i-1}) + D+/h^b sum_{k=0}^{i+1} w_k v_{i-k+1}
          + D-/h^b sum_{k=0}^{N-i+1} w_k v_{i+k-1}] = f_i,
     v = sigma u^{j+1} + (1-sigma) u^j, boundary nodes 0 and N zero."""
-    n, M, h, b = prob.n, prob.M, prob.h, prob.beta
+    n, M, b = prob.n, prob.M, prob.beta
     N = n + 1
-    sigma = prob.sigma
-    kap = O.l21s_kappa(prob.alpha, prob.tau)
+    h, tau = (prob.b - prob.a) / N, prob.T / M
+    sigma = 1.0 - prob.alpha / 2.0
+    kap = O.l21s_kappa(prob.alpha, tau)
     w = O.wsgd_weights(b, N + 1)
-    u0 = prob.initial_vector()
+    u0 = prob.phi(prob.a + h * np.arange(1, N))
     G = np.zeros((M * n, M * n))
     R = np.zeros(M * n)
 
@@ -111,7 +113,7 @@ def _all_levels_at_once(prob, f_levels):
             G[row, (level - 1) * n + node - 1] += coef
 
     for j in range(M):
-        t = prob.t_sigma(j)
+        t = (j + sigma) * tau
         gam, dp, dm = prob.gamma(t), prob.dplus(t), prob.dminus(t)
         c = O.l21s_c(prob.alpha, j)
         for i in range(1, N):
@@ -198,9 +200,9 @@ def test_history_enters_with_minus_sign():
     U = O.march(prob)
     good = O.error_norms(prob, U)[0]
     Ubad = np.zeros_like(U)
-    Ubad[0] = prob.initial_vector()
+    Ubad[0] = O.initial_level(prob)
     for j in range(prob.M):
-        g = O.level_B(prob, j) @ Ubad[j] + O.history_term(prob, Ubad, j) + prob.source_level(j)
+        g = O.level_B(prob, j) @ Ubad[j] + O.history_term(prob, Ubad, j) + O.source_level(prob, j)
         Ubad[j + 1] = np.linalg.solve(O.level_A(prob, j), g)
     bad = O.error_norms(prob, Ubad)[0]
     assert good < 3e-4 < 30 * good < bad

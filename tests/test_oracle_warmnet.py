@@ -105,8 +105,8 @@ def test_adam_first_step_is_lr_sign():
 
 
 def test_level_features_by_hand():
-    class P:
-        sigma, h, beta, alpha = 0.75, 0.25, 1.5, 0.5
+    class P:  # alpha = 0.5: sigma = 0.75; n = 3 on [0, 1]: h = 0.25
+        beta, alpha, a, b, n = 1.5, 0.5, 0.0, 1.0, 3
     f = N.level_features(P, 0, eta_j=2.0, gamma_j=-1.0, dplus_j=1.0, dminus_j=0.5)
     qg = 0.75 * -1.0 / (0.25 * 2.0)
     qp = 0.75 * 1.0 * 0.25 ** -1.5 / 2.0

@@ -5,8 +5,8 @@ Carpentieri and Alikhanov, arXiv:1603.00279.
 This package only *describes problems*: coefficient functions, initial data,
 closed-form manufactured solutions and the source terms they imply, and the
 seeded parameter draws of the benchmark workloads.  It contains none of the
-difference scheme's arithmetic (no Grunwald weights, no L2-1sigma tables, no
-matrices, no solver).  Both the CPU oracle and the GPU path take their inputs
+difference scheme's arithmetic: no grid, no sampling instants, no weights,
+no time-discretisation tables, no matrices, no solver.  Both the CPU oracle and the GPU path take their inputs
 from here; neither imports the other.
 """
 from .problems import (  # noqa: F401
@@ -20,4 +20,5 @@ from .problems import (  # noqa: F401
     warmstart_instances,
     HELD_OUT,
     SEED_BASE,
+    device_sources,
 )

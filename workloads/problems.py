@@ -2,12 +2,11 @@
 
 Conventions (shared by the oracle and the GPU path):
 
-* ``n`` is the number of interior unknowns; the mesh is x_i = a + i*h,
-  i = 0..n+1, h = (b - a)/(n + 1).  The paper's N (number of subintervals,
-  Sec. 2.1) is therefore n + 1.
-* ``M`` is the number of time steps, tau = T/M, t_j = j*tau.
-* Coefficients gamma(t), d_+(t), d_-(t) and the source f(x, t) are plain
-  callables; the scheme samples them at t_{j+sigma} (Sec. 2.1).
+* ``n`` is the number of interior unknowns and ``M`` the number of time
+  steps; where the grid points and sampling instants lie is the solver's
+  business (the CPU oracle and the library each compute their own).
+* Coefficients gamma(t), d_+(t), d_-(t), the source f(x, t) and the initial
+  condition phi(x) are plain callables of continuous x and t.
 
 Manufactured solutions have the separable form u(x, t) = theta(t) * P(x),
 with theta a finite sum of powers of t and P a polynomial carrying a double
@@ -140,26 +139,6 @@ class Problem:
     name: str = ""
     meta: dict = field(default_factory=dict)
 
-    # --- mesh ------------------------------------------------------------
-    @property
-    def h(self) -> float:
-        return (self.b - self.a) / (self.n + 1)
-
-    @property
-    def tau(self) -> float:
-        return self.T / self.M
-
-    @property
-    def sigma(self) -> float:
-        return 1.0 - self.alpha / 2.0
-
-    def x_interior(self) -> np.ndarray:
-        return self.a + self.h * np.arange(1, self.n + 1, dtype=np.float64)
-
-    def t_sigma(self, j: int) -> float:
-        """t_{j+sigma} = (j + sigma) * tau (Lemma 1)."""
-        return (j + self.sigma) * self.tau
-
     # --- data ------------------------------------------------------------
     def phi(self, x) -> np.ndarray:
         if self.phi_fn is not None:
@@ -184,34 +163,28 @@ class Problem:
             raise ValueError("no closed-form solution for this problem")
         return self.solution.u(x, t)
 
-    # --- level samples ---------------------------------------------------
-    def coefficient_samples(self):
-        """gamma, d_+, d_- at t_{j+sigma}, j = 0..M-1 (arrays of length M)."""
-        ts = [self.t_sigma(j) for j in range(self.M)]
-        return (np.array([self.gamma(t) for t in ts], dtype=np.float64),
-                np.array([self.dplus(t) for t in ts], dtype=np.float64),
-                np.array([self.dminus(t) for t in ts], dtype=np.float64))
-
-    def initial_vector(self) -> np.ndarray:
-        return self.phi(self.x_interior())
-
-    def source_level(self, j: int) -> np.ndarray:
-        """f(x_i, t_{j+sigma}) on the interior nodes."""
-        return self.f(self.x_interior(), self.t_sigma(j))
-
-    def source_profiles(self):
-        """(profiles[4, n], coeffs[M, 4]) with f_j = coeffs[j] @ profiles.
-
-        Available for manufactured problems without a custom f; it lets a
-        caller build all M source vectors as one small matrix product.
-        """
+    # --- separable sources -----------------------------------------------
+    def source_matrix(self, x, ts):
+        """(profiles[4, len(x)], coeffs[len(ts), 4]) with f(x, t_k) =
+        coeffs[k] @ profiles for a manufactured problem without a custom f:
+        all sources at the nodes x and the instants ts come from one small
+        matrix product.  The caller chooses x and ts."""
         if self.solution is None or self.f_fn is not None:
             raise ValueError("separable source only for manufactured problems")
-        prof = self.solution.profiles(self.x_interior(), self.beta)
-        co = np.stack([self.solution.profile_coeffs(self.t_sigma(j), self.alpha, self.gamma,
-                                                    self.dplus, self.dminus)
-                       for j in range(self.M)])
+        prof = self.solution.profiles(np.asarray(x, dtype=np.float64), self.beta)
+        co = np.stack([self.solution.profile_coeffs(float(t), self.alpha, self.gamma, self.dplus, self.dminus)
+                       for t in ts])
         return prof, co
+
+
+def device_sources(prob: Problem, x, ts, device):
+    """f(x_i, t_k) for every instant t_k in ``ts`` (rows) at the nodes ``x``,
+    as an FP64 torch tensor on ``device``, from the separable form of a
+    manufactured source (one (K x 4) @ (4 x n) product)."""
+    import torch
+    prof, co = prob.source_matrix(x, ts)
+    return (torch.as_tensor(co, dtype=torch.float64, device=device)
+            @ torch.as_tensor(prof, dtype=torch.float64, device=device)).contiguous()
 
 
 def _x2_one_minus_x2(extra=(1.0,)):
@@ -223,7 +196,7 @@ def _x2_one_minus_x2(extra=(1.0,)):
 def example1(alpha: float, beta: float, N: int, M: Optional[int] = None) -> Problem:
     """Example 1 of Sec. 4: d_+ = 0.8, d_- = 0.5, gamma = -0.1 on [0,1]x[0,1],
     u = (t^(2+alpha) + 1) x^2 (1-x)^2.  ``N`` is the paper's number of
-    subintervals (h = 1/N); ``M`` defaults to N (tau = h)."""
+    subintervals; ``M`` (time steps) defaults to N."""
     M = N if M is None else M
     sol = ManufacturedSolution([(1.0, 2.0 + alpha), (1.0, 0.0)], _x2_one_minus_x2())
     return Problem(alpha=alpha, beta=beta, n=N - 1, M=M,
@@ -302,7 +275,7 @@ def warmstart_instances(count: int, n: int, M: int, seed: int = SEED_BASE + 4, h
     distributions at one grid size n, with (alpha, beta) outside the held-out
     rectangle HELD_OUT (training) or inside it (held-out evaluation), and
     Example 2's time dependence u = A (t^{2+alpha} + 1) x^2 (1-x)^2, whose
-    third time difference O(tau^3 t^{alpha-1}) leaves quadratic extrapolation
+    third time difference (of order step^3 t^{alpha-1}) leaves quadratic extrapolation
     a smooth error to correct (for a solution quadratic in t it would be
     exact).  Rejection sampling keeps the two sets disjoint for any seed."""
     rng = np.random.default_rng(seed)
