@@ -140,7 +140,56 @@ def forms(args, P, W, prob, F, u0, levels, plain_value, dev):
         res["batched"] = batched_form(args, P, W, dev)
     if args.form in ("all", "learned"):
         res["learned"] = learned_form(args, P, W, dev)
+    if args.form in ("all", "krylov"):
+        res["krylov"] = krylov_forms(args, P, prob, F, u0, levels, plain_value)
+    if args.form in ("all", "gsf"):
+        res["constant_gsf"] = gsf_form(args, P, W, dev)
     return res
+
+
+def krylov_forms(args, P, prob, F, u0, levels, plain_value):
+    """The headline march with the other Krylov method and the other
+    circulant preconditioner, beside the plain PCGS with Strang's."""
+    import numpy as np
+    import torch
+    out = {"workload": "headline"}
+    for name, kr, pc in (("bicgstab_strang", P.TSFCDE_KRYLOV_BICGSTAB, P.TSFCDE_PREC_STRANG),
+                         ("cgs_tchan", P.TSFCDE_KRYLOV_CGS, P.TSFCDE_PREC_TCHAN),
+                         ("bicgstab_tchan", P.TSFCDE_KRYLOV_BICGSTAB, P.TSFCDE_PREC_TCHAN)):
+        with P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, krylov=kr, preconditioner=pc) as sk:
+            timed_march(sk, F, u0, min(levels, 16), torch)  # warm-up
+            dt, st = timed_march(sk, F, u0, levels, torch)
+        out[name] = {"value": levels / dt, "unit": "level-solves/s",
+                     "iterations_mean": float(np.mean([x["iters"] for x in st])),
+                     "speedup_vs_plain": (levels / dt) / plain_value, "acceptance": acceptance(st)}
+        log(f"form {name}: {levels / dt:.1f} level-solves/s, {out[name]['iterations_mean']:.2f} iterations")
+    return out
+
+
+def gsf_form(args, P, W, dev):
+    """Constant coefficients at the headline size (Example 1's gamma, d_+-,
+    n = 2^20, M = 512): Algorithm 3 with the Gohberg-Semencul formula against
+    the plain PCGS march of the same problem."""
+    import numpy as np
+    import torch
+    prob = W.config_large_constant(n=args.n, M=args.M)
+    out = {"workload": f"n={prob.n}, M={prob.M}, alpha={prob.alpha}, beta={prob.beta}, gamma=-0.1, d+=0.8, d-=0.5"}
+    F = None
+    for name, flags in (("pcgs", 0), ("gsf", P.TSFCDE_FLAG_CONSTANT_GSF)):
+        with P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, flags=flags) as sg:
+            if F is None:
+                F = build_sources(prob, sg)
+            u0 = sg.history()[0].clone()
+            timed_march(sg, F, u0, prob.M, torch)  # warm-up (and, for gsf, the solves (3.4))
+            dt, st = timed_march(sg, F, u0, prob.M, torch)
+        out[name] = {"value": prob.M / dt, "unit": "level-solves/s", "acceptance": acceptance(st),
+                     "iterations_mean": float(np.mean([x["iters"] for x in st]))}
+        log(f"constant coefficients, {name}: {prob.M / dt:.1f} level-solves/s")
+    out["speedup_vs_plain"] = out["gsf"]["value"] / out["pcgs"]["value"]
+    out["note"] = ("timed march after a warm-up march; the two solves (3.4) run once per plan, before its first "
+                   "level j >= 1 (in the warm-up)")
+    del F
+    return out
 
 
 def warm_forms(args, P, prob, F, u0, levels, plain_value, res):
@@ -204,8 +253,9 @@ def batched_form(args, P, W, dev):
     ns = [p.n for p in probs]
     out = {"workload": f"{len(probs)} instances, n log-uniform in [2^10, 2^16] (sum {sum(ns)}), M={args.batch_M}"}
     Fall = None
-    for ws, key in ((P.TSFCDE_WS_ZERO, "zero_guess"), (P.TSFCDE_WS_EXTRAP, "extrapolated")):
-        with P.BatchSolver(probs, rtol=args.rtol, warm_start=ws) as bs:
+    for ws, key, flags in ((P.TSFCDE_WS_ZERO, "zero_guess", 0), (P.TSFCDE_WS_ZERO, "zero_guess_graphs", P.TSFCDE_FLAG_GRAPHS),
+                           (P.TSFCDE_WS_EXTRAP, "extrapolated", 0)):
+        with P.BatchSolver(probs, rtol=args.rtol, warm_start=ws, flags=flags) as bs:
             if Fall is None:  # (M x n) per instance at its own nodes and instants
                 Fall = [W.device_sources(p, bs.nodes(i), bs.level_times(i), dev) for i, p in enumerate(probs)]
             zeros = [torch.zeros(n, dtype=torch.float64, device=dev) for n in ns]
@@ -369,7 +419,7 @@ def main():
     ap.add_argument("--profile-period", type=int, default=7,
                     help="events on every k-th launch of the profiled class (1 = all)")
     ap.add_argument("--fp32-n", type=int, default=2048, help="grid of the FP32-refined form inside its envelope")
-    ap.add_argument("--form", default="all", choices=["all", "warm", "fp32", "batched", "learned"],
+    ap.add_argument("--form", default="all", choices=["all", "warm", "fp32", "batched", "learned", "krylov", "gsf"],
                     help="which of the other forms to run (for profiling one of them)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-M", type=int, default=128)
@@ -391,13 +441,18 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     if args.copy_calibration > 0:
+        # reference for the HBM counters: plain copies of a source larger than
+        # the 256 MB Infinity Cache, evicted before each copy by writing a
+        # second buffer of the same size
         src = torch.rand(args.copy_calibration << 17, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
+        evict = torch.empty_like(src)
         for _ in range(3):
+            evict.fill_(1.0)
             dst.copy_(src)
         torch.cuda.synchronize()
-        log(f"copy calibration: 3 copies of {args.copy_calibration} MiB")
-        del src, dst
+        log(f"copy calibration: 3 copies of {args.copy_calibration} MiB, each after a {args.copy_calibration} MiB fill")
+        del src, dst, evict
     prob = W.config_large(n=args.n, M=args.M)
     levels = args.levels if args.levels > 0 else prob.M
     log(f"workload n={prob.n} M={prob.M} levels/step={levels} alpha={prob.alpha} beta={prob.beta}")

@@ -100,6 +100,55 @@ extern "C" {
 #define TSFCDE_FLAG_STRICT_RESIDUAL 16 /* accept a level only at a true residual
                                     |g - A u| <= rtol |g| (not at backward
                                     error 1e-13); otherwise TSFCDE_EACCEPT   */
+#define TSFCDE_FLAG_CONSTANT_GSF 32 /* constant gamma, d_+- (every sample equal,
+                                    else tsfcde_plan returns TSFCDE_EINVAL;
+                                    FP64 single plans only): Algorithm 3.
+                                    Level 0 by PCGS; before level 1, A x = e_1
+                                    and A y = e_n (3.4) by PCGS to 1e-13 (or
+                                    rtol if tighter); every level j >= 1 then
+                                    applies A^-1 by the Gohberg-Semencul
+                                    formula (Algorithm 1: four triangular
+                                    Toeplitz products through the length-2n
+                                    embedding) and checks the result like a
+                                    converged CGS solve (CGS continues from
+                                    it if the check fails).  xi_0 = 0 or a
+                                    failed solve (3.4) ends level 1 with
+                                    TSFCDE_EBREAKDOWN or that solve's code  */
+
+/* Krylov methods (tsfcde_problem.krylov).  Both are right-preconditioned
+ * (the monitored residual is the unpreconditioned one), run on
+ * device-resident scalars and meet the same stopping and acceptance tests;
+ * each iteration makes two products with A and two preconditioner solves.
+ * The FP32 inner solve of TSFCDE_FP32_REFINED is always CGS; the batched
+ * form runs CGS only. */
+#define TSFCDE_KRYLOV_CGS 0      /* conjugate gradient squared (Sec. 3.2)    */
+#define TSFCDE_KRYLOV_BICGSTAB 1 /* BiCGSTAB (van der Vorst 1992), the smooth-
+                                    residual alternative the paper's outlook
+                                    (Sec. 5) points to among Krylov solvers  */
+
+/* circulant preconditioners (tsfcde_problem.preconditioner), each assembled
+ * like (3.7) from the circulants of Q, W_beta and W_beta^T */
+#define TSFCDE_PREC_STRANG 0     /* Strang's circulant s(.) of (3.7)         */
+#define TSFCDE_PREC_TCHAN 1      /* T. Chan's optimal circulant (the circulant
+                                    nearest in the Frobenius norm):
+                                    c_k = ((n-k) t_k + k t_{k-n}) / n        */
+
+#define TSFCDE_FLAG_GRAPHS 64   /* batched form: replay each chunk of CGS
+                                    iterations (every group's launches) from
+                                    a HIP graph captured the first time that
+                                    chunk length is needed (kernels only; the
+                                    level's descriptors are re-staged at the
+                                    same device addresses); the results are
+                                    bitwise those of direct launches          */
+
+#define TSFCDE_FLAG_NO_TUNE 128 /* batched form: keep the default values per
+                                    lane (8) in every group's middle passes
+                                    instead of timing 4 and 8 at plan time   */
+
+/* solution methods reported in tsfcde_stats.method */
+#define TSFCDE_METHOD_PCGS 0     /* Strang-preconditioned CGS (Algorithm 2)  */
+#define TSFCDE_METHOD_GSF 1      /* Gohberg-Semencul formula (Algorithm 1)   */
+#define TSFCDE_METHOD_PBICGSTAB 2 /* preconditioned BiCGSTAB                 */
 
 /* operators for tsfcde_apply */
 #define TSFCDE_OP_A 0            /* y = A^(j+sigma) x      (3.3)            */
@@ -149,6 +198,10 @@ typedef struct tsfcde_problem {
      * device source pointer is NULL; NULL here means f = 0 at such levels. */
     tsfcde_src_fn f;
     void *f_user;
+    int32_t krylov;         /* TSFCDE_KRYLOV_CGS (0, the paper's PCGS) or
+                               TSFCDE_KRYLOV_BICGSTAB                        */
+    int32_t preconditioner; /* TSFCDE_PREC_STRANG (0, (3.7)) or
+                               TSFCDE_PREC_TCHAN                             */
 } tsfcde_problem;
 
 typedef struct tsfcde_stats {
@@ -173,6 +226,10 @@ typedef struct tsfcde_stats {
                              TSFCDE_FP32_REFINED_FELL_BACK                   */
     int32_t guess;        /* initial guess used: TSFCDE_WS_ZERO, _PREV,
                              _EXTRAP or _NET                                 */
+    int32_t method;       /* TSFCDE_METHOD_*; the first TSFCDE_METHOD_GSF
+                             level's iters and restarts include those of the
+                             two solves (3.4)                                */
+    int32_t pad;
 } tsfcde_stats;
 
 typedef struct tsfcde_plan_s *tsfcde_plan_t;
@@ -282,6 +339,7 @@ int tsfcde_profile_issued(tsfcde_plan_t plan, int32_t kernel_class, int64_t *iss
 /* Release the plan (host state only; the caller frees the workspace). */
 int tsfcde_destroy(tsfcde_plan_t plan);
 
+
 /* ---- batched form ----------------------------------------------------
  * Many independent instances of (1.1) (any n, alpha, beta, coefficients,
  * same M) advanced level by level together.  Every level runs as grouped
@@ -321,6 +379,21 @@ int tsfcde_batch_set_level(tsfcde_batch_t batch, int64_t level);
 int tsfcde_batch_step(tsfcde_batch_t batch, const double *const *d_f, tsfcde_stats *stats);
 
 int tsfcde_batch_destroy(tsfcde_batch_t batch);
+
+/* Autotuned launch geometry.  Instances with the same embedding length L form
+ * a group that shares every launch.  Unless probs[0].flags has
+ * TSFCDE_FLAG_NO_TUNE, tsfcde_plan_batch times each group's middle pass (the
+ * row FFTs of the products and preconditioner solves, Sec. 3.2) at 4 and at 8
+ * values per lane on the group's own buffers and keeps the faster; choices
+ * are cached for the process by (row length, rows, instances) and, when the
+ * environment variable TSFCDE_TUNE_CACHE names a file, in that file, which a
+ * later process reads before tuning.  Different values per lane change the
+ * FFT's rounding, not its result beyond it.
+ * tsfcde_batch_group_count: number of groups (or TSFCDE_EINVAL).
+ * tsfcde_batch_group_info: group g's L, member count and chosen values per
+ * lane (each output nullable). */
+int tsfcde_batch_group_count(tsfcde_batch_t batch);
+int tsfcde_batch_group_info(tsfcde_batch_t batch, int32_t g, int64_t *L, int32_t *members, int32_t *values_per_lane);
 
 /* ---- learned warm start ----------------------------------------------
  * A four-layer 1-D convolutional network (7 -> 32 -> 32 -> 32 -> 1 channels,

@@ -24,6 +24,9 @@ What is computed, and where it is defined:
   the eigenvalues of circulants  -- (3.7), Lemma 8, Sec. 3.2.
 * Row-by-row evaluation of (A u)_i and g_i by direct O(n) sums, for checks at
   sizes where no dense matrix fits.
+* Constant coefficients: Algorithm 3, with A^-1 applied by the
+  Gohberg-Semencul formula of Sec. 3.1 (Algorithm 1) from the two solves
+  (3.4), all with dense matrices.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against closed forms,
 library special cases, the numbers printed in the paper's tables, and an
@@ -54,7 +57,7 @@ __all__ = [
     "strang_column", "circulant", "preconditioner_matrix", "circulant_eigenvalues",
     "embedding_column", "apply_A_rows", "apply_P_rows", "rhs_rows", "caputo_l21s",
     "embedding_eigenvalues", "embedding_product", "strang_eigenvalues", "strang_solve", "rhs_fft",
-    "level_solve_pcgs",
+    "level_solve_pcgs", "level_solve_pbicgstab", "tchan_column", "coefficients_constant", "gsf_generators", "gsf_matrices", "gsf_apply", "march_gsf",
 ]
 
 
@@ -311,6 +314,17 @@ def strang_column(lag_value, n: int) -> np.ndarray:
     return c
 
 
+def tchan_column(lag_value, n: int) -> np.ndarray:
+    """First column of T. Chan's optimal circulant of a Toeplitz matrix whose
+    entry at lag m = i - k is lag_value(m): c_k = ((n - k) t_k + k t_{k-n}) / n
+    (T. Chan, SIAM J. Sci. Stat. Comput. 9 (1988); the circulant nearest to
+    the Toeplitz matrix in the Frobenius norm)."""
+    c = np.zeros(n)
+    for k in range(n):
+        c[k] = ((n - k) * lag_value(k) + (k * lag_value(k - n) if k > 0 else 0.0)) / n
+    return c
+
+
 def circulant(col: np.ndarray) -> np.ndarray:
     """Dense circulant C[i, k] = col[(i - k) mod n]."""
     n = len(col)
@@ -331,13 +345,16 @@ def _Q_lag(m):
     return -1.0 if m == 1 else (1.0 if m == -1 else 0.0)
 
 
-def preconditioner_matrix(prob, j: int) -> np.ndarray:
+def preconditioner_matrix(prob, j: int, kind: str = "strang") -> np.ndarray:
     """P^(j+sigma) = eta_j I - sigma (gamma/(2h) s(Q) + D_+/h^beta s(W)
-    + D_-/h^beta s(W)^T)  (3.7), as a dense matrix."""
+    + D_-/h^beta s(W)^T)  (3.7), as a dense matrix; kind "tchan" puts T.
+    Chan's circulant c(.) in place of Strang's s(.) (c(W^T) = c(W)^T
+    exactly)."""
     e, gam, dp, dm = level_scalars(prob, j)
     n, h, beta = prob.n, mesh_h(prob), prob.beta
-    sQ = circulant(strang_column(_Q_lag, n))
-    sW = circulant(strang_column(_W_lag(beta, n), n))
+    col = {"strang": strang_column, "tchan": tchan_column}[kind]
+    sQ = circulant(col(_Q_lag, n))
+    sW = circulant(col(_W_lag(beta, n), n))
     return e * np.eye(n) - sigma_of(prob.alpha) * (gam / (2.0 * h) * sQ + dp / h ** beta * sW
                                          + dm / h ** beta * sW.T)
 
@@ -453,13 +470,15 @@ def embedding_product(prob, j: int, x: np.ndarray, which: str = "A", lam=None) -
     return e * x - sigma * Lx if which == "A" else e * x + (1.0 - sigma) * Lx
 
 
-def strang_eigenvalues(prob, j: int) -> np.ndarray:
+def strang_eigenvalues(prob, j: int, kind: str = "strang") -> np.ndarray:
     """Eigenvalues of the Strang preconditioner (3.7): eta_j - sigma (gamma/(2h)
-    lam(s(Q)) + D+/h^beta lam(s(W)) + D-/h^beta conj lam(s(W)))."""
+    lam(s(Q)) + D+/h^beta lam(s(W)) + D-/h^beta conj lam(s(W))); kind
+    "tchan" for T. Chan's circulants instead."""
     e, gam, dp, dm = level_scalars(prob, j)
     n, h, beta, sigma = prob.n, mesh_h(prob), prob.beta, sigma_of(prob.alpha)
-    lq = circulant_eigenvalues(strang_column(_Q_lag, n))
-    lw = circulant_eigenvalues(strang_column(_W_lag(beta, n), n))
+    col = {"strang": strang_column, "tchan": tchan_column}[kind]
+    lq = circulant_eigenvalues(col(_Q_lag, n))
+    lw = circulant_eigenvalues(col(_W_lag(beta, n), n))
     return e - sigma * (gam / (2.0 * h) * lq + dp / h ** beta * lw + dm / h ** beta * np.conj(lw))
 
 
@@ -483,12 +502,13 @@ def rhs_fft(prob, U: np.ndarray, j: int, f_j: np.ndarray, lam=None) -> np.ndarra
     return g - l21s_kappa(prob.alpha, time_step(prob)) * acc
 
 
-def level_solve_pcgs(prob, U: np.ndarray, j: int, f_j: np.ndarray, rtol: float = 1e-10, maxit: int = 500):
+def level_solve_pcgs(prob, U: np.ndarray, j: int, f_j: np.ndarray, rtol: float = 1e-10, maxit: int = 500,
+                     kind: str = "strang"):
     """u^{j+1} by preconditioned CGS on A^(j+sigma) u = g (3.3) from x0 = 0,
     stopped when the recursive residual falls to rtol |g| (Sec. 4).  Returns
     (u, iterations)."""
     lam_e = embedding_eigenvalues(prob)
-    lam_p = strang_eigenvalues(prob, j)
+    lam_p = strang_eigenvalues(prob, j, kind)
     g = rhs_fft(prob, U, j, f_j, lam_e)
     A = lambda v: embedding_product(prob, j, v, "A", lam_e)  # noqa: E731
     Pinv = lambda v: strang_solve(prob, j, v, lam_p)  # noqa: E731
@@ -519,3 +539,119 @@ def level_solve_pcgs(prob, U: np.ndarray, j: int, f_j: np.ndarray, rtol: float =
         rho_old = rho
     return x, maxit
 
+
+
+# ---------------------------------------------------------------------------
+# Constant coefficients: Algorithm 3 with the Gohberg-Semencul formula of
+# Sec. 3.1 ((3.4), the formula after it, and Algorithm 1).  With gamma, d_+-
+# constant, A^(j+sigma) = A for every j >= 1 (eta_j is the same for j >= 1),
+# so A^-1 is reconstructed from two solves, A x = e_1 and A y = e_n.
+# ---------------------------------------------------------------------------
+
+def level_solve_pbicgstab(prob, U: np.ndarray, j: int, f_j: np.ndarray, rtol: float = 1e-10, maxit: int = 500,
+                          kind: str = "strang"):
+    """u^{j+1} by right-preconditioned BiCGSTAB (van der Vorst 1992, in the
+    form of Barrett et al., Templates 1994) on A^(j+sigma) u = g from x0 = 0,
+    with the circulant preconditioner of the given kind, stopped when the
+    residual falls to rtol |g|.  Returns (u, iterations)."""
+    lam_e = embedding_eigenvalues(prob)
+    lam_p = strang_eigenvalues(prob, j, kind)
+    g = rhs_fft(prob, U, j, f_j, lam_e)
+    A = lambda v: embedding_product(prob, j, v, "A", lam_e)  # noqa: E731
+    Pinv = lambda v: strang_solve(prob, j, v, lam_p)  # noqa: E731
+    x = np.zeros(prob.n)
+    r = g.copy()
+    rt = r.copy()
+    gnorm = np.linalg.norm(g)
+    rho_old = alpha = omega = 1.0
+    p = v = np.zeros(prob.n)
+    for it in range(1, maxit + 1):
+        rho = float(rt @ r)
+        if rho == 0.0:
+            return x, it
+        if it == 1:
+            p = r.copy()
+        else:
+            beta = (rho / rho_old) * (alpha / omega)
+            p = r + beta * (p - omega * v)
+        phat = Pinv(p)
+        v = A(phat)
+        alpha = rho / float(rt @ v)
+        s = r - alpha * v
+        shat = Pinv(s)
+        t = A(shat)
+        tt = float(t @ t)
+        omega = float(t @ s) / tt if tt > 0 else 0.0
+        x = x + alpha * phat + omega * shat
+        r = s - omega * t
+        if np.linalg.norm(r) <= rtol * gnorm:
+            return x, it
+        if omega == 0.0:
+            return x, it
+        rho_old = rho
+    return x, maxit
+
+
+def coefficients_constant(prob) -> bool:
+    """gamma, d_+- take the same values at every sampling instant."""
+    vals = {(prob.gamma(t_sigma(prob, j)), prob.dplus(t_sigma(prob, j)), prob.dminus(t_sigma(prob, j)))
+            for j in range(prob.M)}
+    return len(vals) == 1
+
+
+def gsf_generators(prob):
+    """(x, y) of (3.4): A x = e_1 and A y = e_n for the level matrix of
+    levels j >= 1, by Gaussian elimination."""
+    A = level_A(prob, 1 if prob.M > 1 else 0)
+    n = prob.n
+    e1 = np.zeros(n)
+    e1[0] = 1.0
+    en = np.zeros(n)
+    en[-1] = 1.0
+    return np.linalg.solve(A, e1), np.linalg.solve(A, en)
+
+
+def gsf_matrices(x: np.ndarray, y: np.ndarray):
+    """The four triangular Toeplitz factors of the Gohberg-Semencul formula,
+    as printed after (3.4):
+      L_p  lower, first column (xi_0, ..., xi_{n-1});
+      R_p  upper, first row (eta_{n-1}, ..., eta_0);
+      L0_p strictly lower, first column (0, eta_0, ..., eta_{n-2});
+      R0_p strictly upper, first row (0, xi_{n-1}, ..., xi_1)."""
+    n = len(x)
+    d = np.arange(n)[:, None] - np.arange(n)[None, :]  # i - k
+    Lp = np.where(d >= 0, x[np.clip(d, 0, n - 1)], 0.0)
+    Rp = np.where(d <= 0, y[np.clip(n - 1 + d, 0, n - 1)], 0.0)
+    L0 = np.where(d >= 1, y[np.clip(d - 1, 0, n - 1)], 0.0)
+    R0 = np.where(d <= -1, x[np.clip(n + d, 0, n - 1)], 0.0)
+    return Lp, Rp, L0, R0
+
+
+def gsf_apply(x: np.ndarray, y: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """z = A^-1 v by Algorithm 1: z1 = R0_p v, z2 = R_p v, z3 = L0_p z1,
+    z4 = L_p z2, z = (z4 - z3) / xi_0 (requires xi_0 != 0)."""
+    Lp, Rp, L0, R0 = gsf_matrices(x, y)
+    z1 = R0 @ v
+    z2 = Rp @ v
+    z3 = L0 @ z1
+    z4 = Lp @ z2
+    return (z4 - z3) / x[0]
+
+
+def march_gsf(prob, f_levels: Optional[Iterable[np.ndarray]] = None) -> np.ndarray:
+    """Algorithm 3: level 0 solves A^(sigma) u^1 = g^(1) by Gaussian
+    elimination; every later level forms g^(j+1) (with the history entering
+    with the minus sign of (3.1)) and applies A^-1 by Algorithm 1."""
+    if not coefficients_constant(prob):
+        raise ValueError("Algorithm 3 needs constant gamma, d_+-")
+    U = np.zeros((prob.M + 1, prob.n))
+    U[0] = initial_level(prob)
+    flist = list(f_levels) if f_levels is not None else None
+    x, y = gsf_generators(prob)
+    for j in range(prob.M):
+        f_j = flist[j] if flist is not None else source_level(prob, j)
+        if j == 0:
+            U[1] = level_solve(prob, U, 0, f_j)
+        else:
+            U[j + 1] = gsf_apply(x, y, rhs(prob, U, j, f_j))
+    return U

@@ -10,7 +10,9 @@ from ._native import (  # noqa: F401
     TSFCDE_ENONFINITE, TSFCDE_EDONE, TSFCDE_EUNSUPPORTED, TSFCDE_EACCEPT, TSFCDE_FP64, TSFCDE_FP32_REFINED,
     TSFCDE_FP32_REFINED_FELL_BACK, TSFCDE_WS_ZERO, TSFCDE_WS_PREV, TSFCDE_WS_EXTRAP, TSFCDE_WS_NET,
     TSFCDE_FLAG_TRUE_RESIDUAL, TSFCDE_FLAG_VERIFY, TSFCDE_FLAG_FORCE_FP32, TSFCDE_FLAG_NO_FOLD,
-    TSFCDE_FLAG_STRICT_RESIDUAL, TSFCDE_OP_A,
+    TSFCDE_FLAG_STRICT_RESIDUAL, TSFCDE_FLAG_CONSTANT_GSF, TSFCDE_FLAG_GRAPHS, TSFCDE_FLAG_NO_TUNE, TSFCDE_METHOD_PCGS, TSFCDE_METHOD_GSF,
+    TSFCDE_METHOD_PBICGSTAB, TSFCDE_KRYLOV_CGS, TSFCDE_KRYLOV_BICGSTAB, TSFCDE_PREC_STRANG, TSFCDE_PREC_TCHAN,
+    TSFCDE_OP_A,
     TSFCDE_OP_B, TSFCDE_OP_PINV, TSFCDE_SPEC_EMBED, TSFCDE_SPEC_STRANG, TsfcdeError, lib, header_symbols,
 )
 from .solver import BatchSolver, TimeLevelSolver  # noqa: F401

@@ -37,6 +37,12 @@ TSFCDE_FLAG_VERIFY = 2
 TSFCDE_FLAG_FORCE_FP32 = 4
 TSFCDE_FLAG_NO_FOLD = 8
 TSFCDE_FLAG_STRICT_RESIDUAL = 16
+TSFCDE_FLAG_CONSTANT_GSF = 32
+TSFCDE_FLAG_GRAPHS = 64
+TSFCDE_FLAG_NO_TUNE = 128
+TSFCDE_METHOD_PCGS, TSFCDE_METHOD_GSF, TSFCDE_METHOD_PBICGSTAB = 0, 1, 2
+TSFCDE_KRYLOV_CGS, TSFCDE_KRYLOV_BICGSTAB = 0, 1
+TSFCDE_PREC_STRANG, TSFCDE_PREC_TCHAN = 0, 1
 TSFCDE_OP_A, TSFCDE_OP_B, TSFCDE_OP_PINV = 0, 1, 2
 TSFCDE_SPEC_EMBED, TSFCDE_SPEC_STRANG = 0, 1
 
@@ -49,7 +55,7 @@ class tsfcde_problem(ctypes.Structure):
         ("gamma_at", POINTER(c_double)), ("dplus_at", POINTER(c_double)), ("dminus_at", POINTER(c_double)),
         ("phi", IC_FN), ("phi_user", c_void_p),
         ("rtol", c_double), ("maxit", c_int32), ("precision", c_int32), ("warm_start", c_int32),
-        ("flags", c_int32), ("f", SRC_FN), ("f_user", c_void_p),
+        ("flags", c_int32), ("f", SRC_FN), ("f_user", c_void_p), ("krylov", c_int32), ("preconditioner", c_int32),
     ]
 
 
@@ -57,7 +63,7 @@ class tsfcde_stats(ctypes.Structure):
     _fields_ = [
         ("iters", c_int32), ("outer_iters", c_int32), ("restarts", c_int32), ("status", c_int32),
         ("relres", c_double), ("relres_true", c_double), ("backward_err", c_double), ("seconds", c_double),
-        ("precision_used", c_int32), ("guess", c_int32),
+        ("precision_used", c_int32), ("guess", c_int32), ("method", c_int32), ("pad", c_int32),
     ]
 
     def as_dict(self):
@@ -98,6 +104,8 @@ _SIGS = {
     "tsfcde_batch_set_level": (c_int32, [c_void_p, c_int64]),
     "tsfcde_batch_step": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(tsfcde_stats)]),
     "tsfcde_batch_destroy": (c_int32, [c_void_p]),
+    "tsfcde_batch_group_count": (c_int32, [c_void_p]),
+    "tsfcde_batch_group_info": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_int32), POINTER(c_int32)]),
     "tsfcde_strerror": (c_char_p, [c_int32]),
     "tsfcde_net_param_count": (c_int32, []),
     "tsfcde_net_workspace_bytes": (c_int32, [c_int64, c_int32, POINTER(c_size_t)]),

@@ -41,6 +41,7 @@ struct DevScalars {
     // a restart pass (cleared by the right-hand side); nchecks counts the
     // acceptance checks of the level, prestat keeps the status CGS stopped with
     int checked, nchecks, prestat;
+    double omega;  // BiCGSTAB's omega of the last iteration
 };
 
 enum : int { ST_OK = 0, ST_BREAKDOWN = 1, ST_NONFINITE = 2 };
@@ -419,6 +420,201 @@ template <class S> struct OutRealT {  // x[2m], x[2m+1] for 2m < nr
     double *partials;
 };
 using OutReal = OutRealT<double>;
+
+// ---------------------------------------------------------------------------
+// BiCGSTAB (van der Vorst 1992; the right-preconditioned form of Barrett et
+// al., Templates 1994), on the same passes as CGS: per iteration
+//   p = r + beta (p - omega v)  (p = r when fresh), beta = (rho/rho_prev)(alpha/omega)
+//   phat = P^-1 p ; v = A phat ; alpha = rho / (rt . v)
+//   s = r - alpha v ; shat = P^-1 s ; t = A shat ; omega = (t . s) / (t . t)
+//   x += alpha phat + omega shat ; r = s - omega t ; rho' = rt . r
+// The scalars stay on the device: each reducing pass's finishing step writes
+// them, the next pass reads them.
+// ---------------------------------------------------------------------------
+struct InBiP {  // p (written), transformed for the preconditioner solve
+    const double *r, *v;
+    double *p;
+    int64_t nr, C;
+    double beta = 0.0, omega = 0.0;
+    bool first = true;
+    __device__ void prep(const DevScalars *sc) {
+        first = sc->fresh != 0;
+        omega = sc->omega;
+        beta = first ? 0.0 : (sc->rho / sc->rho_prev) * (sc->alpha / sc->omega);
+    }
+    static constexpr int NL = 3;
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
+        const int64_t i = 2 * (row * C + col);
+        if (i >= nr) return;
+        raw[0] = ld2(r, i, nr);
+        if (!first) {
+            raw[1] = ld2(p, i, nr);
+            raw[2] = ld2(v, i, nr);
+        }
+    }
+    __device__ __forceinline__ double2 finish(int row, int64_t col, const double2 *raw) const {
+        const int64_t i = 2 * (row * C + col);
+        if (i >= nr) return make_double2(0.0, 0.0);
+        double2 pv = raw[0];
+        if (!first) {
+            const double2 po = raw[1], vv = raw[2];
+            pv.x = fma(beta, fma(-omega, vv.x, po.x), pv.x);
+            pv.y = fma(beta, fma(-omega, vv.y, po.y), pv.y);
+        }
+        st2(p, i, nr, pv);
+        return pv;
+    }
+};
+
+struct OutBiV {  // v = A phat (written); alpha = rho / (rt . v)
+    double *v;
+    const double *rt;
+    int64_t nr, C;
+    static constexpr int NACC = 1, NPRE = 1;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *pre) const {
+        const int64_t i = 2 * (row * C + col);
+        if (i < nr) pre[0] = ld2(rt, i, nr);
+    }
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc, const double2 *pre) const {
+        const int64_t i = 2 * (row * C + col);
+        if (i < nr) {
+            if (i + 1 >= nr) val.y = 0.0;
+            st2(v, i, nr, val);
+            acc[0] = fma(pre[0].x, val.x, fma(pre[0].y, val.y, acc[0]));
+        }
+    }
+    __device__ void final(const double *tot, DevScalars *sc) const {
+        sc->rtv = tot[0];
+        sc->alpha = sc->rho / tot[0];
+        if (tot[0] == 0.0) {
+            sc->status = ST_BREAKDOWN;
+            sc->done = 1;
+        } else if (!finite(sc->alpha)) {
+            sc->status = ST_NONFINITE;
+            sc->done = 1;
+        }
+    }
+    double *partials;
+};
+
+struct InBiS {  // s = r - alpha v (written), transformed for the preconditioner solve
+    const double *r, *v;
+    double *s;
+    int64_t nr, C;
+    double alpha = 0.0;
+    __device__ void prep(const DevScalars *sc) { alpha = sc->alpha; }
+    static constexpr int NL = 2;
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *raw) const {
+        const int64_t i = 2 * (row * C + col);
+        if (i >= nr) return;
+        raw[0] = ld2(r, i, nr);
+        raw[1] = ld2(v, i, nr);
+    }
+    __device__ __forceinline__ double2 finish(int row, int64_t col, const double2 *raw) const {
+        const int64_t i = 2 * (row * C + col);
+        if (i >= nr) return make_double2(0.0, 0.0);
+        const double2 sv = make_double2(fma(-alpha, raw[1].x, raw[0].x), fma(-alpha, raw[1].y, raw[0].y));
+        st2(s, i, nr, sv);
+        return sv;
+    }
+};
+
+struct OutBiT {  // t = A shat (written); omega = (t . s) / (t . t)
+    double *t;
+    const double *s;
+    int64_t nr, C;
+    static constexpr int NACC = 2, NPRE = 1;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *pre) const {
+        const int64_t i = 2 * (row * C + col);
+        if (i < nr) pre[0] = ld2(s, i, nr);
+    }
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *acc, const double2 *pre) const {
+        const int64_t i = 2 * (row * C + col);
+        if (i < nr) {
+            if (i + 1 >= nr) val.y = 0.0;
+            st2(t, i, nr, val);
+            acc[0] = fma(val.x, pre[0].x, fma(val.y, pre[0].y, acc[0]));
+            acc[1] = fma(val.x, val.x, fma(val.y, val.y, acc[1]));
+        }
+    }
+    __device__ void final(const double *tot, DevScalars *sc) const {
+        // t = 0 means s = 0: x + alpha phat is the answer, and omega = 0
+        // leaves r = s for the update's convergence test
+        sc->omega = tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
+        if (!finite(tot[0]) || !finite(tot[1])) {
+            sc->status = ST_NONFINITE;
+            sc->done = 1;
+        }
+    }
+    double *partials;
+};
+
+// x += alpha phat + omega shat ; r = s - omega t ; partial sums of |r|^2 and
+// rt . r per workgroup (256 threads).
+__global__ void __launch_bounds__(256) k_bicg_update(double *__restrict__ x, double *__restrict__ r,
+                                                     const double *__restrict__ rt, const double *__restrict__ phat,
+                                                     const double *__restrict__ shat, const double *__restrict__ s,
+                                                     const double *__restrict__ t, int64_t n, const DevScalars *sc,
+                                                     double *partials, int pred) {
+    if (skip(pred, sc)) return;
+    const double alpha = sc->alpha, omega = sc->omega;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] = fma(omega, shat[i], fma(alpha, phat[i], x[i]));
+        const double ri = fma(-omega, t[i], s[i]);
+        r[i] = ri;
+        acc[0] = fma(ri, ri, acc[0]);
+        acc[1] = fma(rt[i], ri, acc[1]);
+    }
+    block_partial<2>(acc, partials, blockIdx.x);
+}
+
+// Finishing step of k_bicg_update: rho_prev = rho, rho = rt . r, |r|^2, the
+// iteration count and the stopping, breakdown and non-finite tests.
+__global__ void __launch_bounds__(256) k_bicg_final(const double *partials, int nparts, DevScalars *sc, int pred) {
+    if (skip(pred, sc)) return;
+    double tot[2];
+    reduce_partials<2>(partials, nparts, tot);
+    if (threadIdx.x == 0) {
+        sc->rnorm2 = tot[0];
+        sc->rho_prev = sc->rho;
+        sc->rho = tot[1];
+        sc->iter += 1;
+        sc->fresh = 0;
+        if (!finite(tot[0]) || !finite(tot[1])) {
+            sc->status = ST_NONFINITE;
+            sc->done = 1;
+        } else if (tot[0] <= sc->tol2) {
+            sc->done = 1;
+        } else if (tot[1] == 0.0 || sc->omega == 0.0) {
+            sc->status = ST_BREAKDOWN;
+            sc->done = 1;
+        }
+    }
+}
+
+// Last step of the Gohberg-Semencul product (Algorithm 1): the pass that
+// forms z3 = L0_p z1 stores x = (z4 - z3) / xi_0.
+struct OutGsfCombine {
+    const double *z4;
+    double *x;
+    int64_t nr, C;
+    double inv_xi0;
+    static constexpr int NACC = 0, NPRE = 1;
+    __device__ void prep(const DevScalars *) {}
+    __device__ __forceinline__ void fetch(int row, int64_t col, double2 *pre) const {
+        const int64_t i = 2 * (row * C + col);
+        if (i < nr) pre[0] = ld2(z4, i, nr);
+    }
+    __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *, const double2 *pre) const {
+        const int64_t i = 2 * (row * C + col);
+        if (i < nr) st2(x, i, nr, make_double2((pre[0].x - val.x) * inv_xi0, (pre[0].y - val.y) * inv_xi0));
+    }
+    __device__ void final(const double *, DevScalars *) const {}
+    double *partials;
+};
 
 // vhat = A phat; accumulates rt . vhat; the last workgroup sets alpha = rho / (rt . vhat).
 template <class S> struct OutCgsDotT {
@@ -1744,12 +1940,80 @@ __global__ void k_embed_column(const double *w, int64_t n, int64_t L, double *c)
     }
 }
 
+// First column of T. Chan's optimal circulant of W_beta (the circulant nearest
+// to W_beta in the Frobenius norm): c_k = ((n - k) t_k + k t_{k-n}) / n with
+// t_lag = omega_{lag+1} for lag >= -1, else 0; t_{k-n} is nonzero only at
+// k = n - 1 (lag -1, omega_0).
+__global__ void k_tchan_column(const double *w, int64_t n, double *c) {
+    const double inv = 1.0 / (double)n;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        double v = (double)(n - k) * w[k + 1];
+        if (k == n - 1) v = fma((double)k, w[0], v);
+        c[k] = v * inv;
+    }
+}
+
 // First column of the Strang circulant s(W_beta): lag k for 0 <= k <= n/2,
 // lag k - n otherwise; W has lags -1..n-1 with entry omega_{lag+1}.
 __global__ void k_strang_column(const double *w, int64_t n, double *c) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t lag = k <= n / 2 ? k : k - n;
         c[k] = lag >= -1 ? w[lag + 1] : 0.0;
+    }
+}
+
+// Columns of the length-L circulant embeddings of the four triangular
+// Toeplitz factors of the Gohberg-Semencul formula (Sec. 3.1), from
+// x = A^-1 e_1 and y = A^-1 e_n; lag m = i - k >= 0 sits at index m, lag
+// m < 0 at L + m (L >= 2n keeps the two ranges apart):
+//   which 0: L_p,  lags 0..n-1,      entry x_m;
+//   which 1: R_p,  lags -(n-1)..0,   entry y_{n-1+m};
+//   which 2: L0_p, lags 1..n-1,      entry y_{m-1};
+//   which 3: R0_p, lags -(n-1)..-1,  entry x_{n+m}.
+__global__ void k_gsf_column(const double *x, const double *y, int64_t n, int64_t L, int which, double *c) {
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < L; m += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (m < n) {
+            if (which == 0) v = x[m];
+            else if (which == 1 && m == 0) v = y[n - 1];
+            else if (which == 2 && m >= 1) v = y[m - 1];
+        } else if (L - m < n) {
+            const int64_t lag = m - L;  // -(n-1) .. -1
+            if (which == 1) v = y[n - 1 + lag];
+            else if (which == 3) v = x[n + lag];
+        }
+        c[m] = v;
+    }
+}
+
+// g = e_pos, x = 0, r = rt = e_pos (rows of ld values, pads zero), and the
+// device scalars of a fresh CGS solve of A x = g to |r| <= tol |g| (|g| = 1),
+// as the right-hand side pass leaves them.
+__global__ void k_unit_rhs(double *g, double *x, double *r, double *rt, int64_t ld, int64_t pos, double tol,
+                           DevScalars *sc) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ld; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = i == pos ? 1.0 : 0.0;
+        g[i] = v;
+        x[i] = 0.0;
+        r[i] = v;
+        rt[i] = v;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->gnorm2 = 1.0;
+        sc->rnorm2 = 1.0;
+        sc->rho = 1.0;
+        sc->rho_prev = 1.0;
+        sc->beta = 0.0;
+        sc->alpha = 0.0;
+        sc->tol2 = tol * tol;
+        sc->iter = 0;
+        sc->fresh = 1;
+        sc->aux0 = 1.0;
+        sc->r0sq = 1.0;
+        sc->status = ST_OK;
+        sc->checked = 0;
+        sc->nchecks = 0;
+        sc->done = 0;
     }
 }
 

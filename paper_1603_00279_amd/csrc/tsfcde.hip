@@ -15,7 +15,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -92,7 +95,7 @@ bool rt_setup(RT &A, RT &P, RT &B, int64_t n, bool force_general = false) {
 struct Layout {
     size_t off_U, off_vec, off_v32, off_tmp, off_w, off_g0, off_cbase, off_buf, off_bufP, off_specA, off_specP, off_tw, off_tw2A,
         off_tw2P, off_part, off_sc, off_bufB, off_Bhat, off_chirp, off_Ls, off_wv, off_Wt, off_specPj, off_tw2B,
-        off_buf32, off_bufP32, off_specA32, off_specP32, off_specPj32, total;
+        off_buf32, off_bufP32, off_specA32, off_specP32, off_specPj32, off_gsf, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -103,7 +106,8 @@ constexpr int NV32 = 9;   // FP32 inner solve: r rt u p q phat vhat uhat d
 // internal row stride: n rounded up to even, so every row starts 16-byte aligned
 int64_t ld_of(int64_t n) { return n + (n & 1); }
 
-Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P, const RT &B, bool p2, bool fp32) {
+Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P, const RT &B, bool p2, bool fp32,
+                  bool gsf = false) {
     const int64_t ld = ld_of(n);
     Layout l{};
     size_t o = 0;
@@ -144,6 +148,9 @@ Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P, const RT &B, b
     l.off_specA32 = take(sizeof(float2) * f * (size_t)A.N);
     l.off_specP32 = take(sizeof(float2) * f * (size_t)(p2 ? P.N : 0));
     l.off_specPj32 = take(sizeof(float2) * f * (size_t)(p2 ? 0 : A.N));
+    // Gohberg-Semencul path: x = A^-1 e_1, y = A^-1 e_n and the spectra of
+    // the four triangular factors
+    l.off_gsf = take(gsf ? 2 * sizeof(double) * (size_t)ld + 4 * al(sizeof(double2) * (size_t)A.N) : 0);
     l.total = o;
     return l;
 }
@@ -163,6 +170,9 @@ int validate(const tsfcde_problem *p) {
         return TSFCDE_EINVAL;
     if (!std::isfinite(p->rtol)) return TSFCDE_EINVAL;
     if (p->n < 4 || p->n > (is_pow2(p->n) ? NMAX : NMAX / 2)) return TSFCDE_EUNSUPPORTED;
+    if (p->krylov != TSFCDE_KRYLOV_CGS && p->krylov != TSFCDE_KRYLOV_BICGSTAB) return TSFCDE_EINVAL;
+    if (p->preconditioner != TSFCDE_PREC_STRANG && p->preconditioner != TSFCDE_PREC_TCHAN) return TSFCDE_EINVAL;
+    if ((p->flags & TSFCDE_FLAG_CONSTANT_GSF) && p->precision != TSFCDE_FP64) return TSFCDE_EUNSUPPORTED;
     return TSFCDE_OK;
 }
 
@@ -215,6 +225,19 @@ struct tsfcde_plan_s {
     tsfcde_src_fn fcb = nullptr;  // f(x, t) for levels stepped without a device source
     void *fuser = nullptr;
     double *h_f = nullptr;        // pinned staging of those f values (n doubles)
+    // a plan made for one level only (tsfcde_apply_noalloc): that level's
+    // scalars stand in for the per-level tables
+    bool one_level = false;
+    double one_eta = 0.0, one_gam = 0.0, one_dp = 0.0, one_dm = 0.0;
+    // constant coefficients (TSFCDE_FLAG_CONSTANT_GSF): levels j >= 1 apply
+    // A^-1 by the Gohberg-Semencul formula from x = A^-1 e_1, y = A^-1 e_n
+    int krylov = TSFCDE_KRYLOV_CGS;  // Krylov method of the FP64 solves
+    int prec = TSFCDE_PREC_STRANG;   // circulant preconditioner
+    double qfac = 1.0;  // eigenvalues of the preconditioner's circulant of Q over 2i sin(2 pi k/n)
+    bool gsf = false, gsf_ready = false;
+    double *gx = nullptr, *gy = nullptr;
+    double2 *gspec[4] = {nullptr, nullptr, nullptr, nullptr};  // L_p, R_p, L0_p, R0_p
+    double gsf_inv_xi0 = 0.0;
     ProfRec prof[NPROF];
     std::vector<hipEvent_t> event_pool;
 };
@@ -680,11 +703,15 @@ hipError_t launch_row(tsfcde_plan_s *pl, double2 *Y, const double2 *spec, double
 
 // s = -sigma for A and P, (1 - sigma) for B.  Product scale 1/(4N); solve scale 4N.
 SymParams symbol(const tsfcde_plan_s *pl, int64_t j, double s, const RT &rt, bool solve) {
+    const bool o = pl->one_level;
+    const double eta = o ? pl->one_eta : pl->eta[j], gam = o ? pl->one_gam : pl->gam[j];
+    const double dp = o ? pl->one_dp : pl->dp[j], dm = o ? pl->one_dm : pl->dm[j];
     SymParams sp;
-    sp.s0 = pl->eta[j];
-    sp.cre = s * (pl->dp[j] + pl->dm[j]) * pl->hb;
-    sp.cim = s * (pl->dp[j] - pl->dm[j]) * pl->hb;
-    sp.cq = s * pl->gam[j] / pl->h;
+    sp.s0 = eta;
+    sp.cre = s * (dp + dm) * pl->hb;
+    sp.cim = s * (dp - dm) * pl->hb;
+    sp.cq = s * gam / pl->h;
+    if (solve) sp.cq *= pl->qfac;
     sp.scale = solve ? 4.0 * (double)rt.N : 1.0 / (4.0 * (double)rt.N);
     return sp;
 }
@@ -749,12 +776,22 @@ hipError_t bluestein(tsfcde_plan_s *pl, const double2 *zc, const double *zr, dou
     return launch_col<1>(pl, B, InSpec{pl->bufB, B.tw, B.C}, oc, 0);
 }
 
+// Symbol of level j's preconditioner for k_pc_column: that of A with the
+// circulant of Q in place of Q (the stored spectrum Ls is that of the
+// preconditioner's circulant of W_beta).
+SymParams precond_symbol(const tsfcde_plan_s *pl, int64_t j) {
+    SymParams sp = symbol(pl, j, -pl->sigma, pl->A, false);
+    sp.cq *= pl->qfac;
+    return sp;
+}
+
 // Inverse Strang circulant of level j (general n): p = IDFT_n(1/lambda_P) and
 // the DFT of its length-L embedding, in the product transform's native order.
 hipError_t precond_level(tsfcde_plan_s *pl, int64_t j) {
     if (pl->p2 || pl->pj_level == j) return hipSuccess;
+    if (pl->gsf && j >= 1 && pl->pj_level >= 1) return hipSuccess;  // constant coefficients: one P for j >= 1
     const int64_t n = pl->n;
-    const SymParams sp = symbol(pl, j, -pl->sigma, pl->A, false);
+    const SymParams sp = precond_symbol(pl, j);
     hipLaunchKernelGGL(k_pc_column, dim3(256), dim3(256), 0, pl->stream, pl->Ls, n, sp, pl->wv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -889,6 +926,41 @@ hipError_t cgs_iteration_general(tsfcde_plan_s *pl, int64_t j, const Bufs<S, CS>
     if ((e = run_op_on<0>(pl, pl->A, b.buf, b.specPj, sI, i3, o3, 1))) return e;
     OutCgsRT<S> o4 = with_red(OutCgsRT<S>{b.r, b.rt, n, C, 0.0}, pl, 1);
     return run_op_on<0>(pl, pl->A, b.buf, b.specA, sA, InCgsXT<S>{b.uhat, x, n, C, 0.0}, o4, 1, !fold);
+}
+
+// One BiCGSTAB iteration in FP64 (any n): two preconditioner solves, two
+// products with A, one update pass; the vectors p, v, s, t, phat, shat sit in
+// the plan's p, vhat, q, u, phat, uhat.
+hipError_t bicg_iteration(tsfcde_plan_s *pl, int64_t j, double *x) {
+    const int64_t n = pl->n;
+    const RT &A = pl->A;
+    const RT &R = pl->p2 ? pl->P : pl->A;  // geometry of the preconditioner solve
+    const SymParams sA = symbol(pl, j, -pl->sigma, A, false);
+    const SymParams sP = symbol(pl, j, -pl->sigma, pl->P, true);
+    auto psolve = [&](const auto &in, double *out) {
+        OutReal o{out, n, R.C};
+        o.partials = nullptr;
+        return pl->p2 ? run_op_on<1>(pl, pl->P, pl->bufP, (const double2 *)pl->specP, sP, in, o, 1)
+                      : run_op_on<0>(pl, pl->A, pl->buf, (const double2 *)pl->specPj, unit_symbol(pl->A), in, o, 1);
+    };
+    hipError_t e;
+    if ((e = psolve(InBiP{pl->r, pl->vhat, pl->p, n, R.C}, pl->phat)) != hipSuccess) return e;
+    OutBiV ov = with_red(OutBiV{pl->vhat, pl->rt, n, A.C}, pl, 0);
+    if ((e = run_op_on<0>(pl, A, pl->buf, (const double2 *)pl->specA, sA, InReal{pl->phat, n, A.C}, ov, 1)) !=
+        hipSuccess)
+        return e;
+    if ((e = psolve(InBiS{pl->r, pl->vhat, pl->q, n, R.C}, pl->uhat)) != hipSuccess) return e;
+    OutBiT ot = with_red(OutBiT{pl->u, pl->q, n, A.C}, pl, 1);
+    if ((e = run_op_on<0>(pl, A, pl->buf, (const double2 *)pl->specA, sA, InReal{pl->uhat, n, A.C}, ot, 1)) !=
+        hipSuccess)
+        return e;
+    const int grid = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    double *part = pl->part + (size_t)2 * PARTIAL_SLOTS;
+    hipLaunchKernelGGL(k_bicg_update, dim3(grid), dim3(256), 0, pl->stream, x, pl->r, (const double *)pl->rt,
+                       (const double *)pl->phat, (const double *)pl->uhat, (const double *)pl->q,
+                       (const double *)pl->u, n, (const DevScalars *)pl->sc, part, 1);
+    hipLaunchKernelGGL(k_bicg_final, dim3(1), dim3(256), 0, pl->stream, (const double *)part, grid, pl->sc, 1);
+    return hipGetLastError();
 }
 
 template <class S, class CS>
@@ -1088,7 +1160,13 @@ int fp64_cgs(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so) {
         // from x recovers from a breakdown and checks a converged level,
         // continuing CGS from x when the check fails
         const int todo = std::min(chunk, pl->maxit - iters_seen);
-        if (todo > 0) HIPCHK(cgs_chunk(pl, j, b64, x, todo));
+        if (todo > 0) {
+            if (pl->krylov == TSFCDE_KRYLOV_BICGSTAB) {
+                for (int k = 0; k < todo; ++k) HIPCHK(bicg_iteration(pl, j, x));
+            } else {
+                HIPCHK(cgs_chunk(pl, j, b64, x, todo));
+            }
+        }
         if ((rc = restart_launch(pl, j, x, bwtol, 3, true))) return rc;
         if ((rc = poll(pl))) return rc;
         const DevScalars &h = *pl->h_sc;
@@ -1252,6 +1330,81 @@ int ir_solve(tsfcde_plan_s *pl, int64_t j, double *x, SolveOut &so, int &outer, 
     return TSFCDE_OK;
 }
 
+// ---- constant coefficients: Algorithm 3 with the Gohberg-Semencul formula
+// (Sec. 3.1).  Every level j >= 1 has the same matrix A, whose inverse is
+// applied from x = A^-1 e_1 and y = A^-1 e_n (3.4), solved once by the FP64
+// PCGS, as four triangular Toeplitz products through the product transform
+// (Algorithm 1).
+
+// Tolerance of the two solves (3.4): tighter than the levels' own, since the
+// formula's products carry their error into every later level.
+constexpr double GSF_GEN_RTOL = 1e-13;
+
+// The solves (3.4) for the matrix of levels j >= 1 and the spectra of the
+// four factors.  Uses g, r, rt and the device scalars as scratch (before the
+// level's right-hand side).  so accumulates the solves' iterations.
+int gsf_prepare(tsfcde_plan_s *pl, SolveOut &so) {
+    const int64_t n = pl->n, j = 1;
+    HIPCHK(precond_level(pl, j));
+    const double tol = std::min(pl->rtol, GSF_GEN_RTOL);
+    double *outs[2] = {pl->gx, pl->gy};
+    const int64_t pos[2] = {0, n - 1};
+    for (int k = 0; k < 2; ++k) {
+        hipLaunchKernelGGL(k_unit_rhs, dim3(256), dim3(256), 0, pl->stream, pl->g, outs[k], pl->r, pl->rt, pl->ldn,
+                           pos[k], tol, pl->sc);
+        HIPCHK(hipGetLastError());
+        SolveOut one;
+        if (int rc = fp64_cgs(pl, j, outs[k], one)) return rc;
+        so.iters += one.iters;
+        so.restarts += one.restarts;
+        if (one.code != TSFCDE_OK) return one.code;
+    }
+    double xi0 = 0.0;
+    HIPCHK(hipMemcpyAsync(&xi0, pl->gx, sizeof(double), hipMemcpyDeviceToHost, pl->stream));
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    if (!(std::isfinite(xi0) && xi0 != 0.0)) return TSFCDE_EBREAKDOWN;  // the formula needs xi_0 != 0
+    pl->gsf_inv_xi0 = 1.0 / xi0;
+    for (int w = 0; w < 4; ++w) {
+        hipLaunchKernelGGL(k_gsf_column, dim3(512), dim3(256), 0, pl->stream, (const double *)pl->gx,
+                           (const double *)pl->gy, n, pl->A.L, w, pl->tmp);
+        HIPCHK(hipGetLastError());
+        HIPCHK(launch_col<-1>(pl, pl->A, InReal{pl->tmp, pl->A.L, pl->A.C}, out_spec(pl, pl->A), 0));
+        HIPCHK(launch_mid<2>(pl, pl->A, pl->buf, (const double2 *)nullptr, pl->gspec[w], SymParams{}, 0));
+    }
+    pl->gsf_ready = true;
+    return TSFCDE_OK;
+}
+
+// x = A^-1 g by Algorithm 1: z2 = R_p g, z1 = R0_p g, z4 = L_p z2, and the
+// pass that forms z3 = L0_p z1 stores x = (z4 - z3) / xi_0.
+int gsf_apply(tsfcde_plan_s *pl, double *x) {
+    const int64_t n = pl->n, C = pl->A.C;
+    const SymParams sI = unit_symbol(pl->A);
+    double *z1 = pl->phat, *z2 = pl->vhat, *z4 = pl->uhat;
+    OutReal o{z2, n, C};
+    o.partials = nullptr;
+    HIPCHK(run_op<0>(pl, pl->A, pl->gspec[1], sI, InReal{pl->g, n, C}, o, 0));
+    o.x = z1;
+    HIPCHK(run_op<0>(pl, pl->A, pl->gspec[3], sI, InReal{pl->g, n, C}, o, 0));
+    o.x = z4;
+    HIPCHK(run_op<0>(pl, pl->A, pl->gspec[0], sI, InReal{z2, n, C}, o, 0));
+    OutGsfCombine oc{z4, x, n, C, pl->gsf_inv_xi0};
+    oc.partials = nullptr;
+    HIPCHK(run_op<0>(pl, pl->A, pl->gspec[2], sI, InReal{z1, n, C}, oc, 0));
+    return TSFCDE_OK;
+}
+
+// eta_j = kappa c_0^(j): kappa a_0 at level 0, kappa (a_0 + b_1) after
+// (Lemma 1; the diagonal of A and B in (3.3)).
+double eta_level(double alpha, double sigma, double kappa, int64_t j) {
+    const double al = alpha, sg = sigma;
+    const double a0 = std::pow(sg, 1.0 - al);
+    if (j == 0) return kappa * a0;
+    const double b1 = (std::pow(1.0 + sg, 2.0 - al) - std::pow(sg, 2.0 - al)) / (2.0 - al) -
+                      0.5 * (std::pow(1.0 + sg, 1.0 - al) + std::pow(sg, 1.0 - al));
+    return kappa * (a0 + b1);
+}
+
 // t_{j+sigma} = (j + sigma) tau (Lemma 1)
 double level_time(const tsfcde_plan_s *pl, int64_t j) { return ((double)j + pl->sigma) * pl->tau; }
 
@@ -1284,12 +1437,20 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
         if (int rc = callback_source(pl, j, &d_f)) return rc;
     }
     double *x = pl->U + (size_t)(j + 1) * pl->ldn;
+    // Gohberg-Semencul levels (constant coefficients, j >= 1): the two solves
+    // (3.4) before the first such level's right-hand side
+    const bool gsf_level = pl->gsf && j >= 1;
+    SolveOut gprep;
+    if (gsf_level && !pl->gsf_ready) {
+        if (int rc = gsf_prepare(pl, gprep)) return rc;
+    }
     // initial guess: 0, u^j, or quadratic extrapolation (u^j below level 2)
     int warm = 0;
     if (pl->warm == TSFCDE_WS_PREV) warm = 1;
     if (pl->warm == TSFCDE_WS_EXTRAP) warm = j >= 2 ? 2 : (j >= 1 ? 1 : 0);
-    const bool use_net = pl->warm == TSFCDE_WS_NET && pl->net && j >= 2;
+    const bool use_net = pl->warm == TSFCDE_WS_NET && pl->net && j >= 2 && !gsf_level;
     if (pl->warm == TSFCDE_WS_NET) warm = j >= 1 ? 1 : 0;
+    if (gsf_level) warm = 0;
     int rc = level_rhs(pl, j, d_f, x, warm);
     if (rc) return rc;
     int guess = warm == 2 ? TSFCDE_WS_EXTRAP : (warm == 1 ? TSFCDE_WS_PREV : TSFCDE_WS_ZERO);
@@ -1314,10 +1475,18 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
     HIPCHK(precond_level(pl, j));
     SolveOut so;
     int outer = 1;
-    bool fp32 = level_uses_fp32(pl, j), fell_back = false;
+    bool fp32 = !gsf_level && level_uses_fp32(pl, j), fell_back = false;
     {
         ProfScope ps(pl, 3);
-        if (fp32) {
+        if (gsf_level) {
+            // x = A^-1 g by the formula, then the acceptance check as after a
+            // CGS solve; CGS continues from x only if the check fails
+            if ((rc = gsf_apply(pl, x))) return rc;
+            const bool no_bw = (pl->flags & (TSFCDE_FLAG_VERIFY | TSFCDE_FLAG_STRICT_RESIDUAL)) != 0;
+            if ((rc = restart_launch(pl, j, x, no_bw ? 0.0 : BW_TOL))) return rc;
+            if ((rc = fp64_cgs(pl, j, x, so))) return rc;
+            guess = TSFCDE_WS_ZERO;
+        } else if (fp32) {
             if ((rc = ir_solve(pl, j, x, so, outer, fell_back))) return rc;
         } else {
             if (warm == 2 && !use_net && (rc = restart_launch(pl, j, x, 0.0))) return rc;  // r0 = g - A x0
@@ -1347,142 +1516,19 @@ int level_step(tsfcde_plan_s *pl, const double *d_f, double *d_u_out, tsfcde_sta
         st->backward_err = so.backward_err;
         st->precision_used = fp32 ? (fell_back ? TSFCDE_FP32_REFINED_FELL_BACK : TSFCDE_FP32_REFINED) : TSFCDE_FP64;
         st->guess = use_net ? (hs.netkept ? TSFCDE_WS_NET : TSFCDE_WS_PREV) : guess;
+        st->method = gsf_level ? TSFCDE_METHOD_GSF
+                               : (pl->krylov == TSFCDE_KRYLOV_BICGSTAB && !fp32 ? TSFCDE_METHOD_PBICGSTAB
+                                                                               : TSFCDE_METHOD_PCGS);
+        st->pad = 0;
+        st->iters += gprep.iters;
+        st->restarts += gprep.restarts;
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return so.code;
 }
 
-double sample(tsfcde_coef_fn fn, const double *arr, void *user, int64_t j, double t) {
-    return fn ? fn(t, user) : arr[j];
-}
-
-}  // namespace
-
-extern "C" {
-
-static int workspace_bytes_impl(const tsfcde_problem *prob, bool force_general, size_t *bytes) {
-    int rc = validate(prob);
-    if (rc) return rc;
-    if (!bytes) return TSFCDE_EINVAL;
-    RT A, P, B;
-    const bool p2 = rt_setup(A, P, B, prob->n, force_general);
-    if (!partials_fit(A)) return TSFCDE_EUNSUPPORTED;
-    *bytes = layout_for(prob->n, prob->M, A, P, B, p2, prob->precision == TSFCDE_FP32_REFINED).total;
-    return TSFCDE_OK;
-}
-
-int tsfcde_workspace_bytes(const tsfcde_problem *prob, size_t *bytes) {
-    return workspace_bytes_impl(prob, false, bytes);
-}
-
-static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t bytes, void *stream,
-                       bool force_general, tsfcde_plan_t *out) {
-    if (!out) return TSFCDE_EINVAL;
-    *out = nullptr;
-    int rc = validate(prob);
-    if (rc) return rc;
-    if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255)) return TSFCDE_EINVAL;
-    {
-        RT A, P, B;
-        rt_setup(A, P, B, prob->n, force_general);
-        if (!partials_fit(A)) return TSFCDE_EUNSUPPORTED;
-    }
-    const int64_t n = prob->n, M = prob->M;
-    tsfcde_plan_s *pl = new (std::nothrow) tsfcde_plan_s();
-    if (!pl) return TSFCDE_ENOMEM;
-    pl->alpha = prob->alpha;
-    pl->beta = prob->beta;
-    pl->a = prob->a;
-    pl->b = prob->b;
-    pl->T = prob->T;
-    pl->n = n;
-    pl->M = M;
-    pl->h = (prob->b - prob->a) / (double)(n + 1);
-    pl->tau = prob->T / (double)M;
-    pl->sigma = 1.0 - prob->alpha / 2.0;
-    pl->kappa = std::pow(pl->tau, -prob->alpha) / std::tgamma(2.0 - prob->alpha);
-    pl->hb = std::pow(pl->h, -prob->beta);
-    pl->rtol = prob->rtol > 0 ? prob->rtol : 1e-10;
-    pl->maxit = prob->maxit > 0 ? prob->maxit : 500;
-    pl->warm = prob->warm_start;
-    pl->flags = prob->flags;
-    pl->fcb = prob->f;
-    pl->fuser = prob->f_user;
-    // coefficients at t_{j+sigma}
-    pl->gam.resize(M);
-    pl->dp.resize(M);
-    pl->dm.resize(M);
-    for (int64_t j = 0; j < M; ++j) {
-        const double t = level_time(pl, j);
-        pl->gam[j] = sample(prob->gamma, prob->gamma_at, prob->coef_user, j, t);
-        pl->dp[j] = sample(prob->dplus, prob->dplus_at, prob->coef_user, j, t);
-        pl->dm[j] = sample(prob->dminus, prob->dminus_at, prob->coef_user, j, t);
-        if (!std::isfinite(pl->gam[j]) || !std::isfinite(pl->dp[j]) || !std::isfinite(pl->dm[j]) ||
-            pl->dp[j] < 0.0 || pl->dm[j] < 0.0) {
-            delete pl;
-            return TSFCDE_EINVAL;
-        }
-    }
-    // L2-1sigma tables (Lemma 1)
-    {
-        const double al = prob->alpha, sg = pl->sigma;
-        std::vector<double> av(M + 2), bv(M + 2, 0.0);
-        av[0] = std::pow(sg, 1.0 - al);
-        for (int64_t l = 1; l <= M + 1; ++l) {
-            av[l] = std::pow(l + sg, 1.0 - al) - std::pow(l - 1 + sg, 1.0 - al);
-            bv[l] = (std::pow(l + sg, 2.0 - al) - std::pow(l - 1 + sg, 2.0 - al)) / (2.0 - al) -
-                    0.5 * (std::pow(l + sg, 1.0 - al) + std::pow(l - 1 + sg, 1.0 - al));
-        }
-        pl->eta.resize(M);
-        pl->cbase.assign(M + 2, 0.0);
-        pl->clast.assign(M + 1, 0.0);
-        for (int64_t j = 0; j < M; ++j) pl->eta[j] = pl->kappa * (j == 0 ? av[0] : av[0] + bv[1]);
-        for (int64_t m = 1; m <= M; ++m) pl->cbase[m] = av[m] + bv[m + 1] - bv[m];
-        for (int64_t j = 1; j <= M; ++j) pl->clast[j] = av[j] - bv[j];
-    }
-    pl->p2 = rt_setup(pl->A, pl->P, pl->B, n, force_general);
-    pl->ldn = ld_of(n);
-    // |A|_2 <= eta + sigma (|gamma|/h + (d+ + d-) h^-beta sum_k |omega_k|): A is
-    // eta I - sigma L with |Q|_2 <= 2 and |W|_2 <= max(|W|_1, |W|_inf) <= sum |omega_k|
-    {
-        const double b = prob->beta;
-        const double l1 = (b * b + 3.0 * b + 2.0) / 12.0, l0 = (4.0 - b * b) / 6.0, lm1 = (b * b - 3.0 * b + 2.0) / 12.0;
-        double gkm2 = 0.0, gkm1 = 0.0, gk = 1.0, sabs = 0.0;  // g_{k-2}, g_{k-1}, g_k (Lemma 3 recurrence)
-        for (int64_t k = 0; k <= n; ++k) {
-            if (k > 0) {
-                gkm2 = gkm1;
-                gkm1 = gk;
-                gk = (1.0 - (b + 1.0) / (double)k) * gkm1;
-            }
-            const double om = l1 * gk + (k >= 1 ? l0 * gkm1 : 0.0) + (k >= 2 ? lm1 * gkm2 : 0.0);
-            sabs += std::fabs(om);
-        }
-        pl->anorm.resize(M);
-        for (int64_t j = 0; j < M; ++j)
-            pl->anorm[j] = pl->eta[j] + pl->sigma * (std::fabs(pl->gam[j]) / pl->h + (pl->dp[j] + pl->dm[j]) * pl->hb * sabs);
-    }
-    pl->fp32 = prob->precision == TSFCDE_FP32_REFINED;
-    pl->lay = layout_for(n, M, pl->A, pl->P, pl->B, pl->p2, pl->fp32);
-    if (pl->fp32) {
-        // |A| / eta <= 1 + sigma (|gamma|/h + (d+ + d-) h^-beta 2|omega_1|) / eta  (Remark 3.1, eig(Q))
-        const double b = prob->beta;
-        const double om1 = std::fabs(-b * (b * b + 3.0 * b + 2.0) / 12.0 + (4.0 - b * b) / 6.0);
-        pl->kbound.resize(M);
-        for (int64_t j = 0; j < M; ++j)
-            pl->kbound[j] = 1.0 + pl->sigma *
-                                      (std::fabs(pl->gam[j]) / pl->h + (pl->dp[j] + pl->dm[j]) * pl->hb * 2.0 * om1) /
-                                      pl->eta[j];
-    }
-    if (bytes < pl->lay.total) {
-        delete pl;
-        return TSFCDE_ENOMEM;
-    }
-    if (hipGetDevice(&pl->device) != hipSuccess) {
-        delete pl;
-        return TSFCDE_EDEVICE;
-    }
-    pl->stream = reinterpret_cast<hipStream_t>(stream);
-    char *ws = reinterpret_cast<char *>(d_workspace);
+// Pointers of every buffer of pl->lay inside the workspace ws.
+void bind_workspace(tsfcde_plan_s *pl, char *ws) {
     pl->ws = ws;
     const Layout &L = pl->lay;
     pl->U = reinterpret_cast<double *>(ws + L.off_U);
@@ -1529,7 +1575,215 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
         pl->specP32 = reinterpret_cast<float2 *>(ws + L.off_specP32);
         pl->specPj32 = reinterpret_cast<float2 *>(ws + L.off_specPj32);
     }
+    if (pl->gsf) {
+        char *g = ws + L.off_gsf;
+        pl->gx = reinterpret_cast<double *>(g);
+        pl->gy = pl->gx + pl->ldn;
+        g += 2 * sizeof(double) * (size_t)pl->ldn;
+        for (int w = 0; w < 4; ++w) pl->gspec[w] = reinterpret_cast<double2 *>(g + (size_t)w * al(sizeof(double2) * (size_t)pl->A.N));
+    }
+}
 
+// Twiddle tables, the WSGD weights omega_0..omega_n and the two circulant
+// spectra of W_beta (Sec. 3.2), queued on pl->stream into the bound workspace
+// (everything a plan computes on the device before its first level).
+hipError_t setup_spectra(tsfcde_plan_s *pl, double beta) {
+    const int64_t n = pl->n;
+    // twiddle tables
+    hipLaunchKernelGGL(k_twiddle_packed, dim3(32), dim3(256), 0, pl->stream, pl->tw_all, PMAX_LOG2);
+    for (RT *rt : {&pl->A, pl->p2 ? &pl->P : &pl->B})
+        hipLaunchKernelGGL(k_twiddle_tw2, dim3(64), dim3(256), 0, pl->stream, rt->lo, rt->hi, rt->L, rt->shift,
+                           rt->nhi);
+    // WSGD weights omega_0..omega_n (Lemma 2, Lemma 3 recurrence)
+    hipLaunchKernelGGL(k_grunwald, dim3(1), dim3(1024), 0, pl->stream, beta, n, pl->g0);
+    {
+        const double b2 = beta * beta;
+        const double l1 = (b2 + 3.0 * beta + 2.0) / 12.0, l0 = (4.0 - b2) / 6.0,
+                     lm1 = (b2 - 3.0 * beta + 2.0) / 12.0;
+        hipLaunchKernelGGL(k_wsgd, dim3(256), dim3(256), 0, pl->stream, pl->g0, n, l1, l0, lm1, pl->w);
+    }
+    if (hipError_t e = hipGetLastError()) return e;
+    // spectra: embedding of W (length 2n) and Strang s(W) (length n)
+    {
+        hipLaunchKernelGGL(k_embed_column, dim3(512), dim3(256), 0, pl->stream, pl->w, n, pl->A.L, pl->tmp);
+        InReal in{pl->tmp, pl->A.L, pl->A.C};
+        if (launch_col<-1>(pl, pl->A, in, out_spec(pl, pl->A), 0) != hipSuccess) return hipErrorLaunchFailure;
+        SymParams sp{};
+        if (launch_mid<2>(pl, pl->A, pl->buf, (const double2 *)nullptr, pl->specA, sp, 0) != hipSuccess)
+            return hipErrorLaunchFailure;
+        if (pl->prec == TSFCDE_PREC_TCHAN)
+            hipLaunchKernelGGL(k_tchan_column, dim3(512), dim3(256), 0, pl->stream, pl->w, n, pl->tmp);
+        else
+            hipLaunchKernelGGL(k_strang_column, dim3(512), dim3(256), 0, pl->stream, pl->w, n, pl->tmp);
+        if (pl->p2) {
+            InReal inP{pl->tmp, n, pl->P.C};
+            if (launch_col<-1>(pl, pl->P, inP, out_spec(pl, pl->P), 0) != hipSuccess) return hipErrorLaunchFailure;
+            if (launch_mid<2>(pl, pl->P, pl->bufP, (const double2 *)nullptr, pl->specP, sp, 0) != hipSuccess)
+                return hipErrorLaunchFailure;
+        } else {
+            // Bluestein set-up: chirp, the spectrum of its circular arrangement
+            // (with the 1/L of the inverse transform folded in), then the Strang
+            // spectrum lambda = DFT_n(strang column).
+            const RT &B = pl->B;
+            hipLaunchKernelGGL(k_chirp, dim3(256), dim3(256), 0, pl->stream, pl->chirp, n);
+            hipLaunchKernelGGL(k_chirp_embed, dim3(256), dim3(256), 0, pl->stream, pl->chirp, n, B.N,
+                               1.0 / (double)B.N, pl->Bhat);
+            OutSpec o{pl->bufB, B.tw, B.C};
+            o.partials = nullptr;
+            if (launch_col<-1>(pl, B, InCplx{pl->Bhat, nullptr, nullptr, B.N, B.C}, o, 0) != hipSuccess)
+                return hipErrorLaunchFailure;
+            if (launch_row<4>(pl, pl->bufB, nullptr, pl->Bhat) != hipSuccess) return hipErrorLaunchFailure;
+            if (bluestein(pl, nullptr, pl->tmp, pl->Ls) != hipSuccess) return hipErrorLaunchFailure;
+        }
+    }
+    return hipGetLastError();
+}
+
+double sample(tsfcde_coef_fn fn, const double *arr, void *user, int64_t j, double t) {
+    return fn ? fn(t, user) : arr[j];
+}
+
+}  // namespace
+
+extern "C" {
+
+static int workspace_bytes_impl(const tsfcde_problem *prob, bool force_general, size_t *bytes) {
+    int rc = validate(prob);
+    if (rc) return rc;
+    if (!bytes) return TSFCDE_EINVAL;
+    RT A, P, B;
+    const bool p2 = rt_setup(A, P, B, prob->n, force_general);
+    if (!partials_fit(A)) return TSFCDE_EUNSUPPORTED;
+    *bytes = layout_for(prob->n, prob->M, A, P, B, p2, prob->precision == TSFCDE_FP32_REFINED,
+                        (prob->flags & TSFCDE_FLAG_CONSTANT_GSF) != 0)
+                 .total;
+    return TSFCDE_OK;
+}
+
+int tsfcde_workspace_bytes(const tsfcde_problem *prob, size_t *bytes) {
+    return workspace_bytes_impl(prob, false, bytes);
+}
+
+static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t bytes, void *stream,
+                       bool force_general, tsfcde_plan_t *out) {
+    if (!out) return TSFCDE_EINVAL;
+    *out = nullptr;
+    int rc = validate(prob);
+    if (rc) return rc;
+    if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255)) return TSFCDE_EINVAL;
+    {
+        RT A, P, B;
+        rt_setup(A, P, B, prob->n, force_general);
+        if (!partials_fit(A)) return TSFCDE_EUNSUPPORTED;
+    }
+    const int64_t n = prob->n, M = prob->M;
+    tsfcde_plan_s *pl = new (std::nothrow) tsfcde_plan_s();
+    if (!pl) return TSFCDE_ENOMEM;
+    pl->alpha = prob->alpha;
+    pl->beta = prob->beta;
+    pl->a = prob->a;
+    pl->b = prob->b;
+    pl->T = prob->T;
+    pl->n = n;
+    pl->M = M;
+    pl->h = (prob->b - prob->a) / (double)(n + 1);
+    pl->tau = prob->T / (double)M;
+    pl->sigma = 1.0 - prob->alpha / 2.0;
+    pl->kappa = std::pow(pl->tau, -prob->alpha) / std::tgamma(2.0 - prob->alpha);
+    pl->hb = std::pow(pl->h, -prob->beta);
+    pl->rtol = prob->rtol > 0 ? prob->rtol : 1e-10;
+    pl->maxit = prob->maxit > 0 ? prob->maxit : 500;
+    pl->warm = prob->warm_start;
+    pl->flags = prob->flags;
+    pl->fcb = prob->f;
+    pl->fuser = prob->f_user;
+    pl->krylov = prob->krylov;
+    pl->prec = prob->preconditioner;
+    pl->qfac = pl->prec == TSFCDE_PREC_TCHAN ? (double)(n - 1) / (double)n : 1.0;
+    // coefficients at t_{j+sigma}
+    pl->gam.resize(M);
+    pl->dp.resize(M);
+    pl->dm.resize(M);
+    for (int64_t j = 0; j < M; ++j) {
+        const double t = level_time(pl, j);
+        pl->gam[j] = sample(prob->gamma, prob->gamma_at, prob->coef_user, j, t);
+        pl->dp[j] = sample(prob->dplus, prob->dplus_at, prob->coef_user, j, t);
+        pl->dm[j] = sample(prob->dminus, prob->dminus_at, prob->coef_user, j, t);
+        if (!std::isfinite(pl->gam[j]) || !std::isfinite(pl->dp[j]) || !std::isfinite(pl->dm[j]) ||
+            pl->dp[j] < 0.0 || pl->dm[j] < 0.0) {
+            delete pl;
+            return TSFCDE_EINVAL;
+        }
+    }
+    // L2-1sigma tables (Lemma 1)
+    {
+        const double al = prob->alpha, sg = pl->sigma;
+        std::vector<double> av(M + 2), bv(M + 2, 0.0);
+        av[0] = std::pow(sg, 1.0 - al);
+        for (int64_t l = 1; l <= M + 1; ++l) {
+            av[l] = std::pow(l + sg, 1.0 - al) - std::pow(l - 1 + sg, 1.0 - al);
+            bv[l] = (std::pow(l + sg, 2.0 - al) - std::pow(l - 1 + sg, 2.0 - al)) / (2.0 - al) -
+                    0.5 * (std::pow(l + sg, 1.0 - al) + std::pow(l - 1 + sg, 1.0 - al));
+        }
+        pl->eta.resize(M);
+        pl->cbase.assign(M + 2, 0.0);
+        pl->clast.assign(M + 1, 0.0);
+        for (int64_t j = 0; j < M; ++j) pl->eta[j] = eta_level(al, sg, pl->kappa, j);
+        for (int64_t m = 1; m <= M; ++m) pl->cbase[m] = av[m] + bv[m + 1] - bv[m];
+        for (int64_t j = 1; j <= M; ++j) pl->clast[j] = av[j] - bv[j];
+    }
+    pl->p2 = rt_setup(pl->A, pl->P, pl->B, n, force_general);
+    pl->ldn = ld_of(n);
+    // |A|_2 <= eta + sigma (|gamma|/h + (d+ + d-) h^-beta sum_k |omega_k|): A is
+    // eta I - sigma L with |Q|_2 <= 2 and |W|_2 <= max(|W|_1, |W|_inf) <= sum |omega_k|
+    {
+        const double b = prob->beta;
+        const double l1 = (b * b + 3.0 * b + 2.0) / 12.0, l0 = (4.0 - b * b) / 6.0, lm1 = (b * b - 3.0 * b + 2.0) / 12.0;
+        double gkm2 = 0.0, gkm1 = 0.0, gk = 1.0, sabs = 0.0;  // g_{k-2}, g_{k-1}, g_k (Lemma 3 recurrence)
+        for (int64_t k = 0; k <= n; ++k) {
+            if (k > 0) {
+                gkm2 = gkm1;
+                gkm1 = gk;
+                gk = (1.0 - (b + 1.0) / (double)k) * gkm1;
+            }
+            const double om = l1 * gk + (k >= 1 ? l0 * gkm1 : 0.0) + (k >= 2 ? lm1 * gkm2 : 0.0);
+            sabs += std::fabs(om);
+        }
+        pl->anorm.resize(M);
+        for (int64_t j = 0; j < M; ++j)
+            pl->anorm[j] = pl->eta[j] + pl->sigma * (std::fabs(pl->gam[j]) / pl->h + (pl->dp[j] + pl->dm[j]) * pl->hb * sabs);
+    }
+    pl->fp32 = prob->precision == TSFCDE_FP32_REFINED;
+    pl->gsf = (prob->flags & TSFCDE_FLAG_CONSTANT_GSF) != 0;
+    if (pl->gsf) {  // Algorithm 3 needs gamma, d_+- constant in t
+        for (int64_t j = 1; j < M; ++j)
+            if (pl->gam[j] != pl->gam[0] || pl->dp[j] != pl->dp[0] || pl->dm[j] != pl->dm[0]) {
+                delete pl;
+                return TSFCDE_EINVAL;
+            }
+    }
+    pl->lay = layout_for(n, M, pl->A, pl->P, pl->B, pl->p2, pl->fp32, pl->gsf);
+    if (pl->fp32) {
+        // |A| / eta <= 1 + sigma (|gamma|/h + (d+ + d-) h^-beta 2|omega_1|) / eta  (Remark 3.1, eig(Q))
+        const double b = prob->beta;
+        const double om1 = std::fabs(-b * (b * b + 3.0 * b + 2.0) / 12.0 + (4.0 - b * b) / 6.0);
+        pl->kbound.resize(M);
+        for (int64_t j = 0; j < M; ++j)
+            pl->kbound[j] = 1.0 + pl->sigma *
+                                      (std::fabs(pl->gam[j]) / pl->h + (pl->dp[j] + pl->dm[j]) * pl->hb * 2.0 * om1) /
+                                      pl->eta[j];
+    }
+    if (bytes < pl->lay.total) {
+        delete pl;
+        return TSFCDE_ENOMEM;
+    }
+    if (hipGetDevice(&pl->device) != hipSuccess) {
+        delete pl;
+        return TSFCDE_EDEVICE;
+    }
+    pl->stream = reinterpret_cast<hipStream_t>(stream);
+    bind_workspace(pl, reinterpret_cast<char *>(d_workspace));
+    const Layout &L = pl->lay;
     auto fail = [&](int code) {
         if (pl->h_sc) (void)hipHostFree(pl->h_sc);
         delete pl;
@@ -1544,54 +1798,11 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
     if (hipMemcpyAsync(pl->sc, pl->h_sc, sizeof(DevScalars), hipMemcpyHostToDevice, pl->stream) != hipSuccess)
         return fail(TSFCDE_EDEVICE);
     // stored levels and vectors start at zero (the pad of an odd-length row stays zero)
-    if (hipMemsetAsync(ws + L.off_U, 0, L.off_tmp - L.off_U, pl->stream) != hipSuccess) return fail(TSFCDE_EDEVICE);
+    if (hipMemsetAsync(pl->ws + L.off_U, 0, L.off_tmp - L.off_U, pl->stream) != hipSuccess) return fail(TSFCDE_EDEVICE);
     if (hipMemcpyAsync(pl->cb, pl->cbase.data(), sizeof(double) * (M + 1), hipMemcpyHostToDevice, pl->stream) !=
         hipSuccess)
         return fail(TSFCDE_EDEVICE);
-    // twiddle tables
-    hipLaunchKernelGGL(k_twiddle_packed, dim3(32), dim3(256), 0, pl->stream, pl->tw_all, PMAX_LOG2);
-    for (RT *rt : {&pl->A, pl->p2 ? &pl->P : &pl->B})
-        hipLaunchKernelGGL(k_twiddle_tw2, dim3(64), dim3(256), 0, pl->stream, rt->lo, rt->hi, rt->L, rt->shift,
-                           rt->nhi);
-    // WSGD weights omega_0..omega_n (Lemma 2, Lemma 3 recurrence)
-    hipLaunchKernelGGL(k_grunwald, dim3(1), dim3(1024), 0, pl->stream, prob->beta, n, pl->g0);
-    {
-        const double b2 = prob->beta * prob->beta;
-        const double l1 = (b2 + 3.0 * prob->beta + 2.0) / 12.0, l0 = (4.0 - b2) / 6.0,
-                     lm1 = (b2 - 3.0 * prob->beta + 2.0) / 12.0;
-        hipLaunchKernelGGL(k_wsgd, dim3(256), dim3(256), 0, pl->stream, pl->g0, n, l1, l0, lm1, pl->w);
-    }
-    if (hipGetLastError() != hipSuccess) return fail(TSFCDE_EDEVICE);
-    // spectra: embedding of W (length 2n) and Strang s(W) (length n)
-    {
-        hipLaunchKernelGGL(k_embed_column, dim3(512), dim3(256), 0, pl->stream, pl->w, n, pl->A.L, pl->tmp);
-        InReal in{pl->tmp, pl->A.L, pl->A.C};
-        if (launch_col<-1>(pl, pl->A, in, out_spec(pl, pl->A), 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
-        SymParams sp{};
-        if (launch_mid<2>(pl, pl->A, pl->buf, (const double2 *)nullptr, pl->specA, sp, 0) != hipSuccess)
-            return fail(TSFCDE_EDEVICE);
-        hipLaunchKernelGGL(k_strang_column, dim3(512), dim3(256), 0, pl->stream, pl->w, n, pl->tmp);
-        if (pl->p2) {
-            InReal inP{pl->tmp, n, pl->P.C};
-            if (launch_col<-1>(pl, pl->P, inP, out_spec(pl, pl->P), 0) != hipSuccess) return fail(TSFCDE_EDEVICE);
-            if (launch_mid<2>(pl, pl->P, pl->bufP, (const double2 *)nullptr, pl->specP, sp, 0) != hipSuccess)
-                return fail(TSFCDE_EDEVICE);
-        } else {
-            // Bluestein set-up: chirp, the spectrum of its circular arrangement
-            // (with the 1/L of the inverse transform folded in), then the Strang
-            // spectrum lambda = DFT_n(strang column).
-            const RT &B = pl->B;
-            hipLaunchKernelGGL(k_chirp, dim3(256), dim3(256), 0, pl->stream, pl->chirp, n);
-            hipLaunchKernelGGL(k_chirp_embed, dim3(256), dim3(256), 0, pl->stream, pl->chirp, n, B.N,
-                               1.0 / (double)B.N, pl->Bhat);
-            OutSpec o{pl->bufB, B.tw, B.C};
-            o.partials = nullptr;
-            if (launch_col<-1>(pl, B, InCplx{pl->Bhat, nullptr, nullptr, B.N, B.C}, o, 0) != hipSuccess)
-                return fail(TSFCDE_EDEVICE);
-            if (launch_row<4>(pl, pl->bufB, nullptr, pl->Bhat) != hipSuccess) return fail(TSFCDE_EDEVICE);
-            if (bluestein(pl, nullptr, pl->tmp, pl->Ls) != hipSuccess) return fail(TSFCDE_EDEVICE);
-        }
-    }
+    if (setup_spectra(pl, prob->beta) != hipSuccess) return fail(TSFCDE_EDEVICE);
     // FP32 copies of the spectra for the inner solve of the FP32-refined form
     if (pl->fp32) {
         hipLaunchKernelGGL(k_to_f32, dim3(512), dim3(256), 0, pl->stream, pl->specA, pl->specA32, pl->A.N);
@@ -1649,8 +1860,8 @@ int tsfcde_solve(tsfcde_plan_t pl, const double *d_F, int64_t ldF, double *d_U_o
 
 static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-int tsfcde_apply(tsfcde_plan_t pl, int32_t op, int64_t j, const double *d_x, double *d_y) {
-    if (!pl || !d_x || !d_y || j < 0 || j >= pl->M || !aligned16(d_x) || !aligned16(d_y)) return TSFCDE_EINVAL;
+// y = op x at level j, queued on the plan's stream (arguments checked by the caller).
+static int apply_queue(tsfcde_plan_t pl, int32_t op, int64_t j, const double *d_x, double *d_y) {
     const int64_t n = pl->n;
     if (op == TSFCDE_OP_A || op == TSFCDE_OP_B) {
         const double s = op == TSFCDE_OP_A ? -pl->sigma : 1.0 - pl->sigma;
@@ -1672,6 +1883,12 @@ int tsfcde_apply(tsfcde_plan_t pl, int32_t op, int64_t j, const double *d_x, dou
     } else {
         return TSFCDE_EINVAL;
     }
+    return TSFCDE_OK;
+}
+
+int tsfcde_apply(tsfcde_plan_t pl, int32_t op, int64_t j, const double *d_x, double *d_y) {
+    if (!pl || !d_x || !d_y || j < 0 || j >= pl->M || !aligned16(d_x) || !aligned16(d_y)) return TSFCDE_EINVAL;
+    if (int rc = apply_queue(pl, op, j, d_x, d_y)) return rc;
     HIPCHK(hipStreamSynchronize(pl->stream));
     harvest(pl);
     return TSFCDE_OK;
@@ -1956,10 +2173,16 @@ __global__ void k_gather_state(DevScalars *const *__restrict__ scs, int count, D
 
 namespace {
 
+struct ChunkGraph {
+    hipGraphExec_t exec;
+    const void *key;  // descriptor address the capture read
+};
+
 struct BatchGroup {
     int64_t L = 0;
     RT A, B;
     std::vector<int> members;
+    int e_mid = TSF_E_MID;  // values per lane of the group's middle passes (autotuned)
 };
 
 // bump allocator mirroring a pinned host staging area onto a device area
@@ -1991,6 +2214,8 @@ struct tsfcde_batch_s {
     int last_iters = 8;
     bool fold = true;  // finishing steps folded into later passes (TSFCDE_FLAG_NO_FOLD clears it)
     bool strict = false;  // TSFCDE_FLAG_STRICT_RESIDUAL: accept only at a true residual within rtol |g|
+    bool graphs = false;  // TSFCDE_FLAG_GRAPHS: CGS chunks replayed from captured HIP graphs
+    std::map<int, ChunkGraph> chunk_graphs;  // by chunk length
 };
 
 namespace {
@@ -2043,20 +2268,31 @@ hipError_t bfinal(tsfcde_batch_s *bt, const RT &rt, const ColDesc<In, Out> *d, i
     }
 }
 
-template <int C_, int MODE>
-hipError_t blaunch_mid_t(tsfcde_batch_s *bt, const RT &rt, const MidDesc *d, int cnt, int pred) {
-    using G = MidGeo<C_, TSF_E_MID>;
-    hipLaunchKernelGGL((k_mid_b<C_, TSF_E_MID, MODE>), dim3((unsigned)(rt.R / 2), cnt), dim3(G::NT), 0, bt->stream,
-                       d, bt->plans[0]->tw_all, pred);
+template <int C_, int E, int MODE>
+hipError_t blaunch_mid_e(tsfcde_batch_s *bt, const RT &rt, const MidDesc *d, int cnt, int pred) {
+    using G = MidGeo<C_, E>;
+    hipLaunchKernelGGL((k_mid_b<C_, E, MODE>), dim3((unsigned)(rt.R / 2), cnt), dim3(G::NT), 0, bt->stream, d,
+                       bt->plans[0]->tw_all, pred);
     return hipGetLastError();
 }
 
+// Values per lane the batch's middle passes can take (the tuner picks one
+// per group): 4 or the default 8 on rows of 16..1024 points.
+constexpr int TUNE_E_ALT = 4;
+template <int C_, int MODE>
+hipError_t blaunch_mid_t(tsfcde_batch_s *bt, const RT &rt, const MidDesc *d, int cnt, int pred, int e) {
+    if constexpr (C_ >= 16 && C_ <= 1024) {
+        if (e == TUNE_E_ALT) return blaunch_mid_e<C_, TUNE_E_ALT, MODE>(bt, rt, d, cnt, pred);
+    }
+    return blaunch_mid_e<C_, TSF_E_MID, MODE>(bt, rt, d, cnt, pred);
+}
+
 template <int MODE>
-hipError_t blaunch_mid(tsfcde_batch_s *bt, const RT &rt, const MidDesc *d, int cnt, int pred) {
+hipError_t blaunch_mid(tsfcde_batch_s *bt, const RT &rt, const MidDesc *d, int cnt, int pred, int e = TSF_E_MID) {
     if (!d) return hipErrorOutOfMemory;
     switch (rt.C) {
 #define TSF_CASE(P) \
-    case P: return blaunch_mid_t<P, MODE>(bt, rt, d, cnt, pred);
+    case P: return blaunch_mid_t<P, MODE>(bt, rt, d, cnt, pred, e);
         TSF_SIZES(TSF_CASE)
 #undef TSF_CASE
         default: return hipErrorInvalidValue;
@@ -2218,6 +2454,185 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
     return S.used <= S.cap;
 }
 
+#define BCHK(x)                                             \
+    do {                                                    \
+        hipError_t e_ = (x);                                \
+        if (e_ != hipSuccess) return TSFCDE_EDEVICE;        \
+    } while (0)
+
+// `todo` CGS iterations of every group, as launches on the batch stream.  With
+// folding, the two reductions' finishing steps run inside the next passes
+// and the chunk ends with one finishing kernel per group.
+hipError_t issue_chunk(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, int todo) {
+    const bool fold = bt->fold;
+    hipError_t e = hipSuccess;
+#define TSF_TRY(x)                          \
+    do {                                    \
+        if ((e = (x)) != hipSuccess) return e; \
+    } while (0)
+    for (int k = 0; k < todo; ++k) {
+        for (size_t g = 0; g < bt->groups.size(); ++g) {
+            const BatchGroup &G = bt->groups[g];
+            const int c = (int)G.members.size();
+            const GroupDesc &D = gd[g];
+            TSF_TRY(blaunch_col<-1>(bt, G.A, D.s1[fold ? s1_variant(k) : 0], c, 1));
+            TSF_TRY(blaunch_mid<0>(bt, G.A, D.midP, c, 1, G.e_mid));
+            TSF_TRY(blaunch_col<1>(bt, G.A, D.s3, c, 1));
+            TSF_TRY(blaunch_col<-1>(bt, G.A, D.s4, c, 1));
+            TSF_TRY(blaunch_mid<0>(bt, G.A, D.midA, c, 1, G.e_mid));
+            TSF_TRY(blaunch_col<1>(bt, G.A, D.s6, c, 1, !fold));
+            if (fold) {
+                TSF_TRY(blaunch_col<-1>(bt, G.A, D.s7[s7_variant(k)], c, 1));
+            } else {
+                TSF_TRY(blaunch_col<-1>(bt, G.A, D.s7_plain, c, 1));
+            }
+            TSF_TRY(blaunch_mid<0>(bt, G.A, D.midP, c, 1, G.e_mid));
+            TSF_TRY(blaunch_col<1>(bt, G.A, D.s9, c, 1));
+            TSF_TRY(blaunch_col<-1>(bt, G.A, D.s10, c, 1));
+            TSF_TRY(blaunch_mid<0>(bt, G.A, D.midA, c, 1, G.e_mid));
+            TSF_TRY(blaunch_col<1>(bt, G.A, D.s12[0], c, 1, !fold));
+        }
+    }
+    if (fold) {
+        for (size_t g = 0; g < bt->groups.size(); ++g)
+            TSF_TRY(bfinal(bt, bt->groups[g].A, gd[g].s12[s7_variant(todo - 1)], (int)bt->groups[g].members.size(), 1));
+    }
+#undef TSF_TRY
+    return e;
+}
+
+// The chunk of `todo` iterations as an instantiated HIP graph, captured from
+// issue_chunk the first time that length is needed.  Its kernels read every
+// level-dependent value (symbols, scalars, vector addresses) from the staged
+// descriptors and the device scalars, never from their launch arguments, so
+// one capture serves every level while the descriptors sit at the same
+// addresses (checked; a change recaptures).  Kernels only: no memset or copy
+// nodes.
+int chunk_graph(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, int todo, hipGraphExec_t *out) {
+    const void *key = gd.empty() ? nullptr : (const void *)gd[0].s1[0];
+    auto it = bt->chunk_graphs.find(todo);
+    if (it != bt->chunk_graphs.end() && it->second.key == key) {
+        *out = it->second.exec;
+        return TSFCDE_OK;
+    }
+    if (it != bt->chunk_graphs.end()) {
+        (void)hipGraphExecDestroy(it->second.exec);
+        bt->chunk_graphs.erase(it);
+    }
+    hipGraph_t graph = nullptr;
+    BCHK(hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t e = issue_chunk(bt, gd, todo);
+    const hipError_t ec = hipStreamEndCapture(bt->stream, &graph);
+    if (e != hipSuccess || ec != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return TSFCDE_EDEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess || !ex) return TSFCDE_EDEVICE;
+    bt->chunk_graphs[todo] = ChunkGraph{ex, key};
+    *out = ex;
+    return TSFCDE_OK;
+}
+
+// ---- autotuner of the batch's middle passes ---------------------------------
+// A group's middle passes (the row FFTs with the symbol, most of a product's
+// time) can hold 4 or 8 values per lane; which is faster depends on the row
+// length and on how many instances share the launch.  plan_batch times both
+// on the group's own buffers and keeps the faster.  Choices are cached per
+// process by (row length, rows, instances) and, when the environment variable
+// TSFCDE_TUNE_CACHE names a file, in that file too (one line per choice:
+// "mid <C> <R> <instances> <E> <us E=4> <us E=8>"), read before tuning.
+struct TuneKey {
+    int64_t C, R;
+    int count;
+    bool operator<(const TuneKey &o) const {
+        return C != o.C ? C < o.C : (R != o.R ? R < o.R : count < o.count);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune_cache;
+bool g_tune_file_read = false;
+
+void tune_cache_read() {
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char *path = std::getenv("TSFCDE_TUNE_CACHE");
+    if (!path) return;
+    FILE *fh = std::fopen(path, "r");
+    if (!fh) return;
+    char kind[16];
+    long long c, r;
+    int cnt, e;
+    double t4, t8;
+    while (std::fscanf(fh, "%15s %lld %lld %d %d %lf %lf", kind, &c, &r, &cnt, &e, &t4, &t8) == 7)
+        if (std::strcmp(kind, "mid") == 0 && (e == TUNE_E_ALT || e == TSF_E_MID)) g_tune_cache[TuneKey{c, r, cnt}] = e;
+    std::fclose(fh);
+}
+
+void tune_cache_append(const TuneKey &k, int e, double t4, double t8) {
+    const char *path = std::getenv("TSFCDE_TUNE_CACHE");
+    if (!path) return;
+    if (FILE *fh = std::fopen(path, "a")) {
+        std::fprintf(fh, "mid %lld %lld %d %d %.3f %.3f\n", (long long)k.C, (long long)k.R, k.count, e, t4, t8);
+        std::fclose(fh);
+    }
+}
+
+// Times the group's middle pass (product mode, unit symbol, on every
+// member's own transform buffer) at each values-per-lane choice: one warm-up
+// launch, then the mean of `reps` launches between events.
+int tune_group(tsfcde_batch_s *bt, BatchGroup &G) {
+    const int cnt = (int)G.members.size();
+    const TuneKey key{G.A.C, G.A.R, cnt};
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_cache_read();
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+        G.e_mid = it->second;
+        return TSFCDE_OK;
+    }
+    if (G.A.C < 16 || G.A.C > 1024) return TSFCDE_OK;  // one choice only
+    std::vector<MidDesc> md;
+    for (int idx : G.members) {
+        tsfcde_plan_s *pl = bt->plans[idx];
+        md.push_back(MidDesc{pl->A.R, pl->buf, pl->specA, nullptr, pl->A.tw, unit_symbol(pl->A), pl->sc});
+    }
+    bt->st.used = 0;
+    MidDesc *d = bt->st.put(md);
+    if (!d) return TSFCDE_ENOMEM;
+    BCHK(hipMemcpyAsync(bt->st.dev, bt->st.host, bt->st.used, hipMemcpyHostToDevice, bt->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return TSFCDE_EDEVICE;
+    }
+    constexpr int reps = 4;
+    double us[2] = {0.0, 0.0};
+    const int cand[2] = {TUNE_E_ALT, TSF_E_MID};
+    hipError_t err = hipSuccess;
+    for (int c = 0; c < 2 && err == hipSuccess; ++c) {
+        err = blaunch_mid<0>(bt, G.A, d, cnt, 0, cand[c]);
+        if (err == hipSuccess) err = hipEventRecord(e0, bt->stream);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = blaunch_mid<0>(bt, G.A, d, cnt, 0, cand[c]);
+        if (err == hipSuccess) err = hipEventRecord(e1, bt->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        us[c] = 1e3 * (double)ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    bt->st.used = 0;
+    if (err != hipSuccess) return TSFCDE_EDEVICE;
+    G.e_mid = us[0] < us[1] ? cand[0] : cand[1];
+    g_tune_cache[key] = G.e_mid;
+    tune_cache_append(key, G.e_mid, us[0], us[1]);
+    return TSFCDE_OK;
+}
+
 int batch_poll(tsfcde_batch_s *bt) {
     hipLaunchKernelGGL(k_gather_state, dim3((bt->count + 255) / 256), dim3(256), 0, bt->stream, bt->d_scs, bt->count,
                        bt->d_done);
@@ -2227,11 +2642,6 @@ int batch_poll(tsfcde_batch_s *bt) {
     return TSFCDE_OK;
 }
 
-#define BCHK(x)                                             \
-    do {                                                    \
-        hipError_t e_ = (x);                                \
-        if (e_ != hipSuccess) return TSFCDE_EDEVICE;        \
-    } while (0)
 
 int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats) {
     if (bt->level >= bt->M) return TSFCDE_EDONE;
@@ -2280,16 +2690,18 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
                 hcatch.push_back(d);
             }
         }
-        pc.push_back(PcDesc{pl->Ls, pl->wv, pl->Wt, pl->tmp, pl->n, pl->A.L, symbol(pl, j, -pl->sigma, pl->A, false)});
+        pc.push_back(PcDesc{pl->Ls, pl->wv, pl->Wt, pl->tmp, pl->n, pl->A.L, precond_symbol(pl, j)});
         nmax = std::max(nmax, pl->n);
         Lmax = std::max(Lmax, pl->A.L);
     }
-    HistDesc *dhs = hsweep.empty() ? nullptr : bt->st.put(hsweep);
-    HistDesc *dhc = hcatch.empty() ? nullptr : bt->st.put(hcatch);
-    PcDesc *dpc = bt->st.put(pc);
+    // the groups' descriptors first: their offsets in the staging area are then
+    // the same at every level, which the captured chunk graphs rely on
     std::vector<GroupDesc> gd(bt->groups.size());
     for (size_t g = 0; g < bt->groups.size(); ++g)
         if (!stage_group(bt, bt->groups[g], j, fptr.data(), warm, gd[g])) return TSFCDE_ENOMEM;
+    HistDesc *dhs = hsweep.empty() ? nullptr : bt->st.put(hsweep);
+    HistDesc *dhc = hcatch.empty() ? nullptr : bt->st.put(hcatch);
+    PcDesc *dpc = bt->st.put(pc);
     if ((!hsweep.empty() && !dhs) || (!hcatch.empty() && !dhc) || !dpc || bt->st.used > bt->st.cap)
         return TSFCDE_ENOMEM;
     BCHK(hipMemcpyAsync(bt->st.dev, bt->st.host, bt->st.used, hipMemcpyHostToDevice, bt->stream));
@@ -2309,11 +2721,11 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
         const BatchGroup &G = bt->groups[g];
         const int c = (int)G.members.size();
         BCHK(blaunch_col<-1>(bt, G.A, gd[g].rhsA, c, 0));
-        BCHK(blaunch_mid<0>(bt, G.A, gd[g].midA, c, 0));
+        BCHK(blaunch_mid<0>(bt, G.A, gd[g].midA, c, 0, G.e_mid));
         BCHK(blaunch_col<1>(bt, G.A, gd[g].rhsC, c, 0));
         if (warm == 2) {
             BCHK(blaunch_col<-1>(bt, G.A, gd[g].rstA, c, 0));
-            BCHK(blaunch_mid<0>(bt, G.A, gd[g].midA, c, 0));
+            BCHK(blaunch_mid<0>(bt, G.A, gd[g].midA, c, 0, G.e_mid));
             BCHK(blaunch_col<1>(bt, G.A, gd[g].rstC, c, 0));
         }
     }
@@ -2335,7 +2747,7 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
         const BatchGroup &G = bt->groups[g];
         const int c = (int)G.members.size();
         BCHK(blaunch_col<-1>(bt, G.A, gd[g].r2cA, c, 0));
-        BCHK(blaunch_mid<2>(bt, G.A, gd[g].midR2C, c, 0));
+        BCHK(blaunch_mid<2>(bt, G.A, gd[g].midR2C, c, 0, G.e_mid));
     }
     for (tsfcde_plan_s *pl : bt->plans) pl->pj_level = j;
     // CGS, every instance on its own convergence flag; then every instance's
@@ -2349,36 +2761,14 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
         for (;;) {
             const int todo = std::min(chunk, bt->maxit - iters_seen);
             if (todo <= 0) break;
-            // with folding, the two reductions' finishing steps run inside the
-            // next passes and the chunk ends with one finishing kernel
-            const bool fold = bt->fold;
-            for (int k = 0; k < todo; ++k) {
-                for (size_t g = 0; g < bt->groups.size(); ++g) {
-                    const BatchGroup &G = bt->groups[g];
-                    const int c = (int)G.members.size();
-                    const GroupDesc &D = gd[g];
-                    BCHK(blaunch_col<-1>(bt, G.A, D.s1[fold ? s1_variant(k) : 0], c, 1));
-                    BCHK(blaunch_mid<0>(bt, G.A, D.midP, c, 1));
-                    BCHK(blaunch_col<1>(bt, G.A, D.s3, c, 1));
-                    BCHK(blaunch_col<-1>(bt, G.A, D.s4, c, 1));
-                    BCHK(blaunch_mid<0>(bt, G.A, D.midA, c, 1));
-                    BCHK(blaunch_col<1>(bt, G.A, D.s6, c, 1, !fold));
-                    if (fold) {
-                        BCHK(blaunch_col<-1>(bt, G.A, D.s7[s7_variant(k)], c, 1));
-                    } else {
-                        BCHK(blaunch_col<-1>(bt, G.A, D.s7_plain, c, 1));
-                    }
-                    BCHK(blaunch_mid<0>(bt, G.A, D.midP, c, 1));
-                    BCHK(blaunch_col<1>(bt, G.A, D.s9, c, 1));
-                    BCHK(blaunch_col<-1>(bt, G.A, D.s10, c, 1));
-                    BCHK(blaunch_mid<0>(bt, G.A, D.midA, c, 1));
-                    BCHK(blaunch_col<1>(bt, G.A, D.s12[0], c, 1, !fold));
+            if (todo > 0) {
+                if (bt->graphs) {
+                    hipGraphExec_t ex = nullptr;
+                    if (int rc = chunk_graph(bt, gd, todo, &ex)) return rc;
+                    BCHK(hipGraphLaunch(ex, bt->stream));
+                } else {
+                    BCHK(issue_chunk(bt, gd, todo));
                 }
-            }
-            if (fold && todo > 0) {
-                for (size_t g = 0; g < bt->groups.size(); ++g)
-                    BCHK(bfinal(bt, bt->groups[g].A, gd[g].s12[s7_variant(todo - 1)], (int)bt->groups[g].members.size(),
-                                1));
             }
             int rc = batch_poll(bt);
             if (rc) return rc;
@@ -2406,7 +2796,7 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
             const BatchGroup &G = bt->groups[g];
             const int c = (int)G.members.size();
             BCHK(blaunch_col<-1>(bt, G.A, gd[g].rstA, c, 0));
-            BCHK(blaunch_mid<0>(bt, G.A, gd[g].midA, c, 0));
+            BCHK(blaunch_mid<0>(bt, G.A, gd[g].midA, c, 0, G.e_mid));
             BCHK(blaunch_col<1>(bt, G.A, gd[g].vfyC, c, 0));
         }
         int rc = batch_poll(bt);
@@ -2449,6 +2839,10 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
             s.backward_err = rounds > 0 ? (den > 0 ? std::sqrt(r.aux0) / den : 0.0) : -1.0;
             s.precision_used = TSFCDE_FP64;
             s.seconds = secs;
+            s.guess = bt->warm == TSFCDE_WS_EXTRAP ? (j >= 2 ? TSFCDE_WS_EXTRAP : (j >= 1 ? TSFCDE_WS_PREV : TSFCDE_WS_ZERO))
+                                                   : (bt->warm == TSFCDE_WS_PREV ? TSFCDE_WS_PREV : TSFCDE_WS_ZERO);
+            s.method = TSFCDE_METHOD_PCGS;
+            s.pad = 0;
         }
     }
     bt->last_iters = std::max(1, maxiter);
@@ -2472,6 +2866,8 @@ int tsfcde_batch_workspace_bytes(const tsfcde_problem *probs, int32_t count, siz
         int rc = workspace_bytes_impl(&probs[i], true, &b);
         if (rc) return rc;
         if (probs[i].precision != TSFCDE_FP64) return TSFCDE_EUNSUPPORTED;  // the batch runs the FP64 form
+        if (probs[i].flags & TSFCDE_FLAG_CONSTANT_GSF) return TSFCDE_EUNSUPPORTED;  // single plans only
+        if (probs[i].krylov != TSFCDE_KRYLOV_CGS) return TSFCDE_EUNSUPPORTED;       // the batch runs CGS
         if (probs[i].M != probs[0].M) return TSFCDE_EINVAL;
         tot += al(b);
     }
@@ -2499,6 +2895,7 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
     bt->warm = probs[0].warm_start;
     bt->fold = (probs[0].flags & TSFCDE_FLAG_NO_FOLD) == 0;
     bt->strict = (probs[0].flags & TSFCDE_FLAG_STRICT_RESIDUAL) != 0;
+    bt->graphs = (probs[0].flags & TSFCDE_FLAG_GRAPHS) != 0;
     char *ws = reinterpret_cast<char *>(d_workspace);
     size_t off = 0;
     auto fail = [&](int code) {
@@ -2550,7 +2947,22 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
         }
         it->members.push_back(i);
     }
+    if (!(probs[0].flags & TSFCDE_FLAG_NO_TUNE)) {
+        for (BatchGroup &G : bt->groups)
+            if ((rc = tune_group(bt, G))) return fail(rc);
+    }
     *out = bt;
+    return TSFCDE_OK;
+}
+
+int tsfcde_batch_group_count(tsfcde_batch_t bt) { return bt ? (int)bt->groups.size() : TSFCDE_EINVAL; }
+
+int tsfcde_batch_group_info(tsfcde_batch_t bt, int32_t g, int64_t *L, int32_t *members, int32_t *values_per_lane) {
+    if (!bt || g < 0 || g >= (int)bt->groups.size()) return TSFCDE_EINVAL;
+    const BatchGroup &G = bt->groups[g];
+    if (L) *L = G.L;
+    if (members) *members = (int32_t)G.members.size();
+    if (values_per_lane) *values_per_lane = G.e_mid;
     return TSFCDE_OK;
 }
 
@@ -2577,6 +2989,7 @@ int tsfcde_batch_set_level(tsfcde_batch_t bt, int64_t level) {
 int tsfcde_batch_destroy(tsfcde_batch_t bt) {
     if (!bt) return TSFCDE_EINVAL;
     (void)hipStreamSynchronize(bt->stream);
+    for (auto &kv : bt->chunk_graphs) (void)hipGraphExecDestroy(kv.second.exec);
     for (tsfcde_plan_s *pl : bt->plans) tsfcde_destroy(pl);
     if (bt->st.host) (void)hipHostFree(bt->st.host);
     if (bt->h_done) (void)hipHostFree(bt->h_done);

@@ -46,7 +46,7 @@ def _coef_fields(gamma, dplus, dminus, keep: list):
 
 
 def _problem(*, alpha, beta, n, M, a, b, T, gamma, dplus, dminus, phi, f, rtol, maxit, precision, warm_start,
-             flags, keep: list):
+             flags, keep: list, krylov=N.TSFCDE_KRYLOV_CGS, preconditioner=N.TSFCDE_PREC_STRANG):
     """A tsfcde_problem; the Python callables and arrays it points to are
     appended to ``keep`` (they must outlive every library call that uses it)."""
     fields = _coef_fields(gamma, dplus, dminus, keep)
@@ -63,7 +63,7 @@ def _problem(*, alpha, beta, n, M, a, b, T, gamma, dplus, dminus, phi, f, rtol, 
     return N.tsfcde_problem(
         alpha=alpha, beta=beta, a=a, b=b, T=T, n=int(n), M=int(M), coef_user=None, phi=phi_cb, phi_user=None,
         rtol=rtol, maxit=maxit, precision=precision, warm_start=warm_start, flags=flags, f=f_cb, f_user=None,
-        **fields)
+        krylov=krylov, preconditioner=preconditioner, **fields)
 
 
 def _scalar_phi(prob):
@@ -88,6 +88,7 @@ class TimeLevelSolver:
                  phi: Optional[Callable] = None, f: Optional[Callable] = None,
                  a: float = 0.0, b: float = 1.0, T: float = 1.0, rtol: float = 1e-10, maxit: int = 500,
                  warm_start: int = N.TSFCDE_WS_ZERO, flags: int = 0, precision: int = N.TSFCDE_FP64,
+                 krylov: int = N.TSFCDE_KRYLOV_CGS, preconditioner: int = N.TSFCDE_PREC_STRANG,
                  device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
         self._lib = N.lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -99,7 +100,8 @@ class TimeLevelSolver:
         self._keep = []
         self.problem = _problem(alpha=alpha, beta=beta, n=n, M=M, a=a, b=b, T=T, gamma=gamma, dplus=dplus,
                                 dminus=dminus, phi=phi, f=f, rtol=rtol, maxit=maxit, precision=precision,
-                                warm_start=warm_start, flags=flags, keep=self._keep)
+                                warm_start=warm_start, flags=flags, keep=self._keep, krylov=krylov,
+                                preconditioner=preconditioner)
         nbytes = ctypes.c_size_t(0)
         N.check(self._lib.tsfcde_workspace_bytes(ctypes.byref(self.problem), ctypes.byref(nbytes)),
                 "tsfcde_workspace_bytes")
@@ -253,6 +255,7 @@ class BatchSolver:
 
     def __init__(self, problems, *, rtol: float = 1e-10, maxit: int = 500, warm_start: int = N.TSFCDE_WS_ZERO,
                  precision: int = N.TSFCDE_FP64, flags: int = 0, callbacks: bool = False,
+                 preconditioner: int = N.TSFCDE_PREC_STRANG, krylov: int = N.TSFCDE_KRYLOV_CGS,
                  device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
         self._lib = N.lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -266,7 +269,8 @@ class BatchSolver:
             arr[i] = _problem(alpha=prob.alpha, beta=prob.beta, n=prob.n, M=prob.M, a=prob.a, b=prob.b, T=prob.T,
                               gamma=prob.gamma, dplus=prob.dplus, dminus=prob.dminus, phi=None,
                               f=_scalar_f(prob) if callbacks else None, rtol=rtol, maxit=maxit,
-                              precision=precision, warm_start=warm_start, flags=flags, keep=self._keep)
+                              precision=precision, warm_start=warm_start, flags=flags, keep=self._keep,
+                              krylov=krylov, preconditioner=preconditioner)
         self._arr = arr
         nbytes = ctypes.c_size_t(0)
         N.check(self._lib.tsfcde_batch_workspace_bytes(arr, self.count, ctypes.byref(nbytes)),
@@ -288,6 +292,16 @@ class BatchSolver:
 
     def member(self, i: int):
         return self._lib.tsfcde_batch_member(self._batch, i)
+
+    def groups(self):
+        """[(L, members, values per lane of the middle passes)] per group."""
+        out = []
+        for g in range(int(self._lib.tsfcde_batch_group_count(self._batch))):
+            L, m, e = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+            N.check(self._lib.tsfcde_batch_group_info(self._batch, g, ctypes.byref(L), ctypes.byref(m),
+                                                      ctypes.byref(e)), "tsfcde_batch_group_info")
+            out.append((L.value, m.value, e.value))
+        return out
 
     def nodes(self, i: int) -> np.ndarray:
         """Member i's interior nodes."""

@@ -107,3 +107,29 @@ def test_batch_folded_finishing_is_bitwise_unfolded():
     assert runs[0][1] == runs[1][1]
     for a, b in zip(runs[0][0], runs[1][0]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("warm", [0, 2])
+def test_batch_graph_replay_is_bitwise_direct(warm):
+    """CGS chunks replayed from captured HIP graphs (TSFCDE_FLAG_GRAPHS) give
+    the same levels and iteration counts bit for bit as direct launches.
+    Every level re-stages its descriptors, runs history and right-hand-side
+    kernels eagerly and polls the host between replays, and each chunk
+    length is captured once and replayed at many levels."""
+    import paper_1603_00279_amd as P
+    banner(f"batch graphs warm={warm}")
+    probs = _instances(7, 12, 60, 5000, seed=31)
+    runs = []
+    Fs = None
+    for flags in (0, P.TSFCDE_FLAG_GRAPHS):
+        its = []
+        with P.BatchSolver(probs, rtol=1e-12, flags=flags, warm_start=warm) as bs:
+            Fs = batch_sources(bs, probs) if Fs is None else Fs
+            for j in range(probs[0].M):
+                code, stats = bs.step([F[j] for F in Fs])
+                assert code == 0, stats
+                its.append([st["iters"] for st in stats])
+            runs.append(([host(bs.history(i)) for i in range(len(probs))], its))
+    assert runs[0][1] == runs[1][1]
+    for a, b in zip(runs[0][0], runs[1][0]):
+        assert np.array_equal(a, b)

@@ -107,7 +107,7 @@ def test_pcgs_iterations_on_example2(N):
 
 
 def _wrong_strang_eigenvalues(sign_dplus, sign_dminus):
-    def lam(p, j):
+    def lam(p, j, kind="strang"):
         e, gam, dp, dm = O.level_scalars(p, j)
         lw = O.circulant_eigenvalues(O.strang_column(O.ids_oracle._W_lag(p.beta, p.n), p.n))
         lq = O.circulant_eigenvalues(O.strang_column(O.ids_oracle._Q_lag, p.n))
@@ -164,3 +164,69 @@ def test_adam_alternating_gradient_steps():
     th3, m, v = NO.adam_step(th2, m, v, g, 3, lr, eps=0.0)
     assert np.allclose(th3 - th2, -lr * (0.1 * 0.91 / 0.271) * np.sign(g), rtol=1e-12, atol=0)
     assert math.isclose(0.1 * 0.91 / 0.271, 0.33579335793357934, rel_tol=1e-15)
+
+
+def _optimal_circulant(T):
+    """The circulant nearest to T in the Frobenius norm: its first column
+    averages T over each wrapped diagonal, c_k = mean of T[i, l] with
+    (i - l) mod n = k (the minimisation over the n circulant parameters)."""
+    n = T.shape[0]
+    d = (np.arange(n)[:, None] - np.arange(n)[None, :]) % n
+    col = np.array([T[d == k].mean() for k in range(n)])
+    return col[d]
+
+
+@pytest.mark.parametrize("n", [5, 8, 31, 64])
+def test_tchan_is_the_frobenius_optimal_circulant_of_A(n):
+    """T. Chan's preconditioner is the optimal circulant of A itself (the
+    identity, Q, W and W^T parts each averaged over wrapped diagonals), for
+    odd and even n alike, and it is the Frobenius minimiser: any change of one
+    circulant parameter moves it further from A."""
+    for prob in _problems(n):
+        j = 3
+        A = O.level_A(prob, j)
+        P = O.preconditioner_matrix(prob, j, "tchan")
+        C = _optimal_circulant(A)
+        assert np.max(np.abs(P - C)) <= 1e-13 * np.max(np.abs(A))
+        d = (np.arange(n)[:, None] - np.arange(n)[None, :]) % n
+        base = np.linalg.norm(P - A)
+        for k in (0, 1, n - 1):
+            bumped = P + 1e-3 * np.max(np.abs(A)) * (d == k)
+            assert np.linalg.norm(bumped - A) > base
+
+
+@pytest.mark.parametrize("n", [7, 64])
+def test_tchan_eigenvalues_and_theorem_3_1(n):
+    """The FFT eigenvalues of the T. Chan preconditioner are those of its
+    dense matrix, and their real parts are positive (the argument of
+    Theorem 3.1 carries over: c(Q) is skew, c(W) + c(W)^T is negative
+    semidefinite for D_+- >= 0)."""
+    prob = W.Problem(alpha=0.6, beta=1.7, n=n, M=4, gamma=lambda t: -3.0 + t, dplus=lambda t: 2.0 * t,
+                     dminus=lambda t: 0.7 + t)
+    for j in range(prob.M):
+        lam = O.strang_eigenvalues(prob, j, "tchan")
+        dense = np.linalg.eigvals(O.preconditioner_matrix(prob, j, "tchan"))
+        tol = 1e-9 * np.abs(lam).max()
+        assert np.max(np.min(np.abs(lam[:, None] - dense[None, :]), axis=1)) <= tol
+        assert np.max(np.min(np.abs(dense[:, None] - lam[None, :]), axis=1)) <= tol
+        assert np.min(lam.real) > 0
+
+
+@pytest.mark.parametrize("kind", ["strang", "tchan"])
+@pytest.mark.parametrize("n", [63, 64, 255])
+def test_pbicgstab_reaches_the_lu_solution(kind, n):
+    """BiCGSTAB with either circulant preconditioner converges, in a handful
+    of iterations, to the dense-LU solution of the level (brute force)."""
+    prob = W.config_large(n=n, M=8, alpha=0.6, beta=1.7)
+    rng = np.random.default_rng(n)
+    U = rng.standard_normal((prob.M + 1, n))
+    f = rng.standard_normal(n)
+    for j in (0, 5):
+        A = O.level_A(prob, j)
+        ref = O.level_solve(prob, U, j, f)
+        u, its = O.level_solve_pbicgstab(prob, U, j, f, rtol=1e-13, kind=kind)
+        bound = max(1e-10, 8 * 2.2e-16 * np.linalg.cond(A, 1))
+        assert np.linalg.norm(u - ref) <= bound * np.linalg.norm(ref), (j, its)
+        assert its <= 30
+        u2, its2 = O.level_solve_pcgs(prob, U, j, f, rtol=1e-13, kind=kind)
+        assert np.linalg.norm(u2 - ref) <= bound * np.linalg.norm(ref), (j, its2)

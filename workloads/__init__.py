@@ -16,6 +16,7 @@ from .problems import (  # noqa: F401
     example2,
     config_small,
     config_large,
+    config_large_constant,
     batched_instances,
     warmstart_instances,
     HELD_OUT,

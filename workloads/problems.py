@@ -242,6 +242,21 @@ def config_large(n: int = 1 << 20, M: int = 512, alpha: float = 0.7, beta: float
                    meta={"amplitudes": amps.tolist(), "seed": seed})
 
 
+def config_large_constant(n: int = 1 << 20, M: int = 512, alpha: float = 0.7, beta: float = 1.8,
+                          seed: int = SEED_BASE + 1) -> Problem:
+    """The large single-instance case with Example 1's constant coefficients
+    (gamma = -0.1, d_+ = 0.8, d_- = 0.5) in place of the time-dependent ones,
+    the same seeded solution family: the workload of the constant-coefficient
+    path (Algorithm 3)."""
+    rng = np.random.default_rng(seed)
+    amps = rng.uniform(0.5, 2.0, size=3)
+    sol = ManufacturedSolution([(1.0, 2.0)], _x2_one_minus_x2(amps))
+    return Problem(alpha=alpha, beta=beta, n=n, M=M,
+                   gamma=lambda t: -0.1, dplus=lambda t: 0.8, dminus=lambda t: 0.5, solution=sol,
+                   name=f"large_constant(n={n},M={M},alpha={alpha},beta={beta})",
+                   meta={"amplitudes": amps.tolist(), "seed": seed})
+
+
 def batched_instances(count: int = 512, M: int = 128, nmin: int = 1 << 10, nmax: int = 1 << 16,
                       seed: int = SEED_BASE + 3):
     """Independent instances of uneven size: n = round(exp(U(ln nmin, ln nmax))),
