@@ -144,7 +144,31 @@ def forms(args, P, W, prob, F, u0, levels, plain_value, dev):
         res["krylov"] = krylov_forms(args, P, prob, F, u0, levels, plain_value)
     if args.form in ("all", "gsf"):
         res["constant_gsf"] = gsf_form(args, P, W, dev)
+    if args.form in ("all", "history"):
+        res["fast_history"] = history_form(args, P, prob, F, u0, levels, plain_value)
     return res
+
+
+def history_form(args, P, prob, F, u0, levels, plain_value):
+    """The headline march with the fast history (the L2-1sigma weights as a
+    fitted sum of exponentials, tolerance 1e-12) beside the exact one; the
+    largest per-level difference between the two marches is reported."""
+    import numpy as np
+    import torch
+    out = {"workload": "headline", "history_tol": 1e-12}
+    Us = {}
+    for name, ht in (("exact", 0.0), ("fast", 1e-12)):
+        with P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, history_tol=ht) as sh:
+            timed_march(sh, F, u0, min(levels, 16), torch)  # warm-up
+            dt, st = timed_march(sh, F, u0, levels, torch)
+            Us[name] = sh.history()[: levels + 1].clone()
+        out[name] = {"value": levels / dt, "unit": "level-solves/s", "acceptance": acceptance(st)}
+        log(f"history {name}: {levels / dt:.1f} level-solves/s")
+    d = (Us["fast"] - Us["exact"]).norm(dim=1) / Us["exact"].norm(dim=1).clamp_min(1e-300)
+    out["max_level_rel_diff"] = float(d.max())
+    out["speedup_vs_exact"] = out["fast"]["value"] / out["exact"]["value"]
+    del Us
+    return out
 
 
 def krylov_forms(args, P, prob, F, u0, levels, plain_value):
@@ -265,6 +289,8 @@ def batched_form(args, P, W, dev):
             its, allst = [], []
             for j in range(args.batch_M):
                 code, st = bs.step([Fi[j] for Fi in Fall], raise_on_error=False)
+                if code in (P.TSFCDE_EDEVICE, P.TSFCDE_EINVAL, P.TSFCDE_ENOMEM):
+                    raise RuntimeError(f"batched form ({key}): tsfcde_batch_step returned {code}")
                 for x in st:
                     x["code"] = x["status"]
                 allst += st
@@ -419,7 +445,7 @@ def main():
     ap.add_argument("--profile-period", type=int, default=7,
                     help="events on every k-th launch of the profiled class (1 = all)")
     ap.add_argument("--fp32-n", type=int, default=2048, help="grid of the FP32-refined form inside its envelope")
-    ap.add_argument("--form", default="all", choices=["all", "warm", "fp32", "batched", "learned", "krylov", "gsf"],
+    ap.add_argument("--form", default="all", choices=["all", "warm", "fp32", "batched", "learned", "krylov", "gsf", "history"],
                     help="which of the other forms to run (for profiling one of them)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-M", type=int, default=128)
@@ -595,6 +621,10 @@ def large_leg(args, P, W, dev, n=1 << 24, M=8):
            "level_solves_per_s": M / dt, "cgs_iterations_mean": float(np.mean(iters)),
            "path_frac_lower_bound": (path_bytes(n, M, M, iters)) / dt / 1e9 / 8000.0,
            "cgs_iteration_bytes": cgs_bytes, "acceptance": acceptance(st)}
+    traffic = committed_traffic("mid_matvec", n)
+    out["traffic"] = traffic["bytes_per_launch"] if traffic else None
+    if traffic:
+        out["traffic_source"] = traffic["source"]
     log(f"n=2^24 leg: mid_matvec {achieved:.0f} GB/s ({out['frac']:.3f}), {M / dt:.1f} level-solves/s")
     del F
     return out

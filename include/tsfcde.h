@@ -202,6 +202,19 @@ typedef struct tsfcde_problem {
                                TSFCDE_KRYLOV_BICGSTAB                        */
     int32_t preconditioner; /* TSFCDE_PREC_STRANG (0, (3.7)) or
                                TSFCDE_PREC_TCHAN                             */
+    double history_tol;     /* 0: the history sum of (3.3) over all earlier
+                               levels exactly (Lemma 1's weights).  In
+                               (0, 1e-2]: the fast history -- the weights c_m,
+                               m >= 2, replaced by a sum of exponentials plus
+                               a cubic in m, fitted at plan time to relative
+                               error <= history_tol for every m the march
+                               uses (TSFCDE_EUNSUPPORTED if the fit cannot),
+                               so that each level costs K + 4 vector
+                               recursions (K ~ 30-90) instead of a sum over
+                               j levels; the result then differs from the
+                               exact scheme by at most kappa history_tol
+                               sum_m c_m |u^{j-m+1} - u^{j-m}| per level in
+                               the history term.  Single plans only.       */
 } tsfcde_problem;
 
 typedef struct tsfcde_stats {
@@ -310,6 +323,18 @@ double tsfcde_level_time(tsfcde_plan_t plan, int64_t j);
 /* The plan's interior nodes x_i = a + i h, i = 1..n, h = (b-a)/(n+1)
  * (Sec. 2.1), into the host array h_x of n doubles. */
 int tsfcde_nodes(tsfcde_plan_t plan, double *h_x);
+
+/* The fast history's fit (host only, no device work): for time order alpha,
+ * M levels and relative tolerance tol, *terms = K exponentials rho_k (ratios)
+ * with weights w_k and the cubic's coefficients poly[0..3], such that
+ * c_m ~ sum_k w_k rho_k^m + sum_p poly[p] m^p for 2 <= m <= M-2 (the weights
+ * of Lemma 1); *max_rel_err is the largest relative error met over those m
+ * (against c_m from its integral form by Gauss-Legendre quadrature).  rho
+ * and w (nullable) are written when K <= capacity.  Returns TSFCDE_OK when
+ * the error is within tol, TSFCDE_EUNSUPPORTED otherwise, TSFCDE_EINVAL for
+ * alpha outside (0, 1], M < 1 or tol <= 0. */
+int tsfcde_history_soe_fit(double alpha, int64_t M, double tol, int32_t capacity, int32_t *terms, double *rho,
+                           double *w, double *poly, double *max_rel_err);
 
 /* Length L of the circulant embedding used for the Toeplitz products. */
 int64_t tsfcde_embedding_length(tsfcde_plan_t plan);

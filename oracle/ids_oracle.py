@@ -57,7 +57,7 @@ __all__ = [
     "strang_column", "circulant", "preconditioner_matrix", "circulant_eigenvalues",
     "embedding_column", "apply_A_rows", "apply_P_rows", "rhs_rows", "caputo_l21s",
     "embedding_eigenvalues", "embedding_product", "strang_eigenvalues", "strang_solve", "rhs_fft",
-    "level_solve_pcgs", "level_solve_pbicgstab", "tchan_column", "coefficients_constant", "gsf_generators", "gsf_matrices", "gsf_apply", "march_gsf",
+    "level_solve_pcgs", "level_solve_pbicgstab", "tchan_column", "coefficients_constant", "history_perturbation_bound", "gsf_generators", "gsf_matrices", "gsf_apply", "march_gsf",
 ]
 
 
@@ -655,3 +655,18 @@ def march_gsf(prob, f_levels: Optional[Iterable[np.ndarray]] = None) -> np.ndarr
         else:
             U[j + 1] = gsf_apply(x, y, rhs(prob, U, j, f_j))
     return U
+
+
+def history_perturbation_bound(prob, U: np.ndarray, j: int, rel_tol: float) -> np.ndarray:
+    """Elementwise bound on how far a history term whose weights c_m
+    (2 <= m <= j-1) each carry a relative error of at most rel_tol can move
+    from the exact one of (3.3):  kappa rel_tol sum_{m=2}^{j-1} c_m |u^{j-m+1} - u^{j-m}|
+    (the weights of Lemma 1 are positive).  Zero for j <= 2."""
+    n = U.shape[1]
+    acc = np.zeros(n)
+    if j <= 2:
+        return acc
+    c = l21s_c(prob.alpha, j)
+    for m in range(2, j):
+        acc += abs(c[m]) * np.abs(U[j - m + 1] - U[j - m])
+    return l21s_kappa(prob.alpha, time_step(prob)) * rel_tol * acc

@@ -56,6 +56,7 @@ class tsfcde_problem(ctypes.Structure):
         ("phi", IC_FN), ("phi_user", c_void_p),
         ("rtol", c_double), ("maxit", c_int32), ("precision", c_int32), ("warm_start", c_int32),
         ("flags", c_int32), ("f", SRC_FN), ("f_user", c_void_p), ("krylov", c_int32), ("preconditioner", c_int32),
+        ("history_tol", c_double),
     ]
 
 
@@ -93,6 +94,8 @@ _SIGS = {
     "tsfcde_embedding_length": (c_int64, [c_void_p]),
     "tsfcde_level_time": (c_double, [c_void_p, c_int64]),
     "tsfcde_nodes": (c_int32, [c_void_p, POINTER(c_double)]),
+    "tsfcde_history_soe_fit": (c_int32, [c_double, c_int64, c_double, c_int32, POINTER(c_int32), c_void_p, c_void_p,
+                                         c_void_p, POINTER(c_double)]),
     "tsfcde_profile": (c_int32, [c_void_p, c_int32, c_int32]),
     "tsfcde_profile_read": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
     "tsfcde_profile_issued": (c_int32, [c_void_p, c_int32, POINTER(c_int64)]),

@@ -595,6 +595,41 @@ __global__ void __launch_bounds__(256) k_bicg_final(const double *partials, int 
     }
 }
 
+// Fast history (the L2-1sigma weights c_m, m >= 2, as sum_k w_k rho_k^m +
+// sum_p C_p m^p).  At level L >= 2 (write_p):
+//   P_L = kappa [sum_k w_k S_k + sum_p C_p T_p + c_L^(L) (u^1 - u^0) - c_1 u^{L-1}]
+// with S_k = sum_{m=2}^{L-1} rho_k^m delta_{L-m}, T_p = sum_{m=2}^{L-1} m^p delta_{L-m},
+// delta_s = u^{s+1} - u^s; then (advance) the recursions move to level L+1:
+//   S_k <- rho_k (S_k + rho_k delta_{L-1}),  T_p <- 2^p delta_{L-1} + sum_{q<=p} C(p,q) T_q.
+// S holds K + 4 rows of ld values (the K exponentials, then T_0..T_3).
+struct SoePoly {
+    double c[4];
+};
+__global__ void __launch_bounds__(256) k_hist_soe(const double *__restrict__ U, int64_t n, int64_t ld, int L,
+                                                  double *__restrict__ S, int K, const double *__restrict__ rho,
+                                                  const double *__restrict__ w, SoePoly poly, double kappa, double c1,
+                                                  double cL, double *__restrict__ P, int write_p, int advance) {
+    const double *uL = U + (size_t)L * ld, *uLm = U + (size_t)(L - 1) * ld;
+    double *T = S + (size_t)K * ld;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double um = uLm[i], d = uL[i] - um;
+        double t0 = T[i], t1 = T[ld + i], t2 = T[2 * ld + i], t3 = T[3 * ld + i];
+        double acc = poly.c[0] * t0 + poly.c[1] * t1 + poly.c[2] * t2 + poly.c[3] * t3;
+        for (int k = 0; k < K; ++k) {
+            double sk = S[(size_t)k * ld + i];
+            acc = fma(w[k], sk, acc);
+            if (advance) S[(size_t)k * ld + i] = rho[k] * fma(rho[k], d, sk);
+        }
+        if (write_p) P[i] = kappa * (acc + cL * (U[ld + i] - U[i]) - c1 * um);
+        if (advance) {
+            T[3 * ld + i] = 8.0 * d + t0 + 3.0 * t1 + 3.0 * t2 + t3;
+            T[2 * ld + i] = 4.0 * d + t0 + 2.0 * t1 + t2;
+            T[ld + i] = 2.0 * d + t0 + t1;
+            T[i] = d + t0;
+        }
+    }
+}
+
 // Last step of the Gohberg-Semencul product (Algorithm 1): the pass that
 // forms z3 = L0_p z1 stores x = (z4 - z3) / xi_0.
 struct OutGsfCombine {

@@ -95,7 +95,7 @@ bool rt_setup(RT &A, RT &P, RT &B, int64_t n, bool force_general = false) {
 struct Layout {
     size_t off_U, off_vec, off_v32, off_tmp, off_w, off_g0, off_cbase, off_buf, off_bufP, off_specA, off_specP, off_tw, off_tw2A,
         off_tw2P, off_part, off_sc, off_bufB, off_Bhat, off_chirp, off_Ls, off_wv, off_Wt, off_specPj, off_tw2B,
-        off_buf32, off_bufP32, off_specA32, off_specP32, off_specPj32, off_gsf, total;
+        off_buf32, off_bufP32, off_specA32, off_specP32, off_specPj32, off_gsf, off_soe, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -107,7 +107,7 @@ constexpr int NV32 = 9;   // FP32 inner solve: r rt u p q phat vhat uhat d
 int64_t ld_of(int64_t n) { return n + (n & 1); }
 
 Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P, const RT &B, bool p2, bool fp32,
-                  bool gsf = false) {
+                  bool gsf = false, int soe_terms = -1) {
     const int64_t ld = ld_of(n);
     Layout l{};
     size_t o = 0;
@@ -151,6 +151,8 @@ Layout layout_for(int64_t n, int64_t M, const RT &A, const RT &P, const RT &B, b
     // Gohberg-Semencul path: x = A^-1 e_1, y = A^-1 e_n and the spectra of
     // the four triangular factors
     l.off_gsf = take(gsf ? 2 * sizeof(double) * (size_t)ld + 4 * al(sizeof(double2) * (size_t)A.N) : 0);
+    // fast history: K + 4 recursion vectors, then the K weights and K ratios
+    l.off_soe = take(soe_terms >= 0 ? sizeof(double) * ((size_t)(soe_terms + 4) * ld + 2 * (size_t)soe_terms) : 0);
     l.total = o;
     return l;
 }
@@ -171,6 +173,7 @@ int validate(const tsfcde_problem *p) {
     if (!std::isfinite(p->rtol)) return TSFCDE_EINVAL;
     if (p->n < 4 || p->n > (is_pow2(p->n) ? NMAX : NMAX / 2)) return TSFCDE_EUNSUPPORTED;
     if (p->krylov != TSFCDE_KRYLOV_CGS && p->krylov != TSFCDE_KRYLOV_BICGSTAB) return TSFCDE_EINVAL;
+    if (!(p->history_tol >= 0.0 && p->history_tol <= 1e-2)) return TSFCDE_EINVAL;
     if (p->preconditioner != TSFCDE_PREC_STRANG && p->preconditioner != TSFCDE_PREC_TCHAN) return TSFCDE_EINVAL;
     if ((p->flags & TSFCDE_FLAG_CONSTANT_GSF) && p->precision != TSFCDE_FP64) return TSFCDE_EUNSUPPORTED;
     return TSFCDE_OK;
@@ -234,6 +237,13 @@ struct tsfcde_plan_s {
     int krylov = TSFCDE_KRYLOV_CGS;  // Krylov method of the FP64 solves
     int prec = TSFCDE_PREC_STRANG;   // circulant preconditioner
     double qfac = 1.0;  // eigenvalues of the preconditioner's circulant of Q over 2i sin(2 pi k/n)
+    // fast history (history_tol > 0): P_j from K + 4 recursions (soe_fit)
+    bool soe = false;
+    int soe_K = 0;
+    int64_t soe_level = -1;  // the level whose history the recursions hold (-1: none)
+    double *soe_S = nullptr, *soe_rho = nullptr, *soe_w = nullptr;
+    SoePoly soe_poly{{0, 0, 0, 0}};
+    double soe_err = 0.0;
     bool gsf = false, gsf_ready = false;
     double *gx = nullptr, *gy = nullptr;
     double2 *gspec[4] = {nullptr, nullptr, nullptr, nullptr};  // L_p, R_p, L0_p, R0_p
@@ -1001,7 +1011,34 @@ HistBlock hist_block_params(const tsfcde_plan_s *pl, int64_t b) {
 }
 
 // Where the right-hand side of level j >= 1 finds P_j.
-const double *hist_src(const tsfcde_plan_s *pl, int64_t j) { return j == hist_block_of(j) ? pl->Hq : pl->H; }
+const double *hist_src(const tsfcde_plan_s *pl, int64_t j) {
+    if (pl->soe && j >= 2) return pl->H;
+    return j == hist_block_of(j) ? pl->Hq : pl->H;
+}
+
+// Fast history: one pass of k_hist_soe at level L (writing P_L into H when
+// write_p, advancing the recursions to level L + 1).
+hipError_t launch_soe(tsfcde_plan_s *pl, int64_t L, bool write_p) {
+    const int64_t n = pl->n;
+    const unsigned grid = (unsigned)std::min<int64_t>(2048, (n + 255) / 256);
+    const double cL = pl->clast[L], c1 = pl->cbase[1];
+    launch_timed(pl, 0, k_hist_soe, dim3(grid), dim3(256), (const double *)pl->U, n, pl->ldn, (int)L, pl->soe_S,
+                 pl->soe_K, (const double *)pl->soe_rho, (const double *)pl->soe_w, pl->soe_poly, pl->kappa, c1, cL,
+                 pl->H, write_p ? 1 : 0, 1);
+    return hipGetLastError();
+}
+
+// The recursions for level j >= 2 rebuilt from the stored levels (after a
+// resume, or a right-hand side asked out of order): zero, then advanced
+// through levels 2..j-1.
+int soe_rebuild(tsfcde_plan_s *pl, int64_t j) {
+    const size_t cnt = (size_t)(pl->soe_K + 4) * pl->ldn;
+    hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, pl->stream, pl->soe_S, 0.0, (int64_t)cnt);
+    HIPCHK(hipGetLastError());
+    for (int64_t L = 2; L < j; ++L) HIPCHK(launch_soe(pl, L, false));
+    pl->soe_level = j;
+    return TSFCDE_OK;
+}
 
 #ifndef TSF_HIST_SIDE_WG
 #define TSF_HIST_SIDE_WG 256
@@ -1040,6 +1077,14 @@ int history_quiesce(tsfcde_plan_s *pl) {
 // are final), then the catch-up of a level past the block's first.
 int history_for(tsfcde_plan_s *pl, int64_t j) {
     if (j < 1) return TSFCDE_OK;
+    if (pl->soe && j >= 2) {
+        if (pl->soe_level != j) {
+            if (int rc = soe_rebuild(pl, j)) return rc;
+        }
+        HIPCHK(launch_soe(pl, j, true));
+        pl->soe_level = j + 1;
+        return TSFCDE_OK;
+    }
     const int64_t b = hist_block_of(j);
     if (pl->hist_pending) {  // whatever the side stream queued is finished before the buffers are used
         HIPCHK(hipStreamWaitEvent(pl->stream, pl->ev_hist, 0));
@@ -1058,6 +1103,7 @@ int history_for(tsfcde_plan_s *pl, int64_t j) {
 // everything the main stream has queued, including the right-hand side and
 // catch-up that last read the block buffers it overwrites.
 int history_next(tsfcde_plan_s *pl, int64_t j) {
+    if (pl->soe) return TSFCDE_OK;  // no block sweeps: levels from 2 on use the recursions
     const int64_t b = j + 1;
     if (b >= pl->M || hist_block_of(b) != b || pl->hist_block == b) return TSFCDE_OK;
     if (!pl->hs) {
@@ -1394,6 +1440,135 @@ int gsf_apply(tsfcde_plan_s *pl, double *x) {
     return TSFCDE_OK;
 }
 
+// ---- fast history: a sum of exponentials for the L2-1sigma weights --------
+// For m >= 2 the weights c_m = a_m + b_{m+1} - b_m of Lemma 1 are integrals
+// of the kernels x^-alpha and x^-alpha-1 over unit intervals:
+//   a_m = (1-alpha) int_0^1 g(m-1+sigma+t) dt,                  g(x) = x^-alpha,
+//   b_m = alpha(1-alpha)/2 int_0^1 t(1-t) h(m-1+sigma+t) dt,     h(x) = x^-alpha-1
+// (the second is the trapezoid rule's error for x^(1-alpha) on the interval).
+// Each kernel has the integral form x^-b = (1/Gamma(b)) int e^(b y - x e^y) dy;
+// its trapezoid sum with step D on the grid y_k = y0 + k D is spectrally
+// accurate in D.  Grid points with y_k >= y0 give exponentials e^(-s_k x),
+// s_k = e^(y_k); those below y0, where s x <= e^y0 x_max = 1e-3, are summed
+// as a geometric series of the Taylor terms of e^(-s x), a cubic in x.  The
+// t-integrals of exponentials and cubics are closed form, so
+//   c_m ~ sum_k W_k rho_k^m + sum_{p<=3} C_p m^p,   rho_k = e^(-s_k),
+// and the history sum over m = 2..j-1 runs as K + 4 recursions, one vector
+// each, updated once per level.  The fit is checked against c_m for every m
+// the march uses, c_m evaluated from its integral form by Gauss-Legendre
+// quadrature (the closed form's differences of powers lose about m^(2-alpha)
+// ulps to cancellation, more than the fit's tolerance at large m).
+struct SoeFit {
+    std::vector<double> rho, w;  // exponentials
+    double poly[4] = {0, 0, 0, 0};  // cubic in m
+    double max_rel_err = 0.0;
+};
+
+// int_0^1 e^{-s t} dt and int_0^1 t (1-t) e^{-s t} dt, stable for small s.
+double int_e(double s) { return s < 1e-4 ? 1.0 - s / 2 + s * s / 6 : -std::expm1(-s) / s; }
+double int_tt_e(double s) {
+    if (s < 1e-2) return 1.0 / 6 - s / 12 + s * s / 40 - s * s * s / 180;
+    return ((s - 2.0) + (s + 2.0) * std::exp(-s)) / (s * s * s);
+}
+
+// c_m of Lemma 1 for m >= 2 from the integral forms above by 24-point
+// Gauss-Legendre quadrature on [0, 1] (smooth integrands), free of the
+// cancellation the closed form's differences of powers suffer at large m:
+// c_m = (1-alpha) int_0^1 g(m-1+sg+t) dt
+//       + alpha(1-alpha)/2 int_0^1 t(1-t) [h(m+sg+t) - h(m-1+sg+t)] dt.
+struct GaussLegendre {
+    double x[24], w[24];
+    GaussLegendre() {
+        const int n = 24;
+        for (int i = 0; i < n; ++i) {  // Newton on P_n from the Chebyshev guess
+            double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), pp = 1.0;
+            for (int it = 0; it < 100; ++it) {
+                double p1 = 1.0, p2 = 0.0;
+                for (int k = 1; k <= n; ++k) {
+                    const double p3 = p2;
+                    p2 = p1;
+                    p1 = ((2.0 * k - 1.0) * z * p2 - (k - 1.0) * p3) / k;
+                }
+                pp = n * (z * p1 - p2) / (z * z - 1.0);
+                const double dz = p1 / pp;
+                z -= dz;
+                if (std::fabs(dz) < 1e-16) break;
+            }
+            x[i] = 0.5 * (1.0 - z);
+            w[i] = 1.0 / ((1.0 - z * z) * pp * pp);  // 2/((1-z^2)P'^2), halved for [0, 1]
+        }
+    }
+};
+
+double l21s_cbase_accurate(double al, double sg, int64_t m) {
+    static const GaussLegendre gl;
+    double a = 0.0, db = 0.0;
+    for (int q = 0; q < 24; ++q) {
+        const double t = gl.x[q], x0 = (double)m - 1.0 + sg + t;
+        a += gl.w[q] * std::pow(x0, -al);
+        // h(x0 + 1) - h(x0) = x0^-(al+1) ((1 + 1/x0)^-(al+1) - 1), the bracket by expm1/log1p
+        db += gl.w[q] * t * (1.0 - t) * std::pow(x0, -al - 1.0) * std::expm1(-(al + 1.0) * std::log1p(1.0 / x0));
+    }
+    return (1.0 - al) * a + al * (1.0 - al) / 2.0 * db;
+}
+
+int soe_fit(double al, int64_t M, double tol, SoeFit &fit) {
+    const double sg = 1.0 - al / 2.0;
+    if (M < 4) return TSFCDE_OK;  // no m in 2..M-2 ever used: nothing to fit
+    const double xmin = 1.0 + sg, xmax = (double)M + sg;
+    // the trapezoid sum's relative error is about 4 e^(-pi^2 / D)
+    const double D = std::min(0.6, M_PI * M_PI / std::log(40.0 / tol));
+    const double y0 = std::log(1e-3 / xmax), y1 = std::log(40.0 / xmin);
+    const double ga = std::tgamma(al), gh = std::tgamma(al + 1.0);
+    const double k1 = 1.0 - al, k2 = al * (1.0 - al) / 2.0;
+    fit.rho.clear();
+    fit.w.clear();
+    for (double y = y0; y <= y1 + 1e-12; y += D) {
+        const double sk = std::exp(y);
+        const double pg = D * std::exp(al * y) / ga, ph = D * std::exp((al + 1.0) * y) / gh;
+        // a_m: k1 pg e^{-s(m-1+sg)} int_e(s); b_{m+1} - b_m: k2 ph int_tt_e(s) e^{-s(m-1+sg)} (e^{-s} - 1)
+        const double base = std::exp(-sk * (sg - 1.0));
+        const double wk = base * (k1 * pg * int_e(sk) + k2 * ph * int_tt_e(sk) * std::expm1(-sk));
+        fit.rho.push_back(std::exp(-sk));
+        fit.w.push_back(wk);
+    }
+    // tails below y0: x^-b ~ sum_p tau_p x^p, tau_p = (-1)^p/p! D sum_{k<0} e^{(b+p) y_k} / Gamma(b)
+    auto tail = [&](double b, double gb, int p) {
+        const double fact[4] = {1, 1, 2, 6};
+        const double geo = std::exp((b + p) * (y0 - D)) / (-std::expm1(-(b + p) * D));
+        return ((p & 1) ? -1.0 : 1.0) / fact[p] * D * geo / gb;
+    };
+    // the cubic part of c_m: each tail sum_p tau_p x^p at x = m + c(t),
+    // expanded in powers of m (binomially) and integrated over t by 3-point
+    // Gauss-Legendre (exact for the degree-5 integrands); the coefficients come
+    // out directly, with no extrapolation from small m
+    const double gx[3] = {0.5 - 0.5 * std::sqrt(0.6), 0.5, 0.5 + 0.5 * std::sqrt(0.6)};
+    const double gw[3] = {5.0 / 18, 8.0 / 18, 5.0 / 18};
+    const double binom[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
+    for (int p = 0; p < 4; ++p) {
+        const double tg = tail(al, ga, p), th = tail(al + 1.0, gh, p);
+        for (int q = 0; q <= p; ++q) {
+            double acc = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                const double t = gx[i], c0 = sg - 1.0 + t, c1 = sg + t;
+                const double e = (double)(p - q);
+                acc += gw[i] * (k1 * tg * std::pow(c0, e) + k2 * th * t * (1.0 - t) * (std::pow(c1, e) - std::pow(c0, e)));
+            }
+            fit.poly[q] += binom[p][q] * acc;
+        }
+    }
+    // check against the exact weights for every m the recursion serves
+    double worst = 0.0;
+    for (int64_t m = 2; m <= M - 2; ++m) {
+        double v = fit.poly[0] + m * (fit.poly[1] + m * (fit.poly[2] + m * fit.poly[3]));
+        for (size_t k = 0; k < fit.rho.size(); ++k) v += fit.w[k] * std::pow(fit.rho[k], (double)m);
+        const double c = l21s_cbase_accurate(al, sg, m);
+        worst = std::max(worst, std::fabs(v - c) / std::fabs(c));
+    }
+    fit.max_rel_err = worst;
+    return worst <= tol ? TSFCDE_OK : TSFCDE_EUNSUPPORTED;
+}
+
 // eta_j = kappa c_0^(j): kappa a_0 at level 0, kappa (a_0 + b_1) after
 // (Lemma 1; the diagonal of A and B in (3.3)).
 double eta_level(double alpha, double sigma, double kappa, int64_t j) {
@@ -1575,6 +1750,11 @@ void bind_workspace(tsfcde_plan_s *pl, char *ws) {
         pl->specP32 = reinterpret_cast<float2 *>(ws + L.off_specP32);
         pl->specPj32 = reinterpret_cast<float2 *>(ws + L.off_specPj32);
     }
+    if (pl->soe) {
+        pl->soe_S = reinterpret_cast<double *>(ws + L.off_soe);
+        pl->soe_rho = pl->soe_S + (size_t)(pl->soe_K + 4) * pl->ldn;
+        pl->soe_w = pl->soe_rho + pl->soe_K;
+    }
     if (pl->gsf) {
         char *g = ws + L.off_gsf;
         pl->gx = reinterpret_cast<double *>(g);
@@ -1654,8 +1834,14 @@ static int workspace_bytes_impl(const tsfcde_problem *prob, bool force_general, 
     RT A, P, B;
     const bool p2 = rt_setup(A, P, B, prob->n, force_general);
     if (!partials_fit(A)) return TSFCDE_EUNSUPPORTED;
+    int soe_terms = -1;
+    if (prob->history_tol > 0.0) {
+        SoeFit fit;
+        if ((rc = soe_fit(prob->alpha, prob->M, prob->history_tol, fit))) return rc;
+        soe_terms = (int)fit.rho.size();
+    }
     *bytes = layout_for(prob->n, prob->M, A, P, B, p2, prob->precision == TSFCDE_FP32_REFINED,
-                        (prob->flags & TSFCDE_FLAG_CONSTANT_GSF) != 0)
+                        (prob->flags & TSFCDE_FLAG_CONSTANT_GSF) != 0, soe_terms)
                  .total;
     return TSFCDE_OK;
 }
@@ -1762,7 +1948,18 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
                 return TSFCDE_EINVAL;
             }
     }
-    pl->lay = layout_for(n, M, pl->A, pl->P, pl->B, pl->p2, pl->fp32, pl->gsf);
+    SoeFit fit;
+    if (prob->history_tol > 0.0) {
+        if ((rc = soe_fit(prob->alpha, M, prob->history_tol, fit))) {
+            delete pl;
+            return rc;
+        }
+        pl->soe = true;
+        pl->soe_K = (int)fit.rho.size();
+        for (int p = 0; p < 4; ++p) pl->soe_poly.c[p] = fit.poly[p];
+        pl->soe_err = fit.max_rel_err;
+    }
+    pl->lay = layout_for(n, M, pl->A, pl->P, pl->B, pl->p2, pl->fp32, pl->gsf, pl->soe ? pl->soe_K : -1);
     if (pl->fp32) {
         // |A| / eta <= 1 + sigma (|gamma|/h + (d+ + d-) h^-beta 2|omega_1|) / eta  (Remark 3.1, eig(Q))
         const double b = prob->beta;
@@ -1803,6 +2000,13 @@ static int plan_create(const tsfcde_problem *prob, void *d_workspace, size_t byt
         hipSuccess)
         return fail(TSFCDE_EDEVICE);
     if (setup_spectra(pl, prob->beta) != hipSuccess) return fail(TSFCDE_EDEVICE);
+    if (pl->soe && pl->soe_K > 0) {
+        if (hipMemcpyAsync(pl->soe_rho, fit.rho.data(), sizeof(double) * pl->soe_K, hipMemcpyHostToDevice,
+                           pl->stream) != hipSuccess ||
+            hipMemcpyAsync(pl->soe_w, fit.w.data(), sizeof(double) * pl->soe_K, hipMemcpyHostToDevice, pl->stream) !=
+                hipSuccess)
+            return fail(TSFCDE_EDEVICE);
+    }
     // FP32 copies of the spectra for the inner solve of the FP32-refined form
     if (pl->fp32) {
         hipLaunchKernelGGL(k_to_f32, dim3(512), dim3(256), 0, pl->stream, pl->specA, pl->specA32, pl->A.N);
@@ -1835,6 +2039,7 @@ int tsfcde_set_state(tsfcde_plan_t pl, int64_t level, const double *d_U) {
     HIPCHK(hipMemcpy2DAsync(pl->U, sizeof(double) * pl->ldn, d_U, sizeof(double) * pl->n, sizeof(double) * pl->n,
                             (size_t)(level + 1), hipMemcpyDeviceToDevice, pl->stream));
     pl->level = level;
+    pl->soe_level = -1;  // the recursions no longer match the stored levels
     return TSFCDE_OK;
 }
 
@@ -1935,6 +2140,24 @@ const double *tsfcde_history(tsfcde_plan_t pl) { return pl ? pl->U : nullptr; }
 int64_t tsfcde_history_ld(tsfcde_plan_t pl) { return pl ? pl->ldn : -1; }
 
 int64_t tsfcde_embedding_length(tsfcde_plan_t pl) { return pl ? pl->A.L : -1; }
+
+int tsfcde_history_soe_fit(double alpha, int64_t M, double tol, int32_t capacity, int32_t *terms, double *rho,
+                           double *w, double *poly, double *max_rel_err) {
+    if (!(alpha > 0.0 && alpha <= 1.0) || M < 1 || !(tol > 0.0) || capacity < 0) return TSFCDE_EINVAL;
+    SoeFit fit;
+    const int rc = soe_fit(alpha, M, tol, fit);
+    if (terms) *terms = (int32_t)fit.rho.size();
+    if (max_rel_err) *max_rel_err = fit.max_rel_err;
+    if ((int)fit.rho.size() <= capacity) {
+        for (size_t k = 0; k < fit.rho.size(); ++k) {
+            if (rho) rho[k] = fit.rho[k];
+            if (w) w[k] = fit.w[k];
+        }
+    }
+    if (poly)
+        for (int p = 0; p < 4; ++p) poly[p] = fit.poly[p];
+    return rc;
+}
 
 double tsfcde_level_time(tsfcde_plan_t pl, int64_t j) {
     if (!pl || j < 0 || j >= pl->M) return std::nan("");
@@ -2215,6 +2438,7 @@ struct tsfcde_batch_s {
     bool fold = true;  // finishing steps folded into later passes (TSFCDE_FLAG_NO_FOLD clears it)
     bool strict = false;  // TSFCDE_FLAG_STRICT_RESIDUAL: accept only at a true residual within rtol |g|
     bool graphs = false;  // TSFCDE_FLAG_GRAPHS: CGS chunks replayed from captured HIP graphs
+    hipStream_t cap_stream = nullptr;  // private stream the chunk graphs are captured on
     std::map<int, ChunkGraph> chunk_graphs;  // by chunk length
 };
 
@@ -2507,7 +2731,8 @@ hipError_t issue_chunk(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, int
 // descriptors and the device scalars, never from their launch arguments, so
 // one capture serves every level while the descriptors sit at the same
 // addresses (checked; a change recaptures).  Kernels only: no memset or copy
-// nodes.
+// nodes.  The capture runs on a private stream (the batch's own may be the
+// null stream, which cannot capture); the graph is launched on the batch's.
 int chunk_graph(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, int todo, hipGraphExec_t *out) {
     const void *key = gd.empty() ? nullptr : (const void *)gd[0].s1[0];
     auto it = bt->chunk_graphs.find(todo);
@@ -2519,12 +2744,17 @@ int chunk_graph(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, int todo, 
         (void)hipGraphExecDestroy(it->second.exec);
         bt->chunk_graphs.erase(it);
     }
+    if (!bt->cap_stream) BCHK(hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
-    BCHK(hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal));
+    BCHK(hipStreamBeginCapture(bt->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipStream_t own = bt->stream;
+    bt->stream = bt->cap_stream;  // issue_chunk launches on bt->stream
     const hipError_t e = issue_chunk(bt, gd, todo);
-    const hipError_t ec = hipStreamEndCapture(bt->stream, &graph);
+    bt->stream = own;
+    const hipError_t ec = hipStreamEndCapture(bt->cap_stream, &graph);
     if (e != hipSuccess || ec != hipSuccess || !graph) {
         if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();  // leave no sticky error behind
         return TSFCDE_EDEVICE;
     }
     hipGraphExec_t ex = nullptr;
@@ -2868,6 +3098,7 @@ int tsfcde_batch_workspace_bytes(const tsfcde_problem *probs, int32_t count, siz
         if (probs[i].precision != TSFCDE_FP64) return TSFCDE_EUNSUPPORTED;  // the batch runs the FP64 form
         if (probs[i].flags & TSFCDE_FLAG_CONSTANT_GSF) return TSFCDE_EUNSUPPORTED;  // single plans only
         if (probs[i].krylov != TSFCDE_KRYLOV_CGS) return TSFCDE_EUNSUPPORTED;       // the batch runs CGS
+        if (probs[i].history_tol > 0.0) return TSFCDE_EUNSUPPORTED;                // exact history only
         if (probs[i].M != probs[0].M) return TSFCDE_EINVAL;
         tot += al(b);
     }
@@ -2990,6 +3221,7 @@ int tsfcde_batch_destroy(tsfcde_batch_t bt) {
     if (!bt) return TSFCDE_EINVAL;
     (void)hipStreamSynchronize(bt->stream);
     for (auto &kv : bt->chunk_graphs) (void)hipGraphExecDestroy(kv.second.exec);
+    if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
     for (tsfcde_plan_s *pl : bt->plans) tsfcde_destroy(pl);
     if (bt->st.host) (void)hipHostFree(bt->st.host);
     if (bt->h_done) (void)hipHostFree(bt->h_done);

@@ -46,7 +46,8 @@ def _coef_fields(gamma, dplus, dminus, keep: list):
 
 
 def _problem(*, alpha, beta, n, M, a, b, T, gamma, dplus, dminus, phi, f, rtol, maxit, precision, warm_start,
-             flags, keep: list, krylov=N.TSFCDE_KRYLOV_CGS, preconditioner=N.TSFCDE_PREC_STRANG):
+             flags, keep: list, krylov=N.TSFCDE_KRYLOV_CGS, preconditioner=N.TSFCDE_PREC_STRANG,
+             history_tol=0.0):
     """A tsfcde_problem; the Python callables and arrays it points to are
     appended to ``keep`` (they must outlive every library call that uses it)."""
     fields = _coef_fields(gamma, dplus, dminus, keep)
@@ -63,7 +64,7 @@ def _problem(*, alpha, beta, n, M, a, b, T, gamma, dplus, dminus, phi, f, rtol, 
     return N.tsfcde_problem(
         alpha=alpha, beta=beta, a=a, b=b, T=T, n=int(n), M=int(M), coef_user=None, phi=phi_cb, phi_user=None,
         rtol=rtol, maxit=maxit, precision=precision, warm_start=warm_start, flags=flags, f=f_cb, f_user=None,
-        krylov=krylov, preconditioner=preconditioner, **fields)
+        krylov=krylov, preconditioner=preconditioner, history_tol=history_tol, **fields)
 
 
 def _scalar_phi(prob):
@@ -89,6 +90,7 @@ class TimeLevelSolver:
                  a: float = 0.0, b: float = 1.0, T: float = 1.0, rtol: float = 1e-10, maxit: int = 500,
                  warm_start: int = N.TSFCDE_WS_ZERO, flags: int = 0, precision: int = N.TSFCDE_FP64,
                  krylov: int = N.TSFCDE_KRYLOV_CGS, preconditioner: int = N.TSFCDE_PREC_STRANG,
+                 history_tol: float = 0.0,
                  device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
         self._lib = N.lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -101,7 +103,7 @@ class TimeLevelSolver:
         self.problem = _problem(alpha=alpha, beta=beta, n=n, M=M, a=a, b=b, T=T, gamma=gamma, dplus=dplus,
                                 dminus=dminus, phi=phi, f=f, rtol=rtol, maxit=maxit, precision=precision,
                                 warm_start=warm_start, flags=flags, keep=self._keep, krylov=krylov,
-                                preconditioner=preconditioner)
+                                preconditioner=preconditioner, history_tol=history_tol)
         nbytes = ctypes.c_size_t(0)
         N.check(self._lib.tsfcde_workspace_bytes(ctypes.byref(self.problem), ctypes.byref(nbytes)),
                 "tsfcde_workspace_bytes")

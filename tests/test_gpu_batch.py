@@ -29,7 +29,8 @@ def test_batch_matches_single_and_oracle(warm):
     banner(f"batch vs single, warm={warm}")
     probs = _instances(12, 6, 40, 3000, seed=11)
     assert len({p.n for p in probs}) > 6
-    with P.BatchSolver(probs, rtol=1e-13, warm_start=warm) as bs:
+    # the default values per lane (the single plans' own) for the bitwise check
+    with P.BatchSolver(probs, rtol=1e-13, warm_start=warm, flags=P.TSFCDE_FLAG_NO_TUNE) as bs:
         Fs = batch_sources(bs, probs)
         for j in range(probs[0].M):
             code, stats = bs.step([F[j] for F in Fs])
@@ -133,3 +134,32 @@ def test_batch_graph_replay_is_bitwise_direct(warm):
     assert runs[0][1] == runs[1][1]
     for a, b in zip(runs[0][0], runs[1][0]):
         assert np.array_equal(a, b)
+
+
+def test_autotuned_batch_matches_oracle():
+    """The autotuner picks 4 or 8 values per lane for each group's middle
+    passes (TSFCDE_FLAG_NO_TUNE keeps 8 everywhere); the tuned batch matches
+    the oracle to 1e-10 per level and the untuned one to FFT rounding."""
+    import paper_1603_00279_amd as P
+    banner("batch autotuner")
+    probs = _instances(10, 5, 500, 6000, seed=41)
+    runs = {}
+    for flags in (0, P.TSFCDE_FLAG_NO_TUNE):
+        with P.BatchSolver(probs, rtol=1e-13, flags=flags) as bs:
+            groups = bs.groups()
+            Fs = batch_sources(bs, probs)
+            for j in range(probs[0].M):
+                code, stats = bs.step([F[j] for F in Fs])
+                assert code == 0, stats
+            runs[flags] = ([host(bs.history(i)) for i in range(len(probs))], groups)
+    print(f"[autotuner] groups (L, members, values per lane): {runs[0][1]}", flush=True)
+    assert sum(m for _, m, _ in runs[0][1]) == len(probs)
+    assert all(e in (4, 8) for _, _, e in runs[0][1])
+    assert all(e == 8 for _, _, e in runs[P.TSFCDE_FLAG_NO_TUNE][1])
+    for i, prob in enumerate(probs):
+        Uref = O.march(prob)
+        for j in range(1, prob.M + 1):
+            # 1e-10, or the forward error a backward-stable solve can promise
+            bound = max(1e-10, 8 * 2.2e-16 * np.linalg.cond(O.level_A(prob, j - 1), 1))
+            assert relerr(runs[0][0][i][j], Uref[j]) < bound, (i, prob.n, j, bound)
+            assert relerr(runs[0][0][i][j], runs[P.TSFCDE_FLAG_NO_TUNE][0][i][j]) < bound, (i, j)

@@ -94,7 +94,7 @@ def test_batch_tchan_equals_single_plans():
     import paper_1603_00279_amd as P
     banner("batch tchan")
     probs = W.batched_instances(count=5, M=5, nmin=50, nmax=1500, seed=17)
-    with P.BatchSolver(probs, rtol=1e-13, preconditioner=P.TSFCDE_PREC_TCHAN) as bs:
+    with P.BatchSolver(probs, rtol=1e-13, preconditioner=P.TSFCDE_PREC_TCHAN, flags=P.TSFCDE_FLAG_NO_TUNE) as bs:
         Fs = batch_sources(bs, probs)
         for j in range(probs[0].M):
             code, stats = bs.step([F[j] for F in Fs])
