@@ -364,6 +364,28 @@ int tsfcde_profile_issued(tsfcde_plan_t plan, int32_t kernel_class, int64_t *iss
 /* Release the plan (host state only; the caller frees the workspace). */
 int tsfcde_destroy(tsfcde_plan_t plan);
 
+/* ---- allocation-free operator application ----------------------------
+ * For callers that cannot allocate device or pinned memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * y = op x at level j of `prob`, exactly what tsfcde_plan(prob) followed by
+ * tsfcde_apply(plan, op, j, d_x, d_y) gives, with no plan and no workspace.
+ * Every device buffer (twiddles, weights, spectra, transform buffers) lives
+ * in one static device array of TSFCDE_NOALLOC_SCRATCH_BYTES bytes inside
+ * the library, which each device holds from the first call on it until the
+ * process ends; the call makes no hipMalloc, hipFree, hipHostMalloc or
+ * hipMemset.  d_x, d_y: device vectors of n values, 16-byte aligned,
+ * caller-owned.  stream: a hipStream_t (NULL = default stream); the work is
+ * queued on it and the call returns without waiting (y is ready when the
+ * stream reaches that point).  All calls on one device share the array:
+ * calls that overlap on a device (other streams, other threads) race, and
+ * each call overwrites what the last one left.  Errors: TSFCDE_EINVAL as in
+ * tsfcde_plan / tsfcde_apply; TSFCDE_EUNSUPPORTED for n >
+ * TSFCDE_NOALLOC_NMAX; TSFCDE_EDEVICE when the array's address cannot be
+ * found. */
+#define TSFCDE_NOALLOC_NMAX 32768
+#define TSFCDE_NOALLOC_SCRATCH_BYTES 16777216
+int tsfcde_apply_noalloc(const tsfcde_problem *prob, int32_t op, int64_t j, const double *d_x, double *d_y,
+                         void *stream);
 
 /* ---- batched form ----------------------------------------------------
  * Many independent instances of (1.1) (any n, alpha, beta, coefficients,

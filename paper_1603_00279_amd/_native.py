@@ -45,6 +45,8 @@ TSFCDE_KRYLOV_CGS, TSFCDE_KRYLOV_BICGSTAB = 0, 1
 TSFCDE_PREC_STRANG, TSFCDE_PREC_TCHAN = 0, 1
 TSFCDE_OP_A, TSFCDE_OP_B, TSFCDE_OP_PINV = 0, 1, 2
 TSFCDE_SPEC_EMBED, TSFCDE_SPEC_STRANG = 0, 1
+TSFCDE_NOALLOC_NMAX = 32768
+TSFCDE_NOALLOC_SCRATCH_BYTES = 16777216
 
 
 class tsfcde_problem(ctypes.Structure):
@@ -100,6 +102,7 @@ _SIGS = {
     "tsfcde_profile_read": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
     "tsfcde_profile_issued": (c_int32, [c_void_p, c_int32, POINTER(c_int64)]),
     "tsfcde_destroy": (c_int32, [c_void_p]),
+    "tsfcde_apply_noalloc": (c_int32, [POINTER(tsfcde_problem), c_int32, c_int64, c_void_p, c_void_p, c_void_p]),
     "tsfcde_batch_workspace_bytes": (c_int32, [POINTER(tsfcde_problem), c_int32, POINTER(c_size_t)]),
     "tsfcde_plan_batch": (c_int32, [POINTER(tsfcde_problem), c_int32, c_void_p, c_size_t, c_void_p,
                                     POINTER(c_void_p)]),

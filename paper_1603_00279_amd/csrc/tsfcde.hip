@@ -2099,6 +2099,73 @@ int tsfcde_apply(tsfcde_plan_t pl, int32_t op, int64_t j, const double *d_x, dou
     return TSFCDE_OK;
 }
 
+// ---- tsfcde_apply_noalloc: the same product or solve with every device
+// buffer in a static array of this library (no allocation of any kind) ----
+static __device__ __align__(256) char scratch[TSFCDE_NOALLOC_SCRATCH_BYTES];
+static constexpr int NOALLOC_MAX_DEVICES = 64;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];  // device address of `scratch` on each device
+static std::mutex g_scratch_mu;
+
+// The address of `scratch` on device dev (current), looked up once per device.
+static int scratch_address(int dev, char **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TSFCDE_EDEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = static_cast<char *>(g_scratch_ptr[dev]);
+    return TSFCDE_OK;
+}
+
+int tsfcde_apply_noalloc(const tsfcde_problem *prob, int32_t op, int64_t j, const double *d_x, double *d_y,
+                         void *stream) {
+    if (int rc = validate(prob)) return rc;
+    if (!d_x || !d_y || j < 0 || j >= prob->M || !aligned16(d_x) || !aligned16(d_y)) return TSFCDE_EINVAL;
+    if (op != TSFCDE_OP_A && op != TSFCDE_OP_B && op != TSFCDE_OP_PINV) return TSFCDE_EINVAL;
+    if (prob->n > TSFCDE_NOALLOC_NMAX) return TSFCDE_EUNSUPPORTED;
+    tsfcde_plan_s pl;  // host state only; every device buffer lies in `scratch`
+    pl.alpha = prob->alpha;
+    pl.beta = prob->beta;
+    pl.a = prob->a;
+    pl.b = prob->b;
+    pl.T = prob->T;
+    pl.n = prob->n;
+    pl.M = prob->M;
+    pl.h = (prob->b - prob->a) / (double)(prob->n + 1);
+    pl.tau = prob->T / (double)prob->M;
+    pl.sigma = 1.0 - prob->alpha / 2.0;
+    pl.kappa = std::pow(pl.tau, -prob->alpha) / std::tgamma(2.0 - prob->alpha);
+    pl.hb = std::pow(pl.h, -prob->beta);
+    pl.prec = prob->preconditioner;
+    pl.qfac = pl.prec == TSFCDE_PREC_TCHAN ? (double)(pl.n - 1) / (double)pl.n : 1.0;
+    pl.one_level = true;
+    {
+        const double t = level_time(&pl, j);
+        pl.one_gam = sample(prob->gamma, prob->gamma_at, prob->coef_user, j, t);
+        pl.one_dp = sample(prob->dplus, prob->dplus_at, prob->coef_user, j, t);
+        pl.one_dm = sample(prob->dminus, prob->dminus_at, prob->coef_user, j, t);
+        if (!std::isfinite(pl.one_gam) || !std::isfinite(pl.one_dp) || !std::isfinite(pl.one_dm) ||
+            pl.one_dp < 0.0 || pl.one_dm < 0.0)
+            return TSFCDE_EINVAL;
+        pl.one_eta = eta_level(pl.alpha, pl.sigma, pl.kappa, j);
+    }
+    pl.p2 = rt_setup(pl.A, pl.P, pl.B, pl.n, false);
+    if (!partials_fit(pl.A)) return TSFCDE_EUNSUPPORTED;
+    pl.ldn = ld_of(pl.n);
+    pl.lay = layout_for(pl.n, 1, pl.A, pl.P, pl.B, pl.p2, false);
+    if (pl.lay.total > TSFCDE_NOALLOC_SCRATCH_BYTES) return TSFCDE_EUNSUPPORTED;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return TSFCDE_EDEVICE;
+    char *ws = nullptr;
+    if (int rc = scratch_address(dev, &ws)) return rc;
+    pl.device = dev;
+    pl.stream = reinterpret_cast<hipStream_t>(stream);
+    bind_workspace(&pl, ws);
+    HIPCHK(setup_spectra(&pl, prob->beta));
+    return apply_queue(&pl, op, j, d_x, d_y);
+}
+
 int tsfcde_rhs(tsfcde_plan_t pl, int64_t j, const double *d_f, double *d_g) {
     if (!pl || !d_g || j < 0 || j >= pl->M || j > pl->level || !aligned16(d_g)) return TSFCDE_EINVAL;
     int rc = level_rhs(pl, j, d_f, pl->uhat, 0);
