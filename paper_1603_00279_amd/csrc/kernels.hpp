@@ -1129,7 +1129,13 @@ __global__ void __launch_bounds__((ColGeo<R, EMAX>::NT)) k_col(int64_t C, In in,
 
 // Batched form: one launch for a group of instances with the same transform
 // geometry; blockIdx.y selects the instance, whose loader, store and scalars
-// come from a descriptor in device memory.
+// come from a descriptor in device memory.  With an index list `act` the
+// launch covers only the listed instances (descriptor act[blockIdx.y]), so a
+// group's converged instances cost no workgroups at all.
+__device__ __forceinline__ int batch_member(const int *__restrict__ act) {
+    return act ? act[blockIdx.y] : (int)blockIdx.y;
+}
+
 template <class In, class Out> struct ColDesc {
     int64_t C;
     In in;
@@ -1139,14 +1145,16 @@ template <class In, class Out> struct ColDesc {
 
 template <int R, int EMAX, int DIR, class In, class Out>
 __global__ void __launch_bounds__((ColGeo<R, EMAX>::NT)) k_col_b(const ColDesc<In, Out> *__restrict__ d,
+                                                               const int *__restrict__ act,
                                                                const double2 *__restrict__ tw_all, int pred) {
-    const ColDesc<In, Out> D = d[blockIdx.y];
+    const ColDesc<In, Out> D = d[batch_member(act)];
     col_body<R, EMAX, DIR, In, Out>(D.C, D.in, D.out, tw_all, D.sc, pred);
 }
 
 template <int NT, class In, class Out>
-__global__ void __launch_bounds__(NT) k_final_b(const ColDesc<In, Out> *__restrict__ d, int nparts, int pred) {
-    const ColDesc<In, Out> &D = d[blockIdx.y];
+__global__ void __launch_bounds__(NT) k_final_b(const ColDesc<In, Out> *__restrict__ d,
+                                                 const int *__restrict__ act, int nparts, int pred) {
+    const ColDesc<In, Out> &D = d[batch_member(act)];
     if (skip(pred, D.sc)) return;
     double tot[Out::NACC];
     reduce_partials<Out::NACC>(D.out.partials, nparts, tot);
@@ -1521,8 +1529,9 @@ struct MidDesc {
 
 template <int C_, int EMAX, int MODE>
 __global__ void __launch_bounds__((MidGeo<C_, EMAX>::NT)) k_mid_b(const MidDesc *__restrict__ d,
+                                                                const int *__restrict__ act,
                                                                 const double2 *__restrict__ tw_all, int pred) {
-    const MidDesc D = d[blockIdx.y];
+    const MidDesc D = d[batch_member(act)];
     mid_body<C_, EMAX, MODE, double2>(D.R, D.Y, D.spec, D.spec_out, D.twL, D.sp, tw_all, D.sc, pred);
 }
 

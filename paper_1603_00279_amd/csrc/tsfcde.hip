@@ -2438,7 +2438,7 @@ const char *tsfcde_strerror(int s) {
 // preconditioner), so they run the same kernel sequence.
 // ===========================================================================
 struct DoneRec {
-    int done, status, iter, pad;
+    int done, status, iter, checked, nchecks, pad;
     double rnorm2, gnorm2, aux0, aux1;
 };
 
@@ -2451,12 +2451,26 @@ __global__ void k_gather_state(DevScalars *const *__restrict__ scs, int count, D
         r.done = s->done;
         r.status = s->status;
         r.iter = s->iter;
+        r.checked = s->checked;
+        r.nchecks = s->nchecks;
         r.pad = 0;
         r.rnorm2 = s->rnorm2;
         r.gnorm2 = s->gnorm2;
         r.aux0 = s->aux0;
         r.aux1 = s->aux1;
         out[i] = r;
+    }
+}
+
+// Instances the host has stopped (restarts or iterations exhausted) are
+// marked done and checked, so that no later launch of the level, predicated
+// or not on a list, touches them again.
+__global__ void k_retire(DevScalars *const *__restrict__ scs, const int *__restrict__ list, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) {
+        DevScalars *s = scs[list[k]];
+        s->done = 1;
+        s->checked = 1;
     }
 }
 }  // namespace tsf
@@ -2501,12 +2515,23 @@ struct tsfcde_batch_s {
     Stage st;
     DevScalars **d_scs = nullptr;
     DoneRec *d_done = nullptr, *h_done = nullptr;
-    int last_iters = 8;
     bool fold = true;  // finishing steps folded into later passes (TSFCDE_FLAG_NO_FOLD clears it)
     bool strict = false;  // TSFCDE_FLAG_STRICT_RESIDUAL: accept only at a true residual within rtol |g|
     bool graphs = false;  // TSFCDE_FLAG_GRAPHS: CGS chunks replayed from captured HIP graphs
     hipStream_t cap_stream = nullptr;  // private stream the chunk graphs are captured on
     std::map<int, ChunkGraph> chunk_graphs;  // by chunk length
+    // instance lists of a round (group-local indices per group, then the
+    // instances to retire), staged in pinned memory and copied to the device
+    const int *act = nullptr;  // list the grouped launches read (null: every instance)
+    int *h_act = nullptr, *d_act = nullptr;
+    // streams the groups' rounds run on, and their joins with the batch stream
+    std::vector<hipStream_t> gstreams;
+    hipEvent_t ev_go = nullptr;
+    std::vector<hipEvent_t> ev_done;
+    // per instance: CGS iterations to its first stop at the last level (the
+    // estimate that sizes the next level's chunks)
+    std::vector<int> conv_iters;
+    std::vector<char> conv_seen;
 };
 
 namespace {
@@ -2516,11 +2541,11 @@ hipError_t blaunch_col_t(tsfcde_batch_s *bt, int64_t C, const ColDesc<In, Out> *
     using G = ColGeo<R, TSF_E_COL>;
     const int64_t grid = (C + G::B - 1) / G::B;
     hipLaunchKernelGGL((k_col_b<R, TSF_E_COL, DIR, In, Out>), dim3((unsigned)grid, cnt), dim3(G::NT), 0, bt->stream,
-                       d, bt->plans[0]->tw_all, pred);
+                       d, bt->act, bt->plans[0]->tw_all, pred);
     if constexpr (Out::NACC > 0) {
         if (finish)
-            hipLaunchKernelGGL((k_final_b<G::NT, In, Out>), dim3(1, cnt), dim3(G::NT), 0, bt->stream, d, (int)grid,
-                               pred);
+            hipLaunchKernelGGL((k_final_b<G::NT, In, Out>), dim3(1, cnt), dim3(G::NT), 0, bt->stream, d, bt->act,
+                               (int)grid, pred);
     }
     return hipGetLastError();
 }
@@ -2528,7 +2553,7 @@ hipError_t blaunch_col_t(tsfcde_batch_s *bt, int64_t C, const ColDesc<In, Out> *
 template <int R, class In, class Out>
 hipError_t bfinal_t(tsfcde_batch_s *bt, int64_t C, const ColDesc<In, Out> *d, int cnt, int pred) {
     using G = ColGeo<R, TSF_E_COL>;
-    hipLaunchKernelGGL((k_final_b<G::NT, In, Out>), dim3(1, cnt), dim3(G::NT), 0, bt->stream, d,
+    hipLaunchKernelGGL((k_final_b<G::NT, In, Out>), dim3(1, cnt), dim3(G::NT), 0, bt->stream, d, bt->act,
                        (int)((C + G::B - 1) / G::B), pred);
     return hipGetLastError();
 }
@@ -2563,7 +2588,7 @@ template <int C_, int E, int MODE>
 hipError_t blaunch_mid_e(tsfcde_batch_s *bt, const RT &rt, const MidDesc *d, int cnt, int pred) {
     using G = MidGeo<C_, E>;
     hipLaunchKernelGGL((k_mid_b<C_, E, MODE>), dim3((unsigned)(rt.R / 2), cnt), dim3(G::NT), 0, bt->stream, d,
-                       bt->plans[0]->tw_all, pred);
+                       bt->act, bt->plans[0]->tw_all, pred);
     return hipGetLastError();
 }
 
@@ -2680,9 +2705,10 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
         rstA.push_back(cdesc(pl, C, InReal{x, n, C}, osA));
         rstC.push_back(cdesc(pl, C, isA, with_red(OutRestart{pl->g, x, pl->r, pl->rt, n, C, pl->anorm[j], 0.0}, pl, 3)));
         // acceptance check of a converged instance (backward error)
-        vfyC.push_back(cdesc(pl, C, isA,
-                             with_red(OutRestart{pl->g, x, pl->r, pl->rt, n, C, pl->anorm[j], bt->strict ? 0.0 : BW_TOL},
-                                      pl, 3)));
+        OutRestart ovfy =
+            with_red(OutRestart{pl->g, x, pl->r, pl->rt, n, C, pl->anorm[j], bt->strict ? 0.0 : BW_TOL}, pl, 3);
+        ovfy.check = 1;  // counted in nchecks: the host learns that the check ran
+        vfyC.push_back(cdesc(pl, C, isA, ovfy));
         // inverse Strang circulant of level j: Bluestein DFT and embedding spectrum
         OutSpec osB{pl->bufB, pl->B.tw, CB};
         bsA.push_back(cdesc(pl, CB, InCplx{pl->wv, nullptr, pl->chirp, n, CB}, nored(osB)));
@@ -2751,44 +2777,58 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
         if (e_ != hipSuccess) return TSFCDE_EDEVICE;        \
     } while (0)
 
-// `todo` CGS iterations of every group, as launches on the batch stream.  With
-// folding, the two reductions' finishing steps run inside the next passes
-// and the chunk ends with one finishing kernel per group.
-hipError_t issue_chunk(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, int todo) {
-    const bool fold = bt->fold;
-    hipError_t e = hipSuccess;
-#define TSF_TRY(x)                          \
-    do {                                    \
+#define TSF_TRY(x)                             \
+    do {                                       \
         if ((e = (x)) != hipSuccess) return e; \
     } while (0)
+
+// `todo` CGS iterations of one group's `c` instances (all of them, or the
+// ones bt->act lists), as launches on bt->stream.  With folding, the two
+// reductions' finishing steps run inside the next passes and the chunk ends
+// with one finishing kernel.
+hipError_t issue_group_chunk(tsfcde_batch_s *bt, const BatchGroup &G, const GroupDesc &D, int c, int todo) {
+    const bool fold = bt->fold;
+    hipError_t e = hipSuccess;
     for (int k = 0; k < todo; ++k) {
-        for (size_t g = 0; g < bt->groups.size(); ++g) {
-            const BatchGroup &G = bt->groups[g];
-            const int c = (int)G.members.size();
-            const GroupDesc &D = gd[g];
-            TSF_TRY(blaunch_col<-1>(bt, G.A, D.s1[fold ? s1_variant(k) : 0], c, 1));
-            TSF_TRY(blaunch_mid<0>(bt, G.A, D.midP, c, 1, G.e_mid));
-            TSF_TRY(blaunch_col<1>(bt, G.A, D.s3, c, 1));
-            TSF_TRY(blaunch_col<-1>(bt, G.A, D.s4, c, 1));
-            TSF_TRY(blaunch_mid<0>(bt, G.A, D.midA, c, 1, G.e_mid));
-            TSF_TRY(blaunch_col<1>(bt, G.A, D.s6, c, 1, !fold));
-            if (fold) {
-                TSF_TRY(blaunch_col<-1>(bt, G.A, D.s7[s7_variant(k)], c, 1));
-            } else {
-                TSF_TRY(blaunch_col<-1>(bt, G.A, D.s7_plain, c, 1));
-            }
-            TSF_TRY(blaunch_mid<0>(bt, G.A, D.midP, c, 1, G.e_mid));
-            TSF_TRY(blaunch_col<1>(bt, G.A, D.s9, c, 1));
-            TSF_TRY(blaunch_col<-1>(bt, G.A, D.s10, c, 1));
-            TSF_TRY(blaunch_mid<0>(bt, G.A, D.midA, c, 1, G.e_mid));
-            TSF_TRY(blaunch_col<1>(bt, G.A, D.s12[0], c, 1, !fold));
+        TSF_TRY(blaunch_col<-1>(bt, G.A, D.s1[fold ? s1_variant(k) : 0], c, 1));
+        TSF_TRY(blaunch_mid<0>(bt, G.A, D.midP, c, 1, G.e_mid));
+        TSF_TRY(blaunch_col<1>(bt, G.A, D.s3, c, 1));
+        TSF_TRY(blaunch_col<-1>(bt, G.A, D.s4, c, 1));
+        TSF_TRY(blaunch_mid<0>(bt, G.A, D.midA, c, 1, G.e_mid));
+        TSF_TRY(blaunch_col<1>(bt, G.A, D.s6, c, 1, !fold));
+        if (fold) {
+            TSF_TRY(blaunch_col<-1>(bt, G.A, D.s7[s7_variant(k)], c, 1));
+        } else {
+            TSF_TRY(blaunch_col<-1>(bt, G.A, D.s7_plain, c, 1));
         }
+        TSF_TRY(blaunch_mid<0>(bt, G.A, D.midP, c, 1, G.e_mid));
+        TSF_TRY(blaunch_col<1>(bt, G.A, D.s9, c, 1));
+        TSF_TRY(blaunch_col<-1>(bt, G.A, D.s10, c, 1));
+        TSF_TRY(blaunch_mid<0>(bt, G.A, D.midA, c, 1, G.e_mid));
+        TSF_TRY(blaunch_col<1>(bt, G.A, D.s12[0], c, 1, !fold));
     }
-    if (fold) {
-        for (size_t g = 0; g < bt->groups.size(); ++g)
-            TSF_TRY(bfinal(bt, bt->groups[g].A, gd[g].s12[s7_variant(todo - 1)], (int)bt->groups[g].members.size(), 1));
-    }
-#undef TSF_TRY
+    if (fold && todo > 0) TSF_TRY(bfinal(bt, G.A, D.s12[s7_variant(todo - 1)], c, 1));
+    return e;
+}
+
+// The acceptance check of one group's `c` instances, queued behind a chunk:
+// y = A x, r = g - y and the backward-error test, run by the device only for
+// instances the chunk stopped that no check has confirmed yet (pred 3).  One
+// that fails restarts CGS from x.
+hipError_t issue_group_check(tsfcde_batch_s *bt, const BatchGroup &G, const GroupDesc &D, int c) {
+    hipError_t e = hipSuccess;
+    TSF_TRY(blaunch_col<-1>(bt, G.A, D.rstA, c, 3));
+    TSF_TRY(blaunch_mid<0>(bt, G.A, D.midA, c, 3, G.e_mid));
+    TSF_TRY(blaunch_col<1>(bt, G.A, D.vfyC, c, 3));
+    return e;
+}
+
+// `todo` CGS iterations of every group over all its instances (the form the
+// chunk graphs capture).
+hipError_t issue_chunk(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, int todo) {
+    hipError_t e = hipSuccess;
+    for (size_t g = 0; g < bt->groups.size(); ++g)
+        TSF_TRY(issue_group_chunk(bt, bt->groups[g], gd[g], (int)bt->groups[g].members.size(), todo));
     return e;
 }
 
@@ -2939,6 +2979,97 @@ int batch_poll(tsfcde_batch_s *bt) {
     return TSFCDE_OK;
 }
 
+// One round of a level's CGS: for every group with instances still
+// iterating (`active`), a chunk over those instances and the acceptance
+// check behind it.  A group's chunk is sized so that about three quarters of
+// its instances are expected to stop within it, from the iterations each
+// took to its first stop at the last level.  Groups run on up to four
+// streams of their own, joined to the batch stream before and after.  With
+// chunk graphs every group runs over all its instances (the graph's launches
+// are fixed), the longest chunk for all.  `retire` lists instances the host
+// has stopped; they are marked done on the device first.
+int batch_round(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, const std::vector<char> &active,
+                const std::vector<int> &iter_now, const std::vector<int> &retire) {
+    const size_t ng = bt->groups.size();
+    std::vector<int> off(ng, 0), nact(ng, 0), todo(ng, 0);
+    int used = 0, longest = 0;
+    for (size_t g = 0; g < ng; ++g) {
+        const BatchGroup &G = bt->groups[g];
+        off[g] = used;
+        std::vector<int> rem;
+        int itmax = 0;
+        for (size_t m = 0; m < G.members.size(); ++m) {
+            const int i = G.members[m];
+            if (!active[i]) continue;
+            bt->h_act[used++] = (int)m;
+            rem.push_back(std::max(0, bt->conv_iters[i] - iter_now[i]));
+            itmax = std::max(itmax, iter_now[i]);
+        }
+        nact[g] = used - off[g];
+        if (!nact[g]) continue;
+        std::sort(rem.begin(), rem.end());
+        const int q = rem[(rem.size() - 1) * 3 / 4];
+        todo[g] = std::max(1, std::min(std::max(2, q), bt->maxit - itmax));
+        longest = std::max(longest, todo[g]);
+    }
+    const int roff = used;
+    for (int i : retire) bt->h_act[used++] = i;
+    if (used > 0)
+        BCHK(hipMemcpyAsync(bt->d_act, bt->h_act, sizeof(int) * used, hipMemcpyHostToDevice, bt->stream));
+    if (!retire.empty()) {
+        hipLaunchKernelGGL(k_retire, dim3((unsigned)((retire.size() + 255) / 256)), dim3(256), 0, bt->stream,
+                           bt->d_scs, bt->d_act + roff, (int)retire.size());
+        BCHK(hipGetLastError());
+    }
+    if (longest == 0) return TSFCDE_OK;
+    if (bt->graphs) {
+        hipGraphExec_t ex = nullptr;
+        if (int rc = chunk_graph(bt, gd, longest, &ex)) return rc;
+        BCHK(hipGraphLaunch(ex, bt->stream));
+        for (size_t g = 0; g < ng; ++g)
+            BCHK(issue_group_check(bt, bt->groups[g], gd[g], (int)bt->groups[g].members.size()));
+        return TSFCDE_OK;
+    }
+    if (bt->gstreams.empty()) {
+        const size_t ns = std::min<size_t>(4, ng);
+        for (size_t k = 0; k < ns; ++k) {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+            BCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            bt->gstreams.push_back(st);
+            BCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            bt->ev_done.push_back(ev);
+        }
+        BCHK(hipEventCreateWithFlags(&bt->ev_go, hipEventDisableTiming));
+    }
+    // the largest groups (by unknowns still iterating) spread over the streams
+    std::vector<size_t> order;
+    for (size_t g = 0; g < ng; ++g)
+        if (nact[g]) order.push_back(g);
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        return bt->groups[a].L * nact[a] > bt->groups[b].L * nact[b];
+    });
+    const size_t ns = std::min(bt->gstreams.size(), order.size());
+    BCHK(hipEventRecord(bt->ev_go, bt->stream));
+    for (size_t k = 0; k < ns; ++k) BCHK(hipStreamWaitEvent(bt->gstreams[k], bt->ev_go, 0));
+    hipStream_t own = bt->stream;
+    hipError_t e = hipSuccess;
+    for (size_t k = 0; k < order.size() && e == hipSuccess; ++k) {
+        const size_t g = order[k];
+        bt->stream = bt->gstreams[k % ns];
+        bt->act = bt->d_act + off[g];
+        e = issue_group_chunk(bt, bt->groups[g], gd[g], nact[g], todo[g]);
+        if (e == hipSuccess) e = issue_group_check(bt, bt->groups[g], gd[g], nact[g]);
+    }
+    bt->stream = own;
+    bt->act = nullptr;
+    for (size_t k = 0; k < ns; ++k) {
+        if (e == hipSuccess) e = hipEventRecord(bt->ev_done[k], bt->gstreams[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(bt->stream, bt->ev_done[k], 0);
+    }
+    BCHK(e);
+    return TSFCDE_OK;
+}
 
 int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats) {
     if (bt->level >= bt->M) return TSFCDE_EDONE;
@@ -3047,71 +3178,60 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
         BCHK(blaunch_mid<2>(bt, G.A, gd[g].midR2C, c, 0, G.e_mid));
     }
     for (tsfcde_plan_s *pl : bt->plans) pl->pj_level = j;
-    // CGS, every instance on its own convergence flag; then every instance's
-    // answer is checked (backward error) and the ones that fail restart from x
-    int iters_seen = 0, chunk = std::max(2, bt->last_iters), rounds = 0;
-    std::vector<int> restarts(cnt, 0);
+    // CGS in rounds.  A round queues, for every group with instances still
+    // iterating, a chunk of CGS over those instances only, followed by the
+    // acceptance check (one product and the backward-error test), which the
+    // device runs only for instances the chunk has just stopped; groups run
+    // on streams of their own.  One poll per round then says which instances
+    // were accepted, which failed their check (and restarted from x on the
+    // device) and which still iterate.
+    std::vector<int> restarts(cnt, 0), seen_checks(cnt, 0);
     // accepted: the last acceptance check passed the instance's x; checked:
-    // it was checked at least once (it converged on its recursive residual)
-    std::vector<char> accepted(cnt, 0), checked(cnt, 0);
+    // it was checked at least once; active: it still takes CGS launches
+    std::vector<char> accepted(cnt, 0), checked(cnt, 0), active(cnt, 1);
+    std::vector<int> iter_now(cnt, 0), retire;
     for (;;) {
-        for (;;) {
-            const int todo = std::min(chunk, bt->maxit - iters_seen);
-            if (todo <= 0) break;
-            if (todo > 0) {
-                if (bt->graphs) {
-                    hipGraphExec_t ex = nullptr;
-                    if (int rc = chunk_graph(bt, gd, todo, &ex)) return rc;
-                    BCHK(hipGraphLaunch(ex, bt->stream));
-                } else {
-                    BCHK(issue_chunk(bt, gd, todo));
-                }
-            }
-            int rc = batch_poll(bt);
-            if (rc) return rc;
-            bool all = true;
-            int maxiter = 0;
-            for (int i = 0; i < cnt; ++i) {
-                all = all && bt->h_done[i].done;
-                maxiter = std::max(maxiter, bt->h_done[i].iter);
-            }
-            iters_seen = maxiter;
-            if (all) break;
-            chunk = 2;
-        }
-        // the instances that stopped on a breakdown or on the recursive
-        // residual are checked; non-finite and unconverged ones keep their state
-        std::vector<char> check(cnt, 0);
-        bool any = false;
-        for (int i = 0; i < cnt; ++i) {
-            const DoneRec &r = bt->h_done[i];
-            check[i] = r.done && r.status != ST_NONFINITE && restarts[i] <= MAX_RESTARTS;
-            any = any || check[i];
-        }
-        if (!any) break;
-        for (size_t g = 0; g < bt->groups.size(); ++g) {
-            const BatchGroup &G = bt->groups[g];
-            const int c = (int)G.members.size();
-            BCHK(blaunch_col<-1>(bt, G.A, gd[g].rstA, c, 0));
-            BCHK(blaunch_mid<0>(bt, G.A, gd[g].midA, c, 0, G.e_mid));
-            BCHK(blaunch_col<1>(bt, G.A, gd[g].vfyC, c, 0));
-        }
+        if (int rc = batch_round(bt, gd, active, iter_now, retire)) return rc;
+        retire.clear();
         int rc = batch_poll(bt);
         if (rc) return rc;
-        bool all = true;
+        bool any = false;
         for (int i = 0; i < cnt; ++i) {
-            if (check[i]) {
+            if (!active[i]) continue;
+            const DoneRec &r = bt->h_done[i];
+            iter_now[i] = r.iter;
+            const bool ran = r.nchecks > seen_checks[i];
+            seen_checks[i] = r.nchecks;
+            if (ran) {
                 checked[i] = 1;
-                accepted[i] = bt->h_done[i].done && bt->h_done[i].status == ST_OK;
+                accepted[i] = r.done && r.status == ST_OK;
+                if (!bt->conv_seen[i]) {  // iterations to the first stop, the next level's estimate
+                    bt->conv_seen[i] = 1;
+                    bt->conv_iters[i] = r.iter;
+                }
+                if (r.done) {
+                    active[i] = 0;  // accepted, or non-finite
+                } else if (restarts[i] >= MAX_RESTARTS) {
+                    active[i] = 0;  // x stays as it is (TSFCDE_EACCEPT)
+                    retire.push_back(i);
+                } else {
+                    ++restarts[i];  // the device restarted CGS from x
+                }
+            } else if (r.done) {
+                // stopped with no check of its own: the level's first residual
+                // already met the tolerance
+                accepted[i] = r.status == ST_OK;
+                active[i] = 0;
             }
-            if (!bt->h_done[i].done) ++restarts[i];
-            all = all && bt->h_done[i].done;
+            if (active[i] && r.iter >= bt->maxit) {  // TSFCDE_ENOCONV (or EACCEPT after a failed check)
+                active[i] = 0;
+                if (!r.done) retire.push_back(i);
+            }
+            any = any || active[i];
         }
-        ++rounds;
-        if (all || rounds > MAX_RESTARTS || iters_seen >= bt->maxit) break;
-        chunk = 2;
+        if (!any) break;
     }
-    int code = TSFCDE_OK, maxiter = 0;
+    int code = TSFCDE_OK;
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int i = 0; i < cnt; ++i) {
         const DoneRec &r = bt->h_done[i];
@@ -3122,7 +3242,6 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
         int ci = status_code(r.status);
         if (ci == TSFCDE_OK && !accepted[i]) ci = checked[i] ? TSFCDE_EACCEPT : TSFCDE_ENOCONV;
         if (ci && !code) code = ci;
-        maxiter = std::max(maxiter, r.iter);
         pl->level = j + 1;
         if (stats) {
             tsfcde_stats &s = stats[i];
@@ -3131,9 +3250,9 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
             s.restarts = restarts[i];
             s.status = ci;
             s.relres = r.gnorm2 > 0 ? std::sqrt(r.rnorm2 / r.gnorm2) : 0.0;
-            s.relres_true = rounds > 0 && r.gnorm2 > 0 ? std::sqrt(r.aux0 / r.gnorm2) : -1.0;
+            s.relres_true = checked[i] ? (r.gnorm2 > 0 ? std::sqrt(r.aux0 / r.gnorm2) : 0.0) : -1.0;
             const double den = pl->anorm[j] * std::sqrt(r.aux1) + std::sqrt(r.gnorm2);
-            s.backward_err = rounds > 0 ? (den > 0 ? std::sqrt(r.aux0) / den : 0.0) : -1.0;
+            s.backward_err = checked[i] ? (den > 0 ? std::sqrt(r.aux0) / den : 0.0) : -1.0;
             s.precision_used = TSFCDE_FP64;
             s.seconds = secs;
             s.guess = bt->warm == TSFCDE_WS_EXTRAP ? (j >= 2 ? TSFCDE_WS_EXTRAP : (j >= 1 ? TSFCDE_WS_PREV : TSFCDE_WS_ZERO))
@@ -3142,7 +3261,10 @@ int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats
             s.pad = 0;
         }
     }
-    bt->last_iters = std::max(1, maxiter);
+    for (int i = 0; i < cnt; ++i) {
+        if (!bt->conv_seen[i]) bt->conv_iters[i] = bt->h_done[i].iter;
+        bt->conv_seen[i] = 0;
+    }
     bt->level = j + 1;
     return code;
 }
@@ -3169,8 +3291,9 @@ int tsfcde_batch_workspace_bytes(const tsfcde_problem *probs, int32_t count, siz
         if (probs[i].M != probs[0].M) return TSFCDE_EINVAL;
         tot += al(b);
     }
-    // descriptors (per level), scalar pointers, gathered states
-    tot += al(batch_staging_bytes(count)) + al(sizeof(void *) * count) + al(sizeof(DoneRec) * count);
+    // descriptors (per level), scalar pointers, gathered states, instance lists
+    tot += al(batch_staging_bytes(count)) + al(sizeof(void *) * count) + al(sizeof(DoneRec) * count) +
+           al(sizeof(int) * 2 * (size_t)count);
     *bytes = tot;
     return TSFCDE_OK;
 }
@@ -3200,6 +3323,7 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
         for (tsfcde_plan_s *pl : bt->plans) tsfcde_destroy(pl);
         if (bt->st.host) (void)hipHostFree(bt->st.host);
         if (bt->h_done) (void)hipHostFree(bt->h_done);
+        if (bt->h_act) (void)hipHostFree(bt->h_act);
         delete bt;
         return code;
     };
@@ -3219,7 +3343,13 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
     off += al(sizeof(void *) * count);
     bt->d_done = reinterpret_cast<DoneRec *>(ws + off);
     off += al(sizeof(DoneRec) * count);
+    bt->d_act = reinterpret_cast<int *>(ws + off);
+    off += al(sizeof(int) * 2 * (size_t)count);
     if (off > need) return fail(TSFCDE_EINVAL);  // the layout outgrew tsfcde_batch_workspace_bytes
+    bt->conv_iters.assign(count, 8);
+    bt->conv_seen.assign(count, 0);
+    if (hipHostMalloc(reinterpret_cast<void **>(&bt->h_act), sizeof(int) * 2 * (size_t)count) != hipSuccess)
+        return fail(TSFCDE_EDEVICE);
     if (hipHostMalloc(reinterpret_cast<void **>(&bt->st.host), bt->st.cap) != hipSuccess) return fail(TSFCDE_EDEVICE);
     if (hipHostMalloc(reinterpret_cast<void **>(&bt->h_done), sizeof(DoneRec) * count) != hipSuccess)
         return fail(TSFCDE_EDEVICE);
@@ -3287,11 +3417,18 @@ int tsfcde_batch_set_level(tsfcde_batch_t bt, int64_t level) {
 int tsfcde_batch_destroy(tsfcde_batch_t bt) {
     if (!bt) return TSFCDE_EINVAL;
     (void)hipStreamSynchronize(bt->stream);
+    for (hipStream_t st : bt->gstreams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t ev : bt->ev_done) (void)hipEventDestroy(ev);
+    if (bt->ev_go) (void)hipEventDestroy(bt->ev_go);
     for (auto &kv : bt->chunk_graphs) (void)hipGraphExecDestroy(kv.second.exec);
     if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
     for (tsfcde_plan_s *pl : bt->plans) tsfcde_destroy(pl);
     if (bt->st.host) (void)hipHostFree(bt->st.host);
     if (bt->h_done) (void)hipHostFree(bt->h_done);
+    if (bt->h_act) (void)hipHostFree(bt->h_act);
     delete bt;
     return TSFCDE_OK;
 }

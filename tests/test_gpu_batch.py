@@ -163,3 +163,37 @@ def test_autotuned_batch_matches_oracle():
             bound = max(1e-10, 8 * 2.2e-16 * np.linalg.cond(O.level_A(prob, j - 1), 1))
             assert relerr(runs[0][0][i][j], Uref[j]) < bound, (i, prob.n, j, bound)
             assert relerr(runs[0][0][i][j], runs[P.TSFCDE_FLAG_NO_TUNE][0][i][j]) < bound, (i, j)
+
+
+def test_batch_large_members_sampled_rows():
+    """Members with n in (4096, 2^16], the largest groups of the 512-instance
+    workload (embedding lengths up to 2^17): every level is accepted (true
+    residual within the tolerance or backward error at most 1e-13), and the
+    oracle's rows of g - A u^{j+1} (its own sampling
+    of f, its own history sum) are rounding-sized against the row scale
+    (a componentwise backward error, as at the headline size)."""
+    import paper_1603_00279_amd as P
+    from gpu_util import row_scale, sample_rows
+    banner("batch large members")
+    probs = _instances(5, 3, 5000, 1 << 16, seed=53)
+    probs += W.batched_instances(count=1, M=3, nmin=60000, nmax=65536, seed=59)
+    with P.BatchSolver(probs, rtol=1e-10) as bs:
+        groups = bs.groups()
+        Fs = batch_sources(bs, probs)
+        all_stats = []
+        for j in range(probs[0].M):
+            code, stats = bs.step([F[j] for F in Fs])
+            assert code == 0, stats
+            all_stats.append(stats)
+        Ub = [host(bs.history(i)) for i in range(len(probs))]
+    print(f"[batch large] n = {[p.n for p in probs]}, groups {groups}", flush=True)
+    assert max(L for L, _, _ in groups) >= 1 << 16
+    for i, prob in enumerate(probs):
+        rows = sample_rows(prob.n, 60 + i, k=16, width=64)
+        for j in range(prob.M):
+            st = all_stats[j][i]
+            assert st["iters"] > 0 and (st["relres_true"] <= 1e-10 or 0.0 <= st["backward_err"] <= 1e-13), (i, j, st)
+            f = O.source_level(prob, j)
+            r = O.rhs_rows(prob, Ub[i], j, f, rows) - O.apply_A_rows(prob, j, Ub[i][j + 1], rows, "A")
+            S = row_scale(prob, j, Ub[i][j + 1])
+            assert np.abs(r).max() <= 1e-12 * S, (i, prob.n, j, np.abs(r).max() / S)
