@@ -389,12 +389,12 @@ int tsfcde_apply_noalloc(const tsfcde_problem *prob, int32_t op, int64_t j, cons
 
 /* ---- batched form ----------------------------------------------------
  * Many independent instances of (1.1) (any n, alpha, beta, coefficients,
- * same M) advanced level by level together.  Every level runs as grouped
- * launches: instances with the same embedding length share each kernel launch
- * (one workgroup row per instance), each instance follows Algorithm 2 with
- * its own CGS recurrence and stops on its own convergence flag.  All
- * instances use the general-n preconditioner path.  Results equal those of
- * single-instance plans of the same problems. */
+ * same M) advanced together.  Work runs as grouped launches: instances with
+ * the same embedding length share each kernel launch (one workgroup row per
+ * listed instance); each instance follows Algorithm 2 with its own CGS
+ * recurrence, stops on its own convergence flag and then drops out of its
+ * group's launches.  All instances use the general-n preconditioner path.
+ * Results equal those of single-instance plans of the same problems. */
 typedef struct tsfcde_batch_s *tsfcde_batch_t;
 
 /* Workspace for `count` instances (all with the same M). */
@@ -412,8 +412,9 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
                       tsfcde_batch_t *out);
 
 /* Member i as a plan handle, for tsfcde_set_state / tsfcde_history /
- * tsfcde_apply; step the batch only with tsfcde_batch_step (after
- * tsfcde_set_state on every member, tsfcde_batch_set_level re-synchronises). */
+ * tsfcde_apply; step the batch only with tsfcde_batch_step or
+ * tsfcde_batch_solve (after tsfcde_set_state on every member,
+ * tsfcde_batch_set_level re-synchronises). */
 tsfcde_plan_t tsfcde_batch_member(tsfcde_batch_t batch, int32_t i);
 int tsfcde_batch_set_level(tsfcde_batch_t batch, int64_t level);
 
@@ -424,6 +425,23 @@ int tsfcde_batch_set_level(tsfcde_batch_t batch, int64_t level);
  * NULL.  Returns the first failing instance's code (all instances still
  * advance). */
 int tsfcde_batch_step(tsfcde_batch_t batch, const double *const *d_f, tsfcde_stats *stats);
+
+/* Every remaining level of every instance (Algorithm 2's loop to j = M - 1),
+ * in one call.  Instances advance on their own: one whose level has passed
+ * its acceptance check starts its next level while others still iterate, so
+ * the slowest instance of a level delays none of the others.  The numbers are
+ * those of calling tsfcde_batch_step level by level.
+ * d_F: host array of `count` device pointers, entry i holding f of instance
+ * i at level j (at t_{j+sigma}) in row j, at d_F[i] + j * ldF[i] for
+ * j = 0..M-1 (rows before the batch's current level are not read); ldF:
+ * host array of `count` row strides (>= that instance's n).  An entry, or
+ * d_F itself, may be NULL: that instance's f then comes from its f callback.
+ * stats: count * (M - level) entries, instance-major (entry
+ * i * (M - level) + (j - level)), or NULL.  Returns TSFCDE_EDONE when no
+ * level is left, TSFCDE_EINVAL for a missing ldF or a stride below n, and
+ * otherwise the first failure of any instance and level (all levels of all
+ * instances are still computed). */
+int tsfcde_batch_solve(tsfcde_batch_t batch, const double *const *d_F, const int64_t *ldF, tsfcde_stats *stats);
 
 int tsfcde_batch_destroy(tsfcde_batch_t batch);
 

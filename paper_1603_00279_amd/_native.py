@@ -11,6 +11,7 @@ import os
 import re
 from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_void_p, c_char_p
 
+import numpy as np
 import torch  # noqa: F401  -- must precede loading the HIP library
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -73,6 +74,11 @@ class tsfcde_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+# the same record as a numpy structured type (views of stats arrays)
+STATS_DTYPE = np.dtype([(k, np.int32 if t is c_int32 else np.float64) for k, t in tsfcde_stats._fields_])
+assert STATS_DTYPE.itemsize == ctypes.sizeof(tsfcde_stats)
+
+
 class tsfcde_net_sample(ctypes.Structure):
     _fields_ = [
         ("u_next", c_void_p), ("u0", c_void_p), ("u1", c_void_p), ("u2", c_void_p),
@@ -109,6 +115,7 @@ _SIGS = {
     "tsfcde_batch_member": (c_void_p, [c_void_p, c_int32]),
     "tsfcde_batch_set_level": (c_int32, [c_void_p, c_int64]),
     "tsfcde_batch_step": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(tsfcde_stats)]),
+    "tsfcde_batch_solve": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_int64), POINTER(tsfcde_stats)]),
     "tsfcde_batch_destroy": (c_int32, [c_void_p]),
     "tsfcde_batch_group_count": (c_int32, [c_void_p]),
     "tsfcde_batch_group_info": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_int32), POINTER(c_int32)]),

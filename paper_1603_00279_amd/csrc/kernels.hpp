@@ -1636,8 +1636,9 @@ struct RowDesc {
 
 template <int C_, int EMAX, int MODE>
 __global__ void __launch_bounds__((RowGeo<C_, EMAX>::NT)) k_row_b(const RowDesc *__restrict__ d,
+                                                                  const int *__restrict__ act,
                                                                   const double2 *__restrict__ tw_all) {
-    const RowDesc D = d[blockIdx.y];
+    const RowDesc D = d[batch_member(act)];
     row_body<C_, EMAX, MODE>(D.Y, D.spec, D.spec_out, tw_all);
 }
 

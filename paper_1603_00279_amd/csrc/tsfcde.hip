@@ -2482,11 +2482,36 @@ struct ChunkGraph {
     const void *key;  // descriptor address the capture read
 };
 
+// The descriptors of one group for a level, staged for upload (pointers into
+// the device staging area).
+struct GroupDesc {
+    ColDesc<InReal, OutSpec> *rhsA, *rstA, *r2cA, *s4;
+    ColDesc<InSpec, OutRhs> *rhsC;
+    ColDesc<InSpec, OutRestart> *rstC, *vfyC;
+    MidDesc *midA, *midR2C, *midP;
+    ColDesc<InCplx, OutSpec> *bsA;
+    RowDesc *bsRow;
+    ColDesc<InSpec, OutCplx> *bsC;
+    // CGS passes.  Folded finishing steps read and write parity slots that
+    // depend on the iteration's index ci in its chunk, so the two folding
+    // passes and the chunk's closing finishing kernel come in variants:
+    // s1[v]: v = 0 (ci = 0, no fold), 1 (ci = 1), 2 (even ci >= 2), 3 (odd ci >= 3);
+    // s7[v], s12[v]: v = 0 (ci = 0), 1 (odd ci), 2 (even ci >= 2).
+    ColDesc<InCgsUP, OutSpec> *s1[4];
+    ColDesc<InSpec, OutReal> *s3, *s9;
+    ColDesc<InSpec, OutCgsDot> *s6;
+    ColDesc<InCgsQ, OutSpec> *s7[3], *s7_plain;
+    ColDesc<InCgsX, OutSpec> *s10;
+    ColDesc<InSpec, OutCgsR> *s12[3];
+};
+
 struct BatchGroup {
     int64_t L = 0;
     RT A, B;
     std::vector<int> members;
     int e_mid = TSF_E_MID;  // values per lane of the group's middle passes (autotuned)
+    int slot = 0;           // the group's stream (the largest groups on different ones)
+    GroupDesc fixed{};      // the descriptors that are the same at every level
 };
 
 // bump allocator mirroring a pinned host staging area onto a device area
@@ -2513,6 +2538,8 @@ struct tsfcde_batch_s {
     std::vector<tsfcde_plan_s *> plans;
     std::vector<BatchGroup> groups;
     Stage st;
+    size_t st_fixed = 0;   // end of the fixed descriptors in the staging area (its start)
+    size_t st_levels = 0;  // end of the per-instance level slots (after the fixed ones)
     DevScalars **d_scs = nullptr;
     DoneRec *d_done = nullptr, *h_done = nullptr;
     bool fold = true;  // finishing steps folded into later passes (TSFCDE_FLAG_NO_FOLD clears it)
@@ -2520,17 +2547,21 @@ struct tsfcde_batch_s {
     bool graphs = false;  // TSFCDE_FLAG_GRAPHS: CGS chunks replayed from captured HIP graphs
     hipStream_t cap_stream = nullptr;  // private stream the chunk graphs are captured on
     std::map<int, ChunkGraph> chunk_graphs;  // by chunk length
-    // instance lists of a round (group-local indices per group, then the
-    // instances to retire), staged in pinned memory and copied to the device
+    // instance lists of a round (per group: starting, extrapolating and
+    // iterating instances as group-local positions; then the instances to
+    // retire), staged in pinned memory and copied to the device
     const int *act = nullptr;  // list the grouped launches read (null: every instance)
     int *h_act = nullptr, *d_act = nullptr;
-    // streams the groups' rounds run on, and their joins with the batch stream
+    // streams the groups' set-up and rounds run on (none with chunk graphs),
+    // and their joins with the batch stream; groups by size, largest first
     std::vector<hipStream_t> gstreams;
+    std::vector<size_t> group_order;
     hipEvent_t ev_go = nullptr;
     std::vector<hipEvent_t> ev_done;
-    // per instance: CGS iterations to its first stop at the last level (the
-    // estimate that sizes the next level's chunks)
-    std::vector<int> conv_iters;
+    // per instance: CGS iterations to its first stop and in all at the last
+    // level (the estimates that size the next level's chunks before and after
+    // a failed acceptance check)
+    std::vector<int> conv_iters, final_iters;
     std::vector<char> conv_seen;
 };
 
@@ -2619,7 +2650,7 @@ template <int C_>
 hipError_t blaunch_row_t(tsfcde_batch_s *bt, const RT &rt, const RowDesc *d, int cnt) {
     using G = RowGeo<C_, TSF_E_MID>;
     hipLaunchKernelGGL((k_row_b<C_, TSF_E_MID, 3>), dim3((unsigned)rt.R, cnt), dim3(G::NT), 0, bt->stream, d,
-                       bt->plans[0]->tw_all);
+                       bt->act, bt->plans[0]->tw_all);
     return hipGetLastError();
 }
 
@@ -2643,37 +2674,16 @@ template <class Out> Out nored(Out o) {
     return o;
 }
 
-// The descriptors of one group for level j, staged for upload.
-struct GroupDesc {
-    ColDesc<InReal, OutSpec> *rhsA, *rstA, *r2cA, *s4;
-    ColDesc<InSpec, OutRhs> *rhsC;
-    ColDesc<InSpec, OutRestart> *rstC, *vfyC;
-    MidDesc *midA, *midR2C, *midP;
-    ColDesc<InCplx, OutSpec> *bsA;
-    RowDesc *bsRow;
-    ColDesc<InSpec, OutCplx> *bsC;
-    // CGS passes.  Folded finishing steps read and write parity slots that
-    // depend on the iteration's index ci in its chunk, so the two folding
-    // passes and the chunk's closing finishing kernel come in variants:
-    // s1[v]: v = 0 (ci = 0, no fold), 1 (ci = 1), 2 (even ci >= 2), 3 (odd ci >= 3);
-    // s7[v], s12[v]: v = 0 (ci = 0), 1 (odd ci), 2 (even ci >= 2).
-    ColDesc<InCgsUP, OutSpec> *s1[4];
-    ColDesc<InSpec, OutReal> *s3, *s9;
-    ColDesc<InSpec, OutCgsDot> *s6;
-    ColDesc<InCgsQ, OutSpec> *s7[3], *s7_plain;
-    ColDesc<InCgsX, OutSpec> *s10;
-    ColDesc<InSpec, OutCgsR> *s12[3];
-};
 
 int s1_variant(int ci) { return ci <= 1 ? ci : 2 + (ci & 1); }
 int s7_variant(int ci) { return ci == 0 ? 0 : ((ci & 1) ? 1 : 2); }
 
-bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const double *const *d_f, int warm,
-                 GroupDesc &D) {
-    std::vector<ColDesc<InReal, OutSpec>> rhsA, rstA, r2cA, s4;
-    std::vector<ColDesc<InSpec, OutRhs>> rhsC;
-    std::vector<ColDesc<InSpec, OutRestart>> rstC, vfyC;
-    std::vector<MidDesc> midA, midR2C, midP;
+// Descriptors of one group that stay the same at every level (the CGS passes
+// other than x's update, the preconditioner's construction and solve),
+// staged once when the batch is planned.
+bool stage_group_fixed(tsfcde_batch_s *bt, const BatchGroup &g, GroupDesc &D) {
+    std::vector<ColDesc<InReal, OutSpec>> r2cA, s4;
+    std::vector<MidDesc> midR2C, midP;
     std::vector<ColDesc<InCplx, OutSpec>> bsA;
     std::vector<RowDesc> bsRow;
     std::vector<ColDesc<InSpec, OutCplx>> bsC;
@@ -2681,35 +2691,15 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
     std::vector<ColDesc<InSpec, OutReal>> s3, s9;
     std::vector<ColDesc<InSpec, OutCgsDot>> s6;
     std::vector<ColDesc<InCgsQ, OutSpec>> s7[3], s7_plain;
-    std::vector<ColDesc<InCgsX, OutSpec>> s10;
     std::vector<ColDesc<InSpec, OutCgsR>> s12[3];
     const int fnparts = col_grid(g.A);
     for (int idx : g.members) {
         tsfcde_plan_s *pl = bt->plans[idx];
-        const int64_t n = pl->n, ld = pl->ldn, C = pl->A.C, CB = pl->B.C;
-        double *x = pl->U + (size_t)(j + 1) * ld;
-        const double *f = d_f ? d_f[idx] : nullptr;
-        const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
+        const int64_t n = pl->n, C = pl->A.C, CB = pl->B.C;
         const SymParams sI = unit_symbol(pl->A);
         OutSpec osA = out_spec(pl, pl->A);
         InSpec isA = in_spec(pl, pl->A);
-        // right-hand side through A u^j
-        rhsA.push_back(cdesc(pl, C, InReal{pl->U + (size_t)j * ld, n, C}, osA));
-        OutRhs orhs{pl->U + (size_t)j * ld, j >= 1 ? hist_src(pl, j) : nullptr, f, pl->g, pl->r, pl->rt, x, n, C,
-                    pl->eta[j] / pl->sigma - (j >= 1 ? hist_c1(pl, j) : 0.0), (1.0 - pl->sigma) / pl->sigma, warm,
-                    j >= 1 ? 1 : 0,
-                    j >= 2 ? pl->U + (size_t)(j - 1) * ld : nullptr, j >= 2 ? pl->U + (size_t)(j - 2) * ld : nullptr};
-        rhsC.push_back(cdesc(pl, C, isA, with_red(orhs, pl, 2)));
-        midA.push_back(MidDesc{pl->A.R, pl->buf, pl->specA, nullptr, pl->A.tw, sA, pl->sc});
-        // restart from an extrapolated guess
-        rstA.push_back(cdesc(pl, C, InReal{x, n, C}, osA));
-        rstC.push_back(cdesc(pl, C, isA, with_red(OutRestart{pl->g, x, pl->r, pl->rt, n, C, pl->anorm[j], 0.0}, pl, 3)));
-        // acceptance check of a converged instance (backward error)
-        OutRestart ovfy =
-            with_red(OutRestart{pl->g, x, pl->r, pl->rt, n, C, pl->anorm[j], bt->strict ? 0.0 : BW_TOL}, pl, 3);
-        ovfy.check = 1;  // counted in nchecks: the host learns that the check ran
-        vfyC.push_back(cdesc(pl, C, isA, ovfy));
-        // inverse Strang circulant of level j: Bluestein DFT and embedding spectrum
+        // inverse Strang circulant of a level: Bluestein DFT and embedding spectrum
         OutSpec osB{pl->bufB, pl->B.tw, CB};
         bsA.push_back(cdesc(pl, CB, InCplx{pl->wv, nullptr, pl->chirp, n, CB}, nored(osB)));
         bsRow.push_back(RowDesc{pl->bufB, pl->Bhat, nullptr});
@@ -2742,15 +2732,8 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
             s12[v].push_back(cdesc(pl, C, isA, out));
         }
         s9.push_back(cdesc(pl, C, isA, nored(OutReal{pl->uhat, n, C})));
-        s10.push_back(cdesc(pl, C, InCgsX{pl->uhat, x, n, C, 0.0}, osA));
     }
     Stage &S = bt->st;
-    D.rhsA = S.put(rhsA);
-    D.rhsC = S.put(rhsC);
-    D.midA = S.put(midA);
-    D.rstA = S.put(rstA);
-    D.rstC = S.put(rstC);
-    D.vfyC = S.put(vfyC);
     D.bsA = S.put(bsA);
     D.bsRow = S.put(bsRow);
     D.bsC = S.put(bsC);
@@ -2767,8 +2750,61 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
     }
     D.s7_plain = S.put(s7_plain);
     D.s9 = S.put(s9);
-    D.s10 = S.put(s10);
     return S.used <= S.cap;
+}
+
+// Descriptors that depend on an instance's level (its right-hand side, the
+// product's symbol, x = u^{j+1}, the acceptance check): one slot per
+// instance in each of the group's arrays, reserved when the batch is planned
+// and rewritten in the pinned staging copy whenever an instance starts a
+// level, so that instances of one group may be at different levels.
+bool reserve_group_levels(tsfcde_batch_s *bt, const BatchGroup &g, GroupDesc &D) {
+    const size_t c = g.members.size();
+    Stage &S = bt->st;
+    D.rhsA = S.put(std::vector<ColDesc<InReal, OutSpec>>(c));
+    D.rhsC = S.put(std::vector<ColDesc<InSpec, OutRhs>>(c));
+    D.midA = S.put(std::vector<MidDesc>(c));
+    D.rstA = S.put(std::vector<ColDesc<InReal, OutSpec>>(c));
+    D.rstC = S.put(std::vector<ColDesc<InSpec, OutRestart>>(c));
+    D.vfyC = S.put(std::vector<ColDesc<InSpec, OutRestart>>(c));
+    D.s10 = S.put(std::vector<ColDesc<InCgsX, OutSpec>>(c));
+    return S.used <= S.cap;
+}
+
+template <class T> T *host_slot(Stage &S, T *dev, size_t k) {
+    return reinterpret_cast<T *>(S.host + (reinterpret_cast<char *>(dev) - S.dev)) + k;
+}
+
+// Writes the level-j descriptors of instance idx (position k in group g)
+// into the pinned staging copy; f is its source at level j, warm its guess.
+void stage_member_level(tsfcde_batch_s *bt, const GroupDesc &D, size_t k, int idx, int64_t j, const double *f,
+                        int warm) {
+    tsfcde_plan_s *pl = bt->plans[idx];
+    Stage &S = bt->st;
+    const int64_t n = pl->n, ld = pl->ldn, C = pl->A.C;
+    double *x = pl->U + (size_t)(j + 1) * ld;
+    const SymParams sA = symbol(pl, j, -pl->sigma, pl->A, false);
+    OutSpec osA = out_spec(pl, pl->A);
+    InSpec isA = in_spec(pl, pl->A);
+    // right-hand side through A u^j
+    *host_slot(S, D.rhsA, k) = cdesc(pl, C, InReal{pl->U + (size_t)j * ld, n, C}, osA);
+    OutRhs orhs{pl->U + (size_t)j * ld, j >= 1 ? hist_src(pl, j) : nullptr, f, pl->g, pl->r, pl->rt, x, n, C,
+                pl->eta[j] / pl->sigma - (j >= 1 ? hist_c1(pl, j) : 0.0), (1.0 - pl->sigma) / pl->sigma, warm,
+                j >= 1 ? 1 : 0,
+                j >= 2 ? pl->U + (size_t)(j - 1) * ld : nullptr, j >= 2 ? pl->U + (size_t)(j - 2) * ld : nullptr};
+    *host_slot(S, D.rhsC, k) = cdesc(pl, C, isA, with_red(orhs, pl, 2));
+    *host_slot(S, D.midA, k) = MidDesc{pl->A.R, pl->buf, pl->specA, nullptr, pl->A.tw, sA, pl->sc};
+    // restart from an extrapolated guess
+    *host_slot(S, D.rstA, k) = cdesc(pl, C, InReal{x, n, C}, osA);
+    *host_slot(S, D.rstC, k) =
+        cdesc(pl, C, isA, with_red(OutRestart{pl->g, x, pl->r, pl->rt, n, C, pl->anorm[j], 0.0}, pl, 3));
+    // acceptance check of a converged instance (backward error)
+    OutRestart ovfy =
+        with_red(OutRestart{pl->g, x, pl->r, pl->rt, n, C, pl->anorm[j], bt->strict ? 0.0 : BW_TOL}, pl, 3);
+    ovfy.check = 1;  // counted in nchecks: the host learns that the check ran
+    *host_slot(S, D.vfyC, k) = cdesc(pl, C, isA, ovfy);
+    // CGS: x += alpha uhat
+    *host_slot(S, D.s10, k) = cdesc(pl, C, InCgsX{pl->uhat, x, n, C, 0.0}, osA);
 }
 
 #define BCHK(x)                                             \
@@ -2782,33 +2818,36 @@ bool stage_group(tsfcde_batch_s *bt, const BatchGroup &g, int64_t j, const doubl
         if ((e = (x)) != hipSuccess) return e; \
     } while (0)
 
-// `todo` CGS iterations of one group's `c` instances (all of them, or the
-// ones bt->act lists), as launches on bt->stream.  With folding, the two
-// reductions' finishing steps run inside the next passes and the chunk ends
-// with one finishing kernel.
-hipError_t issue_group_chunk(tsfcde_batch_s *bt, const BatchGroup &G, const GroupDesc &D, int c, int todo) {
+// Iteration k (0-based) of a chunk of CGS over one group's `c` instances (all
+// of them, or the ones bt->act lists), as launches on bt->stream.  With
+// folding, the two reductions' finishing steps run inside the next passes
+// and the chunk ends with one finishing kernel (issue_group_close).
+hipError_t issue_group_iteration(tsfcde_batch_s *bt, const BatchGroup &G, const GroupDesc &D, int c, int k) {
     const bool fold = bt->fold;
     hipError_t e = hipSuccess;
-    for (int k = 0; k < todo; ++k) {
-        TSF_TRY(blaunch_col<-1>(bt, G.A, D.s1[fold ? s1_variant(k) : 0], c, 1));
-        TSF_TRY(blaunch_mid<0>(bt, G.A, D.midP, c, 1, G.e_mid));
-        TSF_TRY(blaunch_col<1>(bt, G.A, D.s3, c, 1));
-        TSF_TRY(blaunch_col<-1>(bt, G.A, D.s4, c, 1));
-        TSF_TRY(blaunch_mid<0>(bt, G.A, D.midA, c, 1, G.e_mid));
-        TSF_TRY(blaunch_col<1>(bt, G.A, D.s6, c, 1, !fold));
-        if (fold) {
-            TSF_TRY(blaunch_col<-1>(bt, G.A, D.s7[s7_variant(k)], c, 1));
-        } else {
-            TSF_TRY(blaunch_col<-1>(bt, G.A, D.s7_plain, c, 1));
-        }
-        TSF_TRY(blaunch_mid<0>(bt, G.A, D.midP, c, 1, G.e_mid));
-        TSF_TRY(blaunch_col<1>(bt, G.A, D.s9, c, 1));
-        TSF_TRY(blaunch_col<-1>(bt, G.A, D.s10, c, 1));
-        TSF_TRY(blaunch_mid<0>(bt, G.A, D.midA, c, 1, G.e_mid));
-        TSF_TRY(blaunch_col<1>(bt, G.A, D.s12[0], c, 1, !fold));
+    TSF_TRY(blaunch_col<-1>(bt, G.A, D.s1[fold ? s1_variant(k) : 0], c, 1));
+    TSF_TRY(blaunch_mid<0>(bt, G.A, D.midP, c, 1, G.e_mid));
+    TSF_TRY(blaunch_col<1>(bt, G.A, D.s3, c, 1));
+    TSF_TRY(blaunch_col<-1>(bt, G.A, D.s4, c, 1));
+    TSF_TRY(blaunch_mid<0>(bt, G.A, D.midA, c, 1, G.e_mid));
+    TSF_TRY(blaunch_col<1>(bt, G.A, D.s6, c, 1, !fold));
+    if (fold) {
+        TSF_TRY(blaunch_col<-1>(bt, G.A, D.s7[s7_variant(k)], c, 1));
+    } else {
+        TSF_TRY(blaunch_col<-1>(bt, G.A, D.s7_plain, c, 1));
     }
-    if (fold && todo > 0) TSF_TRY(bfinal(bt, G.A, D.s12[s7_variant(todo - 1)], c, 1));
+    TSF_TRY(blaunch_mid<0>(bt, G.A, D.midP, c, 1, G.e_mid));
+    TSF_TRY(blaunch_col<1>(bt, G.A, D.s9, c, 1));
+    TSF_TRY(blaunch_col<-1>(bt, G.A, D.s10, c, 1));
+    TSF_TRY(blaunch_mid<0>(bt, G.A, D.midA, c, 1, G.e_mid));
+    TSF_TRY(blaunch_col<1>(bt, G.A, D.s12[0], c, 1, !fold));
     return e;
+}
+
+// The finishing kernel that closes a folded chunk of `todo` iterations.
+hipError_t issue_group_close(tsfcde_batch_s *bt, const BatchGroup &G, const GroupDesc &D, int c, int todo) {
+    if (!bt->fold || todo <= 0) return hipSuccess;
+    return bfinal(bt, G.A, D.s12[s7_variant(todo - 1)], c, 1);
 }
 
 // The acceptance check of one group's `c` instances, queued behind a chunk:
@@ -2827,8 +2866,11 @@ hipError_t issue_group_check(tsfcde_batch_s *bt, const BatchGroup &G, const Grou
 // chunk graphs capture).
 hipError_t issue_chunk(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, int todo) {
     hipError_t e = hipSuccess;
+    for (int k = 0; k < todo; ++k)
+        for (size_t g = 0; g < bt->groups.size(); ++g)
+            TSF_TRY(issue_group_iteration(bt, bt->groups[g], gd[g], (int)bt->groups[g].members.size(), k));
     for (size_t g = 0; g < bt->groups.size(); ++g)
-        TSF_TRY(issue_group_chunk(bt, bt->groups[g], gd[g], (int)bt->groups[g].members.size(), todo));
+        TSF_TRY(issue_group_close(bt, bt->groups[g], gd[g], (int)bt->groups[g].members.size(), todo));
     return e;
 }
 
@@ -2979,40 +3021,75 @@ int batch_poll(tsfcde_batch_s *bt) {
     return TSFCDE_OK;
 }
 
-// One round of a level's CGS: for every group with instances still
-// iterating (`active`), a chunk over those instances and the acceptance
-// check behind it.  A group's chunk is sized so that about three quarters of
-// its instances are expected to stop within it, from the iterations each
-// took to its first stop at the last level.  Groups run on up to four
-// streams of their own, joined to the batch stream before and after.  With
-// chunk graphs every group runs over all its instances (the graph's launches
-// are fixed), the longest chunk for all.  `retire` lists instances the host
-// has stopped; they are marked done on the device first.
-int batch_round(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, const std::vector<char> &active,
-                const std::vector<int> &iter_now, const std::vector<int> &retire) {
-    const size_t ng = bt->groups.size();
-    std::vector<int> off(ng, 0), nact(ng, 0), todo(ng, 0);
-    int used = 0, longest = 0;
-    for (size_t g = 0; g < ng; ++g) {
-        const BatchGroup &G = bt->groups[g];
-        off[g] = used;
-        std::vector<int> rem;
-        int itmax = 0;
-        for (size_t m = 0; m < G.members.size(); ++m) {
-            const int i = G.members[m];
-            if (!active[i]) continue;
-            bt->h_act[used++] = (int)m;
-            rem.push_back(std::max(0, bt->conv_iters[i] - iter_now[i]));
-            itmax = std::max(itmax, iter_now[i]);
-        }
-        nact[g] = used - off[g];
-        if (!nact[g]) continue;
-        std::sort(rem.begin(), rem.end());
-        const int q = rem[(rem.size() - 1) * 3 / 4];
-        todo[g] = std::max(1, std::min(std::max(2, q), bt->maxit - itmax));
-        longest = std::max(longest, todo[g]);
+// Sources of a batch run: f of instance i at level j, or null when the plan
+// samples its own (the f callback) or f is zero.
+struct BatchSources {
+    const double *const *d_f = nullptr;  // one level: a vector per instance
+    const double *const *d_F = nullptr;  // all levels: rows 0..M-1 per instance
+    const int64_t *ldF = nullptr;
+    const double *get(int i, int64_t j) const {
+        if (d_F) return d_F[i] ? d_F[i] + (size_t)j * (size_t)ldF[i] : nullptr;
+        return d_f ? d_f[i] : nullptr;
     }
-    const int roff = used;
+};
+
+// Progress of one instance in a batch run.
+struct MemberRun {
+    int64_t level = 0;    // the level being solved (the run's end once finished)
+    bool active = false;  // takes CGS launches
+    bool start = false;   // its level's set-up goes out in the next round
+    int restarts = 0, seen_checks = 0, iter = 0;  // iter: CGS iterations of the level so far
+    char accepted = 0, checked = 0;
+    std::chrono::steady_clock::time_point t0;
+};
+
+// Per group, the instance lists of one round (group-local positions): the
+// instances whose level starts (set-up), those of them restarting from an
+// extrapolated guess, and those that iterate (including the starting ones).
+struct RoundLists {
+    std::vector<int> start, warm2, iter;
+    int todo = 0;
+};
+
+// One round: for every group, the set-up of the levels its starting
+// instances begin, then a chunk of CGS over the instances that iterate and
+// the acceptance check behind it.  A group's chunk is sized so that about
+// three quarters of its iterating instances are expected to stop within it,
+// from the iterations each took at its last level (to its first stop, or in
+// all once its check has failed at this level).  Groups run on up to four
+// streams of their own, joined to the batch stream before and after; with
+// chunk graphs everything runs on the batch stream and the chunk covers every
+// instance (the graph's launches are fixed).  `retire` lists instances the
+// host has stopped; they are marked done on the device first.
+int batch_round(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, std::vector<RoundLists> &rl,
+                const std::vector<int> &retire, const std::vector<HistDesc> &hsweep,
+                const std::vector<HistDesc> &hcatch, const std::vector<PcDesc> &pc,
+                const std::vector<size_t> &pcoff, const std::vector<int> &pccnt, int64_t nmax) {
+    const size_t ng = bt->groups.size();
+    // staging: level slots are already in the pinned copy; the lists follow
+    bt->st.used = bt->st_levels;
+    HistDesc *dhs = hsweep.empty() ? nullptr : bt->st.put(hsweep);
+    HistDesc *dhc = hcatch.empty() ? nullptr : bt->st.put(hcatch);
+    PcDesc *dpc = pc.empty() ? nullptr : bt->st.put(pc);
+    if ((!hsweep.empty() && !dhs) || (!hcatch.empty() && !dhc) || (!pc.empty() && !dpc) ||
+        bt->st.used > bt->st.cap)
+        return TSFCDE_ENOMEM;
+    BCHK(hipMemcpyAsync(bt->st.dev + bt->st_fixed, bt->st.host + bt->st_fixed, bt->st.used - bt->st_fixed,
+                        hipMemcpyHostToDevice, bt->stream));
+    // index lists
+    std::vector<size_t> o_start(ng), o_warm(ng), o_iter(ng);
+    size_t used = 0;
+    int longest = 0;
+    for (size_t g = 0; g < ng; ++g) {
+        o_start[g] = used;
+        for (int k : rl[g].start) bt->h_act[used++] = k;
+        o_warm[g] = used;
+        for (int k : rl[g].warm2) bt->h_act[used++] = k;
+        o_iter[g] = used;
+        for (int k : rl[g].iter) bt->h_act[used++] = k;
+        longest = std::max(longest, rl[g].todo);
+    }
+    const size_t roff = used;
     for (int i : retire) bt->h_act[used++] = i;
     if (used > 0)
         BCHK(hipMemcpyAsync(bt->d_act, bt->h_act, sizeof(int) * used, hipMemcpyHostToDevice, bt->stream));
@@ -3021,49 +3098,94 @@ int batch_round(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, const std:
                            bt->d_scs, bt->d_act + roff, (int)retire.size());
         BCHK(hipGetLastError());
     }
-    if (longest == 0) return TSFCDE_OK;
-    if (bt->graphs) {
-        hipGraphExec_t ex = nullptr;
-        if (int rc = chunk_graph(bt, gd, longest, &ex)) return rc;
-        BCHK(hipGraphLaunch(ex, bt->stream));
-        for (size_t g = 0; g < ng; ++g)
-            BCHK(issue_group_check(bt, bt->groups[g], gd[g], (int)bt->groups[g].members.size()));
-        return TSFCDE_OK;
+    // history sums of the starting levels (every group's, on the batch stream)
+    const unsigned gx = (unsigned)std::min<int64_t>(1024, ((nmax + 1) / 2 + 255) / 256);
+    if (dhs) {
+        hipLaunchKernelGGL(k_hist_sweep_b, dim3(gx, (unsigned)hsweep.size()), dim3(256), 0, bt->stream, dhs);
+        BCHK(hipGetLastError());
     }
-    if (bt->gstreams.empty()) {
-        const size_t ns = std::min<size_t>(4, ng);
-        for (size_t k = 0; k < ns; ++k) {
-            hipStream_t st = nullptr;
-            hipEvent_t ev = nullptr;
-            BCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-            bt->gstreams.push_back(st);
-            BCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-            bt->ev_done.push_back(ev);
-        }
-        BCHK(hipEventCreateWithFlags(&bt->ev_go, hipEventDisableTiming));
+    if (dhc) {
+        hipLaunchKernelGGL(k_hist_catch_b, dim3(gx, (unsigned)hcatch.size()), dim3(256), 0, bt->stream, dhc);
+        BCHK(hipGetLastError());
     }
-    // the largest groups (by unknowns still iterating) spread over the streams
-    std::vector<size_t> order;
-    for (size_t g = 0; g < ng; ++g)
-        if (nact[g]) order.push_back(g);
-    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-        return bt->groups[a].L * nact[a] > bt->groups[b].L * nact[b];
-    });
-    const size_t ns = std::min(bt->gstreams.size(), order.size());
-    BCHK(hipEventRecord(bt->ev_go, bt->stream));
-    for (size_t k = 0; k < ns; ++k) BCHK(hipStreamWaitEvent(bt->gstreams[k], bt->ev_go, 0));
+    const bool split = !bt->gstreams.empty();
+    const size_t ns = bt->gstreams.size();
+    if (split) {
+        BCHK(hipEventRecord(bt->ev_go, bt->stream));
+        for (size_t k = 0; k < ns; ++k) BCHK(hipStreamWaitEvent(bt->gstreams[k], bt->ev_go, 0));
+    }
     hipStream_t own = bt->stream;
     hipError_t e = hipSuccess;
-    for (size_t k = 0; k < order.size() && e == hipSuccess; ++k) {
-        const size_t g = order[k];
-        bt->stream = bt->gstreams[k % ns];
-        bt->act = bt->d_act + off[g];
-        e = issue_group_chunk(bt, bt->groups[g], gd[g], nact[g], todo[g]);
-        if (e == hipSuccess) e = issue_group_check(bt, bt->groups[g], gd[g], nact[g]);
+    auto on = [&](size_t g, const size_t *o) {
+        if (split) bt->stream = bt->gstreams[bt->groups[g].slot];
+        bt->act = o ? bt->d_act + o[g] : nullptr;
+    };
+    // set-up of the starting levels: right-hand side and initial guess, then
+    // the inverse Strang circulant (its column, Bluestein DFT, embedding and
+    // spectrum)
+    for (size_t g : bt->group_order) {
+        const BatchGroup &G = bt->groups[g];
+        const GroupDesc &D = gd[g];
+        const int c = (int)rl[g].start.size();
+        if (!c || e != hipSuccess) continue;
+        on(g, o_start.data());
+        e = blaunch_col<-1>(bt, G.A, D.rhsA, c, 0);
+        if (e == hipSuccess) e = blaunch_mid<0>(bt, G.A, D.midA, c, 0, G.e_mid);
+        if (e == hipSuccess) e = blaunch_col<1>(bt, G.A, D.rhsC, c, 0);
+        const int c2 = (int)rl[g].warm2.size();
+        if (c2 && e == hipSuccess) {
+            on(g, o_warm.data());
+            e = blaunch_col<-1>(bt, G.A, D.rstA, c2, 0);
+            if (e == hipSuccess) e = blaunch_mid<0>(bt, G.A, D.midA, c2, 0, G.e_mid);
+            if (e == hipSuccess) e = blaunch_col<1>(bt, G.A, D.rstC, c2, 0);
+            on(g, o_start.data());
+        }
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_pc_column_b, dim3((unsigned)std::min<int64_t>(256, (G.L / 2 + 255) / 256), pccnt[g]),
+                           dim3(256), 0, bt->stream, dpc + pcoff[g]);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = blaunch_col<-1>(bt, G.B, D.bsA, c, 0);
+        if (e == hipSuccess) e = blaunch_row(bt, G.B, D.bsRow, c);
+        if (e == hipSuccess) e = blaunch_col<1>(bt, G.B, D.bsC, c, 0);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_pc_embed_b, dim3((unsigned)std::min<int64_t>(256, (G.L + 255) / 256), pccnt[g]),
+                               dim3(256), 0, bt->stream, dpc + pcoff[g]);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = blaunch_col<-1>(bt, G.A, D.r2cA, c, 0);
+        if (e == hipSuccess) e = blaunch_mid<2>(bt, G.A, D.midR2C, c, 0, G.e_mid);
+    }
+    if (e == hipSuccess && longest > 0) {
+        if (bt->graphs) {
+            bt->stream = own;
+            bt->act = nullptr;
+            hipGraphExec_t ex = nullptr;
+            if (int rc = chunk_graph(bt, gd, longest, &ex)) return rc;
+            e = hipGraphLaunch(ex, bt->stream);
+            for (size_t g = 0; g < ng && e == hipSuccess; ++g)
+                e = issue_group_check(bt, bt->groups[g], gd[g], (int)bt->groups[g].members.size());
+        } else {
+            // launches go out iteration by iteration across the groups, so that
+            // every stream has work queued within microseconds of the round's start
+            for (int it = 0; it < longest && e == hipSuccess; ++it) {
+                for (size_t g : bt->group_order) {
+                    if (it >= rl[g].todo || e != hipSuccess) continue;
+                    on(g, o_iter.data());
+                    e = issue_group_iteration(bt, bt->groups[g], gd[g], (int)rl[g].iter.size(), it);
+                }
+            }
+            for (size_t g : bt->group_order) {
+                if (!rl[g].todo || e != hipSuccess) continue;
+                on(g, o_iter.data());
+                const int c = (int)rl[g].iter.size();
+                e = issue_group_close(bt, bt->groups[g], gd[g], c, rl[g].todo);
+                if (e == hipSuccess) e = issue_group_check(bt, bt->groups[g], gd[g], c);
+            }
+        }
     }
     bt->stream = own;
     bt->act = nullptr;
-    for (size_t k = 0; k < ns; ++k) {
+    for (size_t k = 0; k < ns && split; ++k) {
         if (e == hipSuccess) e = hipEventRecord(bt->ev_done[k], bt->gstreams[k]);
         if (e == hipSuccess) e = hipStreamWaitEvent(bt->stream, bt->ev_done[k], 0);
     }
@@ -3071,202 +3193,194 @@ int batch_round(tsfcde_batch_s *bt, const std::vector<GroupDesc> &gd, const std:
     return TSFCDE_OK;
 }
 
-int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats) {
-    if (bt->level >= bt->M) return TSFCDE_EDONE;
-    auto t0 = std::chrono::steady_clock::now();
-    const int64_t j = bt->level;
+// Levels [bt->level, jend) of every instance.  Instances advance on their own:
+// one that has passed its acceptance check starts its next level in the next
+// round while others still iterate, so a level's slowest instances hold up
+// none of the rest.  stats (optional) gets one record per instance and level,
+// instance-major: stats[i * (jend - j0) + (j - j0)].  Returns the first
+// failure of any instance and level (every level is still computed).
+int batch_run(tsfcde_batch_s *bt, int64_t jend, const BatchSources &src, tsfcde_stats *stats) {
+    const int64_t j0 = bt->level;
+    if (j0 >= bt->M) return TSFCDE_EDONE;
+    jend = std::min(jend, bt->M);
+    const int64_t nlev = jend - j0;
     const int cnt = bt->count;
-    // sources that are not 16-byte aligned go through each plan's own buffer
-    std::vector<const double *> fptr(cnt, nullptr);
+    const size_t ng = bt->groups.size();
+    std::vector<MemberRun> mr(cnt);
     for (int i = 0; i < cnt; ++i) {
-        const double *f = d_f ? d_f[i] : nullptr;
-        tsfcde_plan_s *pl = bt->plans[i];
-        if (f && (reinterpret_cast<uintptr_t>(f) & 15)) {
-            hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, bt->stream, f, pl->fbuf, pl->n);
-            f = pl->fbuf;
-        }
-        if (!f) {
-            if (int rc = callback_source(pl, j, &f)) return rc;
-        }
-        fptr[i] = f;
+        mr[i].level = j0;
+        mr[i].start = true;
     }
-    const int warm = bt->warm == TSFCDE_WS_PREV ? 1 : (bt->warm == TSFCDE_WS_EXTRAP ? (j >= 2 ? 2 : (j >= 1)) : 0);
-    // descriptors of the level
-    bt->st.used = 0;
-    // history: the block's sweep for members whose block sums are not those of
-    // block b (on the batch stream: the same sums as the single-instance
-    // path), then the catch-up of a level past the block's first
-    std::vector<HistDesc> hsweep, hcatch;
-    std::vector<PcDesc> pc;
-    int64_t nmax = 0, Lmax = 0;
-    const int64_t hb0 = j >= 1 ? hist_block_of(j) : 0;
-    for (tsfcde_plan_s *pl : bt->plans) {
-        if (j >= 1) {
-            if (pl->hist_pending) {
-                if (int rc = history_quiesce(pl)) return rc;
-            }
-            HistDesc d{pl->U, pl->n, pl->ldn, pl->cb, hist_block_params(pl, hb0), (int)j, pl->clast[j],
-                       j == 1 ? pl->clast[1] : pl->cbase[1], pl->kappa, nullptr, nullptr};
-            if (pl->hist_block != hb0) {
-                d.out = pl->Hq;
-                hsweep.push_back(d);
-                pl->hist_block = hb0;
-            }
-            if (j > hb0) {
-                d.QL = pl->Hq + (size_t)(j - hb0) * pl->ldn;
-                d.out = pl->H;
-                hcatch.push_back(d);
-            }
+    // position of every instance in its group
+    std::vector<int> gof(cnt), pos(cnt);
+    for (size_t g = 0; g < ng; ++g)
+        for (size_t k = 0; k < bt->groups[g].members.size(); ++k) {
+            gof[bt->groups[g].members[k]] = (int)g;
+            pos[bt->groups[g].members[k]] = (int)k;
         }
-        pc.push_back(PcDesc{pl->Ls, pl->wv, pl->Wt, pl->tmp, pl->n, pl->A.L, precond_symbol(pl, j)});
-        nmax = std::max(nmax, pl->n);
-        Lmax = std::max(Lmax, pl->A.L);
-    }
-    // the groups' descriptors first: their offsets in the staging area are then
-    // the same at every level, which the captured chunk graphs rely on
-    std::vector<GroupDesc> gd(bt->groups.size());
-    for (size_t g = 0; g < bt->groups.size(); ++g)
-        if (!stage_group(bt, bt->groups[g], j, fptr.data(), warm, gd[g])) return TSFCDE_ENOMEM;
-    HistDesc *dhs = hsweep.empty() ? nullptr : bt->st.put(hsweep);
-    HistDesc *dhc = hcatch.empty() ? nullptr : bt->st.put(hcatch);
-    PcDesc *dpc = bt->st.put(pc);
-    if ((!hsweep.empty() && !dhs) || (!hcatch.empty() && !dhc) || !dpc || bt->st.used > bt->st.cap)
-        return TSFCDE_ENOMEM;
-    BCHK(hipMemcpyAsync(bt->st.dev, bt->st.host, bt->st.used, hipMemcpyHostToDevice, bt->stream));
-    // history sums, right-hand sides, initial guesses
-    if (j >= 1) {
-        const unsigned gx = (unsigned)std::min<int64_t>(1024, ((nmax + 1) / 2 + 255) / 256);
-        if (!hsweep.empty()) {
-            hipLaunchKernelGGL(k_hist_sweep_b, dim3(gx, (unsigned)hsweep.size()), dim3(256), 0, bt->stream, dhs);
-            BCHK(hipGetLastError());
-        }
-        if (!hcatch.empty()) {
-            hipLaunchKernelGGL(k_hist_catch_b, dim3(gx, (unsigned)hcatch.size()), dim3(256), 0, bt->stream, dhc);
-            BCHK(hipGetLastError());
-        }
-    }
-    for (size_t g = 0; g < bt->groups.size(); ++g) {
-        const BatchGroup &G = bt->groups[g];
-        const int c = (int)G.members.size();
-        BCHK(blaunch_col<-1>(bt, G.A, gd[g].rhsA, c, 0));
-        BCHK(blaunch_mid<0>(bt, G.A, gd[g].midA, c, 0, G.e_mid));
-        BCHK(blaunch_col<1>(bt, G.A, gd[g].rhsC, c, 0));
-        if (warm == 2) {
-            BCHK(blaunch_col<-1>(bt, G.A, gd[g].rstA, c, 0));
-            BCHK(blaunch_mid<0>(bt, G.A, gd[g].midA, c, 0, G.e_mid));
-            BCHK(blaunch_col<1>(bt, G.A, gd[g].rstC, c, 0));
-        }
-    }
-    // inverse Strang circulants of the level
-    hipLaunchKernelGGL(k_pc_column_b, dim3((unsigned)std::min<int64_t>(256, (nmax + 255) / 256), cnt), dim3(256), 0,
-                       bt->stream, dpc);
-    BCHK(hipGetLastError());
-    for (size_t g = 0; g < bt->groups.size(); ++g) {
-        const BatchGroup &G = bt->groups[g];
-        const int c = (int)G.members.size();
-        BCHK(blaunch_col<-1>(bt, G.B, gd[g].bsA, c, 0));
-        BCHK(blaunch_row(bt, G.B, gd[g].bsRow, c));
-        BCHK(blaunch_col<1>(bt, G.B, gd[g].bsC, c, 0));
-    }
-    hipLaunchKernelGGL(k_pc_embed_b, dim3((unsigned)std::min<int64_t>(256, (Lmax + 255) / 256), cnt), dim3(256), 0,
-                       bt->stream, dpc);
-    BCHK(hipGetLastError());
-    for (size_t g = 0; g < bt->groups.size(); ++g) {
-        const BatchGroup &G = bt->groups[g];
-        const int c = (int)G.members.size();
-        BCHK(blaunch_col<-1>(bt, G.A, gd[g].r2cA, c, 0));
-        BCHK(blaunch_mid<2>(bt, G.A, gd[g].midR2C, c, 0, G.e_mid));
-    }
-    for (tsfcde_plan_s *pl : bt->plans) pl->pj_level = j;
-    // CGS in rounds.  A round queues, for every group with instances still
-    // iterating, a chunk of CGS over those instances only, followed by the
-    // acceptance check (one product and the backward-error test), which the
-    // device runs only for instances the chunk has just stopped; groups run
-    // on streams of their own.  One poll per round then says which instances
-    // were accepted, which failed their check (and restarted from x on the
-    // device) and which still iterate.
-    std::vector<int> restarts(cnt, 0), seen_checks(cnt, 0);
-    // accepted: the last acceptance check passed the instance's x; checked:
-    // it was checked at least once; active: it still takes CGS launches
-    std::vector<char> accepted(cnt, 0), checked(cnt, 0), active(cnt, 1);
-    std::vector<int> iter_now(cnt, 0), retire;
+    std::vector<GroupDesc> gd(ng);
+    for (size_t g = 0; g < ng; ++g) gd[g] = bt->groups[g].fixed;
+    int code = TSFCDE_OK;
+    std::vector<int> retire;
     for (;;) {
-        if (int rc = batch_round(bt, gd, active, iter_now, retire)) return rc;
-        retire.clear();
-        int rc = batch_poll(bt);
-        if (rc) return rc;
+        std::vector<RoundLists> rl(ng);
+        std::vector<HistDesc> hsweep, hcatch;
+        std::vector<PcDesc> pc;
+        std::vector<size_t> pcoff(ng, 0);
+        std::vector<int> pccnt(ng, 0);
+        int64_t nmax = 0;
         bool any = false;
+        // instances that start a level this round, group by group (each
+        // group's preconditioner descriptors contiguous)
+        for (size_t g = 0; g < ng; ++g) {
+            pcoff[g] = pc.size();
+            for (int i : bt->groups[g].members) {
+                MemberRun &m = mr[i];
+                if (!m.start) continue;
+                tsfcde_plan_s *pl = bt->plans[i];
+                const int64_t j = m.level;
+                // sources that are not 16-byte aligned go through the plan's own buffer
+                const double *f = src.get(i, j);
+                if (f && (reinterpret_cast<uintptr_t>(f) & 15)) {
+                    hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, bt->stream, f, pl->fbuf, pl->n);
+                    BCHK(hipGetLastError());
+                    f = pl->fbuf;
+                }
+                if (!f) {
+                    if (int rc = callback_source(pl, j, &f)) return rc;
+                }
+                const int warm =
+                    bt->warm == TSFCDE_WS_PREV ? 1 : (bt->warm == TSFCDE_WS_EXTRAP ? (j >= 2 ? 2 : (j >= 1)) : 0);
+                // history: the block's sweep when the instance's block sums are
+                // not those of its block, then the catch-up of a level past the
+                // block's first
+                if (j >= 1) {
+                    if (pl->hist_pending) {
+                        if (int rc = history_quiesce(pl)) return rc;
+                    }
+                    const int64_t hb0 = hist_block_of(j);
+                    HistDesc d{pl->U, pl->n, pl->ldn, pl->cb, hist_block_params(pl, hb0), (int)j, pl->clast[j],
+                               j == 1 ? pl->clast[1] : pl->cbase[1], pl->kappa, nullptr, nullptr};
+                    if (pl->hist_block != hb0) {
+                        d.out = pl->Hq;
+                        hsweep.push_back(d);
+                        pl->hist_block = hb0;
+                    }
+                    if (j > hb0) {
+                        d.QL = pl->Hq + (size_t)(j - hb0) * pl->ldn;
+                        d.out = pl->H;
+                        hcatch.push_back(d);
+                    }
+                    nmax = std::max(nmax, pl->n);
+                }
+                stage_member_level(bt, gd[g], (size_t)pos[i], i, j, f, warm);
+                pc.push_back(PcDesc{pl->Ls, pl->wv, pl->Wt, pl->tmp, pl->n, pl->A.L, precond_symbol(pl, j)});
+                ++pccnt[g];
+                rl[g].start.push_back(pos[i]);
+                if (warm == 2) rl[g].warm2.push_back(pos[i]);
+                m.start = false;
+                m.active = true;
+                m.restarts = m.seen_checks = m.iter = 0;
+                m.accepted = m.checked = 0;
+                m.t0 = std::chrono::steady_clock::now();
+                bt->conv_seen[i] = 0;
+            }
+        }
+        // the iterating instances and their chunk lengths
+        for (size_t g = 0; g < ng; ++g) {
+            std::vector<int> rem;
+            int itmax = 0;
+            for (int i : bt->groups[g].members) {
+                if (!mr[i].active) continue;
+                rl[g].iter.push_back(pos[i]);
+                const int now = mr[i].iter;
+                const int est = bt->conv_seen[i] ? bt->final_iters[i] : bt->conv_iters[i];
+                rem.push_back(std::max(0, est - now));
+                itmax = std::max(itmax, now);
+            }
+            if (rem.empty()) continue;
+            any = true;
+            std::sort(rem.begin(), rem.end());
+            const int q = rem[(rem.size() - 1) * 3 / 4];
+            rl[g].todo = std::max(1, std::min(std::max(2, q), bt->maxit - itmax));
+        }
+        if (!any) break;
+        if (int rc = batch_round(bt, gd, rl, retire, hsweep, hcatch, pc, pcoff, pccnt, nmax)) return rc;
+        retire.clear();
+        if (int rc = batch_poll(bt)) return rc;
         for (int i = 0; i < cnt; ++i) {
-            if (!active[i]) continue;
+            MemberRun &m = mr[i];
+            if (!m.active) continue;
+            tsfcde_plan_s *pl = bt->plans[i];
             const DoneRec &r = bt->h_done[i];
-            iter_now[i] = r.iter;
-            const bool ran = r.nchecks > seen_checks[i];
-            seen_checks[i] = r.nchecks;
+            m.iter = r.iter;
+            const bool ran = r.nchecks > m.seen_checks;
+            m.seen_checks = r.nchecks;
             if (ran) {
-                checked[i] = 1;
-                accepted[i] = r.done && r.status == ST_OK;
+                m.checked = 1;
+                m.accepted = r.done && r.status == ST_OK;
                 if (!bt->conv_seen[i]) {  // iterations to the first stop, the next level's estimate
                     bt->conv_seen[i] = 1;
                     bt->conv_iters[i] = r.iter;
                 }
                 if (r.done) {
-                    active[i] = 0;  // accepted, or non-finite
-                } else if (restarts[i] >= MAX_RESTARTS) {
-                    active[i] = 0;  // x stays as it is (TSFCDE_EACCEPT)
+                    m.active = false;  // accepted, or non-finite
+                } else if (m.restarts >= MAX_RESTARTS) {
+                    m.active = false;  // x stays as it is (TSFCDE_EACCEPT)
                     retire.push_back(i);
                 } else {
-                    ++restarts[i];  // the device restarted CGS from x
+                    ++m.restarts;  // the device restarted CGS from x
                 }
             } else if (r.done) {
                 // stopped with no check of its own: the level's first residual
                 // already met the tolerance
-                accepted[i] = r.status == ST_OK;
-                active[i] = 0;
+                m.accepted = r.status == ST_OK;
+                m.active = false;
             }
-            if (active[i] && r.iter >= bt->maxit) {  // TSFCDE_ENOCONV (or EACCEPT after a failed check)
-                active[i] = 0;
+            if (m.active && r.iter >= bt->maxit) {  // TSFCDE_ENOCONV (or EACCEPT after a failed check)
+                m.active = false;
                 if (!r.done) retire.push_back(i);
             }
-            any = any || active[i];
-        }
-        if (!any) break;
-    }
-    int code = TSFCDE_OK;
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    for (int i = 0; i < cnt; ++i) {
-        const DoneRec &r = bt->h_done[i];
-        tsfcde_plan_s *pl = bt->plans[i];
-        // an instance whose last check failed after all restarts keeps x and
-        // reports TSFCDE_EACCEPT (as the single-instance path does); one that
-        // never converged is TSFCDE_ENOCONV
-        int ci = status_code(r.status);
-        if (ci == TSFCDE_OK && !accepted[i]) ci = checked[i] ? TSFCDE_EACCEPT : TSFCDE_ENOCONV;
-        if (ci && !code) code = ci;
-        pl->level = j + 1;
-        if (stats) {
-            tsfcde_stats &s = stats[i];
-            s.iters = r.iter;
-            s.outer_iters = 1;
-            s.restarts = restarts[i];
-            s.status = ci;
-            s.relres = r.gnorm2 > 0 ? std::sqrt(r.rnorm2 / r.gnorm2) : 0.0;
-            s.relres_true = checked[i] ? (r.gnorm2 > 0 ? std::sqrt(r.aux0 / r.gnorm2) : 0.0) : -1.0;
-            const double den = pl->anorm[j] * std::sqrt(r.aux1) + std::sqrt(r.gnorm2);
-            s.backward_err = checked[i] ? (den > 0 ? std::sqrt(r.aux0) / den : 0.0) : -1.0;
-            s.precision_used = TSFCDE_FP64;
-            s.seconds = secs;
-            s.guess = bt->warm == TSFCDE_WS_EXTRAP ? (j >= 2 ? TSFCDE_WS_EXTRAP : (j >= 1 ? TSFCDE_WS_PREV : TSFCDE_WS_ZERO))
-                                                   : (bt->warm == TSFCDE_WS_PREV ? TSFCDE_WS_PREV : TSFCDE_WS_ZERO);
-            s.method = TSFCDE_METHOD_PCGS;
-            s.pad = 0;
+            if (m.active) continue;
+            // the instance's level is finished
+            const int64_t j = m.level;
+            int ci = status_code(r.status);
+            if (ci == TSFCDE_OK && !m.accepted) ci = m.checked ? TSFCDE_EACCEPT : TSFCDE_ENOCONV;
+            if (ci && !code) code = ci;
+            if (!bt->conv_seen[i]) bt->conv_iters[i] = r.iter;
+            bt->final_iters[i] = r.iter;
+            pl->level = j + 1;
+            pl->pj_level = j;
+            if (stats) {
+                tsfcde_stats &s = stats[(size_t)i * (size_t)nlev + (size_t)(j - j0)];
+                s.iters = r.iter;
+                s.outer_iters = 1;
+                s.restarts = m.restarts;
+                s.status = ci;
+                s.relres = r.gnorm2 > 0 ? std::sqrt(r.rnorm2 / r.gnorm2) : 0.0;
+                s.relres_true = m.checked ? (r.gnorm2 > 0 ? std::sqrt(r.aux0 / r.gnorm2) : 0.0) : -1.0;
+                const double den = pl->anorm[j] * std::sqrt(r.aux1) + std::sqrt(r.gnorm2);
+                s.backward_err = m.checked ? (den > 0 ? std::sqrt(r.aux0) / den : 0.0) : -1.0;
+                s.precision_used = TSFCDE_FP64;
+                s.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - m.t0).count();
+                s.guess = bt->warm == TSFCDE_WS_EXTRAP
+                              ? (j >= 2 ? TSFCDE_WS_EXTRAP : (j >= 1 ? TSFCDE_WS_PREV : TSFCDE_WS_ZERO))
+                              : (bt->warm == TSFCDE_WS_PREV ? TSFCDE_WS_PREV : TSFCDE_WS_ZERO);
+                s.method = TSFCDE_METHOD_PCGS;
+                s.pad = 0;
+            }
+            m.level = j + 1;
+            m.start = m.level < jend;
         }
     }
-    for (int i = 0; i < cnt; ++i) {
-        if (!bt->conv_seen[i]) bt->conv_iters[i] = bt->h_done[i].iter;
-        bt->conv_seen[i] = 0;
-    }
-    bt->level = j + 1;
+    bt->level = jend;
     return code;
+}
+
+int batch_step(tsfcde_batch_s *bt, const double *const *d_f, tsfcde_stats *stats) {
+    BatchSources src;
+    src.d_f = d_f;
+    return batch_run(bt, bt->level + 1, src, stats);
 }
 
 }  // namespace
@@ -3293,7 +3407,7 @@ int tsfcde_batch_workspace_bytes(const tsfcde_problem *probs, int32_t count, siz
     }
     // descriptors (per level), scalar pointers, gathered states, instance lists
     tot += al(batch_staging_bytes(count)) + al(sizeof(void *) * count) + al(sizeof(DoneRec) * count) +
-           al(sizeof(int) * 2 * (size_t)count);
+           al(sizeof(int) * 4 * (size_t)count);
     *bytes = tot;
     return TSFCDE_OK;
 }
@@ -3324,6 +3438,9 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
         if (bt->st.host) (void)hipHostFree(bt->st.host);
         if (bt->h_done) (void)hipHostFree(bt->h_done);
         if (bt->h_act) (void)hipHostFree(bt->h_act);
+        for (hipStream_t st : bt->gstreams) (void)hipStreamDestroy(st);
+        for (hipEvent_t ev : bt->ev_done) (void)hipEventDestroy(ev);
+        if (bt->ev_go) (void)hipEventDestroy(bt->ev_go);
         delete bt;
         return code;
     };
@@ -3344,11 +3461,12 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
     bt->d_done = reinterpret_cast<DoneRec *>(ws + off);
     off += al(sizeof(DoneRec) * count);
     bt->d_act = reinterpret_cast<int *>(ws + off);
-    off += al(sizeof(int) * 2 * (size_t)count);
+    off += al(sizeof(int) * 4 * (size_t)count);
     if (off > need) return fail(TSFCDE_EINVAL);  // the layout outgrew tsfcde_batch_workspace_bytes
     bt->conv_iters.assign(count, 8);
+    bt->final_iters.assign(count, 8);
     bt->conv_seen.assign(count, 0);
-    if (hipHostMalloc(reinterpret_cast<void **>(&bt->h_act), sizeof(int) * 2 * (size_t)count) != hipSuccess)
+    if (hipHostMalloc(reinterpret_cast<void **>(&bt->h_act), sizeof(int) * 4 * (size_t)count) != hipSuccess)
         return fail(TSFCDE_EDEVICE);
     if (hipHostMalloc(reinterpret_cast<void **>(&bt->st.host), bt->st.cap) != hipSuccess) return fail(TSFCDE_EDEVICE);
     if (hipHostMalloc(reinterpret_cast<void **>(&bt->h_done), sizeof(DoneRec) * count) != hipSuccess)
@@ -3379,6 +3497,44 @@ int tsfcde_plan_batch(const tsfcde_problem *probs, int32_t count, void *d_worksp
         for (BatchGroup &G : bt->groups)
             if ((rc = tune_group(bt, G))) return fail(rc);
     }
+    // the descriptors that are the same at every level, staged once, and the
+    // slots of those that depend on an instance's level
+    bt->st.used = 0;
+    for (BatchGroup &G : bt->groups)
+        if (!stage_group_fixed(bt, G, G.fixed)) return fail(TSFCDE_ENOMEM);
+    bt->st_fixed = bt->st.used;
+    for (BatchGroup &G : bt->groups)
+        if (!reserve_group_levels(bt, G, G.fixed)) return fail(TSFCDE_ENOMEM);
+    bt->st_levels = bt->st.used;
+    if (hipMemcpyAsync(bt->st.dev, bt->st.host, bt->st_levels, hipMemcpyHostToDevice, bt->stream) != hipSuccess ||
+        hipStreamSynchronize(bt->stream) != hipSuccess)
+        return fail(TSFCDE_EDEVICE);
+    // groups by unknowns (embedding length times instances), largest first,
+    // spread over up to four streams of their own
+    for (size_t g = 0; g < bt->groups.size(); ++g) bt->group_order.push_back(g);
+    std::sort(bt->group_order.begin(), bt->group_order.end(), [&](size_t a, size_t b) {
+        const BatchGroup &A = bt->groups[a], &B = bt->groups[b];
+        return A.L * (int64_t)A.members.size() > B.L * (int64_t)B.members.size();
+    });
+    if (!bt->graphs) {
+        const size_t ns = std::min<size_t>(4, bt->groups.size());
+        for (size_t k = 0; k < ns; ++k) {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(TSFCDE_EDEVICE);
+            bt->gstreams.push_back(st);
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return fail(TSFCDE_EDEVICE);
+            bt->ev_done.push_back(ev);
+        }
+        if (hipEventCreateWithFlags(&bt->ev_go, hipEventDisableTiming) != hipSuccess) return fail(TSFCDE_EDEVICE);
+        // largest first, each to the stream with the least work so far
+        std::vector<int64_t> load(ns, 0);
+        for (size_t g : bt->group_order) {
+            const size_t k = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+            bt->groups[g].slot = (int)k;
+            load[k] += bt->groups[g].L * (int64_t)bt->groups[g].members.size();
+        }
+    }
     *out = bt;
     return TSFCDE_OK;
 }
@@ -3404,6 +3560,21 @@ int tsfcde_batch_step(tsfcde_batch_t bt, const double *const *d_f, tsfcde_stats 
     for (tsfcde_plan_s *pl : bt->plans)
         if (pl->level != bt->level) return TSFCDE_EINVAL;
     return batch_step(bt, d_f, stats);
+}
+
+int tsfcde_batch_solve(tsfcde_batch_t bt, const double *const *d_F, const int64_t *ldF, tsfcde_stats *stats) {
+    if (!bt) return TSFCDE_EINVAL;
+    for (tsfcde_plan_s *pl : bt->plans)
+        if (pl->level != bt->level) return TSFCDE_EINVAL;
+    if (d_F) {
+        if (!ldF) return TSFCDE_EINVAL;
+        for (int i = 0; i < bt->count; ++i)
+            if (d_F[i] && ldF[i] < bt->plans[i]->n) return TSFCDE_EINVAL;
+    }
+    BatchSources src;
+    src.d_F = d_F;
+    src.ldF = ldF;
+    return batch_run(bt, bt->M, src, stats);
 }
 
 int tsfcde_batch_set_level(tsfcde_batch_t bt, int64_t level) {

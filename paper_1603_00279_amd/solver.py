@@ -249,8 +249,9 @@ class TimeLevelSolver:
 
 
 class BatchSolver:
-    """Many independent instances advanced level by level with grouped
-    launches (tsfcde_plan_batch / tsfcde_batch_step).  ``problems`` are
+    """Many independent instances advanced with grouped launches
+    (tsfcde_plan_batch / tsfcde_batch_step level by level, or
+    tsfcde_batch_solve for every remaining level).  ``problems`` are
     problem descriptions as for TimeLevelSolver.from_problem, all with the
     same M; coefficients go to the library as callbacks, u^0 is phi at each
     member's nodes, and with ``callbacks`` f is a callback too."""
@@ -332,6 +333,28 @@ class BatchSolver:
         for i, u0 in enumerate(u0s):
             N.check(self._lib.tsfcde_set_state(self.member(i), 0, ctypes.c_void_p(u0.data_ptr())), "tsfcde_set_state")
         N.check(self._lib.tsfcde_batch_set_level(self._batch, 0), "tsfcde_batch_set_level")
+
+    def solve(self, Fs=None, raise_on_error=True):
+        """Every remaining level of every instance in one call
+        (tsfcde_batch_solve): instances advance on their own.  Fs: list of
+        device tensors, entry i holding f of instance i at level j in row j
+        (M x ld, ld >= n), or None (entries may be None) for the f callback.
+        Returns (code, stats) with stats a numpy structured array of shape
+        (count, levels) with the fields of tsfcde_stats."""
+        nlev = self.M - int(self._level())
+        ptrs = lds = None
+        if Fs is not None:
+            ptrs = (ctypes.c_void_p * self.count)(*[F.data_ptr() if F is not None else None for F in Fs])
+            lds = (ctypes.c_int64 * self.count)(*[F.stride(0) if F is not None else 0 for F in Fs])
+        stats = (N.tsfcde_stats * (self.count * max(nlev, 1)))()
+        code = self._lib.tsfcde_batch_solve(self._batch, ptrs, lds, stats)
+        if raise_on_error:
+            N.check(code, "tsfcde_batch_solve")
+        arr = np.frombuffer(stats, dtype=N.STATS_DTYPE).reshape(self.count, max(nlev, 1))[:, :nlev].copy()
+        return code, arr
+
+    def _level(self):
+        return self._lib.tsfcde_level(self.member(0))
 
     def step(self, fs=None, raise_on_error=True):
         """fs: list of device tensors (f of each instance at this level) or None."""

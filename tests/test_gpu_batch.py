@@ -197,3 +197,41 @@ def test_batch_large_members_sampled_rows():
             r = O.rhs_rows(prob, Ub[i], j, f, rows) - O.apply_A_rows(prob, j, Ub[i][j + 1], rows, "A")
             S = row_scale(prob, j, Ub[i][j + 1])
             assert np.abs(r).max() <= 1e-12 * S, (i, prob.n, j, np.abs(r).max() / S)
+
+
+@pytest.mark.parametrize("warm", [0, 2])
+def test_batch_solve_equals_level_steps(warm):
+    """tsfcde_batch_solve (instances advance through the levels on their own)
+    gives bitwise the levels and iteration counts of tsfcde_batch_step called
+    level by level, with stats instance-major; one instance takes its f from
+    the callback."""
+    import paper_1603_00279_amd as P
+    banner(f"batch solve vs steps, warm={warm}")
+    probs = _instances(10, 7, 40, 5000, seed=71)
+    flags = P.TSFCDE_FLAG_NO_TUNE
+    with P.BatchSolver(probs, rtol=1e-12, warm_start=warm, flags=flags) as bs:
+        Fs = batch_sources(bs, probs)
+        its_step = []
+        for j in range(probs[0].M):
+            code, stats = bs.step([F[j] for F in Fs])
+            assert code == 0, stats
+            its_step.append([st["iters"] for st in stats])
+        U1 = [host(bs.history(i)) for i in range(len(probs))]
+    with P.BatchSolver(probs, rtol=1e-12, warm_start=warm, flags=flags, callbacks=True) as bs:
+        Fs2 = list(batch_sources(bs, probs))
+        Fs2[3] = None  # the callback samples f itself
+        code, st = bs.solve(Fs2)
+        assert code == 0
+        U2 = [host(bs.history(i)) for i in range(len(probs))]
+        assert int(bs._level()) == probs[0].M
+        code, _ = bs.solve(Fs2, raise_on_error=False)
+        assert code == P.TSFCDE_EDONE
+    assert st.shape == (len(probs), probs[0].M)
+    assert np.array_equal(st["iters"].T, np.array(its_step)), (st["iters"].T, its_step)
+    assert np.all(st["status"] == 0)
+    assert np.all((st["backward_err"] >= 0) & ((st["backward_err"] <= 1e-13) | (st["relres_true"] <= 1e-12)))
+    for i in range(len(probs)):
+        if i == 3:  # f sampled by the callback on the host: the same values up to rounding
+            assert relerr(U2[i], U1[i]) < 1e-10, relerr(U2[i], U1[i])
+        else:
+            assert np.array_equal(U1[i], U2[i]), (i, probs[i].n)
