@@ -208,6 +208,17 @@ __device__ __forceinline__ void pair_stage(double2 (&v)[E], int j, bool active, 
 // PAIR != 0: the transform runs in the paired layout (see Paired), with
 // partner lanes PAIR (1 or 8) hardware lanes apart; every lane of each wave
 // must call.
+// Sinks with a prefetch() hook get it called before the exchange that
+// precedes the last stage, so that the operands their stores combine with
+// are in flight during that exchange but do not occupy registers across the
+// whole transform.
+template <class T, class = void> struct HasPrefetch {
+    static constexpr bool value = false;
+};
+template <class T> struct HasPrefetch<T, decltype(void(static_cast<T *>(nullptr)->prefetch()))> {
+    static constexpr bool value = true;
+};
+
 template <int P, int E, int NS, int DIR, int TS, class Sink, int PAIR = 0>
 __device__ __forceinline__ void fft_stages(double2 (&v)[E], int j, bool active, const double2 *twP, double2 *lds,
                                            int LS, Sink &sink) {
@@ -230,6 +241,9 @@ __device__ __forceinline__ void fft_stages(double2 (&v)[E], int j, bool active, 
             }
         }
     } else {
+        constexpr int NS2 = NS * RAD;
+        constexpr int RAD2 = P / NS2 >= E ? E : P / NS2;
+        if constexpr (HasPrefetch<Sink>::value && NS2 * RAD2 == P) sink.prefetch();
         if (active) {
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
@@ -310,6 +324,25 @@ struct Tw2 {
     __device__ __forceinline__ void fetch(int64_t m, double2 *hl) const {
         hl[0] = hi[m >> shift];
         hl[1] = lo[m & ((int64_t(1) << shift) - 1)];
+    }
+};
+
+// Four-step twiddles w(2 (r0 + S m) c), m = 0, 1, 2, ..., of one lane's
+// values (their rows form an arithmetic progression) as a running product
+// w(2 r0 c) * w(2 S c)^m: two table lookups per lane instead of two per
+// value.  Each step adds about one rounding unit, so after the at most 15
+// steps of a lane the twiddle errs by a few units, the size of the FFT's own
+// rounding.  next() returns the current twiddle and advances.
+struct TwRec {
+    double2 w, step;
+    __device__ __forceinline__ void init(const Tw2 &tw, int64_t r0, int64_t S, int64_t c) {
+        w = tw(2 * r0 * c);
+        step = tw(2 * S * c);
+    }
+    __device__ __forceinline__ double2 next() {
+        const double2 cur = w;
+        w = cmul(w, step);
+        return cur;
     }
 };
 

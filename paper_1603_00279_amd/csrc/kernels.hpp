@@ -383,6 +383,11 @@ template <class CS> struct OutSpecT {
     __device__ __forceinline__ void store(int row, int64_t col, double2 val, double *, const double2 *pre) const {
         stc(y, row * C + col, cmul(val, cmul(pre[0], pre[1])));
     }
+    // with the twiddle from a running product (TwRec) instead of prefetched entries
+    static constexpr bool REC = true;
+    __device__ __forceinline__ void store_tw(int row, int64_t col, double2 val, double2 w) const {
+        stc(y, row * C + col, cmul(val, w));
+    }
     __device__ void final(const double *, DevScalars *) const {}
     double *partials;
 };
@@ -404,6 +409,10 @@ template <class CS> struct InSpecT {
     __device__ __forceinline__ double2 finish(int, int64_t, const double2 *raw) const {
         return cmul(raw[0], cconj(cmul(raw[1], raw[2])));
     }
+    // the value alone, its twiddle then from a running product (TwRec)
+    static constexpr bool REC = true;
+    __device__ __forceinline__ double2 value(int row, int64_t col) const { return ldc(y, row * C + col); }
+    __device__ __forceinline__ double2 finish_tw(double2 val, double2 w) const { return cmul(val, cconj(w)); }
 };
 using InSpec = InSpecT<double2>;
 
@@ -1004,13 +1013,17 @@ struct OutIR {
 #ifndef TSF_E_COL_1024  // column passes of length 1024 (single plans)
 #define TSF_E_COL_1024 TSF_E_COL
 #endif
+// Columns of 2048 at sixteen values per lane: four columns per workgroup
+// (64-byte row segments) instead of two.  With the four-step twiddles from
+// running products the passes do not spill, and the march ran 8.5% faster
+// at n = 2^22 and 7% at n = 2^24 than at eight (measured).
 #ifndef TSF_E_COL_2048  // column passes of length 2048 (single plans)
-#define TSF_E_COL_2048 TSF_E_COL
+#define TSF_E_COL_2048 16
 #endif
 // Columns of 4096 at eight values per lane fit one per workgroup (16-byte
 // row segments); at sixteen, two columns of 256 lanes, with the twiddles
-// read from the global table: 6% faster per iteration at n = 2^24 despite
-// register spills (measured; columns of 2048 gained nothing).
+// read from the global table (measured 6% faster per iteration at n = 2^24
+// even when these passes still spilled registers).
 #ifndef TSF_E_COL_4096  // column passes of length 4096 (single plans)
 #define TSF_E_COL_4096 16
 #endif
@@ -1023,6 +1036,9 @@ struct OutIR {
 // spill, and the pass ran 32% faster (measured at n = 2^24).
 #ifndef TSF_E_MID_4096  // middle passes with rows of 4096 (single plans)
 #define TSF_E_MID_4096 16
+#endif
+#ifndef TSF_E_MID_2048  // middle passes with rows of 2048 (single plans)
+#define TSF_E_MID_2048 TSF_E_MID
 #endif
 #ifndef TSF_E_MID_SOLVE  // middle pass of the preconditioner solve (single plans)
 #define TSF_E_MID_SOLVE 4
@@ -1051,6 +1067,46 @@ template <int R, int EMAX> struct ColGeo {
     static_assert(lpad_size(R) * B <= LDS_VALUES - 64, "data slab fits in LDS");
 };
 
+// Loaders and stores whose per-value operands are only the four-step
+// twiddle can take it from a running product instead (TwRec).
+template <class T, class = void> struct HasRec {
+    static constexpr bool value = false;
+};
+template <class T> struct HasRec<T, decltype(void(T::REC))> {
+    static constexpr bool value = T::REC;
+};
+
+// Last-stage outputs of butterfly group q (slots q + NB r) sit at positions
+// pos(j, q) + NS r: one running product per group.
+template <class Out, int NB> struct ColRecSink {
+    const Out *out;
+    int64_t c;
+    TwRec *tr;
+    __device__ __forceinline__ void operator()(int pos, double2 val, int slot) const {
+        out->store_tw(pos, c, val, tr[slot % NB].next());
+    }
+};
+
+// ColSink whose epilogue operands are fetched late (prefetch(), before the
+// exchange that precedes the last stage) rather than before the transform.
+template <class Out, int NP, int R, int E> struct ColLateSink {
+    Out *out;
+    int64_t c;
+    double *acc;
+    double2 (*pre)[NP];
+    int j;
+    bool active;
+    __device__ __forceinline__ void prefetch() const {
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) out->fetch(LastStage<R, E>::pos(j, m), c, pre[m]);
+        }
+    }
+    __device__ __forceinline__ void operator()(int pos, double2 val, int slot) const {
+        out->store(pos, c, val, acc, pre[slot]);
+    }
+};
+
 template <class Out, int NP> struct ColSink {
     Out *out;
     int64_t c;
@@ -1076,15 +1132,43 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
     const bool active = c < C;
     in.prep(sc);
     out.prep(sc);
+    // At sixteen values per lane the twiddle-table entries of every value
+    // would not fit beside the values in the register file (the pass spilled
+    // to scratch); the four-step twiddles of the input and of the output then
+    // come from running products (TwRec): the lane's rows form arithmetic
+    // progressions j + T m, and in the last stage pos(j, q) + NS r for each
+    // of a lane's butterfly groups q.
+    constexpr bool REC_IN = E >= 16 && HasRec<In>::value;
+    constexpr bool REC_OUT = E >= 16 && HasRec<Out>::value;
+    constexpr int NBL = LastStage<R, E>::NB;
     // every load of the pass is issued before the first store: the inputs,
     // then the operands the last stage's stores combine with each output
-    double2 raw[E][In::NL];
+    double2 raw[E][REC_IN ? 1 : In::NL];
 #pragma unroll
-    for (int m = 0; m < E; ++m)
-        if (active) in.fetch(j + T * m, c, raw[m]);
-    constexpr int NP = Out::NPRE > 0 ? Out::NPRE : 1;
-    double2 pre[E][NP];
-    if constexpr (Out::NPRE > 0) {
+    for (int m = 0; m < E; ++m) {
+        if (active) {
+            if constexpr (REC_IN) {
+                raw[m][0] = in.value(j + T * m, c);
+            } else {
+                in.fetch(j + T * m, c, raw[m]);
+            }
+        }
+    }
+    TwRec trin, trout[REC_OUT ? NBL : 1];
+    if constexpr (REC_IN) {
+        if (active) trin.init(in.tw, j, T, c);
+    }
+    if constexpr (REC_OUT) {
+#pragma unroll
+        for (int q = 0; q < NBL; ++q)
+            if (active) trout[q].init(out.tw, LastStage<R, E>::pos(j, q), LastStage<R, E>::NS, c);
+    }
+    // the same width leaves no room for the epilogue's operands across the
+    // transform either: they are fetched before its last exchange instead
+    constexpr bool LATE = E >= 16 && Out::NPRE > 0 && !REC_OUT;
+    constexpr int NP = Out::NPRE > 0 && !REC_OUT ? Out::NPRE : 1;
+    double2 pre[REC_OUT ? 1 : E][NP];
+    if constexpr (Out::NPRE > 0 && !REC_OUT && !LATE) {
 #pragma unroll
         for (int m = 0; m < E; ++m)
             if (active) out.fetch(LastStage<R, E>::pos(j, m), c, pre[m]);
@@ -1096,17 +1180,40 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
     }
     double2 v[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = active ? in.finish(j + T * m, c, raw[m]) : make_double2(0.0, 0.0);
+    for (int m = 0; m < E; ++m) {
+        if constexpr (REC_IN) {
+            v[m] = active ? in.finish_tw(raw[m][0], trin.next()) : make_double2(0.0, 0.0);
+        } else {
+            v[m] = active ? in.finish(j + T * m, c, raw[m]) : make_double2(0.0, 0.0);
+        }
+    }
     // the first barrier inside the transform orders these writes before any use
     if constexpr (G::TWL) stage_twiddles<R>(twl, tw_all, t, G::NT);
     double acc[Out::NACC > 0 ? Out::NACC : 1];
 #pragma unroll
     for (int a = 0; a < (Out::NACC > 0 ? Out::NACC : 1); ++a) acc[a] = 0.0;
-    ColSink<Out, NP> sink{&out, c, acc, pre};
-    if constexpr (G::TWL) {
-        fft_t<R, E, DIR, 1>(v, j, active, twl, lds + b, B, sink);
+    if constexpr (REC_OUT) {
+        static_assert(Out::NACC == 0, "running-product twiddles serve plain spectrum stores");
+        ColRecSink<Out, NBL> sink{&out, c, trout};
+        if constexpr (G::TWL) {
+            fft_t<R, E, DIR, 1>(v, j, active, twl, lds + b, B, sink);
+        } else {
+            fft<R, E, DIR>(v, j, active, tw_all, lds + b, B, sink);
+        }
+    } else if constexpr (LATE) {
+        ColLateSink<Out, NP, R, E> sink{&out, c, acc, pre, j, active};
+        if constexpr (G::TWL) {
+            fft_t<R, E, DIR, 1>(v, j, active, twl, lds + b, B, sink);
+        } else {
+            fft<R, E, DIR>(v, j, active, tw_all, lds + b, B, sink);
+        }
     } else {
-        fft<R, E, DIR>(v, j, active, tw_all, lds + b, B, sink);
+        ColSink<Out, NP> sink{&out, c, acc, pre};
+        if constexpr (G::TWL) {
+            fft_t<R, E, DIR, 1>(v, j, active, twl, lds + b, B, sink);
+        } else {
+            fft<R, E, DIR>(v, j, active, tw_all, lds + b, B, sink);
+        }
     }
     if constexpr (Out::NACC > 0) block_partial<Out::NACC>(acc, out.partials, tile);
 }
@@ -1195,6 +1302,15 @@ template <class S> struct OpCgsXT {  // x += alpha * uhat at real indices 2m, 2m
 };
 using OpCgsX = OpCgsXT<double>;
 
+template <class CS, int NB> struct BufRecSink {  // y[pos*C + c] = val * tw(2*pos*c), twiddles from running products
+    CS *y;
+    TwRec *tr;  // one per butterfly group of the last stage
+    int64_t C, c;
+    __device__ __forceinline__ void operator()(int pos, double2 val, int slot) const {
+        stc(y, pos * C + c, cmul(val, tr[slot % NB].next()));
+    }
+};
+
 template <int NS_, class CS> struct BufSink {  // y[pos*C + c] = val * tw(2*pos*c), table entries fetched per slot
     CS *y;
     const double2 (*tw)[2];
@@ -1244,15 +1360,29 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
     const bool colok = c < C;
     const bool activeP = colok && j < TP;
     op.prep(sc);
+    // with sixteen values per lane in the product transform, the four-step
+    // twiddles come from running products (TwRec), as in the column passes
+    constexpr bool RECP = EA >= 16;
+    constexpr bool RECA = EA >= 16;
+    constexpr int NBA = LastStage<RA, EA>::NB;
     // inverse preconditioner column FFT (conjugate four-step twiddle first)
-    double2 rp[EP][3];
+    double2 rp[EP][RECP ? 1 : 3];
 #pragma unroll
     for (int m = 0; m < EP; ++m) {
         const int row = j + TP * m;
         if (activeP) {
             rp[m][0] = ldc(bufP, row * C + c);
-            twP.fetch(2 * (int64_t)row * c, rp[m] + 1);
+            if constexpr (!RECP) twP.fetch(2 * (int64_t)row * c, rp[m] + 1);
         }
+    }
+    TwRec trp, tra[NBA];
+    if constexpr (RECP) {
+        if (activeP) trp.init(twP, j, TP, c);
+    }
+    if constexpr (RECA) {
+#pragma unroll
+        for (int q = 0; q < NBA; ++q)
+            if (colok) tra[q].init(twA, LastStage<RA, EA>::pos(j, q), LastStage<RA, EA>::NS, c);
     }
     // operands of the update and of the product's four-step twiddle, fetched now
     double2 xo[EA];
@@ -1263,14 +1393,21 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
             if (colok && row < RP) op.fetch(row, c, xo[m]);
         }
     }
-    double2 twa[EA][2];
+    double2 twa[RECA ? 1 : EA][2];
+    if constexpr (!RECA) {
 #pragma unroll
-    for (int m = 0; m < EA; ++m)
-        if (colok) twA.fetch(2 * (int64_t)LastStage<RA, EA>::pos(j, m) * c, twa[m]);
+        for (int m = 0; m < EA; ++m)
+            if (colok) twA.fetch(2 * (int64_t)LastStage<RA, EA>::pos(j, m) * c, twa[m]);
+    }
     double2 vp[EP];
 #pragma unroll
-    for (int m = 0; m < EP; ++m)
-        vp[m] = activeP ? cmul(rp[m][0], cconj(cmul(rp[m][1], rp[m][2]))) : make_double2(0.0, 0.0);
+    for (int m = 0; m < EP; ++m) {
+        if constexpr (RECP) {
+            vp[m] = activeP ? cmul(rp[m][0], cconj(trp.next())) : make_double2(0.0, 0.0);
+        } else {
+            vp[m] = activeP ? cmul(rp[m][0], cconj(cmul(rp[m][1], rp[m][2]))) : make_double2(0.0, 0.0);
+        }
+    }
     if constexpr (TWL) stage_twiddles<RA>(twl, tw_all, t, G::NT);
     __syncthreads();
     LdsSink lsink{lds + b, B};
@@ -1290,11 +1427,20 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
         va[m] = val;
     }
     __syncthreads();
-    BufSink<EA, CS> bsink{bufA, twa, C, c};
-    if constexpr (TWL) {
-        fft_t<RA, EA, -1, 1>(va, j, colok, twl, lds + b, B, bsink);
+    if constexpr (RECA) {
+        BufRecSink<CS, NBA> bsink{bufA, tra, C, c};
+        if constexpr (TWL) {
+            fft_t<RA, EA, -1, 1>(va, j, colok, twl, lds + b, B, bsink);
+        } else {
+            fft<RA, EA, -1>(va, j, colok, tw_all, lds + b, B, bsink);
+        }
     } else {
-        fft<RA, EA, -1>(va, j, colok, tw_all, lds + b, B, bsink);
+        BufSink<EA, CS> bsink{bufA, twa, C, c};
+        if constexpr (TWL) {
+            fft_t<RA, EA, -1, 1>(va, j, colok, twl, lds + b, B, bsink);
+        } else {
+            fft<RA, EA, -1>(va, j, colok, tw_all, lds + b, B, bsink);
+        }
     }
 }
 

@@ -671,7 +671,9 @@ template <int C_, int MODE, class CS>
 hipError_t launch_mid_t(tsfcde_plan_s *pl, const RT &rt, CS *Y, const CS *spec, double2 *spec_out,
                         const SymParams &sp, int pred) {
     // rows of 2048 at four values per lane need 1024-thread workgroups: 14% slower
-    constexpr int EM = C_ >= 4096 ? TSF_E_MID_4096 : (MODE == 1 && C_ <= 1024 ? TSF_E_MID_SOLVE : TSF_E_MID);
+    constexpr int EM = C_ >= 4096   ? TSF_E_MID_4096
+                       : C_ == 2048 ? TSF_E_MID_2048
+                                    : (MODE == 1 && C_ <= 1024 ? TSF_E_MID_SOLVE : TSF_E_MID);
     using G = MidGeo<C_, EM>;
     launch_timed(pl, MODE == 1 ? 4 : 2, k_mid<C_, EM, MODE, CS>, dim3((unsigned)(rt.R / 2)), dim3(G::NT), rt.R,
                  Y, spec, spec_out, rt.tw, sp, (const double2 *)pl->tw_all, pl->sc, pred);

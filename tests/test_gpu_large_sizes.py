@@ -106,3 +106,29 @@ def test_levels_n_2p22(precision):
         r = O.rhs_rows(prob, U, j, F[j], rows) - O.apply_A_rows(prob, j, U[j + 1], rows, "A")
         S = row_scale(prob, j, U[j + 1])
         assert np.abs(r).max() <= 1e-12 * S, (j, np.abs(r).max() / S)
+
+
+def test_levels_n_2p24():
+    """The first two levels at n = 2^24 (alpha = 0.7, beta = 1.8): every pass
+    of the CGS iteration at sixteen values per lane (product columns of 4096,
+    preconditioner columns of 2048), whose four-step twiddles come from
+    running products.  Acceptance and the oracle's sampled rows of
+    g - A u^{j+1} as in the n = 2^22 test."""
+    import paper_1603_00279_amd as P
+    banner("levels n=2^24 M=4")
+    prob = W.config_large(n=1 << 24, M=4)
+    rows = sample_rows(prob.n, 11, k=16, width=4096)
+    F = [O.source_level(prob, j) for j in range(2)]
+    with make(prob, rtol=1e-10, flags=P.TSFCDE_FLAG_VERIFY) as s:
+        Fd = sources(s, prob, 2)
+        stats = [s.step(Fd[j]) for j in range(2)]
+        U = host(s.history()[:3])
+    for j in range(2):
+        st = stats[j]
+        print(f"[levels n=2^24] j={j} iters {st['iters']} relres_true {st['relres_true']:.2e} "
+              f"backward_err {st['backward_err']:.2e}", flush=True)
+        assert st["code"] == P.TSFCDE_OK and st["iters"] > 0, st
+        assert st["relres_true"] <= 1e-10 or 0.0 <= st["backward_err"] <= 1e-13, st
+        r = O.rhs_rows(prob, U, j, F[j], rows) - O.apply_A_rows(prob, j, U[j + 1], rows, "A")
+        S = row_scale(prob, j, U[j + 1])
+        assert np.abs(r).max() <= 1e-12 * S, (j, np.abs(r).max() / S)
