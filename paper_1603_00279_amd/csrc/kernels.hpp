@@ -1068,7 +1068,14 @@ template <int R, int EMAX> struct ColGeo {
 };
 
 // Loaders and stores whose per-value operands are only the four-step
-// twiddle can take it from a running product instead (TwRec).
+// twiddle can take it from a running product instead (TwRec), in passes of
+// at least TSF_REC_MIN_E values per lane: there it removed the register
+// spills at sixteen, and at eight it cut the headline march's time by 2.8%
+// and the batch's by 3.7% (fewer table loads); at four it gained less
+// (measured).
+#ifndef TSF_REC_MIN_E
+#define TSF_REC_MIN_E 8
+#endif
 template <class T, class = void> struct HasRec {
     static constexpr bool value = false;
 };
@@ -1132,14 +1139,14 @@ __device__ __forceinline__ void col_body(int64_t C, In in, Out out, const double
     const bool active = c < C;
     in.prep(sc);
     out.prep(sc);
-    // At sixteen values per lane the twiddle-table entries of every value
-    // would not fit beside the values in the register file (the pass spilled
-    // to scratch); the four-step twiddles of the input and of the output then
-    // come from running products (TwRec): the lane's rows form arithmetic
-    // progressions j + T m, and in the last stage pos(j, q) + NS r for each
-    // of a lane's butterfly groups q.
-    constexpr bool REC_IN = E >= 16 && HasRec<In>::value;
-    constexpr bool REC_OUT = E >= 16 && HasRec<Out>::value;
+    // The four-step twiddles of the input and of the output come from
+    // running products (TwRec) rather than two table entries per value (at
+    // sixteen values per lane those entries did not fit beside the values in
+    // the register file): the lane's rows form arithmetic progressions
+    // j + T m, and in the last stage pos(j, q) + NS r for each of a lane's
+    // butterfly groups q.
+    constexpr bool REC_IN = E >= TSF_REC_MIN_E && HasRec<In>::value;
+    constexpr bool REC_OUT = E >= TSF_REC_MIN_E && HasRec<Out>::value;
     constexpr int NBL = LastStage<R, E>::NB;
     // every load of the pass is issued before the first store: the inputs,
     // then the operands the last stage's stores combine with each output
@@ -1360,10 +1367,10 @@ __global__ void __launch_bounds__((FuseGeo<RP, EMAX>::NT)) k_fuse(int64_t C, con
     const bool colok = c < C;
     const bool activeP = colok && j < TP;
     op.prep(sc);
-    // with sixteen values per lane in the product transform, the four-step
-    // twiddles come from running products (TwRec), as in the column passes
-    constexpr bool RECP = EA >= 16;
-    constexpr bool RECA = EA >= 16;
+    // the four-step twiddles come from running products (TwRec), as in the
+    // column passes
+    constexpr bool RECP = EA >= TSF_REC_MIN_E;
+    constexpr bool RECA = EA >= TSF_REC_MIN_E;
     constexpr int NBA = LastStage<RA, EA>::NB;
     // inverse preconditioner column FFT (conjugate four-step twiddle first)
     double2 rp[EP][RECP ? 1 : 3];
