@@ -1037,6 +1037,9 @@ struct OutIR {
 #ifndef TSF_E_MID_4096  // middle passes with rows of 4096 (single plans)
 #define TSF_E_MID_4096 16
 #endif
+#ifndef TSF_MID_PAIRS  // row pairs per workgroup of a single plan's middle passes (1 or 2)
+#define TSF_MID_PAIRS 2
+#endif
 #ifndef TSF_E_MID_2048  // middle passes with rows of 2048 (single plans)
 #define TSF_E_MID_2048 TSF_E_MID
 #endif
@@ -1508,62 +1511,81 @@ template <class CS> struct RowSinkT {  // Y[row*C + pos] = val
 };
 using RowSink = RowSinkT<double2>;
 
-template <int C_, int EMAX, int MODE, class CS>
-__device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, double2 *spec_out, Tw2 twL,
-                                         SymParams sp, const double2 *__restrict__ tw_all, DevScalars *sc, int pred) {
-    if (skip(pred, sc)) return;
+// One row pair (k1, R - k1) of a middle pass: the thread's row values and
+// the pair step's operands, loaded before the pair's transform starts.
+template <int C_, int EMAX, int MODE, class CS> struct MidPair {
     using G = MidGeo<C_, EMAX>;
-    constexpr int E = G::E, T = G::T, LS = G::LS;
-    constexpr int64_t C = C_;
-    // stage twiddles in LDS when both rows and the table fit in 160 KiB
-    constexpr bool TWL = C_ > E && (2 * LS + C_) * 16 <= 163840;
-    __shared__ double2 lds[2 * LS];
-    __shared__ double2 twl[TWL ? C_ : 1];
-    const int wg = blockIdx.x;
-    const int64_t ra = wg == 0 ? 0 : wg;
-    const int64_t rb = wg == 0 ? R / 2 : R - wg;
-    const int t = threadIdx.x;
+    static constexpr int E = G::E, T = G::T;
+    static constexpr int NPT = (C_ + G::NT - 1) / G::NT;
+    // rows of 4096 would hold the pair step's operands across the transform
+    // in more registers than a 1024-thread workgroup has; they load them in
+    // the pair step instead
+    static constexpr bool PF = C_ <= 2048;
     // rows of 2 * 8^k run their last (radix-2) stage on registers, with the
     // row's logical lanes placed so that partners share a row of 16 lanes
-    constexpr int PAIR = Paired<C_, E>::OK ? (T >= 16 ? 8 : 1) : 0;
-    const int sel = t / T, j = PAIR ? paired_lane<T>(t % T) : t % T;
-    const bool active = sel < 2;
-    const int64_t row = sel == 0 ? ra : rb;
-    double2 *slab = lds + (sel < 2 ? sel : 0) * LS;
+    static constexpr int PAIR = Paired<C_, E>::OK ? (T >= 16 ? 8 : 1) : 0;
+    int64_t wg, ra, rb, row;
+    int j, sel;
+    bool active;
     double2 v[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = active ? ldc(Y, row * C + j + T * m) : make_double2(0.0, 0.0);
-    // Everything the pair step needs is fetched now, so its latency overlaps the
-    // row loads and the forward transform: spectrum values and untangle twiddles
-    // of this thread's pairs (rows ra, rb with ra != 0), and the stage twiddles.
-    constexpr int NPT = (C_ + G::NT - 1) / G::NT;
-    // rows of 4096 would hold these operands across the transform in more
-    // registers than a 1024-thread workgroup has; they load them in the pair
-    // step instead
-    constexpr bool PF = C_ <= 2048;
     double2 pLa[PF ? NPT : 1], pLb[PF ? NPT : 1], pW[PF ? NPT : 1];
-    if constexpr (PF) {
-        if (wg != 0) {
+
+    // pair index w: rows (w, R - w), and for w = 0 the self-paired rows 0, R/2
+    __device__ __forceinline__ void fetch(int64_t w, int64_t R, const CS *Y, const CS *spec, const Tw2 &twL) {
+        constexpr int64_t C = C_;
+        wg = w;
+        ra = w == 0 ? 0 : w;
+        rb = w == 0 ? R / 2 : R - w;
+        const int t = threadIdx.x;
+        sel = t / T;
+        j = PAIR ? paired_lane<T>(t % T) : t % T;
+        active = sel < 2;
+        row = sel == 0 ? ra : rb;
 #pragma unroll
-            for (int i = 0; i < NPT; ++i) {
-                const int k2 = t + G::NT * i;
-                pLa[i] = pLb[i] = pW[i] = make_double2(0.0, 0.0);
-                if (k2 < C_) {
-                    if constexpr (MODE != 2) {
-                        pLa[i] = ldc(spec, ra * C + k2);
-                        pLb[i] = ldc(spec, rb * C + (C_ - 1 - k2));
+        for (int m = 0; m < E; ++m) v[m] = active ? ldc(Y, row * C + j + T * m) : make_double2(0.0, 0.0);
+        // Everything the pair step needs is fetched now, so its latency overlaps
+        // the row loads and the forward transform: spectrum values and untangle
+        // twiddles of this thread's pairs (rows ra, rb with ra != 0).
+        if constexpr (PF) {
+            if (wg != 0) {
+#pragma unroll
+                for (int i = 0; i < NPT; ++i) {
+                    const int k2 = t + G::NT * i;
+                    pLa[i] = pLb[i] = pW[i] = make_double2(0.0, 0.0);
+                    if (k2 < C_) {
+                        if constexpr (MODE != 2) {
+                            pLa[i] = ldc(spec, ra * C + k2);
+                            pLb[i] = ldc(spec, rb * C + (C_ - 1 - k2));
+                        }
+                        pW[i] = twL(ra + R * k2);
                     }
-                    pW[i] = twL(ra + R * k2);
                 }
             }
         }
     }
+};
+
+// The transform of one fetched row pair: forward row FFTs, untangle, symbol,
+// retangle, inverse row FFTs (MODE 2 stops after the untangle).  twl holds
+// the stage twiddles when TWL (staged by the caller).
+template <int C_, int EMAX, int MODE, class CS, bool TWL>
+__device__ __forceinline__ void mid_transform(MidPair<C_, EMAX, MODE, CS> &P, int64_t R, CS *Y, const CS *spec,
+                                              double2 *spec_out, const Tw2 &twL, const SymParams &sp,
+                                              const double2 *__restrict__ tw_all, double2 *lds, const double2 *twl) {
+    using G = MidGeo<C_, EMAX>;
+    using MP = MidPair<C_, EMAX, MODE, CS>;
+    constexpr int E = G::E, T = G::T, LS = G::LS, NPT = MP::NPT, PAIR = MP::PAIR;
+    constexpr bool PF = MP::PF;
+    constexpr int64_t C = C_;
+    const int64_t wg = P.wg, ra = P.ra, rb = P.rb, row = P.row;
+    const int t = threadIdx.x, j = P.j;
+    const bool active = P.active;
+    double2 *slab = lds + (P.sel < 2 ? P.sel : 0) * LS;
     LdsSink lsink{slab, 1};
     if constexpr (TWL) {
-        stage_twiddles<C_>(twl, tw_all, t, G::NT);
-        fft_t<C_, E, -1, 1, LdsSink, PAIR>(v, j, active, twl, slab, 1, lsink);
+        fft_t<C_, E, -1, 1, LdsSink, PAIR>(P.v, j, active, twl, slab, 1, lsink);
     } else {
-        fft<C_, E, -1, LdsSink, PAIR>(v, j, active, tw_all, slab, 1, lsink);
+        fft<C_, E, -1, LdsSink, PAIR>(P.v, j, active, tw_all, slab, 1, lsink);
     }
     __syncthreads();
     double2 *s0 = lds, *s1 = lds + LS;
@@ -1578,7 +1600,7 @@ __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, doubl
             const int64_t pa = ra * C + k2, pb = rb * C + k2b;
             double2 xa, xb;
             if constexpr (PF) {
-                pair_update<MODE>(za, zb, pW[i], pLa[i], pLb[i], sp, &xa, &xb);
+                pair_update<MODE>(za, zb, P.pW[i], P.pLa[i], P.pLb[i], sp, &xa, &xb);
             } else {
                 const double2 La = MODE != 2 ? ldc(spec, pa) : make_double2(0.0, 0.0);
                 const double2 Lb = MODE != 2 ? ldc(spec, pb) : make_double2(0.0, 0.0);
@@ -1651,6 +1673,7 @@ __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, doubl
     }
     if constexpr (MODE == 2) return;
     __syncthreads();
+    double2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = active ? slab[lpad(j + T * m)] : make_double2(0.0, 0.0);
     __syncthreads();
@@ -1662,12 +1685,43 @@ __device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, doubl
     }
 }
 
-template <int C_, int EMAX, int MODE, class CS>
+// A middle pass over NPAIR row pairs per workgroup (pairs NPAIR*b ...).  With
+// two, the second pair's loads are issued before the first pair's transform,
+// so its memory traffic overlaps the first pair's LDS and arithmetic work,
+// and the first pair's stores overlap the second's transform.
+template <int C_, int EMAX, int MODE, class CS, int NPAIR = 1>
+__device__ __forceinline__ void mid_body(int64_t R, CS *Y, const CS *spec, double2 *spec_out, Tw2 twL,
+                                         SymParams sp, const double2 *__restrict__ tw_all, DevScalars *sc, int pred) {
+    if (skip(pred, sc)) return;
+    using G = MidGeo<C_, EMAX>;
+    constexpr int LS = G::LS;
+    // stage twiddles in LDS when both rows and the table fit in 160 KiB
+    constexpr bool TWL = C_ > G::E && (2 * LS + C_) * 16 <= 163840;
+    __shared__ double2 lds[2 * LS];
+    __shared__ double2 twl[TWL ? C_ : 1];
+    using MP = MidPair<C_, EMAX, MODE, CS>;
+    MP A;
+    A.fetch((int64_t)NPAIR * blockIdx.x, R, Y, spec, twL);
+    if constexpr (NPAIR == 2) {
+        MP B;
+        B.fetch(2 * (int64_t)blockIdx.x + 1, R, Y, spec, twL);
+        // the first barrier inside the transform orders these writes before any use
+        if constexpr (TWL) stage_twiddles<C_>(twl, tw_all, threadIdx.x, G::NT);
+        mid_transform<C_, EMAX, MODE, CS, TWL>(A, R, Y, spec, spec_out, twL, sp, tw_all, lds, twl);
+        __syncthreads();  // the slabs are free again
+        mid_transform<C_, EMAX, MODE, CS, TWL>(B, R, Y, spec, spec_out, twL, sp, tw_all, lds, twl);
+    } else {
+        if constexpr (TWL) stage_twiddles<C_>(twl, tw_all, threadIdx.x, G::NT);
+        mid_transform<C_, EMAX, MODE, CS, TWL>(A, R, Y, spec, spec_out, twL, sp, tw_all, lds, twl);
+    }
+}
+
+template <int C_, int EMAX, int MODE, class CS, int NPAIR = 1>
 __global__ void __launch_bounds__((MidGeo<C_, EMAX>::NT)) k_mid(int64_t R, CS *Y, const CS *spec,
                                                               double2 *spec_out, Tw2 twL, SymParams sp,
                                                               const double2 *__restrict__ tw_all, DevScalars *sc,
                                                               int pred) {
-    mid_body<C_, EMAX, MODE, CS>(R, Y, spec, spec_out, twL, sp, tw_all, sc, pred);
+    mid_body<C_, EMAX, MODE, CS, NPAIR>(R, Y, spec, spec_out, twL, sp, tw_all, sc, pred);
 }
 
 struct MidDesc {
