@@ -22,4 +22,7 @@ from .problems import (  # noqa: F401
     HELD_OUT,
     SEED_BASE,
     device_sources,
+    Problem2D,
+    problem_2d,
+    device_sources_2d,
 )

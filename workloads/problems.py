@@ -315,3 +315,120 @@ def warmstart_instances(count: int, n: int, M: int, seed: int = SEED_BASE + 4, h
                            solution=sol, name=f"warm[{k}](n={n})",
                            meta={"c_plus": cp, "c_minus": cm, "g": g, "A": A}))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Two space dimensions (the extension the paper names as future work):
+#   D_t^alpha u = gx u_x + gy u_y + dxp D_{a+,x}^bx u + dxm D_{x,b-}^bx u
+#                 + dyp D_{c+,y}^by u + dym D_{y,d-}^by u + f   on [a,b] x [c,d],
+# u = 0 on the boundary, u(x, y, 0) = phi(x, y).
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Problem2D:
+    """Problem (1.1) in two space dimensions with its discretisation sizes.
+
+    Arrays of the solution are (nx, ny): x along axis 0, y along axis 1.
+    A manufactured solution is u = theta(t) Px(x) Py(y) with Px from
+    ``sol_x`` (its theta is used) and Py from ``sol_y``."""
+
+    alpha: float
+    beta_x: float
+    beta_y: float
+    nx: int
+    ny: int
+    M: int
+    gamma_x: Callable[[float], float]
+    gamma_y: Callable[[float], float]
+    dplus_x: Callable[[float], float]
+    dminus_x: Callable[[float], float]
+    dplus_y: Callable[[float], float]
+    dminus_y: Callable[[float], float]
+    a: float = 0.0
+    b: float = 1.0
+    c: float = 0.0
+    d: float = 1.0
+    T: float = 1.0
+    sol_x: Optional[ManufacturedSolution] = None
+    sol_y: Optional[ManufacturedSolution] = None
+    name: str = ""
+
+    def axis(self, which: str) -> Problem:
+        """The one-dimensional problem along x or y (coefficients, order,
+        interval and grid of that axis; no source)."""
+        if which == "x":
+            return Problem(alpha=self.alpha, beta=self.beta_x, n=self.nx, M=self.M, gamma=self.gamma_x,
+                           dplus=self.dplus_x, dminus=self.dminus_x, a=self.a, b=self.b, T=self.T)
+        return Problem(alpha=self.alpha, beta=self.beta_y, n=self.ny, M=self.M, gamma=self.gamma_y,
+                       dplus=self.dplus_y, dminus=self.dminus_y, a=self.c, b=self.d, T=self.T)
+
+    def swapped(self) -> "Problem2D":
+        """The same problem with the roles of x and y exchanged."""
+        return Problem2D(alpha=self.alpha, beta_x=self.beta_y, beta_y=self.beta_x, nx=self.ny, ny=self.nx,
+                         M=self.M, gamma_x=self.gamma_y, gamma_y=self.gamma_x, dplus_x=self.dplus_y,
+                         dminus_x=self.dminus_y, dplus_y=self.dplus_x, dminus_y=self.dminus_x, a=self.c,
+                         b=self.d, c=self.a, d=self.b, T=self.T,
+                         sol_x=None if self.sol_y is None else ManufacturedSolution(
+                             self.sol_x.theta_terms, self.sol_y.poly_s, self.sol_y.a, self.sol_y.b),
+                         sol_y=None if self.sol_x is None else ManufacturedSolution(
+                             [(1.0, 0.0)], self.sol_x.poly_s, self.sol_x.a, self.sol_x.b),
+                         name=self.name + " (x<->y)")
+
+    def theta(self, t):
+        return self.sol_x.theta(t)
+
+    def phi(self, x, y) -> np.ndarray:
+        if self.sol_x is None:
+            return np.zeros((len(x), len(y)))
+        return self.theta(0.0) * np.outer(self.sol_x.P(x), self.sol_y.P(y))
+
+    def exact(self, x, y, t) -> np.ndarray:
+        return self.theta(t) * np.outer(self.sol_x.P(x), self.sol_y.P(y))
+
+    def source_terms(self, x, y, t):
+        """(coeffs[7], X[7, nx], Y[7, ny]) with f(x_i, y_k, t) =
+        sum_m coeffs[m] X[m, i] Y[m, k] (the closed-form derivatives of
+        the separable manufactured solution)."""
+        sx, sy = self.sol_x, self.sol_y
+        th = self.theta(t)
+        Px, Py = sx.P(x), sy.P(y)
+        X = np.stack([Px, sx.dP(x), Px, sx.rl_left(x, self.beta_x), sx.rl_right(x, self.beta_x), Px, Px])
+        Y = np.stack([Py, Py, sy.dP(y), Py, Py, sy.rl_left(y, self.beta_y), sy.rl_right(y, self.beta_y)])
+        co = np.array([sx.caputo_theta(t, self.alpha), -th * self.gamma_x(t), -th * self.gamma_y(t),
+                       -th * self.dplus_x(t), -th * self.dminus_x(t), -th * self.dplus_y(t),
+                       -th * self.dminus_y(t)])
+        return co, X, Y
+
+    def f(self, x, y, t) -> np.ndarray:
+        if self.sol_x is None:
+            return np.zeros((len(x), len(y)))
+        co, X, Y = self.source_terms(x, y, t)
+        return (co[:, None] * X).T @ Y
+
+
+def device_sources_2d(prob: Problem2D, x, y, ts, device):
+    """f at the nodes x (axis 0), y (axis 1) and every instant in ``ts`` as an
+    FP64 torch tensor (len(ts), nx, ny) on ``device``, from the separable form."""
+    import torch
+    out = []
+    for t in ts:
+        co, X, Y = prob.source_terms(np.asarray(x, dtype=np.float64), np.asarray(y, dtype=np.float64), float(t))
+        Xd = torch.as_tensor((co[:, None] * X).T, dtype=torch.float64, device=device)
+        out.append(Xd @ torch.as_tensor(Y, dtype=torch.float64, device=device))
+    return torch.stack(out).contiguous()
+
+
+def problem_2d(nx: int, ny: int, M: int, alpha: float = 0.6, beta_x: float = 1.7, beta_y: float = 1.4,
+               seed: int = SEED_BASE + 5) -> Problem2D:
+    """A 2D instance of the headline family: gamma_x = -(1+t)/2, gamma_y =
+    (1+t)/4, d_+-^x = c_+-^x (1+t), d_+-^y = c_+-^y (1+t) with seed-drawn
+    c ~ U(0.5, 2) and amplitude A ~ U(0.5, 2); u = A t^2 x^2 (1-x)^2 y^2 (1-y)^2."""
+    rng = np.random.default_rng(seed)
+    cxp, cxm, cyp, cym, A = (float(v) for v in rng.uniform(0.5, 2.0, size=5))
+    return Problem2D(alpha=alpha, beta_x=beta_x, beta_y=beta_y, nx=nx, ny=ny, M=M,
+                     gamma_x=lambda t: -(1.0 + t) / 2.0, gamma_y=lambda t: (1.0 + t) / 4.0,
+                     dplus_x=lambda t, c=cxp: c * (1.0 + t), dminus_x=lambda t, c=cxm: c * (1.0 + t),
+                     dplus_y=lambda t, c=cyp: c * (1.0 + t), dminus_y=lambda t, c=cym: c * (1.0 + t),
+                     sol_x=ManufacturedSolution([(A, 2.0)], _x2_one_minus_x2()),
+                     sol_y=ManufacturedSolution([(1.0, 0.0)], _x2_one_minus_x2()),
+                     name=f"2d(nx={nx}, ny={ny}, M={M})")
