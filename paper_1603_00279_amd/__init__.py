@@ -16,4 +16,5 @@ from ._native import (  # noqa: F401
     TSFCDE_OP_B, TSFCDE_OP_PINV, TSFCDE_SPEC_EMBED, TSFCDE_SPEC_STRANG, TsfcdeError, lib, header_symbols,
 )
 from .solver import BatchSolver, TimeLevelSolver  # noqa: F401
+from .solver2d import TimeLevelSolver2D  # noqa: F401
 from .warmnet import WarmStartNet  # noqa: F401

@@ -17,10 +17,13 @@ import torch  # noqa: F401  -- must precede loading the HIP library
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libtsfcde.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "tsfcde.h")
+HEADERS = [HEADER, os.path.join(os.path.dirname(PKG), "include", "tsfcde2d.h")]
 
 COEF_FN = ctypes.CFUNCTYPE(c_double, c_double, c_void_p)
 IC_FN = ctypes.CFUNCTYPE(c_double, c_double, c_void_p)
 SRC_FN = ctypes.CFUNCTYPE(c_double, c_double, c_double, c_void_p)
+IC2_FN = ctypes.CFUNCTYPE(c_double, c_double, c_double, c_void_p)
+SRC2_FN = ctypes.CFUNCTYPE(c_double, c_double, c_double, c_double, c_void_p)
 
 TSFCDE_OK = 0
 STATUS = {0: "TSFCDE_OK", -1: "TSFCDE_EINVAL", -2: "TSFCDE_ENOMEM", -3: "TSFCDE_EDEVICE",
@@ -79,6 +82,18 @@ STATS_DTYPE = np.dtype([(k, np.int32 if t is c_int32 else np.float64) for k, t i
 assert STATS_DTYPE.itemsize == ctypes.sizeof(tsfcde_stats)
 
 
+class tsfcde2d_problem(ctypes.Structure):
+    _fields_ = [
+        ("alpha", c_double), ("beta_x", c_double), ("beta_y", c_double),
+        ("a", c_double), ("b", c_double), ("c", c_double), ("d", c_double), ("T", c_double),
+        ("nx", c_int64), ("ny", c_int64), ("M", c_int64),
+        ("gamma_x", COEF_FN), ("gamma_y", COEF_FN), ("dplus_x", COEF_FN), ("dminus_x", COEF_FN),
+        ("dplus_y", COEF_FN), ("dminus_y", COEF_FN), ("coef_user", c_void_p),
+        ("phi", IC2_FN), ("phi_user", c_void_p), ("f", SRC2_FN), ("f_user", c_void_p),
+        ("rtol", c_double), ("maxit", c_int32), ("flags", c_int32),
+    ]
+
+
 class tsfcde_net_sample(ctypes.Structure):
     _fields_ = [
         ("u_next", c_void_p), ("u0", c_void_p), ("u1", c_void_p), ("u2", c_void_p),
@@ -131,16 +146,30 @@ _SIGS = {
     "tsfcde_net_predict": (c_int32, [c_void_p, POINTER(tsfcde_net_sample), c_int64, c_void_p]),
     "tsfcde_plan_set_net": (c_int32, [c_void_p, c_void_p]),
     "tsfcde_net_destroy": (c_int32, [c_void_p]),
+    "tsfcde2d_workspace_bytes": (c_int32, [POINTER(tsfcde2d_problem), POINTER(c_size_t)]),
+    "tsfcde2d_plan": (c_int32, [POINTER(tsfcde2d_problem), c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
+    "tsfcde2d_set_state": (c_int32, [c_void_p, c_int64, c_void_p]),
+    "tsfcde2d_step": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(tsfcde_stats)]),
+    "tsfcde2d_solve": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, POINTER(tsfcde_stats)]),
+    "tsfcde2d_apply": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_void_p]),
+    "tsfcde2d_nodes": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double)]),
+    "tsfcde2d_level_time": (c_double, [c_void_p, c_int64]),
+    "tsfcde2d_level": (c_int64, [c_void_p]),
+    "tsfcde2d_history": (c_void_p, [c_void_p]),
+    "tsfcde2d_destroy": (c_int32, [c_void_p]),
 }
 
 _LIB = None
 
 
-def header_symbols(path: str = HEADER):
-    """Names of the functions declared in include/tsfcde.h."""
-    text = open(path).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tsfcde_[a-z_]+)\s*\(", text)) - {"tsfcde_coef_fn", "tsfcde_ic_fn", "tsfcde_src_fn"})
+def header_symbols(paths=None):
+    """Names of the functions declared in include/tsfcde.h and include/tsfcde2d.h."""
+    names = set()
+    for path in (paths or HEADERS):
+        text = open(path).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(tsfcde2?d?_[a-z0-9_]+)\s*\(", text))
+    return sorted(names - {"tsfcde_coef_fn", "tsfcde_ic_fn", "tsfcde_src_fn", "tsfcde2d_ic_fn", "tsfcde2d_src_fn"})
 
 
 def lib():

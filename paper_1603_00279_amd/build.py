@@ -30,9 +30,9 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    src = os.path.join(CSRC, "tsfcde.hip")
+    srcs = [os.path.join(CSRC, "tsfcde.hip"), os.path.join(CSRC, "tsfcde2d.hip")]
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), src, "-o", tmp]
+    cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

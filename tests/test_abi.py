@@ -138,3 +138,66 @@ def test_header_constants_match_binding(N):
         assert getattr(N, name) == value, (name, getattr(N, name), value)
         found += 1
     assert found >= 20
+
+
+def _problem2d(N, keep, **kw):
+    cb = N.COEF_FN(lambda t, _u: 1.0)
+    keep.append(cb)
+    p = N.tsfcde2d_problem(alpha=0.5, beta_x=1.5, beta_y=1.7, a=0.0, b=1.0, c=0.0, d=2.0, T=1.0, nx=64, ny=32, M=8)
+    for name in ("gamma_x", "gamma_y", "dplus_x", "dminus_x", "dplus_y", "dminus_y"):
+        setattr(p, name, cb)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("alpha", 0.0, -1), ("beta_x", 1.0, -1), ("beta_y", 2.5, -1), ("d", 0.0, -1), ("T", 0.0, -1), ("M", 0, -1),
+    ("nx", 0, -1), ("nx", 48, -8), ("ny", 8, -8), ("ny", 2048, -8), ("nx", 1024, 0), ("ny", 16, 0),
+])
+def test_2d_validation(N, field, value, code):
+    keep = []
+    p = _problem2d(N, keep, **{field: value})
+    nb = ctypes.c_size_t(0)
+    assert N.lib().tsfcde2d_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == code
+    if code == 0:
+        assert nb.value >= 8 * (p.M + 1) * p.nx * p.ny
+
+
+def test_2d_missing_callback_and_null_plan(N):
+    keep = []
+    p = _problem2d(N, keep)
+    p.dminus_y = N.COEF_FN()
+    nb = ctypes.c_size_t(0)
+    L = N.lib()
+    assert L.tsfcde2d_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == -1
+    assert L.tsfcde2d_destroy(None) == -1
+    assert L.tsfcde2d_level(None) == -1
+    assert L.tsfcde2d_history(None) is None
+    assert L.tsfcde2d_step(None, None, None, None) == -1
+    assert L.tsfcde2d_apply(None, 0, 0, None, None) == -1
+    import math
+    assert math.isnan(L.tsfcde2d_level_time(None, 0))
+
+
+def test_2d_struct_layout_matches_c(N, tmp_path):
+    import os
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tsfcde2d.h"', "int main(void) {"]
+    for fname, _ in N.tsfcde2d_problem._fields_:
+        lines.append(f'printf("{fname} %zu\\n", offsetof(tsfcde2d_problem, {fname}));')
+    lines.append('printf("size %zu\\n", sizeof(tsfcde2d_problem)); return 0; }')
+    src = tmp_path / "layout2d.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout2d"
+    subprocess.run([gcc, "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               check=True).stdout.split("\n") if line)
+    for fname, _ in N.tsfcde2d_problem._fields_:
+        assert int(out[fname]) == getattr(N.tsfcde2d_problem, fname).offset, fname
+    assert int(out["size"]) == ctypes.sizeof(N.tsfcde2d_problem)

@@ -1,0 +1,130 @@
+"""GPU parity of the two-dimensional solver (include/tsfcde2d.h) against the
+2D oracle: the operators A, B and P^{-1} on random arrays, whole marches
+against the dense direct solves, sampled points at 1024 x 1024, exchange of
+the axes, the f callback and the zero problem."""
+import numpy as np
+import pytest
+import torch
+
+import oracle.ids2d_oracle as O2
+import workloads as W
+from gpu_util import banner, host, need_gpu, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    import paper_1603_00279_amd as P
+    P.lib()
+
+
+def solver(prob, **kw):
+    import paper_1603_00279_amd as P
+    return P.TimeLevelSolver2D.from_problem(prob, **kw)
+
+
+def sources(s, prob):
+    x, y = s.nodes()
+    return W.device_sources_2d(prob, x, y, s.level_times(), torch.device("cuda"))
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 16), (32, 64), (128, 32), (256, 256)])
+def test_operators_match_oracle(nx, ny):
+    import paper_1603_00279_amd as P
+    banner(f"2d operators {nx}x{ny}")
+    prob = W.problem_2d(nx, ny, 6, beta_x=1.8, beta_y=1.3)
+    rng = np.random.default_rng(nx + 7 * ny)
+    X = rng.standard_normal((nx, ny))
+    with solver(prob) as s:
+        for j in (0, 5):
+            S = O2.anorm2(prob, j) * np.max(np.abs(X))
+            for op, which in ((P.TSFCDE_OP_A, "A"), (P.TSFCDE_OP_B, "B")):
+                got = host(s.apply(op, j, torch.as_tensor(X, device="cuda")))
+                d = np.max(np.abs(got - O2.product2(prob, j, X, which)))
+                print(f"[2d {nx}x{ny}] j={j} {which}: max|diff|/S = {d / S:.2e}", flush=True)
+                assert d <= 1e-13 * S, (j, which, d / S)
+            Y = host(s.apply(P.TSFCDE_OP_PINV, j, torch.as_tensor(X, device="cuda")))
+            eig = O2.bccb_eigenvalues(prob, j)
+            back = np.fft.ifft2(np.fft.fft2(Y) * eig).real  # P Y by the oracle's eigenvalues
+            SY = np.max(np.abs(eig)) * np.max(np.abs(Y))
+            d = np.max(np.abs(back - X))
+            print(f"[2d {nx}x{ny}] j={j} P^-1: max|P y - x| / S = {d / SY:.2e}", flush=True)
+            assert d <= 1e-13 * SY, (j, d / SY)
+
+
+@pytest.mark.parametrize("nx,ny,M", [(16, 16, 8), (32, 16, 5), (16, 64, 4)])
+def test_march_matches_dense_oracle(nx, ny, M):
+    """Every level against the oracle's dense direct solves (its own sampling
+    of f and its own history sum); the levels are accepted."""
+    banner(f"2d march {nx}x{ny} M={M}")
+    prob = W.problem_2d(nx, ny, M, alpha=0.7, beta_x=1.8, beta_y=1.5)
+    with solver(prob, rtol=1e-12) as s:
+        code, stats = s.solve(sources(s, prob))
+        U = host(s.history())
+    assert code == 0, stats
+    Uref = O2.march2(prob)
+    for j in range(1, M + 1):
+        e = relerr(U[j], Uref[j])
+        ee = np.max(np.abs(U[j] - Uref[j])) / np.max(np.abs(Uref[j]))
+        assert e < 1e-10 and ee < 1e-10, (j, e, ee)
+    print(f"[2d march {nx}x{ny}] worst rel err {max(relerr(U[j], Uref[j]) for j in range(1, M + 1)):.2e}, "
+          f"iterations {[st['iters'] for st in stats]}", flush=True)
+    for st in stats:
+        assert st["relres_true"] <= 1e-12 or 0.0 <= st["backward_err"] <= 1e-13, st
+
+
+def test_axes_exchanged_give_the_transpose():
+    banner("2d axis exchange")
+    prob = W.problem_2d(64, 32, 3, beta_x=1.3, beta_y=1.9)
+    with solver(prob, rtol=1e-13) as s:
+        s.solve(sources(s, prob))
+        U = host(s.history())
+    ps = prob.swapped()
+    with solver(ps, rtol=1e-13) as s:
+        s.solve(sources(s, ps))
+        Us = host(s.history())
+    assert Us.shape == (4, 32, 64)
+    assert np.max(np.abs(Us - np.transpose(U, (0, 2, 1)))) <= 1e-10 * np.max(np.abs(U))
+
+
+def test_callback_source_and_zero_problem():
+    banner("2d callback and zero problem")
+    prob = W.problem_2d(32, 32, 3)
+    with solver(prob, rtol=1e-12) as s:
+        s.solve(sources(s, prob))
+        U1 = host(s.history())
+    with solver(prob, rtol=1e-12, f=lambda x, y, t: float(prob.f(np.array([x]), np.array([y]), t)[0, 0])) as s:
+        s.solve(None)
+        U2 = host(s.history())
+    assert relerr(U2, U1) < 1e-12
+    z = W.problem_2d(16, 32, 3)
+    with solver(z, with_phi=False) as s:
+        code, stats = s.solve(torch.zeros(3, 16, 32, dtype=torch.float64, device="cuda"))
+        U = host(s.history())
+    assert code == 0 and np.all(U == 0.0) and all(st["iters"] == 0 for st in stats)
+
+
+def test_large_sampled_points():
+    """1024 x 1024 (2^20 unknowns), two levels: acceptance and the oracle's
+    point residuals g - A u^{j+1} (its own sampling of f) against the row
+    scale |A| max|u|."""
+    banner("2d 1024x1024")
+    prob = W.problem_2d(1024, 1024, 8)
+    rng = np.random.default_rng(5)
+    pts = [(0, 0), (1023, 1023), (0, 1023), (1023, 0), (511, 512)] + [tuple(v) for v in rng.integers(0, 1024, (11, 2))]
+    with solver(prob) as s:
+        F = sources(s, prob)
+        stats = [s.step(F[j]) for j in range(2)]
+        U = host(s.history()[:3])
+    for j in range(2):
+        st = stats[j]
+        print(f"[2d 1024x1024] j={j} iters {st['iters']} relres_true {st['relres_true']:.2e} "
+              f"backward_err {st['backward_err']:.2e}", flush=True)
+        assert st["code"] == 0 and st["iters"] > 0, st
+        assert st["relres_true"] <= 1e-10 or 0.0 <= st["backward_err"] <= 1e-13, st
+        f = O2.source_level(prob, j)
+        r = O2.rhs2_points(prob, U, j, f, pts) - O2.apply_A2_points(prob, j, U[j + 1], pts, "A")
+        S = O2.anorm2(prob, j) * np.max(np.abs(U[j + 1]))
+        assert np.max(np.abs(r)) <= 1e-12 * S, (j, np.max(np.abs(r)) / S)
