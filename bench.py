@@ -109,7 +109,7 @@ def acceptance(stats):
                 "max_relres_true": float(tr.max()) if tr.size else None, "restarts": int(st["restarts"].sum())}
     bw = [st["backward_err"] for st in stats if st["backward_err"] >= 0]
     tr = [st["relres_true"] for st in stats if st["relres_true"] >= 0]
-    return {"levels": len(stats), "failed_levels": sum(1 for st in stats if st["code"] != 0),
+    return {"levels": len(stats), "failed_levels": sum(1 for st in stats if st.get("code", st["status"]) != 0),
             "max_backward_err": max(bw) if bw else None, "max_relres_true": max(tr) if tr else None,
             "restarts": sum(st["restarts"] for st in stats)}
 
@@ -155,7 +155,62 @@ def forms(args, P, W, prob, F, u0, levels, plain_value, dev):
         res["constant_gsf"] = gsf_form(args, P, W, dev)
     if args.form in ("all", "history"):
         res["fast_history"] = history_form(args, P, prob, F, u0, levels, plain_value)
+    if args.form in ("all", "2d"):
+        res["two_dimensional"] = two_d_form(args, P, W, dev)
     return res
+
+
+def path_bytes_2d(N, levels, iters, restarts=0):
+    """Algorithmic HBM bytes of a two-dimensional march of ``levels`` levels
+    on N = nx ny unknowns, FP64, as the kernels move them (units of 8N):
+    a CGS iteration makes two BCCB solves (row transform: read 1, write the
+    complex spectrum 2; column pass: 2 + 2; inverse row pass: 2 + 1), two
+    Kronecker-sum products (y lines: read 1, write 1; x lines: read 2, write
+    1) and the vector updates (5 + 2 + 4 + 7): 48 units; a level adds the
+    history (j + 2 units at level j >= 1), the right-hand side (product 5,
+    rhs 6, zero guess 1) and each acceptance check (product 5, residual 5)."""
+    hist = sum(j + 2 for j in range(1, levels))
+    return 8 * N * (48 * sum(iters) + 12 * levels + 10 * (levels + restarts) + hist)
+
+
+def two_d_form(args, P, W, dev, nx=1024, ny=1024, M=32):
+    """The two-dimensional extension at nx = ny = 1024 (N = 2^20 unknowns,
+    the headline's count), M levels of the 2D family (alpha = 0.6, beta_x =
+    1.7, beta_y = 1.4), zero initial guess, rtol as the headline; sources on
+    the device before timing.  The working set (about 20 vectors of 8 MiB)
+    fits in the 256 MiB Infinity Cache, so the byte rate can exceed HBM's."""
+    import numpy as np
+    import torch
+    prob = W.problem_2d(nx, ny, M)
+    with P.TimeLevelSolver2D.from_problem(prob, rtol=args.rtol) as s2:
+        x, y = s2.nodes()
+        F = W.device_sources_2d(prob, x, y, s2.level_times(), dev)
+        u0 = s2.history()[0].clone()
+        dts, st = [], None
+        for _ in range(3):  # the first march warms up
+            s2.set_state(0, u0.view(1, nx, ny))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            code, st = s2.solve(F, raise_on_error=False)
+            torch.cuda.synchronize()
+            dts.append(time.perf_counter() - t0)
+    dt = min(dts[1:])
+    iters = [int(q["iters"]) for q in st]
+    restarts = int(sum(int(q["restarts"]) for q in st))
+    nbytes = path_bytes_2d(nx * ny, M, iters, restarts)
+    out = {"workload": f"nx=ny={nx}, M={M}, alpha={prob.alpha}, beta_x={prob.beta_x}, beta_y={prob.beta_y}, "
+                       "seeded manufactured solution, zero guess, BCCB Strang preconditioner",
+           "value": M / dt, "unit": "level-solves/s", "code": int(code),
+           "cgs_iterations": {"mean": float(np.mean(iters)), "min": int(min(iters)), "max": int(max(iters))},
+           "ms_per_cgs_iteration": 1e3 * dt / max(1, sum(iters)),
+           "path_roofline": {"bound": "hbm", "bytes_per_march": nbytes, "achieved": nbytes / dt / 1e9,
+                             "peak": 8000.0, "unit": "GB/s", "frac": nbytes / dt / 1e9 / 8000.0,
+                             "model": "48 x 8N B per CGS iteration; 22 x 8N B per level plus the history"},
+           "acceptance": acceptance(st)}
+    log(f"form two_dimensional: {M / dt:.1f} level-solves/s, {np.mean(iters):.1f} iterations, "
+        f"{out['path_roofline']['achieved']:.0f} GB/s by the byte model")
+    del F
+    return out
 
 
 def history_form(args, P, prob, F, u0, levels, plain_value):
@@ -449,7 +504,7 @@ def main():
     ap.add_argument("--profile-period", type=int, default=7,
                     help="events on every k-th launch of the profiled class (1 = all)")
     ap.add_argument("--fp32-n", type=int, default=2048, help="grid of the FP32-refined form inside its envelope")
-    ap.add_argument("--form", default="all", choices=["all", "warm", "fp32", "batched", "learned", "krylov", "gsf", "history"],
+    ap.add_argument("--form", default="all", choices=["all", "warm", "fp32", "batched", "learned", "krylov", "gsf", "history", "2d"],
                     help="which of the other forms to run (for profiling one of them)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-M", type=int, default=128)

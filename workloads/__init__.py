@@ -25,4 +25,7 @@ from .problems import (  # noqa: F401
     Problem2D,
     problem_2d,
     device_sources_2d,
+    Problem3D,
+    problem_3d,
+    device_sources_3d,
 )

@@ -432,3 +432,128 @@ def problem_2d(nx: int, ny: int, M: int, alpha: float = 0.6, beta_x: float = 1.7
                      sol_x=ManufacturedSolution([(A, 2.0)], _x2_one_minus_x2()),
                      sol_y=ManufacturedSolution([(1.0, 0.0)], _x2_one_minus_x2()),
                      name=f"2d(nx={nx}, ny={ny}, M={M})")
+
+
+# ---------------------------------------------------------------------------
+# Three space dimensions: the same operator on each of x, y, z,
+#   D_t^alpha u = sum_axes [ g u_axis + dp D_{lo+}^b u + dm D_{hi-}^b u ] + f
+# on a box, u = 0 on its boundary, u(., 0) = phi.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Problem3D:
+    """Problem (1.1) in three space dimensions with its discretisation sizes.
+
+    Per-axis data are tuples in axis order (x, y, z); arrays of the solution
+    are (nx, ny, nz), z fastest when flattened.  A manufactured solution is
+    u = theta(t) Px(x) Py(y) Pz(z) from ``sols`` (theta from sols[0])."""
+
+    alpha: float
+    betas: Tuple[float, float, float]
+    ns: Tuple[int, int, int]
+    M: int
+    gammas: Tuple[Callable[[float], float], ...]
+    dpluses: Tuple[Callable[[float], float], ...]
+    dminuses: Tuple[Callable[[float], float], ...]
+    lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    hi: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    T: float = 1.0
+    sols: Optional[Tuple[ManufacturedSolution, ...]] = None
+    name: str = ""
+
+    @property
+    def N(self) -> int:
+        return int(self.ns[0] * self.ns[1] * self.ns[2])
+
+    def axis(self, k: int) -> Problem:
+        """The one-dimensional problem along axis k (coefficients, order,
+        interval and grid of that axis; no source)."""
+        return Problem(alpha=self.alpha, beta=self.betas[k], n=self.ns[k], M=self.M, gamma=self.gammas[k],
+                       dplus=self.dpluses[k], dminus=self.dminuses[k], a=self.lo[k], b=self.hi[k], T=self.T)
+
+    def permuted(self, perm) -> "Problem3D":
+        """The same problem with its axes reordered: new axis k is old axis
+        perm[k] (the solution array is transposed by perm)."""
+        pk = lambda v: tuple(v[p] for p in perm)  # noqa: E731
+        sols = None
+        if self.sols is not None:
+            theta = self.sols[0].theta_terms
+            sols = tuple(ManufacturedSolution(theta if k == 0 else [(1.0, 0.0)], self.sols[p].poly_s,
+                                              self.sols[p].a, self.sols[p].b) for k, p in enumerate(perm))
+        return Problem3D(alpha=self.alpha, betas=pk(self.betas), ns=pk(self.ns), M=self.M, gammas=pk(self.gammas),
+                         dpluses=pk(self.dpluses), dminuses=pk(self.dminuses), lo=pk(self.lo), hi=pk(self.hi),
+                         T=self.T, sols=sols, name=self.name + f" (axes {tuple(perm)})")
+
+    def theta(self, t):
+        return self.sols[0].theta(t)
+
+    def _outer(self, a, b, c):
+        return a[:, None, None] * b[None, :, None] * c[None, None, :]
+
+    def phi(self, x, y, z) -> np.ndarray:
+        if self.sols is None:
+            return np.zeros((len(x), len(y), len(z)))
+        return self.theta(0.0) * self._outer(self.sols[0].P(x), self.sols[1].P(y), self.sols[2].P(z))
+
+    def exact(self, x, y, z, t) -> np.ndarray:
+        return self.theta(t) * self._outer(self.sols[0].P(x), self.sols[1].P(y), self.sols[2].P(z))
+
+    def source_terms(self, x, y, z, t):
+        """(coeffs[10], (X[10, nx], Y[10, ny], Z[10, nz])) with f(x_i, y_k, z_l, t)
+        = sum_m coeffs[m] X[m, i] Y[m, k] Z[m, l]: the Caputo derivative of
+        theta times P, then per axis the convection and the two Riemann-
+        Liouville terms (closed forms of the separable solution)."""
+        pts = (x, y, z)
+        th = self.theta(t)
+        P = [s.P(q) for s, q in zip(self.sols, pts)]
+        co = [self.sols[0].caputo_theta(t, self.alpha)]
+        fac = [list(P)]
+        for k in range(3):
+            s, q, b = self.sols[k], pts[k], self.betas[k]
+            for c, Fk in ((-th * self.gammas[k](t), s.dP(q)), (-th * self.dpluses[k](t), s.rl_left(q, b)),
+                          (-th * self.dminuses[k](t), s.rl_right(q, b))):
+                co.append(c)
+                row = list(P)
+                row[k] = Fk
+                fac.append(row)
+        co = np.array(co)
+        return co, tuple(np.stack([r[k] for r in fac]) for k in range(3))
+
+    def f(self, x, y, z, t) -> np.ndarray:
+        if self.sols is None:
+            return np.zeros((len(x), len(y), len(z)))
+        co, (X, Y, Z) = self.source_terms(x, y, z, t)
+        return np.einsum("m,mi,mk,ml->ikl", co, X, Y, Z)
+
+
+def device_sources_3d(prob: Problem3D, x, y, z, ts, device):
+    """f at the nodes (x, y, z) and every instant in ``ts`` as an FP64 torch
+    tensor (len(ts), nx, ny, nz) on ``device``, from the separable form."""
+    import torch
+    out = []
+    for t in ts:
+        co, (X, Y, Z) = prob.source_terms(np.asarray(x, dtype=np.float64), np.asarray(y, dtype=np.float64),
+                                          np.asarray(z, dtype=np.float64), float(t))
+        Xd = torch.as_tensor(co[:, None] * X, dtype=torch.float64, device=device)
+        Yd = torch.as_tensor(Y, dtype=torch.float64, device=device)
+        Zd = torch.as_tensor(Z, dtype=torch.float64, device=device)
+        XY = (Xd[:, :, None] * Yd[:, None, :]).reshape(len(co), -1)  # (m, nx*ny)
+        out.append((XY.T @ Zd).reshape(len(x), len(y), len(z)))
+    return torch.stack(out).contiguous()
+
+
+def problem_3d(nx: int, ny: int, nz: int, M: int, alpha: float = 0.6, betas=(1.7, 1.4, 1.85),
+               seed: int = SEED_BASE + 6) -> Problem3D:
+    """A 3D instance of the headline family: gamma = (-(1+t)/2, (1+t)/4,
+    -(1+t)/3) per axis, d_+- = c_+- (1+t) with seed-drawn c ~ U(0.5, 2) per
+    axis and side, amplitude A ~ U(0.5, 2); u = A t^2 prod_axes s^2 (1-s)^2."""
+    rng = np.random.default_rng(seed)
+    c = [float(v) for v in rng.uniform(0.5, 2.0, size=7)]
+    A = c[6]
+    sol = lambda theta: ManufacturedSolution(theta, _x2_one_minus_x2())  # noqa: E731
+    return Problem3D(alpha=alpha, betas=tuple(float(b) for b in betas), ns=(nx, ny, nz), M=M,
+                     gammas=(lambda t: -(1.0 + t) / 2.0, lambda t: (1.0 + t) / 4.0, lambda t: -(1.0 + t) / 3.0),
+                     dpluses=tuple((lambda t, cc=c[2 * k]: cc * (1.0 + t)) for k in range(3)),
+                     dminuses=tuple((lambda t, cc=c[2 * k + 1]: cc * (1.0 + t)) for k in range(3)),
+                     sols=(sol([(A, 2.0)]), sol([(1.0, 0.0)]), sol([(1.0, 0.0)])),
+                     name=f"3d(nx={nx}, ny={ny}, nz={nz}, M={M})")
