@@ -17,4 +17,5 @@ from ._native import (  # noqa: F401
 )
 from .solver import BatchSolver, TimeLevelSolver  # noqa: F401
 from .solver2d import TimeLevelSolver2D  # noqa: F401
+from .solver3d import TimeLevelSolver3D  # noqa: F401
 from .warmnet import WarmStartNet  # noqa: F401

@@ -17,13 +17,15 @@ import torch  # noqa: F401  -- must precede loading the HIP library
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libtsfcde.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "tsfcde.h")
-HEADERS = [HEADER, os.path.join(os.path.dirname(PKG), "include", "tsfcde2d.h")]
+HEADERS = [HEADER] + [os.path.join(os.path.dirname(PKG), "include", h) for h in ("tsfcde2d.h", "tsfcde3d.h")]
 
 COEF_FN = ctypes.CFUNCTYPE(c_double, c_double, c_void_p)
 IC_FN = ctypes.CFUNCTYPE(c_double, c_double, c_void_p)
 SRC_FN = ctypes.CFUNCTYPE(c_double, c_double, c_double, c_void_p)
 IC2_FN = ctypes.CFUNCTYPE(c_double, c_double, c_double, c_void_p)
 SRC2_FN = ctypes.CFUNCTYPE(c_double, c_double, c_double, c_double, c_void_p)
+IC3_FN = ctypes.CFUNCTYPE(c_double, c_double, c_double, c_double, c_void_p)
+SRC3_FN = ctypes.CFUNCTYPE(c_double, c_double, c_double, c_double, c_double, c_void_p)
 
 TSFCDE_OK = 0
 STATUS = {0: "TSFCDE_OK", -1: "TSFCDE_EINVAL", -2: "TSFCDE_ENOMEM", -3: "TSFCDE_EDEVICE",
@@ -94,6 +96,16 @@ class tsfcde2d_problem(ctypes.Structure):
     ]
 
 
+class tsfcde3d_problem(ctypes.Structure):
+    _fields_ = [
+        ("alpha", c_double), ("beta", c_double * 3), ("lo", c_double * 3), ("hi", c_double * 3), ("T", c_double),
+        ("n", c_int64 * 3), ("M", c_int64),
+        ("gamma", COEF_FN * 3), ("dplus", COEF_FN * 3), ("dminus", COEF_FN * 3), ("coef_user", c_void_p),
+        ("phi", IC3_FN), ("phi_user", c_void_p), ("f", SRC3_FN), ("f_user", c_void_p),
+        ("rtol", c_double), ("maxit", c_int32), ("flags", c_int32),
+    ]
+
+
 class tsfcde_net_sample(ctypes.Structure):
     _fields_ = [
         ("u_next", c_void_p), ("u0", c_void_p), ("u1", c_void_p), ("u2", c_void_p),
@@ -157,19 +169,31 @@ _SIGS = {
     "tsfcde2d_level": (c_int64, [c_void_p]),
     "tsfcde2d_history": (c_void_p, [c_void_p]),
     "tsfcde2d_destroy": (c_int32, [c_void_p]),
+    "tsfcde3d_workspace_bytes": (c_int32, [POINTER(tsfcde3d_problem), POINTER(c_size_t)]),
+    "tsfcde3d_plan": (c_int32, [POINTER(tsfcde3d_problem), c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
+    "tsfcde3d_set_state": (c_int32, [c_void_p, c_int64, c_void_p]),
+    "tsfcde3d_step": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(tsfcde_stats)]),
+    "tsfcde3d_solve": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, POINTER(tsfcde_stats)]),
+    "tsfcde3d_apply": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_void_p]),
+    "tsfcde3d_nodes": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
+    "tsfcde3d_level_time": (c_double, [c_void_p, c_int64]),
+    "tsfcde3d_level": (c_int64, [c_void_p]),
+    "tsfcde3d_history": (c_void_p, [c_void_p]),
+    "tsfcde3d_destroy": (c_int32, [c_void_p]),
 }
 
 _LIB = None
 
 
 def header_symbols(paths=None):
-    """Names of the functions declared in include/tsfcde.h and include/tsfcde2d.h."""
+    """Names of the functions declared in include/tsfcde.h, tsfcde2d.h and tsfcde3d.h."""
     names = set()
     for path in (paths or HEADERS):
         text = open(path).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        names |= set(re.findall(r"\b(tsfcde2?d?_[a-z0-9_]+)\s*\(", text))
-    return sorted(names - {"tsfcde_coef_fn", "tsfcde_ic_fn", "tsfcde_src_fn", "tsfcde2d_ic_fn", "tsfcde2d_src_fn"})
+        names |= set(re.findall(r"\b(tsfcde(?:[23]d)?_[a-z0-9_]+)\s*\(", text))
+    return sorted(names - {"tsfcde_coef_fn", "tsfcde_ic_fn", "tsfcde_src_fn", "tsfcde2d_ic_fn", "tsfcde2d_src_fn",
+                           "tsfcde3d_ic_fn", "tsfcde3d_src_fn"})
 
 
 def lib():

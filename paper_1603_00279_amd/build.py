@@ -30,7 +30,7 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, "tsfcde.hip"), os.path.join(CSRC, "tsfcde2d.hip")]
+    srcs = [os.path.join(CSRC, "tsfcde.hip"), os.path.join(CSRC, "tsfcde_nd.hip")]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), *srcs, "-o", tmp]
     if verbose:

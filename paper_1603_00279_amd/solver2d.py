@@ -102,6 +102,10 @@ class TimeLevelSolver2D:
         N.check(self._lib.tsfcde2d_set_state(self._plan, level, _dptr(U)), "tsfcde2d_set_state")
 
     def step(self, f: Optional[torch.Tensor] = None, u_out: Optional[torch.Tensor] = None, raise_on_error=True):
+        if f is not None and f.numel() != self.nx * self.ny:
+            raise ValueError("f must hold nx*ny values")
+        if u_out is not None and u_out.numel() != self.nx * self.ny:
+            raise ValueError("u_out must hold nx*ny values")
         st = N.tsfcde_stats()
         code = self._lib.tsfcde2d_step(self._plan, _dptr(f.contiguous() if f is not None else None), _dptr(u_out),
                                        ctypes.byref(st))
@@ -114,6 +118,8 @@ class TimeLevelSolver2D:
     def solve(self, F: Optional[torch.Tensor] = None, raise_on_error=True):
         """Every remaining level; F: (M, nx, ny) device sources or None."""
         nlev = self.M - self.level
+        if F is not None and F.numel() != self.M * self.nx * self.ny:
+            raise ValueError("F must hold M arrays of nx*ny values (row j for level j)")
         stats = (N.tsfcde_stats * max(nlev, 1))()
         ld = self.nx * self.ny
         code = self._lib.tsfcde2d_solve(self._plan, _dptr(F.contiguous() if F is not None else None), ld, None, stats)
@@ -122,6 +128,8 @@ class TimeLevelSolver2D:
         return code, [stats[k].as_dict() for k in range(nlev)]
 
     def apply(self, op: int, j: int, x: torch.Tensor) -> torch.Tensor:
+        if x.numel() != self.nx * self.ny:
+            raise ValueError("x must hold nx*ny values")
         x = x.contiguous()
         y = torch.empty_like(x)
         N.check(self._lib.tsfcde2d_apply(self._plan, op, j, _dptr(x), _dptr(y)), "tsfcde2d_apply")

@@ -201,3 +201,75 @@ def test_2d_struct_layout_matches_c(N, tmp_path):
     for fname, _ in N.tsfcde2d_problem._fields_:
         assert int(out[fname]) == getattr(N.tsfcde2d_problem, fname).offset, fname
     assert int(out["size"]) == ctypes.sizeof(N.tsfcde2d_problem)
+
+
+def _problem3d(N, keep, **kw):
+    cb = N.COEF_FN(lambda t, _u: 1.0)
+    keep.append(cb)
+    p = N.tsfcde3d_problem(alpha=0.5, T=1.0, M=8)
+    for k, (b, n) in enumerate(((1.5, 64), (1.7, 32), (1.2, 16))):
+        p.beta[k], p.n[k], p.lo[k], p.hi[k] = b, n, 0.0, 1.0 + k
+        p.gamma[k] = p.dplus[k] = p.dminus[k] = cb
+    for k, v in kw.items():
+        arr, idx = (k.rsplit("_", 1)[0], int(k.rsplit("_", 1)[1])) if k[-1].isdigit() else (k, None)
+        if idx is None:
+            setattr(p, k, v)
+        else:
+            getattr(p, arr)[idx] = v
+    return p
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("alpha", 1.5, -1), ("beta_0", 1.0, -1), ("beta_2", 2.01, -1), ("hi_1", 0.0, -1), ("T", -1.0, -1), ("M", 0, -1),
+    ("n_0", 0, -1), ("n_1", 24, -8), ("n_2", 8, -8), ("n_0", 2048, -8), ("n_2", 1024, 0), ("n_1", 16, 0),
+])
+def test_3d_validation(N, field, value, code):
+    keep = []
+    p = _problem3d(N, keep, **{field: value})
+    nb = ctypes.c_size_t(0)
+    assert N.lib().tsfcde3d_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == code
+    if code == 0:
+        assert nb.value >= 8 * (p.M + 1) * p.n[0] * p.n[1] * p.n[2]
+
+
+def test_3d_missing_callback_and_null_plan(N):
+    keep = []
+    p = _problem3d(N, keep)
+    p.dminus[2] = N.COEF_FN()
+    nb = ctypes.c_size_t(0)
+    L = N.lib()
+    assert L.tsfcde3d_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == -1
+    assert L.tsfcde3d_workspace_bytes(None, ctypes.byref(nb)) == -1
+    assert L.tsfcde3d_destroy(None) == -1
+    assert L.tsfcde3d_level(None) == -1
+    assert L.tsfcde3d_history(None) is None
+    assert L.tsfcde3d_step(None, None, None, None) == -1
+    assert L.tsfcde3d_solve(None, None, 0, None, None) == -1
+    assert L.tsfcde3d_apply(None, 0, 0, None, None) == -1
+    assert L.tsfcde3d_set_state(None, 0, None) == -1
+    assert L.tsfcde3d_nodes(None, None, None, None) == -1
+    import math
+    assert math.isnan(L.tsfcde3d_level_time(None, 0))
+
+
+def test_3d_struct_layout_matches_c(N, tmp_path):
+    import os
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tsfcde3d.h"', "int main(void) {"]
+    for fname, _ in N.tsfcde3d_problem._fields_:
+        lines.append(f'printf("{fname} %zu\\n", offsetof(tsfcde3d_problem, {fname}));')
+    lines.append('printf("size %zu\\n", sizeof(tsfcde3d_problem)); return 0; }')
+    src = tmp_path / "layout3d.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout3d"
+    subprocess.run([gcc, "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               check=True).stdout.split("\n") if line)
+    for fname, _ in N.tsfcde3d_problem._fields_:
+        assert int(out[fname]) == getattr(N.tsfcde3d_problem, fname).offset, fname
+    assert int(out["size"]) == ctypes.sizeof(N.tsfcde3d_problem)

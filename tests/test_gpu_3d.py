@@ -1,0 +1,153 @@
+"""GPU parity of the three-dimensional solver (include/tsfcde3d.h) against the
+3D oracle: the operators A, B and P^{-1} on random arrays, whole marches
+against the dense direct solves and (larger grids) the oracle's FFT-route
+PCGS, sampled points at 256^3, permutations of the axes, the f callback and
+the zero problem."""
+import numpy as np
+import pytest
+import torch
+
+import oracle.ids3d_oracle as O3
+import workloads as W
+from gpu_util import banner, host, need_gpu, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    import paper_1603_00279_amd as P
+    P.lib()
+
+
+def solver(prob, **kw):
+    import paper_1603_00279_amd as P
+    return P.TimeLevelSolver3D.from_problem(prob, **kw)
+
+
+def sources(s, prob):
+    x, y, z = s.nodes()
+    return W.device_sources_3d(prob, x, y, z, s.level_times(), torch.device("cuda"))
+
+
+@pytest.mark.parametrize("ns", [(16, 16, 16), (16, 32, 64), (64, 16, 32), (128, 64, 128)])
+def test_operators_match_oracle(ns):
+    import paper_1603_00279_amd as P
+    banner(f"3d operators {ns}")
+    prob = W.problem_3d(*ns, 6, betas=(1.8, 1.3, 1.55))
+    rng = np.random.default_rng(sum(ns))
+    X = rng.standard_normal(ns)
+    with solver(prob) as s:
+        for j in (0, 5):
+            S = O3.anorm3(prob, j) * np.max(np.abs(X))
+            for op, which in ((P.TSFCDE_OP_A, "A"), (P.TSFCDE_OP_B, "B")):
+                got = host(s.apply(op, j, torch.as_tensor(X, device="cuda")))
+                d = np.max(np.abs(got - O3.product3(prob, j, X, which)))
+                print(f"[3d {ns}] j={j} {which}: max|diff|/S = {d / S:.2e}", flush=True)
+                assert d <= 1e-13 * S, (j, which, d / S)
+            Y = host(s.apply(P.TSFCDE_OP_PINV, j, torch.as_tensor(X, device="cuda")))
+            eig = O3.bccb3_eigenvalues(prob, j)
+            back = np.fft.ifftn(np.fft.fftn(Y) * eig).real  # P Y by the oracle's eigenvalues
+            SY = np.max(np.abs(eig)) * np.max(np.abs(Y))
+            d = np.max(np.abs(back - X))
+            print(f"[3d {ns}] j={j} P^-1: max|P y - x| / S = {d / SY:.2e}", flush=True)
+            assert d <= 1e-13 * SY, (j, d / SY)
+
+
+def test_march_matches_dense_oracle():
+    """Every level of a 16^3 march against the oracle's dense direct solves
+    (its own sampling of f and its own history sum); the levels are accepted."""
+    banner("3d march 16^3 dense")
+    prob = W.problem_3d(16, 16, 16, 4, alpha=0.7, betas=(1.8, 1.5, 1.25))
+    with solver(prob, rtol=1e-12) as s:
+        code, stats = s.solve(sources(s, prob))
+        U = host(s.history())
+    assert code == 0, stats
+    Uref = O3.march3(prob)
+    for j in range(1, prob.M + 1):
+        e = relerr(U[j], Uref[j])
+        ee = np.max(np.abs(U[j] - Uref[j])) / np.max(np.abs(Uref[j]))
+        assert e < 1e-10 and ee < 1e-10, (j, e, ee)
+    print(f"[3d march 16^3] worst rel err {max(relerr(U[j], Uref[j]) for j in range(1, prob.M + 1)):.2e}, "
+          f"iterations {[st['iters'] for st in stats]}", flush=True)
+    for st in stats:
+        assert st["relres_true"] <= 1e-12 or 0.0 <= st["backward_err"] <= 1e-13, st
+
+
+@pytest.mark.parametrize("ns,M", [((32, 16, 64), 3), ((16, 128, 32), 2)])
+def test_march_matches_fft_oracle(ns, M):
+    """Larger grids against the oracle's FFT-route PCGS march (pinned against
+    the dense route), both solved to 1e-13."""
+    banner(f"3d march {ns} fft oracle")
+    prob = W.problem_3d(*ns, M, alpha=0.4, betas=(1.35, 1.9, 1.6))
+    with solver(prob, rtol=1e-13) as s:
+        code, stats = s.solve(sources(s, prob))
+        U = host(s.history())
+    assert code == 0, stats
+    Uref, its = O3.march_pcgs3(prob, rtol=1e-13)
+    worst = max(np.max(np.abs(U[j] - Uref[j])) / np.max(np.abs(Uref[j])) for j in range(1, M + 1))
+    print(f"[3d march {ns}] worst rel err {worst:.2e}, iterations {[st['iters'] for st in stats]} "
+          f"(oracle {its})", flush=True)
+    assert worst < 1e-10
+
+
+def test_permuted_axes_give_the_transpose():
+    banner("3d axis permutation")
+    prob = W.problem_3d(64, 16, 32, 3, betas=(1.3, 1.9, 1.6))
+    with solver(prob, rtol=1e-13) as s:
+        s.solve(sources(s, prob))
+        U = host(s.history())
+    perm = (2, 0, 1)
+    pp = prob.permuted(perm)
+    with solver(pp, rtol=1e-13) as s:
+        s.solve(sources(s, pp))
+        Up = host(s.history())
+    ref = np.transpose(U, (0, 3, 1, 2))
+    assert Up.shape == ref.shape
+    assert np.max(np.abs(Up - ref)) <= 1e-10 * np.max(np.abs(U))
+
+
+def test_callback_source_and_zero_problem():
+    banner("3d callback and zero problem")
+    prob = W.problem_3d(16, 32, 16, 3)
+    with solver(prob, rtol=1e-12) as s:
+        s.solve(sources(s, prob))
+        U1 = host(s.history())
+    f = lambda x, y, z, t: float(prob.f(np.array([x]), np.array([y]), np.array([z]), t)[0, 0, 0])  # noqa: E731
+    with solver(prob, rtol=1e-12, f=f) as s:
+        s.solve(None)
+        U2 = host(s.history())
+    assert relerr(U2, U1) < 1e-12
+    z = W.problem_3d(16, 16, 32, 3)
+    with solver(z, with_phi=False) as s:
+        code, stats = s.solve(torch.zeros(3, 16, 16, 32, dtype=torch.float64, device="cuda"))
+        U = host(s.history())
+    assert code == 0 and np.all(U == 0.0) and all(st["iters"] == 0 for st in stats)
+
+
+def test_large_sampled_points():
+    """256^3 (2^24 unknowns), two levels: acceptance and the oracle's point
+    residuals g - A u^{j+1} (its own sampling of f) against the row scale
+    |A| max|u|."""
+    banner("3d 256^3")
+    n = 256
+    prob = W.problem_3d(n, n, n, 8)
+    rng = np.random.default_rng(6)
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 0), (n - 1, 0, n - 1), (127, 128, 129)]
+    pts += [tuple(v) for v in rng.integers(0, n, (11, 3))]
+    with solver(prob) as s:
+        F = sources(s, prob)
+        stats = [s.step(F[j]) for j in range(2)]
+        del F
+        U = host(s.history()[:3])
+    for j in range(2):
+        st = stats[j]
+        print(f"[3d 256^3] j={j} iters {st['iters']} relres_true {st['relres_true']:.2e} "
+              f"backward_err {st['backward_err']:.2e}", flush=True)
+        assert st["code"] == 0 and st["iters"] > 0, st
+        assert st["relres_true"] <= 1e-10 or 0.0 <= st["backward_err"] <= 1e-13, st
+        f = O3.source_level(prob, j)
+        r = O3.rhs3_points(prob, U, j, f, pts) - O3.apply_A3_points(prob, j, U[j + 1], pts, "A")
+        S = O3.anorm3(prob, j) * np.max(np.abs(U[j + 1]))
+        assert np.max(np.abs(r)) <= 1e-12 * S, (j, np.max(np.abs(r)) / S)
