@@ -156,60 +156,84 @@ def forms(args, P, W, prob, F, u0, levels, plain_value, dev):
     if args.form in ("all", "history"):
         res["fast_history"] = history_form(args, P, prob, F, u0, levels, plain_value)
     if args.form in ("all", "2d"):
-        res["two_dimensional"] = two_d_form(args, P, W, dev)
+        res["two_dimensional"] = nd_form(args, P, W, dev, 2)
+    if args.form in ("all", "3d"):
+        res["three_dimensional"] = nd_form(args, P, W, dev, 3)
     return res
 
 
-def path_bytes_2d(N, levels, iters, restarts=0):
-    """Algorithmic HBM bytes of a two-dimensional march of ``levels`` levels
-    on N = nx ny unknowns, FP64, as the kernels move them (units of 8N):
-    a CGS iteration makes two BCCB solves (row transform: read 1, write the
-    complex spectrum 2; column pass: 2 + 2; inverse row pass: 2 + 1), two
-    Kronecker-sum products (y lines: read 1, write 1; x lines: read 2, write
-    1) and the vector updates (5 + 2 + 4 + 7): 48 units; a level adds the
-    history (j + 2 units at level j >= 1), the right-hand side (product 5,
-    rhs 6, zero guess 1) and each acceptance check (product 5, residual 5)."""
+def path_bytes_nd(d, N, levels, iters, restarts=0):
+    """Algorithmic HBM bytes of a march of ``levels`` levels of the d-axis
+    solver (d = 2, 3) on N unknowns, FP64, as its kernels move them (units of
+    8N).  A CGS iteration: the first preconditioner solve (fast-axis forward
+    pass with the u/p update: r, q, p in, u, p and the half spectrum out, 6;
+    then 2 per further pass: the middle axis twice in 3D, the division pass,
+    the inverse fast-axis pass), the product (fast axis 2, middle axis 3, the
+    slow axis with rt.vhat 4), the second solve (forward pass with the q
+    update: u, vhat in, q and the spectrum out, 4; then as before) and the
+    product with the x/r update (slow axis: uhat, w, rt, x, r in, x, r out,
+    7): 33 units in 2D, 47 in 3D.  A level adds its right-hand side and one
+    acceptance check per (re)start (products of 3d - 1 units each, the
+    right-hand side kernel 6, the zero guess 1, the residual 5) and the
+    history (j + 2 units at level j >= 1)."""
+    per_iter = {2: 33, 3: 47}[d]
     hist = sum(j + 2 for j in range(1, levels))
-    return 8 * N * (48 * sum(iters) + 12 * levels + 10 * (levels + restarts) + hist)
+    prod = 3 * d - 1
+    return 8 * N * (per_iter * sum(iters) + (prod + 7) * levels + (prod + 5) * (levels + restarts) + hist)
 
 
-def two_d_form(args, P, W, dev, nx=1024, ny=1024, M=32):
-    """The two-dimensional extension at nx = ny = 1024 (N = 2^20 unknowns,
-    the headline's count), M levels of the 2D family (alpha = 0.6, beta_x =
-    1.7, beta_y = 1.4), zero initial guess, rtol as the headline; sources on
-    the device before timing.  The working set (about 20 vectors of 8 MiB)
-    fits in the 256 MiB Infinity Cache, so the byte rate can exceed HBM's."""
+ND_FORMS = {2: dict(ns=(1024, 1024), M=32), 3: dict(ns=(256, 256, 256), M=8)}
+
+
+def nd_form(args, P, W, dev, d):
+    """The d-axis extension (d = 2: nx = ny = 1024, N = 2^20 unknowns, the
+    headline's count, M = 32; d = 3: 256^3, N = 2^24, M = 8) on its seeded
+    family (alpha = 0.6, one order per axis), zero initial guess, rtol as
+    the headline; sources on the device before timing.  Two timed marches
+    after a warm-up march; the faster counts.  At 2^20 unknowns the working
+    set (about 20 vectors of 8 MiB) fits in the 256 MiB Infinity Cache, so the
+    byte rate is not bounded by HBM; at 2^24 it is."""
     import numpy as np
     import torch
-    prob = W.problem_2d(nx, ny, M)
-    with P.TimeLevelSolver2D.from_problem(prob, rtol=args.rtol) as s2:
-        x, y = s2.nodes()
-        F = W.device_sources_2d(prob, x, y, s2.level_times(), dev)
-        u0 = s2.history()[0].clone()
-        dts, st = [], None
+    cfg = ND_FORMS[d]
+    ns, M = cfg["ns"], cfg["M"]
+    if d == 2:
+        prob = W.problem_2d(*ns, M)
+        Solver, src = P.TimeLevelSolver2D, W.device_sources_2d
+    else:
+        prob = W.problem_3d(*ns, M)
+        Solver, src = P.TimeLevelSolver3D, W.device_sources_3d
+    N = int(np.prod(ns))
+    with Solver.from_problem(prob, rtol=args.rtol) as sv:
+        F = src(prob, *sv.nodes(), sv.level_times(), dev)
+        u0 = sv.history()[0].clone()
+        dts, st, code = [], None, 0
         for _ in range(3):  # the first march warms up
-            s2.set_state(0, u0.view(1, nx, ny))
+            sv.set_state(0, u0.view((1,) + tuple(ns)))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            code, st = s2.solve(F, raise_on_error=False)
+            code, st = sv.solve(F, raise_on_error=False)
             torch.cuda.synchronize()
             dts.append(time.perf_counter() - t0)
+        del F
     dt = min(dts[1:])
     iters = [int(q["iters"]) for q in st]
     restarts = int(sum(int(q["restarts"]) for q in st))
-    nbytes = path_bytes_2d(nx * ny, M, iters, restarts)
-    out = {"workload": f"nx=ny={nx}, M={M}, alpha={prob.alpha}, beta_x={prob.beta_x}, beta_y={prob.beta_y}, "
-                       "seeded manufactured solution, zero guess, BCCB Strang preconditioner",
+    nbytes = path_bytes_nd(d, N, M, iters, restarts)
+    out = {"workload": f"{'x'.join(str(n) for n in ns)}, M={M}, alpha={prob.alpha}, "
+                       f"betas={(prob.beta_x, prob.beta_y) if d == 2 else prob.betas}, "
+                       "seeded manufactured solution, zero guess, multi-level circulant Strang preconditioner",
            "value": M / dt, "unit": "level-solves/s", "code": int(code),
            "cgs_iterations": {"mean": float(np.mean(iters)), "min": int(min(iters)), "max": int(max(iters))},
            "ms_per_cgs_iteration": 1e3 * dt / max(1, sum(iters)),
            "path_roofline": {"bound": "hbm", "bytes_per_march": nbytes, "achieved": nbytes / dt / 1e9,
                              "peak": 8000.0, "unit": "GB/s", "frac": nbytes / dt / 1e9 / 8000.0,
-                             "model": "48 x 8N B per CGS iteration; 22 x 8N B per level plus the history"},
+                             "model": f"{ {2: 33, 3: 47}[d]} x 8N B per CGS iteration, "
+                                      f"{6 * d + 10} x 8N B per level plus the history"},
            "acceptance": acceptance(st)}
-    log(f"form two_dimensional: {M / dt:.1f} level-solves/s, {np.mean(iters):.1f} iterations, "
-        f"{out['path_roofline']['achieved']:.0f} GB/s by the byte model")
-    del F
+    log(f"form {d}d: {M / dt:.2f} level-solves/s, {np.mean(iters):.1f} iterations, "
+        f"{out['ms_per_cgs_iteration']:.3f} ms per iteration, {out['path_roofline']['achieved']:.0f} GB/s "
+        "by the byte model")
     return out
 
 
@@ -504,7 +528,7 @@ def main():
     ap.add_argument("--profile-period", type=int, default=7,
                     help="events on every k-th launch of the profiled class (1 = all)")
     ap.add_argument("--fp32-n", type=int, default=2048, help="grid of the FP32-refined form inside its envelope")
-    ap.add_argument("--form", default="all", choices=["all", "warm", "fp32", "batched", "learned", "krylov", "gsf", "history", "2d"],
+    ap.add_argument("--form", default="all", choices=["all", "warm", "fp32", "batched", "learned", "krylov", "gsf", "history", "2d", "3d"],
                     help="which of the other forms to run (for profiling one of them)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-M", type=int, default=128)

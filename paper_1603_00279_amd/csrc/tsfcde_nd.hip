@@ -148,8 +148,8 @@ template <int NA> __device__ __forceinline__ void reduce_partials(const double *
 // ---------------------------------------------------------------------------
 // Line transforms.
 // ---------------------------------------------------------------------------
-template <int P, int NTL> struct LineGeo {
-    static constexpr int E = 8;       // values per lane
+template <int P, int NTL, int E_ = 8> struct LineGeo {
+    static constexpr int E = E_;      // values per lane
     static constexpr int T = P / E;   // lanes per line
     static constexpr int B = NTL / T;  // lines per workgroup
     static constexpr int LS = lpad_size(P);
@@ -184,10 +184,10 @@ template <class Op> struct OpSink {
 //   step; every thread calls it, and its result is uniform).
 // (four waves per SIMD: the register budget that lets the LDS-bound number
 // of workgroups per CU run together)
-template <int P, bool ROWS, int NTL, class Op>
+template <int P, bool ROWS, int NTL, class Op, int EV>
 __global__ void __launch_bounds__(NTL, 4) k_line(Op op, int64_t nlines, const double2 *__restrict__ tw_all, Sc *sc) {
     if (op.pred && sc->done) return;
-    using G = LineGeo<P, NTL>;
+    using G = LineGeo<P, NTL, EV>;
     constexpr int E = G::E, T = G::T, B = G::B, LS = G::LS;
     __shared__ double2 lds[B * LS];
     const int t = threadIdx.x;
@@ -859,24 +859,35 @@ int nblocks(int64_t N) { return (int)std::min<int64_t>(RBLK, (N + RB - 1) / RB);
     } while (0)
 
 // Launch of k_line, one tile per workgroup; returns the grid through
-// *grid_out.  Workgroups of 256 threads when 512-thread ones would not give
-// every CU two of them (small batches of lines: the same waves spread over
-// more CUs).
+// *grid_out.  Row passes take workgroups of 256 threads when 512-thread ones
+// would not give every CU two of them (small batches of lines: the same
+// waves spread over more CUs); strided passes keep 512 threads, whose wider
+// tiles (more adjacent lines) read longer runs of each row (measured: 11%
+// less time per CGS iteration at 1024 x 1024).
+// Eight values per lane in every pass: sixteen in the Toeplitz passes of 256
+// points and more (half the exchanges at 256, 1024 and 2048 points, twice the
+// LDS per workgroup) measured 13% slower per CGS iteration at 1024 x 1024 and
+// 22% at 256^3.
+template <class Op, int P> constexpr int line_e() { return 8; }
+
 template <int P, bool ROWS, int NTL, class Op>
 hipError_t line_g(NdPlan *pl, const Op &op, int64_t nlines, int *grid_out) {
-    using G = LineGeo<P, NTL>;
+    constexpr int EV = line_e<Op, P>();
+    using G = LineGeo<P, NTL, EV>;
     const int64_t grid = (nlines + G::B - 1) / G::B;
     if (grid < 1 || grid > INT32_MAX) return hipErrorInvalidValue;
     if (grid_out) *grid_out = (int)grid;
-    hipLaunchKernelGGL((k_line<P, ROWS, NTL, Op>), dim3((unsigned)grid), dim3(NTL), 0, pl->stream, op, nlines,
+    hipLaunchKernelGGL((k_line<P, ROWS, NTL, Op, EV>), dim3((unsigned)grid), dim3(NTL), 0, pl->stream, op, nlines,
                        (const double2 *)pl->tw, pl->sc);
     return hipGetLastError();
 }
 
 template <int P, bool ROWS, class Op>
 hipError_t line_t(NdPlan *pl, const Op &op, int64_t nlines, int *grid_out) {
-    constexpr int64_t T = P / 8;
-    if (nlines * T < int64_t(256) * 2 * NT) return line_g<P, ROWS, 256>(pl, op, nlines, grid_out);
+    constexpr int64_t T = P / line_e<Op, P>();
+    if constexpr (ROWS) {
+        if (nlines * T < int64_t(256) * 2 * NT) return line_g<P, ROWS, 256>(pl, op, nlines, grid_out);
+    }
     return line_g<P, ROWS, NT>(pl, op, nlines, grid_out);
 }
 
