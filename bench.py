@@ -109,7 +109,7 @@ def acceptance(stats):
                 "max_relres_true": float(tr.max()) if tr.size else None, "restarts": int(st["restarts"].sum())}
     bw = [st["backward_err"] for st in stats if st["backward_err"] >= 0]
     tr = [st["relres_true"] for st in stats if st["relres_true"] >= 0]
-    return {"levels": len(stats), "failed_levels": sum(1 for st in stats if st.get("code", st["status"]) != 0),
+    return {"levels": len(stats), "failed_levels": sum(1 for st in stats if (st["code"] if "code" in st else st["status"]) != 0),
             "max_backward_err": max(bw) if bw else None, "max_relres_true": max(tr) if tr else None,
             "restarts": sum(st["restarts"] for st in stats)}
 
