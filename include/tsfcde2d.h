@@ -65,7 +65,13 @@ typedef struct tsfcde2d_problem {
     void *f_user;
     double rtol;           /* CGS stop |r| <= rtol |g| (<= 0: 1e-10)          */
     int32_t maxit;         /* CGS iterations per level (<= 0: 500)            */
-    int32_t flags;         /* 0 (reserved)                                    */
+    int32_t warm_start;    /* CGS initial guess of each level: TSFCDE_WS_ZERO
+                              (as in Sec. 4), TSFCDE_WS_PREV (u^j) or
+                              TSFCDE_WS_EXTRAP (3u^j - 3u^{j-1} + u^{j-2};
+                              u^j at level 1, 0 at level 0); a nonzero guess
+                              goes through the acceptance test first and CGS
+                              restarts from it when it fails (EINVAL for
+                              other values)                                   */
 } tsfcde2d_problem;
 
 typedef struct tsfcde2d_plan_s *tsfcde2d_plan_t;
@@ -93,7 +99,7 @@ int tsfcde2d_plan(const tsfcde2d_problem *prob, void *d_workspace, size_t bytes,
 int tsfcde2d_set_state(tsfcde2d_plan_t plan, int64_t level, const double *d_U);
 
 /* One level (Algorithm 2's loop body): g = B u^j - history + f, then PCGS
- * on A u^{j+1} = g from u^{j+1} = 0; the level is accepted when the true
+ * on A u^{j+1} = g from the initial guess (warm_start); the level is accepted when the true
  * residual is within rtol |g| or the normwise backward error
  * |g - A u| / (|A| |u| + |g|) is at most 1e-13 (|A| bounded above by
  * eta + sigma sum over the axes of |gamma|/h + (d+ + d-) h^-beta

@@ -64,7 +64,8 @@ typedef struct tsfcde3d_problem {
     void *f_user;
     double rtol;            /* CGS stop |r| <= rtol |g| (<= 0: 1e-10)          */
     int32_t maxit;          /* CGS iterations per level (<= 0: 500)            */
-    int32_t flags;          /* 0 (reserved)                                    */
+    int32_t warm_start;     /* CGS initial guess, as in tsfcde2d_problem:
+                               TSFCDE_WS_ZERO, _PREV or _EXTRAP              */
 } tsfcde3d_problem;
 
 typedef struct tsfcde3d_plan_s *tsfcde3d_plan_t;
@@ -92,7 +93,7 @@ int tsfcde3d_plan(const tsfcde3d_problem *prob, void *d_workspace, size_t bytes,
 int tsfcde3d_set_state(tsfcde3d_plan_t plan, int64_t level, const double *d_U);
 
 /* One level (Algorithm 2's loop body): g = B u^j - history + f, then PCGS
- * on A u^{j+1} = g from u^{j+1} = 0, accepted as in tsfcde2d_step (true
+ * on A u^{j+1} = g from the initial guess (warm_start), accepted as in tsfcde2d_step (true
  * residual within rtol |g| or normwise backward error at most 1e-13, |A|
  * bounded above by eta + sigma sum over the three axes of |gamma|/h +
  * (d+ + d-) h^-beta sum_k |omega_k|, at most 3 restarts).  d_f: f at

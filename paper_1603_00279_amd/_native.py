@@ -92,7 +92,7 @@ class tsfcde2d_problem(ctypes.Structure):
         ("gamma_x", COEF_FN), ("gamma_y", COEF_FN), ("dplus_x", COEF_FN), ("dminus_x", COEF_FN),
         ("dplus_y", COEF_FN), ("dminus_y", COEF_FN), ("coef_user", c_void_p),
         ("phi", IC2_FN), ("phi_user", c_void_p), ("f", SRC2_FN), ("f_user", c_void_p),
-        ("rtol", c_double), ("maxit", c_int32), ("flags", c_int32),
+        ("rtol", c_double), ("maxit", c_int32), ("warm_start", c_int32),
     ]
 
 
@@ -102,7 +102,7 @@ class tsfcde3d_problem(ctypes.Structure):
         ("n", c_int64 * 3), ("M", c_int64),
         ("gamma", COEF_FN * 3), ("dplus", COEF_FN * 3), ("dminus", COEF_FN * 3), ("coef_user", c_void_p),
         ("phi", IC3_FN), ("phi_user", c_void_p), ("f", SRC3_FN), ("f_user", c_void_p),
-        ("rtol", c_double), ("maxit", c_int32), ("flags", c_int32),
+        ("rtol", c_double), ("maxit", c_int32), ("warm_start", c_int32),
     ]
 
 

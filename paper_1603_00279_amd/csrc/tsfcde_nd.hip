@@ -636,6 +636,18 @@ __global__ void __launch_bounds__(RB) k_hist(const double *__restrict__ U, int64
     }
 }
 
+// initial guess of level j: u^j (mode 1) or 3u^j - 3u^{j-1} + u^{j-2} (mode 2)
+__global__ void __launch_bounds__(RB) k_guess(const double *__restrict__ U, int64_t N, int j, int mode,
+                                              double *__restrict__ x) {
+    const double *uj = U + (int64_t)j * N;
+    if (mode == 1) {
+        TSFND_LOOP(i, N) x[i] = uj[i];
+    } else {
+        const double *u1 = uj - N, *u2 = uj - 2 * N;  // mode 2 only at j >= 2
+        TSFND_LOOP(i, N) x[i] = fma(3.0, uj[i] - u1[i], u2[i]);
+    }
+}
+
 // g = B u^j - H + f; r = rt = g (zero initial guess); partial |g|^2
 __global__ void __launch_bounds__(RB) k_rhs(const double *__restrict__ Bu, const double *__restrict__ H,
                                             const double *__restrict__ f, double *__restrict__ g,
@@ -764,7 +776,7 @@ struct NdPlan {
     int64_t n[3] = {1, 1, 1}, N = 0, M = 0, level = 0, W = 0, Nh = 0;
     double alpha = 0, T = 0, tau = 0, sigma = 0, kappa = 0, rtol = 1e-10;
     double beta[3] = {}, lo[3] = {}, h[3] = {}, hb[3] = {};
-    int maxit = 500, last_iters = 8;
+    int maxit = 500, last_iters = 8, warm = TSFCDE_WS_ZERO;
     std::vector<double> eta, anorm, cbase, clast, gam[3], dp[3], dm[3];
     tsfcde2d_src_fn f2 = nullptr;
     tsfcde3d_src_fn f3 = nullptr;
@@ -1178,7 +1190,22 @@ int level_step(NdPlan *pl, const double *d_f, double *d_u_out, tsfcde_stats *st)
     hipLaunchKernelGGL(k_rhs, dim3(nb), dim3(RB), 0, pl->stream, (const double *)pl->t,
                        (const double *)(j >= 1 ? pl->H : nullptr), d_f, pl->g, pl->r, pl->rt, N, pl->partv);
     hipLaunchKernelGGL(k_fin_rhs, dim3(1), dim3(RB), 0, pl->stream, (const double *)pl->partv, nb, pl->sc, pl->rtol);
-    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(RB), 0, pl->stream, x, N, 0.0);
+    // initial guess: zero, or u^j / the quadratic extrapolation, which goes
+    // through the acceptance check at once (the CGS passes are predicated off
+    // when it is accepted; otherwise CGS starts from it with r = g - A x0)
+    const int mode = pl->warm == TSFCDE_WS_PREV ? 1 : pl->warm == TSFCDE_WS_EXTRAP ? (j >= 2 ? 2 : (j >= 1 ? 1 : 0)) : 0;
+    const int guess = mode == 2 ? TSFCDE_WS_EXTRAP : (mode == 1 ? TSFCDE_WS_PREV : TSFCDE_WS_ZERO);
+    if (mode > 0) {
+        hipLaunchKernelGGL(k_guess, dim3(nb), dim3(RB), 0, pl->stream, (const double *)pl->U, N, (int)j, mode, x);
+        HIPCHK(hipGetLastError());
+        HIPCHK(product(pl, j, x, pl->t, pl->eta[j], -pl->sigma, 0, Fin::Y));
+        hipLaunchKernelGGL(k_true, dim3(nb), dim3(RB), 0, pl->stream, (const double *)pl->g, (const double *)pl->t,
+                           (const double *)x, pl->r, pl->rt, N, pl->partv);
+        hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(RB), 0, pl->stream, (const double *)pl->partv, nb, pl->sc,
+                           pl->anorm[j], BW_TOL, 0);
+    } else {
+        hipLaunchKernelGGL(k_fill, dim3(nb), dim3(RB), 0, pl->stream, x, N, 0.0);
+    }
     HIPCHK(hipGetLastError());
     // CGS in chunks between polls; a stopped solve is checked on its true
     // residual and backward error and restarted from x when it fails
@@ -1244,7 +1271,7 @@ int level_step(NdPlan *pl, const double *d_f, double *d_u_out, tsfcde_stats *st)
         st->backward_err = checked ? (den > 0 ? std::sqrt(h.aux0) / den : 0.0) : -1.0;
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         st->precision_used = TSFCDE_FP64;
-        st->guess = TSFCDE_WS_ZERO;
+        st->guess = guess;
         st->method = 0;
         st->pad = 0;
     }
@@ -1259,12 +1286,13 @@ struct NdProblem {
     int64_t n[3], M;
     tsfcde_coef_fn gam[3], dp[3], dm[3];
     void *coef_user;
-    int maxit;
+    int maxit, warm;
 };
 
 int validate(const NdProblem &p) {
     if (!(p.alpha > 0.0 && p.alpha <= 1.0)) return TSFCDE_EINVAL;
     if (!(p.T > 0.0) || !std::isfinite(p.T) || p.M < 1) return TSFCDE_EINVAL;
+    if (p.warm != TSFCDE_WS_ZERO && p.warm != TSFCDE_WS_PREV && p.warm != TSFCDE_WS_EXTRAP) return TSFCDE_EINVAL;
     for (int a = 0; a < p.d; ++a) {
         if (!(p.beta[a] > 1.0 && p.beta[a] <= 2.0)) return TSFCDE_EINVAL;
         if (!(p.hi[a] > p.lo[a]) || !std::isfinite(p.lo[a]) || !std::isfinite(p.hi[a])) return TSFCDE_EINVAL;
@@ -1303,6 +1331,7 @@ NdProblem from2(const tsfcde2d_problem *p) {
     q.coef_user = p->coef_user;
     q.rtol = p->rtol;
     q.maxit = p->maxit;
+    q.warm = p->warm_start;
     return q;
 }
 
@@ -1324,6 +1353,7 @@ NdProblem from3(const tsfcde3d_problem *p) {
     q.coef_user = p->coef_user;
     q.rtol = p->rtol;
     q.maxit = p->maxit;
+    q.warm = p->warm_start;
     return q;
 }
 
@@ -1365,6 +1395,7 @@ int plan_create(const NdProblem &prob, void *d_workspace, size_t bytes, void *st
     pl->kappa = std::pow(pl->tau, -prob.alpha) / std::tgamma(2.0 - prob.alpha);
     pl->rtol = prob.rtol > 0 ? prob.rtol : 1e-10;
     pl->maxit = prob.maxit > 0 ? prob.maxit : 500;
+    pl->warm = prob.warm;
     // coefficients at t_{j+sigma}
     for (int a = 0; a < d; ++a) {
         pl->gam[a].resize(M);

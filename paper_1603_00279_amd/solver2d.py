@@ -20,10 +20,10 @@ class TimeLevelSolver2D:
     (x along axis 0).  Coefficients are callables of t (sampled by the library
     at its own t_{j+sigma}); phi(x, y) and f(x, y, t) callables of scalars are
     optional (the initial level is 0 without phi; levels stepped without a
-    source use f, or 0)."""
+    source use f, or 0).  warm_start: TSFCDE_WS_ZERO, _PREV or _EXTRAP."""
 
     def __init__(self, *, alpha, beta_x, beta_y, nx, ny, M, gamma_x, gamma_y, dplus_x, dminus_x, dplus_y,
-                 dminus_y, a=0.0, b=1.0, c=0.0, d=1.0, T=1.0, phi=None, f=None, rtol=1e-10, maxit=500, flags=0,
+                 dminus_y, a=0.0, b=1.0, c=0.0, d=1.0, T=1.0, phi=None, f=None, rtol=1e-10, maxit=500, warm_start=0,
                  device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
         self._lib = N.lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -31,7 +31,7 @@ class TimeLevelSolver2D:
         self.nx, self.ny, self.M = int(nx), int(ny), int(M)
         self._keep = []
         p = N.tsfcde2d_problem(alpha=alpha, beta_x=beta_x, beta_y=beta_y, a=a, b=b, c=c, d=d, T=T, nx=nx, ny=ny,
-                               M=M, rtol=rtol, maxit=maxit, flags=flags)
+                               M=M, rtol=rtol, maxit=maxit, warm_start=warm_start)
         for name, fn in (("gamma_x", gamma_x), ("gamma_y", gamma_y), ("dplus_x", dplus_x), ("dminus_x", dminus_x),
                          ("dplus_y", dplus_y), ("dminus_y", dminus_y)):
             cb = N.COEF_FN(lambda t, _u, fn=fn: float(fn(t)))

@@ -20,10 +20,10 @@ class TimeLevelSolver3D:
     tensors (z fastest).  Per-axis arguments are sequences in the order x, y,
     z; coefficients are callables of t (sampled by the library at its own
     t_{j+sigma}); phi(x, y, z) and f(x, y, z, t) callables of scalars are
-    optional."""
+    optional.  warm_start: TSFCDE_WS_ZERO, _PREV or _EXTRAP."""
 
     def __init__(self, *, alpha, betas, ns, M, gammas, dpluses, dminuses, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
-                 T=1.0, phi=None, f=None, rtol=1e-10, maxit=500, flags=0, device: Optional[torch.device] = None,
+                 T=1.0, phi=None, f=None, rtol=1e-10, maxit=500, warm_start=0, device: Optional[torch.device] = None,
                  stream: Optional[torch.cuda.Stream] = None):
         self._lib = N.lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -32,7 +32,7 @@ class TimeLevelSolver3D:
         self.N = int(np.prod(self.ns))
         self.M = int(M)
         self._keep = []
-        p = N.tsfcde3d_problem(alpha=alpha, T=T, M=M, rtol=rtol, maxit=maxit, flags=flags)
+        p = N.tsfcde3d_problem(alpha=alpha, T=T, M=M, rtol=rtol, maxit=maxit, warm_start=warm_start)
         for k in range(3):
             p.beta[k] = float(betas[k])
             p.lo[k] = float(lo[k])

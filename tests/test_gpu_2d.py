@@ -128,3 +128,32 @@ def test_large_sampled_points():
         r = O2.rhs2_points(prob, U, j, f, pts) - O2.apply_A2_points(prob, j, U[j + 1], pts, "A")
         S = O2.anorm2(prob, j) * np.max(np.abs(U[j + 1]))
         assert np.max(np.abs(r)) <= 1e-12 * S, (j, np.max(np.abs(r)) / S)
+
+
+@pytest.mark.parametrize("warm", ["prev", "extrap"])
+def test_warm_started_march_matches_dense_oracle(warm):
+    """The previous-level and extrapolated initial guesses: every level against
+    the oracle's dense direct solves (the converged level does not depend on
+    the guess); the extrapolation takes fewer CGS iterations in total than the
+    zero guess."""
+    import paper_1603_00279_amd as P
+    ws = P.TSFCDE_WS_PREV if warm == "prev" else P.TSFCDE_WS_EXTRAP
+    banner(f"2d warm march {warm}")
+    prob = W.problem_2d(32, 16, 8, alpha=0.7, beta_x=1.8, beta_y=1.5)
+    with solver(prob, rtol=1e-12) as s:
+        code0, st0 = s.solve(sources(s, prob))
+    with solver(prob, rtol=1e-12, warm_start=ws) as s:
+        code, stats = s.solve(sources(s, prob))
+        U = host(s.history())
+    assert code == 0 and code0 == 0, stats
+    Uref = O2.march2(prob)
+    worst = max(np.max(np.abs(U[j] - Uref[j])) / np.max(np.abs(Uref[j])) for j in range(1, prob.M + 1))
+    its, its0 = [st["iters"] for st in stats], [st["iters"] for st in st0]
+    print(f"[2d warm {warm}] worst rel err {worst:.2e}, iterations {its} (zero guess {its0}), "
+          f"guesses {[st['guess'] for st in stats]}", flush=True)
+    assert worst < 1e-10
+    # the previous level saves little with tau = 1/8; the extrapolation must save iterations
+    assert sum(its) < sum(its0) if warm == "extrap" else sum(its) <= sum(its0) + prob.M
+    want = [ws if warm == "prev" else (P.TSFCDE_WS_EXTRAP if j >= 2 else P.TSFCDE_WS_PREV if j == 1
+                                         else P.TSFCDE_WS_ZERO) for j in range(prob.M)]
+    assert [st["guess"] for st in stats] == want
