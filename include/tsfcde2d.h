@@ -51,7 +51,7 @@ typedef struct tsfcde2d_problem {
     double a, b, c, d;     /* [a,b] x [c,d], a < b, c < d                     */
     double T;              /* final time, T > 0                               */
     int64_t nx, ny;        /* interior unknowns per axis: powers of two in
-                              [16, 1024] (TSFCDE_EUNSUPPORTED otherwise)       */
+                              [16, 2048] (TSFCDE_EUNSUPPORTED otherwise)       */
     int64_t M;             /* time steps, M >= 1                              */
     /* gx, gy, dxp, dxm, dyp, dym at t: host callbacks, called during
      * tsfcde2d_plan at t_{j+sigma}, j = 0..M-1; none may be NULL; the d's

@@ -51,7 +51,8 @@ typedef struct tsfcde3d_problem {
     double lo[3], hi[3];    /* the box, lo < hi on every axis                  */
     double T;               /* final time, T > 0                               */
     int64_t n[3];           /* interior unknowns per axis: powers of two in
-                               [16, 1024] (TSFCDE_EUNSUPPORTED otherwise)       */
+                               [16, 2048], N at most 2^30 (TSFCDE_EUNSUPPORTED
+                               otherwise)                                      */
     int64_t M;              /* time steps, M >= 1                              */
     /* gamma_s, d+_s, d-_s at t: host callbacks, called during tsfcde3d_plan
      * at t_{j+sigma}, j = 0..M-1; none may be NULL; the d's must be >= 0 */

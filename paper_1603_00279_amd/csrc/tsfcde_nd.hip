@@ -54,7 +54,7 @@ using tsf::lpad;
 using tsf::lpad_size;
 using tsf::tw_offset;
 
-constexpr int PMAX_LOG2 = 11;  // transforms up to 2048 points (embeddings of n = 1024)
+constexpr int PMAX_LOG2 = 12;  // transforms up to 4096 points (embeddings of n = 2048)
 constexpr int NT = 512;        // threads of a line workgroup at most
 constexpr int RB = 256;        // threads of a vector workgroup
 constexpr int RBLK = 1024;     // vector workgroups at most (partial sums)
@@ -871,11 +871,14 @@ int nblocks(int64_t N) { return (int)std::min<int64_t>(RBLK, (N + RB - 1) / RB);
     } while (0)
 
 // Launch of k_line, one tile per workgroup; returns the grid through
-// *grid_out.  Row passes take workgroups of 256 threads when 512-thread ones
-// would not give every CU two of them (small batches of lines: the same
-// waves spread over more CUs); strided passes keep 512 threads, whose wider
-// tiles (more adjacent lines) read longer runs of each row (measured: 11%
-// less time per CGS iteration at 1024 x 1024).
+// *grid_out.  Row passes take workgroups of 256 threads: half the LDS per
+// workgroup, twice the workgroups per CU, whose load, transform and store
+// phases overlap better (1.7% less time per CGS iteration at 256^3; at
+// 1024 x 1024 the same waves spread over more CUs); rows of 4096 points (512
+// lanes each) take 512.  Strided passes keep 512 threads, whose wider tiles
+// (more adjacent lines) read longer runs of each row (11% less time per CGS
+// iteration at 1024 x 1024; 256 threads in the strided passes of up to 512
+// points were 3% slower at 256^3).
 // Eight values per lane in every pass: sixteen in the Toeplitz passes of 256
 // points and more (half the exchanges at 256, 1024 and 2048 points, twice the
 // LDS per workgroup) measured 13% slower per CGS iteration at 1024 x 1024 and
@@ -896,10 +899,7 @@ hipError_t line_g(NdPlan *pl, const Op &op, int64_t nlines, int *grid_out) {
 
 template <int P, bool ROWS, class Op>
 hipError_t line_t(NdPlan *pl, const Op &op, int64_t nlines, int *grid_out) {
-    constexpr int64_t T = P / line_e<Op, P>();
-    if constexpr (ROWS) {
-        if (nlines * T < int64_t(256) * 2 * NT) return line_g<P, ROWS, 256>(pl, op, nlines, grid_out);
-    }
+    if constexpr (ROWS && P / 8 <= 256) return line_g<P, ROWS, 256>(pl, op, nlines, grid_out);
     return line_g<P, ROWS, NT>(pl, op, nlines, grid_out);
 }
 
@@ -914,6 +914,7 @@ hipError_t line(NdPlan *pl, int64_t P, const Op &op, int64_t nlines, int *grid_o
         case 512: return line_t<512, ROWS>(pl, op, nlines, grid_out);
         case 1024: return line_t<1024, ROWS>(pl, op, nlines, grid_out);
         case 2048: return line_t<2048, ROWS>(pl, op, nlines, grid_out);
+        case 4096: return line_t<4096, ROWS>(pl, op, nlines, grid_out);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1300,7 +1301,7 @@ int validate(const NdProblem &p) {
         if (p.n[a] < 1) return TSFCDE_EINVAL;
     }
     for (int a = 0; a < p.d; ++a)
-        if (!pow2_in(p.n[a], 16, 1024)) return TSFCDE_EUNSUPPORTED;
+        if (!pow2_in(p.n[a], 16, 2048)) return TSFCDE_EUNSUPPORTED;
     if (p.M > (int64_t(1) << 20)) return TSFCDE_EUNSUPPORTED;
     int64_t N = 1;
     for (int a = 0; a < p.d; ++a) N *= p.n[a];

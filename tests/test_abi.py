@@ -153,7 +153,7 @@ def _problem2d(N, keep, **kw):
 
 @pytest.mark.parametrize("field,value,code", [
     ("alpha", 0.0, -1), ("beta_x", 1.0, -1), ("beta_y", 2.5, -1), ("d", 0.0, -1), ("T", 0.0, -1), ("M", 0, -1),
-    ("nx", 0, -1), ("nx", 48, -8), ("ny", 8, -8), ("ny", 2048, -8), ("nx", 1024, 0), ("ny", 16, 0),
+    ("nx", 0, -1), ("nx", 48, -8), ("ny", 8, -8), ("ny", 4096, -8), ("nx", 2048, 0), ("ny", 16, 0),
     ("warm_start", 2, 0), ("warm_start", 3, -1), ("warm_start", -1, -1),
 ])
 def test_2d_validation(N, field, value, code):
@@ -222,7 +222,7 @@ def _problem3d(N, keep, **kw):
 
 @pytest.mark.parametrize("field,value,code", [
     ("alpha", 1.5, -1), ("beta_0", 1.0, -1), ("beta_2", 2.01, -1), ("hi_1", 0.0, -1), ("T", -1.0, -1), ("M", 0, -1),
-    ("n_0", 0, -1), ("n_1", 24, -8), ("n_2", 8, -8), ("n_0", 2048, -8), ("n_2", 1024, 0), ("n_1", 16, 0),
+    ("n_0", 0, -1), ("n_1", 24, -8), ("n_2", 8, -8), ("n_0", 4096, -8), ("n_2", 2048, 0), ("n_1", 16, 0),
     ("warm_start", 1, 0), ("warm_start", 3, -1),
 ])
 def test_3d_validation(N, field, value, code):

@@ -1,6 +1,6 @@
 """GPU parity of the two-dimensional solver (include/tsfcde2d.h) against the
 2D oracle: the operators A, B and P^{-1} on random arrays, whole marches
-against the dense direct solves, sampled points at 1024 x 1024, exchange of
+against the dense direct solves, sampled points at 1024^2 and 2048^2, exchange of
 the axes, the f callback and the zero problem."""
 import numpy as np
 import pytest
@@ -30,7 +30,7 @@ def sources(s, prob):
     return W.device_sources_2d(prob, x, y, s.level_times(), torch.device("cuda"))
 
 
-@pytest.mark.parametrize("nx,ny", [(16, 16), (32, 64), (128, 32), (256, 256)])
+@pytest.mark.parametrize("nx,ny", [(16, 16), (32, 64), (128, 32), (256, 256), (2048, 16), (16, 2048)])
 def test_operators_match_oracle(nx, ny):
     import paper_1603_00279_amd as P
     banner(f"2d operators {nx}x{ny}")
@@ -106,21 +106,24 @@ def test_callback_source_and_zero_problem():
     assert code == 0 and np.all(U == 0.0) and all(st["iters"] == 0 for st in stats)
 
 
-def test_large_sampled_points():
-    """1024 x 1024 (2^20 unknowns), two levels: acceptance and the oracle's
-    point residuals g - A u^{j+1} (its own sampling of f) against the row
-    scale |A| max|u|."""
-    banner("2d 1024x1024")
-    prob = W.problem_2d(1024, 1024, 8)
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_large_sampled_points(n):
+    """n x n (2^20 and 2^22 unknowns; 2048 points per axis runs the 4096-point
+    Toeplitz transforms), two levels: acceptance and the oracle's point
+    residuals g - A u^{j+1} (its own sampling of f) against the row scale
+    |A| max|u|."""
+    banner(f"2d {n}x{n}")
+    prob = W.problem_2d(n, n, 8)
     rng = np.random.default_rng(5)
-    pts = [(0, 0), (1023, 1023), (0, 1023), (1023, 0), (511, 512)] + [tuple(v) for v in rng.integers(0, 1024, (11, 2))]
+    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (n // 2 - 1, n // 2)]
+    pts += [tuple(v) for v in rng.integers(0, n, (11, 2))]
     with solver(prob) as s:
         F = sources(s, prob)
         stats = [s.step(F[j]) for j in range(2)]
         U = host(s.history()[:3])
     for j in range(2):
         st = stats[j]
-        print(f"[2d 1024x1024] j={j} iters {st['iters']} relres_true {st['relres_true']:.2e} "
+        print(f"[2d {n}x{n}] j={j} iters {st['iters']} relres_true {st['relres_true']:.2e} "
               f"backward_err {st['backward_err']:.2e}", flush=True)
         assert st["code"] == 0 and st["iters"] > 0, st
         assert st["relres_true"] <= 1e-10 or 0.0 <= st["backward_err"] <= 1e-13, st

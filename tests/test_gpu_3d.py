@@ -31,7 +31,7 @@ def sources(s, prob):
     return W.device_sources_3d(prob, x, y, z, s.level_times(), torch.device("cuda"))
 
 
-@pytest.mark.parametrize("ns", [(16, 16, 16), (16, 32, 64), (64, 16, 32), (128, 64, 128)])
+@pytest.mark.parametrize("ns", [(16, 16, 16), (16, 32, 64), (64, 16, 32), (128, 64, 128), (2048, 16, 32), (16, 32, 2048)])
 def test_operators_match_oracle(ns):
     import paper_1603_00279_amd as P
     banner(f"3d operators {ns}")
