@@ -525,6 +525,35 @@ def cpu_baseline(n_full, M_full, rtol, budget_s=15.0, lu_sizes=(64, 256, 1024, 2
     }
 
 
+def cpu_baseline_nd(rtol, its=(6, 3)):
+    """The 2D and 3D oracles' FFT route (numpy FFTs, one thread) on a bounded
+    sample: the right-hand side and its[0] (2D, 1024 x 1024, the bench form's
+    size) or its[1] (3D, at 128^3: a 256^3 iteration takes tens of seconds on
+    one core) CGS iterations of level 0; seconds per CGS iteration."""
+    import numpy as np
+    import oracle.ids2d_oracle as O2
+    import oracle.ids3d_oracle as O3
+    import workloads as W
+    from threadpoolctl import threadpool_limits
+    out = {}
+    with threadpool_limits(limits=1):
+        for d, prob, mod, k in ((2, W.problem_2d(1024, 1024, ND_FORMS[2]["M"]), O2, its[0]),
+                                (3, W.problem_3d(128, 128, 128, ND_FORMS[3]["M"]), O3, its[1])):
+            U = np.array([mod.initial_level(prob)])
+            f = mod.source_level(prob, 0)
+            solve = O2.level_solve_pcgs2 if d == 2 else O3.level_solve_pcgs3
+            t0 = time.perf_counter()
+            _, done = solve(prob, U, 0, f, rtol=rtol, maxit=k)
+            dt = time.perf_counter() - t0
+            size = "x".join(str(v) for v in ((prob.nx, prob.ny) if d == 2 else prob.ns))
+            out[f"{d}d"] = {"grid": size, "cgs_iterations": int(done), "seconds": dt,
+                            "seconds_per_cgs_iteration": dt / max(1, done), "cores": 1, "kind": "oracle",
+                            "sample": f"level 0 of the {d}D family at {size}: right-hand side, spectra and "
+                                      f"{done} CGS iterations of the FFT-route oracle"}
+            log(f"cpu baseline {d}D oracle at {size}: {dt / max(1, done):.2f} s per CGS iteration")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -684,6 +713,16 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(n, prob.M, args.rtol)
+        if not args.no_forms and args.form in ("all", "2d", "3d"):
+            nd = cpu_baseline_nd(args.rtol)
+            for d, key in ((2, "two_dimensional"), (3, "three_dimensional")):
+                form = out.get("forms", {}).get(key)
+                if form and d == 2:
+                    # same grid: the oracle's level at the GPU's mean iteration count
+                    nd["2d"]["level_solves_per_s_at_gpu_iterations"] = 1.0 / (
+                        nd["2d"]["seconds_per_cgs_iteration"] * form["cgs_iterations"]["mean"])
+                    nd["2d"]["gpu_over_oracle"] = form["value"] / nd["2d"]["level_solves_per_s_at_gpu_iterations"]
+            out["cpu_baseline"]["nd"] = nd
     print(json.dumps(out), flush=True)
     if accept["failed_levels"]:
         log(f"{accept['failed_levels']} timed levels failed the acceptance test")
