@@ -25,6 +25,13 @@ def solver(prob, **kw):
     return P.TimeLevelSolver2D.from_problem(prob, **kw)
 
 
+def box_solution(theta, a, b):
+    """theta(t) (x-a)^2 (b-x)^2: the manufactured profile on [a, b] (double
+    roots at both ends, as the closed-form fractional derivatives need)."""
+    L = b - a
+    return W.ManufacturedSolution(theta, np.array([0.0, 0.0, L * L, -2.0 * L, 1.0]), a, b)
+
+
 def sources(s, prob):
     x, y = s.nodes()
     return W.device_sources_2d(prob, x, y, s.level_times(), torch.device("cuda"))
@@ -160,3 +167,56 @@ def test_warm_started_march_matches_dense_oracle(warm):
     want = [ws if warm == "prev" else (P.TSFCDE_WS_EXTRAP if j >= 2 else P.TSFCDE_WS_PREV if j == 1
                                          else P.TSFCDE_WS_ZERO) for j in range(prob.M)]
     assert [st["guess"] for st in stats] == want
+
+
+def test_edge_orders_and_box():
+    """alpha = 1 (Crank-Nicolson in time), beta_x = 2 and beta_y near 1, a box
+    other than the unit square and T != 1: every level against the dense
+    oracle (both take the same problem statement and sample it themselves)."""
+    import dataclasses
+    banner("2d edge orders and box")
+    base = W.problem_2d(16, 32, 4, alpha=1.0, beta_x=2.0, beta_y=1.02)
+    prob = dataclasses.replace(base, a=-1.0, b=2.0, c=0.5, d=1.5, T=0.5,
+                               sol_x=box_solution(base.sol_x.theta_terms, -1.0, 2.0),
+                               sol_y=box_solution([(1.0, 0.0)], 0.5, 1.5))
+    with solver(prob, rtol=1e-13) as s:
+        code, stats = s.solve(sources(s, prob))
+        U = host(s.history())
+    assert code == 0, stats
+    Uref = O2.march2(prob)
+    worst = max(np.max(np.abs(U[j] - Uref[j])) / np.max(np.abs(Uref[j])) for j in range(1, prob.M + 1))
+    print(f"[2d edge] worst rel err {worst:.2e}, iterations {[st['iters'] for st in stats]}", flush=True)
+    assert worst < 1e-10
+
+
+def test_determinism_resume_and_errors():
+    """Two runs are bitwise equal (fixed-order reductions); a plan resumed from
+    level 3 by set_state continues bitwise as the uninterrupted march; a tiny
+    maxit gives TSFCDE_ENOCONV; bad calls are refused without side effects."""
+    import paper_1603_00279_amd as P
+    banner("2d determinism, resume, errors")
+    prob = W.problem_2d(64, 32, 6)
+    runs = []
+    for _ in range(2):
+        with solver(prob) as s:
+            F = sources(s, prob)
+            s.solve(F)
+            runs.append(host(s.history()))
+    assert np.array_equal(runs[0], runs[1])
+    with solver(prob) as s:
+        s.set_state(3, torch.as_tensor(runs[0][:4], device="cuda"))
+        code, _ = s.solve(F)
+        assert code == 0
+        assert np.array_equal(host(s.history()), runs[0])
+        assert s.step(F[0], raise_on_error=False)["code"] == P.TSFCDE_EDONE
+    with solver(prob, maxit=3) as s:
+        st = s.step(F[0], raise_on_error=False)
+        assert st["code"] == P.TSFCDE_ENOCONV and st["iters"] == 3, st
+        x = torch.zeros(64 * 32, dtype=torch.float64, device="cuda")
+        L = P.lib()
+        assert L.tsfcde2d_apply(s._plan, P.TSFCDE_OP_A, 0, x.data_ptr(), x.data_ptr()) == P.TSFCDE_EINVAL
+        assert L.tsfcde2d_apply(s._plan, 7, 0, x.data_ptr(), x.data_ptr() + 8) == P.TSFCDE_EINVAL
+        assert L.tsfcde2d_apply(s._plan, P.TSFCDE_OP_A, prob.M, x.data_ptr(), x.data_ptr() + 8) == P.TSFCDE_EINVAL
+        assert L.tsfcde2d_set_state(s._plan, prob.M, x.data_ptr()) == P.TSFCDE_EINVAL
+        assert L.tsfcde2d_solve(s._plan, x.data_ptr(), 5, None, None) == P.TSFCDE_EINVAL
+        assert s.level == 1
