@@ -199,55 +199,52 @@ __global__ void __launch_bounds__(NTL, 4) k_line(Op op, int64_t nlines, const do
 #pragma unroll
     for (int a = 0; a < (Op::NACC > 0 ? Op::NACC : 1); ++a) acc[a] = 0.0;
     const int64_t ntiles = (nlines + B - 1) / B;
-    const double2 *tw = tw_all;
-    {
-        const int64_t tile = ROWS ? (int64_t)blockIdx.x : xcd_tile(blockIdx.x, ntiles);
-        const int64_t line = tile * B + b;
-        const bool active = line < nlines;
-        double2 *slab = ROWS ? lds + b * LS : lds + b;
-        const int ls = ROWS ? 1 : B;
-        typename Op::Ctx ctx{};
-        if (active) ctx = o.ctx(line);
-        double raw[E][Op::NRAW];
+    const int64_t tile = ROWS ? (int64_t)blockIdx.x : xcd_tile(blockIdx.x, ntiles);
+    const int64_t line = tile * B + b;
+    const bool active = line < nlines;
+    double2 *slab = ROWS ? lds + b * LS : lds + b;
+    const int ls = ROWS ? 1 : B;
+    typename Op::Ctx ctx{};
+    if (active) ctx = o.ctx(line);
+    double raw[E][Op::NRAW];
 #pragma unroll
-        for (int m = 0; m < E; ++m)
-            if (active) o.fetch(ctx, j + T * m, raw[m]);
-        // a folded finishing step runs while the loads are in flight
-        if constexpr (Op::FOLD) {
-            if (o.fold(sc)) return;
+    for (int m = 0; m < E; ++m)
+        if (active) o.fetch(ctx, j + T * m, raw[m]);
+    // a folded finishing step runs while the loads are in flight
+    if constexpr (Op::FOLD) {
+        if (o.fold(sc)) return;
+    }
+    double2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = active ? o.finish(ctx, j + T * m, raw[m]) : make_double2(0.0, 0.0);
+    OpSink<Op> sink{&o, &ctx, acc};
+    if constexpr (Op::NFFT == 2) {
+        LdsSink lsink{slab, ls};
+        fft<P, E, -1>(v, j, active, tw_all, slab, ls, lsink);
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int k = j + T * m;
+            v[m] = active ? o.spec(ctx, k, slab[lpad(k) * ls]) : make_double2(0.0, 0.0);
         }
-        double2 v[E];
-#pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = active ? o.finish(ctx, j + T * m, raw[m]) : make_double2(0.0, 0.0);
-        OpSink<Op> sink{&o, &ctx, acc};
-        if constexpr (Op::NFFT == 2) {
-            LdsSink lsink{slab, ls};
-            fft<P, E, -1>(v, j, active, tw, slab, ls, lsink);
-            __syncthreads();
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int k = j + T * m;
-                v[m] = active ? o.spec(ctx, k, slab[lpad(k) * ls]) : make_double2(0.0, 0.0);
+        __syncthreads();
+        fft<P, E, 1>(v, j, active, tw_all, slab, ls, sink);
+    } else if constexpr (Op::HALF) {
+        // Z = DFT(a + i b) of two real rows: A_k = (Z_k + conj Z_{P-k}) / 2,
+        // B_k = (Z_k - conj Z_{P-k}) / (2i), k = 0..P/2
+        LdsSink lsink{slab, ls};
+        fft<P, E, -1>(v, j, active, tw_all, slab, ls, lsink);
+        __syncthreads();
+        if (active) {
+            for (int k = j; k <= P / 2; k += T) {
+                const double2 Z = slab[lpad(k) * ls];
+                const double2 Zc = slab[lpad((P - k) & (P - 1)) * ls];
+                o.store_half(ctx, k, make_double2(0.5 * (Z.x + Zc.x), 0.5 * (Z.y - Zc.y)),
+                             make_double2(0.5 * (Z.y + Zc.y), -0.5 * (Z.x - Zc.x)));
             }
-            __syncthreads();
-            fft<P, E, 1>(v, j, active, tw, slab, ls, sink);
-        } else if constexpr (Op::HALF) {
-            // Z = DFT(a + i b) of two real rows: A_k = (Z_k + conj Z_{P-k}) / 2,
-            // B_k = (Z_k - conj Z_{P-k}) / (2i), k = 0..P/2
-            LdsSink lsink{slab, ls};
-            fft<P, E, -1>(v, j, active, tw, slab, ls, lsink);
-            __syncthreads();
-            if (active) {
-                for (int k = j; k <= P / 2; k += T) {
-                    const double2 Z = slab[lpad(k) * ls];
-                    const double2 Zc = slab[lpad((P - k) & (P - 1)) * ls];
-                    o.store_half(ctx, k, make_double2(0.5 * (Z.x + Zc.x), 0.5 * (Z.y - Zc.y)),
-                                 make_double2(0.5 * (Z.y + Zc.y), -0.5 * (Z.x - Zc.x)));
-                }
-            }
-        } else {
-            fft<P, E, Op::DIR>(v, j, active, tw, slab, ls, sink);
         }
+    } else {
+        fft<P, E, Op::DIR>(v, j, active, tw_all, slab, ls, sink);
     }
     if constexpr (Op::NACC > 0) block_partial<Op::NACC>(acc, o.part, blockIdx.x);
 }
