@@ -76,7 +76,7 @@ typedef struct tsfcde2d_problem {
 
 typedef struct tsfcde2d_plan_s *tsfcde2d_plan_t;
 
-/* Device workspace a plan needs, in bytes (about (M + 20) nx ny doubles).
+/* Device workspace a plan needs, in bytes (about (M + 23) nx ny doubles).
  * TSFCDE_EINVAL / TSFCDE_EUNSUPPORTED for a problem tsfcde2d_plan would
  * refuse. */
 int tsfcde2d_workspace_bytes(const tsfcde2d_problem *prob, size_t *bytes);

@@ -71,7 +71,7 @@ typedef struct tsfcde3d_problem {
 
 typedef struct tsfcde3d_plan_s *tsfcde3d_plan_t;
 
-/* Device workspace a plan needs, in bytes (about (M + 14) N doubles for
+/* Device workspace a plan needs, in bytes (about (M + 23) N doubles for
  * N = nx ny nz).  TSFCDE_EINVAL / TSFCDE_EUNSUPPORTED for a problem
  * tsfcde3d_plan would refuse. */
 int tsfcde3d_workspace_bytes(const tsfcde3d_problem *prob, size_t *bytes);

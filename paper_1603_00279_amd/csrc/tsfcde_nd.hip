@@ -621,14 +621,49 @@ __global__ void __launch_bounds__(RB) k_fill(double *x, int64_t N, double val) {
     TSFND_LOOP(i, N) x[i] = val;
 }
 
-// history of (3.1): H = kappa sum_{s<j} c_{j-s}^(j) (u^{s+1} - u^s), with
-// c_j^(j) = clast_j and c_m^(j) = cbase[m] for 1 <= m < j (Lemma 1)
-__global__ void __launch_bounds__(RB) k_hist(const double *__restrict__ U, int64_t N, int j,
-                                             const double *__restrict__ cbase, double clast_j, double kappa,
-                                             double *__restrict__ H) {
+// History of (3.1): H_L = kappa sum_{s<L} c_{L-s}^(L) (u^{s+1} - u^s), with
+// c_L^(L) = clast_L (the s = 0 term) and c_m^(L) = cbase[m] for 1 <= m < L
+// (Lemma 1), summed in blocks of HB levels: at a block's first level b the
+// sweep forms, in one pass over u^0..u^{b-1}, the part of every level
+// L = b..b+HB-1 that uses only those levels (s <= b-2); each level L then
+// adds the terms s = b-1..L-1 (the catch-up).  About b + HB vectors per
+// block plus L - b + 3 per level, against L + 2 per level for the whole sum.
+constexpr int HB = 8;
+struct HbLast {
+    double c[HB];  // clast of the block's levels
+};
+
+__global__ void __launch_bounds__(RB) k_hist_sweep(const double *__restrict__ U, int64_t N, int b, int nl,
+                                                   const double *__restrict__ cbase, HbLast cl,
+                                                   double *__restrict__ Q) {
     TSFND_LOOP(i, N) {
-        double acc = clast_j * (U[N + i] - U[i]);
-        for (int s = 1; s < j; ++s) acc = fma(cbase[j - s], U[(int64_t)(s + 1) * N + i] - U[(int64_t)s * N + i], acc);
+        double acc[HB];
+#pragma unroll
+        for (int q = 0; q < HB; ++q) acc[q] = 0.0;
+        double prev = U[i];
+        for (int s = 0; s <= b - 2; ++s) {
+            const double next = U[(int64_t)(s + 1) * N + i];
+            const double d = next - prev;
+            prev = next;
+#pragma unroll
+            for (int q = 0; q < HB; ++q) acc[q] = fma(s == 0 ? cl.c[q] : cbase[b + q - s], d, acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < HB; ++q)
+            if (q < nl) Q[(int64_t)q * N + i] = acc[q];
+    }
+}
+
+// catch-up of level L in the block starting at b: Q_L (NULL in the first
+// block) plus the terms s = max(b-1, 0)..L-1, times kappa
+__global__ void __launch_bounds__(RB) k_hist_catch(const double *__restrict__ U, int64_t N, int L, int b,
+                                                   const double *__restrict__ cbase, double clast_L, double kappa,
+                                                   const double *__restrict__ QL, double *__restrict__ H) {
+    const int s0 = b - 1 > 0 ? b - 1 : 0;
+    TSFND_LOOP(i, N) {
+        double acc = QL ? QL[i] : 0.0;
+        for (int s = s0; s < L; ++s)
+            acc = fma(s == 0 ? clast_L : cbase[L - s], U[(int64_t)(s + 1) * N + i] - U[(int64_t)s * N + i], acc);
         H[i] = kappa * acc;
     }
 }
@@ -787,6 +822,8 @@ struct NdPlan {
            *d_cbase = nullptr, *cols = nullptr;
     double2 *Z = nullptr, *lam[3] = {}, *ls[3] = {}, *tw = nullptr;
     Sc *sc = nullptr;
+    double *Q = nullptr;  // the current history block's partial sums (HB vectors)
+    int64_t qblock = 0;   // first level of the block Q holds (0: none)
     // what the folding passes read: rt.vhat (fold1) and rt.r, r.r (fold2)
     // partials, nfold1 / nfold2 of them
     const double *fold1 = nullptr, *fold2 = nullptr;
@@ -807,7 +844,7 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr int NVEC = 13;  // g r rt u p q phat uhat vhat t w H fbuf
 
 struct Layout {
-    size_t U, vec, Z, lam, tw, part, sc, cb, cols, total;
+    size_t U, vec, Z, lam, tw, part, sc, cb, Q, cols, total;
 };
 
 int64_t spec_len(const int64_t *n, int d) {
@@ -839,7 +876,8 @@ Layout layout(const int64_t *n, int d, int64_t M) {
     L.tw = take(sizeof(double2) * (size_t)((int64_t(1) << (PMAX_LOG2 + 1)) - 2));
     L.part = take(sizeof(double) * (size_t)(2 * 2 * part_len(N) + 2 * RBLK + 4));
     L.sc = take(sizeof(Sc));
-    L.cb = take(sizeof(double) * (size_t)(M + 2));
+    L.cb = take(sizeof(double) * (size_t)(M + 2 + HB));
+    L.Q = take(sizeof(double) * HB * (size_t)N);
     L.cols = take(sizeof(double) * (size_t)spec_len(n, d));
     L.total = o;
     return L;
@@ -1180,8 +1218,19 @@ int level_step(NdPlan *pl, const double *d_f, double *d_u_out, tsfcde_stats *st)
     double *x = pl->U + (size_t)(j + 1) * (size_t)N;
     // history sum and right-hand side g = B u^j - H + f
     if (j >= 1) {
-        hipLaunchKernelGGL(k_hist, dim3(nb), dim3(RB), 0, pl->stream, (const double *)pl->U, N, (int)j,
-                           (const double *)pl->d_cbase, pl->clast[j], pl->kappa, pl->H);
+        const int64_t b = 1 + HB * ((j - 1) / HB);
+        if (b > 1 && pl->qblock != b) {
+            HbLast cl{};
+            const int nl = (int)std::min<int64_t>(HB, pl->M - b);
+            for (int q = 0; q < nl; ++q) cl.c[q] = pl->clast[b + q];
+            hipLaunchKernelGGL(k_hist_sweep, dim3(nb), dim3(RB), 0, pl->stream, (const double *)pl->U, N, (int)b, nl,
+                               (const double *)pl->d_cbase, cl, pl->Q);
+            HIPCHK(hipGetLastError());
+            pl->qblock = b;
+        }
+        hipLaunchKernelGGL(k_hist_catch, dim3(nb), dim3(RB), 0, pl->stream, (const double *)pl->U, N, (int)j, (int)b,
+                           (const double *)pl->d_cbase, pl->clast[j], pl->kappa,
+                           (const double *)(b > 1 ? pl->Q + (size_t)(j - b) * (size_t)N : nullptr), pl->H);
         HIPCHK(hipGetLastError());
     }
     HIPCHK(product(pl, j, pl->U + (size_t)j * (size_t)N, pl->t, pl->eta[j], 1.0 - pl->sigma, 0, Fin::Y));
@@ -1424,7 +1473,7 @@ int plan_create(const NdProblem &prob, void *d_workspace, size_t bytes, void *st
                     0.5 * (std::pow(l + sg, 1.0 - al) + std::pow(l - 1 + sg, 1.0 - al));
         }
         pl->eta.resize(M);
-        pl->cbase.assign(M + 2, 0.0);
+        pl->cbase.assign(M + 2 + HB, 0.0);  // zeros past M for the sweep's last block
         pl->clast.assign(M + 1, 0.0);
         for (int64_t j = 0; j < M; ++j) pl->eta[j] = pl->kappa * (j == 0 ? av[0] : av[0] + bv[1]);
         for (int64_t m = 1; m <= M; ++m) pl->cbase[m] = av[m] + bv[m + 1] - bv[m];
@@ -1479,13 +1528,14 @@ int plan_create(const NdProblem &prob, void *d_workspace, size_t bytes, void *st
     pl->sq = pl->partv + 2 * RBLK;
     pl->sc = reinterpret_cast<Sc *>(ws + L.sc);
     pl->d_cbase = reinterpret_cast<double *>(ws + L.cb);
+    pl->Q = reinterpret_cast<double *>(ws + L.Q);
     pl->cols = reinterpret_cast<double *>(ws + L.cols);
     if (hipHostMalloc(reinterpret_cast<void **>(&pl->h_sc), sizeof(Sc)) != hipSuccess) {
         pl->h_sc = nullptr;
         return fail(TSFCDE_EDEVICE);
     }
     std::memset(pl->h_sc, 0, sizeof(Sc));
-    bool ok = hipMemcpyAsync(pl->d_cbase, pl->cbase.data(), sizeof(double) * (size_t)(M + 2), hipMemcpyHostToDevice,
+    bool ok = hipMemcpyAsync(pl->d_cbase, pl->cbase.data(), sizeof(double) * (size_t)(M + 2 + HB), hipMemcpyHostToDevice,
                              pl->stream) == hipSuccess &&
               hipMemcpyAsync(pl->cols, cols.data(), sizeof(double) * cols.size(), hipMemcpyHostToDevice, pl->stream) ==
                   hipSuccess &&
@@ -1528,6 +1578,7 @@ int set_state(NdPlan *pl, int64_t level, const double *d_U) {
                           pl->stream));
     HIPCHK(hipStreamSynchronize(pl->stream));
     pl->level = level;
+    pl->qblock = 0;  // the history block sums are rebuilt from the new levels
     return TSFCDE_OK;
 }
 

@@ -220,3 +220,24 @@ def test_determinism_resume_and_errors():
         assert L.tsfcde2d_set_state(s._plan, prob.M, x.data_ptr()) == P.TSFCDE_EINVAL
         assert L.tsfcde2d_solve(s._plan, x.data_ptr(), 5, None, None) == P.TSFCDE_EINVAL
         assert s.level == 1
+
+
+def test_history_blocks_and_mid_block_resume():
+    """A march of 20 levels (history sums in blocks of 8: levels 1-8, 9-16,
+    17-20) against the dense oracle; a plan resumed at level 13, inside the
+    second block, continues bitwise as the uninterrupted march."""
+    banner("2d history blocks")
+    prob = W.problem_2d(16, 16, 20, alpha=0.3, beta_x=1.6, beta_y=1.9)
+    with solver(prob, rtol=1e-13) as s:
+        F = sources(s, prob)
+        code, stats = s.solve(F)
+        U = host(s.history())
+    assert code == 0, stats
+    Uref = O2.march2(prob)
+    worst = max(np.max(np.abs(U[j] - Uref[j])) / np.max(np.abs(Uref[j])) for j in range(1, prob.M + 1))
+    print(f"[2d history blocks] worst rel err {worst:.2e}", flush=True)
+    assert worst < 1e-10
+    with solver(prob, rtol=1e-13) as s:
+        s.set_state(13, torch.as_tensor(U[:14], device="cuda"))
+        code, _ = s.solve(F)
+        assert code == 0 and np.array_equal(host(s.history()), U)

@@ -202,3 +202,18 @@ def test_edge_orders_box_and_resume():
         s.set_state(2, torch.as_tensor(U[:3], device="cuda"))
         code, _ = s.solve(F)
         assert code == 0 and np.array_equal(host(s.history()), U)
+
+
+def test_history_blocks():
+    """19 levels at 16 x 16 x 32 (history sums in blocks of 8) against the
+    oracle's FFT-route march, both to 1e-13."""
+    banner("3d history blocks")
+    prob = W.problem_3d(16, 16, 32, 19, alpha=0.3, betas=(1.6, 1.9, 1.2))
+    with solver(prob, rtol=1e-13) as s:
+        code, stats = s.solve(sources(s, prob))
+        U = host(s.history())
+    assert code == 0, stats
+    Uref, _ = O3.march_pcgs3(prob, rtol=1e-13)
+    worst = max(np.max(np.abs(U[j] - Uref[j])) / np.max(np.abs(Uref[j])) for j in range(1, prob.M + 1))
+    print(f"[3d history blocks] worst rel err {worst:.2e}", flush=True)
+    assert worst < 1e-10
