@@ -204,12 +204,18 @@ __global__ void __launch_bounds__(NTL, 4) k_line(Op op, int64_t nlines, const do
     const bool active = line < nlines;
     double2 *slab = ROWS ? lds + b * LS : lds + b;
     const int ls = ROWS ? 1 : B;
+    if constexpr (Op::IN_T) {  // transposed input staged in LDS by the whole workgroup
+        o.stage_in(lds, LS, B, tile * B, nlines, t, NTL);
+        __syncthreads();
+    }
     typename Op::Ctx ctx{};
     if (active) ctx = o.ctx(line);
+    if constexpr (Op::IN_T) ctx.slab = slab;
     double raw[E][Op::NRAW];
 #pragma unroll
     for (int m = 0; m < E; ++m)
         if (active) o.fetch(ctx, j + T * m, raw[m]);
+    if constexpr (Op::IN_T) __syncthreads();  // every staged value read: the slab is the transform's
     // a folded finishing step runs while the loads are in flight
     if constexpr (Op::FOLD) {
         if (o.fold(sc)) return;
@@ -243,6 +249,12 @@ __global__ void __launch_bounds__(NTL, 4) k_line(Op op, int64_t nlines, const do
                              make_double2(0.5 * (Z.y + Zc.y), -0.5 * (Z.x - Zc.x)));
             }
         }
+    } else if constexpr (Op::HALF_T) {
+        // as HALF, the unpacked half spectra written transposed by the workgroup
+        LdsSink lsink{slab, ls};
+        fft<P, E, -1>(v, j, active, tw_all, slab, ls, lsink);
+        __syncthreads();
+        o.store_half_t(lds, LS, B, tile * B, nlines, t, NTL);
     } else {
         fft<P, E, Op::DIR>(v, j, active, tw_all, slab, ls, sink);
     }
@@ -270,7 +282,7 @@ enum : int { EPI_W = 0, EPI_WADD = 1, EPI_Y = 2, EPI_DOT = 3, EPI_XR = 4 };
 //   EPI_XR: (y = A uhat, v = uhat) x += alpha v, r -= alpha y, reduce rt.r and r.r.
 template <int EPI> struct ToepOp {
     static constexpr int NFFT = 2, DIR = 0, NRAW = 2, FOLD = 0;
-    static constexpr bool HALF = false;
+    static constexpr bool HALF = false, HALF_T = false, IN_T = false;
     static constexpr int NACC = EPI == EPI_DOT ? 1 : EPI == EPI_XR ? 2 : 0;
     struct Ctx {
         int64_t ia, ib;
@@ -345,9 +357,12 @@ enum : int { PRE_X = 0, PRE_UP = 1, PRE_Q = 2 };
 //     the previous iteration's rt.r and r.r, which also decides convergence;
 //   PRE_Q: u + q after q = u - alpha vhat (q stored); alpha = rho / rt.vhat
 //     from the folded reduction of rt.vhat.
-template <int PRE> struct HalfFwdOp {
+template <int PRE, bool TR = false> struct HalfFwdOp {
     static constexpr int NFFT = 1, DIR = -1, FOLD = PRE != PRE_X, NACC = 0;
-    static constexpr bool HALF = true;
+    // TR: the half spectra go to Z transposed (Z[k * nx + row], two dimensions),
+    // written by the whole workgroup from LDS so that each k takes a run of
+    // the tile's rows
+    static constexpr bool HALF = !TR, HALF_T = TR, IN_T = false;
     static constexpr int NRAW = PRE == PRE_X ? 2 : PRE == PRE_UP ? 6 : 4;
     struct Ctx {
         int64_t ra, hb;
@@ -357,7 +372,7 @@ template <int PRE> struct HalfFwdOp {
     double *p_io, *u_out;   // PRE_UP
     double *q_out;          // PRE_Q
     double2 *Z;
-    int64_t nf, W;
+    int64_t nf, W, nx;      // nx: rows of the array (TR)
     const double *fpart;    // partials folded here
     int fnp, k, fresh;
     double coef;            // beta (PRE_UP) or alpha (PRE_Q)
@@ -460,14 +475,49 @@ template <int PRE> struct HalfFwdOp {
         Z[cx.hb + k] = A;
         Z[cx.hb + W + k] = Bv;
     }
+    // TR: the tile's B pairs (rows 2 c0 .. 2 c0 + 2B - 1) from their LDS slabs
+    // (natural order) to Z[k * nx + row], thread t taking k = idx / 2B, row
+    // 2 c0 + idx % 2B, so consecutive threads write consecutive rows
+    __device__ __forceinline__ void store_half_t(const double2 *lds, int LS, int B, int64_t c0, int64_t npairs,
+                                                 int t, int nt) const {
+        const int R = 2 * B;
+        const int P = (int)nf;
+        for (int idx = t; idx < (int)W * R; idx += nt) {
+            const int k = idx / R, r = idx % R, q = r >> 1;
+            if (c0 + q >= npairs) continue;
+            const double2 *sl = lds + q * LS;
+            const double2 Zk = sl[lpad(k)], Zc = sl[lpad((P - k) & (P - 1))];
+            Z[(int64_t)k * nx + 2 * c0 + r] = (r & 1) ? make_double2(0.5 * (Zk.y + Zc.y), -0.5 * (Zk.x - Zc.x))
+                                                      : make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y - Zc.y));
+        }
+    }
 };
+
+template <int PRE> HalfFwdOp<PRE, true> transposed(const HalfFwdOp<PRE, false> &f, int64_t nx) {
+    HalfFwdOp<PRE, true> t{};
+    t.x = f.x;
+    t.q_in = f.q_in;
+    t.p_io = f.p_io;
+    t.u_out = f.u_out;
+    t.q_out = f.q_out;
+    t.Z = f.Z;
+    t.nf = f.nf;
+    t.W = f.W;
+    t.nx = nx;
+    t.fpart = f.fpart;
+    t.fnp = f.fnp;
+    t.k = f.k;
+    t.fresh = f.fresh;
+    t.pred = f.pred;
+    return t;
+}
 
 // P^{-1}, pass along a middle axis (3D: y) of the half spectra, in place,
 // forward (DIR -1) or inverse (DIR +1).  Line l: base (l / W) * n W + l % W,
 // stride W.
 template <int DIR_> struct CplxOp {
     static constexpr int NFFT = 1, DIR = DIR_, NRAW = 2, FOLD = 0, NACC = 0;
-    static constexpr bool HALF = false;
+    static constexpr bool HALF = false, HALF_T = false, IN_T = false;
     struct Ctx {
         int64_t base;
     };
@@ -498,13 +548,14 @@ template <int DIR_> struct CplxOp {
 // sum (Strang circulants' eigenvalues).
 struct DivOp {
     static constexpr int NFFT = 2, DIR = 0, NRAW = 2, FOLD = 0, NACC = 0;
-    static constexpr bool HALF = false;
+    static constexpr bool HALF = false, HALF_T = false, IN_T = false;
     struct Ctx {
         int64_t l;
         double2 mo;
     };
     double2 *Z;
-    int64_t nl, W;
+    int64_t nl, W;  // element p of line l at l * ll + p * nl
+    int64_t ll = 1;
     int mid;  // 1 in 3D
     Sym sx, sm, sf;
     double eta, sigma;
@@ -519,7 +570,7 @@ struct DivOp {
             mo.x += m2.x;
             mo.y += m2.y;
         }
-        return Ctx{l, mo};
+        return Ctx{l * ll, mo};
     }
     __device__ __forceinline__ void fetch(const Ctx &cx, int p, double *raw) const {
         const double2 z = Z[cx.l + p * nl];
@@ -545,7 +596,7 @@ struct DivOp {
 // part -> row 2c, imaginary part -> row 2c+1, scaled by 1/N.
 struct HalfInvOp {
     static constexpr int NFFT = 1, DIR = 1, NRAW = 4, FOLD = 0, NACC = 0;
-    static constexpr bool HALF = false;
+    static constexpr bool HALF = false, HALF_T = false, IN_T = false;
     struct Ctx {
         int64_t ra, hb;
     };
@@ -585,10 +636,67 @@ struct HalfInvOp {
     __device__ void store_half(const Ctx &, int, double2, double2) const {}
 };
 
+// P^{-1}, fast-axis inverse pass from transposed half spectra (two
+// dimensions, Z[k * nx + row]): the workgroup first copies its pairs' half
+// spectra into LDS (consecutive threads, consecutive rows of one k; row 2c's
+// values at slab[k], row 2c+1's at slab[W + k], 2W <= LS slots), then works
+// as HalfInvOp.
+struct HalfInvTOp {
+    static constexpr int NFFT = 1, DIR = 1, NRAW = 4, FOLD = 0, NACC = 0;
+    static constexpr bool HALF = false, HALF_T = false, IN_T = true;
+    struct Ctx {
+        int64_t ra;
+        const double2 *slab;
+    };
+    const double2 *Z;
+    double *y;
+    int64_t nf, W, nx;
+    double scale;
+    double *part;
+    int pred;
+    __device__ void prep(const Sc *) {}
+    __device__ bool fold(Sc *) { return false; }
+    __device__ __forceinline__ Ctx ctx(int64_t c) const { return Ctx{2 * c * nf, nullptr}; }
+    __device__ __forceinline__ void stage_in(double2 *lds, int LS, int B, int64_t c0, int64_t npairs, int t,
+                                             int nt) const {
+        const int R = 2 * B;
+        for (int idx = t; idx < (int)W * R; idx += nt) {
+            const int k = idx / R, r = idx % R, q = r >> 1;
+            if (c0 + q >= npairs) continue;
+            lds[q * LS + (r & 1) * (int)W + k] = Z[(int64_t)k * nx + 2 * c0 + r];
+        }
+    }
+    __device__ __forceinline__ void fetch(const Ctx &cx, int p, double *raw) const {
+        const int k = p <= nf / 2 ? p : (int)nf - p;
+        const double2 a = cx.slab[k], b = cx.slab[W + k];
+        raw[0] = a.x;
+        raw[1] = a.y;
+        raw[2] = b.x;
+        raw[3] = b.y;
+    }
+    __device__ __forceinline__ double2 finish(const Ctx &, int p, const double *raw) const {
+        double ay = raw[1], by = raw[3];
+        if (p == 0 || p == nf / 2) {
+            ay = 0.0;
+            by = 0.0;
+        } else if (p > nf / 2) {
+            ay = -ay;
+            by = -by;
+        }
+        return make_double2(raw[0] - by, ay + raw[2]);
+    }
+    __device__ __forceinline__ double2 spec(const Ctx &, int, double2 V) const { return V; }
+    __device__ __forceinline__ void store(const Ctx &cx, int p, double2 V, double *) const {
+        y[cx.ra + p] = V.x * scale;
+        y[cx.ra + nf + p] = V.y * scale;
+    }
+    __device__ void store_half(const Ctx &, int, double2, double2) const {}
+};
+
 // Forward DFT of one real column of `len` values zero-padded to P (spectra).
 struct SpecOp {
     static constexpr int NFFT = 1, DIR = -1, NRAW = 1, FOLD = 0, NACC = 0;
-    static constexpr bool HALF = false;
+    static constexpr bool HALF = false, HALF_T = false, IN_T = false;
     struct Ctx {
         int dummy;
     };
@@ -1069,7 +1177,35 @@ hipError_t product(NdPlan *pl, int64_t j, const double *v, double *y, double ca,
 template <class First> hipError_t psolve_from(NdPlan *pl, int64_t j, const First &first, double *y, int pred) {
     const int d = pl->d;
     const int64_t nf = pl->n[d - 1], W = pl->W, rows2 = pl->N / nf / 2;
-    hipError_t e = line<true>(pl, nf, first, rows2);
+    hipError_t e;
+    if (d == 2) {
+        // two dimensions: the half spectrum kept transposed (Z[ky * nx + kx]),
+        // so the division pass runs along contiguous rows
+        const int64_t nx = pl->n[0];
+        if ((e = line<true>(pl, nf, transposed(first, nx), rows2)) != hipSuccess) return e;
+        DivOp dv{};
+        dv.Z = pl->Z;
+        dv.nl = 1;
+        dv.ll = nx;
+        dv.W = W;
+        dv.mid = 0;
+        dv.sx = symbol(pl, 0, j, false);
+        dv.sf = symbol(pl, 1, j, false);
+        dv.eta = pl->eta[j];
+        dv.sigma = pl->sigma;
+        dv.pred = pred;
+        if ((e = line<true>(pl, nx, dv, W)) != hipSuccess) return e;
+        HalfInvTOp hi{};
+        hi.Z = pl->Z;
+        hi.y = y;
+        hi.nf = nf;
+        hi.W = W;
+        hi.nx = nx;
+        hi.scale = 1.0 / (double)pl->N;
+        hi.pred = pred;
+        return line<true>(pl, nf, hi, rows2);
+    }
+    e = line<true>(pl, nf, first, rows2);
     if (e != hipSuccess) return e;
     if (d == 3) {
         CplxOp<-1> o{};
