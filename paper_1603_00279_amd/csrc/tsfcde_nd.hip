@@ -25,13 +25,18 @@
 //    transforms, divides by the eigenvalues eta - sigma sum mu_axis(k_axis)
 //    and transforms back; then y back (3D), and the fast axis back
 //    (HalfInvOp: the half spectra of two rows rebuilt into one complex
-//    transform whose real and imaginary parts are the two rows).
+//    transform whose real and imaginary parts are the two rows).  In two
+//    dimensions the half spectrum is stored transposed, written and read
+//    through LDS by whole workgroups (HalfFwdOp<., true>, HalfInvTOp), so
+//    that the division pass runs along contiguous rows.
+//  * The history sum in blocks of HB levels (k_hist_sweep, k_hist_catch).
 //  * The CGS vector updates run inside the passes: the u/p update in the
 //    first pass of the first preconditioner solve of an iteration, the q/s
 //    update in the first pass of the second, x and r in the last product's
 //    epilogue.  Dot products are reduced per workgroup (fixed order) and
 //    finished inside the pass that needs them, in the same fixed order in
-//    every workgroup (reproducible results, no finishing launches).
+//    every workgroup (reproducible results; a one-workgroup kernel only when
+//    a pass has more than MAXPART workgroups, and at the end of a chunk).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
