@@ -270,21 +270,26 @@ __global__ void __launch_bounds__(NTL, 4) k_line(Op op, int64_t nlines, const do
 // Strang circulant (length n): cre Re lam(k) + i (cim Im lam(k) + cq sin(2 pi k / P)),
 // lam the DFT of W's column (embedding or Strang), cre = h^-b (d+ + d-),
 // cim = h^-b (d+ - d-), cq = gamma/h (Q's spectrum is 2i sin(2 pi k / P)).
+// A real shift c0 (the identity's symbol is 1) folds the a v term of the
+// slow-axis pass into its transform, so that pass's epilogue needs no
+// second read of v.
 struct Sym {
     const double2 *lam, *tw;  // tw: the length-P twiddle table
-    double cre, cim, cq;
+    double cre, cim, cq, c0 = 0.0;
     __device__ __forceinline__ double2 operator()(int64_t k) const {
         const double2 L = lam[k];
-        return make_double2(cre * L.x, fma(cim, L.y, -cq * tw[k].y));
+        return make_double2(fma(cre, L.x, c0), fma(cim, L.y, -cq * tw[k].y));
     }
 };
 
 enum : int { EPI_W = 0, EPI_WADD = 1, EPI_Y = 2, EPI_DOT = 3, EPI_XR = 4 };
 
 // L_axis v on pairs of real lines (2c, 2c+1) of one axis.  EPI_W: w = L v;
-// EPI_WADD: w += L v; otherwise y = ca v + cb (w + L v) and
+// EPI_WADD: w += L v; otherwise y = cb (w + (ca/cb + L) v), the shift ca/cb
+// in the symbol (Sym::c0), and
 //   EPI_Y: store y;  EPI_DOT: store y, reduce rt.y;
-//   EPI_XR: (y = A uhat, v = uhat) x += alpha v, r -= alpha y, reduce rt.r and r.r.
+//   EPI_XR: (y = A uhat) r -= alpha y, reduce rt.r and r.r (x += alpha uhat
+//   is done where uhat is formed, HalfInvOp).
 template <int EPI> struct ToepOp {
     static constexpr int NFFT = 2, DIR = 0, NRAW = 2, FOLD = 0;
     static constexpr bool HALF = false, HALF_T = false, IN_T = false;
@@ -298,9 +303,9 @@ template <int EPI> struct ToepOp {
     double invP;
     double *w;
     double *y;
-    double ca, cb;
+    double cb;
     const double *rt;
-    double *x, *r;
+    double *r;
     double *part;
     double alpha;
     int pred;
@@ -327,15 +332,13 @@ template <int EPI> struct ToepOp {
         } else if constexpr (EPI == EPI_WADD) {
             w[i] += Lv;
         } else {
-            const double vi = v[i];
-            const double yi = fma(ca, vi, cb * (w[i] + Lv));
+            const double yi = cb * (w[i] + Lv);
             if constexpr (EPI == EPI_Y) {
                 y[i] = yi;
             } else if constexpr (EPI == EPI_DOT) {
                 y[i] = yi;
                 acc[0] = fma(rt[i], yi, acc[0]);
             } else {
-                x[i] = fma(alpha, vi, x[i]);
                 const double ri = fma(-alpha, yi, r[i]);
                 r[i] = ri;
                 acc[0] = fma(rt[i], ri, acc[0]);
@@ -607,11 +610,14 @@ struct HalfInvOp {
     };
     const double2 *Z;
     double *y;
+    double *x;  // non-NULL: also x += alpha y (CGS, the second solve of an iteration)
     int64_t nf, W;
-    double scale;
+    double scale, alpha;
     double *part;
     int pred;
-    __device__ void prep(const Sc *) {}
+    __device__ void prep(const Sc *sc) {
+        if (x) alpha = sc->alpha;
+    }
     __device__ bool fold(Sc *) { return false; }
     __device__ __forceinline__ Ctx ctx(int64_t c) const { return Ctx{2 * c * nf, 2 * c * W}; }
     __device__ __forceinline__ void fetch(const Ctx &cx, int p, double *raw) const {
@@ -635,8 +641,14 @@ struct HalfInvOp {
     }
     __device__ __forceinline__ double2 spec(const Ctx &, int, double2 V) const { return V; }
     __device__ __forceinline__ void store(const Ctx &cx, int p, double2 V, double *) const {
-        y[cx.ra + p] = V.x * scale;
-        y[cx.ra + nf + p] = V.y * scale;
+        const int64_t ia = cx.ra + p, ib = ia + nf;
+        const double ya = V.x * scale, yb = V.y * scale;
+        y[ia] = ya;
+        y[ib] = yb;
+        if (x) {
+            x[ia] = fma(alpha, ya, x[ia]);
+            x[ib] = fma(alpha, yb, x[ib]);
+        }
     }
     __device__ void store_half(const Ctx &, int, double2, double2) const {}
 };
@@ -655,11 +667,14 @@ struct HalfInvTOp {
     };
     const double2 *Z;
     double *y;
+    double *x;  // non-NULL: also x += alpha y, as in HalfInvOp
     int64_t nf, W, nx;
-    double scale;
+    double scale, alpha;
     double *part;
     int pred;
-    __device__ void prep(const Sc *) {}
+    __device__ void prep(const Sc *sc) {
+        if (x) alpha = sc->alpha;
+    }
     __device__ bool fold(Sc *) { return false; }
     __device__ __forceinline__ Ctx ctx(int64_t c) const { return Ctx{2 * c * nf, nullptr}; }
     __device__ __forceinline__ void stage_in(double2 *lds, int LS, int B, int64_t c0, int64_t npairs, int t,
@@ -692,8 +707,14 @@ struct HalfInvTOp {
     }
     __device__ __forceinline__ double2 spec(const Ctx &, int, double2 V) const { return V; }
     __device__ __forceinline__ void store(const Ctx &cx, int p, double2 V, double *) const {
-        y[cx.ra + p] = V.x * scale;
-        y[cx.ra + nf + p] = V.y * scale;
+        const int64_t ia = cx.ra + p, ib = ia + nf;
+        const double ya = V.x * scale, yb = V.y * scale;
+        y[ia] = ya;
+        y[ib] = yb;
+        if (x) {
+            x[ia] = fma(alpha, ya, x[ia]);
+            x[ib] = fma(alpha, yb, x[ib]);
+        }
     }
     __device__ void store_half(const Ctx &, int, double2, double2) const {}
 };
@@ -1105,11 +1126,11 @@ Sym symbol(const NdPlan *pl, int a, int64_t j, bool emb) {
 enum class Fin { Y, DOT, XR };
 
 // y = ca v + cb L v at level j, L = sum_axes L_axis: the fast axis first
-// (w = L v), a middle axis adds (w += L v), the slow axis finishes with
-// the epilogue `fin` (Y: store y; DOT: store y = vhat and reduce rt.y into
-// part1; XR: update x and r from y = A v and reduce rt.r, r.r into part2).
-hipError_t product(NdPlan *pl, int64_t j, const double *v, double *y, double ca, double cb, int pred, Fin fin,
-                   double *x = nullptr) {
+// (w = L v), a middle axis adds (w += L v), the slow axis finishes (with
+// ca/cb folded into its symbol) with the epilogue `fin` (Y: store y; DOT:
+// store y = vhat and reduce rt.y into part1; XR: update r from y = A v and
+// reduce rt.r, r.r into part2).  cb must not be 0.
+hipError_t product(NdPlan *pl, int64_t j, const double *v, double *y, double ca, double cb, int pred, Fin fin) {
     const int d = pl->d;
     hipError_t e;
     for (int a = d - 1; a >= 1; --a) {
@@ -1146,10 +1167,10 @@ hipError_t product(NdPlan *pl, int64_t j, const double *v, double *y, double ca,
         o.s = s;
         o.ns = n * s;
         o.sym = symbol(pl, 0, j, true);
+        o.sym.c0 = ca / cb;
         o.invP = 1.0 / (double)(2 * n);
         o.w = pl->w;
         o.y = y;
-        o.ca = ca;
         o.cb = cb;
         o.rt = pl->rt;
         o.pred = pred;
@@ -1169,7 +1190,6 @@ hipError_t product(NdPlan *pl, int64_t j, const double *v, double *y, double ca,
     }
     ToepOp<EPI_XR> o{};
     fill(o);
-    o.x = x;
     o.r = pl->r;
     o.part = pl->part2;
     if ((e = line<false>(pl, 2 * n, o, nlines, &np)) != hipSuccess) return e;
@@ -1179,7 +1199,8 @@ hipError_t product(NdPlan *pl, int64_t j, const double *v, double *y, double ca,
 // y = P^{-1} (input of the first pass) at level j: the fast-axis forward pass
 // `first` (built by the caller), the middle axis (3D), the slow axis with
 // the division, the middle axis back, the fast axis back into y.
-template <class First> hipError_t psolve_from(NdPlan *pl, int64_t j, const First &first, double *y, int pred) {
+template <class First>
+hipError_t psolve_from(NdPlan *pl, int64_t j, const First &first, double *y, int pred, double *x_upd = nullptr) {
     const int d = pl->d;
     const int64_t nf = pl->n[d - 1], W = pl->W, rows2 = pl->N / nf / 2;
     hipError_t e;
@@ -1203,6 +1224,7 @@ template <class First> hipError_t psolve_from(NdPlan *pl, int64_t j, const First
         HalfInvTOp hi{};
         hi.Z = pl->Z;
         hi.y = y;
+        hi.x = x_upd;
         hi.nf = nf;
         hi.W = W;
         hi.nx = nx;
@@ -1243,6 +1265,7 @@ template <class First> hipError_t psolve_from(NdPlan *pl, int64_t j, const First
     HalfInvOp hi{};
     hi.Z = pl->Z;
     hi.y = y;
+    hi.x = x_upd;
     hi.nf = nf;
     hi.W = W;
     hi.scale = 1.0 / (double)pl->N;
@@ -1294,8 +1317,8 @@ hipError_t cgs_iteration(NdPlan *pl, int64_t j, double *x, int k, bool fresh) {
     c.fnp = pl->nfold1;
     c.k = k;
     c.pred = 1;
-    if ((e = psolve_from(pl, j, c, pl->uhat, 1)) != hipSuccess) return e;
-    return product(pl, j, pl->uhat, nullptr, eta, -sg, 1, Fin::XR, x);
+    if ((e = psolve_from(pl, j, c, pl->uhat, 1, x)) != hipSuccess) return e;  // and x += alpha uhat
+    return product(pl, j, pl->uhat, nullptr, eta, -sg, 1, Fin::XR);
 }
 
 int poll(NdPlan *pl) {
