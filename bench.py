@@ -172,12 +172,13 @@ def path_bytes_nd(d, N, levels, iters, restarts=0):
     then 2 per further pass: the middle axis twice in 3D, the division pass,
     the inverse fast-axis pass), the product (fast axis 2, middle axis 3, the
     slow axis with rt.vhat 4), the second solve (forward pass with the q
-    update: u, vhat in, q and the spectrum out, 4; then as before) and the
-    product with the x/r update (slow axis: uhat, w, rt, x, r in, x, r out,
-    7): 33 units in 2D, 47 in 3D.  A level adds its right-hand side and one
-    acceptance check per (re)start (products of 3d - 1 units each, the
-    right-hand side kernel 6, the zero guess 1, the residual 5) and the
-    history (j + 2 units at level j >= 1)."""
+    update: u, vhat in, q and the spectrum out, 4; then as before, its last
+    pass also updating x: 2 more) and the product with the r update (slow
+    axis: uhat, w, rt, r in, r out, 5): 33 units in 2D, 47 in 3D.  A level
+    adds its right-hand side and one acceptance check per (re)start
+    (products of 3d - 1 units each, the right-hand side kernel 6, the zero
+    guess 1, the residual 5) and the history (j + 2 units at level j >= 1,
+    the whole sum; the blocked sum moves fewer)."""
     per_iter = {2: 33, 3: 47}[d]
     hist = sum(j + 2 for j in range(1, levels))
     prod = 3 * d - 1
