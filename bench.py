@@ -194,7 +194,8 @@ def nd_form(args, P, W, dev, d):
     family (alpha = 0.6, one order per axis), zero initial guess, rtol as
     the headline; sources on the device before timing.  Two timed marches
     after a warm-up march; the faster counts.  The same with the quadratic
-    extrapolation as each level's initial guess.  At 2^20 unknowns the working
+    extrapolation as each level's initial guess, and (2D) one march of the
+    headline's M = 512 levels with that guess.  At 2^20 unknowns the working
     set (about 20 vectors of 8 MiB) fits in the 256 MiB Infinity Cache, so the
     byte rate is not bounded by HBM; at 2^24 it is."""
     import numpy as np
@@ -229,6 +230,23 @@ def nd_form(args, P, W, dev, d):
     dt, st, code = run(P.TSFCDE_WS_ZERO)
     dtx, stx, codex = run(P.TSFCDE_WS_EXTRAP)
     del F
+    long = None
+    if d == 2:
+        # the headline's M = 512 levels (tau = 1/512, history sums over up to
+        # 512 levels, blocked), extrapolated guess: one timed march
+        probl = W.problem_2d(*ns, 512)
+        with Solver.from_problem(probl, rtol=args.rtol, warm_start=P.TSFCDE_WS_EXTRAP) as sv:
+            Fl = src(probl, *sv.nodes(), sv.level_times(), dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            codel, stl = sv.solve(Fl, raise_on_error=False)
+            torch.cuda.synchronize()
+            dtl = time.perf_counter() - t0
+            del Fl
+        long = {"workload": f"{'x'.join(str(n) for n in ns)}, M=512, extrapolated guess", "value": 512 / dtl,
+                "unit": "level-solves/s", "code": int(codel),
+                "cgs_iterations_mean": float(np.mean([int(q["iters"]) for q in stl])), "acceptance": acceptance(stl)}
+        log(f"form 2d, M=512, extrapolated guess: {512 / dtl:.1f} level-solves/s")
     iters = [int(q["iters"]) for q in st]
     restarts = int(sum(int(q["restarts"]) for q in st))
     nbytes = path_bytes_nd(d, N, M, iters, restarts)
@@ -246,6 +264,8 @@ def nd_form(args, P, W, dev, d):
            "extrapolated": {"value": M / dtx, "unit": "level-solves/s", "code": int(codex),
                             "cgs_iterations_mean": float(np.mean([int(q["iters"]) for q in stx])),
                             "speedup_vs_zero_guess": dt / dtx, "acceptance": acceptance(stx)}}
+    if long is not None:
+        out["long_march_extrapolated"] = long
     log(f"form {d}d extrapolated guess: {M / dtx:.2f} level-solves/s, "
         f"{out['extrapolated']['cgs_iterations_mean']:.1f} iterations")
     log(f"form {d}d: {M / dt:.2f} level-solves/s, {np.mean(iters):.1f} iterations, "
