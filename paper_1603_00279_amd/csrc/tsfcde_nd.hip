@@ -297,14 +297,36 @@ __global__ void __launch_bounds__(NTL, 4) k_line(Op op, int64_t nlines, const do
 // A real shift c0 (the identity's symbol is 1) folds the a v term of the
 // slow-axis pass into its transform, so that pass's epilogue needs no
 // second read of v.
+// The level's symbol values are tabulated once per level (k_symbols): one
+// load per frequency in the passes instead of the spectrum and a twiddle.
 struct Sym {
-    const double2 *lam, *tw;  // tw: the length-P twiddle table
-    double cre, cim, cq, c0 = 0.0;
+    const double2 *tab;  // the level's symbol at k = 0..P-1
+    double c0 = 0.0;
     __device__ __forceinline__ double2 operator()(int64_t k) const {
-        const double2 L = lam[k];
-        return make_double2(fma(cre, L.x, c0), fma(cim, L.y, -cq * tw[k].y));
+        const double2 S = tab[k];
+        return make_double2(S.x + c0, S.y);
     }
 };
+
+// The symbols of one level: for each of up to 6 tables (per axis, the
+// embedding of length 2n and the Strang circulant of length n),
+// out[k] = (cre Re lam(k), cim Im lam(k) + cq sin(2 pi k / P)).
+struct SymTabs {
+    const double2 *lam[6];
+    const double2 *tw[6];  // the length-P twiddle tables
+    double2 *out[6];
+    int64_t P[6];
+    double cre[6], cim[6], cq[6];
+    int count;
+};
+__global__ void __launch_bounds__(256) k_symbols(SymTabs t) {
+    const int e = blockIdx.y;
+    if (e >= t.count) return;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < t.P[e]; k += (int64_t)gridDim.x * 256) {
+        const double2 L = t.lam[e][k];
+        t.out[e][k] = make_double2(t.cre[e] * L.x, fma(t.cim[e], L.y, -t.cq[e] * t.tw[e][k].y));
+    }
+}
 
 enum : int { EPI_W = 0, EPI_WADD = 1, EPI_Y = 2, EPI_DOT = 3, EPI_XR = 4 };
 
@@ -980,6 +1002,8 @@ struct NdPlan {
            *d_cbase = nullptr, *cols = nullptr;
     double2 *Z = nullptr, *lam[3] = {}, *ls[3] = {}, *tw = nullptr;
     Sc *sc = nullptr;
+    double2 *symE[3] = {}, *symS[3] = {};  // level sym_level's symbols (embedding, Strang)
+    int64_t sym_level = -1;
     double *Q = nullptr;  // the current history block's partial sums (HB vectors)
     int64_t qblock = 0;   // first level of the block Q holds (0: none)
     // what the folding passes read: rt.vhat (fold1) and rt.r, r.r (fold2)
@@ -1002,7 +1026,7 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr int NVEC = 13;  // g r rt u p q phat uhat vhat t w H fbuf
 
 struct Layout {
-    size_t U, vec, Z, lam, tw, part, sc, cb, Q, cols, total;
+    size_t U, vec, Z, lam, sym, tw, part, sc, cb, Q, cols, total;
 };
 
 int64_t spec_len(const int64_t *n, int d) {
@@ -1031,6 +1055,7 @@ Layout layout(const int64_t *n, int d, int64_t M) {
     L.vec = take(sizeof(double) * NVEC * (size_t)N);
     L.Z = take(sizeof(double2) * (size_t)Nh);
     L.lam = take(sizeof(double2) * (size_t)spec_len(n, d));
+    L.sym = take(sizeof(double2) * (size_t)spec_len(n, d));
     L.tw = take(sizeof(double2) * (size_t)((int64_t(1) << (PMAX_LOG2 + 1)) - 2));
     L.part = take(sizeof(double) * (size_t)(2 * 2 * part_len(N) + 2 * RBLK + 4));
     L.sc = take(sizeof(Sc));
@@ -1136,14 +1161,34 @@ int64_t stride_of(const NdPlan *pl, int a) {
     return s;
 }
 
-Sym symbol(const NdPlan *pl, int a, int64_t j, bool emb) {
+// The symbol tables of level j (all axes), computed when the plan's tables
+// hold another level.
+hipError_t ensure_symbols(NdPlan *pl, int64_t j) {
+    if (pl->sym_level == j) return hipSuccess;
+    SymTabs t{};
+    for (int a = 0; a < pl->d; ++a) {
+        for (int emb = 0; emb < 2; ++emb) {
+            const int e = t.count++;
+            const int64_t P = emb ? 2 * pl->n[a] : pl->n[a];
+            t.lam[e] = emb ? pl->lam[a] : pl->ls[a];
+            t.tw[e] = pl->tw + tw_offset((int)P);
+            t.out[e] = emb ? pl->symE[a] : pl->symS[a];
+            t.P[e] = P;
+            t.cre[e] = pl->hb[a] * (pl->dp[a][j] + pl->dm[a][j]);
+            t.cim[e] = pl->hb[a] * (pl->dp[a][j] - pl->dm[a][j]);
+            t.cq[e] = pl->gam[a][j] / pl->h[a];
+        }
+    }
+    hipLaunchKernelGGL(k_symbols, dim3(16, (unsigned)t.count), dim3(256), 0, pl->stream, t);
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) pl->sym_level = j;
+    return e;
+}
+
+// level j's symbol of axis a (ensure_symbols(pl, j) queued before)
+Sym symbol(const NdPlan *pl, int a, int64_t, bool emb) {
     Sym s{};
-    const int64_t P = emb ? 2 * pl->n[a] : pl->n[a];
-    s.lam = emb ? pl->lam[a] : pl->ls[a];
-    s.tw = pl->tw + tw_offset((int)P);
-    s.cre = pl->hb[a] * (pl->dp[a][j] + pl->dm[a][j]);
-    s.cim = pl->hb[a] * (pl->dp[a][j] - pl->dm[a][j]);
-    s.cq = pl->gam[a][j] / pl->h[a];
+    s.tab = emb ? pl->symE[a] : pl->symS[a];
     return s;
 }
 
@@ -1404,6 +1449,7 @@ int level_step(NdPlan *pl, const double *d_f, double *d_u_out, tsfcde_stats *st)
         if (int rc = callback_source(pl, j, &d_f)) return rc;
     }
     double *x = pl->U + (size_t)(j + 1) * (size_t)N;
+    HIPCHK(ensure_symbols(pl, j));
     // history sum and right-hand side g = B u^j - H + f
     if (j >= 1) {
         const int64_t b = 1 + HB * ((j - 1) / HB);
@@ -1702,11 +1748,14 @@ int plan_create(const NdProblem &prob, void *d_workspace, size_t bytes, void *st
     for (int k = 0; k < NVEC; ++k) *bufs[k] = vec + (size_t)k * (size_t)N;
     pl->Z = reinterpret_cast<double2 *>(ws + L.Z);
     {
-        double2 *sp = reinterpret_cast<double2 *>(ws + L.lam);
+        double2 *sp = reinterpret_cast<double2 *>(ws + L.lam), *sy = reinterpret_cast<double2 *>(ws + L.sym);
         for (int a = 0; a < d; ++a) {
             pl->lam[a] = sp;
             pl->ls[a] = sp + 2 * pl->n[a];
+            pl->symE[a] = sy;
+            pl->symS[a] = sy + 2 * pl->n[a];
             sp += 3 * pl->n[a];
+            sy += 3 * pl->n[a];
         }
     }
     pl->tw = reinterpret_cast<double2 *>(ws + L.tw);
@@ -1793,7 +1842,9 @@ int solve_all(NdPlan *pl, const double *d_F, int64_t ldF, double *d_U_out, tsfcd
 
 int apply_op(NdPlan *pl, int32_t op, int64_t j, const double *d_x, double *d_y) {
     if (!pl || !d_x || !d_y || d_x == d_y || j < 0 || j >= pl->M) return TSFCDE_EINVAL;
-    hipError_t e;
+    if (op != TSFCDE_OP_A && op != TSFCDE_OP_B && op != TSFCDE_OP_PINV) return TSFCDE_EINVAL;
+    hipError_t e = ensure_symbols(pl, j);
+    if (e != hipSuccess) return TSFCDE_EDEVICE;
     if (op == TSFCDE_OP_A) {
         e = product(pl, j, d_x, d_y, pl->eta[j], -pl->sigma, 0, Fin::Y);
     } else if (op == TSFCDE_OP_B) {
