@@ -241,3 +241,29 @@ def test_history_blocks_and_mid_block_resume():
         s.set_state(13, torch.as_tensor(U[:14], device="cuda"))
         code, _ = s.solve(F)
         assert code == 0 and np.array_equal(host(s.history()), U)
+
+
+def test_level_symbols_follow_the_level():
+    """The axis symbols are tabulated once per level: A and P^{-1} applied at
+    levels 5, 0, 5, 3 in turn match the oracle at each, and a march run after
+    an apply at another level is bitwise the march of a fresh plan."""
+    import paper_1603_00279_amd as P
+    banner("2d level symbol tables")
+    prob = W.problem_2d(32, 64, 6, beta_x=1.6, beta_y=1.3)
+    X = np.random.default_rng(21).standard_normal((32, 64))
+    with solver(prob, rtol=1e-12) as s:
+        F = sources(s, prob)
+        for j in (5, 0, 5, 3):
+            S = O2.anorm2(prob, j) * np.max(np.abs(X))
+            got = host(s.apply(P.TSFCDE_OP_A, j, torch.as_tensor(X, device="cuda")))
+            assert np.max(np.abs(got - O2.product2(prob, j, X, "A"))) <= 1e-13 * S, j
+            Y = host(s.apply(P.TSFCDE_OP_PINV, j, torch.as_tensor(X, device="cuda")))
+            eig = O2.bccb_eigenvalues(prob, j)
+            back = np.fft.ifft2(np.fft.fft2(Y) * eig).real
+            assert np.max(np.abs(back - X)) <= 1e-13 * np.max(np.abs(eig)) * np.max(np.abs(Y)), j
+        code, _ = s.solve(F)
+        U1 = host(s.history())
+    assert code == 0
+    with solver(prob, rtol=1e-12) as s:
+        code, _ = s.solve(F)
+        assert code == 0 and np.array_equal(host(s.history()), U1)

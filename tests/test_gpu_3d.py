@@ -217,3 +217,29 @@ def test_history_blocks():
     worst = max(np.max(np.abs(U[j] - Uref[j])) / np.max(np.abs(Uref[j])) for j in range(1, prob.M + 1))
     print(f"[3d history blocks] worst rel err {worst:.2e}", flush=True)
     assert worst < 1e-10
+
+
+def test_level_symbols_follow_the_level():
+    """The axis symbols are tabulated once per level: A and P^{-1} applied at
+    levels 4, 0, 4, 2 in turn match the oracle at each, and a march run after
+    an apply at another level is bitwise the march of a fresh plan."""
+    import paper_1603_00279_amd as P
+    banner("3d level symbol tables")
+    prob = W.problem_3d(16, 32, 16, 5, betas=(1.6, 1.3, 1.9))
+    X = np.random.default_rng(22).standard_normal(prob.ns)
+    with solver(prob, rtol=1e-12) as s:
+        F = sources(s, prob)
+        for j in (4, 0, 4, 2):
+            S = O3.anorm3(prob, j) * np.max(np.abs(X))
+            got = host(s.apply(P.TSFCDE_OP_A, j, torch.as_tensor(X, device="cuda")))
+            assert np.max(np.abs(got - O3.product3(prob, j, X, "A"))) <= 1e-13 * S, j
+            Y = host(s.apply(P.TSFCDE_OP_PINV, j, torch.as_tensor(X, device="cuda")))
+            eig = O3.bccb3_eigenvalues(prob, j)
+            back = np.fft.ifftn(np.fft.fftn(Y) * eig).real
+            assert np.max(np.abs(back - X)) <= 1e-13 * np.max(np.abs(eig)) * np.max(np.abs(Y)), j
+        code, _ = s.solve(F)
+        U1 = host(s.history())
+    assert code == 0
+    with solver(prob, rtol=1e-12) as s:
+        code, _ = s.solve(F)
+        assert code == 0 and np.array_equal(host(s.history()), U1)
