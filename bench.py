@@ -436,42 +436,79 @@ def batched_form(args, P, W, dev):
     return out
 
 
+def iteration_summary(its):
+    """Mean and distribution of per-level CGS iteration counts."""
+    import numpy as np
+    a = np.asarray(its, dtype=float)
+    return {"mean": float(a.mean()), "p50": float(np.percentile(a, 50)), "p90": float(np.percentile(a, 90)),
+            "max": float(a.max())}
+
+
+def net_cost_iterations(prev, extrap, net):
+    """The network's cost per level in CGS-iteration equivalents.  Each
+    argument is (seconds per level, mean CGS iterations per level); the
+    previous-level and extrapolated guesses (both checked by the same
+    acceptance product, neither with inference) fix the line
+    seconds = c + t_it * iterations, and the network's excess over that line,
+    divided by t_it, is its cost.  None when the two guesses take the same
+    iterations (no slope)."""
+    (tp, ip), (te, ie), (tn, i_n) = prev, extrap, net
+    if abs(ip - ie) < 1e-9:
+        return None
+    t_it = (tp - te) / (ip - ie)
+    if t_it <= 0.0:
+        return None
+    c = te - t_it * ie
+    return (tn - (c + t_it * i_n)) / t_it
+
+
 def learned_form(args, P, W, dev):
     """The learned warm start with the committed parameters (trained by
     paper_1603_00279_amd.warmnet on 2000 trajectories at n = 2^14, M = 256)
-    on held-out (alpha, beta) at n = 2^14, against the previous-level and
-    extrapolated guesses."""
+    on held-out (alpha, beta) at n = 2^14 and 2^18, against the plain,
+    previous-level and extrapolated guesses: level-solves/s, the distribution
+    of CGS iterations per level and the network's cost in iteration
+    equivalents."""
     import numpy as np
     import torch
     from paper_1603_00279_amd import warmnet as WN
     path = os.path.join(ROOT, "paper_1603_00279_amd", "data", "warmnet_c4.npz")
     theta = np.load(path)["theta"]
-    n, M = 1 << 14, 256
-    held = W.warmstart_instances(2, n, M, seed=W.SEED_BASE + 77, held_out=True)
-    out = {"workload": f"held-out (alpha, beta), n={n}, M={M}, Example-2 time dependence", "parameters":
-           os.path.relpath(path, ROOT)}
-    with P.WarmStartNet(max_points=n, max_batch=1) as net:
-        net.set_params(theta)
-        for ws, key in ((P.TSFCDE_WS_ZERO, "plain"), (P.TSFCDE_WS_PREV, "previous_level"),
-                        (P.TSFCDE_WS_EXTRAP, "extrapolated"), (P.TSFCDE_WS_NET, "network")):
-            tot, its, kept = 0.0, [], []
-            for prob in held:
-                with P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, warm_start=ws) as s1:
-                    F = WN.device_sources(prob, s1)
-                    if ws == P.TSFCDE_WS_NET:
-                        net.attach(s1)
-                    u0 = s1.history()[0].clone()
-                    timed_march(s1, F, u0, M, torch)
-                    dt, st = timed_march(s1, F, u0, M, torch)
-                tot += dt
-                its += [x["iters"] for x in st[2:]]
-                kept += [x["guess"] == P.TSFCDE_WS_NET for x in st[2:]]
-            out[key] = {"value": len(held) * M / tot, "unit": "level-solves/s",
-                        "cgs_iterations_mean": float(np.mean(its))}
-            if ws == P.TSFCDE_WS_NET:
-                out[key]["levels_using_network_guess"] = float(np.mean(kept))
-            log(f"learned form ({key}): {out[key]['value']:.1f} level-solves/s, {np.mean(its):.2f} iterations")
-    out["speedup_vs_plain"] = out["network"]["value"] / out["plain"]["value"]
+    M = 256
+    out = {"workload": f"held-out (alpha, beta), n=16384 (and 262144), M={M}, Example-2 time dependence",
+           "parameters": os.path.relpath(path, ROOT)}
+    for n, key_n in ((1 << 14, None), (1 << 18, "n_2p18")):
+        held = W.warmstart_instances(2, n, M, seed=W.SEED_BASE + 77, held_out=True)
+        rec = {} if key_n else out
+        if key_n:
+            rec["workload"] = f"held-out (alpha, beta), n={n}, M={M}, Example-2 time dependence"
+        with P.WarmStartNet(max_points=n, max_batch=1) as net:
+            net.set_params(theta)
+            for ws, key in ((P.TSFCDE_WS_ZERO, "plain"), (P.TSFCDE_WS_PREV, "previous_level"),
+                            (P.TSFCDE_WS_EXTRAP, "extrapolated"), (P.TSFCDE_WS_NET, "network")):
+                tot, its, kept = 0.0, [], []
+                for prob in held:
+                    with P.TimeLevelSolver.from_problem(prob, rtol=args.rtol, warm_start=ws) as s1:
+                        F = WN.device_sources(prob, s1)
+                        if ws == P.TSFCDE_WS_NET:
+                            net.attach(s1)
+                        u0 = s1.history()[0].clone()
+                        timed_march(s1, F, u0, M, torch)
+                        dt, st = timed_march(s1, F, u0, M, torch)
+                        del F
+                    tot += dt
+                    its += [x["iters"] for x in st[2:]]
+                    kept += [x["guess"] == P.TSFCDE_WS_NET for x in st[2:]]
+                rec[key] = {"value": len(held) * M / tot, "unit": "level-solves/s",
+                            "cgs_iterations_mean": float(np.mean(its)), "cgs_iterations": iteration_summary(its)}
+                if ws == P.TSFCDE_WS_NET:
+                    rec[key]["levels_using_network_guess"] = float(np.mean(kept))
+                log(f"learned form n={n} ({key}): {rec[key]['value']:.1f} level-solves/s, {np.mean(its):.2f} iterations")
+        pt = {k: (1.0 / rec[k]["value"], rec[k]["cgs_iterations_mean"]) for k in ("previous_level", "extrapolated", "network")}
+        rec["network_cost_iterations"] = net_cost_iterations(pt["previous_level"], pt["extrapolated"], pt["network"])
+        rec["speedup_vs_plain"] = rec["network"]["value"] / rec["plain"]["value"]
+        if key_n:
+            out[key_n] = rec
     return out
 
 

@@ -68,3 +68,20 @@ def test_fused_bytes_model():
     import bench
     n = 1000
     assert bench.fused_bytes(n, 16, 1, [7]) == 8 * n * (45 * 7 + 20)
+
+
+def test_iteration_summary_and_network_cost():
+    """Iteration distribution of a march, and the network's cost in CGS
+    iterations from the line through the previous-level and extrapolated
+    points (level time = c + t_it * iterations)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    s = bench.iteration_summary([4, 6, 5, 9, 6])
+    assert s["mean"] == 6.0 and s["p50"] == 6.0 and s["max"] == 9.0
+    assert abs(s["p90"] - 7.8) < 1e-12  # linear interpolation between 6 and 9
+    c, t_it = 0.2e-3, 0.05e-3
+    prev, extrap = (c + 10 * t_it, 10.0), (c + 7 * t_it, 7.0)
+    # a network guess worth 6 iterations whose inference costs 0.75 of one
+    net = (c + 6 * t_it + 0.75 * t_it, 6.0)
+    assert abs(bench.net_cost_iterations(prev, extrap, net) - 0.75) < 1e-9
+    assert bench.net_cost_iterations(prev, (c + 10 * t_it, 10.0), net) is None
