@@ -243,3 +243,46 @@ def test_level_symbols_follow_the_level():
     with solver(prob, rtol=1e-12) as s:
         code, _ = s.solve(F)
         assert code == 0 and np.array_equal(host(s.history()), U1)
+
+
+class _PointSource:
+    """f at t_{j+sigma} evaluated one node at a time, indexed like the full
+    (nx, ny, nz) array (the point checks read only the sampled nodes)."""
+
+    def __init__(self, prob, j):
+        self.prob, self.t, self.xyz = prob, O3.t_sigma(prob, j), O3.nodes(prob)
+
+    def __getitem__(self, idx):
+        i, k, l = idx
+        x, y, z = self.xyz
+        return float(self.prob.f(x[i:i + 1], y[k:k + 1], z[l:l + 1], self.t)[0, 0, 0])
+
+
+def test_maximum_size_sampled_points():
+    """2048 x 256 x 512 = 2^28 unknowns (2 GiB per vector: offsets of the
+    plan's vectors and levels pass 2^31 elements), the longest axis at the
+    largest supported length: two levels accepted and the oracle's point
+    residuals g - A u^{j+1} within 1e-12 of |A| max|u|."""
+    banner("3d 2048x256x512 (2^28 unknowns)")
+    ns = (2048, 256, 512)
+    prob = W.problem_3d(*ns, 2, betas=(1.5, 1.8, 1.3))
+    rng = np.random.default_rng(28)
+    pts = [(0, 0, 0), (2047, 255, 511), (2047, 0, 511), (0, 255, 0), (1024, 128, 256), (1500, 7, 400)]
+    pts += [tuple(int(v) for v in (rng.integers(0, ns[0]), rng.integers(0, ns[1]), rng.integers(0, ns[2])))
+            for _ in range(6)]
+    with solver(prob) as s:
+        F = sources(s, prob)
+        stats = [s.step(F[j]) for j in range(2)]
+        del F
+        U = host(s.history())
+    for j in range(2):
+        st = stats[j]
+        print(f"[3d 2^28] j={j} iters {st['iters']} relres_true {st['relres_true']:.2e} "
+              f"backward_err {st['backward_err']:.2e}", flush=True)
+        assert st["code"] == 0 and st["iters"] > 0, st
+        assert st["relres_true"] <= 1e-10 or 0.0 <= st["backward_err"] <= 1e-13, st
+        r = (O3.rhs3_points(prob, U, j, _PointSource(prob, j), pts)
+             - O3.apply_A3_points(prob, j, U[j + 1], pts, "A"))
+        S = O3.anorm3(prob, j) * np.max(np.abs(U[j + 1]))
+        print(f"[3d 2^28] j={j} max point residual / (|A| max|u|) = {np.max(np.abs(r)) / S:.2e}", flush=True)
+        assert np.max(np.abs(r)) <= 1e-12 * S, (j, np.max(np.abs(r)) / S)
