@@ -193,6 +193,9 @@ __global__ void __launch_bounds__((ConvGeo<CI, CO>::NT)) k_conv(const float *__r
     float acc[OPT];
 #pragma unroll
     for (int o = 0; o < OPT; ++o) acc[o] = 0.0f;
+    // one input channel per iteration: the loop kept rolled holds one
+    // channel's KS * OPT weights at a time
+#pragma unroll 1
     for (int ci = 0; ci < CI; ++ci) {
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
