@@ -59,15 +59,25 @@ def _oracle_case(us, feat):
     return X, base, s, NO.target(un, base, s)
 
 
-def test_forward_matches_oracle():
+@pytest.mark.parametrize("n", [777, 65869])
+def test_forward_matches_oracle(n):
+    """Several tiles of every kernel and a ragged tail, on a short grid and on
+    one of 65869 points (about a thousand workgroups per layer).  The hidden
+    layers round their inputs to bfloat16: the device rounds its FP32 values,
+    the oracle its FP64 ones, so an activation within FP32 error of a bfloat16
+    midpoint can round the other way.  On the long grid a few dozen of the
+    4 million rounded activations do, each moving the points within the
+    following layers' reach (clusters of at most 13); the points outside them
+    agree to 2e-5 of the scale.  There the check is: at most 1% of points
+    beyond 2e-5, none beyond 5e-3 (one bfloat16 unit of an activation times
+    the layers after it)."""
     import paper_1603_00279_amd as P
-    banner("net forward")
+    banner(f"net forward n={n}")
     rng = np.random.default_rng(7)
-    n = 777  # several tiles of every kernel and a ragged tail
     us = _levels(rng, n)
     feat = rng.normal(size=5).astype(np.float32)
     theta = _params(rng)
-    with P.WarmStartNet(max_points=4096, max_batch=4) as net:
+    with P.WarmStartNet(max_points=max(4096, n), max_batch=4) as net:
         net.set_params(theta)
         dev = [torch.as_tensor(u, device="cuda") for u in us]
         x0 = net.predict(_sample(P, dev, feat, target=False), n).cpu().numpy()
@@ -76,7 +86,17 @@ def test_forward_matches_oracle():
     x0_ref = NO.predict(th, u0, u1, u2, feat.astype(np.float64))
     base = 3.0 * (u0 - u1) + u2
     corr_ref, corr = x0_ref - base, x0 - base
-    assert np.max(np.abs(corr - corr_ref)) <= 2e-5 * np.max(np.abs(corr_ref)), np.max(np.abs(corr - corr_ref))
+    dev = np.abs(corr - corr_ref)
+    bad = np.nonzero(dev > 2e-5 * np.max(np.abs(corr_ref)))[0]
+    print(f"[net forward n={n}] max dev / scale {np.max(dev) / np.max(np.abs(corr_ref)):.2e}, "
+          f"{len(bad)} points above 2e-5: {bad[:20].tolist()}", flush=True)
+    if n < 4096:
+        assert np.max(dev) <= 2e-5 * np.max(np.abs(corr_ref)), np.max(dev)
+    else:
+        assert len(bad) <= 0.01 * n, len(bad)
+        assert np.max(dev) <= 5e-3 * np.max(np.abs(corr_ref)), np.max(dev)
+        runs = np.split(bad, np.nonzero(np.diff(bad) > 1)[0] + 1) if len(bad) else []
+        assert all(len(r) <= 13 for r in runs), max(len(r) for r in runs)
 
 
 @pytest.mark.parametrize("count,n", [(1, 64), (3, 333), (5, 1000)])
