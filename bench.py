@@ -186,6 +186,47 @@ def path_bytes_nd(d, N, levels, iters, restarts=0):
 
 
 ND_FORMS = {2: dict(ns=(1024, 1024), M=32), 3: dict(ns=(256, 256, 256), M=8)}
+# the largest grid of each family measured beside it (zero guess, a few levels)
+ND_LARGE = {2: dict(ns=(2048, 2048), M=4), 3: dict(ns=(512, 512, 512), M=2)}
+
+
+def nd_large(args, P, W, dev, d):
+    """One march of the d-axis solver on its largest measured grid (2D:
+    2048^2 = 2^22 unknowns, 3D: 512^3 = 2^27, 1 GiB per vector, well beyond
+    the Infinity Cache) after a warm-up march: level-solves/s, the time per
+    CGS iteration and the byte-model rate."""
+    import numpy as np
+    import torch
+    cfg = ND_LARGE[d]
+    ns, M = cfg["ns"], cfg["M"]
+    prob = W.problem_2d(*ns, M) if d == 2 else W.problem_3d(*ns, M)
+    Solver = P.TimeLevelSolver2D if d == 2 else P.TimeLevelSolver3D
+    src = W.device_sources_2d if d == 2 else W.device_sources_3d
+    N = int(np.prod(ns))
+    with Solver.from_problem(prob, rtol=args.rtol) as sv:
+        F = src(prob, *sv.nodes(), sv.level_times(), dev)
+        u0 = sv.history()[0].clone()
+        dts = []
+        for _ in range(2):  # the first march warms up
+            sv.set_state(0, u0.view((1,) + tuple(ns)))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            code, st = sv.solve(F, raise_on_error=False)
+            torch.cuda.synchronize()
+            dts.append(time.perf_counter() - t0)
+        del F
+    dt = dts[-1]
+    iters = [int(q["iters"]) for q in st]
+    nbytes = path_bytes_nd(d, N, M, iters, int(sum(int(q["restarts"]) for q in st)))
+    out = {"workload": f"{'x'.join(str(n) for n in ns)}, M={M}, zero guess", "value": M / dt,
+           "unit": "level-solves/s", "code": int(code), "cgs_iterations_mean": float(np.mean(iters)),
+           "ms_per_cgs_iteration": 1e3 * dt / max(1, sum(iters)),
+           "path_roofline": {"bound": "hbm", "achieved": nbytes / dt / 1e9, "peak": 8000.0, "unit": "GB/s",
+                             "frac": nbytes / dt / 1e9 / 8000.0},
+           "acceptance": acceptance(st)}
+    log(f"form {d}d at {out['workload']}: {out['value']:.2f} level-solves/s, {out['ms_per_cgs_iteration']:.3f} ms "
+        f"per CGS iteration, {out['path_roofline']['achieved']:.0f} GB/s by the byte model")
+    return out
 
 
 def nd_form(args, P, W, dev, d):
@@ -266,6 +307,7 @@ def nd_form(args, P, W, dev, d):
                             "speedup_vs_zero_guess": dt / dtx, "acceptance": acceptance(stx)}}
     if long is not None:
         out["long_march_extrapolated"] = long
+    out["largest"] = nd_large(args, P, W, dev, d)
     log(f"form {d}d extrapolated guess: {M / dtx:.2f} level-solves/s, "
         f"{out['extrapolated']['cgs_iterations_mean']:.1f} iterations")
     log(f"form {d}d: {M / dt:.2f} level-solves/s, {np.mean(iters):.1f} iterations, "
