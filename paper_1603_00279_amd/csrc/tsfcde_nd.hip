@@ -60,7 +60,8 @@ using tsf::lpad_size;
 using tsf::tw_offset;
 
 constexpr int PMAX_LOG2 = 12;  // transforms up to 4096 points (embeddings of n = 2048)
-constexpr int NT = 512;        // threads of a line workgroup at most
+constexpr int NT = 512;        // threads of a strided line workgroup
+constexpr int NT_MAX = 1024;   // threads of a line workgroup at most (strided 1024-point products)
 constexpr int RB = 256;        // threads of a vector workgroup
 constexpr int RBLK = 1024;     // vector workgroups at most (partial sums)
 constexpr int MAXPART = 1024;  // partials a pass folds at most (more are summed first by k_squash)
@@ -98,8 +99,9 @@ __global__ void k_twiddles(double2 *tw, int pmax_log2) {
 // t + 256, ..., then the trees of waves 0..3), the same order in a
 // one-workgroup finishing kernel and in a line pass of 512 threads.
 // ---------------------------------------------------------------------------
-template <int NA> __device__ __forceinline__ void block_partial(const double (&acc)[NA], double *partials, int64_t slot) {
-    __shared__ double red[NA][NT / 64];
+template <int NA, int NTB = RB>  // NTB: the workgroup's threads at most
+__device__ __forceinline__ void block_partial(const double (&acc)[NA], double *partials, int64_t slot) {
+    __shared__ double red[NA][NTB / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwave = (blockDim.x + 63) >> 6;
 #pragma unroll
@@ -158,7 +160,7 @@ template <int P, int NTL, int E_ = 8> struct LineGeo {
     static constexpr int T = P / E;   // lanes per line
     static constexpr int B = NTL / T;  // lines per workgroup
     static constexpr int LS = lpad_size(P);
-    static_assert(P >= 16 && P <= (1 << PMAX_LOG2) && NTL <= NT && B >= 1, "line geometry");
+    static_assert(P >= 16 && P <= (1 << PMAX_LOG2) && NTL <= NT_MAX && B >= 1, "line geometry");
 };
 
 // Workgroups go to the eight XCDs round-robin; tiles of strided lines that
@@ -287,7 +289,7 @@ __global__ void __launch_bounds__(NTL, 4) k_line(Op op, int64_t nlines, const do
     } else {
         fft<P, E, Op::DIR>(v, j, active, tw_all, slab, ls, sink);
     }
-    if constexpr (Op::NACC > 0) block_partial<Op::NACC>(acc, o.part, blockIdx.x);
+    if constexpr (Op::NACC > 0) block_partial<Op::NACC, NTL>(acc, o.part, blockIdx.x);
 }
 
 // Symbol of the level's L_axis on the embedding (length P = 2n) or of its
@@ -338,6 +340,9 @@ enum : int { EPI_W = 0, EPI_WADD = 1, EPI_Y = 2, EPI_DOT = 3, EPI_XR = 4 };
 //   is done where uhat is formed, HalfInvOp).
 template <int EPI> struct ToepOp {
     static constexpr int NFFT = 2, DIR = 0, NRAW = 2, FOLD = 0;
+    // the slow-axis products (y = cb (w + L v) and its CGS forms) take the
+    // wide strided tile at 1024 points (line_t)
+    static constexpr bool WIDE = EPI >= EPI_Y;
     static constexpr bool HALF = false, HALF_T = false, IN_T = false;
     static constexpr int NACC = EPI == EPI_DOT ? 1 : EPI == EPI_XR ? 2 : 0;
     struct Ctx {
@@ -1115,10 +1120,26 @@ hipError_t line_g(NdPlan *pl, const Op &op, int64_t nlines, int *grid_out) {
     return hipGetLastError();
 }
 
+template <class Op, class = void> struct WideTile {
+    static constexpr bool value = false;
+};
+template <class Op> struct WideTile<Op, decltype(void(Op::WIDE))> {
+    static constexpr bool value = Op::WIDE;
+};
+
 template <int P, bool ROWS, class Op>
 hipError_t line_t(NdPlan *pl, const Op &op, int64_t nlines, int *grid_out) {
-    if constexpr (ROWS && P / 8 <= 256) return line_g<P, ROWS, 256>(pl, op, nlines, grid_out);
-    return line_g<P, ROWS, NT>(pl, op, nlines, grid_out);
+    if constexpr (ROWS && P / 8 <= 256) {
+        return line_g<P, ROWS, 256>(pl, op, nlines, grid_out);
+    } else if constexpr (!ROWS && P == 1024 && WideTile<Op>::value) {
+        // slow-axis products on 1024-point embeddings (axes of 512): 1024
+        // threads hold eight lines, so each row run is a whole 128-byte line
+        // instead of 64 bytes (12% and 8% less time for the two CGS forms at
+        // 512^3; the middle-axis pass was 14% slower that way and keeps 512)
+        return line_g<P, ROWS, 1024>(pl, op, nlines, grid_out);
+    } else {
+        return line_g<P, ROWS, NT>(pl, op, nlines, grid_out);
+    }
 }
 
 template <bool ROWS, class Op>

@@ -37,7 +37,7 @@ def sources(s, prob):
     return W.device_sources_2d(prob, x, y, s.level_times(), torch.device("cuda"))
 
 
-@pytest.mark.parametrize("nx,ny", [(16, 16), (32, 64), (128, 32), (256, 256), (2048, 16), (16, 2048)])
+@pytest.mark.parametrize("nx,ny", [(16, 16), (32, 64), (128, 32), (256, 256), (2048, 16), (16, 2048), (512, 64)])
 def test_operators_match_oracle(nx, ny):
     import paper_1603_00279_amd as P
     banner(f"2d operators {nx}x{ny}")

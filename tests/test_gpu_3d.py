@@ -37,7 +37,8 @@ def sources(s, prob):
     return W.device_sources_3d(prob, x, y, z, s.level_times(), torch.device("cuda"))
 
 
-@pytest.mark.parametrize("ns", [(16, 16, 16), (16, 32, 64), (64, 16, 32), (128, 64, 128), (2048, 16, 32), (16, 32, 2048)])
+@pytest.mark.parametrize("ns", [(16, 16, 16), (16, 32, 64), (64, 16, 32), (128, 64, 128), (2048, 16, 32), (16, 32, 2048),
+                                (512, 16, 32), (16, 512, 32), (1024, 16, 16)])
 def test_operators_match_oracle(ns):
     import paper_1603_00279_amd as P
     banner(f"3d operators {ns}")
@@ -81,7 +82,7 @@ def test_march_matches_dense_oracle():
         assert st["relres_true"] <= 1e-12 or 0.0 <= st["backward_err"] <= 1e-13, st
 
 
-@pytest.mark.parametrize("ns,M", [((32, 16, 64), 3), ((16, 128, 32), 2)])
+@pytest.mark.parametrize("ns,M", [((32, 16, 64), 3), ((16, 128, 32), 2), ((512, 16, 16), 2)])
 def test_march_matches_fft_oracle(ns, M):
     """Larger grids against the oracle's FFT-route PCGS march (pinned against
     the dense route), both solved to 1e-13."""
