@@ -1131,11 +1131,14 @@ template <int P, bool ROWS, class Op>
 hipError_t line_t(NdPlan *pl, const Op &op, int64_t nlines, int *grid_out) {
     if constexpr (ROWS && P / 8 <= 256) {
         return line_g<P, ROWS, 256>(pl, op, nlines, grid_out);
-    } else if constexpr (!ROWS && P == 1024 && WideTile<Op>::value) {
-        // slow-axis products on 1024-point embeddings (axes of 512): 1024
-        // threads hold eight lines, so each row run is a whole 128-byte line
-        // instead of 64 bytes (12% and 8% less time for the two CGS forms at
-        // 512^3; the middle-axis pass was 14% slower that way and keeps 512)
+    } else if constexpr (!ROWS && (P == 1024 || P == 4096) && WideTile<Op>::value) {
+        // slow-axis products on 1024- and 4096-point embeddings (axes of 512
+        // and 2048): 1024 threads hold twice the lines of 512, so each row
+        // run is twice as long (at 512^3 whole 128-byte lines: 12% and 8%
+        // less time for the two CGS forms; 8% less per CGS iteration at
+        // 2048^2).  The middle-axis pass was 14% slower that way, and at 2048
+        // points (axes of 1024) the wider form spills: 8% slower per CGS
+        // iteration at 1024^2; both keep 512.
         return line_g<P, ROWS, 1024>(pl, op, nlines, grid_out);
     } else {
         return line_g<P, ROWS, NT>(pl, op, nlines, grid_out);
